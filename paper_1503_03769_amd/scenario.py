@@ -1,0 +1,145 @@
+"""Seeded synthetic inputs shared by the GPU path and the oracle.
+
+This module simulates the *world* the filter observes -- target trajectories,
+detections and clutter -- and defines the named workloads.  It contains none
+of the filter's arithmetic (no likelihood, weight, resampling or exchange), and
+it draws its randomness from numpy's PCG64, never from the filter's Philox
+streams.
+
+Workload recipe (the paper's truth tracks are not available, so a seeded
+generator stands in for them):
+  * target i of n is born at step b_i = 1 + floor(u T/2) and dies at
+    min(T, b_i + ceil(T/2) + floor(u' T/2)), or earlier when it leaves the
+    surveillance square [-1000, 1000]^2;
+  * its initial position is uniform in [-800, 800]^2, its velocity N(0, 10^2 I),
+    and it moves with the constant-velocity model of section 4 (acceleration
+    noise sigma_a on each axis);
+  * each live target is detected with probability p_D; a detection is
+    [range, bearing] + N(0, diag(sigma_r^2, sigma_theta^2)) with the bearing
+    wrapped into [-pi, pi);
+  * clutter is Poisson(lambda) points uniform over [r_min, r_max] x [th_min, th_max);
+  * each measurement set is shuffled.
+"""
+import math
+
+import numpy as np
+
+BASE_MODEL = dict(
+    T=1.0, sigma_a=5.0, sensor_x=0.0, sensor_y=0.0, sigma_r=10.0, sigma_theta=0.02,
+    p_S=0.99, p_D=0.95, clutter_rate=10.0, r_min=0.0, r_max=2000.0,
+    th_min=-math.pi, th_max=math.pi, birth_mass=0.1,
+    region=(-1000.0, 1000.0, -1000.0, 1000.0), birth_sigma_v=10.0, init_mass=1.0,
+    particles_per_target=1000.0, exchange_fraction=0.1, partitions=1, births_per_step=500,
+)
+
+# Named workloads.  "precision" is the GPU path's storage type; the oracle is FP64.
+WORKLOADS = {
+    # 3 targets, 50 steps, one group, FP64 everywhere.
+    "plain_fp64_3tgt": dict(
+        model=dict(BASE_MODEL, clutter_rate=10.0, particles_per_target=1000.0,
+                   births_per_step=500, partitions=1),
+        n_targets=3, steps=50, cap=16384, precision="fp64", max_meas=256, config_index=1),
+    # 10 targets, 100 steps, 64 groups with exchange and fusion, FP32 storage.
+    "large_fp32_10tgt_k64": dict(
+        model=dict(BASE_MODEL, clutter_rate=50.0, particles_per_target=1.0e5,
+                   births_per_step=50000, partitions=64),
+        n_targets=10, steps=100, cap=32768, precision="fp32", max_meas=512, config_index=2),
+}
+
+
+def workload_seed(config_index: int, run: int) -> int:
+    return 0x5EED0000 + 1000 * int(config_index) + int(run)
+
+
+def _cv_step(rng, s, T, sigma_a):
+    a = rng.normal(0.0, sigma_a, size=2)
+    x, vx, y, vy = s
+    return np.array([x + T * vx + 0.5 * T * T * a[0], vx + T * a[0],
+                     y + T * vy + 0.5 * T * T * a[1], vy + T * a[1]])
+
+
+def make_scenario(model: dict, n_targets: int, steps: int, seed: int, start_box=(-800.0, 800.0, -800.0, 800.0),
+                  start_sigma_v=10.0, surveillance=(-1000.0, 1000.0, -1000.0, 1000.0)):
+    """Returns (truth, Z): truth[k] is an array [n_alive, 4] and Z[k] an array
+    [M_k, 2] of (range, bearing) for k = 1..steps (index 0 is unused).
+    start_box / start_sigma_v: where targets appear and their velocity spread;
+    surveillance: targets that leave this square die."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T, sa = model["T"], model["sigma_a"]
+    xmin, xmax, ymin, ymax = surveillance
+    births = [1 + int(math.floor(rng.uniform() * steps / 2)) for _ in range(n_targets)]
+    deaths = [min(steps, b + int(math.ceil(steps / 2)) + int(math.floor(rng.uniform() * steps / 2)))
+              for b in births]
+    states = [None] * n_targets
+    truth = [np.zeros((0, 4))]
+    Z = [np.zeros((0, 2))]
+    for k in range(1, steps + 1):
+        alive = []
+        for i in range(n_targets):
+            if k < births[i] or k > deaths[i]:
+                states[i] = None if k > deaths[i] else states[i]
+                continue
+            if k == births[i]:
+                states[i] = np.array([rng.uniform(start_box[0], start_box[1]), rng.normal(0, start_sigma_v),
+                                      rng.uniform(start_box[2], start_box[3]), rng.normal(0, start_sigma_v)])
+            elif states[i] is not None:
+                states[i] = _cv_step(rng, states[i], T, sa)
+            if states[i] is None:
+                continue
+            s = states[i]
+            if not (xmin <= s[0] <= xmax and ymin <= s[2] <= ymax):
+                states[i] = None
+                deaths[i] = k - 1
+                continue
+            alive.append(s.copy())
+        tk = np.array(alive).reshape(-1, 4)
+        meas = []
+        for s in tk:
+            if rng.uniform() < model["p_D"]:
+                dx, dy = s[0] - model["sensor_x"], s[2] - model["sensor_y"]
+                r = math.hypot(dx, dy) + rng.normal(0, model["sigma_r"])
+                th = math.atan2(dy, dx) + rng.normal(0, model["sigma_theta"])
+                th = (th + math.pi) % (2 * math.pi) - math.pi
+                meas.append((r, th))
+        nc = rng.poisson(model["clutter_rate"])
+        for _ in range(nc):
+            meas.append((rng.uniform(model["r_min"], model["r_max"]),
+                         rng.uniform(model["th_min"], model["th_max"])))
+        zk = np.array(meas, dtype=np.float64).reshape(-1, 2)
+        if zk.shape[0] > 1:
+            zk = zk[rng.permutation(zk.shape[0])]
+        truth.append(tk)
+        Z.append(np.ascontiguousarray(zk))
+    return truth, Z
+
+
+def random_particles(K, cap, counts, seed, truth=None, spread=30.0, dtype=np.float64):
+    """A synthetic particle cloud in the [4][K*cap] layout: part of every
+    partition is scattered around the given truth states, the rest uniform over
+    the surveillance square; weights are positive with a few orders of
+    magnitude of spread.  Returns (X, W, n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = np.zeros((4, K * cap), dtype=np.float64)
+    W = np.zeros(K * cap, dtype=np.float64)
+    n = np.asarray(counts, dtype=np.int32).copy()
+    for j in range(K):
+        nj = int(n[j])
+        base = j * cap
+        pos = rng.uniform(-1000, 1000, size=(nj, 2))
+        vel = rng.normal(0, 10, size=(nj, 2))
+        if truth is not None and len(truth) > 0 and nj > 0:
+            near = rng.uniform(size=nj) < 0.6
+            idx = rng.integers(0, len(truth), size=nj)
+            pos[near, 0] = truth[idx[near], 0] + rng.normal(0, spread, size=near.sum())
+            pos[near, 1] = truth[idx[near], 2] + rng.normal(0, spread, size=near.sum())
+            vel[near, 0] = truth[idx[near], 1] + rng.normal(0, 3, size=near.sum())
+            vel[near, 1] = truth[idx[near], 3] + rng.normal(0, 3, size=near.sum())
+        X[0, base:base + nj] = pos[:, 0]
+        X[1, base:base + nj] = vel[:, 0]
+        X[2, base:base + nj] = pos[:, 1]
+        X[3, base:base + nj] = vel[:, 1]
+        W[base:base + nj] = np.exp(rng.uniform(-3, 0, size=nj)) * 1e-3
+    if dtype == np.float32:
+        X = X.astype(np.float32).astype(np.float64)
+        W = W.astype(np.float32).astype(np.float64)
+    return X, W, n

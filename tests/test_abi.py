@@ -1,0 +1,56 @@
+"""The C ABI library loads and exports every entry point its header declares
+(no device calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pphd.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pphd_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_paper_stages():
+    names = _declared()
+    for n in ("pphd_predict", "pphd_update", "pphd_extract", "pphd_resample", "pphd_exchange",
+              "pphd_create", "pphd_init", "pphd_destroy", "pphd_workspace_size", "pphd_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1503_03769_amd import pphd
+    L = ctypes.CDLL(pphd.LIB_PATH)
+    for n in _declared():
+        assert hasattr(L, n), n
+    # the binding wraps every declared entry point under the same name
+    for n in _declared():
+        assert n in pphd.SIGNATURES, n
+        assert hasattr(pphd, n), n
+
+
+def test_workspace_size_and_argument_errors():
+    """pphd_workspace_size is pure host arithmetic: check it and its error path."""
+    from paper_1503_03769_amd import pphd
+    from paper_1503_03769_amd.scenario import WORKLOADS
+    w = WORKLOADS["large_fp32_10tgt_k64"]
+    m = pphd.model_struct(w["model"], pphd.PPHD_FP32)
+    n32 = pphd.pphd_workspace_size(m, w["cap"], w["max_meas"])
+    m64 = pphd.model_struct(w["model"], pphd.PPHD_FP64)
+    n64 = pphd.pphd_workspace_size(m64, w["cap"], w["max_meas"])
+    KC = 64 * w["cap"]
+    assert n32 >= 2 * 5 * KC * 4 and n64 >= 2 * 5 * KC * 8 and n64 > n32
+    bad = pphd.model_struct(dict(w["model"], partitions=0), pphd.PPHD_FP32)
+    with pytest.raises(pphd.PphdError) as e:
+        pphd.pphd_workspace_size(bad, w["cap"], w["max_meas"])
+    assert e.value.code == pphd.PPHD_EINVAL
+    with pytest.raises(pphd.PphdError):
+        pphd.pphd_workspace_size(m, 10, w["max_meas"])          # cannot hold round(R/K)
+    with pytest.raises(pphd.PphdError):
+        pphd.pphd_workspace_size(m, w["cap"], 0)
+    assert pphd.pphd_kernel_name(3) == "k_weight"

@@ -1,0 +1,139 @@
+"""Pins of the oracle's Step 5 (group-local systematic resampling) against an
+exact rational-arithmetic brute force, and of Step 6 (ring exchange) by the
+properties of a permutation."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1503_03769_amd.scenario import BASE_MODEL
+
+
+def _brute_counts(w, L, r):
+    """Systematic resampling from the definition, in exact rationals: point m
+    sits at (m + r/2^32) W / L; parent i takes the points in [c_{i-1}, c_i)."""
+    W = sum(w, Fraction(0))
+    u = Fraction(r, 2 ** 32)
+    cum = []
+    c = Fraction(0)
+    for x in w:
+        c += x
+        cum.append(c)
+    counts = [0] * len(w)
+    i = 0
+    for m in range(L):
+        pt = (m + u) * W / L
+        while not (pt < cum[i]):
+            i += 1
+        counts[i] += 1
+    return counts
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_resample_counts_match_exact_brute_force(orc, case):
+    rng = np.random.default_rng(100 + case)
+    K = 1 + case % 3
+    cap = 64
+    R = float(rng.choice([10.0, 37.0, 100.0, 250.0])) * K
+    J = int(rng.integers(0, 5))
+    p = dict(BASE_MODEL, partitions=K, particles_per_target=R, births_per_step=J)
+    st = orc.State(K, cap)
+    ks = []
+    for j in range(K):
+        n = int(rng.integers(0, 50))
+        st.n[j] = n
+        k = rng.integers(0, 2 ** 12, size=n)
+        if case % 5 == 0 and n > 3:
+            k[:] = 256                         # equal weights
+        ks.append(k)
+        st.W[j * cap:j * cap + n] = k / 2.0 ** 20   # dyadic weights: quantisation is exact
+        st.X[:, j * cap:j * cap + n] = rng.normal(size=(4, n))
+    step, seed, run = 3 + case, 0xABC + case, case % 4
+    out, counts, mq = orc.resample(p, st, step, seed, run)
+    for j in range(K):
+        n = int(st.n[j])
+        w = [Fraction(int(v), 2 ** 20) for v in ks[j]]
+        W = sum(w, Fraction(0))
+        Jj = orc.births_in_partition(p, j)
+        L = math.floor(W * Fraction(R / K) + Fraction(1, 2)) if W > 0 else 0
+        L = min(L, cap - Jj)
+        assert out.n[j] == L
+        assert mq[j] == float(W)
+        got = list(counts[j * cap:j * cap + n])
+        if L == 0:
+            assert sum(got) == 0
+            continue
+        r = orc.philox([j, step, orc.PURPOSE_RESAMPLE * 16, run], [seed & 0xFFFFFFFF, seed >> 32])[0]
+        want = _brute_counts(w, L, r)
+        assert got == want
+        # systematic property: floor or ceil of the expected count
+        for wi, ci in zip(w, got):
+            e = L * wi / W
+            assert math.floor(e) <= ci <= math.ceil(e)
+        # children in parent order, each with weight W / L
+        kids = np.repeat(np.arange(n), got)
+        assert np.array_equal(out.X[:, j * cap:j * cap + L], st.X[:, j * cap + kids])
+        assert np.all(out.W[j * cap:j * cap + L] == float(W) / L)
+        if ks[j].size and np.all(ks[j] == ks[j][0]) and L == n:
+            assert all(c == 1 for c in got)
+
+
+def test_resample_clamps_to_capacity(orc):
+    p = dict(BASE_MODEL, partitions=1, particles_per_target=1000.0, births_per_step=10)
+    st = orc.State(1, 100)
+    st.n[0] = 50
+    st.W[:50] = 0.1                      # mass 5 -> 5000 children wanted
+    out, counts, mq = orc.resample(p, st, 1, 1, 0)
+    assert out.n[0] == 90 and counts[:50].sum() == 90
+
+
+def test_resample_zero_mass_gives_empty_group(orc):
+    p = dict(BASE_MODEL, partitions=2)
+    st = orc.State(2, 10)
+    st.n[:] = [5, 0]
+    out, counts, mq = orc.resample(p, st, 1, 1, 0)
+    assert list(out.n) == [0, 0] and counts.sum() == 0
+
+
+def _exchange_setup(orc, K, counts, seed):
+    cap = 400
+    p = dict(BASE_MODEL, partitions=K, exchange_fraction=0.1)
+    st = orc.State(K, cap)
+    rng = np.random.default_rng(seed)
+    st.n[:] = counts
+    st.X[:] = rng.normal(size=st.X.shape)
+    for j in range(K):
+        st.W[j * cap:(j + 1) * cap] = rng.uniform(1, 2)   # uniform per group, as after resampling
+    return p, st, cap
+
+
+def _couples(st, j, cap):
+    n = int(st.n[j])
+    return [tuple(st.X[:, j * cap + s]) + (st.W[j * cap + s],) for s in range(n)]
+
+
+@pytest.mark.parametrize("K,counts", [(4, [300, 120, 250, 399]), (3, [50, 50, 50]), (5, [9, 300, 300, 300, 300])])
+def test_exchange_is_a_ring_permutation(orc, K, counts):
+    p, st, cap = _exchange_setup(orc, K, counts, K)
+    before = [_couples(st, j, cap) for j in range(K)]
+    orc.exchange(p, st, 7, 0x55, 1)
+    after = [_couples(st, j, cap) for j in range(K)]
+    L = math.floor(0.1 * min(counts))
+    assert list(st.n) == counts
+    # global multiset of particle-weight couples is unchanged
+    assert sorted(sum(before, [])) == sorted(sum(after, []))
+    for j in range(K):
+        prev = (j - 1) % K
+        came = [c for c in after[j] if c not in set(before[j])]
+        assert len(came) == L
+        assert set(came) <= set(before[prev])
+        kept = [c for c in after[j] if c in set(before[j])]
+        assert len(kept) == counts[j] - L
+
+
+def test_exchange_noop_for_one_group(orc):
+    p, st, cap = _exchange_setup(orc, 1, [200], 1)
+    X0 = st.X.copy()
+    orc.exchange(p, st, 1, 1, 0)
+    assert np.array_equal(st.X, X0)
