@@ -1,0 +1,228 @@
+/*
+ * pphd.h -- C ABI of libpphd, the gfx950 (MI355X) implementation of the per-step
+ * recursion of the distributed computation particle PHD filter (DCPFPHD) of
+ * Wang, Zhao, Su and Ma, "Distributed Computation Particle PHD filter"
+ * (arXiv 1503.03769).
+ *
+ * The K processing elements ("groups") of the paper's section 3 become K
+ * partitions of one particle array in device memory.  Every partition runs a
+ * full local particle PHD filter on its own particles and sees every
+ * measurement; partitions hand particles to their ring neighbour and a central
+ * step fuses their estimates.  Every stage runs in HIP kernels on one stream.
+ *
+ * Conventions for every entry point:
+ *  - The return value is a pphd_status; PPHD_OK (0) on success, a negative
+ *    code otherwise.  pphd_last_error() then returns a message (thread-local,
+ *    valid until the next failing call on the same thread).
+ *  - No C++ type, exception or allocation crosses this boundary.
+ *  - Device pointers are HIP device pointers on the device that was current
+ *    when the filter was created; host pointers are ordinary host memory.
+ *  - All device work is queued on the hipStream_t given to pphd_create, in
+ *    call order.  Calls that return host data synchronise that stream; the
+ *    others return as soon as the work is queued.
+ *  - A filter handle may be used from one thread at a time.
+ *  - The call order of one filter step follows algorithm 1 and Steps 1-6 of
+ *    section 3.1: predict -> update -> [extract] -> resample -> [exchange].
+ *    A call out of that order returns PPHD_ESTATE and changes nothing.
+ */
+#ifndef PPHD_H
+#define PPHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PPHD_OK = 0,
+    PPHD_EINVAL = -1,     /* a bad argument (null pointer, size out of range)         */
+    PPHD_ENOMEM = -2,     /* the workspace is too small or a host allocation failed   */
+    PPHD_ECAPACITY = -3,  /* the capacity cannot hold the initial or born particles   */
+    PPHD_EDEVICE = -4,    /* a HIP call failed (message holds the HIP error string)  */
+    PPHD_ESTATE = -5      /* call out of order for the filter's current phase         */
+} pphd_status;
+
+typedef enum { PPHD_FP64 = 0, PPHD_FP32 = 1 } pphd_precision;
+
+/* Phases a filter moves through within one step (see pphd_write_state). */
+typedef enum {
+    PPHD_PHASE_READY = 1,      /* after init or exchange: next call is predict        */
+    PPHD_PHASE_PREDICTED = 2,  /* after predict: next call is update                  */
+    PPHD_PHASE_UPDATED = 3,    /* after update (or extract): next is extract/resample */
+    PPHD_PHASE_RESAMPLED = 4   /* after resample: next is exchange or predict         */
+} pphd_phase;
+
+/*
+ * Model of one filter run (section 4 simulation model; parameters are the
+ * caller's).  State is 4-D constant velocity [x, vx, y, vy]; the sensor
+ * measures [range, bearing] = [|p - s|, atan2(p_y - s_y, p_x - s_x)] with
+ * independent Gaussian noise.
+ */
+typedef struct {
+    int32_t dim;              /* must be 4                                              */
+    int32_t partitions;       /* K >= 1 groups (processing elements)                    */
+    int32_t births_per_step;  /* J >= 0 births per step over all groups; group j gets   */
+                              /* J/K, plus one when j < J mod K (Step 1, section 3.1)   */
+    int32_t precision;        /* pphd_precision: storage and likelihood precision       */
+    double T, sigma_a;                                  /* sampling period, accel. noise */
+    double sensor_x, sensor_y, sigma_r, sigma_theta;    /* range-bearing sensor          */
+    double p_S, p_D;                                    /* survival, detection prob.     */
+    double clutter_rate;                                /* lambda (Poisson mean)         */
+    double r_min, r_max, th_min, th_max;                /* clutter region; kappa = lambda/area */
+    double birth_mass;                                  /* m_b, mass of the birth PHD    */
+    double region[4];                                   /* xmin, xmax, ymin, ymax        */
+    double birth_sigma_v;                               /* birth velocity std. dev.      */
+    double init_mass;                                   /* PHD mass of each group at t=0 */
+    double particles_per_target;                        /* R over all groups; R_j = R/K  */
+    double exchange_fraction;                           /* rho_x in [0, 0.5)             */
+} pphd_model;
+
+/* One fused (global) estimate: the mean of the local estimates that carry the
+ * same measurement label (Step 4, section 3.1). */
+typedef struct {
+    double state[4];   /* x, vx, y, vy                                   */
+    int32_t label;     /* index of the measurement in this step's set   */
+    int32_t votes;     /* number of groups that reported the label      */
+} pphd_estimate;
+
+typedef struct pphd_filter pphd_filter;
+
+/* Bytes of device workspace a filter with this model needs.
+ * cap_per_partition: particle slots per group (must hold round(R/K) initial
+ * particles and L' + J_j after every resampling; L' is clamped to fit).
+ * max_meas: the largest measurement count a later pphd_update may pass (>= 1).
+ * Returns PPHD_EINVAL for an invalid model or sizes. */
+pphd_status pphd_workspace_size(const pphd_model* model, int64_t cap_per_partition,
+                                int32_t max_meas, size_t* bytes);
+
+/* Creates a filter.  workspace: caller-owned device memory of at least
+ * pphd_workspace_size() bytes, 256-byte aligned; it holds every device array
+ * of the filter (two particle sets, per-stage partial results, outputs) and
+ * must stay allocated until pphd_destroy.  The library never frees it.
+ * seed, run_id: key and counter word of the Philox-4x32-10 streams.
+ * stream: a hipStream_t (NULL = default stream).  The handle is
+ * library-owned; release it with pphd_destroy. */
+pphd_status pphd_create(const pphd_model* model, int64_t cap_per_partition, int32_t max_meas,
+                        void* workspace, size_t workspace_bytes, uint64_t seed, uint32_t run_id,
+                        void* stream, pphd_filter** out);
+
+/* t = 0 of section 3.1: every group draws round(R/K) particles from the
+ * normalised birth density, each with weight init_mass / round(R/K).
+ * Allowed in any phase; moves the filter to PPHD_PHASE_READY. */
+pphd_status pphd_init(pphd_filter* f);
+
+/* Step 1 (Eqs 5 and 6): survivors move through the CV model with Philox noise
+ * and take weight p_S * w; group j appends J_j births drawn from the birth
+ * density with weight m_b / J_j.  step: the time index k >= 1.
+ * Phase READY or RESAMPLED -> PREDICTED. */
+pphd_status pphd_predict(pphd_filter* f, uint32_t step);
+
+/* Step 2 (Eqs 7, 8 and 10-15): C_j(z_p) = sum over group j of p_D g(z_p|x) w
+ * for every measurement, then w <- [1 - p_D + sum_p p_D g(z_p|x)/(kappa +
+ * C_j(z_p))] w, plus the sums that Step 3 needs.
+ * z: m pairs (range, bearing), double[m][2], on the host (z_on_device = 0;
+ * copied before the call returns) or on the device (z_on_device = 1; read in
+ * stream order, so it must stay valid until the stream reaches this work).
+ * 0 <= m <= max_meas.  Phase PREDICTED -> UPDATED. */
+pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on_device);
+
+/* Steps 3 and 4: each group keeps its round(sum w) best-supported measurement
+ * labels with local estimates (Eqs 16-18); labels reported by more than half
+ * of the groups are averaged into global estimates, ordered by label.
+ * out: host array of cap records; *n_out receives the number written.
+ * mass_per_partition: nullable host double[K], receives each group's
+ * updated PHD mass.  Synchronises the stream.  Phase UPDATED (unchanged). */
+pphd_status pphd_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out,
+                         double* mass_per_partition);
+
+/* As pphd_extract, but the records and their count are written to device
+ * memory in stream order (d_out: cap records, d_n_out: one int32); no
+ * synchronisation.  Records beyond cap are dropped; *d_n_out holds the full
+ * count. */
+pphd_status pphd_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t cap,
+                                int32_t* d_n_out);
+
+/* Step 5: every group quantises its weights, draws L' = round(N_j R_j)
+ * children by systematic resampling (one Philox uniform per group; children
+ * in parent order), clamps L' to cap - J_j and gives each child weight
+ * N_j / L'.  step: the time index of the preceding predict.
+ * Phase UPDATED -> RESAMPLED. */
+pphd_status pphd_resample(pphd_filter* f, uint32_t step);
+
+/* Step 6: ring exchange j -> j+1 (mod K) of floor(rho_x min(L'_j, L'_{j+1}))
+ * particle-weight couples per group, all read before any is written.  No-op
+ * for K = 1.  Phase RESAMPLED -> READY. */
+pphd_status pphd_exchange(pphd_filter* f, uint32_t step);
+
+/* Releases the handle and its host resources (not the workspace).
+ * Synchronises the stream.  NULL is accepted. */
+pphd_status pphd_destroy(pphd_filter* f);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* pphd_last_error(void);
+
+/* ---- state access (stage tests, checkpoint and restore) ---------------- */
+
+/* Copies the current particle set to host memory, converted to double.
+ * x: double[4][K*cap] (component d of slot s of group j at d*K*cap + j*cap + s),
+ * w: double[K*cap], count: int32[K] (occupied slots per group).  Any of the
+ * three may be NULL.  Slots beyond count are unspecified.  Synchronises. */
+pphd_status pphd_read_state(pphd_filter* f, double* x, double* w, int32_t* count);
+
+/* Overwrites the current particle set from host memory (same layout as
+ * pphd_read_state; values are rounded to the storage precision) and puts the
+ * filter into the given phase: READY or RESAMPLED (next: predict / exchange)
+ * or PREDICTED (next: update) or UPDATED (next: resample only).
+ * count[j] must be <= cap.  Synchronises. */
+pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w,
+                             const int32_t* count, int32_t phase);
+
+/* Results of the last update, copied to host memory (any pointer may be NULL):
+ * C: double[K][m], C_j(z_p) of Eq 11 (0 where it underflows double);
+ * dW: double[K][m], Delta W^{j,p} of Eq 16; mass: double[K], each group's
+ * updated PHD mass; LT: int32[K], round(mass) capped at m.  Synchronises. */
+pphd_status pphd_read_update(pphd_filter* f, double* C, double* dW, double* mass, int32_t* LT);
+
+/* Local estimates of the last update (Step 3): sel: int32[K][m], 1 where
+ * measurement p is in group j's label set I_j; zeta: double[K][m][4], the
+ * local estimate of that label (0 elsewhere).  Synchronises. */
+pphd_status pphd_read_local(pphd_filter* f, int32_t* sel, double* zeta);
+
+/* Enables (1) or disables (0) recording of per-parent child counts in
+ * resample, which costs one int32 store per parent. */
+pphd_status pphd_set_record_counts(pphd_filter* f, int32_t enable);
+
+/* Results of the last resample: counts: int32[K*cap], children of parent
+ * slot j*cap+i (only if recording was enabled); mass_q: double[K], the
+ * quantised group mass N_j; clamped: total number of group resamplings so
+ * far whose L' was clamped to the capacity.  Synchronises. */
+pphd_status pphd_read_resample(pphd_filter* f, int32_t* counts, double* mass_q, int64_t* clamped);
+
+/* ---- timing ------------------------------------------------------------- */
+
+/* Kernel classes timed by the library. */
+enum {
+    PPHD_K_PREDICT = 0, PPHD_K_CZ = 1, PPHD_K_CZ_COMBINE = 2, PPHD_K_WEIGHT = 3,
+    PPHD_K_FINALIZE = 4, PPHD_K_FUSE = 5, PPHD_K_RS_TILES = 6, PPHD_K_RS_EXPAND = 7,
+    PPHD_K_XCHG_GATHER = 8, PPHD_K_XCHG_SCATTER = 9, PPHD_K_INIT = 10, PPHD_K_WMAX = 11,
+    PPHD_K_COUNT = 12
+};
+
+/* Enables (1) or disables (0) per-launch HIP-event timing on the filter's
+ * stream, and clears the accumulated times. */
+pphd_status pphd_set_timing(pphd_filter* f, int32_t enable);
+
+/* Total milliseconds and launch counts per kernel class since timing was
+ * enabled: ms: double[PPHD_K_COUNT], launches: int64[PPHD_K_COUNT].
+ * Synchronises. */
+pphd_status pphd_read_timing(pphd_filter* f, double* ms, int64_t* launches);
+
+/* Kernel name of a class (for profiler cross-reference), or NULL. */
+const char* pphd_kernel_name(int32_t kernel_class);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPHD_H */

@@ -1,0 +1,728 @@
+// libpphd: C ABI (include/pphd.h) over the HIP kernels in kernels.h.
+//
+// One filter = one run of the distributed particle PHD filter on one device
+// stream.  Every device array lives in the caller's workspace, carved here in a
+// fixed order; the library allocates only pinned host staging and events.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pphd.h"
+#include "kernels.h"
+
+using namespace pphd;
+
+namespace {
+
+thread_local std::string g_err;
+
+pphd_status fail(pphd_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+pphd_status fail(pphd_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(PPHD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+// particles per thread of the two update passes and of resampling
+constexpr int PT1_F32 = 16, PT2_F32 = 16, PT1_F64 = 8, PT2_F64 = 8, PR = 4;
+
+const char* kKernelNames[PPHD_K_COUNT] = {
+    "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
+    "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
+};
+
+struct Layout {
+    size_t off = 0;
+    template <typename P>
+    P* take(char* base, size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+}  // namespace
+
+struct pphd_filter {
+    pphd_model model;
+    DevModel dm;
+    int K = 0, cap = 0, max_meas = 0, prec = 0;
+    size_t KC = 0;
+    size_t esz = 8;
+    hipStream_t stream = nullptr;
+    uint64_t seed = 0;
+    uint32_t run = 0;
+    int phase = 0;  // 0 = created, otherwise a pphd_phase
+    int cur = 0;    // which particle set is current
+    int last_m = 0;
+    bool record = false;
+    bool timing = false;
+    int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0;
+    // device arrays (inside the workspace)
+    void* X[2][4] = {};
+    void* W[2] = {};
+    int *nsurv = nullptr, *ncur = nullptr, *clampctr = nullptr;
+    double* zbuf = nullptr;
+    double *p1s = nullptr, *p1w = nullptr;
+    int* p1h = nullptr;
+    int *zH = nullptr, *zflag = nullptr, *cand = nullptr, *ncand = nullptr;
+    void* zF = nullptr;
+    double *zC = nullptr, *zdW = nullptr;
+    double *p2mass = nullptr, *p2max = nullptr, *p2zeta = nullptr;
+    double* fmass = nullptr;
+    int *fLT = nullptr, *rsS = nullptr, *sel = nullptr;
+    double* zeta = nullptr;
+    EstimateRec* est = nullptr;
+    int* nest = nullptr;
+    double *tsum = nullptr, *massq = nullptr;
+    int* counts = nullptr;
+    void* stage = nullptr;
+    // host side
+    double* pin_z = nullptr;
+    hipEvent_t z_done = nullptr;
+    bool z_pending = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    double acc_ms[PPHD_K_COUNT] = {};
+    long long acc_n[PPHD_K_COUNT] = {};
+};
+
+namespace {
+
+bool model_ok(const pphd_model* m, std::string& why)
+{
+    if (!m) { why = "model is NULL"; return false; }
+    if (m->dim != 4) { why = "dim must be 4"; return false; }
+    if (m->partitions < 1) { why = "partitions must be >= 1"; return false; }
+    if (m->births_per_step < 0) { why = "births_per_step must be >= 0"; return false; }
+    if (m->precision != PPHD_FP64 && m->precision != PPHD_FP32) { why = "precision must be 0 or 1"; return false; }
+    if (!(m->sigma_r > 0) || !(m->sigma_theta > 0)) { why = "sensor sigmas must be > 0"; return false; }
+    if (!(m->p_D >= 0 && m->p_D <= 1) || !(m->p_S >= 0 && m->p_S <= 1)) { why = "p_S, p_D must be in [0,1]"; return false; }
+    if (!(m->clutter_rate >= 0)) { why = "clutter_rate must be >= 0"; return false; }
+    if (!(m->r_max > m->r_min) || !(m->th_max > m->th_min)) { why = "empty clutter region"; return false; }
+    if (!(m->particles_per_target > 0)) { why = "particles_per_target must be > 0"; return false; }
+    if (!(m->exchange_fraction >= 0 && m->exchange_fraction < 0.5)) { why = "exchange_fraction must be in [0, 0.5)"; return false; }
+    if (!(m->birth_mass >= 0) || !(m->init_mass >= 0)) { why = "masses must be >= 0"; return false; }
+    return true;
+}
+
+// Carves every device array from base (or only measures when base == nullptr).
+size_t carve(pphd_filter* f, char* base)
+{
+    Layout L;
+    const size_t KC = f->KC, K = f->K, Mx = f->max_meas, es = f->esz;
+    for (int b = 0; b < 2; ++b) {
+        for (int d = 0; d < 4; ++d) f->X[b][d] = L.take<char>(base, KC * es);
+        f->W[b] = L.take<char>(base, KC * es);
+    }
+    f->nsurv = L.take<int>(base, K * 4);
+    f->ncur = L.take<int>(base, K * 4);
+    f->clampctr = L.take<int>(base, 4);
+    f->zbuf = L.take<double>(base, Mx * 2 * 8);
+    f->p1s = L.take<double>(base, K * f->wtiles1 * Mx * 8);
+    f->p1h = L.take<int>(base, K * f->wtiles1 * Mx * 4);
+    f->p1w = L.take<double>(base, K * f->wtiles1 * 8);
+    f->zH = L.take<int>(base, K * Mx * 4);
+    f->zF = L.take<char>(base, K * Mx * es);
+    f->zC = L.take<double>(base, K * Mx * 8);
+    f->zdW = L.take<double>(base, K * Mx * 8);
+    f->zflag = L.take<int>(base, K * Mx * 4);
+    f->cand = L.take<int>(base, K * Mx * 4);
+    f->ncand = L.take<int>(base, K * 4);
+    f->p2mass = L.take<double>(base, K * f->wtiles2 * 8);
+    f->p2max = L.take<double>(base, K * f->wtiles2 * 8);
+    f->p2zeta = L.take<double>(base, K * f->wtiles2 * Mx * 5 * 8);
+    f->fmass = L.take<double>(base, K * 8);
+    f->fLT = L.take<int>(base, K * 4);
+    f->rsS = L.take<int>(base, K * 4);
+    f->sel = L.take<int>(base, K * Mx * 4);
+    f->zeta = L.take<double>(base, K * Mx * 4 * 8);
+    f->est = L.take<EstimateRec>(base, Mx * sizeof(EstimateRec));
+    f->nest = L.take<int>(base, 4);
+    f->tsum = L.take<double>(base, K * f->rtiles * 8);
+    f->massq = L.take<double>(base, K * 8);
+    f->counts = L.take<int>(base, KC * 4);
+    f->stage = L.take<char>(base, K * (size_t)f->Lmax * 5 * es);
+    return (L.off + 255) & ~(size_t)255;
+}
+
+void set_geometry(pphd_filter* f, const pphd_model* m, int64_t cap, int32_t max_meas)
+{
+    f->model = *m;
+    f->K = m->partitions;
+    f->cap = (int)cap;
+    f->max_meas = max_meas;
+    f->prec = m->precision;
+    f->esz = m->precision == PPHD_FP64 ? 8 : 4;
+    f->KC = (size_t)f->K * (size_t)cap;
+    const int pt1 = f->prec == PPHD_FP64 ? PT1_F64 : PT1_F32;
+    const int pt2 = f->prec == PPHD_FP64 ? PT2_F64 : PT2_F32;
+    f->wt1 = 64 * pt1;
+    f->wt2 = 64 * pt2;
+    f->wtiles1 = (int)((cap + f->wt1 - 1) / f->wt1);
+    f->wtiles2 = (int)((cap + f->wt2 - 1) / f->wt2);
+    f->rtiles = (int)((cap + 256 * PR - 1) / (256 * PR));
+    f->Lmax = (int)std::floor(m->exchange_fraction * (double)cap) + 1;
+}
+
+bool sizes_ok(const pphd_model* m, int64_t cap, int32_t max_meas, std::string& why)
+{
+    if (cap < 1 || cap > (1ll << 30) / 4) { why = "cap_per_partition out of range"; return false; }
+    if ((int64_t)m->partitions * cap > (1ll << 31) - 1) { why = "partitions * cap must fit in 31 bits"; return false; }
+    if (max_meas < 1 || max_meas > 65536) { why = "max_meas must be in [1, 65536]"; return false; }
+    const double Rj = m->particles_per_target / (double)m->partitions;
+    const int M0 = std::max(1, (int)std::floor(Rj + 0.5));
+    const int Jmax = m->births_per_step / m->partitions + (m->births_per_step % m->partitions ? 1 : 0);
+    if (M0 > cap) { why = "cap_per_partition < round(R/K) initial particles"; return false; }
+    if (Jmax >= cap) { why = "cap_per_partition must exceed the births per group"; return false; }
+    if ((int64_t)M0 + Jmax > cap) { why = "cap_per_partition < round(R/K) + births per group"; return false; }
+    return true;
+}
+
+void fill_devmodel(pphd_filter* f)
+{
+    const pphd_model& m = f->model;
+    DevModel& d = f->dm;
+    std::memset(&d, 0, sizeof d);
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    d.T = m.T;
+    d.sigma_a = m.sigma_a;
+    d.sx = m.sensor_x;
+    d.sy = m.sensor_y;
+    d.pS = m.p_S;
+    d.pD = m.p_D;
+    d.nu = 1.0 - m.p_D;
+    d.kappa = m.clutter_rate / ((m.r_max - m.r_min) * (m.th_max - m.th_min));
+    d.birth_mass = m.birth_mass;
+    d.reg0 = m.region[0];
+    d.reg1 = m.region[1];
+    d.reg2 = m.region[2];
+    d.reg3 = m.region[3];
+    d.sigma_v = m.birth_sigma_v;
+    d.init_mass = m.init_mass;
+    d.Rj = m.particles_per_target / (double)m.partitions;
+    d.xfrac = m.exchange_fraction;
+    const double c = std::sqrt(std::log2(std::exp(1.0)) / 2.0);
+    d.cr = c / m.sigma_r;
+    d.ct = c / m.sigma_theta;
+    d.period = two_pi * d.ct;
+    d.inv_period = 1.0 / d.period;
+    d.wscale = m.p_D / (two_pi * m.sigma_r * m.sigma_theta);
+    d.K = m.partitions;
+    d.J = m.births_per_step;
+    d.cap = f->cap;
+    d.M0 = std::max(1, (int)std::floor(d.Rj + 0.5));
+    d.key0 = (uint32_t)f->seed;
+    d.key1 = (uint32_t)(f->seed >> 32);
+    d.run = f->run;
+}
+
+template <typename T>
+SoA<T> soa(pphd_filter* f, int b)
+{
+    SoA<T> s;
+    for (int d = 0; d < 4; ++d) s.x[d] = (T*)f->X[b][d];
+    s.w = (T*)f->W[b];
+    return s;
+}
+
+hipEvent_t take_event(pphd_filter* f)
+{
+    if (!f->ev_pool.empty()) {
+        hipEvent_t e = f->ev_pool.back();
+        f->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch helper: optional start/stop events around the launch, then an error check.
+template <typename F>
+pphd_status launch(pphd_filter* f, int cls, F&& fn)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (f->timing) {
+        a = take_event(f);
+        b = take_event(f);
+        if (a && b) HIP_TRY(hipEventRecord(a, f->stream));
+    }
+    fn();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PPHD_EDEVICE, "%s launch failed: %s", kKernelNames[cls], hipGetErrorString(e));
+    if (f->timing && a && b) {
+        HIP_TRY(hipEventRecord(b, f->stream));
+        f->ev_used.push_back({ cls, { a, b } });
+    }
+    return PPHD_OK;
+}
+
+#define LAUNCH(f, cls, ...)                                          \
+    do {                                                             \
+        pphd_status s_ = launch(f, cls, [&]() { __VA_ARGS__; });     \
+        if (s_ != PPHD_OK) return s_;                                \
+    } while (0)
+
+template <typename T, int PT1, int PT2>
+pphd_status run_update(pphd_filter* f, const double* dz, int M)
+{
+    const DevModel dm = f->dm;
+    SoA<T> st = soa<T>(f, f->cur);
+    const int K = f->K, Mx = f->max_meas;
+    dim3 g1((f->wtiles1 + 3) / 4, K), g2((f->wtiles2 + 3) / 4, K);
+    LAUNCH(f, PPHD_K_CZ,
+           hipLaunchKernelGGL((k_cz<T, PT1>), g1, dim3(256), 0, f->stream, dm, st, f->ncur, dz, M, Mx, f->wtiles1,
+                              f->p1s, f->p1h, f->p1w));
+    LAUNCH(f, PPHD_K_CZ_COMBINE,
+           hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(256), (size_t)Mx * sizeof(double), f->stream, dm,
+                              f->ncur, M, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH, (T*)f->zF, f->zC,
+                              f->zdW, f->zflag, f->cand, f->ncand));
+    LAUNCH(f, PPHD_K_WEIGHT,
+           hipLaunchKernelGGL((k_weight<T, PT2>), g2, dim3(256), 0, f->stream, dm, st, f->ncur, dz, M, Mx,
+                              f->wtiles2, f->zH, (const T*)f->zF, f->zflag, f->cand, f->ncand, f->p2mass, f->p2max,
+                              f->p2zeta));
+    LAUNCH(f, PPHD_K_FINALIZE,
+           hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->ncur, M, Mx, f->wtiles2, f->wt2,
+                              f->p2mass, f->p2max, f->p2zeta, f->cand, f->ncand, f->fmass, f->fLT, f->rsS, f->sel,
+                              f->zeta));
+    return PPHD_OK;
+}
+
+template <typename T>
+pphd_status run_predict(pphd_filter* f, uint32_t step)
+{
+    dim3 g((f->cap + 255) / 256, f->K);
+    LAUNCH(f, PPHD_K_PREDICT,
+           hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, soa<T>(f, f->cur), f->nsurv, f->ncur,
+                              step));
+    return PPHD_OK;
+}
+
+template <typename T>
+pphd_status run_init(pphd_filter* f)
+{
+    dim3 g((f->dm.M0 + 255) / 256, f->K);
+    LAUNCH(f, PPHD_K_INIT,
+           hipLaunchKernelGGL((k_init<T>), g, dim3(256), 0, f->stream, f->dm, soa<T>(f, f->cur), f->nsurv));
+    return PPHD_OK;
+}
+
+template <typename T>
+pphd_status run_resample(pphd_filter* f, uint32_t step)
+{
+    dim3 g(f->rtiles, f->K);
+    SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
+    LAUNCH(f, PPHD_K_RS_TILES,
+           hipLaunchKernelGGL((k_rs_tiles<T, PR>), g, dim3(256), 0, f->stream, f->dm, (const T*)in.w, f->ncur, f->rsS,
+                              f->rtiles, f->tsum));
+    LAUNCH(f, PPHD_K_RS_EXPAND,
+           hipLaunchKernelGGL((k_rs_expand<T, PR>), g, dim3(256), 0, f->stream, f->dm, in, out, f->ncur, f->nsurv,
+                              f->rsS, f->tsum, f->rtiles, step, f->massq, f->clampctr, f->counts,
+                              f->record ? 1 : 0));
+    f->cur = 1 - f->cur;
+    return PPHD_OK;
+}
+
+template <typename T>
+pphd_status run_exchange(pphd_filter* f, uint32_t step)
+{
+    if (f->K < 2) return PPHD_OK;
+    dim3 g((f->Lmax + 255) / 256, f->K);
+    SoA<T> st = soa<T>(f, f->cur);
+    LAUNCH(f, PPHD_K_XCHG_GATHER,
+           hipLaunchKernelGGL((k_xchg_gather<T>), g, dim3(256), 0, f->stream, f->dm, st, f->nsurv, (T*)f->stage,
+                              f->Lmax, step));
+    LAUNCH(f, PPHD_K_XCHG_SCATTER,
+           hipLaunchKernelGGL((k_xchg_scatter<T>), g, dim3(256), 0, f->stream, f->dm, st, f->nsurv,
+                              (const T*)f->stage, f->Lmax, step));
+    return PPHD_OK;
+}
+
+pphd_status check_handle(pphd_filter* f)
+{
+    if (!f) return fail(PPHD_EINVAL, "filter handle is NULL");
+    return PPHD_OK;
+}
+
+#define CHECK_HANDLE(f)                          \
+    do {                                         \
+        pphd_status s_ = check_handle(f);        \
+        if (s_ != PPHD_OK) return s_;            \
+    } while (0)
+
+pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout)
+{
+    LAUNCH(f, PPHD_K_FUSE,
+           hipLaunchKernelGGL(k_fuse, dim3(1), dim3(256), 0, f->stream, f->K, f->last_m, f->max_meas, f->sel, f->zeta,
+                              out, cap, nout));
+    return PPHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pphd_last_error(void) { return g_err.c_str(); }
+
+const char* pphd_kernel_name(int32_t c) { return (c >= 0 && c < PPHD_K_COUNT) ? kKernelNames[c] : nullptr; }
+
+pphd_status pphd_workspace_size(const pphd_model* model, int64_t cap, int32_t max_meas, size_t* bytes)
+{
+    std::string why;
+    if (!model_ok(model, why) || !sizes_ok(model, cap, max_meas, why)) return fail(PPHD_EINVAL, "%s", why.c_str());
+    if (!bytes) return fail(PPHD_EINVAL, "bytes is NULL");
+    pphd_filter tmp;
+    set_geometry(&tmp, model, cap, max_meas);
+    *bytes = carve(&tmp, nullptr);
+    return PPHD_OK;
+}
+
+pphd_status pphd_create(const pphd_model* model, int64_t cap, int32_t max_meas, void* workspace,
+                        size_t workspace_bytes, uint64_t seed, uint32_t run_id, void* stream, pphd_filter** out)
+{
+    std::string why;
+    if (!out) return fail(PPHD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!model_ok(model, why) || !sizes_ok(model, cap, max_meas, why)) return fail(PPHD_EINVAL, "%s", why.c_str());
+    if (!workspace) return fail(PPHD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(PPHD_EINVAL, "workspace must be 256-byte aligned");
+    pphd_filter* f = new (std::nothrow) pphd_filter();
+    if (!f) return fail(PPHD_ENOMEM, "host allocation failed");
+    set_geometry(f, model, cap, max_meas);
+    const size_t need = carve(f, nullptr);
+    if (workspace_bytes < need) {
+        delete f;
+        return fail(PPHD_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    }
+    carve(f, (char*)workspace);
+    f->seed = seed;
+    f->run = run_id;
+    f->stream = (hipStream_t)stream;
+    fill_devmodel(f);
+    hipError_t e = hipHostMalloc((void**)&f->pin_z, (size_t)max_meas * 2 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete f;
+        return fail(PPHD_EDEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));
+    }
+    e = hipEventCreateWithFlags(&f->z_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(f->clampctr, 0, 4, f->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(f->nsurv, 0, (size_t)f->K * 4, f->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(f->ncur, 0, (size_t)f->K * 4, f->stream);
+    if (e != hipSuccess) {
+        (void)hipHostFree(f->pin_z);
+        delete f;
+        return fail(PPHD_EDEVICE, "filter set-up failed: %s", hipGetErrorString(e));
+    }
+    *out = f;
+    return PPHD_OK;
+}
+
+pphd_status pphd_destroy(pphd_filter* f)
+{
+    if (!f) return PPHD_OK;
+    (void)hipStreamSynchronize(f->stream);
+    if (f->pin_z) (void)hipHostFree(f->pin_z);
+    if (f->z_done) (void)hipEventDestroy(f->z_done);
+    for (auto& u : f->ev_used) {
+        (void)hipEventDestroy(u.second.first);
+        (void)hipEventDestroy(u.second.second);
+    }
+    for (auto e : f->ev_pool) (void)hipEventDestroy(e);
+    delete f;
+    return PPHD_OK;
+}
+
+pphd_status pphd_init(pphd_filter* f)
+{
+    CHECK_HANDLE(f);
+    f->cur = 0;
+    pphd_status s = f->prec == PPHD_FP64 ? run_init<double>(f) : run_init<float>(f);
+    if (s != PPHD_OK) return s;
+    f->phase = PPHD_PHASE_READY;
+    return PPHD_OK;
+}
+
+pphd_status pphd_predict(pphd_filter* f, uint32_t step)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_READY && f->phase != PPHD_PHASE_RESAMPLED)
+        return fail(PPHD_ESTATE, "predict needs phase READY or RESAMPLED (have %d)", f->phase);
+    pphd_status s = f->prec == PPHD_FP64 ? run_predict<double>(f, step) : run_predict<float>(f, step);
+    if (s != PPHD_OK) return s;
+    f->phase = PPHD_PHASE_PREDICTED;
+    return PPHD_OK;
+}
+
+pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on_device)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "update needs phase PREDICTED (have %d)", f->phase);
+    if (m < 0 || m > f->max_meas) return fail(PPHD_EINVAL, "m = %d outside [0, %d]", m, f->max_meas);
+    if (m > 0 && !z) return fail(PPHD_EINVAL, "z is NULL");
+    const double* dz = f->zbuf;
+    if (m > 0) {
+        if (z_on_device) {
+            dz = z;
+        } else {
+            if (f->z_pending) HIP_TRY(hipEventSynchronize(f->z_done));
+            std::memcpy(f->pin_z, z, (size_t)m * 2 * sizeof(double));
+            HIP_TRY(hipMemcpyAsync(f->zbuf, f->pin_z, (size_t)m * 2 * sizeof(double), hipMemcpyHostToDevice,
+                                   f->stream));
+            HIP_TRY(hipEventRecord(f->z_done, f->stream));
+            f->z_pending = true;
+        }
+    }
+    pphd_status s = f->prec == PPHD_FP64 ? run_update<double, PT1_F64, PT2_F64>(f, dz, m)
+                                         : run_update<float, PT1_F32, PT2_F32>(f, dz, m);
+    if (s != PPHD_OK) return s;
+    f->last_m = m;
+    f->phase = PPHD_PHASE_UPDATED;
+    return PPHD_OK;
+}
+
+pphd_status pphd_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t cap, int32_t* d_n_out)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
+        return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
+    if (!d_n_out || (cap > 0 && !d_out) || cap < 0) return fail(PPHD_EINVAL, "bad output buffers");
+    static_assert(sizeof(pphd_estimate) == sizeof(EstimateRec), "record layout");
+    return run_fuse(f, (EstimateRec*)d_out, cap, d_n_out);
+}
+
+pphd_status pphd_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out, double* mass)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
+        return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
+    if (!n_out || (cap > 0 && !out) || cap < 0) return fail(PPHD_EINVAL, "bad output buffers");
+    pphd_status s = run_fuse(f, f->est, f->max_meas, f->nest);
+    if (s != PPHD_OK) return s;
+    int n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, f->nest, 4, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    const int k = n < cap ? n : cap;
+    if (k > 0) HIP_TRY(hipMemcpy(out, f->est, (size_t)k * sizeof(pphd_estimate), hipMemcpyDeviceToHost));
+    if (mass) HIP_TRY(hipMemcpy(mass, f->fmass, (size_t)f->K * 8, hipMemcpyDeviceToHost));
+    *n_out = k;
+    return PPHD_OK;
+}
+
+pphd_status pphd_resample(pphd_filter* f, uint32_t step)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_UPDATED) return fail(PPHD_ESTATE, "resample needs phase UPDATED (have %d)", f->phase);
+    pphd_status s = f->prec == PPHD_FP64 ? run_resample<double>(f, step) : run_resample<float>(f, step);
+    if (s != PPHD_OK) return s;
+    f->phase = PPHD_PHASE_RESAMPLED;
+    return PPHD_OK;
+}
+
+pphd_status pphd_exchange(pphd_filter* f, uint32_t step)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_RESAMPLED) return fail(PPHD_ESTATE, "exchange needs phase RESAMPLED (have %d)", f->phase);
+    pphd_status s = f->prec == PPHD_FP64 ? run_exchange<double>(f, step) : run_exchange<float>(f, step);
+    if (s != PPHD_OK) return s;
+    f->phase = PPHD_PHASE_READY;
+    return PPHD_OK;
+}
+
+pphd_status pphd_read_state(pphd_filter* f, double* x, double* w, int32_t* count)
+{
+    CHECK_HANDLE(f);
+    if (f->phase == 0) return fail(PPHD_ESTATE, "filter has no state yet (call pphd_init or pphd_write_state)");
+    const bool current_is_cur = f->phase == PPHD_PHASE_PREDICTED || f->phase == PPHD_PHASE_UPDATED;
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    if (count) HIP_TRY(hipMemcpy(count, current_is_cur ? f->ncur : f->nsurv, (size_t)f->K * 4, hipMemcpyDeviceToHost));
+    std::vector<char> tmp;
+    auto fetch = [&](void* src, double* dst) -> pphd_status {
+        if (f->prec == PPHD_FP64) {
+            HIP_TRY(hipMemcpy(dst, src, f->KC * 8, hipMemcpyDeviceToHost));
+        } else {
+            tmp.resize(f->KC * 4);
+            HIP_TRY(hipMemcpy(tmp.data(), src, f->KC * 4, hipMemcpyDeviceToHost));
+            const float* p = (const float*)tmp.data();
+            for (size_t i = 0; i < f->KC; ++i) dst[i] = (double)p[i];
+        }
+        return PPHD_OK;
+    };
+    if (x)
+        for (int d = 0; d < 4; ++d) {
+            pphd_status s = fetch(f->X[f->cur][d], x + (size_t)d * f->KC);
+            if (s != PPHD_OK) return s;
+        }
+    if (w) {
+        pphd_status s = fetch(f->W[f->cur], w);
+        if (s != PPHD_OK) return s;
+    }
+    return PPHD_OK;
+}
+
+pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, const int32_t* count, int32_t phase)
+{
+    CHECK_HANDLE(f);
+    if (!x || !w || !count) return fail(PPHD_EINVAL, "x, w and count are required");
+    if (phase != PPHD_PHASE_READY && phase != PPHD_PHASE_RESAMPLED && phase != PPHD_PHASE_PREDICTED &&
+        phase != PPHD_PHASE_UPDATED)
+        return fail(PPHD_EINVAL, "unknown phase %d", phase);
+    for (int j = 0; j < f->K; ++j)
+        if (count[j] < 0 || count[j] > f->cap) return fail(PPHD_EINVAL, "count[%d] = %d outside [0, cap]", j, count[j]);
+    if (phase == PPHD_PHASE_READY || phase == PPHD_PHASE_RESAMPLED) {
+        const int Jj0 = f->dm.J / f->K + (f->dm.J % f->K ? 1 : 0);
+        for (int j = 0; j < f->K; ++j)
+            if (count[j] + Jj0 > f->cap) return fail(PPHD_EINVAL, "count[%d] leaves no room for births", j);
+    }
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    std::vector<float> tmp;
+    auto put = [&](void* dst, const double* src) -> pphd_status {
+        if (f->prec == PPHD_FP64) {
+            HIP_TRY(hipMemcpy(dst, src, f->KC * 8, hipMemcpyHostToDevice));
+        } else {
+            tmp.resize(f->KC);
+            for (size_t i = 0; i < f->KC; ++i) tmp[i] = (float)src[i];
+            HIP_TRY(hipMemcpy(dst, tmp.data(), f->KC * 4, hipMemcpyHostToDevice));
+        }
+        return PPHD_OK;
+    };
+    for (int d = 0; d < 4; ++d) {
+        pphd_status s = put(f->X[f->cur][d], x + (size_t)d * f->KC);
+        if (s != PPHD_OK) return s;
+    }
+    pphd_status s = put(f->W[f->cur], w);
+    if (s != PPHD_OK) return s;
+    const bool is_cur = phase == PPHD_PHASE_PREDICTED || phase == PPHD_PHASE_UPDATED;
+    HIP_TRY(hipMemcpy(is_cur ? f->ncur : f->nsurv, count, (size_t)f->K * 4, hipMemcpyHostToDevice));
+    if (phase == PPHD_PHASE_UPDATED) {
+        if (f->prec == PPHD_FP64) {
+            LAUNCH(f, PPHD_K_WMAX,
+                   hipLaunchKernelGGL((k_wmax<double>), dim3(f->K), dim3(256), 0, f->stream, f->dm,
+                                      (const double*)f->W[f->cur], f->ncur, f->rsS));
+        } else {
+            LAUNCH(f, PPHD_K_WMAX,
+                   hipLaunchKernelGGL((k_wmax<float>), dim3(f->K), dim3(256), 0, f->stream, f->dm,
+                                      (const float*)f->W[f->cur], f->ncur, f->rsS));
+        }
+        f->last_m = -1;  // no update results to extract from
+    }
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    f->phase = phase;
+    return PPHD_OK;
+}
+
+pphd_status pphd_read_update(pphd_filter* f, double* C, double* dW, double* mass, int32_t* LT)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
+        return fail(PPHD_ESTATE, "no update results (phase %d)", f->phase);
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    const int M = f->last_m;
+    for (int j = 0; j < f->K && M > 0; ++j) {
+        if (C) HIP_TRY(hipMemcpy(C + (size_t)j * M, f->zC + (size_t)j * f->max_meas, (size_t)M * 8, hipMemcpyDeviceToHost));
+        if (dW) HIP_TRY(hipMemcpy(dW + (size_t)j * M, f->zdW + (size_t)j * f->max_meas, (size_t)M * 8, hipMemcpyDeviceToHost));
+    }
+    if (mass) HIP_TRY(hipMemcpy(mass, f->fmass, (size_t)f->K * 8, hipMemcpyDeviceToHost));
+    if (LT) HIP_TRY(hipMemcpy(LT, f->fLT, (size_t)f->K * 4, hipMemcpyDeviceToHost));
+    return PPHD_OK;
+}
+
+pphd_status pphd_read_local(pphd_filter* f, int32_t* sel, double* zeta)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
+        return fail(PPHD_ESTATE, "no update results (phase %d)", f->phase);
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    const int M = f->last_m;
+    for (int j = 0; j < f->K && M > 0; ++j) {
+        if (sel) HIP_TRY(hipMemcpy(sel + (size_t)j * M, f->sel + (size_t)j * f->max_meas, (size_t)M * 4, hipMemcpyDeviceToHost));
+        if (zeta)
+            HIP_TRY(hipMemcpy(zeta + (size_t)j * M * 4, f->zeta + (size_t)j * f->max_meas * 4, (size_t)M * 32,
+                              hipMemcpyDeviceToHost));
+    }
+    return PPHD_OK;
+}
+
+pphd_status pphd_set_record_counts(pphd_filter* f, int32_t enable)
+{
+    CHECK_HANDLE(f);
+    f->record = enable != 0;
+    return PPHD_OK;
+}
+
+pphd_status pphd_read_resample(pphd_filter* f, int32_t* counts, double* mass_q, int64_t* clamped)
+{
+    CHECK_HANDLE(f);
+    if (f->phase != PPHD_PHASE_RESAMPLED && f->phase != PPHD_PHASE_READY)
+        return fail(PPHD_ESTATE, "no resample results (phase %d)", f->phase);
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    if (counts) HIP_TRY(hipMemcpy(counts, f->counts, f->KC * 4, hipMemcpyDeviceToHost));
+    if (mass_q) HIP_TRY(hipMemcpy(mass_q, f->massq, (size_t)f->K * 8, hipMemcpyDeviceToHost));
+    if (clamped) {
+        int c = 0;
+        HIP_TRY(hipMemcpy(&c, f->clampctr, 4, hipMemcpyDeviceToHost));
+        *clamped = c;
+    }
+    return PPHD_OK;
+}
+
+pphd_status pphd_set_timing(pphd_filter* f, int32_t enable)
+{
+    CHECK_HANDLE(f);
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    for (auto& u : f->ev_used) {
+        f->ev_pool.push_back(u.second.first);
+        f->ev_pool.push_back(u.second.second);
+    }
+    f->ev_used.clear();
+    for (int i = 0; i < PPHD_K_COUNT; ++i) {
+        f->acc_ms[i] = 0;
+        f->acc_n[i] = 0;
+    }
+    f->timing = enable != 0;
+    return PPHD_OK;
+}
+
+pphd_status pphd_read_timing(pphd_filter* f, double* ms, int64_t* launches)
+{
+    CHECK_HANDLE(f);
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    for (auto& u : f->ev_used) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, u.second.first, u.second.second));
+        f->acc_ms[u.first] += t;
+        f->acc_n[u.first] += 1;
+        f->ev_pool.push_back(u.second.first);
+        f->ev_pool.push_back(u.second.second);
+    }
+    f->ev_used.clear();
+    for (int i = 0; i < PPHD_K_COUNT; ++i) {
+        if (ms) ms[i] = f->acc_ms[i];
+        if (launches) launches[i] = f->acc_n[i];
+    }
+    return PPHD_OK;
+}
+
+}  // extern "C"

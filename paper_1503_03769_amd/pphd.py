@@ -1,0 +1,341 @@
+"""Python binding of libpphd (include/pphd.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+computation of its own; each stage of the filter runs in the library's HIP
+kernels.  PyTorch is used for device memory (the workspace) and for the
+stream handle.  If the built library is missing this module raises on first
+use -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpphd.so")
+_LIB = None
+
+PPHD_OK, PPHD_EINVAL, PPHD_ENOMEM, PPHD_ECAPACITY, PPHD_EDEVICE, PPHD_ESTATE = 0, -1, -2, -3, -4, -5
+PPHD_FP64, PPHD_FP32 = 0, 1
+PHASE_READY, PHASE_PREDICTED, PHASE_UPDATED, PHASE_RESAMPLED = 1, 2, 3, 4
+KERNEL_CLASSES = ["predict", "cz", "cz_combine", "weight", "finalize", "fuse", "rs_tiles", "rs_expand",
+                  "xchg_gather", "xchg_scatter", "init", "wmax"]
+K_COUNT = len(KERNEL_CLASSES)
+
+
+class PphdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pphd error {code}: {msg}")
+        self.code = code
+
+
+class pphd_model(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("partitions", ctypes.c_int32),
+        ("births_per_step", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("T", ctypes.c_double), ("sigma_a", ctypes.c_double),
+        ("sensor_x", ctypes.c_double), ("sensor_y", ctypes.c_double),
+        ("sigma_r", ctypes.c_double), ("sigma_theta", ctypes.c_double),
+        ("p_S", ctypes.c_double), ("p_D", ctypes.c_double),
+        ("clutter_rate", ctypes.c_double),
+        ("r_min", ctypes.c_double), ("r_max", ctypes.c_double),
+        ("th_min", ctypes.c_double), ("th_max", ctypes.c_double),
+        ("birth_mass", ctypes.c_double), ("region", ctypes.c_double * 4),
+        ("birth_sigma_v", ctypes.c_double), ("init_mass", ctypes.c_double),
+        ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
+    ]
+
+
+class pphd_estimate(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_double * 4), ("label", ctypes.c_int32), ("votes", ctypes.c_int32)]
+
+
+ESTIMATE_DTYPE = np.dtype([("state", np.float64, (4,)), ("label", np.int32), ("votes", np.int32)])
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I32, _I64, _U32, _U64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+_MP = ctypes.POINTER(pphd_model)
+SIGNATURES = {
+    "pphd_workspace_size": (_I32, [_MP, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "pphd_create": (_I32, [_MP, _I64, _I32, _P, _SZ, _U64, _U32, _P, ctypes.POINTER(_P)]),
+    "pphd_init": (_I32, [_P]),
+    "pphd_predict": (_I32, [_P, _U32]),
+    "pphd_update": (_I32, [_P, _P, _I32, _I32]),
+    "pphd_extract": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32), _P]),
+    "pphd_extract_device": (_I32, [_P, _P, _I32, _P]),
+    "pphd_resample": (_I32, [_P, _U32]),
+    "pphd_exchange": (_I32, [_P, _U32]),
+    "pphd_destroy": (_I32, [_P]),
+    "pphd_last_error": (ctypes.c_char_p, []),
+    "pphd_read_state": (_I32, [_P, _P, _P, _P]),
+    "pphd_write_state": (_I32, [_P, _P, _P, _P, _I32]),
+    "pphd_read_update": (_I32, [_P, _P, _P, _P, _P]),
+    "pphd_read_local": (_I32, [_P, _P, _P]),
+    "pphd_set_record_counts": (_I32, [_P, _I32]),
+    "pphd_read_resample": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
+    "pphd_set_timing": (_I32, [_P, _I32]),
+    "pphd_read_timing": (_I32, [_P, _P, _P]),
+    "pphd_kernel_name": (ctypes.c_char_p, [_I32]),
+}
+
+
+def lib():
+    """Loads libpphd.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _chk(rc):
+    if rc != PPHD_OK:
+        raise PphdError(rc, lib().pphd_last_error().decode())
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def model_struct(p: dict, precision: int) -> pphd_model:
+    m = pphd_model()
+    m.dim = 4
+    m.partitions = int(p["partitions"])
+    m.births_per_step = int(p["births_per_step"])
+    m.precision = int(precision)
+    for k in ("T", "sigma_a", "sensor_x", "sensor_y", "sigma_r", "sigma_theta", "p_S", "p_D",
+              "clutter_rate", "r_min", "r_max", "th_min", "th_max", "birth_mass",
+              "birth_sigma_v", "init_mass", "particles_per_target", "exchange_fraction"):
+        setattr(m, k, float(p[k]))
+    for i in range(4):
+        m.region[i] = float(p["region"][i])
+    return m
+
+
+# ---- one wrapper per entry point -------------------------------------------
+
+def pphd_workspace_size(model: pphd_model, cap: int, max_meas: int) -> int:
+    n = _SZ(0)
+    _chk(lib().pphd_workspace_size(ctypes.byref(model), cap, max_meas, ctypes.byref(n)))
+    return int(n.value)
+
+
+def pphd_create(model, cap, max_meas, workspace_ptr, workspace_bytes, seed, run_id, stream_ptr):
+    h = _P()
+    _chk(lib().pphd_create(ctypes.byref(model), cap, max_meas, workspace_ptr, workspace_bytes,
+                           seed, run_id, stream_ptr, ctypes.byref(h)))
+    return h
+
+
+def pphd_init(h):
+    _chk(lib().pphd_init(h))
+
+
+def pphd_predict(h, step):
+    _chk(lib().pphd_predict(h, step))
+
+
+def pphd_update(h, z, m, z_on_device):
+    _chk(lib().pphd_update(h, z, m, z_on_device))
+
+
+def pphd_extract(h, out_ptr, cap, mass_ptr=None):
+    n = _I32(0)
+    _chk(lib().pphd_extract(h, out_ptr, cap, ctypes.byref(n), mass_ptr))
+    return int(n.value)
+
+
+def pphd_extract_device(h, d_out_ptr, cap, d_n_ptr):
+    _chk(lib().pphd_extract_device(h, d_out_ptr, cap, d_n_ptr))
+
+
+def pphd_resample(h, step):
+    _chk(lib().pphd_resample(h, step))
+
+
+def pphd_exchange(h, step):
+    _chk(lib().pphd_exchange(h, step))
+
+
+def pphd_destroy(h):
+    _chk(lib().pphd_destroy(h))
+
+
+def pphd_read_state(h, x_ptr, w_ptr, count_ptr):
+    _chk(lib().pphd_read_state(h, x_ptr, w_ptr, count_ptr))
+
+
+def pphd_write_state(h, x_ptr, w_ptr, count_ptr, phase):
+    _chk(lib().pphd_write_state(h, x_ptr, w_ptr, count_ptr, phase))
+
+
+def pphd_read_update(h, C_ptr, dW_ptr, mass_ptr, LT_ptr):
+    _chk(lib().pphd_read_update(h, C_ptr, dW_ptr, mass_ptr, LT_ptr))
+
+
+def pphd_read_local(h, sel_ptr, zeta_ptr):
+    _chk(lib().pphd_read_local(h, sel_ptr, zeta_ptr))
+
+
+def pphd_set_record_counts(h, enable):
+    _chk(lib().pphd_set_record_counts(h, int(enable)))
+
+
+def pphd_read_resample(h, counts_ptr, massq_ptr):
+    c = _I64(0)
+    _chk(lib().pphd_read_resample(h, counts_ptr, massq_ptr, ctypes.byref(c)))
+    return int(c.value)
+
+
+def pphd_set_timing(h, enable):
+    _chk(lib().pphd_set_timing(h, int(enable)))
+
+
+def pphd_read_timing(h, ms_ptr, launches_ptr):
+    _chk(lib().pphd_read_timing(h, ms_ptr, launches_ptr))
+
+
+def pphd_last_error():
+    return lib().pphd_last_error().decode()
+
+
+def pphd_kernel_name(c):
+    r = lib().pphd_kernel_name(c)
+    return r.decode() if r else None
+
+
+# ---- convenience object (allocation through torch, arrays through numpy) ---
+
+class Filter:
+    """One filter run on the current torch device and stream.
+
+    The workspace is a torch uint8 tensor; host-side results come back as
+    numpy arrays.  Methods map one-to-one onto the C entry points."""
+
+    def __init__(self, params: dict, precision: int, cap: int, max_meas: int, seed: int, run_id: int = 0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.K = int(params["partitions"])
+        self.cap = int(cap)
+        self.max_meas = int(max_meas)
+        self.precision = int(precision)
+        self.model = model_struct(params, precision)
+        nbytes = pphd_workspace_size(self.model, self.cap, self.max_meas)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = pphd_create(self.model, self.cap, self.max_meas, aligned, nbytes, int(seed), int(run_id),
+                             self.stream.cuda_stream)
+        self.last_m = 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            pphd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # stages
+    def init(self):
+        pphd_init(self.h)
+
+    def predict(self, step):
+        pphd_predict(self.h, int(step))
+
+    def update(self, Z):
+        """Z: numpy array [m, 2] (host) or a torch CUDA float64 tensor [m, 2]."""
+        if isinstance(Z, np.ndarray):
+            Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(-1, 2)
+            m = Z.shape[0]
+            pphd_update(self.h, Z.ctypes.data if m > 0 else None, m, 0)
+        else:
+            assert Z.is_cuda and Z.dtype == self.torch.float64 and Z.is_contiguous()
+            m = Z.shape[0]
+            pphd_update(self.h, Z.data_ptr() if m > 0 else None, m, 1)
+        self.last_m = m
+
+    def extract(self):
+        cap = max(self.max_meas, 1)
+        out = np.zeros(cap, dtype=ESTIMATE_DTYPE)
+        mass = np.zeros(self.K)
+        n = pphd_extract(self.h, out.ctypes.data, cap, mass.ctypes.data)
+        return out[:n].copy(), mass
+
+    def extract_device(self, d_out, d_n, cap):
+        pphd_extract_device(self.h, d_out.data_ptr(), cap, d_n.data_ptr())
+
+    def resample(self, step):
+        pphd_resample(self.h, int(step))
+
+    def exchange(self, step):
+        pphd_exchange(self.h, int(step))
+
+    # state access
+    def read_state(self):
+        KC = self.K * self.cap
+        X = np.zeros((4, KC))
+        W = np.zeros(KC)
+        n = np.zeros(self.K, dtype=np.int32)
+        pphd_read_state(self.h, X.ctypes.data, W.ctypes.data, n.ctypes.data)
+        return X, W, n
+
+    def write_state(self, X, W, n, phase):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        n = np.ascontiguousarray(n, dtype=np.int32)
+        assert X.shape == (4, self.K * self.cap) and W.shape == (self.K * self.cap,) and n.shape == (self.K,)
+        pphd_write_state(self.h, X.ctypes.data, W.ctypes.data, n.ctypes.data, int(phase))
+
+    def read_update(self):
+        M = self.last_m
+        C = np.zeros(max(self.K * M, 1))
+        dW = np.zeros(max(self.K * M, 1))
+        mass = np.zeros(self.K)
+        LT = np.zeros(self.K, dtype=np.int32)
+        pphd_read_update(self.h, C.ctypes.data, dW.ctypes.data, mass.ctypes.data, LT.ctypes.data)
+        return dict(C=C[:self.K * M].reshape(self.K, M), dW=dW[:self.K * M].reshape(self.K, M), mass=mass, LT=LT)
+
+    def read_local(self):
+        M = self.last_m
+        sel = np.zeros(max(self.K * M, 1), dtype=np.int32)
+        zeta = np.zeros(max(self.K * M * 4, 1))
+        pphd_read_local(self.h, sel.ctypes.data, zeta.ctypes.data)
+        return dict(sel=sel[:self.K * M].reshape(self.K, M), zeta=zeta[:self.K * M * 4].reshape(self.K, M, 4))
+
+    def set_record_counts(self, enable=True):
+        pphd_set_record_counts(self.h, enable)
+
+    def read_resample(self):
+        counts = np.zeros(self.K * self.cap, dtype=np.int32)
+        mq = np.zeros(self.K)
+        clamped = pphd_read_resample(self.h, counts.ctypes.data, mq.ctypes.data)
+        return counts, mq, clamped
+
+    def set_timing(self, enable=True):
+        pphd_set_timing(self.h, enable)
+
+    def read_timing(self):
+        ms = np.zeros(K_COUNT)
+        n = np.zeros(K_COUNT, dtype=np.int64)
+        pphd_read_timing(self.h, ms.ctypes.data, n.ctypes.data)
+        return {KERNEL_CLASSES[i]: (float(ms[i]), int(n[i])) for i in range(K_COUNT)}

@@ -1,0 +1,142 @@
+"""Whole-step parity of the HIP path: the FP64 filter against the oracle over a
+full run, the full-size FP32 launch configuration on sampled groups, and
+determinism."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1503_03769_amd import pphd
+from paper_1503_03769_amd.scenario import BASE_MODEL, WORKLOADS, make_scenario, random_particles, workload_seed
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_both(p, prec, cap, steps, n_targets, seed, max_meas=256, start_box=None):
+    kw = {} if start_box is None else dict(start_box=start_box, start_sigma_v=2.0)
+    truth, Z = make_scenario(p, n_targets, steps, seed, **kw)
+    f = P.make_filter(p, prec, cap, max_meas=max_meas, seed=seed, run=3)
+    f.init()
+    o = orc.OracleFilter(p, cap, seed, 3)
+    for k in range(1, steps + 1):
+        print(f"  step {k}", flush=True)
+        f.predict(k)
+        f.update(Z[k])
+        ug = f.read_update()
+        est_g, _ = f.extract()
+        f.resample(k)
+        f.exchange(k)
+        out = o.step(k, Z[k])
+        yield k, f, o, ug, est_g, out
+
+
+@pytest.mark.parametrize("name,K,steps", [("plain_fp64_3tgt", 1, 50), ("four_groups_fp64", 4, 20)])
+def test_fp64_run_matches_oracle(gpu, name, K, steps):
+    """Free-running FP64 filter: every step's masses, estimates, group sizes
+    and the final particle set agree with the oracle."""
+    print(f"end-to-end {name}", flush=True)
+    if name == "plain_fp64_3tgt":
+        w = WORKLOADS[name]
+        p, cap, ntg, box = w["model"], w["cap"], w["n_targets"], None
+        seed = workload_seed(w["config_index"], 0)
+    else:
+        box = (400.0, 600.0, 400.0, 600.0)
+        p = dict(BASE_MODEL, partitions=K, particles_per_target=400.0 * K, births_per_step=400 * K,
+                 region=box, birth_sigma_v=3.0, sigma_a=1.0)
+        cap, ntg, seed = 6000, 3, 4321
+        box = (450.0, 550.0, 450.0, 550.0)
+    for k, f, o, ug, est_g, out in _run_both(p, "fp64", cap, steps, ntg, seed, start_box=box):
+        np.testing.assert_allclose(ug["mass"], out["upd"]["mass"], rtol=1e-9, atol=1e-300)
+        assert list(est_g["label"]) == list(out["est"]["label"]), k
+        if len(est_g):
+            np.testing.assert_allclose(est_g["state"], out["est"]["state"], rtol=1e-9, atol=1e-9)
+        Xg, Wg, ng = f.read_state()
+        assert np.array_equal(ng, o.st.n), (k, ng, o.st.n)
+    P.check_states(Xg, Wg, ng, o.st, "fp64", rtol=1e-9)
+    f.close()
+
+
+def test_full_size_fp32_sampled_groups(gpu):
+    """The benchmark's launch configuration (64 groups, ~16k particles each,
+    ~60 measurements): C, weights and masses of sampled groups against the
+    oracle run on those groups alone; the mass identity on every group."""
+    w = WORKLOADS["large_fp32_10tgt_k64"]
+    p, cap, K = w["model"], w["cap"], 64
+    truth, Z = make_scenario(p, w["n_targets"], 12, workload_seed(w["config_index"], 0))
+    k = max(range(1, 13), key=lambda i: len(truth[i]))
+    tk, zk = truth[k], Z[k]
+    rng = np.random.default_rng(5)
+    counts = rng.integers(15000, 17500, size=K).astype(np.int32)
+    counts[7] = 0
+    X, W, n = P.cloud(K, cap, counts, 61, tk, "fp32")
+    f = P.make_filter(p, "fp32", cap, max_meas=w["max_meas"])
+    f.write_state(X, W, n, pphd.PHASE_PREDICTED)
+    f.update(zk)
+    Xg, Wg, ng = f.read_state()
+    ug = f.read_update()
+    kappa = orc.kappa(p)
+    # identity on every group: sum w' = nu sum w + sum_p C/(kappa + C)
+    for j in range(K):
+        sl = slice(j * cap, j * cap + int(n[j]))
+        rhs = (1 - p["p_D"]) * W[sl].sum() + (ug["C"][j] / (kappa + ug["C"][j])).sum()
+        assert abs(ug["mass"][j] - rhs) <= 1e-5 * max(rhs, 1e-12)
+    p1 = dict(p, partitions=1)
+    for j in (0, 7, 33, 63):
+        print(f"  group {j}", flush=True)
+        st = orc.State(1, cap)
+        st.X[:] = X[:, j * cap:(j + 1) * cap]
+        st.W[:] = W[j * cap:(j + 1) * cap]
+        st.n[0] = n[j]
+        uo = orc.update(p1, st, zk)
+        P.check_cz(ug["C"][j:j + 1], uo["C"], kappa, "fp32")
+        sub = orc.State(1, cap)
+        sub.W[:] = st.W
+        sub.n[0] = n[j]
+        P.check_weights(Wg[j * cap:(j + 1) * cap], sub)
+        assert abs(ug["mass"][j] - uo["mass"][0]) <= 1e-6 * max(uo["mass"][0], 1e-300)
+    f.close()
+
+
+def test_full_size_resample_exact(gpu):
+    """Resampling counts at the benchmark's size, every group, exact."""
+    w = WORKLOADS["large_fp32_10tgt_k64"]
+    p, cap, K = w["model"], w["cap"], 64
+    rng = np.random.default_rng(9)
+    counts = rng.integers(14000, 17000, size=K).astype(np.int32)
+    X, W, n = P.cloud(K, cap, counts, 71, None, "fp32")
+    f = P.make_filter(p, "fp32", cap, max_meas=w["max_meas"])
+    f.set_record_counts(True)
+    f.write_state(X, W, n, pphd.PHASE_UPDATED)
+    f.resample(5)
+    cg, mqg, clamped = f.read_resample()
+    Xg, Wg, ng = f.read_state()
+    st = P.oracle_state(K, cap, X, W, n)
+    out, co, mqo = orc.resample(p, st, 5, 1234, 0)
+    assert np.array_equal(ng, out.n)
+    for j in range(K):
+        sl = slice(j * cap, j * cap + int(n[j]))
+        assert np.array_equal(cg[sl], co[sl]), f"group {j}: counts differ"
+    for j in range(0, K, 9):
+        sl = slice(j * cap, j * cap + int(out.n[j]))
+        assert np.array_equal(Xg[:, sl], out.X[:, sl])
+    f.close()
+
+
+def test_runs_are_deterministic(gpu):
+    """No floating-point atomics: two runs give bit-identical particle sets."""
+    p = dict(BASE_MODEL, partitions=8, particles_per_target=2.0e4, births_per_step=4000, clutter_rate=50.0)
+    truth, Z = make_scenario(p, 6, 5, 3)
+    res = []
+    for _ in range(2):
+        f = P.make_filter(p, "fp32", 8192, max_meas=512, seed=77)
+        f.init()
+        for k in range(1, 6):
+            f.predict(k)
+            f.update(Z[k])
+            f.extract()
+            f.resample(k)
+            f.exchange(k)
+        res.append(f.read_state())
+        f.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
