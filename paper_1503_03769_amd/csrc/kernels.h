@@ -199,18 +199,20 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, SoA<T> st, const int* __
     const size_t pbase = ((size_t)j * wtiles + wtile) * Mmax;
     for (int p = 0; p < M; ++p) {
         const double zr = Z[2 * p] * m.cr, zt = Z[2 * p + 1] * m.ct;
-        T a[PT];
-        T amax = -__builtin_inf();
+        // exponents stay in double until the shift is removed: far from every
+        // particle they reach -1e3 and more, where a float has lost 1e-4
+        double a[PT];
+        double amax = -__builtin_inf();
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
-            a[i] = -(T)sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]);
+            a[i] = -sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]);
             amax = a[i] > amax ? a[i] : amax;
         }
-        amax = wave_max(amax);
-        const T h = (amax == -__builtin_inf()) ? (T)0 : ceil(amax);
+        const float wmax = wave_max((float)amax);
+        const double h = (wmax == -__builtin_inff()) ? 0.0 : (double)ceilf(wmax);
         T s = 0;
 #pragma unroll
-        for (int i = 0; i < PT; ++i) s += fast_exp2(a[i] - h);
+        for (int i = 0; i < PT; ++i) s += fast_exp2((T)(a[i] - h));
         const double sd = wave_sum((double)s);
         if (lane == 0) {
             ps[pbase + p] = sd;

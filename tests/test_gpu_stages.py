@@ -59,7 +59,9 @@ def test_update_extract(gpu, case):
     print(f"update {label}", flush=True)
     cap = max(counts) + 512
     p = dict(BASE_MODEL, partitions=K, clutter_rate=lam, p_D=pD)
-    truth, Z = _scen(dict(p, clutter_rate=max(lam, 10.0)), n=ntg)
+    # with kappa = 0 every measurement must lie within FP64 range of some
+    # particle, or the oracle's C underflows to 0 and Eq 12 becomes 0/0
+    truth, Z = _scen(dict(p, clutter_rate=lam if lam == 0.0 else max(lam, 10.0)), n=ntg)
     if max_meas == 64:
         rng = np.random.default_rng(4)
         extra = np.column_stack([rng.uniform(0, 2000, 64), rng.uniform(-math.pi, math.pi, 64)])
@@ -97,7 +99,7 @@ def test_update_extract(gpu, case):
 RESAMPLE_CASES = [
     ("fp64", 1, [3500], 1000.0, 500, 8192, "one group FP64"),
     ("fp32", 5, [9000, 5000, 1, 0, 2048], 5000.0, 250, 12000, "FP32 ragged groups"),
-    ("fp32", 2, [4000, 4000], 4.0e6, 100, 6000, "clamped to capacity"),
+    ("fp32", 2, [4000, 4000], 4000.0, 100, 6000, "clamped to capacity"),
     ("fp64", 2, [2048, 1000], 1000.0, 0, 4096, "equal weights"),
 ]
 
@@ -110,6 +112,8 @@ def test_resample_counts_exact(gpu, case):
     X, W, n = P.cloud(K, cap, counts, 33, None, prec)
     if label == "equal weights":
         W[:] = 1.0 / 1024
+    if label == "clamped to capacity":
+        W = P.as_storage(W * 10.0, prec)   # mass ~ 13: round(N R_j) far above cap - J_j
     f = P.make_filter(p, prec, cap)
     f.set_record_counts(True)
     f.write_state(X, W, n, pphd.PHASE_UPDATED)
@@ -153,6 +157,26 @@ def test_exchange_exact(gpu, prec, K, counts):
         assert np.array_equal(Xg[:, sl], st.X[:, sl])
         assert np.array_equal(Wg[sl], st.W[sl])
     f.close()
+
+
+def test_no_clutter_far_measurement_keeps_unit_mass(gpu):
+    """kappa = 0 and p_D = 1: each measurement hands exactly one unit of mass
+    to the particles (the sum over i of the Eq 12 terms is C/C = 1), even for
+    a measurement so far from every particle that its C underflows double
+    precision -- the integer-shift scaling of the first pass keeps it."""
+    p = dict(BASE_MODEL, partitions=2, clutter_rate=0.0, p_D=1.0)
+    cap = 4096
+    X, W, n = P.cloud(2, cap, [3000, 2500], 8, None, "fp32")
+    X[0, :] = np.clip(X[0, :], -900, -500)            # particles only in x < -500
+    Z = np.array([[1900.0, 0.01], [1950.0, 0.5], [600.0, 3.0]])   # far to the east / north-west
+    for prec in ("fp32", "fp64"):
+        f = P.make_filter(p, prec, cap)
+        f.write_state(P.as_storage(X, prec), P.as_storage(W, prec), n, pphd.PHASE_PREDICTED)
+        f.update(Z)
+        u = f.read_update()
+        np.testing.assert_allclose(u["mass"], [3.0, 3.0], rtol=1e-5)
+        assert np.all(np.isfinite(f.read_state()[1]))
+        f.close()
 
 
 def test_call_order_and_argument_errors(gpu):
