@@ -1,0 +1,221 @@
+"""Benchmark of the distributed particle PHD filter step on one MI355X.
+
+One step = the whole per-step recursion through the C ABI on one stream:
+predict (+births) -> update (C(z) pass, combine, weight pass, finalize) ->
+extract (fusion, estimates to device memory) -> resample -> exchange.
+All measurement sets are resident in device memory before timing starts.
+
+Prints one JSON line:
+  value        particle x measurement updates per second (sum over timed steps
+               of N_k * M_k, divided by the timed wall time)
+  steps_per_s  filter steps per second
+  roofline     the dominant kernel against the VALU issue rate
+  cpu_baseline the FP64 oracle on the host for a bounded sample of the run
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU issue peak of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-operations per second (non-packed FP32 / FP64 instructions).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic issue slots of one likelihood evaluation of a particle-measurement
+# pair: 2 residuals, 2 for the bearing wrap, 2 fused multiply-adds for the
+# Mahalanobis term, 1 accumulate, plus one exponential at quarter rate (4).
+SLOTS_PER_PAIR_EVAL = 11
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=90)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large_fp32_10tgt_k64")
+    ap.add_argument("--run", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="bound on the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--no-timing-pass", action="store_true",
+                    help="skip the HIP-event pass (for profiler runs)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1503_03769_amd import pphd
+    from paper_1503_03769_amd.metrics import ospa, positions
+    from paper_1503_03769_amd.scenario import WORKLOADS, make_scenario, workload_seed
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    p = w["model"]
+    prec = pphd.PPHD_FP32 if w["precision"] == "fp32" else pphd.PPHD_FP64
+    total = args.warmup + args.steps
+    seed = workload_seed(w["config_index"], args.run)
+    truth, Z = make_scenario(p, w["n_targets"], max(total, w["steps"]), seed)
+    Ms = [Z[k].shape[0] for k in range(len(Z))]
+    assert max(Ms) <= w["max_meas"]
+    # measurement sets resident in HBM before timing
+    offs = np.concatenate([[0], np.cumsum(Ms)])
+    zall = torch.from_numpy(np.concatenate([Z[k] for k in range(len(Z))]).reshape(-1, 2)).cuda()
+    cap_est = w["max_meas"]
+    est_dev = torch.zeros((total + 1, cap_est * 40), dtype=torch.uint8, device="cuda")
+    nest_dev = torch.zeros(total + 1, dtype=torch.int32, device="cuda")
+
+    def make():
+        return pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, args.run)
+
+    def step(f, k):
+        f.predict(k)
+        f.update(zall[offs[k]:offs[k + 1]])
+        f.extract_device(est_dev[k], nest_dev[k:k + 1], cap_est)
+        f.resample(k)
+        f.exchange(k)
+
+    # ---- pass A: timed ------------------------------------------------------
+    f = make()
+    f.init()
+    for k in range(1, args.warmup + 1):
+        step(f, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup + 1, total + 1):
+        step(f, k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f.close()
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # ---- pass B: same run, per-kernel HIP-event times and particle counts ----
+    kern = {}
+    pairs = []
+    parts = []
+    if not args.no_timing_pass:
+        g = make()
+        g.init()
+        for k in range(1, total + 1):
+            if k == args.warmup + 1:
+                g.set_timing(True)
+            g.predict(k)
+            if k > args.warmup:
+                n = g.read_counts()
+                pairs.append(int(n.sum()) * Ms[k])
+                parts.append(int(n.sum()))
+            g.update(zall[offs[k]:offs[k + 1]])
+            g.extract_device(est_dev[k], nest_dev[k:k + 1], cap_est)
+            g.resample(k)
+            g.exchange(k)
+        kern = g.read_timing()
+        g.close()
+
+    # estimates of the timed run -> OSPA against the truth
+    nest = nest_dev.cpu().numpy()
+    raw = est_dev.cpu().numpy()
+    ospas = []
+    for k in range(args.warmup + 1, total + 1):
+        recs = np.frombuffer(raw[k].tobytes(), dtype=pphd.ESTIMATE_DTYPE)[:min(int(nest[k]), cap_est)]
+        ospas.append(ospa(positions(recs["state"]), positions(truth[k])))
+
+    value = float(sum(pairs)) / elapsed if pairs else None
+    line = {
+        "metric": "particle x measurement updates/sec (also filter steps/sec and OSPA) at 1 GPU",
+        "value": value,
+        "unit": "pair-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "steps_per_s": 1e3 / ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == pphd.PPHD_FP32 else "f64",
+        "data": "synthetic (seeded truth tracks, detections and Poisson clutter)",
+        "config": {
+            "workload": args.workload,
+            "partitions": int(p["partitions"]),
+            "targets": int(w["n_targets"]),
+            "clutter_rate": float(p["clutter_rate"]),
+            "births_per_step": int(p["births_per_step"]),
+            "particles_per_target": float(p["particles_per_target"]),
+            "mean_particles": float(np.mean(parts)) if parts else None,
+            "mean_measurements": float(np.mean([Ms[k] for k in range(args.warmup + 1, total + 1)])),
+            "parallelism": "64 particle partitions on one GPU",
+        },
+        "ospa_mean": float(np.mean(ospas)),
+        "ospa_params": {"p": 1, "c": 100.0},
+    }
+    if kern:
+        per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
+        line["kernels"] = per
+        # dominant kernel: the larger of the two likelihood passes
+        dom = max(("cz", "weight"), key=lambda c: kern[c][0])
+        ms, n = kern[dom]
+        avg_s = ms / 1e3 / n
+        pairs_per_launch = float(np.mean(pairs))
+        achieved = SLOTS_PER_PAIR_EVAL * pairs_per_launch / avg_s / 1e12
+        line["roofline"] = {
+            "kernel": pphd.pphd_kernel_name(pphd.KERNEL_CLASSES.index(dom)),
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": None,
+            "avg_launch_us": avg_s * 1e6,
+            "work_per_launch": f"{pairs_per_launch:.4g} pairs x {SLOTS_PER_PAIR_EVAL} issue slots",
+        }
+    if args.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(p, w, truth, Z, seed, args.run, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(p, w, truth, Z, seed, run, budget_s):
+    """The FP64 oracle, single thread, on the same workload from t = 0 for as
+    many steps as fit in about budget_s seconds."""
+    import oracle as orc
+    o = orc.OracleFilter(p, w["cap"], seed, run)
+    pairs = 0
+    steps = 0
+    t0 = time.perf_counter()
+    for k in range(1, len(Z)):
+        orc.predict(p, o.st, k, seed, run)
+        pairs += int(o.st.n.sum()) * Z[k].shape[0]
+        upd = orc.update(p, o.st, Z[k])
+        ext = orc.extract(p, Z[k].shape[0], upd)
+        orc.fuse(p, Z[k].shape[0], ext)
+        o.st, _, _ = orc.resample(p, o.st, k, seed, run)
+        orc.exchange(p, o.st, k, seed, run)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": pairs / el, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} steps of the same run (seed {seed}), FP64 C oracle, one thread",
+            "steps_per_s": steps / el, "cpu": cpu}
+
+
+if __name__ == "__main__":
+    main()

@@ -207,7 +207,8 @@ enum {
     PPHD_K_PREDICT = 0, PPHD_K_CZ = 1, PPHD_K_CZ_COMBINE = 2, PPHD_K_WEIGHT = 3,
     PPHD_K_FINALIZE = 4, PPHD_K_FUSE = 5, PPHD_K_RS_TILES = 6, PPHD_K_RS_EXPAND = 7,
     PPHD_K_XCHG_GATHER = 8, PPHD_K_XCHG_SCATTER = 9, PPHD_K_INIT = 10, PPHD_K_WMAX = 11,
-    PPHD_K_COUNT = 12
+    PPHD_K_GEOM = 12, PPHD_K_WFINAL = 13, PPHD_K_FUSE_COMPACT = 14, PPHD_K_CAND = 15,
+    PPHD_K_COUNT = 16
 };
 
 /* Enables (1) or disables (0) per-launch HIP-event timing on the filter's

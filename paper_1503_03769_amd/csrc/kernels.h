@@ -39,28 +39,88 @@ __device__ __forceinline__ int births_in(const DevModel& m, int j)
 }
 
 // ---------------------------------------------------------------------------
-// wavefront reductions (64 lanes)
+// wavefront reductions (64 lanes, all lanes active).  Within each row of 16
+// lanes the data-parallel-primitive (DPP) lane swizzles combine neighbours in
+// four steps (quad swaps, half-row and row mirrors); the four row results are
+// then read into scalars and combined, so every lane gets the same value and
+// the tree order is fixed (results are reproducible).
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// index of this thread's wavefront in the workgroup, as a wave-uniform value
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140
 template <typename V>
 __device__ __forceinline__ V wave_sum(V v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
+template <typename V>
+__device__ __forceinline__ V vmax(V a, V b) { return a > b ? a : b; }
 template <typename V>
 __device__ __forceinline__ V wave_max(V v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        V u = __shfl_xor(v, o, 64);
-        v = u > v ? u : v;
-    }
-    return v;
+    v = vmax(v, dpp<0xB1>(v));
+    v = vmax(v, dpp<0x4E>(v));
+    v = vmax(v, dpp<0x141>(v));
+    v = vmax(v, dpp<0x140>(v));
+    return vmax(vmax(lane_value(v, 0), lane_value(v, 16)), vmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double fast_exp2(double x) { return exp2(x); }
+
+// inclusive prefix sum over the 64 lanes: row_shr 1, 2, 4, 8 within each row of
+// 16 lanes (a missing source lane reads 0), then the row totals are added to
+// the rows above them
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v) { return dpp<CTRL>(v); }
+__device__ __forceinline__ double wave_incl_scan(double v)
+{
+    const int lane = threadIdx.x & 63;
+    v += dpp<0x111>(v);
+    v += dpp<0x112>(v);
+    v += dpp<0x114>(v);
+    v += dpp<0x118>(v);
+    const double r0 = lane_value(v, 15), r1 = lane_value(v, 31), r2 = lane_value(v, 47);
+    const int row = lane >> 4;
+    if (row >= 1) v += r0;
+    if (row >= 2) v += r1;
+    if (row >= 3) v += r2;
+    return v;
+}
 
 // ---------------------------------------------------------------------------
 // draws from the normalised birth density: position uniform over the region,
@@ -100,11 +160,31 @@ __global__ __launch_bounds__(256) void k_init(DevModel m, SoA<T> st, int* __rest
 }
 
 // ---------------------------------------------------------------------------
+// Per-particle geometry used by the two likelihood passes, in scaled units:
+// rho' = |p - s| c_r, phi' = atan2 c_t, and lw = log2(wscale w) (-inf for
+// w = 0).  Written by predict (and by k_geom when the state comes from the
+// host), so the passes never evaluate sqrt/atan2/log.
+// ---------------------------------------------------------------------------
+struct Geo {
+    double* rho;
+    double* phi;
+    double* lw;
+};
+
+__device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_t g, double x, double y, double w)
+{
+    const double dx = x - m.sx, dy = y - m.sy;
+    geo.rho[g] = sqrt(dx * dx + dy * dy) * m.cr;
+    geo.phi[g] = atan2(dy, dx) * m.ct;
+    geo.lw[g] = (w > 0.0) ? log2(m.wscale * w) : -__builtin_inf();
+}
+
+// ---------------------------------------------------------------------------
 // Step 1 (Eqs 5, 6): survivors through the CV model, births appended.
 // grid (ceil(cap/256), K)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_predict(DevModel m, SoA<T> st, const int* __restrict__ nsurv,
+__global__ __launch_bounds__(256) void k_predict(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
                                                  int* __restrict__ ncur, uint32_t step)
 {
     const int j = blockIdx.y;
@@ -116,33 +196,43 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, SoA<T> st, const in
     if (blockIdx.x == 0 && threadIdx.x == 0) ncur[j] = total;
     if (s >= total) return;
     const size_t g = (size_t)j * m.cap + s;
+    double v[4], w;
     if (s < ns) {
         Block4 r = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_PREDICT, 0, m.run);
         double n1, n2;
         normal_pair(uniform53(r.a, r.b), uniform53(r.c, r.d), n1, n2);
         const double ax = m.sigma_a * n1, ay = m.sigma_a * n2;
         const double half_t2 = m.T * m.T / 2;
-        double x = st.x[0][g], vx = st.x[1][g], y = st.x[2][g], vy = st.x[3][g];
-        st.x[0][g] = (T)(x + m.T * vx + half_t2 * ax);
-        st.x[1][g] = (T)(vx + m.T * ax);
-        st.x[2][g] = (T)(y + m.T * vy + half_t2 * ay);
-        st.x[3][g] = (T)(vy + m.T * ay);
-        st.w[g] = (T)(m.pS * (double)st.w[g]);
+        const double x = st.x[0][g], vx = st.x[1][g], y = st.x[2][g], vy = st.x[3][g];
+        v[0] = x + m.T * vx + half_t2 * ax;
+        v[1] = vx + m.T * ax;
+        v[2] = y + m.T * vy + half_t2 * ay;
+        v[3] = vy + m.T * ay;
+        w = m.pS * (double)st.w[g];
     } else {
-        double v[4];
         draw_birth(m, (uint32_t)g, step, RNG_BIRTH, v);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) st.x[d][g] = (T)v[d];
-        st.w[g] = (T)(m.birth_mass / (double)Jj);
+        w = m.birth_mass / (double)Jj;
     }
+    T t[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        t[d] = (T)v[d];
+        st.x[d][g] = t[d];
+    }
+    const T tw = (T)w;
+    st.w[g] = tw;
+    store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
 }
 
-// per-particle geometry in scaled units
-__device__ __forceinline__ void geometry(const DevModel& m, double x, double y, double& rho, double& phi)
+// geometry of a state written from the host.  grid (ceil(cap/256), K)
+template <typename T>
+__global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ ncur)
 {
-    const double dx = x - m.sx, dy = y - m.sy;
-    rho = sqrt(dx * dx + dy * dy) * m.cr;
-    phi = atan2(dy, dx) * m.ct;
+    const int j = blockIdx.y;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= ncur[j]) return;
+    const size_t g = (size_t)j * m.cap + s;
+    store_geometry(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)st.w[g]);
 }
 
 // scaled squared residual q(z, x) + c
@@ -155,32 +245,46 @@ __device__ __forceinline__ double sq_resid(const DevModel& m, double zr, double 
     return fma(dr, dr, fma(dt, dt, c));
 }
 
+// Work split of the two likelihood passes: group j's slots are cut into wave
+// tiles of WT = 64*PT particles (lane l takes slots base + 64 i + l) and its
+// measurements into zsplit chunks of MZ; one wavefront takes one (tile, chunk)
+// pair, chunks of a tile sitting in the same workgroup.
+struct Split {
+    int wtiles, zsplit, MZ;
+};
+
 // ---------------------------------------------------------------------------
 // Step 2, first pass (Eq 11): C_j(z) for every group and measurement.
-// Each wavefront owns WT = 64*PT consecutive slots of one group (lane l takes
-// slots base + 64 i + l) and, per measurement, returns the scaled partial sum
-//   s = sum_i 2^(-q_i + log2(wscale w_i) - h),  h = ceil(max_i of the exponent),
-// so that C = 2^h s exactly represents p_D sum g w with no underflow of the
-// dominant term (log-sum-exp scaling with an integer shift).
-// Partials: ps/ph[(j*wtiles + wave_tile)*Mmax + p]; pw[j*wtiles + wave_tile]
-// holds the wave's sum of w.  grid (ceil(wtiles/4), K), 256 threads.
+// Per wave and measurement the wave returns the scaled partial sum
+//   s = sum_i 2^(-q_i + lw_i - h),   C = 2^h s  (h an integer shift),
+// written to ps/ph[(j*wtiles + tile)*Mmax + p]; pw[j*wtiles + tile] holds the
+// tile's sum of weights.
+// EXACT = false (kappa > 0): h = ceil(max_i lw_i) of the wave, a bound that
+//   needs no per-pair work; a term lost to float underflow is below
+//   2^-126 w_i, far under the 1e-5 kappa tolerance of C.
+// EXACT = true (kappa = 0, where every C matters): h = ceil(max_i exponent)
+//   per measurement (log-sum-exp scaling), so the largest term is >= 1/2.
+// Exponents stay in double until the shift is removed: far from every
+// particle they reach -1e3, where a float has lost 1e-4.
+// grid (ceil(wtiles*zsplit/4), K), 256 threads.
 // ---------------------------------------------------------------------------
-template <typename T, int PT>
-__global__ __launch_bounds__(256) void k_cz(DevModel m, SoA<T> st, const int* __restrict__ ncur,
-                                            const double* __restrict__ Z, int M, int Mmax, int wtiles,
-                                            double* __restrict__ ps, int* __restrict__ ph,
+template <typename T, int PT, bool EXACT>
+__global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __restrict__ W,
+                                            const int* __restrict__ ncur, const double* __restrict__ Z, int M,
+                                            int Mmax, Split sp, double* __restrict__ ps, int* __restrict__ ph,
                                             double* __restrict__ pw)
 {
     constexpr int WT = 64 * PT;
     const int j = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int wtile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int gw = blockIdx.x * 4 + wave_in_block();
+    const int tile = gw / sp.zsplit, zc = gw - tile * sp.zsplit;
     const int n = ncur[j];
-    const int base = wtile * WT;
-    if (wtile >= wtiles || base >= n) return;
+    const int base = tile * WT;
+    if (tile >= sp.wtiles || base >= n) return;
     const size_t gb = (size_t)j * m.cap;
     double rho[PT], phi[PT], nlw[PT];
-    double wsum = 0.0;
+    double lwmax = -__builtin_inf();
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
@@ -188,48 +292,81 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, SoA<T> st, const int* __
         phi[i] = 0.0;
         nlw[i] = __builtin_inf();
         if (s < n) {
-            const double w = (double)st.w[gb + s];
-            geometry(m, (double)st.x[0][gb + s], (double)st.x[2][gb + s], rho[i], phi[i]);
-            if (w > 0.0) nlw[i] = -log2(m.wscale * w);
-            wsum += w;
+            rho[i] = geo.rho[gb + s];
+            phi[i] = geo.phi[gb + s];
+            const double lw = geo.lw[gb + s];
+            nlw[i] = -lw;
+            lwmax = lw > lwmax ? lw : lwmax;
         }
     }
-    wsum = wave_sum(wsum);
-    if (lane == 0) pw[(size_t)j * wtiles + wtile] = wsum;
-    const size_t pbase = ((size_t)j * wtiles + wtile) * Mmax;
-    for (int p = 0; p < M; ++p) {
-        const double zr = Z[2 * p] * m.cr, zt = Z[2 * p + 1] * m.ct;
-        // exponents stay in double until the shift is removed: far from every
-        // particle they reach -1e3 and more, where a float has lost 1e-4
-        double a[PT];
-        double amax = -__builtin_inf();
+    if (zc == 0) {
+        double ws = 0.0;
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
-            a[i] = -sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]);
-            amax = a[i] > amax ? a[i] : amax;
+            const int s = base + i * 64 + lane;
+            if (s < n) ws += (double)W[gb + s];
         }
-        const float wmax = wave_max((float)amax);
-        const double h = (wmax == -__builtin_inff()) ? 0.0 : (double)ceilf(wmax);
-        T s = 0;
+        ws = wave_sum(ws);
+        if (lane == 0) pw[(size_t)j * sp.wtiles + tile] = ws;
+    }
+    double hw = 0.0;
+    if (!EXACT) {
+        const double wmx = wave_max(lwmax);
+        hw = (wmx == -__builtin_inf()) ? 0.0 : ceil(wmx);
 #pragma unroll
-        for (int i = 0; i < PT; ++i) s += fast_exp2((T)(a[i] - h));
-        const double sd = wave_sum((double)s);
+        for (int i = 0; i < PT; ++i) nlw[i] += hw;  // exponent - h folded into the particle term
+    }
+    const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
+    const int p0 = zc * sp.MZ, p1 = (p0 + sp.MZ < M) ? p0 + sp.MZ : M;
+    // measurements of the chunk, 64 at a time: lane l holds measurement pb + l,
+    // each iteration broadcasts one with v_readlane (no memory latency in the loop)
+    for (int pb = p0; pb < p1; pb += 64) {
+    const int pe = (pb + 64 < p1) ? pb + 64 : p1;
+    double lzr = 0.0, lzt = 0.0;
+    if (pb + lane < pe) {
+        lzr = Z[2 * (pb + lane)] * m.cr;
+        lzt = Z[2 * (pb + lane) + 1] * m.ct;
+    }
+    for (int p = pb; p < pe; ++p) {
+        const double zr = lane_value(lzr, p - pb), zt = lane_value(lzt, p - pb);
+        T s = 0;
+        double h = hw;
+        if (EXACT) {
+            double a[PT];
+            double amax = -__builtin_inf();
+#pragma unroll
+            for (int i = 0; i < PT; ++i) {
+                a[i] = -sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]);
+                amax = a[i] > amax ? a[i] : amax;
+            }
+            const float wmx = wave_max((float)amax);
+            h = (wmx == -__builtin_inff()) ? 0.0 : (double)ceilf(wmx);
+#pragma unroll
+            for (int i = 0; i < PT; ++i) s += fast_exp2((T)(a[i] - h));
+        } else {
+#pragma unroll
+            for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]));
+        }
+        const T sw = wave_sum(s);
         if (lane == 0) {
-            ps[pbase + p] = sd;
+            ps[pbase + p] = (double)sw;
             ph[pbase + p] = (int)h;
         }
+    }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Combine the first-pass partials of group j (one workgroup per group):
-//   H = max h over waves with s > 0, S = sum s 2^(h - H)    (double, fixed order)
+// Combine the first-pass partials: one wavefront per (group j, measurement p),
+// lanes over the group's tiles (fixed tree order):
+//   H = max h over tiles with s > 0, S = sum s 2^(h - H)
 //   C = 2^H S,  F = 1/(kappa 2^-H + S) = 2^H/(kappa + C),  dW = S F = C/(kappa + C)
-// The candidate labels for Step 3 are the top min(LT_c + 1, #dW>0) measurements
-// by dW (ties to the lower index), where LT_c = round(nu sum w + sum dW) is the
-// closed form of the updated mass (the sums of Eq 8 swapped); the exact count
-// LT differs from LT_c by at most one, so the candidates always cover it.
-// grid (K), 256 threads, dynamic LDS Mmax doubles.
+// k_cand then picks, per group, the candidate labels for Step 3:
+// the top min(LT_c + 1, #dW>0) measurements by dW (ties to the lower index),
+// where LT_c = round(nu sum w + sum dW) is the closed form of the updated mass
+// (the sums of Eq 8 swapped); the exact count LT differs from LT_c by at most
+// one, so the candidates always cover it.  zflag[p] = 1 + rank, or 0.
+// grid (max(1, ceil(M/4)), K), 256 threads, dynamic LDS Mmax doubles.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_cz_combine(DevModel m, const int* __restrict__ ncur, int M, int Mmax,
@@ -237,188 +374,199 @@ __global__ __launch_bounds__(256) void k_cz_combine(DevModel m, const int* __res
                                                     const int* __restrict__ ph, const double* __restrict__ pw,
                                                     int* __restrict__ zH, T* __restrict__ zF,
                                                     double* __restrict__ zC, double* __restrict__ zdW,
-                                                    int* __restrict__ zflag, int* __restrict__ cand,
-                                                    int* __restrict__ ncand)
+                                                    int* __restrict__ zflag)
 {
-    extern __shared__ double sm_dw[];
-    __shared__ double red[256];
-    __shared__ int redi[256];
-    const int j = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int j = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_block();
+    const int p = blockIdx.x * 4 + wv;
     const int n = ncur[j];
     const int nw = (n + WT - 1) / WT;
     const size_t zb = (size_t)j * Mmax;
-    double dsum = 0.0;
-    for (int p = tid; p < M; p += 256) {
+    if (p < M) {
         int H = -2147483647 - 1;
-        for (int w = 0; w < nw; ++w) {
-            const size_t o = ((size_t)j * wtiles + w) * Mmax + p;
+        for (int t = lane; t < nw; t += 64) {
+            const size_t o = ((size_t)j * wtiles + t) * Mmax + p;
             if (ps[o] > 0.0 && ph[o] > H) H = ph[o];
         }
+        H = wave_max(H);
         double S = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            const size_t o = ((size_t)j * wtiles + w) * Mmax + p;
+        for (int t = lane; t < nw; t += 64) {
+            const size_t o = ((size_t)j * wtiles + t) * Mmax + p;
             if (ps[o] > 0.0) S += ldexp(ps[o], ph[o] - H);
         }
-        double C = 0.0, F = 0.0, dW = 0.0;
-        if (S > 0.0) {
-            const double D = ldexp(m.kappa, -H) + S;
-            F = 1.0 / D;
-            dW = S / D;
-            C = ldexp(S, H);
-        } else {
-            H = 0;
+        S = wave_sum(S);
+        if (lane == 0) {
+            double C = 0.0, F = 0.0, dW = 0.0;
+            if (S > 0.0) {
+                const double D = ldexp(m.kappa, -H) + S;
+                F = 1.0 / D;
+                dW = S / D;
+                C = ldexp(S, H);
+            } else {
+                H = 0;
+            }
+            zH[zb + p] = H;
+            zF[zb + p] = (T)F;
+            zC[zb + p] = C;
+            zdW[zb + p] = dW;
+            zflag[zb + p] = 0;
         }
-        zH[zb + p] = H;
-        zF[zb + p] = (T)F;
-        zC[zb + p] = C;
-        zdW[zb + p] = dW;
-        zflag[zb + p] = 0;
-        sm_dw[p] = dW;
-        dsum += dW;
     }
-    // pre-update mass and sum of dW
-    double wsum = 0.0;
-    if (tid == 0)
-        for (int w = 0; w < nw; ++w) wsum += pw[(size_t)j * wtiles + w];
-    red[tid] = dsum;
+}
+
+__global__ __launch_bounds__(256) void k_cand(double nu, const int* __restrict__ ncur, int M, int Mmax, int wtiles,
+                                              int WT, const double* __restrict__ pw,
+                                              const double* __restrict__ zdW, int* __restrict__ zflag,
+                                              int* __restrict__ cand, int* __restrict__ ncand)
+{
+    extern __shared__ double sm_dw[];
+    __shared__ double s_red[4];
+    __shared__ int s_redi[4];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_block();
+    const int n = ncur[j];
+    const int nw = (n + WT - 1) / WT;
+    const size_t zb = (size_t)j * Mmax;
+    const int tid = threadIdx.x;
+    double dsum = 0.0;
     int pos = 0;
-    for (int p = tid; p < M; p += 256) pos += sm_dw[p] > 0.0 ? 1 : 0;
-    redi[tid] = pos;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            red[tid] += red[tid + o];
-            redi[tid] += redi[tid + o];
-        }
-        __syncthreads();
+    for (int q = tid; q < M; q += 256) {
+        const double v = zdW[zb + q];
+        sm_dw[q] = v;
+        dsum += v;
+        pos += v > 0.0 ? 1 : 0;
     }
-    __shared__ int s_nc;
-    if (tid == 0) {
-        const double mass_c = m.nu * wsum + red[0];
-        double lt = floor(mass_c + 0.5);
-        int LTc = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
-        int nc = LTc + 1;
-        if (nc > redi[0]) nc = redi[0];
-        s_nc = nc;
-        ncand[j] = nc;
+    double wsum = 0.0;
+    for (int t = tid; t < nw; t += 256) wsum += pw[(size_t)j * wtiles + t];
+    dsum = wave_sum(dsum);
+    wsum = wave_sum(wsum);
+    pos = (int)wave_sum((double)pos);
+    if (lane == 0) {
+        s_red[wv] = nu * wsum + dsum;
+        s_redi[wv] = pos;
     }
     __syncthreads();
-    const int nc = s_nc;
-    for (int p = tid; p < M; p += 256) {
-        const double v = sm_dw[p];
+    const double mass_c = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    const int npos = (s_redi[0] + s_redi[1]) + (s_redi[2] + s_redi[3]);
+    const double lt = floor(mass_c + 0.5);
+    const int LTc = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
+    const int nc = LTc + 1 < npos ? LTc + 1 : npos;
+    if (tid == 0) ncand[j] = nc;
+    for (int q = tid; q < M; q += 256) {
+        const double v = sm_dw[q];
         if (!(v > 0.0)) continue;
         int rank = 0;
-        for (int q = 0; q < M; ++q) {
-            const double u = sm_dw[q];
-            rank += (u > v || (u == v && q < p)) ? 1 : 0;
+        for (int r = 0; r < M; ++r) {
+            const double u = sm_dw[r];
+            rank += (u > v || (u == v && r < q)) ? 1 : 0;
         }
         if (rank < nc) {
-            cand[zb + rank] = p;
-            zflag[zb + p] = 1;
+            cand[zb + rank] = q;
+            zflag[zb + q] = rank + 1;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step 2, second pass (Eqs 12-15) and the sums of Step 3 (Eqs 16-18):
-//   w_i <- nu w_i + wscale w_i sum_p 2^(-q_ip - H_p) F_p
-// For the candidate labels (visited first) the wave also accumulates
-//   u_i = wscale w_i 2^(-q_ip - H_p),  sum u_i x_i (4 components) and sum u_i,
-// whose ratio is the local estimate of Eq 18 (F cancels).
-// Partials: pmass/pmax[j*wtiles + wave_tile] (sum and max of the stored new
-// weights), pzeta[((j*wtiles + wave_tile)*Mmax + c)*5 + k].
-// grid (ceil(wtiles/4), K), 256 threads.
+// Step 2, second pass (Eqs 12-15) and the sums of Step 3 (Eqs 16-18), per
+// (tile, chunk) wave:  acc_i = sum over the chunk of 2^(-q_ip - H_p) F_p,
+// stored to accp[zc][slot]; k_wfinal then forms
+//   w_i <- nu w_i + wscale w_i sum_chunks acc_i.
+// For a candidate label p the wave also sums u_i = wscale w_i 2^(-q_ip - H_p),
+// u_i x_i (4 components) and writes them to pzeta[((j*wtiles + tile)*Mmax +
+// rank)*5 + k]; their ratio is the local estimate of Eq 18 (F cancels).
+// grid (ceil(wtiles*zsplit/4), K), 256 threads.
 // ---------------------------------------------------------------------------
 template <typename T, int PT>
-__global__ __launch_bounds__(256) void k_weight(DevModel m, SoA<T> st, const int* __restrict__ ncur,
-                                                const double* __restrict__ Z, int M, int Mmax, int wtiles,
+__global__ __launch_bounds__(256) void k_weight(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ ncur,
+                                                const double* __restrict__ Z, int M, int Mmax, Split sp,
                                                 const int* __restrict__ zH, const T* __restrict__ zF,
-                                                const int* __restrict__ zflag, const int* __restrict__ cand,
-                                                const int* __restrict__ ncand, double* __restrict__ pmass,
-                                                double* __restrict__ pmax, double* __restrict__ pzeta)
+                                                const int* __restrict__ zflag, double* __restrict__ pzeta,
+                                                T* __restrict__ accp)
 {
     constexpr int WT = 64 * PT;
     const int j = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int wtile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int gw = blockIdx.x * 4 + wave_in_block();
+    const int tile = gw / sp.zsplit, zc = gw - tile * sp.zsplit;
     const int n = ncur[j];
-    const int base = wtile * WT;
-    if (wtile >= wtiles || base >= n) return;
+    const int base = tile * WT;
+    if (tile >= sp.wtiles || base >= n) return;
     const size_t gb = (size_t)j * m.cap;
     const size_t zb = (size_t)j * Mmax;
     double rho[PT], phi[PT];
-    T wt[PT], acc[PT];
+    T acc[PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
         rho[i] = 0.0;
         phi[i] = 0.0;
-        wt[i] = 0;
         acc[i] = 0;
         if (s < n) {
-            geometry(m, (double)st.x[0][gb + s], (double)st.x[2][gb + s], rho[i], phi[i]);
-            wt[i] = (T)(m.wscale * (double)st.w[gb + s]);
+            rho[i] = geo.rho[gb + s];
+            phi[i] = geo.phi[gb + s];
         }
     }
-    const int nc = ncand[j];
-    const size_t pz = ((size_t)j * wtiles + wtile) * Mmax;
-    for (int c = 0; c < nc; ++c) {
-        const int p = cand[zb + c];
-        const double zr = Z[2 * p] * m.cr, zt = Z[2 * p + 1] * m.ct;
-        const double H = (double)zH[zb + p];
-        const T F = zF[zb + p];
-        T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
+    const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
+    const int p0 = zc * sp.MZ, p1 = (p0 + sp.MZ < M) ? p0 + sp.MZ : M;
+    for (int pb = p0; pb < p1; pb += 64) {
+    const int pe = (pb + 64 < p1) ? pb + 64 : p1;
+    double lzr = 0.0, lzt = 0.0;
+    int lH = 0, lfl = 0;
+    T lF = 0;
+    if (pb + lane < pe) {
+        const int q = pb + lane;
+        lzr = Z[2 * q] * m.cr;
+        lzt = Z[2 * q + 1] * m.ct;
+        lH = zH[zb + q];
+        lF = zF[zb + q];
+        lfl = zflag[zb + q];
+    }
+    for (int p = pb; p < pe; ++p) {
+        const int l = p - pb;
+        const double zr = lane_value(lzr, l), zt = lane_value(lzt, l);
+        const double H = (double)lane_value(lH, l);
+        const T F = lane_value(lF, l);
+        const int fl = lane_value(lfl, l);
+        if (fl == 0) {
 #pragma unroll
-        for (int i = 0; i < PT; ++i) {
-            const T e = fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H));
-            acc[i] += e * F;
-            const int s = base + i * 64 + lane;
-            if (s < n) {
-                const T u = e * wt[i];
-                u0 += u * st.x[0][gb + s];
-                u1 += u * st.x[1][gb + s];
-                u2 += u * st.x[2][gb + s];
-                u3 += u * st.x[3][gb + s];
-                u4 += u;
+            for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H)) * F;
+        } else {
+            T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
+#pragma unroll
+            for (int i = 0; i < PT; ++i) {
+                const T e = fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H));
+                acc[i] += e * F;
+                const int s = base + i * 64 + lane;
+                if (s < n) {
+                    const T u = e * (T)(m.wscale * (double)st.w[gb + s]);
+                    u0 += u * st.x[0][gb + s];
+                    u1 += u * st.x[1][gb + s];
+                    u2 += u * st.x[2][gb + s];
+                    u3 += u * st.x[3][gb + s];
+                    u4 += u;
+                }
+            }
+            const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
+                         r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
+            if (lane == 0) {
+                double* o = pzeta + (pz + (fl - 1)) * 5;
+                o[0] = r0;
+                o[1] = r1;
+                o[2] = r2;
+                o[3] = r3;
+                o[4] = r4;
             }
         }
-        const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
-                     r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
-        if (lane == 0) {
-            double* o = pzeta + (pz + c) * 5;
-            o[0] = r0;
-            o[1] = r1;
-            o[2] = r2;
-            o[3] = r3;
-            o[4] = r4;
-        }
     }
-    for (int p = 0; p < M; ++p) {
-        if (zflag[zb + p]) continue;
-        const double zr = Z[2 * p] * m.cr, zt = Z[2 * p + 1] * m.ct;
-        const double H = (double)zH[zb + p];
-        const T F = zF[zb + p];
-#pragma unroll
-        for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H)) * F;
     }
-    double msum = 0.0, mmax = 0.0;
+    const size_t KC = (size_t)m.K * m.cap;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
-        if (s < n) {
-            const double w = (double)st.w[gb + s];
-            const T wn = (T)(m.nu * w + (double)wt[i] * (double)acc[i]);
-            st.w[gb + s] = wn;
-            msum += (double)wn;
-            mmax = (double)wn > mmax ? (double)wn : mmax;
-        }
-    }
-    msum = wave_sum(msum);
-    mmax = wave_max(mmax);
-    if (lane == 0) {
-        pmass[(size_t)j * wtiles + wtile] = msum;
-        pmax[(size_t)j * wtiles + wtile] = mmax;
+        if (s < n) accp[(size_t)zc * KC + gb + s] = acc[i];
     }
 }
 
@@ -439,65 +587,121 @@ __device__ __forceinline__ int quant_shift(double wmax, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Step 3 per group (one workgroup per group): mass N_j, LT_j = round(N_j)
-// capped at M, the first LT_j candidates become the label set I_j, and their
-// local estimates zeta = sum u x / sum u.  Also the quantisation shift of the
-// group's resampling.  grid (K), 256 threads.
+// New weights from the chunk sums (chunk order fixed) and Step 3 per group.
+// k_wfinal: every workgroup turns 256 slots into
+//   w <- nu w + wscale w sum_chunks acc
+// and writes the tile's sum and maximum of the stored weights.
+// grid (tiles256, K).  k_finalize (grid K) then forms the mass N_j,
+// LT_j = round(N_j) capped at M, the label set I_j (the first LT_j
+// candidates), their local estimates zeta = sum u x / sum u, and the
+// quantisation shift of the group's resampling.  256 threads each.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(const int* __restrict__ ncur, int M, int Mmax, int wtiles,
-                                                  int WT, const double* __restrict__ pmass,
-                                                  const double* __restrict__ pmax, const double* __restrict__ pzeta,
-                                                  const int* __restrict__ cand, const int* __restrict__ ncand,
-                                                  double* __restrict__ fmass, int* __restrict__ fLT,
-                                                  int* __restrict__ rsS, int* __restrict__ sel,
-                                                  double* __restrict__ zeta)
+template <typename T>
+__global__ __launch_bounds__(256) void k_wfinal(DevModel m, T* __restrict__ W, const int* __restrict__ ncur,
+                                                const T* __restrict__ accp, int zsplit, int tiles256,
+                                                double* __restrict__ pmass, double* __restrict__ pmax)
+{
+    __shared__ double rs[4], rm[4];
+    const int j = blockIdx.y;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int n = ncur[j];
+    const int nt = (n + 255) / 256;
+    const int active = nt > 0 ? nt : 1;
+    if ((int)blockIdx.x >= active) return;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
+    const size_t KC = (size_t)m.K * m.cap;
+    const size_t g = (size_t)j * m.cap + s;
+    double wn = 0.0;
+    if (s < n) {
+        T acc = 0;
+        for (int zc = 0; zc < zsplit; ++zc) acc += accp[(size_t)zc * KC + g];
+        const double w = (double)W[g];
+        const T t = (T)(m.nu * w + m.wscale * w * (double)acc);
+        W[g] = t;
+        wn = (double)t;
+    }
+    const double sm = wave_sum(wn), mx = wave_max(wn);
+    if (lane == 0) {
+        rs[wv] = sm;
+        rm[wv] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pmass[(size_t)j * tiles256 + blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+        pmax[(size_t)j * tiles256 + blockIdx.x] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const int* __restrict__ ncur, int tiles256,
+                                                  const double* __restrict__ pmass, const double* __restrict__ pmax,
+                                                  int M, int Mmax, int wtiles2, int WT2,
+                                                  const double* __restrict__ pzeta, const int* __restrict__ cand,
+                                                  const int* __restrict__ ncand, double* __restrict__ fmass,
+                                                  int* __restrict__ fLT, int* __restrict__ rsS,
+                                                  int* __restrict__ sel, double* __restrict__ zeta)
 {
     const int j = blockIdx.x;
-    const int tid = threadIdx.x;
     const int n = ncur[j];
-    const int nw = (n + WT - 1) / WT;
+    const int nt = (n + 255) / 256;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t zb = (size_t)j * Mmax;
-    __shared__ int s_nsel;
-    for (int p = tid; p < M; p += 256) {
+    for (int p = threadIdx.x; p < M; p += 256) {
         sel[zb + p] = 0;
 #pragma unroll
         for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = 0.0;
     }
-    if (tid == 0) {
-        double mass = 0.0, wmax = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            mass += pmass[(size_t)j * wtiles + w];
-            wmax = pmax[(size_t)j * wtiles + w] > wmax ? pmax[(size_t)j * wtiles + w] : wmax;
+    __shared__ double s_ms, s_mm;
+    if (wv == 0) {
+        double ms = 0.0, mm = 0.0;
+        for (int t = lane; t < nt; t += 64) {
+            ms += pmass[(size_t)j * tiles256 + t];
+            mm = vmax(mm, pmax[(size_t)j * tiles256 + t]);
         }
-        double lt = floor(mass + 0.5);
-        int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
-        fmass[j] = mass;
-        fLT[j] = LT;
-        rsS[j] = quant_shift(wmax, n);
-        s_nsel = LT < ncand[j] ? LT : ncand[j];
+        ms = wave_sum(ms);
+        mm = wave_max(mm);
+        if (lane == 0) {
+            s_ms = ms;
+            s_mm = mm;
+        }
     }
     __syncthreads();
-    const int nsel = s_nsel;
-    for (int c = tid; c < nsel; c += 256) {
-        const int p = cand[zb + c];
+    const double ms = s_ms, mm = s_mm;
+    const double lt = floor(ms + 0.5);
+    const int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
+    const int nc = ncand[j];
+    const int nsel = LT < nc ? LT : nc;
+    if (threadIdx.x == 0) {
+        fmass[j] = ms;
+        fLT[j] = LT;
+        rsS[j] = quant_shift(mm, n);
+    }
+    __syncthreads();
+    const int nw = (n + WT2 - 1) / WT2;
+    for (int c = wv; c < nsel; c += 4) {
         double a[5] = { 0, 0, 0, 0, 0 };
-        for (int w = 0; w < nw; ++w) {
-            const double* o = pzeta + (((size_t)j * wtiles + w) * Mmax + c) * 5;
+        for (int t = lane; t < nw; t += 64) {
+            const double* o = pzeta + (((size_t)j * wtiles2 + t) * Mmax + c) * 5;
 #pragma unroll
             for (int k = 0; k < 5; ++k) a[k] += o[k];
         }
-        sel[zb + p] = 1;
-        if (a[4] > 0.0) {
 #pragma unroll
-            for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = a[d] / a[4];
+        for (int k = 0; k < 5; ++k) a[k] = wave_sum(a[k]);
+        if (lane == 0) {
+            const int p = cand[zb + c];
+            sel[zb + p] = 1;
+            if (a[4] > 0.0) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = a[d] / a[4];
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step 4, fusion at the central unit (one workgroup): a label is kept when
-// 2*votes > K; its estimate is the mean of the reporting groups' estimates in
-// group order; records are written in label order.  grid (1), 256 threads.
+// Step 4, fusion at the central unit.  k_fuse_labels: one wavefront per label
+// counts the groups that report it and averages their estimates (tree sum
+// over groups in a fixed order); a label is kept when 2*votes > K.
+// k_fuse_compact: one workgroup writes the kept labels in label order.
 // ---------------------------------------------------------------------------
 struct EstimateRec {
     double state[4];
@@ -505,19 +709,48 @@ struct EstimateRec {
     int32_t votes;
 };
 
-__global__ __launch_bounds__(256) void k_fuse(int K, int M, int Mmax, const int* __restrict__ sel,
-                                              const double* __restrict__ zeta, EstimateRec* __restrict__ out,
-                                              int cap, int* __restrict__ nout)
+__global__ __launch_bounds__(256) void k_fuse_labels(int K, int M, int Mmax, const int* __restrict__ sel,
+                                                     const double* __restrict__ zeta, int* __restrict__ fkeep,
+                                                     EstimateRec* __restrict__ frec)
+{
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= M) return;
+    double v = 0.0, a[4] = { 0, 0, 0, 0 };
+    for (int j0 = 0; j0 < K; j0 += 64) {
+        const int j = j0 + lane;
+        if (j < K && sel[(size_t)j * Mmax + p]) {
+            v += 1.0;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) a[d] += zeta[((size_t)j * Mmax + p) * 4 + d];
+        }
+    }
+    const int votes = (int)wave_sum(v);
+    double r[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) r[d] = wave_sum(a[d]);
+    if (lane == 0) {
+        const int keep = 2 * votes > K ? 1 : 0;
+        fkeep[p] = keep;
+        EstimateRec e;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) e.state[d] = keep ? r[d] / (double)votes : 0.0;
+        e.label = p;
+        e.votes = votes;
+        frec[p] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fuse_compact(int M, const int* __restrict__ fkeep,
+                                                      const EstimateRec* __restrict__ frec,
+                                                      EstimateRec* __restrict__ out, int cap, int* __restrict__ nout)
 {
     __shared__ int scan[256];
     const int tid = threadIdx.x;
     int offset = 0;
     for (int p0 = 0; p0 < M; p0 += 256) {
         const int p = p0 + tid;
-        int votes = 0;
-        if (p < M)
-            for (int j = 0; j < K; ++j) votes += sel[(size_t)j * Mmax + p];
-        const int keep = (p < M && 2 * votes > K) ? 1 : 0;
+        const int keep = (p < M) ? fkeep[p] : 0;
         scan[tid] = keep;
         __syncthreads();
         for (int o = 1; o < 256; o <<= 1) {
@@ -527,20 +760,7 @@ __global__ __launch_bounds__(256) void k_fuse(int K, int M, int Mmax, const int*
             __syncthreads();
         }
         const int idx = offset + scan[tid] - keep;
-        if (keep && idx < cap) {
-            double acc[4] = { 0, 0, 0, 0 };
-            for (int j = 0; j < K; ++j) {
-                if (!sel[(size_t)j * Mmax + p]) continue;
-#pragma unroll
-                for (int d = 0; d < 4; ++d) acc[d] += zeta[((size_t)j * Mmax + p) * 4 + d];
-            }
-            EstimateRec r;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) r.state[d] = acc[d] / (double)votes;
-            r.label = p;
-            r.votes = votes;
-            out[idx] = r;
-        }
+        if (keep && idx < cap) out[idx] = frec[p];
         offset += scan[255];
         __syncthreads();
     }
@@ -574,25 +794,19 @@ __global__ __launch_bounds__(256) void k_wmax(DevModel m, const T* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Step 5, resampling, pass A: integer-valued weights q = floor(w 2^S) and their
-// exact per-tile totals (tiles of 256*PR parents).  grid (rtiles, K).
+// exact per-tile totals (tiles of 256 parents).  grid (rtiles, K).
 // ---------------------------------------------------------------------------
-template <typename T, int PR>
+template <typename T>
 __global__ __launch_bounds__(256) void k_rs_tiles(DevModel m, const T* __restrict__ w, const int* __restrict__ ncur,
                                                   const int* __restrict__ rsS, int rtiles, double* __restrict__ tsum)
 {
-    constexpr int TR = 256 * PR;
     __shared__ double red[4];
     const int j = blockIdx.y, t = blockIdx.x;
     const int n = ncur[j];
-    const int base = t * TR;
-    if (base >= n) return;
+    const int s = t * 256 + threadIdx.x;
+    if (t * 256 >= n) return;
     const int S = rsS[j];
-    double q = 0.0;
-#pragma unroll
-    for (int i = 0; i < PR; ++i) {
-        const int s = base + i * 256 + threadIdx.x;
-        if (s < n) q += floor(ldexp((double)w[(size_t)j * m.cap + s], S));
-    }
+    double q = (s < n) ? floor(ldexp((double)w[(size_t)j * m.cap + s], S)) : 0.0;
     q = wave_sum(q);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
     __syncthreads();
@@ -627,13 +841,13 @@ __device__ __forceinline__ double children_count(double mq, double Rj)
 
 // ---------------------------------------------------------------------------
 // Step 5, pass B: exact prefix of q, child counts and parent-order expansion
-// into the other particle set.  Thread t of a tile owns parents
-// [base + t*PR, base + t*PR + PR); the workgroup writes the children of its
-// parents, which occupy one contiguous slot range, with coalesced stores
-// (each child finds its parent by binary search over the tile's child offsets
-// held in LDS).  grid (rtiles, K), 256 threads.
+// into the other particle set.  Thread t of a tile owns parent base + t; its
+// children occupy slots [N(c_{t-1}), N(c_t)).  The workgroup's children form
+// one contiguous slot range written with coalesced stores (each child finds
+// its parent by binary search over the tile's child offsets in LDS).
+// grid (rtiles, K), 256 threads.
 // ---------------------------------------------------------------------------
-template <typename T, int PR>
+template <typename T>
 __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T> out,
                                                    const int* __restrict__ ncur, int* __restrict__ nsurv,
                                                    const int* __restrict__ rsS, const double* __restrict__ tsum,
@@ -641,41 +855,45 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T>
                                                    int* __restrict__ clampctr, int* __restrict__ counts,
                                                    int record)
 {
-    constexpr int TR = 256 * PR;
-    __shared__ int s_off[TR + 1];
-    __shared__ T s_x[4][TR];
-    __shared__ double red[256];
+    __shared__ long long s_end[256];
+    __shared__ long long s_first;
+    __shared__ T s_x[4][256];
+    __shared__ double s_q[3][4];
     const int j = blockIdx.y, t = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const int n = ncur[j];
-    const int ntl = (n + TR - 1) / TR;
+    const int ntl = (n + 255) / 256;
     if (t > 0 && t >= ntl) return;
     const size_t gb = (size_t)j * m.cap;
-    const int base = t * TR;
-    // group total Q and this tile's exclusive prefix P (exact integer sums)
+    const int base = t * 256;
+    const int S = rsS[j];
+    // group total Q and this tile's exclusive prefix P (exact integer sums),
+    // and this thread's integer weight with its in-wave inclusive prefix
     double qa = 0.0, qp = 0.0;
     for (int u = tid; u < ntl; u += 256) {
         const double v = tsum[(size_t)j * rtiles + u];
         qa += v;
         if (u < t) qp += v;
     }
-    red[tid] = qa;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) red[tid] += red[tid + o];
-        __syncthreads();
+    const int sidx = base + tid;
+    const double q = (sidx < n) ? floor(ldexp((double)in.w[gb + sidx], S)) : 0.0;
+    const double qin = wave_incl_scan(q);
+    qa = wave_sum(qa);
+    qp = wave_sum(qp);
+    if (lane == 0) {
+        s_q[0][wv] = qa;
+        s_q[1][wv] = qp;
+        s_q[2][wv] = lane_value(qin, 63);
     }
-    const double Qd = red[0];
-    __syncthreads();
-    red[tid] = qp;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) red[tid] += red[tid + o];
-        __syncthreads();
+    if (sidx < n) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) s_x[d][tid] = in.x[d][gb + sidx];
     }
-    const double Pd = red[0];
     __syncthreads();
-    const int S = rsS[j];
+    const double Qd = (s_q[0][0] + s_q[0][1]) + (s_q[0][2] + s_q[0][3]);
+    const double Pd = (s_q[1][0] + s_q[1][1]) + (s_q[1][2] + s_q[1][3]);
+    double wpre = 0.0;
+    for (int w2 = 0; w2 < wv; ++w2) wpre += s_q[2][w2];
     const int Jj = births_in(m, j);
     long long L = 0;
     double mq = 0.0;
@@ -697,64 +915,26 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T>
         massq[j] = mq;
     }
     if (L == 0 || base >= n) {
-        if (record) {
-            for (int s = base + tid; s < n && s < base + TR; s += 256) counts[gb + s] = 0;
-        }
+        if (record && sidx < n) counts[gb + sidx] = 0;
         return;
     }
     const double wc = mq / (double)L;
     const uint32_t r = rng_block(m.key0, m.key1, (uint32_t)j, step, RNG_RESAMPLE, 0, m.run).a;
     const uint64_t Q = (uint64_t)Qd;
-    // parents of this thread, their integer weights and inclusive prefix
-    double q[PR];
-    double tot = 0.0;
-#pragma unroll
-    for (int i = 0; i < PR; ++i) {
-        const int s = base + tid * PR + i;
-        q[i] = (s < n) ? floor(ldexp((double)in.w[gb + s], S)) : 0.0;
-        tot += q[i];
-    }
-    // workgroup exclusive scan of thread totals (exact)
-    red[tid] = tot;
+    const double c_incl = Pd + wpre + qin;            // c_t = q_0 + ... + q_t of the group
+    const long long nend = points_below((uint64_t)c_incl, Q, L, r);
+    s_end[tid] = nend;
+    if (tid == 0) s_first = points_below((uint64_t)Pd, Q, L, r);
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const double v = tid >= o ? red[tid - o] : 0.0;
-        __syncthreads();
-        red[tid] += v;
-        __syncthreads();
-    }
-    const double excl = red[tid] - tot;
-    double cprev = Pd + excl;
-    long long nprev = points_below((uint64_t)cprev, Q, L, r);
-#pragma unroll
-    for (int i = 0; i < PR; ++i) {
-        const int li = tid * PR + i;
-        s_off[li] = (int)nprev;
-        const double c = cprev + q[i];
-        const long long nc = (q[i] > 0.0) ? points_below((uint64_t)c, Q, L, r) : nprev;
-        if (record && base + li < n) counts[gb + base + li] = (int)(nc - nprev);
-        cprev = c;
-        nprev = nc;
-    }
-    if (tid == 255) s_off[TR] = (int)nprev;
-    // stage parent states in LDS (coalesced)
-#pragma unroll
-    for (int i = 0; i < PR; ++i) {
-        const int li = i * 256 + tid;
-        const int s = base + li;
-        if (s < n) {
-#pragma unroll
-            for (int d = 0; d < 4; ++d) s_x[d][li] = in.x[d][gb + s];
-        }
-    }
-    __syncthreads();
-    const int c0 = s_off[0], c1 = s_off[TR];
-    for (int c = c0 + tid; c < c1; c += 256) {
-        // last parent li with s_off[li] <= c
-        int lo = 0, hi = TR - 1;
+    const long long nbeg = tid == 0 ? s_first : s_end[tid - 1];
+    if (record && sidx < n) counts[gb + sidx] = (int)(nend - nbeg);
+    const long long c0 = s_first, c1 = s_end[255];
+    for (long long c = c0 + tid; c < c1; c += 256) {
+        // last parent li with start(li) <= c, start(0) = s_first, start(li) = s_end[li-1]
+        int lo = 0, hi = 255;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= c) lo = mid; else hi = mid - 1;
+            if (s_end[mid - 1] <= c) lo = mid; else hi = mid - 1;
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d) out.x[d][gb + c] = s_x[d][lo];
@@ -770,10 +950,17 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T>
 // launches) makes every read see the state before the exchange, so the
 // exchange is a permutation of the particles.  grid (ceil(Lmax/256), K).
 // ---------------------------------------------------------------------------
+// exchange count L = floor(rho_x min_j n_j); called by all threads of a workgroup
 __device__ __forceinline__ int exchange_count(const DevModel& m, const int* __restrict__ nsurv)
 {
-    int mn = nsurv[0];
-    for (int j = 1; j < m.K; ++j) mn = nsurv[j] < mn ? nsurv[j] : mn;
+    __shared__ int s_min[4];
+    int mn = 2147483647;
+    for (int j = threadIdx.x; j < m.K; j += 256) mn = nsurv[j] < mn ? nsurv[j] : mn;
+    mn = -wave_max(-mn);
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = mn;
+    __syncthreads();
+    mn = s_min[0];
+    for (int w = 1; w < 4; ++w) mn = s_min[w] < mn ? s_min[w] : mn;
     return (int)floor(m.xfrac * (double)mn);
 }
 

@@ -52,11 +52,13 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b)
 // Box-Muller: two independent N(0, 1) values from two uniforms.
 __device__ __forceinline__ void normal_pair(double u1, double u2, double& n1, double& n2)
 {
-    const double two_pi = 2.0 * 3.14159265358979323846;
-    double rad = sqrt(-2.0 * log(u1));
-    double ang = two_pi * u2;
-    n1 = rad * cos(ang);
-    n2 = rad * sin(ang);
+    // sin/cos of 2 pi u2 through sincospi (one argument reduction, exact
+    // scaling by pi inside the routine)
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    n1 = rad * cs;
+    n2 = rad * sn;
 }
 
 }  // namespace pphd

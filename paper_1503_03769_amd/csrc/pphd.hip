@@ -43,12 +43,16 @@ pphd_status fail(pphd_status s, const char* fmt, ...)
             return fail(PPHD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
     } while (0)
 
-// particles per thread of the two update passes and of resampling
-constexpr int PT1_F32 = 16, PT2_F32 = 16, PT1_F64 = 8, PT2_F64 = 8, PR = 4;
+// particles per thread of the two update passes and of resampling; the
+// measurement loop of the passes is cut into at most ZSPLIT_MAX chunks of
+// about MZ_TARGET measurements
+constexpr int PT1_F32 = 8, PT2_F32 = 8, PT1_F64 = 4, PT2_F64 = 4, PR = 1;
+constexpr int ZSPLIT_MAX = 8, MZ_TARGET = 16;
 
 const char* kKernelNames[PPHD_K_COUNT] = {
-    "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
+    "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse_labels",
     "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
+    "k_geom", "k_wfinal", "k_fuse_compact", "k_cand",
 };
 
 struct Layout {
@@ -79,7 +83,7 @@ struct pphd_filter {
     int last_m = 0;
     bool record = false;
     bool timing = false;
-    int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0;
+    int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0, tiles256 = 0;
     // device arrays (inside the workspace)
     void* X[2][4] = {};
     void* W[2] = {};
@@ -91,6 +95,10 @@ struct pphd_filter {
     void* zF = nullptr;
     double *zC = nullptr, *zdW = nullptr;
     double *p2mass = nullptr, *p2max = nullptr, *p2zeta = nullptr;
+    double *geo_rho = nullptr, *geo_phi = nullptr, *geo_lw = nullptr;
+    void* accp = nullptr;
+    int* fkeep = nullptr;
+    EstimateRec* frec = nullptr;
     double* fmass = nullptr;
     int *fLT = nullptr, *rsS = nullptr, *sel = nullptr;
     double* zeta = nullptr;
@@ -151,8 +159,14 @@ size_t carve(pphd_filter* f, char* base)
     f->zflag = L.take<int>(base, K * Mx * 4);
     f->cand = L.take<int>(base, K * Mx * 4);
     f->ncand = L.take<int>(base, K * 4);
-    f->p2mass = L.take<double>(base, K * f->wtiles2 * 8);
-    f->p2max = L.take<double>(base, K * f->wtiles2 * 8);
+    f->p2mass = L.take<double>(base, K * f->tiles256 * 8);
+    f->p2max = L.take<double>(base, K * f->tiles256 * 8);
+    f->geo_rho = L.take<double>(base, KC * 8);
+    f->geo_phi = L.take<double>(base, KC * 8);
+    f->geo_lw = L.take<double>(base, KC * 8);
+    f->accp = L.take<char>(base, (size_t)ZSPLIT_MAX * KC * es);
+    f->fkeep = L.take<int>(base, Mx * 4);
+    f->frec = L.take<EstimateRec>(base, Mx * sizeof(EstimateRec));
     f->p2zeta = L.take<double>(base, K * f->wtiles2 * Mx * 5 * 8);
     f->fmass = L.take<double>(base, K * 8);
     f->fLT = L.take<int>(base, K * 4);
@@ -184,6 +198,7 @@ void set_geometry(pphd_filter* f, const pphd_model* m, int64_t cap, int32_t max_
     f->wtiles1 = (int)((cap + f->wt1 - 1) / f->wt1);
     f->wtiles2 = (int)((cap + f->wt2 - 1) / f->wt2);
     f->rtiles = (int)((cap + 256 * PR - 1) / (256 * PR));
+    f->tiles256 = (int)((cap + 255) / 256);
     f->Lmax = (int)std::floor(m->exchange_fraction * (double)cap) + 1;
 }
 
@@ -248,6 +263,21 @@ SoA<T> soa(pphd_filter* f, int b)
     return s;
 }
 
+Geo geo_of(pphd_filter* f)
+{
+    return Geo{ f->geo_rho, f->geo_phi, f->geo_lw };
+}
+
+Split split_for(int wtiles, int M)
+{
+    Split sp;
+    sp.wtiles = wtiles;
+    int z = (M + MZ_TARGET - 1) / MZ_TARGET;
+    sp.zsplit = z < 1 ? 1 : (z > ZSPLIT_MAX ? ZSPLIT_MAX : z);
+    sp.MZ = (M + sp.zsplit - 1) / sp.zsplit;
+    return sp;
+}
+
 hipEvent_t take_event(pphd_filter* f)
 {
     if (!f->ev_pool.empty()) {
@@ -291,23 +321,36 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
 {
     const DevModel dm = f->dm;
     SoA<T> st = soa<T>(f, f->cur);
+    const Geo geo = geo_of(f);
     const int K = f->K, Mx = f->max_meas;
-    dim3 g1((f->wtiles1 + 3) / 4, K), g2((f->wtiles2 + 3) / 4, K);
-    LAUNCH(f, PPHD_K_CZ,
-           hipLaunchKernelGGL((k_cz<T, PT1>), g1, dim3(256), 0, f->stream, dm, st, f->ncur, dz, M, Mx, f->wtiles1,
-                              f->p1s, f->p1h, f->p1w));
+    const Split s1 = split_for(f->wtiles1, M), s2 = split_for(f->wtiles2, M);
+    dim3 g1((f->wtiles1 * s1.zsplit + 3) / 4, K), g2((f->wtiles2 * s2.zsplit + 3) / 4, K);
+    if (dm.kappa > 0.0) {
+        LAUNCH(f, PPHD_K_CZ,
+               hipLaunchKernelGGL((k_cz<T, PT1, false>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
+                                  f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
+    } else {
+        LAUNCH(f, PPHD_K_CZ,
+               hipLaunchKernelGGL((k_cz<T, PT1, true>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
+                                  f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
+    }
     LAUNCH(f, PPHD_K_CZ_COMBINE,
-           hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(256), (size_t)Mx * sizeof(double), f->stream, dm,
+           hipLaunchKernelGGL((k_cz_combine<T>), dim3(M > 0 ? (M + 3) / 4 : 1, K), dim3(256), 0, f->stream, dm,
                               f->ncur, M, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH, (T*)f->zF, f->zC,
-                              f->zdW, f->zflag, f->cand, f->ncand));
+                              f->zdW, f->zflag));
+    LAUNCH(f, PPHD_K_CAND,
+           hipLaunchKernelGGL(k_cand, dim3(K), dim3(256), (size_t)Mx * sizeof(double), f->stream, dm.nu, f->ncur, M,
+                              Mx, f->wtiles1, f->wt1, f->p1w, f->zdW, f->zflag, f->cand, f->ncand));
     LAUNCH(f, PPHD_K_WEIGHT,
-           hipLaunchKernelGGL((k_weight<T, PT2>), g2, dim3(256), 0, f->stream, dm, st, f->ncur, dz, M, Mx,
-                              f->wtiles2, f->zH, (const T*)f->zF, f->zflag, f->cand, f->ncand, f->p2mass, f->p2max,
-                              f->p2zeta));
+           hipLaunchKernelGGL((k_weight<T, PT2>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M, Mx, s2,
+                              f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
+    LAUNCH(f, PPHD_K_WFINAL,
+           hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, st.w, f->ncur,
+                              (const T*)f->accp, s2.zsplit, f->tiles256, f->p2mass, f->p2max));
     LAUNCH(f, PPHD_K_FINALIZE,
-           hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->ncur, M, Mx, f->wtiles2, f->wt2,
-                              f->p2mass, f->p2max, f->p2zeta, f->cand, f->ncand, f->fmass, f->fLT, f->rsS, f->sel,
-                              f->zeta));
+           hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->ncur, f->tiles256, f->p2mass,
+                              f->p2max, M, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass, f->fLT,
+                              f->rsS, f->sel, f->zeta));
     return PPHD_OK;
 }
 
@@ -316,8 +359,8 @@ pphd_status run_predict(pphd_filter* f, uint32_t step)
 {
     dim3 g((f->cap + 255) / 256, f->K);
     LAUNCH(f, PPHD_K_PREDICT,
-           hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, soa<T>(f, f->cur), f->nsurv, f->ncur,
-                              step));
+           hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, soa<T>(f, f->cur), geo_of(f),
+                              f->nsurv, f->ncur, step));
     return PPHD_OK;
 }
 
@@ -336,10 +379,10 @@ pphd_status run_resample(pphd_filter* f, uint32_t step)
     dim3 g(f->rtiles, f->K);
     SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
     LAUNCH(f, PPHD_K_RS_TILES,
-           hipLaunchKernelGGL((k_rs_tiles<T, PR>), g, dim3(256), 0, f->stream, f->dm, (const T*)in.w, f->ncur, f->rsS,
+           hipLaunchKernelGGL((k_rs_tiles<T>), g, dim3(256), 0, f->stream, f->dm, (const T*)in.w, f->ncur, f->rsS,
                               f->rtiles, f->tsum));
     LAUNCH(f, PPHD_K_RS_EXPAND,
-           hipLaunchKernelGGL((k_rs_expand<T, PR>), g, dim3(256), 0, f->stream, f->dm, in, out, f->ncur, f->nsurv,
+           hipLaunchKernelGGL((k_rs_expand<T>), g, dim3(256), 0, f->stream, f->dm, in, out, f->ncur, f->nsurv,
                               f->rsS, f->tsum, f->rtiles, step, f->massq, f->clampctr, f->counts,
                               f->record ? 1 : 0));
     f->cur = 1 - f->cur;
@@ -375,9 +418,15 @@ pphd_status check_handle(pphd_filter* f)
 
 pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout)
 {
-    LAUNCH(f, PPHD_K_FUSE,
-           hipLaunchKernelGGL(k_fuse, dim3(1), dim3(256), 0, f->stream, f->K, f->last_m, f->max_meas, f->sel, f->zeta,
-                              out, cap, nout));
+    const int M = f->last_m;
+    if (M > 0) {
+        LAUNCH(f, PPHD_K_FUSE,
+               hipLaunchKernelGGL(k_fuse_labels, dim3((M + 3) / 4), dim3(256), 0, f->stream, f->K, M, f->max_meas,
+                                  f->sel, f->zeta, f->fkeep, f->frec));
+    }
+    LAUNCH(f, PPHD_K_FUSE_COMPACT,
+           hipLaunchKernelGGL(k_fuse_compact, dim3(1), dim3(256), 0, f->stream, M, f->fkeep, f->frec, out, cap,
+                              nout));
     return PPHD_OK;
 }
 
@@ -616,6 +665,18 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
     if (s != PPHD_OK) return s;
     const bool is_cur = phase == PPHD_PHASE_PREDICTED || phase == PPHD_PHASE_UPDATED;
     HIP_TRY(hipMemcpy(is_cur ? f->ncur : f->nsurv, count, (size_t)f->K * 4, hipMemcpyHostToDevice));
+    if (phase == PPHD_PHASE_PREDICTED) {
+        dim3 g((f->cap + 255) / 256, f->K);
+        if (f->prec == PPHD_FP64) {
+            LAUNCH(f, PPHD_K_GEOM,
+                   hipLaunchKernelGGL((k_geom<double>), g, dim3(256), 0, f->stream, f->dm, soa<double>(f, f->cur),
+                                      geo_of(f), f->ncur));
+        } else {
+            LAUNCH(f, PPHD_K_GEOM,
+                   hipLaunchKernelGGL((k_geom<float>), g, dim3(256), 0, f->stream, f->dm, soa<float>(f, f->cur),
+                                      geo_of(f), f->ncur));
+        }
+    }
     if (phase == PPHD_PHASE_UPDATED) {
         if (f->prec == PPHD_FP64) {
             LAUNCH(f, PPHD_K_WMAX,

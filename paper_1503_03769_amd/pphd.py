@@ -19,7 +19,7 @@ PPHD_OK, PPHD_EINVAL, PPHD_ENOMEM, PPHD_ECAPACITY, PPHD_EDEVICE, PPHD_ESTATE = 0
 PPHD_FP64, PPHD_FP32 = 0, 1
 PHASE_READY, PHASE_PREDICTED, PHASE_UPDATED, PHASE_RESAMPLED = 1, 2, 3, 4
 KERNEL_CLASSES = ["predict", "cz", "cz_combine", "weight", "finalize", "fuse", "rs_tiles", "rs_expand",
-                  "xchg_gather", "xchg_scatter", "init", "wmax"]
+                  "xchg_gather", "xchg_scatter", "init", "wmax", "geom", "wfinal", "fuse_compact", "cand"]
 K_COUNT = len(KERNEL_CLASSES)
 
 
@@ -298,6 +298,11 @@ class Filter:
         n = np.zeros(self.K, dtype=np.int32)
         pphd_read_state(self.h, X.ctypes.data, W.ctypes.data, n.ctypes.data)
         return X, W, n
+
+    def read_counts(self):
+        n = np.zeros(self.K, dtype=np.int32)
+        pphd_read_state(self.h, None, None, n.ctypes.data)
+        return n
 
     def write_state(self, X, W, n, phase):
         X = np.ascontiguousarray(X, dtype=np.float64)
