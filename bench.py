@@ -193,13 +193,8 @@ def cpu_baseline(p, w, truth, Z, seed, run, budget_s):
     steps = 0
     t0 = time.perf_counter()
     for k in range(1, len(Z)):
-        orc.predict(p, o.st, k, seed, run)
-        pairs += int(o.st.n.sum()) * Z[k].shape[0]
-        upd = orc.update(p, o.st, Z[k])
-        ext = orc.extract(p, Z[k].shape[0], upd)
-        orc.fuse(p, Z[k].shape[0], ext)
-        o.st, _, _ = orc.resample(p, o.st, k, seed, run)
-        orc.exchange(p, o.st, k, seed, run)
+        out = o.step(k, Z[k])
+        pairs += int(out["n_pred"].sum()) * Z[k].shape[0]
         steps += 1
         if time.perf_counter() - t0 > budget_s:
             break

@@ -38,6 +38,7 @@ class OrcModel(ctypes.Structure):
         ("birth_mass", ctypes.c_double), ("region", ctypes.c_double * 4),
         ("birth_sigma_v", ctypes.c_double), ("init_mass", ctypes.c_double),
         ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
+        ("birth_proposal", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
     ]
 
 
@@ -52,6 +53,8 @@ def model_struct(p: dict) -> OrcModel:
         setattr(m, k, float(p[k]))
     for i in range(4):
         m.region[i] = float(p["region"][i])
+    m.birth_proposal = int(p.get("birth_proposal", 0))
+    m.birth_alpha = float(p.get("birth_alpha", 1.0))
     return m
 
 
@@ -79,6 +82,9 @@ def lib():
         L.orc_init.argtypes = [M, c_int, u64, u32, D, D, I]
         L.orc_predict.argtypes = [M, c_int, u32, u64, u32, D, D, I]
         L.orc_update.argtypes = [M, c_int, D, c_int, D, D, I, D, D, D, D, D]
+        L.orc_birth_proposal_density.argtypes = [M, D, c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_birth_proposal_density.restype = ctypes.c_double
+        L.orc_birth_from_measurements.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
         L.orc_extract.argtypes = [M, c_int, D, D, D, I, I, D]
         L.orc_fuse.argtypes = [M, c_int, I, D, D, I, I, I]
         L.orc_resample.argtypes = [M, c_int, u32, u64, u32, D, D, I, D, D, I, I, D]
@@ -156,6 +162,23 @@ def init(p, st, seed, run):
 def predict(p, st, step, seed, run):
     _check(lib().orc_predict(ctypes.byref(model_struct(p)), st.cap, step, seed, run,
                              _d(st.X), _d(st.W), _i(st.n)), "predict")
+
+
+def _zbuf(Z):
+    Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).reshape(-1, 2))
+    return Z, (Z.reshape(-1) if Z.shape[0] > 0 else np.zeros(2))
+
+
+def birth_proposal_density(p, Z, x, y):
+    Z, Zb = _zbuf(Z)
+    return lib().orc_birth_proposal_density(ctypes.byref(model_struct(p)), _d(Zb), Z.shape[0], x, y)
+
+
+def birth_from_measurements(p, st, step, seed, run, Z):
+    """Fills the J_j reserved birth slots of every group (measurement-driven proposal)."""
+    Z, Zb = _zbuf(Z)
+    _check(lib().orc_birth_from_measurements(ctypes.byref(model_struct(p)), st.cap, step, seed, run, _d(Zb),
+                                              Z.shape[0], _d(st.X), _d(st.W), _i(st.n)), "birth_from_measurements")
 
 
 def update(p, st, Z):
@@ -249,9 +272,12 @@ class OracleFilter:
         p = self.p
         predict(p, self.st, k, self.seed, self.run)
         Z = np.asarray(Z, dtype=np.float64).reshape(-1, 2)
+        if int(p.get("birth_proposal", 0)) == 1:
+            birth_from_measurements(p, self.st, k, self.seed, self.run, Z)
+        n_pred = self.st.n.copy()
         upd = update(p, self.st, Z)
         ext = extract(p, Z.shape[0], upd)
         est = fuse(p, Z.shape[0], ext)
         self.st, counts, mq = resample(p, self.st, k, self.seed, self.run)
         exchange(p, self.st, k, self.seed, self.run)
-        return dict(upd=upd, ext=ext, est=est, counts=counts, mass_q=mq)
+        return dict(upd=upd, ext=ext, est=est, counts=counts, mass_q=mq, n_pred=n_pred)

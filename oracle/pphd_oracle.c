@@ -200,8 +200,10 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
             W[g] = m->p_S * W[g];
         }
         /* Births, Eq 6 with proposal p_k = gamma / m_b: weight m_b / J_j.
-         * Reading: each group carries the full birth mass (J_j births). */
-        for (int b = 0; b < Jj; ++b) {
+         * Reading: each group carries the full birth mass (J_j births).
+         * With the measurement-driven proposal the J_j slots are reserved
+         * here and drawn by orc_birth_from_measurements once Z_k is known. */
+        for (int b = 0; b < Jj && m->birth_proposal == 0; ++b) {
             uint32_t g = (uint32_t)(j * cap + ns + b);
             double st[4];
             orc_draw_birth(m, seed, g, step, ORC_BIRTH, run, st);
@@ -209,6 +211,93 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
             W[g] = m->birth_mass / (double)Jj;
         }
         n[j] = ns + Jj;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Births from a measurement-driven proposal p_k(. | Z_k) (Eq 6).            */
+/* Reading: the proposal is the defensive mixture                            */
+/*   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p q_p(x),              */
+/* where q_p draws R ~ N(r_p, sigma_r^2), Theta ~ N(theta_p, sigma_theta^2)   */
+/* (the inverse of the sensor model) and puts the particle at                */
+/* s + R (cos Theta, sin Theta), with velocity N(0, sigma_v^2 I) as in the    */
+/* birth density.  The weight of Eq 6 is gamma(x) / (J_j q(x)); the velocity */
+/* factors cancel, leaving m_b U(x) / (J_j q_pos(x)) with U the uniform       */
+/* density of the surveillance region.                                        */
+/* ------------------------------------------------------------------------ */
+
+static double orc_gauss(double d, double sigma)
+{
+    double e = d / sigma;
+    return exp(-0.5 * e * e) / (sqrt(2.0 * ORC_PI) * sigma);
+}
+
+/* Position density of the proposal at (x, y).  A point at distance rho and
+ * bearing phi is reached by R = rho, Theta = phi (mod 2 pi) and by R = -rho,
+ * Theta = phi + pi (mod 2 pi); the Jacobian of the polar map is 1/rho.  The
+ * wrapped normal of Theta is represented by its nearest branch (the others
+ * are below exp(-(pi/sigma_theta)^2/2)). */
+double orc_birth_proposal_density(const orc_model* m, const double* Z, int M, double x, double y)
+{
+    double area = (m->region[1] - m->region[0]) * (m->region[3] - m->region[2]);
+    int inside = x >= m->region[0] && x <= m->region[1] && y >= m->region[2] && y <= m->region[3];
+    double u = inside ? 1.0 / area : 0.0;
+    if (M == 0) return u;
+    double dx = x - m->sensor_x, dy = y - m->sensor_y;
+    double rho = sqrt(dx * dx + dy * dy);
+    double phi = atan2(dy, dx);
+    double mix = 0.0;
+    for (int p = 0; p < M; ++p) {
+        double a = orc_gauss(rho - Z[2 * p], m->sigma_r) * orc_gauss(orc_wrap(phi - Z[2 * p + 1]), m->sigma_theta);
+        double b = orc_gauss(rho + Z[2 * p], m->sigma_r) * orc_gauss(orc_wrap(phi + ORC_PI - Z[2 * p + 1]), m->sigma_theta);
+        mix += (a + b) / rho;
+    }
+    return m->birth_alpha * u + (1.0 - m->birth_alpha) * mix / (double)M;
+}
+
+int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
+                                const double* Z, int M, double* X, double* W, const int32_t* n)
+{
+    int K = m->partitions;
+    size_t KC = (size_t)K * (size_t)cap;
+    double area = (m->region[1] - m->region[0]) * (m->region[3] - m->region[2]);
+    for (int j = 0; j < K; ++j) {
+        int Jj = orc_births_in_partition(m, j);
+        int ns = n[j] - Jj;
+        if (ns < 0) return -1;
+        for (int b = 0; b < Jj; ++b) {
+            uint32_t g = (uint32_t)(j * cap + ns + b);
+            uint32_t a[4], v[4], c[4];
+            orc_block(seed, g, step, ORC_BIRTH, 0, run, a);
+            orc_block(seed, g, step, ORC_BIRTH, 1, run, v);
+            orc_block(seed, g, step, ORC_BIRTH, 2, run, c);
+            double u1 = orc_u53(a[0], a[1]), u2 = orc_u53(a[2], a[3]);
+            double uc = orc_u53(c[0], c[1]);
+            double x, y;
+            if (M == 0 || uc <= m->birth_alpha) {
+                x = m->region[0] + u1 * (m->region[1] - m->region[0]);
+                y = m->region[2] + u2 * (m->region[3] - m->region[2]);
+            } else {
+                int p = (int)floor((uc - m->birth_alpha) / (1.0 - m->birth_alpha) * (double)M);
+                if (p > M - 1) p = M - 1;
+                double e1, e2;
+                orc_normal_pair(u1, u2, &e1, &e2);
+                double R = Z[2 * p] + m->sigma_r * e1;
+                double Th = Z[2 * p + 1] + m->sigma_theta * e2;
+                x = m->sensor_x + R * cos(Th);
+                y = m->sensor_y + R * sin(Th);
+            }
+            double n1, n2;
+            orc_normal_pair(orc_u53(v[0], v[1]), orc_u53(v[2], v[3]), &n1, &n2);
+            XS(X, 0, g) = x;
+            XS(X, 1, g) = m->birth_sigma_v * n1;
+            XS(X, 2, g) = y;
+            XS(X, 3, g) = m->birth_sigma_v * n2;
+            int inside = x >= m->region[0] && x <= m->region[1] && y >= m->region[2] && y <= m->region[3];
+            double q = orc_birth_proposal_density(m, Z, M, x, y);
+            W[g] = inside ? m->birth_mass * (1.0 / area) / ((double)Jj * q) : 0.0;
+        }
     }
     return 0;
 }

@@ -36,6 +36,9 @@ typedef struct {
     double init_mass;
     double particles_per_target;                    /* R over all groups */
     double exchange_fraction;                       /* rho_x */
+    int32_t birth_proposal;   /* 0: births from gamma/m_b; 1: measurement-driven mixture */
+    int32_t reserved2;
+    double birth_alpha;       /* weight of gamma/m_b in the mixture (proposal 1) */
 } orc_model;
 
 enum { ORC_INIT = 1, ORC_PREDICT = 2, ORC_BIRTH = 3, ORC_RESAMPLE = 4, ORC_EXCHANGE = 5 };
@@ -51,6 +54,9 @@ int orc_init(const orc_model* m, int cap, uint64_t seed, uint32_t run,
              double* X, double* W, int32_t* n);
 int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                 double* X, double* W, int32_t* n);
+double orc_birth_proposal_density(const orc_model* m, const double* Z, int M, double x, double y);
+int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
+                                const double* Z, int M, double* X, double* W, const int32_t* n);
 int orc_update(const orc_model* m, int cap, const double* Z, int M,
                const double* X, double* W, const int32_t* n,
                double* C, double* dW, double* dW0, double* zeta_num, double* mass);

@@ -23,7 +23,8 @@ struct DevModel {
     double pS, pD, nu, kappa;
     double birth_mass, reg0, reg1, reg2, reg3, sigma_v, init_mass, Rj, xfrac;
     double cr, ct, period, inv_period, wscale;  // scaled likelihood, see above
-    int K, J, cap, M0;
+    double sigma_r, sigma_th, inv_area, alpha;  // measurement-driven birth proposal
+    int K, J, cap, M0, proposal, pad2;
     uint32_t key0, key1, run, pad;
 };
 
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, SoA<T> st, Geo geo,
         v[3] = vy + m.T * ay;
         w = m.pS * (double)st.w[g];
     } else {
+        if (m.proposal != 0) return;  // drawn by k_birth_meas once Z_k is known
         draw_birth(m, (uint32_t)g, step, RNG_BIRTH, v);
         w = m.birth_mass / (double)Jj;
     }
@@ -233,6 +235,90 @@ __global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, co
     if (s >= ncur[j]) return;
     const size_t g = (size_t)j * m.cap + s;
     store_geometry(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)st.w[g]);
+}
+
+// ---------------------------------------------------------------------------
+// Births from the measurement-driven proposal of Eq 6 (birth_proposal 1):
+//   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p q_p(x),
+// q_p drawing range N(r_p, sigma_r^2) and bearing N(theta_p, sigma_theta^2)
+// around the sensor.  Position density of q_p at distance rho, bearing phi:
+// [N(rho - r_p) N(wrap(phi - theta_p)) + N(rho + r_p) N(wrap(phi + pi - theta_p))]
+// / rho (a negative drawn range lands on the opposite side; 1/rho is the
+// polar Jacobian).  Weight gamma/(J_j q) = m_b U(x) / (J_j q_pos(x)) since
+// both components draw velocity from N(0, sigma_v^2 I).
+// grid (ceil(J_max/256), K).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_pi(double d)
+{
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    return d - two_pi * floor((d + 3.14159265358979323846) / two_pi);
+}
+
+// exp(-a) for a >= 0: hardware exp2 in float for the FP32 path (terms below
+// 2^-126 vanish, far under the mixture's alpha U floor), exp in double otherwise
+__device__ __forceinline__ double neg_exp(double a, float) { return (double)__builtin_amdgcn_exp2f((float)(-a * 1.4426950408889634)); }
+__device__ __forceinline__ double neg_exp(double a, double) { return exp(-a); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_birth_meas(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
+                                                    const double* __restrict__ Z, int M, uint32_t step)
+{
+    const int j = blockIdx.y;
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int Jj = births_in(m, j);
+    if (b >= Jj) return;
+    const size_t g = (size_t)j * m.cap + nsurv[j] + b;
+    const Block4 a = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 0, m.run);
+    const Block4 v = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 1, m.run);
+    const Block4 c = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 2, m.run);
+    const double u1 = uniform53(a.a, a.b), u2 = uniform53(a.c, a.d), uc = uniform53(c.a, c.b);
+    double x, y;
+    if (M == 0 || uc <= m.alpha) {
+        x = m.reg0 + u1 * (m.reg1 - m.reg0);
+        y = m.reg2 + u2 * (m.reg3 - m.reg2);
+    } else {
+        int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
+        p = p > M - 1 ? M - 1 : p;
+        double e1, e2;
+        normal_pair(u1, u2, e1, e2);
+        const double R = Z[2 * p] + m.sigma_r * e1;
+        const double th = Z[2 * p + 1] + m.sigma_th * e2;
+        x = m.sx + R * cos(th);
+        y = m.sy + R * sin(th);
+    }
+    double n1, n2;
+    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), n1, n2);
+    const bool inside = x >= m.reg0 && x <= m.reg1 && y >= m.reg2 && y <= m.reg3;
+    const double u = inside ? m.inv_area : 0.0;
+    double q = u;
+    if (M > 0) {
+        const double dx = x - m.sx, dy = y - m.sy;
+        const double rho = sqrt(dx * dx + dy * dy);
+        const double phi = atan2(dy, dx);
+        const double isr = 1.0 / m.sigma_r, ist = 1.0 / m.sigma_th;
+        double mix = 0.0;
+        for (int p = 0; p < M; ++p) {
+            const double zr = Z[2 * p], zt = Z[2 * p + 1];
+            const double er = (rho - zr) * isr, et = wrap_pi(phi - zt) * ist;
+            double t = neg_exp(0.5 * (er * er + et * et), T(0));
+            // the negative-range branch: exactly zero in double once r_p > 40 sigma_r
+            if (zr < 40.0 * m.sigma_r) {
+                const double fr = (rho + zr) * isr, ft = wrap_pi(phi + 3.14159265358979323846 - zt) * ist;
+                t += neg_exp(0.5 * (fr * fr + ft * ft), T(0));
+            }
+            mix += t;
+        }
+        mix *= 1.0 / (2.0 * 3.14159265358979323846 * m.sigma_r * m.sigma_th * rho);
+        q = m.alpha * u + (1.0 - m.alpha) * mix / (double)M;
+    }
+    const double w = inside ? m.birth_mass * m.inv_area / ((double)Jj * q) : 0.0;
+    const T tx = (T)x, ty = (T)y, tw = (T)w;
+    st.x[0][g] = tx;
+    st.x[1][g] = (T)(m.sigma_v * n1);
+    st.x[2][g] = ty;
+    st.x[3][g] = (T)(m.sigma_v * n2);
+    st.w[g] = tw;
+    store_geometry(m, geo, g, (double)tx, (double)ty, (double)tw);
 }
 
 // scaled squared residual q(z, x) + c
@@ -357,33 +443,36 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Combine the first-pass partials: one wavefront per (group j, measurement p),
-// lanes over the group's tiles (fixed tree order):
+// Combine the first-pass partials of group j (one 1024-thread workgroup per
+// group; one wavefront per measurement, lanes over the group's tiles in a
+// fixed tree order):
 //   H = max h over tiles with s > 0, S = sum s 2^(h - H)
 //   C = 2^H S,  F = 1/(kappa 2^-H + S) = 2^H/(kappa + C),  dW = S F = C/(kappa + C)
-// k_cand then picks, per group, the candidate labels for Step 3:
-// the top min(LT_c + 1, #dW>0) measurements by dW (ties to the lower index),
-// where LT_c = round(nu sum w + sum dW) is the closed form of the updated mass
-// (the sums of Eq 8 swapped); the exact count LT differs from LT_c by at most
-// one, so the candidates always cover it.  zflag[p] = 1 + rank, or 0.
-// grid (max(1, ceil(M/4)), K), 256 threads, dynamic LDS Mmax doubles.
+// Then the candidate labels for Step 3: the top min(LT_c + 1, #dW>0)
+// measurements by dW (ties to the lower index), where LT_c = round(nu sum w +
+// sum dW) is the closed form of the updated mass (the sums of Eq 8 swapped);
+// the exact count LT differs from LT_c by at most one, so the candidates
+// always cover it.  zflag[p] = 1 + rank, or 0.
+// grid (K), 1024 threads, dynamic LDS Mmax doubles.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_cz_combine(DevModel m, const int* __restrict__ ncur, int M, int Mmax,
-                                                    int wtiles, int WT, const double* __restrict__ ps,
-                                                    const int* __restrict__ ph, const double* __restrict__ pw,
-                                                    int* __restrict__ zH, T* __restrict__ zF,
-                                                    double* __restrict__ zC, double* __restrict__ zdW,
-                                                    int* __restrict__ zflag)
+__global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const int* __restrict__ ncur, int M, int Mmax,
+                                                     int wtiles, int WT, const double* __restrict__ ps,
+                                                     const int* __restrict__ ph, const double* __restrict__ pw,
+                                                     int* __restrict__ zH, T* __restrict__ zF,
+                                                     double* __restrict__ zC, double* __restrict__ zdW,
+                                                     int* __restrict__ zflag, int* __restrict__ cand,
+                                                     int* __restrict__ ncand)
 {
-    const int j = blockIdx.y;
-    const int lane = threadIdx.x & 63;
-    const int wv = wave_in_block();
-    const int p = blockIdx.x * 4 + wv;
+    extern __shared__ double sm_dw[];
+    __shared__ double s_red[16];
+    __shared__ int s_redi[16];
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const int n = ncur[j];
     const int nw = (n + WT - 1) / WT;
     const size_t zb = (size_t)j * Mmax;
-    if (p < M) {
+    for (int p = wv; p < M; p += 16) {
         int H = -2147483647 - 1;
         for (int t = lane; t < nw; t += 64) {
             const size_t o = ((size_t)j * wtiles + t) * Mmax + p;
@@ -396,65 +485,52 @@ __global__ __launch_bounds__(256) void k_cz_combine(DevModel m, const int* __res
             if (ps[o] > 0.0) S += ldexp(ps[o], ph[o] - H);
         }
         S = wave_sum(S);
+        double C = 0.0, F = 0.0, dW = 0.0;
+        if (S > 0.0) {
+            const double D = ldexp(m.kappa, -H) + S;
+            F = 1.0 / D;
+            dW = S / D;
+            C = ldexp(S, H);
+        } else {
+            H = 0;
+        }
         if (lane == 0) {
-            double C = 0.0, F = 0.0, dW = 0.0;
-            if (S > 0.0) {
-                const double D = ldexp(m.kappa, -H) + S;
-                F = 1.0 / D;
-                dW = S / D;
-                C = ldexp(S, H);
-            } else {
-                H = 0;
-            }
             zH[zb + p] = H;
             zF[zb + p] = (T)F;
             zC[zb + p] = C;
             zdW[zb + p] = dW;
             zflag[zb + p] = 0;
+            sm_dw[p] = dW;
         }
     }
-}
-
-__global__ __launch_bounds__(256) void k_cand(double nu, const int* __restrict__ ncur, int M, int Mmax, int wtiles,
-                                              int WT, const double* __restrict__ pw,
-                                              const double* __restrict__ zdW, int* __restrict__ zflag,
-                                              int* __restrict__ cand, int* __restrict__ ncand)
-{
-    extern __shared__ double sm_dw[];
-    __shared__ double s_red[4];
-    __shared__ int s_redi[4];
-    const int j = blockIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int wv = wave_in_block();
-    const int n = ncur[j];
-    const int nw = (n + WT - 1) / WT;
-    const size_t zb = (size_t)j * Mmax;
-    const int tid = threadIdx.x;
+    double wsum = 0.0;
+    for (int t = tid; t < nw; t += 1024) wsum += pw[(size_t)j * wtiles + t];
+    __syncthreads();
     double dsum = 0.0;
     int pos = 0;
-    for (int q = tid; q < M; q += 256) {
-        const double v = zdW[zb + q];
-        sm_dw[q] = v;
-        dsum += v;
-        pos += v > 0.0 ? 1 : 0;
+    for (int q = tid; q < M; q += 1024) {
+        dsum += sm_dw[q];
+        pos += sm_dw[q] > 0.0 ? 1 : 0;
     }
-    double wsum = 0.0;
-    for (int t = tid; t < nw; t += 256) wsum += pw[(size_t)j * wtiles + t];
     dsum = wave_sum(dsum);
     wsum = wave_sum(wsum);
     pos = (int)wave_sum((double)pos);
     if (lane == 0) {
-        s_red[wv] = nu * wsum + dsum;
+        s_red[wv] = m.nu * wsum + dsum;
         s_redi[wv] = pos;
     }
     __syncthreads();
-    const double mass_c = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-    const int npos = (s_redi[0] + s_redi[1]) + (s_redi[2] + s_redi[3]);
+    double mass_c = 0.0;
+    int npos = 0;
+    for (int w2 = 0; w2 < 16; ++w2) {
+        mass_c += s_red[w2];
+        npos += s_redi[w2];
+    }
     const double lt = floor(mass_c + 0.5);
     const int LTc = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
     const int nc = LTc + 1 < npos ? LTc + 1 : npos;
     if (tid == 0) ncand[j] = nc;
-    for (int q = tid; q < M; q += 256) {
+    for (int q = tid; q < M; q += 1024) {
         const double v = sm_dw[q];
         if (!(v > 0.0)) continue;
         int rank = 0;
@@ -698,10 +774,11 @@ __global__ __launch_bounds__(256) void k_finalize(const int* __restrict__ ncur, 
 }
 
 // ---------------------------------------------------------------------------
-// Step 4, fusion at the central unit.  k_fuse_labels: one wavefront per label
-// counts the groups that report it and averages their estimates (tree sum
-// over groups in a fixed order); a label is kept when 2*votes > K.
-// k_fuse_compact: one workgroup writes the kept labels in label order.
+// Step 4, fusion at the central unit (one 1024-thread workgroup).  One
+// wavefront per label counts the groups that report it and averages their
+// estimates (tree sum over groups in a fixed order); a label is kept when
+// 2*votes > K.  Kept records are staged in LDS and written in label order.
+// grid (1), 1024 threads.
 // ---------------------------------------------------------------------------
 struct EstimateRec {
     double state[4];
@@ -709,59 +786,56 @@ struct EstimateRec {
     int32_t votes;
 };
 
-__global__ __launch_bounds__(256) void k_fuse_labels(int K, int M, int Mmax, const int* __restrict__ sel,
-                                                     const double* __restrict__ zeta, int* __restrict__ fkeep,
-                                                     EstimateRec* __restrict__ frec)
+__global__ __launch_bounds__(1024) void k_fuse(int K, int M, int Mmax, const int* __restrict__ sel,
+                                               const double* __restrict__ zeta, EstimateRec* __restrict__ out,
+                                               int cap, int* __restrict__ nout)
 {
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (p >= M) return;
-    double v = 0.0, a[4] = { 0, 0, 0, 0 };
-    for (int j0 = 0; j0 < K; j0 += 64) {
-        const int j = j0 + lane;
-        if (j < K && sel[(size_t)j * Mmax + p]) {
-            v += 1.0;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) a[d] += zeta[((size_t)j * Mmax + p) * 4 + d];
-        }
-    }
-    const int votes = (int)wave_sum(v);
-    double r[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) r[d] = wave_sum(a[d]);
-    if (lane == 0) {
-        const int keep = 2 * votes > K ? 1 : 0;
-        fkeep[p] = keep;
-        EstimateRec e;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) e.state[d] = keep ? r[d] / (double)votes : 0.0;
-        e.label = p;
-        e.votes = votes;
-        frec[p] = e;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_fuse_compact(int M, const int* __restrict__ fkeep,
-                                                      const EstimateRec* __restrict__ frec,
-                                                      EstimateRec* __restrict__ out, int cap, int* __restrict__ nout)
-{
-    __shared__ int scan[256];
-    const int tid = threadIdx.x;
+    __shared__ EstimateRec s_rec[1024];
+    __shared__ int s_keep[1024];
+    __shared__ int s_wtot[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     int offset = 0;
-    for (int p0 = 0; p0 < M; p0 += 256) {
-        const int p = p0 + tid;
-        const int keep = (p < M) ? fkeep[p] : 0;
-        scan[tid] = keep;
+    for (int p0 = 0; p0 < M; p0 += 1024) {
+        const int pe = (p0 + 1024 < M) ? p0 + 1024 : M;
+        s_keep[tid] = 0;
         __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            int v = tid >= o ? scan[tid - o] : 0;
-            __syncthreads();
-            scan[tid] += v;
-            __syncthreads();
+        for (int p = p0 + wv; p < pe; p += 16) {
+            double v = 0.0, a[4] = { 0, 0, 0, 0 };
+            for (int j0 = 0; j0 < K; j0 += 64) {
+                const int j = j0 + lane;
+                if (j < K && sel[(size_t)j * Mmax + p]) {
+                    v += 1.0;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) a[d] += zeta[((size_t)j * Mmax + p) * 4 + d];
+                }
+            }
+            const int votes = (int)wave_sum(v);
+            double r[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) r[d] = wave_sum(a[d]);
+            if (lane == 0 && 2 * votes > K) {
+                EstimateRec e;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) e.state[d] = r[d] / (double)votes;
+                e.label = p;
+                e.votes = votes;
+                s_rec[p - p0] = e;
+                s_keep[p - p0] = 1;
+            }
         }
-        const int idx = offset + scan[tid] - keep;
-        if (keep && idx < cap) out[idx] = frec[p];
-        offset += scan[255];
+        __syncthreads();
+        const int k = s_keep[tid];
+        const double inc = wave_incl_scan((double)k);
+        if (lane == 63) s_wtot[wv] = (int)inc;
+        __syncthreads();
+        int pre = 0, tot = 0;
+        for (int w2 = 0; w2 < 16; ++w2) {
+            pre += w2 < wv ? s_wtot[w2] : 0;
+            tot += s_wtot[w2];
+        }
+        const int idx = offset + pre + (int)inc - k;
+        if (k && idx < cap) out[idx] = s_rec[tid];
+        offset += tot;
         __syncthreads();
     }
     if (tid == 0) *nout = offset;

@@ -50,9 +50,9 @@ constexpr int PT1_F32 = 8, PT2_F32 = 8, PT1_F64 = 4, PT2_F64 = 4, PR = 1;
 constexpr int ZSPLIT_MAX = 8, MZ_TARGET = 16;
 
 const char* kKernelNames[PPHD_K_COUNT] = {
-    "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse_labels",
+    "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
     "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
-    "k_geom", "k_wfinal", "k_fuse_compact", "k_cand",
+    "k_geom", "k_wfinal", "k_birth_meas",
 };
 
 struct Layout {
@@ -81,7 +81,9 @@ struct pphd_filter {
     int phase = 0;  // 0 = created, otherwise a pphd_phase
     int cur = 0;    // which particle set is current
     int last_m = 0;
+    uint32_t last_step = 0;
     bool record = false;
+    bool births_pending = false;  // birth slots reserved by predict, drawn in update
     bool timing = false;
     int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0, tiles256 = 0;
     // device arrays (inside the workspace)
@@ -97,8 +99,6 @@ struct pphd_filter {
     double *p2mass = nullptr, *p2max = nullptr, *p2zeta = nullptr;
     double *geo_rho = nullptr, *geo_phi = nullptr, *geo_lw = nullptr;
     void* accp = nullptr;
-    int* fkeep = nullptr;
-    EstimateRec* frec = nullptr;
     double* fmass = nullptr;
     int *fLT = nullptr, *rsS = nullptr, *sel = nullptr;
     double* zeta = nullptr;
@@ -133,6 +133,9 @@ bool model_ok(const pphd_model* m, std::string& why)
     if (!(m->particles_per_target > 0)) { why = "particles_per_target must be > 0"; return false; }
     if (!(m->exchange_fraction >= 0 && m->exchange_fraction < 0.5)) { why = "exchange_fraction must be in [0, 0.5)"; return false; }
     if (!(m->birth_mass >= 0) || !(m->init_mass >= 0)) { why = "masses must be >= 0"; return false; }
+    if (m->birth_proposal != 0 && m->birth_proposal != 1) { why = "birth_proposal must be 0 or 1"; return false; }
+    if (m->birth_proposal == 1 && !(m->birth_alpha >= 0 && m->birth_alpha <= 1)) { why = "birth_alpha must be in [0,1]"; return false; }
+    if (!(m->region[1] > m->region[0]) || !(m->region[3] > m->region[2])) { why = "empty surveillance region"; return false; }
     return true;
 }
 
@@ -165,8 +168,6 @@ size_t carve(pphd_filter* f, char* base)
     f->geo_phi = L.take<double>(base, KC * 8);
     f->geo_lw = L.take<double>(base, KC * 8);
     f->accp = L.take<char>(base, (size_t)ZSPLIT_MAX * KC * es);
-    f->fkeep = L.take<int>(base, Mx * 4);
-    f->frec = L.take<EstimateRec>(base, Mx * sizeof(EstimateRec));
     f->p2zeta = L.take<double>(base, K * f->wtiles2 * Mx * 5 * 8);
     f->fmass = L.take<double>(base, K * 8);
     f->fLT = L.take<int>(base, K * 4);
@@ -245,6 +246,11 @@ void fill_devmodel(pphd_filter* f)
     d.period = two_pi * d.ct;
     d.inv_period = 1.0 / d.period;
     d.wscale = m.p_D / (two_pi * m.sigma_r * m.sigma_theta);
+    d.sigma_r = m.sigma_r;
+    d.sigma_th = m.sigma_theta;
+    d.inv_area = 1.0 / ((m.region[1] - m.region[0]) * (m.region[3] - m.region[2]));
+    d.alpha = m.birth_alpha;
+    d.proposal = m.birth_proposal;
     d.K = m.partitions;
     d.J = m.births_per_step;
     d.cap = f->cap;
@@ -324,6 +330,15 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
     const Geo geo = geo_of(f);
     const int K = f->K, Mx = f->max_meas;
     const Split s1 = split_for(f->wtiles1, M), s2 = split_for(f->wtiles2, M);
+    if (f->births_pending) {
+        const int Jmax = dm.J / K + (dm.J % K ? 1 : 0);
+        if (Jmax > 0) {
+            LAUNCH(f, PPHD_K_BIRTH,
+                   hipLaunchKernelGGL((k_birth_meas<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm, st,
+                                      geo, f->nsurv, dz, M, f->last_step));
+        }
+        f->births_pending = false;
+    }
     dim3 g1((f->wtiles1 * s1.zsplit + 3) / 4, K), g2((f->wtiles2 * s2.zsplit + 3) / 4, K);
     if (dm.kappa > 0.0) {
         LAUNCH(f, PPHD_K_CZ,
@@ -335,12 +350,9 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
                                   f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
     }
     LAUNCH(f, PPHD_K_CZ_COMBINE,
-           hipLaunchKernelGGL((k_cz_combine<T>), dim3(M > 0 ? (M + 3) / 4 : 1, K), dim3(256), 0, f->stream, dm,
+           hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
                               f->ncur, M, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH, (T*)f->zF, f->zC,
-                              f->zdW, f->zflag));
-    LAUNCH(f, PPHD_K_CAND,
-           hipLaunchKernelGGL(k_cand, dim3(K), dim3(256), (size_t)Mx * sizeof(double), f->stream, dm.nu, f->ncur, M,
-                              Mx, f->wtiles1, f->wt1, f->p1w, f->zdW, f->zflag, f->cand, f->ncand));
+                              f->zdW, f->zflag, f->cand, f->ncand));
     LAUNCH(f, PPHD_K_WEIGHT,
            hipLaunchKernelGGL((k_weight<T, PT2>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M, Mx, s2,
                               f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
@@ -418,15 +430,9 @@ pphd_status check_handle(pphd_filter* f)
 
 pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout)
 {
-    const int M = f->last_m;
-    if (M > 0) {
-        LAUNCH(f, PPHD_K_FUSE,
-               hipLaunchKernelGGL(k_fuse_labels, dim3((M + 3) / 4), dim3(256), 0, f->stream, f->K, M, f->max_meas,
-                                  f->sel, f->zeta, f->fkeep, f->frec));
-    }
-    LAUNCH(f, PPHD_K_FUSE_COMPACT,
-           hipLaunchKernelGGL(k_fuse_compact, dim3(1), dim3(256), 0, f->stream, M, f->fkeep, f->frec, out, cap,
-                              nout));
+    LAUNCH(f, PPHD_K_FUSE,
+           hipLaunchKernelGGL(k_fuse, dim3(1), dim3(1024), 0, f->stream, f->K, f->last_m, f->max_meas, f->sel,
+                              f->zeta, out, cap, nout));
     return PPHD_OK;
 }
 
@@ -521,6 +527,8 @@ pphd_status pphd_predict(pphd_filter* f, uint32_t step)
         return fail(PPHD_ESTATE, "predict needs phase READY or RESAMPLED (have %d)", f->phase);
     pphd_status s = f->prec == PPHD_FP64 ? run_predict<double>(f, step) : run_predict<float>(f, step);
     if (s != PPHD_OK) return s;
+    f->last_step = step;
+    f->births_pending = f->model.birth_proposal == 1;
     f->phase = PPHD_PHASE_PREDICTED;
     return PPHD_OK;
 }
@@ -665,6 +673,7 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
     if (s != PPHD_OK) return s;
     const bool is_cur = phase == PPHD_PHASE_PREDICTED || phase == PPHD_PHASE_UPDATED;
     HIP_TRY(hipMemcpy(is_cur ? f->ncur : f->nsurv, count, (size_t)f->K * 4, hipMemcpyHostToDevice));
+    f->births_pending = false;  // a written state is complete
     if (phase == PPHD_PHASE_PREDICTED) {
         dim3 g((f->cap + 255) / 256, f->K);
         if (f->prec == PPHD_FP64) {

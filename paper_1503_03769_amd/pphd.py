@@ -19,7 +19,7 @@ PPHD_OK, PPHD_EINVAL, PPHD_ENOMEM, PPHD_ECAPACITY, PPHD_EDEVICE, PPHD_ESTATE = 0
 PPHD_FP64, PPHD_FP32 = 0, 1
 PHASE_READY, PHASE_PREDICTED, PHASE_UPDATED, PHASE_RESAMPLED = 1, 2, 3, 4
 KERNEL_CLASSES = ["predict", "cz", "cz_combine", "weight", "finalize", "fuse", "rs_tiles", "rs_expand",
-                  "xchg_gather", "xchg_scatter", "init", "wmax", "geom", "wfinal", "fuse_compact", "cand"]
+                  "xchg_gather", "xchg_scatter", "init", "wmax", "geom", "wfinal", "birth_meas"]
 K_COUNT = len(KERNEL_CLASSES)
 
 
@@ -43,6 +43,7 @@ class pphd_model(ctypes.Structure):
         ("birth_mass", ctypes.c_double), ("region", ctypes.c_double * 4),
         ("birth_sigma_v", ctypes.c_double), ("init_mass", ctypes.c_double),
         ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
+        ("birth_proposal", ctypes.c_int32), ("reserved", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
     ]
 
 
@@ -122,6 +123,8 @@ def model_struct(p: dict, precision: int) -> pphd_model:
         setattr(m, k, float(p[k]))
     for i in range(4):
         m.region[i] = float(p["region"][i])
+    m.birth_proposal = int(p.get("birth_proposal", 0))
+    m.birth_alpha = float(p.get("birth_alpha", 1.0))
     return m
 
 

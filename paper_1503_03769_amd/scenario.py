@@ -8,12 +8,13 @@ streams.
 
 Workload recipe (the paper's truth tracks are not available, so a seeded
 generator stands in for them):
-  * target i of n is born at step b_i = 1 + floor(u T/2) and dies at
-    min(T, b_i + ceil(T/2) + floor(u' T/2)), or earlier when it leaves the
-    surveillance square [-1000, 1000]^2;
+  * target i of n appears at step b_i = 1 + floor(u T/10) and disappears after
+    step T - floor(u' T/10), so most targets are present for most of the run;
   * its initial position is uniform in [-800, 800]^2, its velocity N(0, 10^2 I),
     and it moves with the constant-velocity model of section 4 (acceleration
-    noise sigma_a on each axis);
+    noise sigma_a on each axis); at the edge of the surveillance square
+    [-1000, 1000]^2 it is reflected (position mirrored, velocity component
+    negated), so it stays in view;
   * each live target is detected with probability p_D; a detection is
     [range, bearing] + N(0, diag(sigma_r^2, sigma_theta^2)) with the bearing
     wrapped into [-pi, pi);
@@ -30,19 +31,22 @@ BASE_MODEL = dict(
     th_min=-math.pi, th_max=math.pi, birth_mass=0.1,
     region=(-1000.0, 1000.0, -1000.0, 1000.0), birth_sigma_v=10.0, init_mass=1.0,
     particles_per_target=1000.0, exchange_fraction=0.1, partitions=1, births_per_step=500,
+    birth_proposal=0, birth_alpha=1.0,
 )
 
 # Named workloads.  "precision" is the GPU path's storage type; the oracle is FP64.
+# Births use the measurement-driven proposal of Eq 6 (a 0.1 share of the
+# birth density itself keeps the importance weights bounded).
 WORKLOADS = {
     # 3 targets, 50 steps, one group, FP64 everywhere.
     "plain_fp64_3tgt": dict(
         model=dict(BASE_MODEL, clutter_rate=10.0, particles_per_target=1000.0,
-                   births_per_step=500, partitions=1),
+                   births_per_step=500, partitions=1, birth_proposal=1, birth_alpha=0.1),
         n_targets=3, steps=50, cap=16384, precision="fp64", max_meas=256, config_index=1),
     # 10 targets, 100 steps, 64 groups with exchange and fusion, FP32 storage.
     "large_fp32_10tgt_k64": dict(
         model=dict(BASE_MODEL, clutter_rate=50.0, particles_per_target=1.0e5,
-                   births_per_step=50000, partitions=64),
+                   births_per_step=50000, partitions=64, birth_proposal=1, birth_alpha=0.1),
         n_targets=10, steps=100, cap=32768, precision="fp32", max_meas=512, config_index=2),
 }
 
@@ -58,18 +62,27 @@ def _cv_step(rng, s, T, sigma_a):
                      y + T * vy + 0.5 * T * T * a[1], vy + T * a[1]])
 
 
+def _reflect(s, lo, hi, ip, iv):
+    while not (lo <= s[ip] <= hi):
+        if s[ip] > hi:
+            s[ip] = 2 * hi - s[ip]
+        else:
+            s[ip] = 2 * lo - s[ip]
+        s[iv] = -s[iv]
+    return s
+
+
 def make_scenario(model: dict, n_targets: int, steps: int, seed: int, start_box=(-800.0, 800.0, -800.0, 800.0),
                   start_sigma_v=10.0, surveillance=(-1000.0, 1000.0, -1000.0, 1000.0)):
     """Returns (truth, Z): truth[k] is an array [n_alive, 4] and Z[k] an array
     [M_k, 2] of (range, bearing) for k = 1..steps (index 0 is unused).
     start_box / start_sigma_v: where targets appear and their velocity spread;
-    surveillance: targets that leave this square die."""
+    surveillance: the square targets are reflected at."""
     rng = np.random.Generator(np.random.PCG64(seed))
     T, sa = model["T"], model["sigma_a"]
     xmin, xmax, ymin, ymax = surveillance
-    births = [1 + int(math.floor(rng.uniform() * steps / 2)) for _ in range(n_targets)]
-    deaths = [min(steps, b + int(math.ceil(steps / 2)) + int(math.floor(rng.uniform() * steps / 2)))
-              for b in births]
+    births = [1 + int(math.floor(rng.uniform() * steps / 10)) for _ in range(n_targets)]
+    deaths = [steps - int(math.floor(rng.uniform() * steps / 10)) for _ in range(n_targets)]
     states = [None] * n_targets
     truth = [np.zeros((0, 4))]
     Z = [np.zeros((0, 2))]
@@ -77,21 +90,15 @@ def make_scenario(model: dict, n_targets: int, steps: int, seed: int, start_box=
         alive = []
         for i in range(n_targets):
             if k < births[i] or k > deaths[i]:
-                states[i] = None if k > deaths[i] else states[i]
                 continue
             if k == births[i]:
                 states[i] = np.array([rng.uniform(start_box[0], start_box[1]), rng.normal(0, start_sigma_v),
                                       rng.uniform(start_box[2], start_box[3]), rng.normal(0, start_sigma_v)])
-            elif states[i] is not None:
+            else:
                 states[i] = _cv_step(rng, states[i], T, sa)
-            if states[i] is None:
-                continue
-            s = states[i]
-            if not (xmin <= s[0] <= xmax and ymin <= s[2] <= ymax):
-                states[i] = None
-                deaths[i] = k - 1
-                continue
-            alive.append(s.copy())
+                states[i] = _reflect(states[i], xmin, xmax, 0, 1)
+                states[i] = _reflect(states[i], ymin, ymax, 2, 3)
+            alive.append(states[i].copy())
         tk = np.array(alive).reshape(-1, 4)
         meas = []
         for s in tk:

@@ -159,6 +159,37 @@ def test_exchange_exact(gpu, prec, K, counts):
     f.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_measurement_driven_births(gpu, prec):
+    """Eq 6 with p_k(.|Z_k): predict reserves the birth slots, update draws
+    them from the measurement-driven mixture and then updates all weights."""
+    print(f"measurement-driven births {prec}", flush=True)
+    K, cap = 3, 4096
+    p = dict(BASE_MODEL, partitions=K, births_per_step=900, birth_proposal=1, birth_alpha=0.1)
+    truth, Z = _scen(p, n=4)
+    X, W, n = P.cloud(K, cap, [2000, 700, 0], 13, truth, prec)
+    f = P.make_filter(p, prec, cap)
+    f.write_state(X, W, n, pphd.PHASE_READY)
+    f.predict(4)
+    f.update(Z)
+    Xg, Wg, ng = f.read_state()
+    st = P.oracle_state(K, cap, X, W, n)
+    orc.predict(p, st, 4, 1234, 0)
+    orc.birth_from_measurements(p, st, 4, 1234, 0, Z)
+    births = st.copy()
+    # the GPU stores the drawn births at its storage precision before updating
+    st.X[:] = P.as_storage(st.X, prec)
+    st.W[:] = P.as_storage(st.W, prec)
+    orc.update(p, st, Z)
+    assert np.array_equal(ng, st.n)
+    rtol = 1e-12 if prec == "fp64" else 1e-6
+    for j in range(K):
+        sl = slice(j * cap, j * cap + int(st.n[j]))
+        np.testing.assert_allclose(Xg[:, sl], births.X[:, sl], rtol=rtol, atol=1e-9 if prec == "fp64" else 1e-4)
+    P.check_weights(Wg, st)
+    f.close()
+
+
 def test_no_clutter_far_measurement_keeps_unit_mass(gpu):
     """kappa = 0 and p_D = 1: each measurement hands exactly one unit of mass
     to the particles (the sum over i of the Eq 12 terms is C/C = 1), even for
