@@ -44,6 +44,9 @@ def parse():
                     help="bound on the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-timing-pass", action="store_true",
                     help="skip the HIP-event pass (for profiler runs)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -61,6 +64,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib > 0:
+        nel = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = WORKLOADS[args.workload]
     p = w["model"]
     prec = pphd.PPHD_FP32 if w["precision"] == "fp32" else pphd.PPHD_FP64

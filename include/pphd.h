@@ -200,6 +200,15 @@ pphd_status pphd_read_update(pphd_filter* f, double* C, double* dW, double* mass
  * local estimate of that label (0 elsewhere).  Synchronises. */
 pphd_status pphd_read_local(pphd_filter* f, int32_t* sel, double* zeta);
 
+/* Tile shape of the two likelihood passes of pphd_update: particles per
+ * thread of the C(z) pass and of the weight pass (4, 8 or 16 with FP32
+ * storage; 2, 4 or 8 with FP64) and the target number of measurements per
+ * wavefront (1..4096; the measurement loop is cut into at most 16 chunks).
+ * Results depend on it only through floating-point summation order.
+ * Defaults: 8, 8, 16 (FP32); 4, 4, 16 (FP64).  Takes effect at the next
+ * update; must not be called between pphd_update and pphd_resample. */
+pphd_status pphd_set_tuning(pphd_filter* f, int32_t pt_cz, int32_t pt_weight, int32_t meas_per_wave);
+
 /* Enables (1) or disables (0) recording of per-parent child counts in
  * resample, which costs one int32 store per parent. */
 pphd_status pphd_set_record_counts(pphd_filter* f, int32_t enable);

@@ -1,0 +1,85 @@
+"""Tile-shape autotuner for the two likelihood passes of pphd_update.
+
+For every tile shape (particles per thread of the C(z) pass and of the weight
+pass, measurements per wavefront) it runs the named workload from t = 0 and
+averages the passes' HIP-event times (k_cz + k_weight + k_wfinal) over a
+window of steady-state steps.  The fastest shape is written to tuning.json
+next to this file, keyed by storage precision; `pphd.Filter` applies it by
+default.  The shape changes only floating-point summation order.
+
+    python -m paper_1503_03769_amd.autotune [--workload NAME] [--steps A B]
+"""
+import argparse
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+SHAPES = {"fp32": [4, 8, 16], "fp64": [2, 4, 8]}
+MEAS_PER_WAVE = [8, 16, 32, 64]
+
+
+def tune(workload: str, first: int, last: int, verbose: bool = True):
+    import torch
+
+    from . import pphd
+    from .scenario import WORKLOADS, make_scenario, workload_seed
+
+    w = WORKLOADS[workload]
+    p = w["model"]
+    prec_name = w["precision"]
+    prec = pphd.PPHD_FP32 if prec_name == "fp32" else pphd.PPHD_FP64
+    seed = workload_seed(w["config_index"], 0)
+    truth, Z = make_scenario(p, w["n_targets"], last, seed)
+    zdev = [None] + [torch.from_numpy(np.ascontiguousarray(Z[k])).cuda() for k in range(1, last + 1)]
+    results = []
+    for pt1, pt2, mz in itertools.product(SHAPES[prec_name], SHAPES[prec_name], MEAS_PER_WAVE):
+        f = pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, 0, apply_tuning=False)
+        f.set_tuning(pt1, pt2, mz)
+        f.init()
+        for k in range(1, last + 1):
+            if k == first:
+                f.set_timing(True)
+            f.predict(k)
+            f.update(zdev[k])
+            f.resample(k)
+            f.exchange(k)
+        t = f.read_timing()
+        f.close()
+        n = max(t["cz"][1], 1)
+        us = 1e3 * (t["cz"][0] + t["weight"][0] + t["wfinal"][0]) / n
+        results.append((us, pt1, pt2, mz))
+        if verbose:
+            print(f"pt_cz={pt1:2d} pt_weight={pt2:2d} meas_per_wave={mz:3d}: {us:8.2f} us per update "
+                  f"(cz {1e3 * t['cz'][0] / n:6.2f}, weight {1e3 * t['weight'][0] / n:6.2f})", flush=True)
+    results.sort()
+    us, pt1, pt2, mz = results[0]
+    return dict(pt_cz=pt1, pt_weight=pt2, meas_per_wave=mz, passes_us=us, workload=workload,
+                steps=[first, last]), results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="large_fp32_10tgt_k64")
+    ap.add_argument("--steps", type=int, nargs=2, default=[20, 40])
+    ap.add_argument("--out", default=TUNING_PATH)
+    args = ap.parse_args()
+    best, _ = tune(args.workload, args.steps[0], args.steps[1])
+    data = {}
+    if os.path.exists(args.out):
+        with open(args.out) as fh:
+            data = json.load(fh)
+    from .scenario import WORKLOADS
+    data[WORKLOADS[args.workload]["precision"]] = best
+    with open(args.out, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(json.dumps(best), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

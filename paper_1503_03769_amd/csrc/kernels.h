@@ -168,7 +168,8 @@ __global__ __launch_bounds__(256) void k_init(DevModel m, SoA<T> st, int* __rest
 // ---------------------------------------------------------------------------
 struct Geo {
     double* rho;
-    double* phi;
+    double* phi;   // bearing c_t in [-pi, pi) c_t
+    double* phib;  // the same bearing in a frame turned by pi, also in [-pi, pi) c_t
     double* lw;
 };
 
@@ -176,7 +177,9 @@ __device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_
 {
     const double dx = x - m.sx, dy = y - m.sy;
     geo.rho[g] = sqrt(dx * dx + dy * dy) * m.cr;
-    geo.phi[g] = atan2(dy, dx) * m.ct;
+    const double ph = atan2(dy, dx);
+    geo.phi[g] = ph * m.ct;
+    geo.phib[g] = (ph < 0.0 ? ph + 3.14159265358979323846 : ph - 3.14159265358979323846) * m.ct;
     geo.lw[g] = (w > 0.0) ? log2(m.wscale * w) : -__builtin_inf();
 }
 
@@ -331,6 +334,32 @@ __device__ __forceinline__ double sq_resid(const DevModel& m, double zr, double 
     return fma(dr, dr, fma(dt, dt, c));
 }
 
+// Bearing frames.  With kappa > 0 the passes skip the modulo-2 pi wrap: a
+// measurement with |theta| <= pi/2 is compared with the particle bearings as
+// they are (frame A), any other with both turned by pi (frame B, where its
+// bearing is within pi/2 of zero).  In either frame a pair whose residual
+// would need wrapping is more than pi/2 apart in bearing, i.e. > 78 sigma_theta
+// for the workloads here, so its term underflows to exactly 0 with or without
+// the wrap.  kappa = 0 (EXACT) keeps the wrap, since there every C matters.
+struct ZFrame {
+    double zr, zt;
+    bool b;
+};
+__device__ __forceinline__ ZFrame z_frame(const DevModel& m, double r, double th)
+{
+    ZFrame f;
+    f.zr = r * m.cr;
+    f.b = fabs(th) > 0.5 * 3.14159265358979323846;
+    f.zt = (f.b ? (th < 0.0 ? th + 3.14159265358979323846 : th - 3.14159265358979323846) : th) * m.ct;
+    return f;
+}
+// scaled squared residual in a frame, + c
+__device__ __forceinline__ double sq_resid_nowrap(double zr, double zt, double rho, double phi, double c)
+{
+    const double dr = zr - rho, dt = zt - phi;
+    return fma(dr, dr, fma(dt, dt, c));
+}
+
 // Work split of the two likelihood passes: group j's slots are cut into wave
 // tiles of WT = 64*PT particles (lane l takes slots base + 64 i + l) and its
 // measurements into zsplit chunks of MZ; one wavefront takes one (tile, chunk)
@@ -354,13 +383,16 @@ struct Split {
 // particle they reach -1e3, where a float has lost 1e-4.
 // grid (ceil(wtiles*zsplit/4), K), 256 threads.
 // ---------------------------------------------------------------------------
-template <typename T, int PT, bool EXACT>
+enum : int { PASS_FRAMES = 0, PASS_WRAP = 1, PASS_EXACT = 2 };
+
+template <typename T, int PT, int MODE>
 __global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __restrict__ W,
                                             const int* __restrict__ ncur, const double* __restrict__ Z, int M,
                                             int Mmax, Split sp, double* __restrict__ ps, int* __restrict__ ph,
                                             double* __restrict__ pw)
 {
     constexpr int WT = 64 * PT;
+    constexpr bool EXACT = MODE == PASS_EXACT, FRAMES = MODE == PASS_FRAMES;
     const int j = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + wave_in_block();
@@ -369,17 +401,19 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __rest
     const int base = tile * WT;
     if (tile >= sp.wtiles || base >= n) return;
     const size_t gb = (size_t)j * m.cap;
-    double rho[PT], phi[PT], nlw[PT];
+    double rho[PT], phi[PT], phib[PT], nlw[PT];
     double lwmax = -__builtin_inf();
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
         rho[i] = 0.0;
         phi[i] = 0.0;
+        phib[i] = 0.0;
         nlw[i] = __builtin_inf();
         if (s < n) {
             rho[i] = geo.rho[gb + s];
             phi[i] = geo.phi[gb + s];
+            if (FRAMES) phib[i] = geo.phib[gb + s];
             const double lw = geo.lw[gb + s];
             nlw[i] = -lw;
             lwmax = lw > lwmax ? lw : lwmax;
@@ -407,38 +441,55 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __rest
     // measurements of the chunk, 64 at a time: lane l holds measurement pb + l,
     // each iteration broadcasts one with v_readlane (no memory latency in the loop)
     for (int pb = p0; pb < p1; pb += 64) {
-    const int pe = (pb + 64 < p1) ? pb + 64 : p1;
-    double lzr = 0.0, lzt = 0.0;
-    if (pb + lane < pe) {
-        lzr = Z[2 * (pb + lane)] * m.cr;
-        lzt = Z[2 * (pb + lane) + 1] * m.ct;
-    }
-    for (int p = pb; p < pe; ++p) {
-        const double zr = lane_value(lzr, p - pb), zt = lane_value(lzt, p - pb);
-        T s = 0;
-        double h = hw;
-        if (EXACT) {
-            double a[PT];
-            double amax = -__builtin_inf();
-#pragma unroll
-            for (int i = 0; i < PT; ++i) {
-                a[i] = -sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]);
-                amax = a[i] > amax ? a[i] : amax;
+        const int pe = (pb + 64 < p1) ? pb + 64 : p1;
+        double lzr = 0.0, lzt = 0.0;
+        int lfb = 0;
+        if (pb + lane < pe) {
+            const int q = pb + lane;
+            if (FRAMES) {
+                const ZFrame zf = z_frame(m, Z[2 * q], Z[2 * q + 1]);
+                lzr = zf.zr;
+                lzt = zf.zt;
+                lfb = zf.b ? 1 : 0;
+            } else {
+                lzr = Z[2 * q] * m.cr;
+                lzt = Z[2 * q + 1] * m.ct;
             }
-            const float wmx = wave_max((float)amax);
-            h = (wmx == -__builtin_inff()) ? 0.0 : (double)ceilf(wmx);
-#pragma unroll
-            for (int i = 0; i < PT; ++i) s += fast_exp2((T)(a[i] - h));
-        } else {
-#pragma unroll
-            for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]));
         }
-        const T sw = wave_sum(s);
-        if (lane == 0) {
-            ps[pbase + p] = (double)sw;
-            ph[pbase + p] = (int)h;
+        for (int p = pb; p < pe; ++p) {
+            const double zr = lane_value(lzr, p - pb), zt = lane_value(lzt, p - pb);
+            T s = 0;
+            double h = hw;
+            if (EXACT) {
+                double a[PT];
+                double amax = -__builtin_inf();
+#pragma unroll
+                for (int i = 0; i < PT; ++i) {
+                    a[i] = -sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]);
+                    amax = a[i] > amax ? a[i] : amax;
+                }
+                const float wmx = wave_max((float)amax);
+                h = (wmx == -__builtin_inff()) ? 0.0 : (double)ceilf(wmx);
+#pragma unroll
+                for (int i = 0; i < PT; ++i) s += fast_exp2((T)(a[i] - h));
+            } else if (FRAMES) {
+                if (lane_value(lfb, p - pb)) {
+#pragma unroll
+                    for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], phib[i], nlw[i]));
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], phi[i], nlw[i]));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], nlw[i]));
+            }
+            const T sw = wave_sum(s);
+            if (lane == 0) {
+                ps[pbase + p] = (double)sw;
+                ph[pbase + p] = (int)h;
+            }
         }
-    }
     }
 }
 
@@ -555,7 +606,7 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const int* __re
 // rank)*5 + k]; their ratio is the local estimate of Eq 18 (F cancels).
 // grid (ceil(wtiles*zsplit/4), K), 256 threads.
 // ---------------------------------------------------------------------------
-template <typename T, int PT>
+template <typename T, int PT, bool FRAMES>
 __global__ __launch_bounds__(256) void k_weight(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ ncur,
                                                 const double* __restrict__ Z, int M, int Mmax, Split sp,
                                                 const int* __restrict__ zH, const T* __restrict__ zF,
@@ -572,71 +623,91 @@ __global__ __launch_bounds__(256) void k_weight(DevModel m, SoA<T> st, Geo geo, 
     if (tile >= sp.wtiles || base >= n) return;
     const size_t gb = (size_t)j * m.cap;
     const size_t zb = (size_t)j * Mmax;
-    double rho[PT], phi[PT];
+    double rho[PT], phi[PT], phib[PT];
     T acc[PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
         rho[i] = 0.0;
         phi[i] = 0.0;
+        phib[i] = 0.0;
         acc[i] = 0;
         if (s < n) {
             rho[i] = geo.rho[gb + s];
             phi[i] = geo.phi[gb + s];
+            if (FRAMES) phib[i] = geo.phib[gb + s];
         }
     }
+    // exponential of one pair in the measurement's frame (or with the wrap)
+    auto term = [&](double zr, double zt, bool fb, double H, int i) -> T {
+        if (FRAMES) return fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], fb ? phib[i] : phi[i], H));
+        return fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H));
+    };
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
     const int p0 = zc * sp.MZ, p1 = (p0 + sp.MZ < M) ? p0 + sp.MZ : M;
     for (int pb = p0; pb < p1; pb += 64) {
-    const int pe = (pb + 64 < p1) ? pb + 64 : p1;
-    double lzr = 0.0, lzt = 0.0;
-    int lH = 0, lfl = 0;
-    T lF = 0;
-    if (pb + lane < pe) {
-        const int q = pb + lane;
-        lzr = Z[2 * q] * m.cr;
-        lzt = Z[2 * q + 1] * m.ct;
-        lH = zH[zb + q];
-        lF = zF[zb + q];
-        lfl = zflag[zb + q];
-    }
-    for (int p = pb; p < pe; ++p) {
-        const int l = p - pb;
-        const double zr = lane_value(lzr, l), zt = lane_value(lzt, l);
-        const double H = (double)lane_value(lH, l);
-        const T F = lane_value(lF, l);
-        const int fl = lane_value(lfl, l);
-        if (fl == 0) {
+        const int pe = (pb + 64 < p1) ? pb + 64 : p1;
+        double lzr = 0.0, lzt = 0.0;
+        int lH = 0, lfl = 0, lfb = 0;
+        T lF = 0;
+        if (pb + lane < pe) {
+            const int q = pb + lane;
+            if (FRAMES) {
+                const ZFrame zf = z_frame(m, Z[2 * q], Z[2 * q + 1]);
+                lzr = zf.zr;
+                lzt = zf.zt;
+                lfb = zf.b ? 1 : 0;
+            } else {
+                lzr = Z[2 * q] * m.cr;
+                lzt = Z[2 * q + 1] * m.ct;
+            }
+            lH = zH[zb + q];
+            lF = zF[zb + q];
+            lfl = zflag[zb + q];
+        }
+        for (int p = pb; p < pe; ++p) {
+            const int l = p - pb;
+            const double zr = lane_value(lzr, l), zt = lane_value(lzt, l);
+            const double H = (double)lane_value(lH, l);
+            const T F = lane_value(lF, l);
+            const int fl = lane_value(lfl, l);
+            const bool fb = FRAMES && lane_value(lfb, l) != 0;
+            if (fl == 0) {
+                if (fb) {
 #pragma unroll
-            for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H)) * F;
-        } else {
-            T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
+                    for (int i = 0; i < PT; ++i) acc[i] += term(zr, zt, true, H, i) * F;
+                } else {
 #pragma unroll
-            for (int i = 0; i < PT; ++i) {
-                const T e = fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H));
-                acc[i] += e * F;
-                const int s = base + i * 64 + lane;
-                if (s < n) {
-                    const T u = e * (T)(m.wscale * (double)st.w[gb + s]);
-                    u0 += u * st.x[0][gb + s];
-                    u1 += u * st.x[1][gb + s];
-                    u2 += u * st.x[2][gb + s];
-                    u3 += u * st.x[3][gb + s];
-                    u4 += u;
+                    for (int i = 0; i < PT; ++i) acc[i] += term(zr, zt, false, H, i) * F;
+                }
+            } else {
+                T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
+#pragma unroll
+                for (int i = 0; i < PT; ++i) {
+                    const T e = term(zr, zt, fb, H, i);
+                    acc[i] += e * F;
+                    const int s = base + i * 64 + lane;
+                    if (s < n) {
+                        const T u = e * (T)(m.wscale * (double)st.w[gb + s]);
+                        u0 += u * st.x[0][gb + s];
+                        u1 += u * st.x[1][gb + s];
+                        u2 += u * st.x[2][gb + s];
+                        u3 += u * st.x[3][gb + s];
+                        u4 += u;
+                    }
+                }
+                const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
+                             r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
+                if (lane == 0) {
+                    double* o = pzeta + (pz + (fl - 1)) * 5;
+                    o[0] = r0;
+                    o[1] = r1;
+                    o[2] = r2;
+                    o[3] = r3;
+                    o[4] = r4;
                 }
             }
-            const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
-                         r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
-            if (lane == 0) {
-                double* o = pzeta + (pz + (fl - 1)) * 5;
-                o[0] = r0;
-                o[1] = r1;
-                o[2] = r2;
-                o[3] = r3;
-                o[4] = r4;
-            }
         }
-    }
     }
     const size_t KC = (size_t)m.K * m.cap;
 #pragma unroll

@@ -43,11 +43,11 @@ pphd_status fail(pphd_status s, const char* fmt, ...)
             return fail(PPHD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
     } while (0)
 
-// particles per thread of the two update passes and of resampling; the
-// measurement loop of the passes is cut into at most ZSPLIT_MAX chunks of
-// about MZ_TARGET measurements
-constexpr int PT1_F32 = 8, PT2_F32 = 8, PT1_F64 = 4, PT2_F64 = 4, PR = 1;
-constexpr int ZSPLIT_MAX = 8, MZ_TARGET = 16;
+// Tile shape of the two likelihood passes (pphd_set_tuning): particles per
+// thread (PT) and measurements per wavefront (the measurement loop is cut into
+// at most ZSPLIT_MAX chunks).  Workspace arrays are sized for the smallest PT.
+constexpr int PT_DEFAULT_F32 = 8, PT_DEFAULT_F64 = 4, PT_MIN_F32 = 4, PT_MIN_F64 = 2, PR = 1;
+constexpr int ZSPLIT_MAX = 16, MZ_DEFAULT = 16;
 
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
@@ -86,6 +86,7 @@ struct pphd_filter {
     bool births_pending = false;  // birth slots reserved by predict, drawn in update
     bool timing = false;
     int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0, tiles256 = 0;
+    int pt1 = 0, pt2 = 0, mz = MZ_DEFAULT, wtiles_max = 0;
     // device arrays (inside the workspace)
     void* X[2][4] = {};
     void* W[2] = {};
@@ -97,7 +98,8 @@ struct pphd_filter {
     void* zF = nullptr;
     double *zC = nullptr, *zdW = nullptr;
     double *p2mass = nullptr, *p2max = nullptr, *p2zeta = nullptr;
-    double *geo_rho = nullptr, *geo_phi = nullptr, *geo_lw = nullptr;
+    double *geo_rho = nullptr, *geo_phi = nullptr, *geo_phib = nullptr, *geo_lw = nullptr;
+    int pass_mode = 0;  // PASS_FRAMES / PASS_WRAP / PASS_EXACT, from the model
     void* accp = nullptr;
     double* fmass = nullptr;
     int *fLT = nullptr, *rsS = nullptr, *sel = nullptr;
@@ -152,9 +154,9 @@ size_t carve(pphd_filter* f, char* base)
     f->ncur = L.take<int>(base, K * 4);
     f->clampctr = L.take<int>(base, 4);
     f->zbuf = L.take<double>(base, Mx * 2 * 8);
-    f->p1s = L.take<double>(base, K * f->wtiles1 * Mx * 8);
-    f->p1h = L.take<int>(base, K * f->wtiles1 * Mx * 4);
-    f->p1w = L.take<double>(base, K * f->wtiles1 * 8);
+    f->p1s = L.take<double>(base, K * f->wtiles_max * Mx * 8);
+    f->p1h = L.take<int>(base, K * f->wtiles_max * Mx * 4);
+    f->p1w = L.take<double>(base, K * f->wtiles_max * 8);
     f->zH = L.take<int>(base, K * Mx * 4);
     f->zF = L.take<char>(base, K * Mx * es);
     f->zC = L.take<double>(base, K * Mx * 8);
@@ -166,9 +168,10 @@ size_t carve(pphd_filter* f, char* base)
     f->p2max = L.take<double>(base, K * f->tiles256 * 8);
     f->geo_rho = L.take<double>(base, KC * 8);
     f->geo_phi = L.take<double>(base, KC * 8);
+    f->geo_phib = L.take<double>(base, KC * 8);
     f->geo_lw = L.take<double>(base, KC * 8);
     f->accp = L.take<char>(base, (size_t)ZSPLIT_MAX * KC * es);
-    f->p2zeta = L.take<double>(base, K * f->wtiles2 * Mx * 5 * 8);
+    f->p2zeta = L.take<double>(base, K * f->wtiles_max * Mx * 5 * 8);
     f->fmass = L.take<double>(base, K * 8);
     f->fLT = L.take<int>(base, K * 4);
     f->rsS = L.take<int>(base, K * 4);
@@ -192,10 +195,11 @@ void set_geometry(pphd_filter* f, const pphd_model* m, int64_t cap, int32_t max_
     f->prec = m->precision;
     f->esz = m->precision == PPHD_FP64 ? 8 : 4;
     f->KC = (size_t)f->K * (size_t)cap;
-    const int pt1 = f->prec == PPHD_FP64 ? PT1_F64 : PT1_F32;
-    const int pt2 = f->prec == PPHD_FP64 ? PT2_F64 : PT2_F32;
-    f->wt1 = 64 * pt1;
-    f->wt2 = 64 * pt2;
+    f->pt1 = f->pt2 = f->prec == PPHD_FP64 ? PT_DEFAULT_F64 : PT_DEFAULT_F32;
+    const int ptmin = f->prec == PPHD_FP64 ? PT_MIN_F64 : PT_MIN_F32;
+    f->wtiles_max = (int)((cap + 64 * ptmin - 1) / (64 * ptmin));
+    f->wt1 = 64 * f->pt1;
+    f->wt2 = 64 * f->pt2;
     f->wtiles1 = (int)((cap + f->wt1 - 1) / f->wt1);
     f->wtiles2 = (int)((cap + f->wt2 - 1) / f->wt2);
     f->rtiles = (int)((cap + 256 * PR - 1) / (256 * PR));
@@ -255,6 +259,10 @@ void fill_devmodel(pphd_filter* f)
     d.J = m.births_per_step;
     d.cap = f->cap;
     d.M0 = std::max(1, (int)std::floor(d.Rj + 0.5));
+    // bearing frames need every wrapped pair to sit at least 160 binary orders
+    // down: (pi/2 c_t)^2 > 160 (sigma_theta below about 0.1 rad)
+    const double half = 0.5 * 3.14159265358979323846 * d.ct;
+    f->pass_mode = d.kappa > 0.0 ? (half * half > 160.0 ? PASS_FRAMES : PASS_WRAP) : PASS_EXACT;
     d.key0 = (uint32_t)f->seed;
     d.key1 = (uint32_t)(f->seed >> 32);
     d.run = f->run;
@@ -271,14 +279,14 @@ SoA<T> soa(pphd_filter* f, int b)
 
 Geo geo_of(pphd_filter* f)
 {
-    return Geo{ f->geo_rho, f->geo_phi, f->geo_lw };
+    return Geo{ f->geo_rho, f->geo_phi, f->geo_phib, f->geo_lw };
 }
 
-Split split_for(int wtiles, int M)
+Split split_for(int wtiles, int M, int mz)
 {
     Split sp;
     sp.wtiles = wtiles;
-    int z = (M + MZ_TARGET - 1) / MZ_TARGET;
+    int z = (M + mz - 1) / mz;
     sp.zsplit = z < 1 ? 1 : (z > ZSPLIT_MAX ? ZSPLIT_MAX : z);
     sp.MZ = (M + sp.zsplit - 1) / sp.zsplit;
     return sp;
@@ -329,7 +337,7 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
     SoA<T> st = soa<T>(f, f->cur);
     const Geo geo = geo_of(f);
     const int K = f->K, Mx = f->max_meas;
-    const Split s1 = split_for(f->wtiles1, M), s2 = split_for(f->wtiles2, M);
+    const Split s1 = split_for(f->wtiles1, M, f->mz), s2 = split_for(f->wtiles2, M, f->mz);
     if (f->births_pending) {
         const int Jmax = dm.J / K + (dm.J % K ? 1 : 0);
         if (Jmax > 0) {
@@ -340,22 +348,32 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
         f->births_pending = false;
     }
     dim3 g1((f->wtiles1 * s1.zsplit + 3) / 4, K), g2((f->wtiles2 * s2.zsplit + 3) / 4, K);
-    if (dm.kappa > 0.0) {
+    if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz<T, PT1, false>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
+               hipLaunchKernelGGL((k_cz<T, PT1, PASS_FRAMES>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
+                                  f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
+    } else if (f->pass_mode == PASS_WRAP) {
+        LAUNCH(f, PPHD_K_CZ,
+               hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
                                   f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
     } else {
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz<T, PT1, true>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
+               hipLaunchKernelGGL((k_cz<T, PT1, PASS_EXACT>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
                                   f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
     }
     LAUNCH(f, PPHD_K_CZ_COMBINE,
            hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
                               f->ncur, M, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH, (T*)f->zF, f->zC,
                               f->zdW, f->zflag, f->cand, f->ncand));
-    LAUNCH(f, PPHD_K_WEIGHT,
-           hipLaunchKernelGGL((k_weight<T, PT2>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M, Mx, s2,
-                              f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
+    if (f->pass_mode == PASS_FRAMES) {
+        LAUNCH(f, PPHD_K_WEIGHT,
+               hipLaunchKernelGGL((k_weight<T, PT2, true>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M,
+                                  Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
+    } else {
+        LAUNCH(f, PPHD_K_WEIGHT,
+               hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M,
+                                  Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
+    }
     LAUNCH(f, PPHD_K_WFINAL,
            hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, st.w, f->ncur,
                               (const T*)f->accp, s2.zsplit, f->tiles256, f->p2mass, f->p2max));
@@ -364,6 +382,24 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
                               f->p2max, M, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass, f->fLT,
                               f->rsS, f->sel, f->zeta));
     return PPHD_OK;
+}
+
+// the tile shapes pphd_set_tuning accepts
+pphd_status dispatch_update(pphd_filter* f, const double* dz, int M)
+{
+#define PPHD_CASE(T, A, B) \
+    if (f->pt1 == A && f->pt2 == B) return run_update<T, A, B>(f, dz, M);
+    if (f->prec == PPHD_FP64) {
+        PPHD_CASE(double, 2, 2) PPHD_CASE(double, 2, 4) PPHD_CASE(double, 2, 8)
+        PPHD_CASE(double, 4, 2) PPHD_CASE(double, 4, 4) PPHD_CASE(double, 4, 8)
+        PPHD_CASE(double, 8, 2) PPHD_CASE(double, 8, 4) PPHD_CASE(double, 8, 8)
+    } else {
+        PPHD_CASE(float, 4, 4) PPHD_CASE(float, 4, 8) PPHD_CASE(float, 4, 16)
+        PPHD_CASE(float, 8, 4) PPHD_CASE(float, 8, 8) PPHD_CASE(float, 8, 16)
+        PPHD_CASE(float, 16, 4) PPHD_CASE(float, 16, 8) PPHD_CASE(float, 16, 16)
+    }
+#undef PPHD_CASE
+    return fail(PPHD_EINVAL, "no kernel for tile shape %d/%d", f->pt1, f->pt2);
 }
 
 template <typename T>
@@ -552,8 +588,7 @@ pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on
             f->z_pending = true;
         }
     }
-    pphd_status s = f->prec == PPHD_FP64 ? run_update<double, PT1_F64, PT2_F64>(f, dz, m)
-                                         : run_update<float, PT1_F32, PT2_F32>(f, dz, m);
+    pphd_status s = dispatch_update(f, dz, m);
     if (s != PPHD_OK) return s;
     f->last_m = m;
     f->phase = PPHD_PHASE_UPDATED;
@@ -732,6 +767,24 @@ pphd_status pphd_read_local(pphd_filter* f, int32_t* sel, double* zeta)
             HIP_TRY(hipMemcpy(zeta + (size_t)j * M * 4, f->zeta + (size_t)j * f->max_meas * 4, (size_t)M * 32,
                               hipMemcpyDeviceToHost));
     }
+    return PPHD_OK;
+}
+
+pphd_status pphd_set_tuning(pphd_filter* f, int32_t pt_cz, int32_t pt_weight, int32_t meas_per_wave)
+{
+    CHECK_HANDLE(f);
+    const bool f64 = f->prec == PPHD_FP64;
+    auto ok = [&](int v) { return f64 ? (v == 2 || v == 4 || v == 8) : (v == 4 || v == 8 || v == 16); };
+    if (!ok(pt_cz) || !ok(pt_weight))
+        return fail(PPHD_EINVAL, "particles per thread must be %s", f64 ? "2, 4 or 8" : "4, 8 or 16");
+    if (meas_per_wave < 1 || meas_per_wave > 4096) return fail(PPHD_EINVAL, "meas_per_wave must be in [1, 4096]");
+    f->pt1 = pt_cz;
+    f->pt2 = pt_weight;
+    f->mz = meas_per_wave;
+    f->wt1 = 64 * f->pt1;
+    f->wt2 = 64 * f->pt2;
+    f->wtiles1 = (int)((f->cap + f->wt1 - 1) / f->wt1);
+    f->wtiles2 = (int)((f->cap + f->wt2 - 1) / f->wt2);
     return PPHD_OK;
 }
 

@@ -74,6 +74,7 @@ SIGNATURES = {
     "pphd_read_update": (_I32, [_P, _P, _P, _P, _P]),
     "pphd_read_local": (_I32, [_P, _P, _P]),
     "pphd_set_record_counts": (_I32, [_P, _I32]),
+    "pphd_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "pphd_read_resample": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
     "pphd_set_timing": (_I32, [_P, _I32]),
     "pphd_read_timing": (_I32, [_P, _P, _P]),
@@ -193,6 +194,10 @@ def pphd_read_local(h, sel_ptr, zeta_ptr):
     _chk(lib().pphd_read_local(h, sel_ptr, zeta_ptr))
 
 
+def pphd_set_tuning(h, pt_cz, pt_weight, meas_per_wave):
+    _chk(lib().pphd_set_tuning(h, int(pt_cz), int(pt_weight), int(meas_per_wave)))
+
+
 def pphd_set_record_counts(h, enable):
     _chk(lib().pphd_set_record_counts(h, int(enable)))
 
@@ -220,6 +225,18 @@ def pphd_kernel_name(c):
     return r.decode() if r else None
 
 
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
+
+
+def load_tuning():
+    """Tile shapes chosen by the autotuner (autotune.py), keyed by precision."""
+    import json
+    if os.path.exists(TUNING_PATH):
+        with open(TUNING_PATH) as fh:
+            return json.load(fh)
+    return {}
+
+
 # ---- convenience object (allocation through torch, arrays through numpy) ---
 
 class Filter:
@@ -229,7 +246,7 @@ class Filter:
     numpy arrays.  Methods map one-to-one onto the C entry points."""
 
     def __init__(self, params: dict, precision: int, cap: int, max_meas: int, seed: int, run_id: int = 0,
-                 stream=None):
+                 stream=None, apply_tuning: bool = True):
         import torch
         self.torch = torch
         self.params = params
@@ -246,6 +263,10 @@ class Filter:
         self.h = pphd_create(self.model, self.cap, self.max_meas, aligned, nbytes, int(seed), int(run_id),
                              self.stream.cuda_stream)
         self.last_m = 0
+        if apply_tuning:
+            t = load_tuning().get("fp64" if self.precision == PPHD_FP64 else "fp32")
+            if t:
+                pphd_set_tuning(self.h, t["pt_cz"], t["pt_weight"], t["meas_per_wave"])
 
     def close(self):
         if getattr(self, "h", None) is not None:
@@ -329,6 +350,9 @@ class Filter:
         zeta = np.zeros(max(self.K * M * 4, 1))
         pphd_read_local(self.h, sel.ctypes.data, zeta.ctypes.data)
         return dict(sel=sel[:self.K * M].reshape(self.K, M), zeta=zeta[:self.K * M * 4].reshape(self.K, M, 4))
+
+    def set_tuning(self, pt_cz, pt_weight, meas_per_wave):
+        pphd_set_tuning(self.h, pt_cz, pt_weight, meas_per_wave)
 
     def set_record_counts(self, enable=True):
         pphd_set_record_counts(self.h, enable)
