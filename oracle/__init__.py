@@ -5,8 +5,9 @@ the distributed computation particle PHD filter (Wang et al., arXiv 1503.03769):
 prediction and births (Eqs 5-6), the grouped update (Eqs 10-15), local
 estimation (Eqs 16-18), central fusion (section 3.1, Step 4), group-local
 resampling (Step 5) and the ring exchange (Step 6), plus the textbook single-set
-filter of section 2.2 for cross-checking.  This module only marshals numpy
-arrays into it.
+filter of section 2.2 for cross-checking, and the births of a learned
+proposal.  This module only marshals numpy arrays into it; ``oracle.mlp`` holds
+the FP64 network of the learned proposal.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library.
@@ -21,7 +22,7 @@ from . import build as _build
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-PURPOSE_INIT, PURPOSE_PREDICT, PURPOSE_BIRTH, PURPOSE_RESAMPLE, PURPOSE_EXCHANGE = 1, 2, 3, 4, 5
+PURPOSE_INIT, PURPOSE_PREDICT, PURPOSE_BIRTH, PURPOSE_RESAMPLE, PURPOSE_EXCHANGE, PURPOSE_PAIRS = 1, 2, 3, 4, 5, 6
 
 
 class OrcModel(ctypes.Structure):
@@ -85,6 +86,10 @@ def lib():
         L.orc_birth_proposal_density.argtypes = [M, D, c_int, ctypes.c_double, ctypes.c_double]
         L.orc_birth_proposal_density.restype = ctypes.c_double
         L.orc_birth_from_measurements.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
+        L.orc_mixture_proposal_density.argtypes = [M, D, c_int, D]
+        L.orc_mixture_proposal_density.restype = ctypes.c_double
+        L.orc_birth_from_mixture.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
+        L.orc_simulate_pairs.argtypes = [M, u64, u32, c_int, c_int, D, D]
         L.orc_extract.argtypes = [M, c_int, D, D, D, I, I, D]
         L.orc_fuse.argtypes = [M, c_int, I, D, D, I, I, I]
         L.orc_resample.argtypes = [M, c_int, u32, u64, u32, D, D, I, D, D, I, I, D]
@@ -181,6 +186,38 @@ def birth_from_measurements(p, st, step, seed, run, Z):
                                               Z.shape[0], _d(st.X), _d(st.W), _i(st.n)), "birth_from_measurements")
 
 
+def _table(table, M):
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.float64).reshape(-1))
+    assert t.size == M * 36, (t.size, M)
+    return t if M > 0 else np.zeros(36)
+
+
+def mixture_proposal_density(p, table, x):
+    """Proposal density (learned mixtures, birth_proposal 2) at state x."""
+    t = np.asarray(table, dtype=np.float64).reshape(-1, 4, 9)
+    M = t.shape[0]
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(4))
+    return lib().orc_mixture_proposal_density(ctypes.byref(model_struct(p)), _d(_table(t, M)), M, _d(xs))
+
+
+def birth_from_mixture(p, st, step, seed, run, table):
+    """Fills the J_j reserved birth slots of every group from the learned
+    proposal; table [M, 4, 9] as made by oracle.mlp.mixture_table."""
+    t = np.asarray(table, dtype=np.float64).reshape(-1, 4, 9)
+    M = t.shape[0]
+    _check(lib().orc_birth_from_mixture(ctypes.byref(model_struct(p)), st.cap, step, seed, run, _d(_table(t, M)),
+                                         M, _d(st.X), _d(st.W), _i(st.n)), "birth_from_mixture")
+
+
+def simulate_pairs(p, seed, run, first, n):
+    """Training pairs (z [n,2], x [n,4]) of the learned proposal."""
+    z = np.zeros((max(n, 1), 2))
+    x = np.zeros((max(n, 1), 4))
+    _check(lib().orc_simulate_pairs(ctypes.byref(model_struct(p)), seed, run, first, n, _d(z), _d(x)),
+           "simulate_pairs")
+    return z[:n], x[:n]
+
+
 def update(p, st, Z):
     """Updates st.W in place.  Returns dict with C, dW [K,M], dW0 [K], zeta_num [K,M,4], mass [K]."""
     Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).reshape(-1, 2))
@@ -263,8 +300,9 @@ class OracleFilter:
     """One run of the grouped filter, step by step, in the paper's order
     (predict, update, extract, fuse, resample, exchange)."""
 
-    def __init__(self, p, cap, seed, run):
+    def __init__(self, p, cap, seed, run, mlp_theta=None, mlp_hidden=128):
         self.p, self.seed, self.run = p, seed, run
+        self.mlp_theta, self.mlp_hidden = mlp_theta, mlp_hidden
         self.st = State(int(p["partitions"]), cap)
         init(p, self.st, seed, run)
 
@@ -274,6 +312,10 @@ class OracleFilter:
         Z = np.asarray(Z, dtype=np.float64).reshape(-1, 2)
         if int(p.get("birth_proposal", 0)) == 1:
             birth_from_measurements(p, self.st, k, self.seed, self.run, Z)
+        elif int(p.get("birth_proposal", 0)) == 2:
+            from . import mlp
+            o, _ = mlp.forward(self.mlp_theta, mlp.features(p, Z), self.mlp_hidden)
+            birth_from_mixture(p, self.st, k, self.seed, self.run, mlp.mixture_table(p, Z, o))
         n_pred = self.st.n.copy()
         upd = update(p, self.st, Z)
         ext = extract(p, Z.shape[0], upd)

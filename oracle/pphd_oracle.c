@@ -674,3 +674,118 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
     free(q);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Births from a learned proposal p_k(. | Z_k) (Eq 6, birth_proposal 2).     */
+/* Reading: as for birth_proposal 1 the proposal is a defensive mixture,     */
+/*   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p q_p(x),              */
+/* but q_p is a 4-component Gaussian mixture over the full state, with the   */
+/* parameters a network maps measurement z_p to (the table).  The velocity   */
+/* factors no longer cancel, so the weight of Eq 6 is                        */
+/*   gamma(x) / (J_j q(x)),  gamma(x) = m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2). */
+/* Draws per birth slot: uniforms (sub 0) for a position from U, normals    */
+/* (sub 1) for the two velocities, uniforms (sub 2) choosing the mixture     */
+/* term (measurement, then component), normals (sub 3) for the two position */
+/* coordinates of a Gaussian component.                                      */
+/* ------------------------------------------------------------------------ */
+
+static double orc_prior_density(const orc_model* m, const double x[4])
+{
+    double area = (m->region[1] - m->region[0]) * (m->region[3] - m->region[2]);
+    int inside = x[0] >= m->region[0] && x[0] <= m->region[1] && x[2] >= m->region[2] && x[2] <= m->region[3];
+    if (!inside) return 0.0;
+    return (1.0 / area) * orc_gauss(x[1], m->birth_sigma_v) * orc_gauss(x[3], m->birth_sigma_v);
+}
+
+double orc_mixture_proposal_density(const orc_model* m, const double* table, int M, const double x[4])
+{
+    double b = orc_prior_density(m, x);
+    if (M == 0) return b;
+    double mix = 0.0;
+    for (int p = 0; p < M; ++p) {
+        for (int c = 0; c < 4; ++c) {
+            const double* t = table + (size_t)(p * 4 + c) * 9;
+            double term = exp(t[0]);
+            for (int d = 0; d < 4; ++d) term *= orc_gauss(x[d] - t[1 + d], t[5 + d]);
+            mix += term;
+        }
+    }
+    return m->birth_alpha * b + (1.0 - m->birth_alpha) * mix / (double)M;
+}
+
+int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
+                           const double* table, int M, double* X, double* W, const int32_t* n)
+{
+    int K = m->partitions;
+    size_t KC = (size_t)K * (size_t)cap;
+    for (int j = 0; j < K; ++j) {
+        int Jj = orc_births_in_partition(m, j);
+        int ns = n[j] - Jj;
+        if (ns < 0) return -1;
+        for (int b = 0; b < Jj; ++b) {
+            uint32_t g = (uint32_t)(j * cap + ns + b);
+            uint32_t a[4], v[4], c[4], e[4];
+            orc_block(seed, g, step, ORC_BIRTH, 0, run, a);
+            orc_block(seed, g, step, ORC_BIRTH, 1, run, v);
+            orc_block(seed, g, step, ORC_BIRTH, 2, run, c);
+            orc_block(seed, g, step, ORC_BIRTH, 3, run, e);
+            double nv1, nv2, e1, e2;
+            orc_normal_pair(orc_u53(v[0], v[1]), orc_u53(v[2], v[3]), &nv1, &nv2);
+            double uc = orc_u53(c[0], c[1]), uk = orc_u53(c[2], c[3]);
+            double x[4];
+            if (M == 0 || uc <= m->birth_alpha) {
+                x[0] = m->region[0] + orc_u53(a[0], a[1]) * (m->region[1] - m->region[0]);
+                x[1] = m->birth_sigma_v * nv1;
+                x[2] = m->region[2] + orc_u53(a[2], a[3]) * (m->region[3] - m->region[2]);
+                x[3] = m->birth_sigma_v * nv2;
+            } else {
+                int p = (int)floor((uc - m->birth_alpha) / (1.0 - m->birth_alpha) * (double)M);
+                if (p > M - 1) p = M - 1;
+                /* component: the first whose cumulative weight reaches uk */
+                int comp = 3;
+                double cum = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    cum += exp(table[(size_t)(p * 4 + k) * 9]);
+                    if (uk <= cum) { comp = k; break; }
+                }
+                const double* t = table + (size_t)(p * 4 + comp) * 9;
+                orc_normal_pair(orc_u53(e[0], e[1]), orc_u53(e[2], e[3]), &e1, &e2);
+                x[0] = t[1] + t[5] * e1;
+                x[1] = t[2] + t[6] * nv1;
+                x[2] = t[3] + t[7] * e2;
+                x[3] = t[4] + t[8] * nv2;
+            }
+            for (int d = 0; d < 4; ++d) XS(X, d, g) = x[d];
+            double gam = m->birth_mass * orc_prior_density(m, x);
+            W[g] = gam > 0.0 ? gam / ((double)Jj * orc_mixture_proposal_density(m, table, M, x)) : 0.0;
+        }
+    }
+    return 0;
+}
+
+/* Training pairs for the learned proposal: state from the birth density,
+ * measurement from the range-bearing model of section 4 (bearing wrapped to
+ * [-pi, pi)). */
+int orc_simulate_pairs(const orc_model* m, uint64_t seed, uint32_t run, int first, int n, double* z, double* x)
+{
+    for (int i = 0; i < n; ++i) {
+        uint32_t idx = (uint32_t)(first + i);
+        uint32_t a[4], v[4], e[4];
+        orc_block(seed, idx, 0, ORC_PAIRS, 0, run, a);
+        orc_block(seed, idx, 0, ORC_PAIRS, 1, run, v);
+        orc_block(seed, idx, 0, ORC_PAIRS, 2, run, e);
+        double px = m->region[0] + orc_u53(a[0], a[1]) * (m->region[1] - m->region[0]);
+        double py = m->region[2] + orc_u53(a[2], a[3]) * (m->region[3] - m->region[2]);
+        double n1, n2, e1, e2;
+        orc_normal_pair(orc_u53(v[0], v[1]), orc_u53(v[2], v[3]), &n1, &n2);
+        orc_normal_pair(orc_u53(e[0], e[1]), orc_u53(e[2], e[3]), &e1, &e2);
+        double dx = px - m->sensor_x, dy = py - m->sensor_y;
+        x[4 * i + 0] = px;
+        x[4 * i + 1] = m->birth_sigma_v * n1;
+        x[4 * i + 2] = py;
+        x[4 * i + 3] = m->birth_sigma_v * n2;
+        z[2 * i + 0] = sqrt(dx * dx + dy * dy) + m->sigma_r * e1;
+        z[2 * i + 1] = orc_wrap(atan2(dy, dx) + m->sigma_theta * e2);
+    }
+    return 0;
+}

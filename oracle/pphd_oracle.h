@@ -36,12 +36,13 @@ typedef struct {
     double init_mass;
     double particles_per_target;                    /* R over all groups */
     double exchange_fraction;                       /* rho_x */
-    int32_t birth_proposal;   /* 0: births from gamma/m_b; 1: measurement-driven mixture */
+    int32_t birth_proposal;   /* 0: births from gamma/m_b; 1: measurement-driven mixture;
+                                 2: learned per-measurement Gaussian mixtures */
     int32_t reserved2;
     double birth_alpha;       /* weight of gamma/m_b in the mixture (proposal 1) */
 } orc_model;
 
-enum { ORC_INIT = 1, ORC_PREDICT = 2, ORC_BIRTH = 3, ORC_RESAMPLE = 4, ORC_EXCHANGE = 5 };
+enum { ORC_INIT = 1, ORC_PREDICT = 2, ORC_BIRTH = 3, ORC_RESAMPLE = 4, ORC_EXCHANGE = 5, ORC_PAIRS = 6 };
 
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_u53(uint32_t a, uint32_t b);
@@ -57,6 +58,17 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
 double orc_birth_proposal_density(const orc_model* m, const double* Z, int M, double x, double y);
 int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                                 const double* Z, int M, double* X, double* W, const int32_t* n);
+/* Learned proposal (birth_proposal 2).  table holds, for each measurement p
+ * and mixture component c, 9 doubles at table[(p*4 + c)*9]: log pi_c (the
+ * normalised log weight), the mean (4, state units) and the standard
+ * deviations (4, state units) of a diagonal Gaussian over [x, vx, y, vy]. */
+double orc_mixture_proposal_density(const orc_model* m, const double* table, int M, const double x[4]);
+int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
+                           const double* table, int M, double* X, double* W, const int32_t* n);
+/* Training pairs (z, x): x drawn from gamma/m_b, z = (range, bearing) drawn
+ * from the sensor model given x.  Pair i (i = first .. first+n-1) goes to
+ * z[2*(i-first)], x[4*(i-first)]. */
+int orc_simulate_pairs(const orc_model* m, uint64_t seed, uint32_t run, int first, int n, double* z, double* x);
 int orc_update(const orc_model* m, int cap, const double* Z, int M,
                const double* X, double* W, const int32_t* n,
                double* C, double* dW, double* dW0, double* zeta_num, double* mass);
