@@ -79,9 +79,11 @@ typedef struct {
     double exchange_fraction;                           /* rho_x in [0, 0.5)             */
     int32_t birth_proposal;   /* 0: births drawn from gamma/m_b in pphd_predict;          */
                               /* 1: births drawn in pphd_update from the measurement-     */
-                              /*    driven mixture of Eq 6's p_k(.|Z_k) (see below)       */
+                              /*    driven mixture of Eq 6's p_k(.|Z_k) (see below);      */
+                              /* 2: births drawn in pphd_update from the learned          */
+                              /*    per-measurement mixtures (pphd_mlp.h)                 */
     int32_t reserved;         /* must be 0                                                */
-    double birth_alpha;       /* proposal 1: weight of gamma/m_b in the mixture, in [0,1] */
+    double birth_alpha;       /* proposals 1, 2: weight of gamma/m_b in the mixture, [0,1] */
 } pphd_model;
 
 /* One fused (global) estimate: the mean of the local estimates that carry the
@@ -125,7 +127,8 @@ pphd_status pphd_init(pphd_filter* f);
  *   q(x|Z_k) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p q_p(x),
  * q_p placing the particle at range N(r_p, sigma_r^2), bearing
  * N(theta_p, sigma_theta^2) with velocity N(0, sigma_v^2 I), and weight
- * gamma(x) / (J_j q(x)) (Eq 6).  step: the time index k >= 1.
+ * gamma(x) / (J_j q(x)) (Eq 6); birth_proposal 2 reserves them the same way for
+ * the learned mixtures of pphd_mlp.h.  step: the time index k >= 1.
  * Phase READY or RESAMPLED -> PREDICTED. */
 pphd_status pphd_predict(pphd_filter* f, uint32_t step);
 
@@ -226,8 +229,9 @@ enum {
     PPHD_K_PREDICT = 0, PPHD_K_CZ = 1, PPHD_K_CZ_COMBINE = 2, PPHD_K_WEIGHT = 3,
     PPHD_K_FINALIZE = 4, PPHD_K_FUSE = 5, PPHD_K_RS_TILES = 6, PPHD_K_RS_EXPAND = 7,
     PPHD_K_XCHG_GATHER = 8, PPHD_K_XCHG_SCATTER = 9, PPHD_K_INIT = 10, PPHD_K_WMAX = 11,
-    PPHD_K_GEOM = 12, PPHD_K_WFINAL = 13, PPHD_K_BIRTH = 14,
-    PPHD_K_COUNT = 15
+    PPHD_K_GEOM = 12, PPHD_K_WFINAL = 13, PPHD_K_BIRTH = 14, PPHD_K_MLP_INFER = 15,
+    PPHD_K_BIRTH_MIX = 16,
+    PPHD_K_COUNT = 17
 };
 
 /* Enables (1) or disables (0) per-launch HIP-event timing on the filter's

@@ -6,9 +6,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpphd.so")
-SOURCES = [os.path.join(CSRC, "pphd.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "kernels.h"), os.path.join(CSRC, "philox_dev.h"),
-                  os.path.join(ROOT, "include", "pphd.h")]
+SOURCES = [os.path.join(CSRC, "pphd.hip"), os.path.join(CSRC, "mlp.hip")]
+DEPS = SOURCES + [os.path.join(CSRC, h) for h in ("kernels.h", "philox_dev.h", "mlp_kernels.h", "mlp_internal.h")] + \
+    [os.path.join(ROOT, "include", h) for h in ("pphd.h", "pphd_mlp.h")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

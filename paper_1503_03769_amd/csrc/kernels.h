@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mlp_internal.h"
 #include "philox_dev.h"
 
 namespace pphd {
@@ -322,6 +323,89 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, SoA<T> st, Geo g
     st.x[3][g] = (T)(m.sigma_v * n2);
     st.w[g] = tw;
     store_geometry(m, geo, g, (double)tx, (double)ty, (double)tw);
+}
+
+// ---------------------------------------------------------------------------
+// Births from the learned proposal of Eq 6 (birth_proposal 2):
+//   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p sum_c pi_pc N(x; mu_pc, diag sigma_pc^2),
+// the table holding each measurement's mixture (layout in mlp_internal.h).
+// Draws per slot: position uniforms (sub 0), velocity normals (sub 1), the
+// choice of measurement and component (sub 2) and the two position normals of
+// a Gaussian component (sub 3).  Weight gamma(x) / (J_j q(x)), gamma(x) =
+// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).  grid (ceil(J_max/256), K).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double normal_pdf(double d, double sigma)
+{
+    const double e = d / sigma;
+    return exp(-0.5 * e * e) / (2.5066282746310002 * sigma);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_birth_mix(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
+                                                   const double* __restrict__ tab, int M, uint32_t step)
+{
+    const int j = blockIdx.y;
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int Jj = births_in(m, j);
+    if (b >= Jj) return;
+    const size_t g = (size_t)j * m.cap + nsurv[j] + b;
+    const Block4 a = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 0, m.run);
+    const Block4 v = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 1, m.run);
+    const Block4 c = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 2, m.run);
+    double nv1, nv2;
+    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), nv1, nv2);
+    const double uc = uniform53(c.a, c.b), uk = uniform53(c.c, c.d);
+    double x[4];
+    if (M == 0 || uc <= m.alpha) {
+        x[0] = m.reg0 + uniform53(a.a, a.b) * (m.reg1 - m.reg0);
+        x[1] = m.sigma_v * nv1;
+        x[2] = m.reg2 + uniform53(a.c, a.d) * (m.reg3 - m.reg2);
+        x[3] = m.sigma_v * nv2;
+    } else {
+        int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
+        p = p > M - 1 ? M - 1 : p;
+        int comp = 3;
+        for (int k = 0; k < 4; ++k) {
+            if (uk <= tab[(size_t)(p * 4 + k) * MIX_TAB + 1]) {
+                comp = k;
+                break;
+            }
+        }
+        const double* t = tab + (size_t)(p * 4 + comp) * MIX_TAB;
+        const Block4 e = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 3, m.run);
+        double e1, e2;
+        normal_pair(uniform53(e.a, e.b), uniform53(e.c, e.d), e1, e2);
+        x[0] = t[4] + t[8] * e1;
+        x[1] = t[5] + t[9] * nv1;
+        x[2] = t[6] + t[10] * e2;
+        x[3] = t[7] + t[11] * nv2;
+    }
+    const bool inside = x[0] >= m.reg0 && x[0] <= m.reg1 && x[2] >= m.reg2 && x[2] <= m.reg3;
+    const double bd = inside ? m.inv_area * normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v) : 0.0;
+    double w = 0.0;
+    if (bd > 0.0) {
+        double q = bd;
+        if (M > 0) {
+            double mix = 0.0;
+            for (int p = 0; p < M * 4; ++p) {
+                const double* t = tab + (size_t)p * MIX_TAB;
+                const double d0 = (x[0] - t[4]) * t[12], d1 = (x[1] - t[5]) * t[13];
+                const double d2 = (x[2] - t[6]) * t[14], d3 = (x[3] - t[7]) * t[15];
+                mix += neg_exp(0.5 * (d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3) - t[2], T(0));
+            }
+            q = m.alpha * bd + (1.0 - m.alpha) * mix / (double)M;
+        }
+        w = m.birth_mass * bd / ((double)Jj * q);
+    }
+    T tx[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        tx[d] = (T)x[d];
+        st.x[d][g] = tx[d];
+    }
+    const T tw = (T)w;
+    st.w[g] = tw;
+    store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
 }
 
 // scaled squared residual q(z, x) + c

@@ -16,7 +16,9 @@
 #include <vector>
 
 #include "../../include/pphd.h"
+#include "../../include/pphd_mlp.h"
 #include "kernels.h"
+#include "mlp_internal.h"
 
 using namespace pphd;
 
@@ -52,7 +54,7 @@ constexpr int ZSPLIT_MAX = 16, MZ_DEFAULT = 16;
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
     "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
-    "k_geom", "k_wfinal", "k_birth_meas",
+    "k_geom", "k_wfinal", "k_birth_meas", "k_mlp_infer", "k_birth_mix",
 };
 
 struct Layout {
@@ -84,6 +86,12 @@ struct pphd_filter {
     uint32_t last_step = 0;
     bool record = false;
     bool births_pending = false;  // birth slots reserved by predict, drawn in update
+    // learned proposal (birth_proposal 2)
+    pphd_mlp* mlp = nullptr;
+    bool mix_preset = false;  // pphd_set_birth_mixture outputs wait for the next update
+    int mix_preset_m = 0;
+    double* mix_tab = nullptr;
+    float* mix_raw = nullptr;
     bool timing = false;
     int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0, tiles256 = 0;
     int pt1 = 0, pt2 = 0, mz = MZ_DEFAULT, wtiles_max = 0;
@@ -135,8 +143,8 @@ bool model_ok(const pphd_model* m, std::string& why)
     if (!(m->particles_per_target > 0)) { why = "particles_per_target must be > 0"; return false; }
     if (!(m->exchange_fraction >= 0 && m->exchange_fraction < 0.5)) { why = "exchange_fraction must be in [0, 0.5)"; return false; }
     if (!(m->birth_mass >= 0) || !(m->init_mass >= 0)) { why = "masses must be >= 0"; return false; }
-    if (m->birth_proposal != 0 && m->birth_proposal != 1) { why = "birth_proposal must be 0 or 1"; return false; }
-    if (m->birth_proposal == 1 && !(m->birth_alpha >= 0 && m->birth_alpha <= 1)) { why = "birth_alpha must be in [0,1]"; return false; }
+    if (m->birth_proposal < 0 || m->birth_proposal > 2) { why = "birth_proposal must be 0, 1 or 2"; return false; }
+    if (m->birth_proposal != 0 && !(m->birth_alpha >= 0 && m->birth_alpha <= 1)) { why = "birth_alpha must be in [0,1]"; return false; }
     if (!(m->region[1] > m->region[0]) || !(m->region[3] > m->region[2])) { why = "empty surveillance region"; return false; }
     return true;
 }
@@ -183,6 +191,10 @@ size_t carve(pphd_filter* f, char* base)
     f->massq = L.take<double>(base, K * 8);
     f->counts = L.take<int>(base, KC * 4);
     f->stage = L.take<char>(base, K * (size_t)f->Lmax * 5 * es);
+    if (f->model.birth_proposal == 2) {
+        f->mix_tab = L.take<double>(base, Mx * 4 * MIX_TAB * 8);
+        f->mix_raw = L.take<float>(base, Mx * PPHD_MLP_OUTPUTS * 4);
+    }
     return (L.off + 255) & ~(size_t)255;
 }
 
@@ -340,11 +352,23 @@ pphd_status run_update(pphd_filter* f, const double* dz, int M)
     const Split s1 = split_for(f->wtiles1, M, f->mz), s2 = split_for(f->wtiles2, M, f->mz);
     if (f->births_pending) {
         const int Jmax = dm.J / K + (dm.J % K ? 1 : 0);
-        if (Jmax > 0) {
+        if (Jmax > 0 && dm.proposal == 1) {
             LAUNCH(f, PPHD_K_BIRTH,
                    hipLaunchKernelGGL((k_birth_meas<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm, st,
                                       geo, f->nsurv, dz, M, f->last_step));
+        } else if (Jmax > 0 && dm.proposal == 2) {
+            // mixture table of this step's measurements: from the outputs the
+            // caller set, else from the attached network
+            pphd_status ms = PPHD_OK;
+            LAUNCH(f, PPHD_K_MLP_INFER,
+                   ms = f->mix_preset ? mlp_head_table(f->model, f->stream, dz, f->mix_raw, M, f->mix_tab)
+                                      : mlp_mixture_table(f->mlp, f->stream, dz, M, f->mix_tab));
+            if (ms != PPHD_OK) return ms;
+            LAUNCH(f, PPHD_K_BIRTH_MIX,
+                   hipLaunchKernelGGL((k_birth_mix<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm, st,
+                                      geo, f->nsurv, f->mix_tab, M, f->last_step));
         }
+        f->mix_preset = false;
         f->births_pending = false;
     }
     dim3 g1((f->wtiles1 * s1.zsplit + 3) / 4, K), g2((f->wtiles2 * s2.zsplit + 3) / 4, K);
@@ -564,7 +588,7 @@ pphd_status pphd_predict(pphd_filter* f, uint32_t step)
     pphd_status s = f->prec == PPHD_FP64 ? run_predict<double>(f, step) : run_predict<float>(f, step);
     if (s != PPHD_OK) return s;
     f->last_step = step;
-    f->births_pending = f->model.birth_proposal == 1;
+    f->births_pending = f->model.birth_proposal != 0;
     f->phase = PPHD_PHASE_PREDICTED;
     return PPHD_OK;
 }
@@ -575,6 +599,12 @@ pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on
     if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "update needs phase PREDICTED (have %d)", f->phase);
     if (m < 0 || m > f->max_meas) return fail(PPHD_EINVAL, "m = %d outside [0, %d]", m, f->max_meas);
     if (m > 0 && !z) return fail(PPHD_EINVAL, "z is NULL");
+    if (f->births_pending && f->model.birth_proposal == 2 && f->dm.J > 0) {
+        if (f->mix_preset && f->mix_preset_m != m)
+            return fail(PPHD_EINVAL, "set_birth_mixture was given %d measurements, update %d", f->mix_preset_m, m);
+        if (!f->mix_preset && !f->mlp)
+            return fail(PPHD_ESTATE, "birth_proposal 2 needs pphd_attach_mlp or pphd_set_birth_mixture");
+    }
     const double* dz = f->zbuf;
     if (m > 0) {
         if (z_on_device) {
@@ -845,6 +875,43 @@ pphd_status pphd_read_timing(pphd_filter* f, double* ms, int64_t* launches)
         if (ms) ms[i] = f->acc_ms[i];
         if (launches) launches[i] = f->acc_n[i];
     }
+    return PPHD_OK;
+}
+
+}  // extern "C"
+
+namespace pphd {
+pphd_status set_error(pphd_status s, const char* msg)
+{
+    g_err = msg;
+    return s;
+}
+}  // namespace pphd
+
+extern "C" {
+
+pphd_status pphd_attach_mlp(pphd_filter* f, pphd_mlp* h)
+{
+    CHECK_HANDLE(f);
+    if (h && f->model.birth_proposal != 2) return fail(PPHD_EINVAL, "the filter's birth_proposal is not 2");
+    f->mlp = h;
+    return PPHD_OK;
+}
+
+pphd_status pphd_set_birth_mixture(pphd_filter* f, const float* raw, int32_t m, int32_t on_device)
+{
+    CHECK_HANDLE(f);
+    if (f->model.birth_proposal != 2) return fail(PPHD_EINVAL, "the filter's birth_proposal is not 2");
+    if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "set_birth_mixture needs phase PREDICTED (have %d)", f->phase);
+    if (m < 0 || m > f->max_meas) return fail(PPHD_EINVAL, "m = %d outside [0, %d]", m, f->max_meas);
+    if (m > 0 && !raw) return fail(PPHD_EINVAL, "raw is NULL");
+    if (m > 0) {
+        HIP_TRY(hipMemcpyAsync(f->mix_raw, raw, (size_t)m * PPHD_MLP_OUTPUTS * 4,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, f->stream));
+        if (!on_device) HIP_TRY(hipStreamSynchronize(f->stream));
+    }
+    f->mix_preset = true;
+    f->mix_preset_m = m;
     return PPHD_OK;
 }
 

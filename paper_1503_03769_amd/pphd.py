@@ -1,4 +1,5 @@
-"""Python binding of libpphd (include/pphd.h): argument marshalling only.
+"""Python binding of libpphd (include/pphd.h, include/pphd_mlp.h): argument
+marshalling only.
 
 Every function here has the name of the C entry point it calls and does no
 computation of its own; each stage of the filter runs in the library's HIP
@@ -19,7 +20,9 @@ PPHD_OK, PPHD_EINVAL, PPHD_ENOMEM, PPHD_ECAPACITY, PPHD_EDEVICE, PPHD_ESTATE = 0
 PPHD_FP64, PPHD_FP32 = 0, 1
 PHASE_READY, PHASE_PREDICTED, PHASE_UPDATED, PHASE_RESAMPLED = 1, 2, 3, 4
 KERNEL_CLASSES = ["predict", "cz", "cz_combine", "weight", "finalize", "fuse", "rs_tiles", "rs_expand",
-                  "xchg_gather", "xchg_scatter", "init", "wmax", "geom", "wfinal", "birth_meas"]
+                  "xchg_gather", "xchg_scatter", "init", "wmax", "geom", "wfinal", "birth_meas",
+                  "mlp_infer", "birth_mix"]
+MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 128, 36, 38052
 K_COUNT = len(KERNEL_CLASSES)
 
 
@@ -45,6 +48,11 @@ class pphd_model(ctypes.Structure):
         ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
         ("birth_proposal", ctypes.c_int32), ("reserved", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
     ]
+
+
+class pphd_mlp_config(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("dataset", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
 class pphd_estimate(ctypes.Structure):
@@ -79,6 +87,20 @@ SIGNATURES = {
     "pphd_set_timing": (_I32, [_P, _I32]),
     "pphd_read_timing": (_I32, [_P, _P, _P]),
     "pphd_kernel_name": (ctypes.c_char_p, [_I32]),
+    "pphd_mlp_workspace_size": (_I32, [ctypes.POINTER(pphd_mlp_config), ctypes.POINTER(_SZ)]),
+    "pphd_mlp_create": (_I32, [_MP, ctypes.POINTER(pphd_mlp_config), _P, _SZ, _U64, _P, ctypes.POINTER(_P)]),
+    "pphd_mlp_init_params": (_I32, [_P, _U32]),
+    "pphd_mlp_set_params": (_I32, [_P, _P, _I32]),
+    "pphd_mlp_get_params": (_I32, [_P, _P, _I32]),
+    "pphd_mlp_simulate": (_I32, [_P, _U32]),
+    "pphd_mlp_read_dataset": (_I32, [_P, _I32, _I32, _P, _P]),
+    "pphd_mlp_loss_grad": (_I32, [_P, _P, _P, _I32, _I32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "pphd_mlp_train": (_I32, [_P, _I32, ctypes.c_double, _P]),
+    "pphd_mlp_forward": (_I32, [_P, _P, _I32, _I32, _P]),
+    "pphd_mlp_steps": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "pphd_mlp_destroy": (_I32, [_P]),
+    "pphd_attach_mlp": (_I32, [_P, _P]),
+    "pphd_set_birth_mixture": (_I32, [_P, _P, _I32, _I32]),
 }
 
 
@@ -214,6 +236,71 @@ def pphd_set_timing(h, enable):
 
 def pphd_read_timing(h, ms_ptr, launches_ptr):
     _chk(lib().pphd_read_timing(h, ms_ptr, launches_ptr))
+
+
+def pphd_mlp_workspace_size(cfg):
+    n = _SZ(0)
+    _chk(lib().pphd_mlp_workspace_size(ctypes.byref(cfg), ctypes.byref(n)))
+    return int(n.value)
+
+
+def pphd_mlp_create(model, cfg, workspace_ptr, workspace_bytes, seed, stream_ptr):
+    h = _P()
+    _chk(lib().pphd_mlp_create(ctypes.byref(model), ctypes.byref(cfg), workspace_ptr, workspace_bytes, seed,
+                               stream_ptr, ctypes.byref(h)))
+    return h
+
+
+def pphd_mlp_init_params(h, init_id):
+    _chk(lib().pphd_mlp_init_params(h, int(init_id)))
+
+
+def pphd_mlp_set_params(h, params_ptr, on_device):
+    _chk(lib().pphd_mlp_set_params(h, params_ptr, int(on_device)))
+
+
+def pphd_mlp_get_params(h, params_ptr, on_device):
+    _chk(lib().pphd_mlp_get_params(h, params_ptr, int(on_device)))
+
+
+def pphd_mlp_simulate(h, run):
+    _chk(lib().pphd_mlp_simulate(h, int(run)))
+
+
+def pphd_mlp_read_dataset(h, first, n, z_ptr, x_ptr):
+    _chk(lib().pphd_mlp_read_dataset(h, int(first), int(n), z_ptr, x_ptr))
+
+
+def pphd_mlp_loss_grad(h, z_ptr, x_ptr, n, on_device, grad_ptr):
+    loss = ctypes.c_double(0.0)
+    _chk(lib().pphd_mlp_loss_grad(h, z_ptr, x_ptr, int(n), int(on_device), grad_ptr, ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def pphd_mlp_train(h, steps, lr, loss_ptr):
+    _chk(lib().pphd_mlp_train(h, int(steps), float(lr), loss_ptr))
+
+
+def pphd_mlp_forward(h, z_ptr, n, on_device, out_ptr):
+    _chk(lib().pphd_mlp_forward(h, z_ptr, int(n), int(on_device), out_ptr))
+
+
+def pphd_mlp_steps(h):
+    n = _I64(0)
+    _chk(lib().pphd_mlp_steps(h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def pphd_mlp_destroy(h):
+    _chk(lib().pphd_mlp_destroy(h))
+
+
+def pphd_attach_mlp(f, h):
+    _chk(lib().pphd_attach_mlp(f, h))
+
+
+def pphd_set_birth_mixture(f, raw_ptr, m, on_device):
+    _chk(lib().pphd_set_birth_mixture(f, raw_ptr, int(m), int(on_device)))
 
 
 def pphd_last_error():
@@ -354,6 +441,17 @@ class Filter:
     def set_tuning(self, pt_cz, pt_weight, meas_per_wave):
         pphd_set_tuning(self.h, pt_cz, pt_weight, meas_per_wave)
 
+    def attach_mlp(self, mlp):
+        """Network whose mixtures the births of birth_proposal 2 draw from."""
+        pphd_attach_mlp(self.h, mlp.h if mlp is not None else None)
+        self.mlp = mlp  # keeps the network alive while the filter uses it
+
+    def set_birth_mixture(self, raw):
+        """Network outputs float32 [m, 36] (host) for the next update."""
+        raw = np.ascontiguousarray(raw, dtype=np.float32).reshape(-1, MLP_OUTPUTS)
+        m = raw.shape[0]
+        pphd_set_birth_mixture(self.h, raw.ctypes.data if m > 0 else None, m, 0)
+
     def set_record_counts(self, enable=True):
         pphd_set_record_counts(self.h, enable)
 
@@ -371,3 +469,72 @@ class Filter:
         n = np.zeros(K_COUNT, dtype=np.int64)
         pphd_read_timing(self.h, ms.ctypes.data, n.ctypes.data)
         return {KERNEL_CLASSES[i]: (float(ms[i]), int(n[i])) for i in range(K_COUNT)}
+
+
+class Mlp:
+    """The learned birth proposal's network (include/pphd_mlp.h) on the current
+    torch device and stream; host arrays are numpy."""
+
+    def __init__(self, params: dict, batch=4096, dataset=1 << 20, seed=0, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, stream=None):
+        import torch
+        self.cfg = pphd_mlp_config(int(batch), int(dataset), float(lr), float(beta1), float(beta2), float(eps))
+        nbytes = pphd_mlp_workspace_size(self.cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = pphd_mlp_create(model_struct(params, PPHD_FP32), self.cfg, aligned, nbytes, int(seed),
+                                 self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            pphd_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_params(self, init_id=0):
+        pphd_mlp_init_params(self.h, init_id)
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32).reshape(MLP_PARAMS)
+        pphd_mlp_set_params(self.h, theta.ctypes.data, 0)
+
+    def get_params(self):
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        pphd_mlp_get_params(self.h, out.ctypes.data, 0)
+        return out
+
+    def simulate(self, run=0):
+        pphd_mlp_simulate(self.h, run)
+
+    def read_dataset(self, first, n):
+        z = np.zeros((max(n, 1), 2), dtype=np.float32)
+        x = np.zeros((max(n, 1), 4), dtype=np.float32)
+        pphd_mlp_read_dataset(self.h, first, n, z.ctypes.data, x.ctypes.data)
+        return z[:n], x[:n]
+
+    def loss_grad(self, z, x):
+        z = np.ascontiguousarray(z, dtype=np.float32).reshape(-1, 2)
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 4)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = pphd_mlp_loss_grad(self.h, z.ctypes.data, x.ctypes.data, z.shape[0], 0, g.ctypes.data)
+        return loss, g
+
+    def train(self, steps, lr=0.0, record_loss=True):
+        loss = np.zeros(max(int(steps), 1), dtype=np.float32) if record_loss else None
+        pphd_mlp_train(self.h, steps, lr, loss.ctypes.data if record_loss else None)
+        return loss[:steps] if record_loss else None
+
+    def forward(self, z):
+        z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, 2)
+        out = np.zeros((max(z.shape[0], 1), MLP_OUTPUTS), dtype=np.float32)
+        pphd_mlp_forward(self.h, z.ctypes.data, z.shape[0], 0, out.ctypes.data)
+        return out[:z.shape[0]]
+
+    def steps(self):
+        return pphd_mlp_steps(self.h)

@@ -48,6 +48,13 @@ WORKLOADS = {
         model=dict(BASE_MODEL, clutter_rate=50.0, particles_per_target=1.0e5,
                    births_per_step=50000, partitions=64, birth_proposal=1, birth_alpha=0.1),
         n_targets=10, steps=100, cap=32768, precision="fp32", max_meas=512, config_index=2),
+    # 10 targets, 16 groups, 2e5 particles at 10 targets (R = 1.98e4 per
+    # target, J = 2000 births, 1% of the budget): the learned birth proposal
+    # against uniform birth at the same particle budget.
+    "learned_fp32_10tgt": dict(
+        model=dict(BASE_MODEL, clutter_rate=50.0, particles_per_target=1.98e4,
+                   births_per_step=2000, partitions=16, birth_proposal=2, birth_alpha=0.1),
+        n_targets=10, steps=100, cap=32768, precision="fp32", max_meas=512, config_index=3),
 }
 
 
@@ -118,6 +125,45 @@ def make_scenario(model: dict, n_targets: int, steps: int, seed: int, start_box=
         truth.append(tk)
         Z.append(np.ascontiguousarray(zk))
     return truth, Z
+
+
+def bf16_representable(a):
+    """float32 values rounded to the nearest BF16 value (ties to even)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def random_mlp_params(seed, scale=1.0, hidden=128):
+    """Random network parameters in the flat layout of the learned proposal
+    (uniform He-style magnitudes; output log-std biases offset to about
+    exp(-3) so the mixtures are moderately narrow), BF16-representable."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_in, n_out in ((2, hidden), (hidden, hidden), (hidden, hidden), (hidden, 36)):
+        a = scale * math.sqrt(6.0 / fan_in) * (0.2 if n_out == 36 else 1.0)
+        parts.append(rng.uniform(-a, a, size=n_out * fan_in))
+        b = rng.normal(0.0, 0.05, size=n_out)
+        if n_out == 36:
+            b[5::9] -= 3.0
+            b[7::9] -= 3.0
+        parts.append(b)
+    return bf16_representable(np.concatenate(parts))
+
+
+def random_mixture_outputs(M, seed):
+    """Random network outputs [M, 36] (float32): logits N(0, 1), mean offsets
+    N(0, 0.02^2) (normalised units), position log-stds N(-4.5, 0.3^2),
+    velocity log-stds N(0, 0.3^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    o = np.zeros((M, 4, 9))
+    o[:, :, 0] = rng.normal(0, 1, (M, 4))
+    o[:, :, 1:5] = rng.normal(0, 0.02, (M, 4, 4))
+    o[:, :, 5] = rng.normal(-4.5, 0.3, (M, 4))
+    o[:, :, 7] = rng.normal(-4.5, 0.3, (M, 4))
+    o[:, :, 6] = rng.normal(0, 0.3, (M, 4))
+    o[:, :, 8] = rng.normal(0, 0.3, (M, 4))
+    return o.reshape(M, 36).astype(np.float32)
 
 
 def random_particles(K, cap, counts, seed, truth=None, spread=30.0, dtype=np.float64):

@@ -7,13 +7,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pphd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pphd_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(pphd_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_paper_stages():
@@ -54,3 +57,22 @@ def test_workspace_size_and_argument_errors():
     with pytest.raises(pphd.PphdError):
         pphd.pphd_workspace_size(m, w["cap"], 0)
     assert pphd.pphd_kernel_name(3) == "k_weight"
+    assert [pphd.pphd_kernel_name(i) for i in range(pphd.K_COUNT)][-2:] == ["k_mlp_infer", "k_birth_mix"]
+    assert pphd.pphd_kernel_name(pphd.K_COUNT) is None
+
+
+def test_learned_proposal_declarations_and_config_errors():
+    from paper_1503_03769_amd import pphd
+    names = _declared()
+    for n in ("pphd_mlp_create", "pphd_mlp_train", "pphd_mlp_loss_grad", "pphd_mlp_forward",
+              "pphd_attach_mlp", "pphd_set_birth_mixture"):
+        assert n in names
+    ok = pphd.pphd_mlp_config(4096, 1 << 20, 1e-3, 0.9, 0.999, 1e-8)
+    n = pphd.pphd_mlp_workspace_size(ok)
+    # the dataset (6 floats per pair) and one gradient partial per 64-pair tile
+    assert n >= (1 << 20) * 24 + 64 * 38052 * 4
+    for bad in (pphd.pphd_mlp_config(100, 1 << 20, 1e-3, 0.9, 0.999, 1e-8),
+                pphd.pphd_mlp_config(4096, 5000, 1e-3, 0.9, 0.999, 1e-8),
+                pphd.pphd_mlp_config(4096, 8192, -1.0, 0.9, 0.999, 1e-8)):
+        with pytest.raises(pphd.PphdError):
+            pphd.pphd_mlp_workspace_size(bad)
