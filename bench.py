@@ -87,8 +87,22 @@ def main():
     est_dev = torch.zeros((total + 1, cap_est * 40), dtype=torch.uint8, device="cuda")
     nest_dev = torch.zeros(total + 1, dtype=torch.int32, device="cuda")
 
+    # learned birth proposal: train the network first (outside the timed region)
+    net, mlp_info = None, None
+    if int(p.get("birth_proposal", 0)) == 2:
+        from paper_1503_03769_amd.proposal import train_proposal
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net, losses = train_proposal(p, seed=1)
+        torch.cuda.synchronize()
+        mlp_info = {"train_s": time.perf_counter() - t0, "train_steps": int(len(losses)),
+                    "final_loss": float(np.mean(losses[-50:])), "pairs": 1 << 20}
+
     def make():
-        return pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, args.run)
+        f = pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, args.run)
+        if net is not None:
+            f.attach_mlp(net)
+        return f
 
     def step(f, k):
         f.predict(k)
@@ -190,16 +204,25 @@ def main():
             "avg_launch_us": avg_s * 1e6,
             "work_per_launch": f"{pairs_per_launch:.4g} pairs x {SLOTS_PER_PAIR_EVAL} issue slots",
         }
+    if mlp_info is not None:
+        # the same run with births from the birth density itself, same budget
+        from paper_1503_03769_amd.runs import run_ospa
+        d, _ = run_ospa(dict(p, birth_proposal=0), prec, w["cap"], w["max_meas"], truth, Z, seed, args.run,
+                        steps=total)
+        mlp_info["ospa_mean_uniform_birth"] = float(np.mean(d[args.warmup:total]))
+        line["learned_proposal"] = mlp_info
     if args.cpu_seconds > 0:
-        line["cpu_baseline"] = cpu_baseline(p, w, truth, Z, seed, args.run, args.cpu_seconds)
+        # with the learned proposal the oracle runs the trained network in FP64
+        theta = net.get_params().astype(np.float64) if mlp_info is not None else None
+        line["cpu_baseline"] = cpu_baseline(p, w, truth, Z, seed, args.run, args.cpu_seconds, theta)
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(p, w, truth, Z, seed, run, budget_s):
+def cpu_baseline(p, w, truth, Z, seed, run, budget_s, mlp_theta=None):
     """The FP64 oracle, single thread, on the same workload from t = 0 for as
     many steps as fit in about budget_s seconds."""
     import oracle as orc
-    o = orc.OracleFilter(p, w["cap"], seed, run)
+    o = orc.OracleFilter(p, w["cap"], seed, run, mlp_theta=mlp_theta)
     pairs = 0
     steps = 0
     t0 = time.perf_counter()

@@ -246,6 +246,71 @@ pphd_status pphd_read_timing(pphd_filter* f, double* ms, int64_t* launches);
 /* Kernel name of a class (for profiler cross-reference), or NULL. */
 const char* pphd_kernel_name(int32_t kernel_class);
 
+/* ---- batches of independent runs ---------------------------------------- */
+
+/* A batch runs many independent filters (runs) of the same model in one set
+ * of launches per stage: every kernel covers the groups of all runs.  The
+ * per-run fields of the model (partitions, births_per_step, clutter_rate,
+ * particles_per_target) are replaced by a run table; everything else is
+ * shared.  Run r uses Philox run word run_id and, for group j of the run,
+ * the slot counters j*cap + s, so it draws exactly the numbers it would draw
+ * as a single filter created with the same seed and run_id: its particles,
+ * weights and estimates equal that filter's (the same arithmetic in the same
+ * order).  pphd_init, pphd_predict, pphd_resample, pphd_exchange,
+ * pphd_read_state, pphd_write_state, pphd_set_tuning, pphd_set_timing and
+ * pphd_destroy accept a batch handle; state arrays hold the groups of all runs
+ * in run order (group g = run_g0 + j).  birth_proposal 0 and 1 only. */
+typedef struct {
+    int32_t partitions;           /* K_r >= 1 groups of the run                      */
+    int32_t births_per_step;      /* J_r >= 0, split over its groups as for a filter */
+    double clutter_rate;          /* lambda_r; kappa_r = lambda_r / clutter area      */
+    double particles_per_target;  /* R_r                                             */
+    uint32_t run_id;              /* Philox run word of the run                      */
+    int32_t reserved;             /* must be 0                                       */
+} pphd_run_desc;
+
+/* Workspace bytes of a batch: nruns runs, cap slots per group,
+ * max_meas_per_run measurements per run and step. */
+pphd_status pphd_batch_workspace_size(const pphd_model* model, const pphd_run_desc* runs, int32_t nruns,
+                                      int64_t cap_per_partition, int32_t max_meas_per_run, size_t* bytes);
+
+/* Creates a batch (see pphd_create for workspace, seed and stream). */
+pphd_status pphd_batch_create(const pphd_model* model, const pphd_run_desc* runs, int32_t nruns,
+                              int64_t cap_per_partition, int32_t max_meas_per_run, void* workspace,
+                              size_t workspace_bytes, uint64_t seed, void* stream, pphd_filter** out);
+
+/* Step 2 for every run.  z: the step's measurement sets of all runs,
+ * concatenated, double[z_count][2] (z_count <= nruns * max_meas_per_run);
+ * windows: int32[nruns][2], (offset, count) of run r's set in z (count <=
+ * max_meas_per_run).  Both on the host (copied before the call returns;
+ * windows outside the set return PPHD_EINVAL) or both on the device
+ * (on_device = 1; read in stream order, windows clamped into the set).
+ * Phase PREDICTED -> UPDATED. */
+pphd_status pphd_batch_update(pphd_filter* f, const double* z, int32_t z_count, const int32_t* windows,
+                              int32_t on_device);
+
+/* Steps 3 and 4 per run: run r's fused estimates go to out + r*cap (at most
+ * cap records, in label order), their count to n_out[r].  Host version:
+ * synchronises; mass (nullable) receives every group's updated mass.
+ * Device version: d_n_out[r] holds the full count, records beyond cap (and
+ * beyond max_meas_per_run) are dropped. */
+pphd_status pphd_batch_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out, double* mass);
+pphd_status pphd_batch_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t cap, int32_t* d_n_out);
+
+/* Captures one whole step of the batch (predict, update over the device
+ * buffers d_z / d_windows, fused estimates to d_out / d_n_out as in
+ * pphd_batch_extract_device, resample, exchange) into HIP graphs, one per
+ * particle-set parity.  Nothing runs at capture.  The step index is a device
+ * counter set to first_step here and advanced at the end of every replay.
+ * The caller refills d_z and d_windows (z_count rows at most) between
+ * replays.  Phase READY or RESAMPLED; timing must be off. */
+pphd_status pphd_batch_capture(pphd_filter* f, const double* d_z, int32_t z_count, const int32_t* d_windows,
+                               pphd_estimate* d_out, int32_t cap, int32_t* d_n_out, uint32_t first_step);
+
+/* Replays the captured step once on the batch's stream (one graph launch).
+ * Phase READY or RESAMPLED -> READY. */
+pphd_status pphd_batch_launch(pphd_filter* f);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,9 +35,39 @@ struct SoA {
     T* w;
 };
 
-__device__ __forceinline__ int births_in(const DevModel& m, int j)
+// Per-group constants.  A filter is a batch of independent runs; each run has
+// K_r groups (partitions), and global group g owns the particle slots
+// [g*cap, g*cap + cap).  The random-number counters of a group use its
+// run-local slot index jl*cap + s and its run's Philox run word, so a run
+// draws the same numbers alone or inside a batch.
+struct Grp {
+    int jl, K, g0, run;  // partition within the run, partitions of the run, run's first group, run index
+    int Jj, M0;          // births per step, initial particles
+    uint32_t rng_run;    // Philox run word of the run
+    int pad0;
+    double kappa, Rj;    // clutter density of the run; particles per target of the group (R/K)
+};
+
+// Measurement window of a run in a batched update: offset (in measurements)
+// into the step's concatenated set and count.
+struct ZWin {
+    int off, M;
+};
+
+// the step index: a value, or (captured graphs) a device counter
+__device__ __forceinline__ uint32_t step_of(uint32_t step, const uint32_t* dstep) { return dstep ? *dstep : step; }
+
+// this group's measurements: from its run's window (batched update) or the
+// whole set (single run, win == nullptr)
+struct ZView {
+    const double* Z;
+    int M;
+};
+__device__ __forceinline__ ZView zview(const Grp& g, const ZWin* win, const double* Z, int M)
 {
-    return m.J / m.K + (j < m.J % m.K ? 1 : 0);
+    if (!win) return ZView{ Z, M };
+    const ZWin w = win[g.run];
+    return ZView{ Z + 2 * (size_t)w.off, w.M };
 }
 
 // ---------------------------------------------------------------------------
@@ -129,10 +159,10 @@ __device__ __forceinline__ double wave_incl_scan(double v)
 // velocity N(0, sigma_v^2 I)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void draw_birth(const DevModel& m, uint32_t slot, uint32_t step, uint32_t purpose,
-                                           double s[4])
+                                           uint32_t run, double s[4])
 {
-    Block4 a = rng_block(m.key0, m.key1, slot, step, purpose, 0, m.run);
-    Block4 b = rng_block(m.key0, m.key1, slot, step, purpose, 1, m.run);
+    Block4 a = rng_block(m.key0, m.key1, slot, step, purpose, 0, run);
+    Block4 b = rng_block(m.key0, m.key1, slot, step, purpose, 1, run);
     double ux = uniform53(a.a, a.b), uy = uniform53(a.c, a.d);
     double n1, n2;
     normal_pair(uniform53(b.a, b.b), uniform53(b.c, b.d), n1, n2);
@@ -147,18 +177,20 @@ __device__ __forceinline__ void draw_birth(const DevModel& m, uint32_t slot, uin
 // grid (ceil(M0/256), K)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_init(DevModel m, SoA<T> st, int* __restrict__ nsurv)
+__global__ __launch_bounds__(256) void k_init(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
+                                              int* __restrict__ nsurv)
 {
     const int j = blockIdx.y;
+    const Grp gr = gd[j];
     const int s = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) nsurv[j] = m.M0;
-    if (s >= m.M0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) nsurv[j] = gr.M0;
+    if (s >= gr.M0) return;
     const size_t g = (size_t)j * m.cap + s;
     double v[4];
-    draw_birth(m, (uint32_t)g, 0u, RNG_INIT, v);
+    draw_birth(m, (uint32_t)(gr.jl * m.cap + s), 0u, RNG_INIT, gr.rng_run, v);
 #pragma unroll
     for (int d = 0; d < 4; ++d) st.x[d][g] = (T)v[d];
-    st.w[g] = (T)(m.init_mass / (double)m.M0);
+    st.w[g] = (T)(m.init_mass / (double)gr.M0);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,21 +221,25 @@ __device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_
 // grid (ceil(cap/256), K)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_predict(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
-                                                 int* __restrict__ ncur, uint32_t step)
+__global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                 const int* __restrict__ nsurv, int* __restrict__ ncur,
+                                                 uint32_t step_arg, const uint32_t* __restrict__ dstep)
 {
     const int j = blockIdx.y;
+    const Grp gr = gd[j];
+    const uint32_t step = step_of(step_arg, dstep);
     const int s = blockIdx.x * 256 + threadIdx.x;
     const int ns = nsurv[j];
-    const int Jj = births_in(m, j);
+    const int Jj = gr.Jj;
     // the host guarantees ns + J_j <= cap; the clamp keeps every store inside the group
     const int total = ns + Jj < m.cap ? ns + Jj : m.cap;
     if (blockIdx.x == 0 && threadIdx.x == 0) ncur[j] = total;
     if (s >= total) return;
     const size_t g = (size_t)j * m.cap + s;
+    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + s);
     double v[4], w;
     if (s < ns) {
-        Block4 r = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_PREDICT, 0, m.run);
+        Block4 r = rng_block(m.key0, m.key1, c0, step, RNG_PREDICT, 0, gr.rng_run);
         double n1, n2;
         normal_pair(uniform53(r.a, r.b), uniform53(r.c, r.d), n1, n2);
         const double ax = m.sigma_a * n1, ay = m.sigma_a * n2;
@@ -216,7 +252,7 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, SoA<T> st, Geo geo,
         w = m.pS * (double)st.w[g];
     } else {
         if (m.proposal != 0) return;  // drawn by k_birth_meas once Z_k is known
-        draw_birth(m, (uint32_t)g, step, RNG_BIRTH, v);
+        draw_birth(m, c0, step, RNG_BIRTH, gr.rng_run, v);
         w = m.birth_mass / (double)Jj;
     }
     T t[4];
@@ -264,17 +300,25 @@ __device__ __forceinline__ double neg_exp(double a, float) { return (double)__bu
 __device__ __forceinline__ double neg_exp(double a, double) { return exp(-a); }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_birth_meas(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
-                                                    const double* __restrict__ Z, int M, uint32_t step)
+__global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                    const int* __restrict__ nsurv, const double* __restrict__ Zall,
+                                                    int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
+                                                    const uint32_t* __restrict__ dstep)
 {
     const int j = blockIdx.y;
+    const Grp gr = gd[j];
     const int b = blockIdx.x * 256 + threadIdx.x;
-    const int Jj = births_in(m, j);
+    const int Jj = gr.Jj;
     if (b >= Jj) return;
+    const uint32_t step = step_of(step_arg, dstep);
+    const ZView zv = zview(gr, win, Zall, Mall);
+    const double* Z = zv.Z;
+    const int M = zv.M;
     const size_t g = (size_t)j * m.cap + nsurv[j] + b;
-    const Block4 a = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 0, m.run);
-    const Block4 v = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 1, m.run);
-    const Block4 c = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 2, m.run);
+    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + nsurv[j] + b);
+    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, gr.rng_run);
+    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, gr.rng_run);
+    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, gr.rng_run);
     const double u1 = uniform53(a.a, a.b), u2 = uniform53(a.c, a.d), uc = uniform53(c.a, c.b);
     double x, y;
     if (M == 0 || uc <= m.alpha) {
@@ -341,17 +385,30 @@ __device__ __forceinline__ double normal_pdf(double d, double sigma)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_birth_mix(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
-                                                   const double* __restrict__ tab, int M, uint32_t step)
+__global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                   const int* __restrict__ nsurv, const double* __restrict__ taball,
+                                                   int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
+                                                   const uint32_t* __restrict__ dstep)
 {
     const int j = blockIdx.y;
+    const Grp gr = gd[j];
     const int b = blockIdx.x * 256 + threadIdx.x;
-    const int Jj = births_in(m, j);
+    const int Jj = gr.Jj;
     if (b >= Jj) return;
+    const uint32_t step = step_of(step_arg, dstep);
+    // the table rows of this run's measurements
+    const double* tab = taball;
+    int M = Mall;
+    if (win) {
+        const ZWin w = win[gr.run];
+        tab = taball + (size_t)w.off * 4 * MIX_TAB;
+        M = w.M;
+    }
     const size_t g = (size_t)j * m.cap + nsurv[j] + b;
-    const Block4 a = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 0, m.run);
-    const Block4 v = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 1, m.run);
-    const Block4 c = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 2, m.run);
+    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + nsurv[j] + b);
+    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, gr.rng_run);
+    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, gr.rng_run);
+    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, gr.rng_run);
     double nv1, nv2;
     normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), nv1, nv2);
     const double uc = uniform53(c.a, c.b), uk = uniform53(c.c, c.d);
@@ -372,7 +429,7 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, SoA<T> st, Geo ge
             }
         }
         const double* t = tab + (size_t)(p * 4 + comp) * MIX_TAB;
-        const Block4 e = rng_block(m.key0, m.key1, (uint32_t)g, step, RNG_BIRTH, 3, m.run);
+        const Block4 e = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 3, gr.rng_run);
         double e1, e2;
         normal_pair(uniform53(e.a, e.b), uniform53(e.c, e.d), e1, e2);
         x[0] = t[4] + t[8] * e1;
@@ -446,11 +503,19 @@ __device__ __forceinline__ double sq_resid_nowrap(double zr, double zt, double r
 
 // Work split of the two likelihood passes: group j's slots are cut into wave
 // tiles of WT = 64*PT particles (lane l takes slots base + 64 i + l) and its
-// measurements into zsplit chunks of MZ; one wavefront takes one (tile, chunk)
-// pair, chunks of a tile sitting in the same workgroup.
+// M measurements into zsplit = clamp(ceil(M/mz), 1, ZSPLIT_MAX) chunks of
+// MZ = ceil(M/zsplit); one wavefront takes one (tile, chunk) pair, chunks of a
+// tile sitting in the same workgroup.  The chunking follows from M alone, so
+// a run splits its measurements the same way alone or in a batch.
+constexpr int ZSPLIT_MAX = 16;
 struct Split {
-    int wtiles, zsplit, MZ;
+    int wtiles, mz;
 };
+__device__ __forceinline__ int zsplit_for(int M, int mz)
+{
+    const int z = (M + mz - 1) / mz;
+    return z < 1 ? 1 : (z > ZSPLIT_MAX ? ZSPLIT_MAX : z);
+}
 
 // ---------------------------------------------------------------------------
 // Step 2, first pass (Eq 11): C_j(z) for every group and measurement.
@@ -470,17 +535,21 @@ struct Split {
 enum : int { PASS_FRAMES = 0, PASS_WRAP = 1, PASS_EXACT = 2 };
 
 template <typename T, int PT, int MODE>
-__global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __restrict__ W,
-                                            const int* __restrict__ ncur, const double* __restrict__ Z, int M,
-                                            int Mmax, Split sp, double* __restrict__ ps, int* __restrict__ ph,
-                                            double* __restrict__ pw)
+__global__ __launch_bounds__(256) void k_cz(DevModel m, const Grp* __restrict__ gd, Geo geo, const T* __restrict__ W,
+                                            const int* __restrict__ ncur, const double* __restrict__ Zall, int Mall,
+                                            const ZWin* __restrict__ win, int Mmax, Split sp,
+                                            double* __restrict__ ps, int* __restrict__ ph, double* __restrict__ pw)
 {
     constexpr int WT = 64 * PT;
     constexpr bool EXACT = MODE == PASS_EXACT, FRAMES = MODE == PASS_FRAMES;
     const int j = blockIdx.y;
+    const ZView zv = zview(gd[j], win, Zall, Mall);
+    const double* Z = zv.Z;
+    const int M = zv.M;
+    const int zsplit = zsplit_for(M, sp.mz), MZ = (M + zsplit - 1) / zsplit;
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + wave_in_block();
-    const int tile = gw / sp.zsplit, zc = gw - tile * sp.zsplit;
+    const int tile = gw / zsplit, zc = gw - tile * zsplit;
     const int n = ncur[j];
     const int base = tile * WT;
     if (tile >= sp.wtiles || base >= n) return;
@@ -521,7 +590,7 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __rest
         for (int i = 0; i < PT; ++i) nlw[i] += hw;  // exponent - h folded into the particle term
     }
     const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
-    const int p0 = zc * sp.MZ, p1 = (p0 + sp.MZ < M) ? p0 + sp.MZ : M;
+    const int p0 = zc * MZ, p1 = (p0 + MZ < M) ? p0 + MZ : M;
     // measurements of the chunk, 64 at a time: lane l holds measurement pb + l,
     // each iteration broadcasts one with v_readlane (no memory latency in the loop)
     for (int pb = p0; pb < p1; pb += 64) {
@@ -591,7 +660,9 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, Geo geo, const T* __rest
 // grid (K), 1024 threads, dynamic LDS Mmax doubles.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const int* __restrict__ ncur, int M, int Mmax,
+__global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __restrict__ gd,
+                                                     const int* __restrict__ ncur, int Mall,
+                                                     const ZWin* __restrict__ win, int Mmax,
                                                      int wtiles, int WT, const double* __restrict__ ps,
                                                      const int* __restrict__ ph, const double* __restrict__ pw,
                                                      int* __restrict__ zH, T* __restrict__ zF,
@@ -603,6 +674,8 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const int* __re
     __shared__ double s_red[16];
     __shared__ int s_redi[16];
     const int j = blockIdx.x;
+    const Grp gr = gd[j];
+    const int M = zview(gr, win, nullptr, Mall).M;
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const int n = ncur[j];
     const int nw = (n + WT - 1) / WT;
@@ -622,7 +695,7 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const int* __re
         S = wave_sum(S);
         double C = 0.0, F = 0.0, dW = 0.0;
         if (S > 0.0) {
-            const double D = ldexp(m.kappa, -H) + S;
+            const double D = ldexp(gr.kappa, -H) + S;
             F = 1.0 / D;
             dW = S / D;
             C = ldexp(S, H);
@@ -691,17 +764,22 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const int* __re
 // grid (ceil(wtiles*zsplit/4), K), 256 threads.
 // ---------------------------------------------------------------------------
 template <typename T, int PT, bool FRAMES>
-__global__ __launch_bounds__(256) void k_weight(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ ncur,
-                                                const double* __restrict__ Z, int M, int Mmax, Split sp,
+__global__ __launch_bounds__(256) void k_weight(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                const int* __restrict__ ncur, const double* __restrict__ Zall,
+                                                int Mall, const ZWin* __restrict__ win, int Mmax, Split sp,
                                                 const int* __restrict__ zH, const T* __restrict__ zF,
                                                 const int* __restrict__ zflag, double* __restrict__ pzeta,
                                                 T* __restrict__ accp)
 {
     constexpr int WT = 64 * PT;
     const int j = blockIdx.y;
+    const ZView zv = zview(gd[j], win, Zall, Mall);
+    const double* Z = zv.Z;
+    const int M = zv.M;
+    const int zsplit = zsplit_for(M, sp.mz), MZ = (M + zsplit - 1) / zsplit;
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + wave_in_block();
-    const int tile = gw / sp.zsplit, zc = gw - tile * sp.zsplit;
+    const int tile = gw / zsplit, zc = gw - tile * zsplit;
     const int n = ncur[j];
     const int base = tile * WT;
     if (tile >= sp.wtiles || base >= n) return;
@@ -728,7 +806,7 @@ __global__ __launch_bounds__(256) void k_weight(DevModel m, SoA<T> st, Geo geo, 
         return fast_exp2(-(T)sq_resid(m, zr, zt, rho[i], phi[i], H));
     };
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
-    const int p0 = zc * sp.MZ, p1 = (p0 + sp.MZ < M) ? p0 + sp.MZ : M;
+    const int p0 = zc * MZ, p1 = (p0 + MZ < M) ? p0 + MZ : M;
     for (int pb = p0; pb < p1; pb += 64) {
         const int pe = (pb + 64 < p1) ? pb + 64 : p1;
         double lzr = 0.0, lzt = 0.0;
@@ -828,12 +906,14 @@ __device__ __forceinline__ int quant_shift(double wmax, int n)
 // quantisation shift of the group's resampling.  256 threads each.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_wfinal(DevModel m, T* __restrict__ W, const int* __restrict__ ncur,
-                                                const T* __restrict__ accp, int zsplit, int tiles256,
+__global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restrict__ gd, T* __restrict__ W,
+                                                const int* __restrict__ ncur, const T* __restrict__ accp, int Mall,
+                                                const ZWin* __restrict__ win, int mz, int tiles256,
                                                 double* __restrict__ pmass, double* __restrict__ pmax)
 {
     __shared__ double rs[4], rm[4];
     const int j = blockIdx.y;
+    const int zsplit = zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
     const int s = blockIdx.x * 256 + threadIdx.x;
     const int n = ncur[j];
     const int nt = (n + 255) / 256;
@@ -863,15 +943,17 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, T* __restrict__ W, c
     }
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const int* __restrict__ ncur, int tiles256,
-                                                  const double* __restrict__ pmass, const double* __restrict__ pmax,
-                                                  int M, int Mmax, int wtiles2, int WT2,
+__global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, const int* __restrict__ ncur,
+                                                  int tiles256, const double* __restrict__ pmass,
+                                                  const double* __restrict__ pmax, int Mall,
+                                                  const ZWin* __restrict__ win, int Mmax, int wtiles2, int WT2,
                                                   const double* __restrict__ pzeta, const int* __restrict__ cand,
                                                   const int* __restrict__ ncand, double* __restrict__ fmass,
                                                   int* __restrict__ fLT, int* __restrict__ rsS,
                                                   int* __restrict__ sel, double* __restrict__ zeta)
 {
     const int j = blockIdx.x;
+    const int M = zview(gd[j], win, nullptr, Mall).M;
     const int n = ncur[j];
     const int nt = (n + 255) / 256;
     const int lane = threadIdx.x & 63, wv = wave_in_block();
@@ -929,11 +1011,12 @@ __global__ __launch_bounds__(256) void k_finalize(const int* __restrict__ ncur, 
 }
 
 // ---------------------------------------------------------------------------
-// Step 4, fusion at the central unit (one 1024-thread workgroup).  One
-// wavefront per label counts the groups that report it and averages their
-// estimates (tree sum over groups in a fixed order); a label is kept when
-// 2*votes > K.  Kept records are staged in LDS and written in label order.
-// grid (1), 1024 threads.
+// Step 4, fusion at the central unit (one 1024-thread workgroup per run).  One
+// wavefront per label counts the run's groups that report it and averages
+// their estimates (tree sum over groups in a fixed order); a label is kept
+// when 2*votes > K.  Kept records are staged in LDS and written in label
+// order to the run's output (cap records at out + run*cap, count at
+// nout[run]).  grid (runs), 1024 threads.
 // ---------------------------------------------------------------------------
 struct EstimateRec {
     double state[4];
@@ -941,13 +1024,22 @@ struct EstimateRec {
     int32_t votes;
 };
 
-__global__ __launch_bounds__(1024) void k_fuse(int K, int M, int Mmax, const int* __restrict__ sel,
-                                               const double* __restrict__ zeta, EstimateRec* __restrict__ out,
-                                               int cap, int* __restrict__ nout)
+__global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ gd, const int* __restrict__ run_g0, int Mall,
+                                               const ZWin* __restrict__ win, int Mmax,
+                                               const int* __restrict__ sel_all, const double* __restrict__ zeta_all,
+                                               EstimateRec* __restrict__ out_all, int cap, int* __restrict__ nout_all)
 {
     __shared__ EstimateRec s_rec[1024];
     __shared__ int s_keep[1024];
     __shared__ int s_wtot[16];
+    const int run = blockIdx.x;
+    const Grp gr = gd[run_g0[run]];
+    const int K = gr.K;
+    const int M = zview(gr, win, nullptr, Mall).M;
+    const int* sel = sel_all + (size_t)gr.g0 * Mmax;
+    const double* zeta = zeta_all + (size_t)gr.g0 * Mmax * 4;
+    EstimateRec* out = out_all + (size_t)run * cap;
+    int* nout = nout_all + run;
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     int offset = 0;
     for (int p0 = 0; p0 < M; p0 += 1024) {
@@ -1077,12 +1169,12 @@ __device__ __forceinline__ double children_count(double mq, double Rj)
 // grid (rtiles, K), 256 threads.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T> out,
+__global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __restrict__ gd, SoA<T> in, SoA<T> out,
                                                    const int* __restrict__ ncur, int* __restrict__ nsurv,
                                                    const int* __restrict__ rsS, const double* __restrict__ tsum,
-                                                   int rtiles, uint32_t step, double* __restrict__ massq,
-                                                   int* __restrict__ clampctr, int* __restrict__ counts,
-                                                   int record)
+                                                   int rtiles, uint32_t step_arg, const uint32_t* __restrict__ dstep,
+                                                   double* __restrict__ massq, int* __restrict__ clampctr,
+                                                   int* __restrict__ counts, int record)
 {
     __shared__ long long s_end[256];
     __shared__ long long s_first;
@@ -1123,12 +1215,13 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T>
     const double Pd = (s_q[1][0] + s_q[1][1]) + (s_q[1][2] + s_q[1][3]);
     double wpre = 0.0;
     for (int w2 = 0; w2 < wv; ++w2) wpre += s_q[2][w2];
-    const int Jj = births_in(m, j);
+    const Grp gr = gd[j];
+    const int Jj = gr.Jj;
     long long L = 0;
     double mq = 0.0;
     if (Qd > 0.0) {
         mq = ldexp(Qd, -S);
-        double Lf = children_count(mq, m.Rj);
+        double Lf = children_count(mq, gr.Rj);
         const double lim = (double)(m.cap - Jj);
         bool clamped = false;
         if (Lf > lim) {
@@ -1148,7 +1241,8 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T>
         return;
     }
     const double wc = mq / (double)L;
-    const uint32_t r = rng_block(m.key0, m.key1, (uint32_t)j, step, RNG_RESAMPLE, 0, m.run).a;
+    const uint32_t r = rng_block(m.key0, m.key1, (uint32_t)gr.jl, step_of(step_arg, dstep), RNG_RESAMPLE, 0,
+                                 gr.rng_run).a;
     const uint64_t Q = (uint64_t)Qd;
     const double c_incl = Pd + wpre + qin;            // c_t = q_0 + ... + q_t of the group
     const long long nend = points_below((uint64_t)c_incl, Q, L, r);
@@ -1172,19 +1266,21 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, SoA<T> in, SoA<T>
 }
 
 // ---------------------------------------------------------------------------
-// Step 6, ring exchange j -> j+1.  One count L = floor(rho_x min_j n_j) for all
-// groups; group j's chosen slots are S_j(m) = (o_j + m floor(n_j/L)) mod n_j
-// with o_j from the EXCHANGE stream, and the couple in S_j(m) replaces the one
-// in S_{j+1}(m).  A gather into a staging buffer followed by a scatter (two
-// launches) makes every read see the state before the exchange, so the
-// exchange is a permutation of the particles.  grid (ceil(Lmax/256), K).
+// Step 6, ring exchange j -> j+1 within each run.  One count L = floor(rho_x
+// min_j n_j) over the run's groups; group j's chosen slots are S_j(m) =
+// (o_j + m floor(n_j/L)) mod n_j with o_j from the EXCHANGE stream, and the
+// couple in S_j(m) replaces the one in S_{j+1}(m).  A gather into a staging
+// buffer followed by a scatter (two launches) makes every read see the state
+// before the exchange, so the exchange is a permutation of the particles.
+// grid (ceil(Lmax/256), groups).
 // ---------------------------------------------------------------------------
-// exchange count L = floor(rho_x min_j n_j); called by all threads of a workgroup
-__device__ __forceinline__ int exchange_count(const DevModel& m, const int* __restrict__ nsurv)
+// exchange count L = floor(rho_x min_j n_j) over the run's groups; called by
+// all threads of a workgroup
+__device__ __forceinline__ int exchange_count(const DevModel& m, const Grp& gr, const int* __restrict__ nsurv)
 {
     __shared__ int s_min[4];
     int mn = 2147483647;
-    for (int j = threadIdx.x; j < m.K; j += 256) mn = nsurv[j] < mn ? nsurv[j] : mn;
+    for (int j = threadIdx.x; j < gr.K; j += 256) mn = nsurv[gr.g0 + j] < mn ? nsurv[gr.g0 + j] : mn;
     mn = -wave_max(-mn);
     if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = mn;
     __syncthreads();
@@ -1193,22 +1289,27 @@ __device__ __forceinline__ int exchange_count(const DevModel& m, const int* __re
     return (int)floor(m.xfrac * (double)mn);
 }
 
-__device__ __forceinline__ uint64_t exchange_slot(const DevModel& m, int j, int nj, int L, int mm, uint32_t step)
+__device__ __forceinline__ uint64_t exchange_slot(const DevModel& m, const Grp& gr, int jl, int nj, int L, int mm,
+                                                  uint32_t step)
 {
-    const Block4 a = rng_block(m.key0, m.key1, (uint32_t)j, step, RNG_EXCHANGE, 0, m.run);
+    const Block4 a = rng_block(m.key0, m.key1, (uint32_t)jl, step, RNG_EXCHANGE, 0, gr.rng_run);
     const uint64_t o = ((uint64_t)a.a * (uint64_t)nj) >> 32;
     return (o + (uint64_t)mm * (uint64_t)(nj / L)) % (uint64_t)nj;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_xchg_gather(DevModel m, SoA<T> st, const int* __restrict__ nsurv,
-                                                     T* __restrict__ stage, int Lmax, uint32_t step)
+__global__ __launch_bounds__(256) void k_xchg_gather(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
+                                                     const int* __restrict__ nsurv, T* __restrict__ stage, int Lmax,
+                                                     uint32_t step_arg, const uint32_t* __restrict__ dstep)
 {
     const int j = blockIdx.y;
+    const Grp gr = gd[j];
+    if (gr.K < 2) return;
     const int mm = blockIdx.x * 256 + threadIdx.x;
-    const int L = exchange_count(m, nsurv);
+    const int L = exchange_count(m, gr, nsurv);
     if (mm >= L || mm >= Lmax) return;
-    const size_t src = (size_t)j * m.cap + (size_t)exchange_slot(m, j, nsurv[j], L, mm, step);
+    const uint32_t step = step_of(step_arg, dstep);
+    const size_t src = (size_t)j * m.cap + (size_t)exchange_slot(m, gr, gr.jl, nsurv[j], L, mm, step);
     T* o = stage + ((size_t)j * Lmax + mm) * 5;
 #pragma unroll
     for (int d = 0; d < 4; ++d) o[d] = st.x[d][src];
@@ -1216,19 +1317,48 @@ __global__ __launch_bounds__(256) void k_xchg_gather(DevModel m, SoA<T> st, cons
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, SoA<T> st, const int* __restrict__ nsurv,
-                                                      const T* __restrict__ stage, int Lmax, uint32_t step)
+__global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
+                                                      const int* __restrict__ nsurv, const T* __restrict__ stage,
+                                                      int Lmax, uint32_t step_arg, const uint32_t* __restrict__ dstep)
 {
     const int j = blockIdx.y;
+    const Grp gr = gd[j];
+    if (gr.K < 2) return;
     const int mm = blockIdx.x * 256 + threadIdx.x;
-    const int L = exchange_count(m, nsurv);
+    const int L = exchange_count(m, gr, nsurv);
     if (mm >= L || mm >= Lmax) return;
-    const int jn = (j + 1) % m.K;
-    const size_t dst = (size_t)jn * m.cap + (size_t)exchange_slot(m, jn, nsurv[jn], L, mm, step);
+    const uint32_t step = step_of(step_arg, dstep);
+    const int jln = (gr.jl + 1) % gr.K;
+    const int jn = gr.g0 + jln;
+    const size_t dst = (size_t)jn * m.cap + (size_t)exchange_slot(m, gr, jln, nsurv[jn], L, mm, step);
     const T* o = stage + ((size_t)j * Lmax + mm) * 5;
 #pragma unroll
     for (int d = 0; d < 4; ++d) st.x[d][dst] = o[d];
     st.w[dst] = o[4];
+}
+
+// ---------------------------------------------------------------------------
+// Batched updates: the runs' measurement windows as given, clamped into the
+// step's set (count to [0, max_meas], the window inside [0, zrows)), so no
+// window can lead a kernel outside the set.  grid (ceil(runs/256)).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_batch_windows(const int32_t* __restrict__ uw, int nruns, int zrows,
+                                                       int max_meas, ZWin* __restrict__ win)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= nruns) return;
+    int off = uw[2 * r], M = uw[2 * r + 1];
+    M = M < 0 ? 0 : (M > max_meas ? max_meas : M);
+    M = M > zrows ? zrows : M;
+    off = off < 0 ? 0 : off;
+    off = off > zrows - M ? zrows - M : off;
+    win[r] = ZWin{ off, M };
+}
+
+// advances the step counter of a captured step (one thread)
+__global__ void k_step_next(uint32_t* dstep)
+{
+    if (threadIdx.x == 0) dstep[0] = dstep[0] + 1u;
 }
 
 }  // namespace pphd

@@ -49,7 +49,7 @@ pphd_status fail(pphd_status s, const char* fmt, ...)
 // thread (PT) and measurements per wavefront (the measurement loop is cut into
 // at most ZSPLIT_MAX chunks).  Workspace arrays are sized for the smallest PT.
 constexpr int PT_DEFAULT_F32 = 8, PT_DEFAULT_F64 = 4, PT_MIN_F32 = 4, PT_MIN_F64 = 2, PR = 1;
-constexpr int ZSPLIT_MAX = 16, MZ_DEFAULT = 16;
+constexpr int MZ_DEFAULT = 16;
 
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
@@ -74,7 +74,24 @@ struct Layout {
 struct pphd_filter {
     pphd_model model;
     DevModel dm;
-    int K = 0, cap = 0, max_meas = 0, prec = 0;
+    int K = 0, cap = 0, max_meas = 0, prec = 0;  // K: groups over all runs
+    // runs: a single filter is one run of K groups; a batch holds nruns
+    // independent runs whose groups follow each other
+    int nruns = 1;
+    bool batch = false;
+    std::vector<Grp> hgd;         // host copy of the group table
+    std::vector<pphd_run_desc> runs;
+    std::vector<int> hrun_g0;
+    Grp* gd = nullptr;            // device group table [K]
+    int* run_g0 = nullptr;        // first group of each run [nruns]
+    ZWin* win = nullptr;          // measurement windows of the batched update [nruns]
+    int32_t* uwin = nullptr;      // windows as given by the caller [nruns][2]
+    uint32_t* dstep = nullptr;    // step counter of captured graphs
+    int z_cap = 0;                // measurements the batch's set buffer holds
+    int Jmax = 0, M0max = 0;
+    int32_t* pin_win = nullptr;
+    hipGraph_t graph[2] = {};          // captured batch steps, starting from particle set 0 / 1
+    hipGraphExec_t graph_exec[2] = {};
     size_t KC = 0;
     size_t esz = 8;
     hipStream_t stream = nullptr;
@@ -129,18 +146,20 @@ struct pphd_filter {
 
 namespace {
 
-bool model_ok(const pphd_model* m, std::string& why)
+// batch: the per-run fields of the model (partitions, births, clutter rate,
+// particles per target) are ignored in favour of the run table
+bool model_ok(const pphd_model* m, std::string& why, bool batch = false)
 {
     if (!m) { why = "model is NULL"; return false; }
     if (m->dim != 4) { why = "dim must be 4"; return false; }
-    if (m->partitions < 1) { why = "partitions must be >= 1"; return false; }
-    if (m->births_per_step < 0) { why = "births_per_step must be >= 0"; return false; }
+    if (!batch && m->partitions < 1) { why = "partitions must be >= 1"; return false; }
+    if (!batch && m->births_per_step < 0) { why = "births_per_step must be >= 0"; return false; }
     if (m->precision != PPHD_FP64 && m->precision != PPHD_FP32) { why = "precision must be 0 or 1"; return false; }
     if (!(m->sigma_r > 0) || !(m->sigma_theta > 0)) { why = "sensor sigmas must be > 0"; return false; }
     if (!(m->p_D >= 0 && m->p_D <= 1) || !(m->p_S >= 0 && m->p_S <= 1)) { why = "p_S, p_D must be in [0,1]"; return false; }
-    if (!(m->clutter_rate >= 0)) { why = "clutter_rate must be >= 0"; return false; }
+    if (!batch && !(m->clutter_rate >= 0)) { why = "clutter_rate must be >= 0"; return false; }
     if (!(m->r_max > m->r_min) || !(m->th_max > m->th_min)) { why = "empty clutter region"; return false; }
-    if (!(m->particles_per_target > 0)) { why = "particles_per_target must be > 0"; return false; }
+    if (!batch && !(m->particles_per_target > 0)) { why = "particles_per_target must be > 0"; return false; }
     if (!(m->exchange_fraction >= 0 && m->exchange_fraction < 0.5)) { why = "exchange_fraction must be in [0, 0.5)"; return false; }
     if (!(m->birth_mass >= 0) || !(m->init_mass >= 0)) { why = "masses must be >= 0"; return false; }
     if (m->birth_proposal < 0 || m->birth_proposal > 2) { why = "birth_proposal must be 0, 1 or 2"; return false; }
@@ -161,7 +180,12 @@ size_t carve(pphd_filter* f, char* base)
     f->nsurv = L.take<int>(base, K * 4);
     f->ncur = L.take<int>(base, K * 4);
     f->clampctr = L.take<int>(base, 4);
-    f->zbuf = L.take<double>(base, Mx * 2 * 8);
+    f->zbuf = L.take<double>(base, (size_t)f->z_cap * 2 * 8);
+    f->gd = L.take<Grp>(base, K * sizeof(Grp));
+    f->run_g0 = L.take<int>(base, (size_t)f->nruns * 4);
+    f->win = L.take<ZWin>(base, (size_t)f->nruns * sizeof(ZWin));
+    f->uwin = L.take<int32_t>(base, (size_t)f->nruns * 8);
+    f->dstep = L.take<uint32_t>(base, 4);
     f->p1s = L.take<double>(base, K * f->wtiles_max * Mx * 8);
     f->p1h = L.take<int>(base, K * f->wtiles_max * Mx * 4);
     f->p1w = L.take<double>(base, K * f->wtiles_max * 8);
@@ -185,25 +209,95 @@ size_t carve(pphd_filter* f, char* base)
     f->rsS = L.take<int>(base, K * 4);
     f->sel = L.take<int>(base, K * Mx * 4);
     f->zeta = L.take<double>(base, K * Mx * 4 * 8);
-    f->est = L.take<EstimateRec>(base, Mx * sizeof(EstimateRec));
-    f->nest = L.take<int>(base, 4);
+    f->est = L.take<EstimateRec>(base, (size_t)f->nruns * Mx * sizeof(EstimateRec));
+    f->nest = L.take<int>(base, (size_t)f->nruns * 4);
     f->tsum = L.take<double>(base, K * f->rtiles * 8);
     f->massq = L.take<double>(base, K * 8);
     f->counts = L.take<int>(base, KC * 4);
     f->stage = L.take<char>(base, K * (size_t)f->Lmax * 5 * es);
     if (f->model.birth_proposal == 2) {
-        f->mix_tab = L.take<double>(base, Mx * 4 * MIX_TAB * 8);
+        f->mix_tab = L.take<double>(base, (size_t)f->z_cap * 4 * MIX_TAB * 8);
         f->mix_raw = L.take<float>(base, Mx * PPHD_MLP_OUTPUTS * 4);
     }
     return (L.off + 255) & ~(size_t)255;
 }
 
-void set_geometry(pphd_filter* f, const pphd_model* m, int64_t cap, int32_t max_meas)
+// the single run a plain filter's model describes
+pphd_run_desc run_of_model(const pphd_model* m, uint32_t run_id)
+{
+    pphd_run_desc r;
+    std::memset(&r, 0, sizeof r);
+    r.partitions = m->partitions;
+    r.births_per_step = m->births_per_step;
+    r.clutter_rate = m->clutter_rate;
+    r.particles_per_target = m->particles_per_target;
+    r.run_id = run_id;
+    return r;
+}
+
+int births_of(const pphd_run_desc& r, int jl)
+{
+    return r.births_per_step / r.partitions + (jl < r.births_per_step % r.partitions ? 1 : 0);
+}
+
+int initial_of(const pphd_run_desc& r)
+{
+    return std::max(1, (int)std::floor(r.particles_per_target / (double)r.partitions + 0.5));
+}
+
+bool runs_ok(const pphd_model* m, const pphd_run_desc* runs, int nruns, std::string& why)
+{
+    if (!runs || nruns < 1) { why = "a batch needs at least one run"; return false; }
+    for (int r = 0; r < nruns; ++r) {
+        const pphd_run_desc& d = runs[r];
+        if (d.partitions < 1) { why = "run partitions must be >= 1"; return false; }
+        if (d.births_per_step < 0) { why = "run births_per_step must be >= 0"; return false; }
+        if (!(d.clutter_rate >= 0)) { why = "run clutter_rate must be >= 0"; return false; }
+        if (!(d.particles_per_target > 0)) { why = "run particles_per_target must be > 0"; return false; }
+        if (d.reserved != 0) { why = "run reserved field must be 0"; return false; }
+    }
+    (void)m;
+    return true;
+}
+
+void set_geometry(pphd_filter* f, const pphd_model* m, const pphd_run_desc* runs, int nruns, int64_t cap,
+                  int32_t max_meas, bool batch)
 {
     f->model = *m;
-    f->K = m->partitions;
+    f->batch = batch;
+    f->nruns = nruns;
+    f->runs.assign(runs, runs + nruns);
+    f->K = 0;
+    for (int r = 0; r < nruns; ++r) f->K += runs[r].partitions;
     f->cap = (int)cap;
     f->max_meas = max_meas;
+    f->z_cap = batch ? nruns * max_meas : max_meas;
+    // group table
+    const double area = (m->r_max - m->r_min) * (m->th_max - m->th_min);
+    f->hgd.clear();
+    f->hrun_g0.clear();
+    f->Jmax = 0;
+    f->M0max = 0;
+    for (int r = 0; r < nruns; ++r) {
+        const pphd_run_desc& d = runs[r];
+        f->hrun_g0.push_back((int)f->hgd.size());
+        for (int jl = 0; jl < d.partitions; ++jl) {
+            Grp g;
+            std::memset(&g, 0, sizeof g);
+            g.jl = jl;
+            g.K = d.partitions;
+            g.g0 = f->hrun_g0.back();
+            g.run = r;
+            g.Jj = births_of(d, jl);
+            g.M0 = initial_of(d);
+            g.rng_run = d.run_id;
+            g.kappa = d.clutter_rate / area;
+            g.Rj = d.particles_per_target / (double)d.partitions;
+            f->Jmax = std::max(f->Jmax, g.Jj);
+            f->M0max = std::max(f->M0max, g.M0);
+            f->hgd.push_back(g);
+        }
+    }
     f->prec = m->precision;
     f->esz = m->precision == PPHD_FP64 ? 8 : 4;
     f->KC = (size_t)f->K * (size_t)cap;
@@ -219,17 +313,22 @@ void set_geometry(pphd_filter* f, const pphd_model* m, int64_t cap, int32_t max_
     f->Lmax = (int)std::floor(m->exchange_fraction * (double)cap) + 1;
 }
 
-bool sizes_ok(const pphd_model* m, int64_t cap, int32_t max_meas, std::string& why)
+bool sizes_ok(const pphd_run_desc* runs, int nruns, int64_t cap, int32_t max_meas, std::string& why)
 {
     if (cap < 1 || cap > (1ll << 30) / 4) { why = "cap_per_partition out of range"; return false; }
-    if ((int64_t)m->partitions * cap > (1ll << 31) - 1) { why = "partitions * cap must fit in 31 bits"; return false; }
     if (max_meas < 1 || max_meas > 65536) { why = "max_meas must be in [1, 65536]"; return false; }
-    const double Rj = m->particles_per_target / (double)m->partitions;
-    const int M0 = std::max(1, (int)std::floor(Rj + 0.5));
-    const int Jmax = m->births_per_step / m->partitions + (m->births_per_step % m->partitions ? 1 : 0);
-    if (M0 > cap) { why = "cap_per_partition < round(R/K) initial particles"; return false; }
-    if (Jmax >= cap) { why = "cap_per_partition must exceed the births per group"; return false; }
-    if ((int64_t)M0 + Jmax > cap) { why = "cap_per_partition < round(R/K) + births per group"; return false; }
+    int64_t groups = 0;
+    for (int r = 0; r < nruns; ++r) {
+        const pphd_run_desc& d = runs[r];
+        groups += d.partitions;
+        const int M0 = initial_of(d);
+        const int Jmax = births_of(d, 0);
+        if (M0 > cap) { why = "cap_per_partition < round(R/K) initial particles"; return false; }
+        if (Jmax >= cap) { why = "cap_per_partition must exceed the births per group"; return false; }
+        if ((int64_t)M0 + Jmax > cap) { why = "cap_per_partition < round(R/K) + births per group"; return false; }
+    }
+    if (groups * cap > (1ll << 31) - 1) { why = "groups * cap must fit in 31 bits"; return false; }
+    if ((int64_t)nruns * max_meas > (1ll << 28)) { why = "runs * max_meas too large"; return false; }
     return true;
 }
 
@@ -246,7 +345,9 @@ void fill_devmodel(pphd_filter* f)
     d.pS = m.p_S;
     d.pD = m.p_D;
     d.nu = 1.0 - m.p_D;
-    d.kappa = m.clutter_rate / ((m.r_max - m.r_min) * (m.th_max - m.th_min));
+    // the smallest clutter density of the runs decides the pass mode
+    d.kappa = f->hgd[0].kappa;
+    for (const Grp& g : f->hgd) d.kappa = std::min(d.kappa, g.kappa);
     d.birth_mass = m.birth_mass;
     d.reg0 = m.region[0];
     d.reg1 = m.region[1];
@@ -254,7 +355,7 @@ void fill_devmodel(pphd_filter* f)
     d.reg3 = m.region[3];
     d.sigma_v = m.birth_sigma_v;
     d.init_mass = m.init_mass;
-    d.Rj = m.particles_per_target / (double)m.partitions;
+    d.Rj = f->hgd[0].Rj;
     d.xfrac = m.exchange_fraction;
     const double c = std::sqrt(std::log2(std::exp(1.0)) / 2.0);
     d.cr = c / m.sigma_r;
@@ -267,10 +368,10 @@ void fill_devmodel(pphd_filter* f)
     d.inv_area = 1.0 / ((m.region[1] - m.region[0]) * (m.region[3] - m.region[2]));
     d.alpha = m.birth_alpha;
     d.proposal = m.birth_proposal;
-    d.K = m.partitions;
-    d.J = m.births_per_step;
+    d.K = f->K;  // groups over all runs
+    d.J = f->Jmax;
     d.cap = f->cap;
-    d.M0 = std::max(1, (int)std::floor(d.Rj + 0.5));
+    d.M0 = f->M0max;
     // bearing frames need every wrapped pair to sit at least 160 binary orders
     // down: (pi/2 c_t)^2 > 160 (sigma_theta below about 0.1 rad)
     const double half = 0.5 * 3.14159265358979323846 * d.ct;
@@ -294,15 +395,23 @@ Geo geo_of(pphd_filter* f)
     return Geo{ f->geo_rho, f->geo_phi, f->geo_phib, f->geo_lw };
 }
 
-Split split_for(int wtiles, int M, int mz)
+// zsplit of a measurement count, as the passes derive it
+int host_zsplit(int M, int mz)
 {
-    Split sp;
-    sp.wtiles = wtiles;
-    int z = (M + mz - 1) / mz;
-    sp.zsplit = z < 1 ? 1 : (z > ZSPLIT_MAX ? ZSPLIT_MAX : z);
-    sp.MZ = (M + sp.zsplit - 1) / sp.zsplit;
-    return sp;
+    const int z = (M + mz - 1) / mz;
+    return z < 1 ? 1 : (z > ZSPLIT_MAX ? ZSPLIT_MAX : z);
 }
+
+// Measurements of an update: one run's set (win == nullptr, M measurements)
+// or a batch's concatenated sets with per-run windows (zrows rows in dz).
+// dstep: the device step counter when the launches are captured in a graph.
+struct UpdArgs {
+    const double* dz;
+    int M;
+    const ZWin* win;
+    int zrows;
+    const uint32_t* dstep;
+};
 
 hipEvent_t take_event(pphd_filter* f)
 {
@@ -343,76 +452,82 @@ pphd_status launch(pphd_filter* f, int cls, F&& fn)
     } while (0)
 
 template <typename T, int PT1, int PT2>
-pphd_status run_update(pphd_filter* f, const double* dz, int M)
+pphd_status run_update(pphd_filter* f, const UpdArgs& a)
 {
     const DevModel dm = f->dm;
     SoA<T> st = soa<T>(f, f->cur);
     const Geo geo = geo_of(f);
     const int K = f->K, Mx = f->max_meas;
-    const Split s1 = split_for(f->wtiles1, M, f->mz), s2 = split_for(f->wtiles2, M, f->mz);
+    const Split s1{ f->wtiles1, f->mz }, s2{ f->wtiles2, f->mz };
+    // chunks per tile: exact for one run, the maximum for a batch (waves past
+    // a group's own chunk count exit at once)
+    const int zs = a.win ? ZSPLIT_MAX : host_zsplit(a.M, f->mz);
     if (f->births_pending) {
-        const int Jmax = dm.J / K + (dm.J % K ? 1 : 0);
+        const int Jmax = f->Jmax;
         if (Jmax > 0 && dm.proposal == 1) {
             LAUNCH(f, PPHD_K_BIRTH,
-                   hipLaunchKernelGGL((k_birth_meas<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm, st,
-                                      geo, f->nsurv, dz, M, f->last_step));
+                   hipLaunchKernelGGL((k_birth_meas<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm,
+                                      f->gd, st, geo, f->nsurv, a.dz, a.M, a.win, f->last_step, a.dstep));
         } else if (Jmax > 0 && dm.proposal == 2) {
             // mixture table of this step's measurements: from the outputs the
             // caller set, else from the attached network
+            const int rows = a.win ? a.zrows : a.M;
             pphd_status ms = PPHD_OK;
             LAUNCH(f, PPHD_K_MLP_INFER,
-                   ms = f->mix_preset ? mlp_head_table(f->model, f->stream, dz, f->mix_raw, M, f->mix_tab)
-                                      : mlp_mixture_table(f->mlp, f->stream, dz, M, f->mix_tab));
+                   ms = f->mix_preset ? mlp_head_table(f->model, f->stream, a.dz, f->mix_raw, rows, f->mix_tab)
+                                      : mlp_mixture_table(f->mlp, f->stream, a.dz, rows, f->mix_tab));
             if (ms != PPHD_OK) return ms;
             LAUNCH(f, PPHD_K_BIRTH_MIX,
-                   hipLaunchKernelGGL((k_birth_mix<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm, st,
-                                      geo, f->nsurv, f->mix_tab, M, f->last_step));
+                   hipLaunchKernelGGL((k_birth_mix<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm,
+                                      f->gd, st, geo, f->nsurv, f->mix_tab, a.M, a.win, f->last_step, a.dstep));
         }
         f->mix_preset = false;
         f->births_pending = false;
     }
-    dim3 g1((f->wtiles1 * s1.zsplit + 3) / 4, K), g2((f->wtiles2 * s2.zsplit + 3) / 4, K);
+    dim3 g1((f->wtiles1 * zs + 3) / 4, K), g2((f->wtiles2 * zs + 3) / 4, K);
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz<T, PT1, PASS_FRAMES>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
-                                  f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
+               hipLaunchKernelGGL((k_cz<T, PT1, PASS_FRAMES>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
+                                  (const T*)st.w, f->ncur, a.dz, a.M, a.win, Mx, s1, f->p1s, f->p1h, f->p1w));
     } else if (f->pass_mode == PASS_WRAP) {
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
-                                  f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
+               hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
+                                  (const T*)st.w, f->ncur, a.dz, a.M, a.win, Mx, s1, f->p1s, f->p1h, f->p1w));
     } else {
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz<T, PT1, PASS_EXACT>), g1, dim3(256), 0, f->stream, dm, geo, (const T*)st.w,
-                                  f->ncur, dz, M, Mx, s1, f->p1s, f->p1h, f->p1w));
+               hipLaunchKernelGGL((k_cz<T, PT1, PASS_EXACT>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
+                                  (const T*)st.w, f->ncur, a.dz, a.M, a.win, Mx, s1, f->p1s, f->p1h, f->p1w));
     }
     LAUNCH(f, PPHD_K_CZ_COMBINE,
            hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
-                              f->ncur, M, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH, (T*)f->zF, f->zC,
-                              f->zdW, f->zflag, f->cand, f->ncand));
+                              f->gd, f->ncur, a.M, a.win, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH,
+                              (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand));
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_WEIGHT,
-               hipLaunchKernelGGL((k_weight<T, PT2, true>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M,
-                                  Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
+               hipLaunchKernelGGL((k_weight<T, PT2, true>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
+                                  a.dz, a.M, a.win, Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta,
+                                  (T*)f->accp));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
-               hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, st, geo, f->ncur, dz, M,
-                                  Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta, (T*)f->accp));
+               hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
+                                  a.dz, a.M, a.win, Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta,
+                                  (T*)f->accp));
     }
     LAUNCH(f, PPHD_K_WFINAL,
-           hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, st.w, f->ncur,
-                              (const T*)f->accp, s2.zsplit, f->tiles256, f->p2mass, f->p2max));
+           hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
+                              (const T*)f->accp, a.M, a.win, f->mz, f->tiles256, f->p2mass, f->p2max));
     LAUNCH(f, PPHD_K_FINALIZE,
-           hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->ncur, f->tiles256, f->p2mass,
-                              f->p2max, M, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass, f->fLT,
-                              f->rsS, f->sel, f->zeta));
+           hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
+                              f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
+                              f->fLT, f->rsS, f->sel, f->zeta));
     return PPHD_OK;
 }
 
 // the tile shapes pphd_set_tuning accepts
-pphd_status dispatch_update(pphd_filter* f, const double* dz, int M)
+pphd_status dispatch_update(pphd_filter* f, const UpdArgs& a)
 {
 #define PPHD_CASE(T, A, B) \
-    if (f->pt1 == A && f->pt2 == B) return run_update<T, A, B>(f, dz, M);
+    if (f->pt1 == A && f->pt2 == B) return run_update<T, A, B>(f, a);
     if (f->prec == PPHD_FP64) {
         PPHD_CASE(double, 2, 2) PPHD_CASE(double, 2, 4) PPHD_CASE(double, 2, 8)
         PPHD_CASE(double, 4, 2) PPHD_CASE(double, 4, 4) PPHD_CASE(double, 4, 8)
@@ -427,26 +542,26 @@ pphd_status dispatch_update(pphd_filter* f, const double* dz, int M)
 }
 
 template <typename T>
-pphd_status run_predict(pphd_filter* f, uint32_t step)
+pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
     dim3 g((f->cap + 255) / 256, f->K);
     LAUNCH(f, PPHD_K_PREDICT,
-           hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, soa<T>(f, f->cur), geo_of(f),
-                              f->nsurv, f->ncur, step));
+           hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
+                              f->nsurv, f->ncur, step, dstep));
     return PPHD_OK;
 }
 
 template <typename T>
 pphd_status run_init(pphd_filter* f)
 {
-    dim3 g((f->dm.M0 + 255) / 256, f->K);
+    dim3 g((f->M0max + 255) / 256, f->K);
     LAUNCH(f, PPHD_K_INIT,
-           hipLaunchKernelGGL((k_init<T>), g, dim3(256), 0, f->stream, f->dm, soa<T>(f, f->cur), f->nsurv));
+           hipLaunchKernelGGL((k_init<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), f->nsurv));
     return PPHD_OK;
 }
 
 template <typename T>
-pphd_status run_resample(pphd_filter* f, uint32_t step)
+pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
     dim3 g(f->rtiles, f->K);
     SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
@@ -454,25 +569,27 @@ pphd_status run_resample(pphd_filter* f, uint32_t step)
            hipLaunchKernelGGL((k_rs_tiles<T>), g, dim3(256), 0, f->stream, f->dm, (const T*)in.w, f->ncur, f->rsS,
                               f->rtiles, f->tsum));
     LAUNCH(f, PPHD_K_RS_EXPAND,
-           hipLaunchKernelGGL((k_rs_expand<T>), g, dim3(256), 0, f->stream, f->dm, in, out, f->ncur, f->nsurv,
-                              f->rsS, f->tsum, f->rtiles, step, f->massq, f->clampctr, f->counts,
+           hipLaunchKernelGGL((k_rs_expand<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
+                              f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr, f->counts,
                               f->record ? 1 : 0));
     f->cur = 1 - f->cur;
     return PPHD_OK;
 }
 
 template <typename T>
-pphd_status run_exchange(pphd_filter* f, uint32_t step)
+pphd_status run_exchange(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
-    if (f->K < 2) return PPHD_OK;
+    bool any = false;
+    for (const pphd_run_desc& r : f->runs) any = any || r.partitions > 1;
+    if (!any) return PPHD_OK;
     dim3 g((f->Lmax + 255) / 256, f->K);
     SoA<T> st = soa<T>(f, f->cur);
     LAUNCH(f, PPHD_K_XCHG_GATHER,
-           hipLaunchKernelGGL((k_xchg_gather<T>), g, dim3(256), 0, f->stream, f->dm, st, f->nsurv, (T*)f->stage,
-                              f->Lmax, step));
+           hipLaunchKernelGGL((k_xchg_gather<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, st, f->nsurv,
+                              (T*)f->stage, f->Lmax, step, dstep));
     LAUNCH(f, PPHD_K_XCHG_SCATTER,
-           hipLaunchKernelGGL((k_xchg_scatter<T>), g, dim3(256), 0, f->stream, f->dm, st, f->nsurv,
-                              (const T*)f->stage, f->Lmax, step));
+           hipLaunchKernelGGL((k_xchg_scatter<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, st, f->nsurv,
+                              (const T*)f->stage, f->Lmax, step, dstep));
     return PPHD_OK;
 }
 
@@ -488,11 +605,11 @@ pphd_status check_handle(pphd_filter* f)
         if (s_ != PPHD_OK) return s_;            \
     } while (0)
 
-pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout)
+pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout, int M, const ZWin* win)
 {
     LAUNCH(f, PPHD_K_FUSE,
-           hipLaunchKernelGGL(k_fuse, dim3(1), dim3(1024), 0, f->stream, f->K, f->last_m, f->max_meas, f->sel,
-                              f->zeta, out, cap, nout));
+           hipLaunchKernelGGL(k_fuse, dim3(f->nruns), dim3(1024), 0, f->stream, f->gd, f->run_g0, M, win, f->max_meas,
+                              f->sel, f->zeta, out, cap, nout));
     return PPHD_OK;
 }
 
@@ -504,29 +621,38 @@ const char* pphd_last_error(void) { return g_err.c_str(); }
 
 const char* pphd_kernel_name(int32_t c) { return (c >= 0 && c < PPHD_K_COUNT) ? kKernelNames[c] : nullptr; }
 
-pphd_status pphd_workspace_size(const pphd_model* model, int64_t cap, int32_t max_meas, size_t* bytes)
+}  // extern "C"
+
+namespace {
+
+pphd_status size_impl(const pphd_model* model, const pphd_run_desc* runs, int nruns, int64_t cap, int32_t max_meas,
+                      bool batch, size_t* bytes)
 {
     std::string why;
-    if (!model_ok(model, why) || !sizes_ok(model, cap, max_meas, why)) return fail(PPHD_EINVAL, "%s", why.c_str());
+    if (!model_ok(model, why, batch) || !runs_ok(model, runs, nruns, why) || !sizes_ok(runs, nruns, cap, max_meas, why))
+        return fail(PPHD_EINVAL, "%s", why.c_str());
     if (!bytes) return fail(PPHD_EINVAL, "bytes is NULL");
     pphd_filter tmp;
-    set_geometry(&tmp, model, cap, max_meas);
+    set_geometry(&tmp, model, runs, nruns, cap, max_meas, batch);
     *bytes = carve(&tmp, nullptr);
     return PPHD_OK;
 }
 
-pphd_status pphd_create(const pphd_model* model, int64_t cap, int32_t max_meas, void* workspace,
-                        size_t workspace_bytes, uint64_t seed, uint32_t run_id, void* stream, pphd_filter** out)
+pphd_status create_impl(const pphd_model* model, const pphd_run_desc* runs, int nruns, int64_t cap,
+                        int32_t max_meas, void* workspace, size_t workspace_bytes, uint64_t seed, uint32_t run_id,
+                        void* stream, bool batch, pphd_filter** out)
 {
     std::string why;
     if (!out) return fail(PPHD_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!model_ok(model, why) || !sizes_ok(model, cap, max_meas, why)) return fail(PPHD_EINVAL, "%s", why.c_str());
+    if (!model_ok(model, why, batch) || !runs_ok(model, runs, nruns, why) || !sizes_ok(runs, nruns, cap, max_meas, why))
+        return fail(PPHD_EINVAL, "%s", why.c_str());
+    if (batch && model->birth_proposal == 2) return fail(PPHD_EINVAL, "batches support birth_proposal 0 and 1");
     if (!workspace) return fail(PPHD_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(PPHD_EINVAL, "workspace must be 256-byte aligned");
     pphd_filter* f = new (std::nothrow) pphd_filter();
     if (!f) return fail(PPHD_ENOMEM, "host allocation failed");
-    set_geometry(f, model, cap, max_meas);
+    set_geometry(f, model, runs, nruns, cap, max_meas, batch);
     const size_t need = carve(f, nullptr);
     if (workspace_bytes < need) {
         delete f;
@@ -537,8 +663,10 @@ pphd_status pphd_create(const pphd_model* model, int64_t cap, int32_t max_meas, 
     f->run = run_id;
     f->stream = (hipStream_t)stream;
     fill_devmodel(f);
-    hipError_t e = hipHostMalloc((void**)&f->pin_z, (size_t)max_meas * 2 * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void**)&f->pin_z, (size_t)f->z_cap * 2 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&f->pin_win, (size_t)f->nruns * 8, hipHostMallocDefault);
     if (e != hipSuccess) {
+        if (f->pin_z) (void)hipHostFree(f->pin_z);
         delete f;
         return fail(PPHD_EDEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));
     }
@@ -546,8 +674,14 @@ pphd_status pphd_create(const pphd_model* model, int64_t cap, int32_t max_meas, 
     if (e == hipSuccess) e = hipMemsetAsync(f->clampctr, 0, 4, f->stream);
     if (e == hipSuccess) e = hipMemsetAsync(f->nsurv, 0, (size_t)f->K * 4, f->stream);
     if (e == hipSuccess) e = hipMemsetAsync(f->ncur, 0, (size_t)f->K * 4, f->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f->gd, f->hgd.data(), f->hgd.size() * sizeof(Grp), hipMemcpyHostToDevice, f->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f->run_g0, f->hrun_g0.data(), f->hrun_g0.size() * 4, hipMemcpyHostToDevice, f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) {
         (void)hipHostFree(f->pin_z);
+        (void)hipHostFree(f->pin_win);
         delete f;
         return fail(PPHD_EDEVICE, "filter set-up failed: %s", hipGetErrorString(e));
     }
@@ -555,11 +689,49 @@ pphd_status pphd_create(const pphd_model* model, int64_t cap, int32_t max_meas, 
     return PPHD_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+pphd_status pphd_workspace_size(const pphd_model* model, int64_t cap, int32_t max_meas, size_t* bytes)
+{
+    if (!model) return fail(PPHD_EINVAL, "model is NULL");
+    const pphd_run_desc r = run_of_model(model, 0);
+    return size_impl(model, &r, 1, cap, max_meas, false, bytes);
+}
+
+pphd_status pphd_create(const pphd_model* model, int64_t cap, int32_t max_meas, void* workspace,
+                        size_t workspace_bytes, uint64_t seed, uint32_t run_id, void* stream, pphd_filter** out)
+{
+    if (!model) return fail(PPHD_EINVAL, "model is NULL");
+    const pphd_run_desc r = run_of_model(model, run_id);
+    return create_impl(model, &r, 1, cap, max_meas, workspace, workspace_bytes, seed, run_id, stream, false, out);
+}
+
+pphd_status pphd_batch_workspace_size(const pphd_model* model, const pphd_run_desc* runs, int32_t nruns,
+                                      int64_t cap, int32_t max_meas_per_run, size_t* bytes)
+{
+    return size_impl(model, runs, nruns, cap, max_meas_per_run, true, bytes);
+}
+
+pphd_status pphd_batch_create(const pphd_model* model, const pphd_run_desc* runs, int32_t nruns, int64_t cap,
+                              int32_t max_meas_per_run, void* workspace, size_t workspace_bytes, uint64_t seed,
+                              void* stream, pphd_filter** out)
+{
+    return create_impl(model, runs, nruns, cap, max_meas_per_run, workspace, workspace_bytes, seed, 0, stream, true,
+                       out);
+}
+
 pphd_status pphd_destroy(pphd_filter* f)
 {
     if (!f) return PPHD_OK;
     (void)hipStreamSynchronize(f->stream);
     if (f->pin_z) (void)hipHostFree(f->pin_z);
+    if (f->pin_win) (void)hipHostFree(f->pin_win);
+    for (int i = 0; i < 2; ++i) {
+        if (f->graph_exec[i]) (void)hipGraphExecDestroy(f->graph_exec[i]);
+        if (f->graph[i]) (void)hipGraphDestroy(f->graph[i]);
+    }
     if (f->z_done) (void)hipEventDestroy(f->z_done);
     for (auto& u : f->ev_used) {
         (void)hipEventDestroy(u.second.first);
@@ -585,7 +757,7 @@ pphd_status pphd_predict(pphd_filter* f, uint32_t step)
     CHECK_HANDLE(f);
     if (f->phase != PPHD_PHASE_READY && f->phase != PPHD_PHASE_RESAMPLED)
         return fail(PPHD_ESTATE, "predict needs phase READY or RESAMPLED (have %d)", f->phase);
-    pphd_status s = f->prec == PPHD_FP64 ? run_predict<double>(f, step) : run_predict<float>(f, step);
+    pphd_status s = f->prec == PPHD_FP64 ? run_predict<double>(f, step, nullptr) : run_predict<float>(f, step, nullptr);
     if (s != PPHD_OK) return s;
     f->last_step = step;
     f->births_pending = f->model.birth_proposal != 0;
@@ -596,6 +768,7 @@ pphd_status pphd_predict(pphd_filter* f, uint32_t step)
 pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on_device)
 {
     CHECK_HANDLE(f);
+    if (f->batch) return fail(PPHD_EINVAL, "a batch is updated with pphd_batch_update");
     if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "update needs phase PREDICTED (have %d)", f->phase);
     if (m < 0 || m > f->max_meas) return fail(PPHD_EINVAL, "m = %d outside [0, %d]", m, f->max_meas);
     if (m > 0 && !z) return fail(PPHD_EINVAL, "z is NULL");
@@ -618,7 +791,7 @@ pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on
             f->z_pending = true;
         }
     }
-    pphd_status s = dispatch_update(f, dz, m);
+    pphd_status s = dispatch_update(f, UpdArgs{ dz, m, nullptr, m, nullptr });
     if (s != PPHD_OK) return s;
     f->last_m = m;
     f->phase = PPHD_PHASE_UPDATED;
@@ -631,8 +804,9 @@ pphd_status pphd_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t ca
     if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
         return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
     if (!d_n_out || (cap > 0 && !d_out) || cap < 0) return fail(PPHD_EINVAL, "bad output buffers");
+    if (f->batch) return fail(PPHD_EINVAL, "a batch's estimates come from pphd_batch_extract(_device)");
     static_assert(sizeof(pphd_estimate) == sizeof(EstimateRec), "record layout");
-    return run_fuse(f, (EstimateRec*)d_out, cap, d_n_out);
+    return run_fuse(f, (EstimateRec*)d_out, cap, d_n_out, f->last_m, nullptr);
 }
 
 pphd_status pphd_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out, double* mass)
@@ -641,7 +815,8 @@ pphd_status pphd_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_
     if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
         return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
     if (!n_out || (cap > 0 && !out) || cap < 0) return fail(PPHD_EINVAL, "bad output buffers");
-    pphd_status s = run_fuse(f, f->est, f->max_meas, f->nest);
+    if (f->batch) return fail(PPHD_EINVAL, "a batch's estimates come from pphd_batch_extract(_device)");
+    pphd_status s = run_fuse(f, f->est, f->max_meas, f->nest, f->last_m, nullptr);
     if (s != PPHD_OK) return s;
     int n = 0;
     HIP_TRY(hipMemcpyAsync(&n, f->nest, 4, hipMemcpyDeviceToHost, f->stream));
@@ -657,7 +832,8 @@ pphd_status pphd_resample(pphd_filter* f, uint32_t step)
 {
     CHECK_HANDLE(f);
     if (f->phase != PPHD_PHASE_UPDATED) return fail(PPHD_ESTATE, "resample needs phase UPDATED (have %d)", f->phase);
-    pphd_status s = f->prec == PPHD_FP64 ? run_resample<double>(f, step) : run_resample<float>(f, step);
+    pphd_status s =
+        f->prec == PPHD_FP64 ? run_resample<double>(f, step, nullptr) : run_resample<float>(f, step, nullptr);
     if (s != PPHD_OK) return s;
     f->phase = PPHD_PHASE_RESAMPLED;
     return PPHD_OK;
@@ -667,7 +843,8 @@ pphd_status pphd_exchange(pphd_filter* f, uint32_t step)
 {
     CHECK_HANDLE(f);
     if (f->phase != PPHD_PHASE_RESAMPLED) return fail(PPHD_ESTATE, "exchange needs phase RESAMPLED (have %d)", f->phase);
-    pphd_status s = f->prec == PPHD_FP64 ? run_exchange<double>(f, step) : run_exchange<float>(f, step);
+    pphd_status s =
+        f->prec == PPHD_FP64 ? run_exchange<double>(f, step, nullptr) : run_exchange<float>(f, step, nullptr);
     if (s != PPHD_OK) return s;
     f->phase = PPHD_PHASE_READY;
     return PPHD_OK;
@@ -714,9 +891,8 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
     for (int j = 0; j < f->K; ++j)
         if (count[j] < 0 || count[j] > f->cap) return fail(PPHD_EINVAL, "count[%d] = %d outside [0, cap]", j, count[j]);
     if (phase == PPHD_PHASE_READY || phase == PPHD_PHASE_RESAMPLED) {
-        const int Jj0 = f->dm.J / f->K + (f->dm.J % f->K ? 1 : 0);
         for (int j = 0; j < f->K; ++j)
-            if (count[j] + Jj0 > f->cap) return fail(PPHD_EINVAL, "count[%d] leaves no room for births", j);
+            if (count[j] + f->hgd[j].Jj > f->cap) return fail(PPHD_EINVAL, "count[%d] leaves no room for births", j);
     }
     HIP_TRY(hipStreamSynchronize(f->stream));
     std::vector<float> tmp;
@@ -771,6 +947,7 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
 pphd_status pphd_read_update(pphd_filter* f, double* C, double* dW, double* mass, int32_t* LT)
 {
     CHECK_HANDLE(f);
+    if (f->batch) return fail(PPHD_EINVAL, "not available for a batch");
     if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
         return fail(PPHD_ESTATE, "no update results (phase %d)", f->phase);
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -787,6 +964,7 @@ pphd_status pphd_read_update(pphd_filter* f, double* C, double* dW, double* mass
 pphd_status pphd_read_local(pphd_filter* f, int32_t* sel, double* zeta)
 {
     CHECK_HANDLE(f);
+    if (f->batch) return fail(PPHD_EINVAL, "not available for a batch");
     if (f->phase != PPHD_PHASE_UPDATED || f->last_m < 0)
         return fail(PPHD_ESTATE, "no update results (phase %d)", f->phase);
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -880,6 +1058,184 @@ pphd_status pphd_read_timing(pphd_filter* f, double* ms, int64_t* launches)
 
 }  // extern "C"
 
+namespace {
+
+pphd_status batch_windows(pphd_filter* f, const int32_t* dwin, int z_count)
+{
+    LAUNCH(f, PPHD_K_FINALIZE,
+           hipLaunchKernelGGL(k_batch_windows, dim3((f->nruns + 255) / 256), dim3(256), 0, f->stream, dwin, f->nruns,
+                              z_count, f->max_meas, f->win));
+    return PPHD_OK;
+}
+
+template <typename T>
+pphd_status step_all(pphd_filter* f, const double* dz, int z_count, const int32_t* dwin, EstimateRec* out, int cap,
+                     int* nout)
+{
+    // one whole step with every kernel reading the step index from the device counter
+    pphd_status s = run_predict<T>(f, 0, f->dstep);
+    if (s != PPHD_OK) return s;
+    f->births_pending = f->model.birth_proposal != 0;
+    s = batch_windows(f, dwin, z_count);
+    if (s != PPHD_OK) return s;
+    s = dispatch_update(f, UpdArgs{ dz, 0, f->win, z_count, f->dstep });
+    if (s != PPHD_OK) return s;
+    s = run_fuse(f, out, cap, nout, 0, f->win);
+    if (s != PPHD_OK) return s;
+    s = run_resample<T>(f, 0, f->dstep);
+    if (s != PPHD_OK) return s;
+    s = run_exchange<T>(f, 0, f->dstep);
+    if (s != PPHD_OK) return s;
+    LAUNCH(f, PPHD_K_FINALIZE, hipLaunchKernelGGL(k_step_next, dim3(1), dim3(64), 0, f->stream, f->dstep));
+    return PPHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pphd_status pphd_batch_update(pphd_filter* f, const double* z, int32_t z_count, const int32_t* windows,
+                              int32_t on_device)
+{
+    CHECK_HANDLE(f);
+    if (!f->batch) return fail(PPHD_EINVAL, "not a batch (use pphd_update)");
+    if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "update needs phase PREDICTED (have %d)", f->phase);
+    if (z_count < 0 || z_count > f->z_cap) return fail(PPHD_EINVAL, "z_count = %d outside [0, %d]", z_count, f->z_cap);
+    if (!windows || (z_count > 0 && !z)) return fail(PPHD_EINVAL, "z and windows are required");
+    if (f->z_pending) HIP_TRY(hipEventSynchronize(f->z_done));
+    const int32_t* dwin = windows;
+    if (!on_device) {
+        for (int r = 0; r < f->nruns; ++r) {
+            const int32_t off = windows[2 * r], cnt = windows[2 * r + 1];
+            if (off < 0 || cnt < 0 || cnt > f->max_meas || (int64_t)off + cnt > z_count)
+                return fail(PPHD_EINVAL, "window of run %d (offset %d, count %d) outside the set", r, off, cnt);
+        }
+        std::memcpy(f->pin_win, windows, (size_t)f->nruns * 8);
+        HIP_TRY(hipMemcpyAsync(f->uwin, f->pin_win, (size_t)f->nruns * 8, hipMemcpyHostToDevice, f->stream));
+        dwin = f->uwin;
+    }
+    const double* dz = f->zbuf;
+    if (z_count > 0) {
+        if (on_device) {
+            dz = z;
+        } else {
+            std::memcpy(f->pin_z, z, (size_t)z_count * 16);
+            HIP_TRY(hipMemcpyAsync(f->zbuf, f->pin_z, (size_t)z_count * 16, hipMemcpyHostToDevice, f->stream));
+        }
+    }
+    if (!on_device) {
+        HIP_TRY(hipEventRecord(f->z_done, f->stream));
+        f->z_pending = true;
+    }
+    pphd_status s = batch_windows(f, dwin, z_count);
+    if (s != PPHD_OK) return s;
+    s = dispatch_update(f, UpdArgs{ dz, 0, f->win, z_count, nullptr });
+    if (s != PPHD_OK) return s;
+    f->last_m = -2;  // per-run counts live in the windows
+    f->phase = PPHD_PHASE_UPDATED;
+    return PPHD_OK;
+}
+
+pphd_status pphd_batch_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t cap, int32_t* d_n_out)
+{
+    CHECK_HANDLE(f);
+    if (!f->batch) return fail(PPHD_EINVAL, "not a batch (use pphd_extract_device)");
+    if (f->phase != PPHD_PHASE_UPDATED || f->last_m != -2)
+        return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
+    if (!d_n_out || !d_out || cap < 1) return fail(PPHD_EINVAL, "bad output buffers");
+    return run_fuse(f, (EstimateRec*)d_out, cap, d_n_out, 0, f->win);
+}
+
+pphd_status pphd_batch_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out, double* mass)
+{
+    CHECK_HANDLE(f);
+    if (!f->batch) return fail(PPHD_EINVAL, "not a batch (use pphd_extract)");
+    if (f->phase != PPHD_PHASE_UPDATED || f->last_m != -2)
+        return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
+    if (!n_out || !out || cap < 1) return fail(PPHD_EINVAL, "bad output buffers");
+    pphd_status s = run_fuse(f, f->est, f->max_meas, f->nest, 0, f->win);
+    if (s != PPHD_OK) return s;
+    std::vector<int> n(f->nruns);
+    HIP_TRY(hipMemcpyAsync(n.data(), f->nest, (size_t)f->nruns * 4, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    for (int r = 0; r < f->nruns; ++r) {
+        const int k = std::min(n[r], std::min(cap, f->max_meas));
+        if (k > 0)
+            HIP_TRY(hipMemcpy(out + (size_t)r * cap, f->est + (size_t)r * f->max_meas, (size_t)k * sizeof(pphd_estimate),
+                              hipMemcpyDeviceToHost));
+        n_out[r] = k;
+    }
+    if (mass) HIP_TRY(hipMemcpy(mass, f->fmass, (size_t)f->K * 8, hipMemcpyDeviceToHost));
+    return PPHD_OK;
+}
+
+pphd_status pphd_batch_capture(pphd_filter* f, const double* d_z, int32_t z_count, const int32_t* d_windows,
+                               pphd_estimate* d_out, int32_t cap, int32_t* d_n_out, uint32_t first_step)
+{
+    CHECK_HANDLE(f);
+    if (!f->batch) return fail(PPHD_EINVAL, "not a batch");
+    if (f->phase != PPHD_PHASE_READY && f->phase != PPHD_PHASE_RESAMPLED)
+        return fail(PPHD_ESTATE, "capture needs phase READY or RESAMPLED (have %d)", f->phase);
+    if (f->timing) return fail(PPHD_ESTATE, "disable timing before capturing");
+    if (z_count < 0 || z_count > f->z_cap) return fail(PPHD_EINVAL, "z_count = %d outside [0, %d]", z_count, f->z_cap);
+    if (!d_windows || !d_out || !d_n_out || cap < 1 || (z_count > 0 && !d_z))
+        return fail(PPHD_EINVAL, "bad buffers");
+    if (f->z_pending) HIP_TRY(hipEventSynchronize(f->z_done));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    HIP_TRY(hipMemcpy(f->dstep, &first_step, 4, hipMemcpyHostToDevice));
+    for (int i = 0; i < 2; ++i) {
+        if (f->graph_exec[i]) (void)hipGraphExecDestroy(f->graph_exec[i]);
+        if (f->graph[i]) (void)hipGraphDestroy(f->graph[i]);
+        f->graph_exec[i] = nullptr;
+        f->graph[i] = nullptr;
+    }
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipStream_t user = f->stream;
+    const int cur0 = f->cur;
+    pphd_status s = PPHD_OK;
+    for (int i = 0; i < 2 && s == PPHD_OK; ++i) {
+        f->cur = i;
+        f->stream = cs;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            s = fail(PPHD_EDEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+            break;
+        }
+        s = f->prec == PPHD_FP64 ? step_all<double>(f, d_z, z_count, d_windows, (EstimateRec*)d_out, cap, d_n_out)
+                                 : step_all<float>(f, d_z, z_count, d_windows, (EstimateRec*)d_out, cap, d_n_out);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (s == PPHD_OK && e != hipSuccess) s = fail(PPHD_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        if (s == PPHD_OK) {
+            f->graph[i] = g;
+            e = hipGraphInstantiate(&f->graph_exec[i], g, nullptr, nullptr, 0);
+            if (e != hipSuccess) s = fail(PPHD_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    f->stream = user;
+    f->cur = cur0;
+    f->births_pending = false;
+    (void)hipStreamDestroy(cs);
+    return s;
+}
+
+pphd_status pphd_batch_launch(pphd_filter* f)
+{
+    CHECK_HANDLE(f);
+    if (!f->batch || !f->graph_exec[0] || !f->graph_exec[1]) return fail(PPHD_ESTATE, "no captured step (pphd_batch_capture)");
+    if (f->phase != PPHD_PHASE_READY && f->phase != PPHD_PHASE_RESAMPLED)
+        return fail(PPHD_ESTATE, "launch needs phase READY or RESAMPLED (have %d)", f->phase);
+    HIP_TRY(hipGraphLaunch(f->graph_exec[f->cur], f->stream));
+    f->cur = 1 - f->cur;
+    f->phase = PPHD_PHASE_READY;
+    return PPHD_OK;
+}
+
+}  // extern "C"
+
 namespace pphd {
 pphd_status set_error(pphd_status s, const char* msg)
 {
@@ -901,7 +1257,7 @@ pphd_status pphd_attach_mlp(pphd_filter* f, pphd_mlp* h)
 pphd_status pphd_set_birth_mixture(pphd_filter* f, const float* raw, int32_t m, int32_t on_device)
 {
     CHECK_HANDLE(f);
-    if (f->model.birth_proposal != 2) return fail(PPHD_EINVAL, "the filter's birth_proposal is not 2");
+    if (f->model.birth_proposal != 2 || f->batch) return fail(PPHD_EINVAL, "the filter's birth_proposal is not 2");
     if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "set_birth_mixture needs phase PREDICTED (have %d)", f->phase);
     if (m < 0 || m > f->max_meas) return fail(PPHD_EINVAL, "m = %d outside [0, %d]", m, f->max_meas);
     if (m > 0 && !raw) return fail(PPHD_EINVAL, "raw is NULL");

@@ -50,6 +50,12 @@ class pphd_model(ctypes.Structure):
     ]
 
 
+class pphd_run_desc(ctypes.Structure):
+    _fields_ = [("partitions", ctypes.c_int32), ("births_per_step", ctypes.c_int32),
+                ("clutter_rate", ctypes.c_double), ("particles_per_target", ctypes.c_double),
+                ("run_id", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
 class pphd_mlp_config(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("dataset", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
@@ -100,6 +106,13 @@ SIGNATURES = {
     "pphd_mlp_steps": (_I32, [_P, ctypes.POINTER(_I64)]),
     "pphd_mlp_destroy": (_I32, [_P]),
     "pphd_attach_mlp": (_I32, [_P, _P]),
+    "pphd_batch_workspace_size": (_I32, [_MP, _P, _I32, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "pphd_batch_create": (_I32, [_MP, _P, _I32, _I64, _I32, _P, _SZ, _U64, _P, ctypes.POINTER(_P)]),
+    "pphd_batch_update": (_I32, [_P, _P, _I32, _P, _I32]),
+    "pphd_batch_extract": (_I32, [_P, _P, _I32, _P, _P]),
+    "pphd_batch_extract_device": (_I32, [_P, _P, _I32, _P]),
+    "pphd_batch_capture": (_I32, [_P, _P, _I32, _P, _P, _I32, _P, _U32]),
+    "pphd_batch_launch": (_I32, [_P]),
     "pphd_set_birth_mixture": (_I32, [_P, _P, _I32, _I32]),
 }
 
@@ -303,6 +316,41 @@ def pphd_set_birth_mixture(f, raw_ptr, m, on_device):
     _chk(lib().pphd_set_birth_mixture(f, raw_ptr, int(m), int(on_device)))
 
 
+def pphd_batch_workspace_size(model, runs_ptr, nruns, cap, max_meas):
+    n = _SZ(0)
+    _chk(lib().pphd_batch_workspace_size(ctypes.byref(model), runs_ptr, int(nruns), int(cap), int(max_meas),
+                                         ctypes.byref(n)))
+    return int(n.value)
+
+
+def pphd_batch_create(model, runs_ptr, nruns, cap, max_meas, workspace_ptr, workspace_bytes, seed, stream_ptr):
+    h = _P()
+    _chk(lib().pphd_batch_create(ctypes.byref(model), runs_ptr, int(nruns), int(cap), int(max_meas), workspace_ptr,
+                                 workspace_bytes, seed, stream_ptr, ctypes.byref(h)))
+    return h
+
+
+def pphd_batch_update(h, z_ptr, z_count, windows_ptr, on_device):
+    _chk(lib().pphd_batch_update(h, z_ptr, int(z_count), windows_ptr, int(on_device)))
+
+
+def pphd_batch_extract(h, out_ptr, cap, n_ptr, mass_ptr=None):
+    _chk(lib().pphd_batch_extract(h, out_ptr, int(cap), n_ptr, mass_ptr))
+
+
+def pphd_batch_extract_device(h, d_out_ptr, cap, d_n_ptr):
+    _chk(lib().pphd_batch_extract_device(h, d_out_ptr, int(cap), d_n_ptr))
+
+
+def pphd_batch_capture(h, d_z_ptr, z_count, d_windows_ptr, d_out_ptr, cap, d_n_ptr, first_step):
+    _chk(lib().pphd_batch_capture(h, d_z_ptr, int(z_count), d_windows_ptr, d_out_ptr, int(cap), d_n_ptr,
+                                  int(first_step)))
+
+
+def pphd_batch_launch(h):
+    _chk(lib().pphd_batch_launch(h))
+
+
 def pphd_last_error():
     return lib().pphd_last_error().decode()
 
@@ -469,6 +517,90 @@ class Filter:
         n = np.zeros(K_COUNT, dtype=np.int64)
         pphd_read_timing(self.h, ms.ctypes.data, n.ctypes.data)
         return {KERNEL_CLASSES[i]: (float(ms[i]), int(n[i])) for i in range(K_COUNT)}
+
+
+def run_table(runs):
+    """ctypes array of pphd_run_desc from dicts (partitions, births_per_step,
+    clutter_rate, particles_per_target, run_id)."""
+    arr = (pphd_run_desc * len(runs))()
+    for i, r in enumerate(runs):
+        arr[i].partitions = int(r["partitions"])
+        arr[i].births_per_step = int(r["births_per_step"])
+        arr[i].clutter_rate = float(r["clutter_rate"])
+        arr[i].particles_per_target = float(r["particles_per_target"])
+        arr[i].run_id = int(r["run_id"])
+        arr[i].reserved = 0
+    return arr
+
+
+class Batch(Filter):
+    """Independent runs of one model in one set of launches per stage
+    (pphd_batch_*).  Inherits the state, tuning and timing methods; the
+    update and extraction take every run's measurements at once."""
+
+    def __init__(self, params: dict, runs, precision: int, cap: int, max_meas: int, seed: int, stream=None,
+                 apply_tuning: bool = True):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.runs = [dict(r) for r in runs]
+        self.nruns = len(runs)
+        self.K = int(sum(int(r["partitions"]) for r in runs))
+        self.run_g0 = np.concatenate([[0], np.cumsum([int(r["partitions"]) for r in runs])])[:-1].astype(int)
+        self.cap = int(cap)
+        self.max_meas = int(max_meas)
+        self.precision = int(precision)
+        self.model = model_struct(dict(params, partitions=1, births_per_step=0, clutter_rate=0.0,
+                                       particles_per_target=1.0), precision)
+        self._table = run_table(runs)
+        nbytes = pphd_batch_workspace_size(self.model, ctypes.addressof(self._table), self.nruns, self.cap,
+                                           self.max_meas)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = pphd_batch_create(self.model, ctypes.addressof(self._table), self.nruns, self.cap, self.max_meas,
+                                   aligned, nbytes, int(seed), self.stream.cuda_stream)
+        self.last_m = 0
+        if apply_tuning:
+            t = load_tuning().get("fp64" if self.precision == PPHD_FP64 else "fp32")
+            if t:
+                pphd_set_tuning(self.h, t["pt_cz"], t["pt_weight"], t["meas_per_wave"])
+
+    @staticmethod
+    def pack(Zs):
+        """Concatenated sets and (offset, count) windows of a list of [m_r, 2] arrays."""
+        counts = np.array([np.asarray(z).reshape(-1, 2).shape[0] for z in Zs], dtype=np.int32)
+        offs = np.concatenate([[0], np.cumsum(counts)])[:-1].astype(np.int32)
+        z = np.concatenate([np.asarray(z, dtype=np.float64).reshape(-1, 2) for z in Zs]) if counts.sum() else \
+            np.zeros((0, 2))
+        return np.ascontiguousarray(z), np.ascontiguousarray(np.stack([offs, counts], axis=1))
+
+    def update(self, Zs):
+        """Zs: list of [m_r, 2] host arrays (one per run)."""
+        z, win = self.pack(Zs)
+        pphd_batch_update(self.h, z.ctypes.data if z.shape[0] else None, z.shape[0], win.ctypes.data, 0)
+
+    def update_device(self, dz, z_count, dwin):
+        pphd_batch_update(self.h, dz.data_ptr(), z_count, dwin.data_ptr(), 1)
+
+    def extract(self):
+        """List (per run) of estimate record arrays, and every group's mass."""
+        cap = max(self.max_meas, 1)
+        out = np.zeros(self.nruns * cap, dtype=ESTIMATE_DTYPE)
+        n = np.zeros(self.nruns, dtype=np.int32)
+        mass = np.zeros(self.K)
+        pphd_batch_extract(self.h, out.ctypes.data, cap, n.ctypes.data, mass.ctypes.data)
+        return [out[r * cap:r * cap + int(n[r])].copy() for r in range(self.nruns)], mass
+
+    def extract_device(self, d_out, d_n, cap):
+        pphd_batch_extract_device(self.h, d_out.data_ptr(), cap, d_n.data_ptr())
+
+    def capture(self, dz, z_count, dwin, d_out, cap, d_n, first_step):
+        pphd_batch_capture(self.h, dz.data_ptr(), z_count, dwin.data_ptr(), d_out.data_ptr(), cap, d_n.data_ptr(),
+                           first_step)
+
+    def launch(self):
+        pphd_batch_launch(self.h)
 
 
 class Mlp:
