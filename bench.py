@@ -44,6 +44,8 @@ def parse():
                     help="bound on the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-timing-pass", action="store_true",
                     help="skip the HIP-event pass (for profiler runs)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch workloads: skip the run-by-run comparison pass (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -73,6 +75,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = WORKLOADS[args.workload]
+    if w.get("batch"):
+        line = bench_batch(args, w)
+        print(json.dumps(line), flush=True)
+        return
     p = w["model"]
     prec = pphd.PPHD_FP32 if w["precision"] == "fp32" else pphd.PPHD_FP64
     total = args.warmup + args.steps
@@ -179,7 +185,7 @@ def main():
             "particles_per_target": float(p["particles_per_target"]),
             "mean_particles": float(np.mean(parts)) if parts else None,
             "mean_measurements": float(np.mean([Ms[k] for k in range(args.warmup + 1, total + 1)])),
-            "parallelism": "64 particle partitions on one GPU",
+            "parallelism": f"{int(p['partitions'])} particle partitions on one GPU",
         },
         "ospa_mean": float(np.mean(ospas)),
         "ospa_params": {"p": 1, "c": 100.0},
@@ -188,22 +194,7 @@ def main():
         per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
         line["kernels"] = per
         # dominant kernel: the larger of the two likelihood passes
-        dom = max(("cz", "weight"), key=lambda c: kern[c][0])
-        ms, n = kern[dom]
-        avg_s = ms / 1e3 / n
-        pairs_per_launch = float(np.mean(pairs))
-        achieved = SLOTS_PER_PAIR_EVAL * pairs_per_launch / avg_s / 1e12
-        line["roofline"] = {
-            "kernel": pphd.pphd_kernel_name(pphd.KERNEL_CLASSES.index(dom)),
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": None,
-            "avg_launch_us": avg_s * 1e6,
-            "work_per_launch": f"{pairs_per_launch:.4g} pairs x {SLOTS_PER_PAIR_EVAL} issue slots",
-        }
+        line["roofline"] = roofline(pphd, kern, float(np.mean(pairs)))
     if mlp_info is not None:
         # the same run with births from the birth density itself, same budget
         from paper_1503_03769_amd.runs import run_ospa
@@ -216,6 +207,187 @@ def main():
         theta = net.get_params().astype(np.float64) if mlp_info is not None else None
         line["cpu_baseline"] = cpu_baseline(p, w, truth, Z, seed, args.run, args.cpu_seconds, theta)
     print(json.dumps(line), flush=True)
+
+
+def roofline(pphd, kern, pairs_per_launch):
+    """The larger of the two likelihood passes against the VALU issue rate."""
+    dom = max(("cz", "weight"), key=lambda c: kern[c][0])
+    ms, n = kern[dom]
+    avg_s = ms / 1e3 / n
+    achieved = SLOTS_PER_PAIR_EVAL * pairs_per_launch / avg_s / 1e12
+    return {
+        "kernel": pphd.pphd_kernel_name(pphd.KERNEL_CLASSES.index(dom)),
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": VALU_PEAK_TOPS,
+        "unit": "TOP/s",
+        "frac": achieved / VALU_PEAK_TOPS,
+        "traffic": None,
+        "avg_launch_us": avg_s * 1e6,
+        "work_per_launch": f"{pairs_per_launch:.4g} pairs x {SLOTS_PER_PAIR_EVAL} issue slots",
+    }
+
+
+def bench_batch(args, w):
+    """Independent runs in one batch: every step is one replay of the captured
+    HIP graph (all stages of all runs); the runs' measurement sets sit in HBM
+    and are copied into the graph's input buffers on the stream."""
+    import torch
+
+    from paper_1503_03769_amd import pphd
+    from paper_1503_03769_amd.metrics import ospa, positions
+    from paper_1503_03769_amd.scenario import batch_runs, make_scenario, workload_seed
+
+    p = w["model"]
+    prec = pphd.PPHD_FP32 if w["precision"] == "fp32" else pphd.PPHD_FP64
+    total = args.warmup + args.steps
+    seed = workload_seed(w["config_index"], args.run)
+    runs, targets = batch_runs(w["n_runs"], seed)
+    R, Mx, cap = len(runs), w["max_meas"], w["cap"]
+    scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), targets[i], total, seed + 7919 * (i + 1))
+            for i, r in enumerate(runs)]
+    packs = [pphd.Batch.pack([scen[i][1][k] for i in range(R)]) for k in range(total + 1)]
+    Ms = np.array([[scen[i][1][k].shape[0] for i in range(R)] for k in range(total + 1)])
+    assert Ms.max() <= Mx
+    zdev = [torch.from_numpy(z).cuda() for z, _ in packs]
+    wdev = [torch.from_numpy(win).cuda() for _, win in packs]
+    dz = torch.zeros((R * Mx, 2), dtype=torch.float64, device="cuda")
+    dwin = torch.zeros((R, 2), dtype=torch.int32, device="cuda")
+    dout = torch.zeros((R * Mx * 40,), dtype=torch.uint8, device="cuda")
+    dn = torch.zeros(R, dtype=torch.int32, device="cuda")
+
+    def fill(k):
+        n = zdev[k].shape[0]
+        if n:
+            dz[:n].copy_(zdev[k])
+        dwin.copy_(wdev[k])
+
+    # ---- pass A: timed graph replays ----------------------------------------
+    b = pphd.Batch(p, runs, prec, cap, Mx, seed)
+    b.init()
+    b.capture(dz, R * Mx, dwin, dout, Mx, dn, 1)
+    for k in range(1, args.warmup + 1):
+        fill(k)
+        b.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup + 1, total + 1):
+        fill(k)
+        b.launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    b.close()
+    del b
+
+    kern, pairs, parts, ospas = {}, [], [], []
+    # ---- pass B: eager batch, per-kernel HIP-event times, counts, estimates --
+    g = pphd.Batch(p, runs, prec, cap, Mx, seed)
+    g.init()
+    pairs, parts = [], []
+    est_hist = torch.zeros((total + 1, R * Mx * 40), dtype=torch.uint8, device="cuda")
+    n_hist = torch.zeros((total + 1, R), dtype=torch.int32, device="cuda")
+    for k in range(1, total + 1):
+        if k == args.warmup + 1 and not args.no_timing_pass:
+            g.set_timing(True)
+        g.predict(k)
+        if k > args.warmup:
+            n = g.read_counts()
+            pairs.append(int(np.dot(n, Ms[k])))
+            parts.append(int(n.sum()))
+        g.update_device(zdev[k], zdev[k].shape[0], wdev[k])
+        g.extract_device(est_hist[k], n_hist[k], Mx)
+        g.resample(k)
+        g.exchange(k)
+    kern = g.read_timing() if not args.no_timing_pass else {}
+    g.close()
+    del g
+    nh = n_hist.cpu().numpy()
+    eh = est_hist.cpu().numpy()
+    for k in range(args.warmup + 1, total + 1):
+        for r in range(R):
+            recs = np.frombuffer(eh[k, r * Mx * 40:(r * Mx + min(int(nh[k, r]), Mx)) * 40].tobytes(),
+                                 dtype=pphd.ESTIMATE_DTYPE)
+            ospas.append(ospa(positions(recs["state"]), positions(scen[r][0][k])))
+
+    # ---- pass C: the same runs as separate filters, one after another --------
+    seq_steps = 3
+    singles = []
+    for r in (runs if not args.no_sequential else []):
+        q = dict(p, partitions=r["partitions"], births_per_step=r["births_per_step"],
+                 clutter_rate=r["clutter_rate"], particles_per_target=r["particles_per_target"])
+        singles.append(pphd.Filter(q, prec, cap, Mx, seed, r["run_id"]))
+    zsets = [[torch.from_numpy(np.ascontiguousarray(scen[i][1][k])).cuda() for k in range(seq_steps + 3)]
+             for i in range(R)]
+    one = torch.zeros(Mx * 40, dtype=torch.uint8, device="cuda")
+    n1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def seq_step(k):
+        for i, f in enumerate(singles):
+            f.predict(k)
+            f.update(zsets[i][k])
+            f.extract_device(one, n1, Mx)
+            f.resample(k)
+            f.exchange(k)
+
+    seq_ms = None
+    if singles:
+        for f in singles:
+            f.init()
+        seq_step(1)
+        seq_step(2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(3, 3 + seq_steps):
+            seq_step(k)
+        torch.cuda.synchronize()
+        seq_ms = (time.perf_counter() - t1) * 1e3 / seq_steps
+    for f in singles:
+        f.close()
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = float(sum(pairs)) / elapsed
+    line = {
+        "metric": "particle x measurement updates/sec (also filter steps/sec and OSPA) at 1 GPU",
+        "value": value,
+        "unit": "pair-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "steps_per_s": 1e3 / ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == pphd.PPHD_FP32 else "f64",
+        "data": "synthetic (seeded truth tracks, detections and Poisson clutter per run)",
+        "timed": "the captured step replayed once per step, inputs copied into its buffers on the stream",
+        "config": {
+            "workload": args.workload,
+            "runs": R,
+            "particle_budget_range": [1e4, 2e5],
+            "clutter_rate_range": [10, 100],
+            "targets_range": [1, 12],
+            "mean_particles_per_run": float(np.mean(parts)) / R,
+            "mean_measurements_per_run": float(Ms[args.warmup + 1:].mean()),
+            "launch": "one HIP-graph replay per step (every stage of every run)",
+        },
+        "ospa_mean": float(np.mean(ospas)),
+        "ospa_params": {"p": 1, "c": 100.0},
+        "sequential_single_filters_ms_per_step": seq_ms,
+        "speedup_vs_sequential": seq_ms / ms_per_step if seq_ms else None,
+    }
+    if kern:
+        per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
+        line["kernels"] = per
+        line["roofline"] = roofline(pphd, kern, float(np.mean(pairs)))
+    if args.cpu_seconds > 0:
+        r = runs[0]
+        q = dict(p, partitions=r["partitions"], births_per_step=r["births_per_step"],
+                 clutter_rate=r["clutter_rate"], particles_per_target=r["particles_per_target"])
+        cb = cpu_baseline(q, dict(w, cap=cap), scen[0][0], scen[0][1], seed, r["run_id"], args.cpu_seconds)
+        cb["sample"] = "run 0 of the batch from t = 0, " + cb["sample"].split(", ", 1)[-1]
+        line["cpu_baseline"] = cb
+    return line
 
 
 def cpu_baseline(p, w, truth, Z, seed, run, budget_s, mlp_theta=None):

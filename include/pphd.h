@@ -84,6 +84,12 @@ typedef struct {
                               /*    per-measurement mixtures (pphd_mlp.h)                 */
     int32_t reserved;         /* must be 0                                                */
     double birth_alpha;       /* proposals 1, 2: weight of gamma/m_b in the mixture, [0,1] */
+    int32_t birth_density;    /* 0: gamma/m_b = U(region) x N(0, birth_sigma_v^2 I);       */
+                              /* 1: gamma/m_b = N(birth_mean, diag(birth_std^2)), the      */
+                              /*    Gaussian birth intensity of section 4 (proposal 0 only) */
+    int32_t reserved2;        /* must be 0                                                */
+    double birth_mean[4];     /* density 1: mean of [x, vx, y, vy]                        */
+    double birth_std[4];      /* density 1: standard deviations (> 0)                     */
 } pphd_model;
 
 /* One fused (global) estimate: the mean of the local estimates that carry the

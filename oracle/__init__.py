@@ -40,6 +40,8 @@ class OrcModel(ctypes.Structure):
         ("birth_sigma_v", ctypes.c_double), ("init_mass", ctypes.c_double),
         ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
         ("birth_proposal", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
+        ("birth_density", ctypes.c_int32), ("reserved3", ctypes.c_int32),
+        ("birth_mean", ctypes.c_double * 4), ("birth_std", ctypes.c_double * 4),
     ]
 
 
@@ -56,6 +58,10 @@ def model_struct(p: dict) -> OrcModel:
         m.region[i] = float(p["region"][i])
     m.birth_proposal = int(p.get("birth_proposal", 0))
     m.birth_alpha = float(p.get("birth_alpha", 1.0))
+    m.birth_density = int(p.get("birth_density", 0))
+    for i in range(4):
+        m.birth_mean[i] = float(p.get("birth_mean", (0.0,) * 4)[i])
+        m.birth_std[i] = float(p.get("birth_std", (1.0,) * 4)[i])
     return m
 
 

@@ -114,9 +114,10 @@ double orc_likelihood(const orc_model* m, double zr, double zth, double x, doubl
 }
 
 /* Draw one particle from the normalised birth density gamma/m_b:
- * position uniform over the surveillance region, velocity N(0, sigma_v^2 I).
- * Reading: a uniform birth density stands in for the paper's Gaussian one,
- * whose mass the paper does not state. */
+ * position uniform over the surveillance region, velocity N(0, sigma_v^2 I)
+ * (birth_density 0; reading: a uniform birth density stands in for the
+ * paper's Gaussian one on the large workloads), or the Gaussian N(x_bar, Q)
+ * of section 4 with diagonal Q (birth_density 1). */
 static void orc_draw_birth(const orc_model* m, uint64_t seed, uint32_t c0, uint32_t step,
                            uint32_t purpose, uint32_t run, double s[4])
 {
@@ -126,6 +127,17 @@ static void orc_draw_birth(const orc_model* m, uint64_t seed, uint32_t c0, uint3
     double ux = orc_u53(a[0], a[1]), uy = orc_u53(a[2], a[3]);
     double n1, n2;
     orc_normal_pair(orc_u53(b[0], b[1]), orc_u53(b[2], b[3]), &n1, &n2);
+    if (m->birth_density == 1) {
+        /* the paper's Gaussian birth intensity (section 4): position normals
+         * from the first block, velocity normals from the second */
+        double p1, p2;
+        orc_normal_pair(ux, uy, &p1, &p2);
+        s[0] = m->birth_mean[0] + m->birth_std[0] * p1;
+        s[1] = m->birth_mean[1] + m->birth_std[1] * n1;
+        s[2] = m->birth_mean[2] + m->birth_std[2] * p2;
+        s[3] = m->birth_mean[3] + m->birth_std[3] * n2;
+        return;
+    }
     s[0] = m->region[0] + ux * (m->region[1] - m->region[0]);
     s[1] = m->birth_sigma_v * n1;
     s[2] = m->region[2] + uy * (m->region[3] - m->region[2]);

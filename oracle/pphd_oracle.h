@@ -40,6 +40,10 @@ typedef struct {
                                  2: learned per-measurement Gaussian mixtures */
     int32_t reserved2;
     double birth_alpha;       /* weight of gamma/m_b in the mixture (proposal 1) */
+    int32_t birth_density;    /* 0: U(region) x N(0, sigma_v^2 I);  1: N(birth_mean, diag(birth_std^2)) */
+    int32_t reserved3;
+    double birth_mean[4];
+    double birth_std[4];
 } orc_model;
 
 enum { ORC_INIT = 1, ORC_PREDICT = 2, ORC_BIRTH = 3, ORC_RESAMPLE = 4, ORC_EXCHANGE = 5, ORC_PAIRS = 6 };

@@ -1,11 +1,12 @@
 """Tile-shape autotuner for the two likelihood passes of pphd_update.
 
 For every tile shape (particles per thread of the C(z) pass and of the weight
-pass, measurements per wavefront) it runs the named workload from t = 0 and
+pass, measurements per wavefront) it runs the named workload (a single filter
+or a batch of runs) from t = 0 and
 averages the passes' HIP-event times (k_cz + k_weight + k_wfinal) over a
 window of steady-state steps.  The fastest shape is written to tuning.json
-next to this file, keyed by storage precision; `pphd.Filter` applies it by
-default.  The shape changes only floating-point summation order.
+next to this file, keyed by storage precision (and "_batch" for batches);
+`pphd.Filter` and `pphd.Batch` apply it by default.  The shape changes only floating-point summation order.
 
     python -m paper_1503_03769_amd.autotune [--workload NAME] [--steps A B]
 """
@@ -30,23 +31,44 @@ def tune(workload: str, first: int, last: int, verbose: bool = True):
     from . import pphd
     from .scenario import WORKLOADS, make_scenario, workload_seed
 
+    from .scenario import batch_runs
+
     w = WORKLOADS[workload]
     p = w["model"]
     prec_name = w["precision"]
     prec = pphd.PPHD_FP32 if prec_name == "fp32" else pphd.PPHD_FP64
     seed = workload_seed(w["config_index"], 0)
-    truth, Z = make_scenario(p, w["n_targets"], last, seed)
-    zdev = [None] + [torch.from_numpy(np.ascontiguousarray(Z[k])).cuda() for k in range(1, last + 1)]
+    if w.get("batch"):
+        runs, targets = batch_runs(w["n_runs"], seed)
+        scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), targets[i], last, seed + 7919 * (i + 1))
+                for i, r in enumerate(runs)]
+        packs = [None] + [pphd.Batch.pack([scen[i][1][k] for i in range(len(runs))]) for k in range(1, last + 1)]
+        zdev = [None] + [(torch.from_numpy(z).cuda(), torch.from_numpy(win).cuda()) for z, win in packs[1:]]
+
+        def make():
+            return pphd.Batch(p, runs, prec, w["cap"], w["max_meas"], seed, apply_tuning=False)
+
+        def update(f, k):
+            f.update_device(zdev[k][0], zdev[k][0].shape[0], zdev[k][1])
+    else:
+        truth, Z = make_scenario(p, w["n_targets"], last, seed)
+        zdev = [None] + [torch.from_numpy(np.ascontiguousarray(Z[k])).cuda() for k in range(1, last + 1)]
+
+        def make():
+            return pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, 0, apply_tuning=False)
+
+        def update(f, k):
+            f.update(zdev[k])
     results = []
     for pt1, pt2, mz in itertools.product(SHAPES[prec_name], SHAPES[prec_name], MEAS_PER_WAVE):
-        f = pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, 0, apply_tuning=False)
+        f = make()
         f.set_tuning(pt1, pt2, mz)
         f.init()
         for k in range(1, last + 1):
             if k == first:
                 f.set_timing(True)
             f.predict(k)
-            f.update(zdev[k])
+            update(f, k)
             f.resample(k)
             f.exchange(k)
         t = f.read_timing()
@@ -75,7 +97,8 @@ def main():
         with open(args.out) as fh:
             data = json.load(fh)
     from .scenario import WORKLOADS
-    data[WORKLOADS[args.workload]["precision"]] = best
+    w = WORKLOADS[args.workload]
+    data[w["precision"] + ("_batch" if w.get("batch") else "")] = best
     with open(args.out, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     print(json.dumps(best), flush=True)

@@ -25,8 +25,9 @@ struct DevModel {
     double birth_mass, reg0, reg1, reg2, reg3, sigma_v, init_mass, Rj, xfrac;
     double cr, ct, period, inv_period, wscale;  // scaled likelihood, see above
     double sigma_r, sigma_th, inv_area, alpha;  // measurement-driven birth proposal
-    int K, J, cap, M0, proposal, pad2;
+    int K, J, cap, M0, proposal, density;  // density: birth density option (1 = Gaussian)
     uint32_t key0, key1, run, pad;
+    double bmean[4], bstd[4];              // Gaussian birth density
 };
 
 template <typename T>
@@ -156,7 +157,7 @@ __device__ __forceinline__ double wave_incl_scan(double v)
 
 // ---------------------------------------------------------------------------
 // draws from the normalised birth density: position uniform over the region,
-// velocity N(0, sigma_v^2 I)
+// velocity N(0, sigma_v^2 I); or (density 1) the Gaussian N(mean, diag std^2)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void draw_birth(const DevModel& m, uint32_t slot, uint32_t step, uint32_t purpose,
                                            uint32_t run, double s[4])
@@ -166,6 +167,16 @@ __device__ __forceinline__ void draw_birth(const DevModel& m, uint32_t slot, uin
     double ux = uniform53(a.a, a.b), uy = uniform53(a.c, a.d);
     double n1, n2;
     normal_pair(uniform53(b.a, b.b), uniform53(b.c, b.d), n1, n2);
+    if (m.density == 1) {
+        // Gaussian birth intensity: position normals from the first block
+        double p1, p2;
+        normal_pair(ux, uy, p1, p2);
+        s[0] = m.bmean[0] + m.bstd[0] * p1;
+        s[1] = m.bmean[1] + m.bstd[1] * n1;
+        s[2] = m.bmean[2] + m.bstd[2] * p2;
+        s[3] = m.bmean[3] + m.bstd[3] * n2;
+        return;
+    }
     s[0] = m.reg0 + ux * (m.reg1 - m.reg0);
     s[1] = m.sigma_v * n1;
     s[2] = m.reg2 + uy * (m.reg3 - m.reg2);
@@ -376,7 +387,8 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
 // Draws per slot: position uniforms (sub 0), velocity normals (sub 1), the
 // choice of measurement and component (sub 2) and the two position normals of
 // a Gaussian component (sub 3).  Weight gamma(x) / (J_j q(x)), gamma(x) =
-// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).  grid (ceil(J_max/256), K).
+// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).  grid (ceil(J_max/4), K), one
+// wavefront per birth.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double normal_pdf(double d, double sigma)
 {
@@ -390,9 +402,12 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __rest
                                                    int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
                                                    const uint32_t* __restrict__ dstep)
 {
+    // one wavefront per birth: every lane draws the same particle, the lanes
+    // split the 4 M mixture terms of its proposal density
     const int j = blockIdx.y;
     const Grp gr = gd[j];
-    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.x * 4 + wave_in_block();
+    const int lane = threadIdx.x & 63;
     const int Jj = gr.Jj;
     if (b >= Jj) return;
     const uint32_t step = step_of(step_arg, dstep);
@@ -444,25 +459,28 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __rest
         double q = bd;
         if (M > 0) {
             double mix = 0.0;
-            for (int p = 0; p < M * 4; ++p) {
+            for (int p = lane; p < M * 4; p += 64) {
                 const double* t = tab + (size_t)p * MIX_TAB;
                 const double d0 = (x[0] - t[4]) * t[12], d1 = (x[1] - t[5]) * t[13];
                 const double d2 = (x[2] - t[6]) * t[14], d3 = (x[3] - t[7]) * t[15];
                 mix += neg_exp(0.5 * (d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3) - t[2], T(0));
             }
+            mix = wave_sum(mix);
             q = m.alpha * bd + (1.0 - m.alpha) * mix / (double)M;
         }
         w = m.birth_mass * bd / ((double)Jj * q);
     }
-    T tx[4];
+    if (lane == 0) {
+        T tx[4];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        tx[d] = (T)x[d];
-        st.x[d][g] = tx[d];
+        for (int d = 0; d < 4; ++d) {
+            tx[d] = (T)x[d];
+            st.x[d][g] = tx[d];
+        }
+        const T tw = (T)w;
+        st.w[g] = tw;
+        store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
     }
-    const T tw = (T)w;
-    st.w[g] = tw;
-    store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
 }
 
 // scaled squared residual q(z, x) + c

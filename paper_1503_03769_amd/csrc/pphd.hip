@@ -164,6 +164,12 @@ bool model_ok(const pphd_model* m, std::string& why, bool batch = false)
     if (!(m->birth_mass >= 0) || !(m->init_mass >= 0)) { why = "masses must be >= 0"; return false; }
     if (m->birth_proposal < 0 || m->birth_proposal > 2) { why = "birth_proposal must be 0, 1 or 2"; return false; }
     if (m->birth_proposal != 0 && !(m->birth_alpha >= 0 && m->birth_alpha <= 1)) { why = "birth_alpha must be in [0,1]"; return false; }
+    if (m->birth_density != 0 && m->birth_density != 1) { why = "birth_density must be 0 or 1"; return false; }
+    if (m->birth_density == 1 && m->birth_proposal != 0) { why = "the Gaussian birth density needs birth_proposal 0"; return false; }
+    if (m->birth_density == 1)
+        for (int d = 0; d < 4; ++d)
+            if (!(m->birth_std[d] > 0)) { why = "birth_std must be > 0"; return false; }
+    if (m->reserved != 0 || m->reserved2 != 0) { why = "reserved fields must be 0"; return false; }
     if (!(m->region[1] > m->region[0]) || !(m->region[3] > m->region[2])) { why = "empty surveillance region"; return false; }
     return true;
 }
@@ -368,6 +374,11 @@ void fill_devmodel(pphd_filter* f)
     d.inv_area = 1.0 / ((m.region[1] - m.region[0]) * (m.region[3] - m.region[2]));
     d.alpha = m.birth_alpha;
     d.proposal = m.birth_proposal;
+    d.density = m.birth_density;
+    for (int k = 0; k < 4; ++k) {
+        d.bmean[k] = m.birth_mean[k];
+        d.bstd[k] = m.birth_std[k];
+    }
     d.K = f->K;  // groups over all runs
     d.J = f->Jmax;
     d.cap = f->cap;
@@ -478,7 +489,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                                       : mlp_mixture_table(f->mlp, f->stream, a.dz, rows, f->mix_tab));
             if (ms != PPHD_OK) return ms;
             LAUNCH(f, PPHD_K_BIRTH_MIX,
-                   hipLaunchKernelGGL((k_birth_mix<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm,
+                   hipLaunchKernelGGL((k_birth_mix<T>), dim3((Jmax + 3) / 4, K), dim3(256), 0, f->stream, dm,
                                       f->gd, st, geo, f->nsurv, f->mix_tab, a.M, a.win, f->last_step, a.dstep));
         }
         f->mix_preset = false;

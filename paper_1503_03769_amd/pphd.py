@@ -47,6 +47,8 @@ class pphd_model(ctypes.Structure):
         ("birth_sigma_v", ctypes.c_double), ("init_mass", ctypes.c_double),
         ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
         ("birth_proposal", ctypes.c_int32), ("reserved", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
+        ("birth_density", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+        ("birth_mean", ctypes.c_double * 4), ("birth_std", ctypes.c_double * 4),
     ]
 
 
@@ -161,6 +163,10 @@ def model_struct(p: dict, precision: int) -> pphd_model:
         m.region[i] = float(p["region"][i])
     m.birth_proposal = int(p.get("birth_proposal", 0))
     m.birth_alpha = float(p.get("birth_alpha", 1.0))
+    m.birth_density = int(p.get("birth_density", 0))
+    for i in range(4):
+        m.birth_mean[i] = float(p.get("birth_mean", (0.0,) * 4)[i])
+        m.birth_std[i] = float(p.get("birth_std", (1.0,) * 4)[i])
     return m
 
 
@@ -562,7 +568,9 @@ class Batch(Filter):
                                    aligned, nbytes, int(seed), self.stream.cuda_stream)
         self.last_m = 0
         if apply_tuning:
-            t = load_tuning().get("fp64" if self.precision == PPHD_FP64 else "fp32")
+            key = "fp64" if self.precision == PPHD_FP64 else "fp32"
+            tun = load_tuning()
+            t = tun.get(key + "_batch", tun.get(key))
             if t:
                 pphd_set_tuning(self.h, t["pt_cz"], t["pt_weight"], t["meas_per_wave"])
 

@@ -54,8 +54,93 @@ WORKLOADS = {
     "learned_fp32_10tgt": dict(
         model=dict(BASE_MODEL, clutter_rate=50.0, particles_per_target=1.98e4,
                    births_per_step=2000, partitions=16, birth_proposal=2, birth_alpha=0.1),
-        n_targets=10, steps=100, cap=32768, precision="fp32", max_meas=512, config_index=3),
+        n_targets=10, steps=100, cap=32768, precision="fp32", max_meas=512, config_index=4),
+    # 256 independent runs in one batch (see batch_runs): 1e4-2e5 particles,
+    # clutter rate 10-100 and 1-12 targets each, one group per run.
+    "batch_fp32_256runs": dict(
+        model=dict(BASE_MODEL, birth_proposal=1, birth_alpha=0.1),
+        n_runs=256, steps=40, cap=300000, precision="fp32", max_meas=192, config_index=3,
+        batch=True),
 }
+
+
+# Section 4 of the paper: 5 tracks over 50 scans, survival 0.9, detection 1,
+# Gaussian birth intensity N([0, 3, 0, -3], diag(10, 1, 10, 1)), clutter over
+# bearing [-pi/2, pi/2] x range [0, 200] m, range-bearing noise 5 m / 0.05 rad
+# (read as standard deviations), 200 particles per target and group, K = 4.
+# Values the paper leaves open: birth mass 0.1 per scan, initial mass 0.1,
+# acceleration noise 0.5 m/s^2 on both axes (the printed noise matrix does not
+# fit this state), 200 births per group and scan.
+PAPER_MODEL = dict(
+    BASE_MODEL, sigma_a=0.5, sigma_r=5.0, sigma_theta=0.05, p_S=0.9, p_D=1.0, clutter_rate=10.0,
+    r_min=0.0, r_max=200.0, th_min=-math.pi / 2, th_max=math.pi / 2, birth_mass=0.1, init_mass=0.1,
+    region=(-100.0, 300.0, -300.0, 100.0), birth_density=1, birth_mean=(0.0, 3.0, 0.0, -3.0),
+    birth_std=(math.sqrt(10.0), 1.0, math.sqrt(10.0), 1.0), partitions=4, particles_per_target=800.0,
+    births_per_step=800, birth_proposal=0, birth_alpha=1.0,
+)
+
+
+def make_paper_scenario(model: dict, steps: int, seed: int, n_targets: int = 5):
+    """Tracks in the paper's setting: target i appears at scan 1 + floor(20u),
+    drawn from the Gaussian birth intensity, moves with the CV model and
+    leaves after 20 + floor(20u') scans (or at the end); every target is
+    detected (p_D = 1 in the paper, but model["p_D"] is honoured); clutter is
+    Poisson(model["clutter_rate"]) uniform over the clutter region.  Returns
+    (truth, Z) like make_scenario."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T, sa = model["T"], model["sigma_a"]
+    mean = np.asarray(model["birth_mean"], dtype=np.float64)
+    std = np.asarray(model["birth_std"], dtype=np.float64)
+    births = [1 + int(math.floor(rng.uniform() * 20)) for _ in range(n_targets)]
+    lives = [20 + int(math.floor(rng.uniform() * 20)) for _ in range(n_targets)]
+    states = [None] * n_targets
+    truth = [np.zeros((0, 4))]
+    Z = [np.zeros((0, 2))]
+    for k in range(1, steps + 1):
+        alive = []
+        for i in range(n_targets):
+            if k < births[i] or k > births[i] + lives[i]:
+                continue
+            if k == births[i]:
+                states[i] = mean + std * rng.normal(size=4)
+            else:
+                states[i] = _cv_step(rng, states[i], T, sa)
+            alive.append(states[i].copy())
+        tk = np.array(alive).reshape(-1, 4)
+        meas = []
+        for st in tk:
+            if rng.uniform() < model["p_D"]:
+                dx, dy = st[0] - model["sensor_x"], st[2] - model["sensor_y"]
+                r = math.hypot(dx, dy) + rng.normal(0, model["sigma_r"])
+                th = math.atan2(dy, dx) + rng.normal(0, model["sigma_theta"])
+                th = (th + math.pi) % (2 * math.pi) - math.pi
+                meas.append((r, th))
+        for _ in range(rng.poisson(model["clutter_rate"])):
+            meas.append((rng.uniform(model["r_min"], model["r_max"]),
+                         rng.uniform(model["th_min"], model["th_max"])))
+        zk = np.array(meas, dtype=np.float64).reshape(-1, 2)
+        if zk.shape[0] > 1:
+            zk = zk[rng.permutation(zk.shape[0])]
+        truth.append(tk)
+        Z.append(np.ascontiguousarray(zk))
+    return truth, Z
+
+
+def batch_runs(n_runs: int, seed: int):
+    """Run table of a batch and the number of targets of each run: particle
+    budget N uniform in [1e4, 2e5], clutter rate uniform in [10, 100], 1-12
+    targets; a fifth of the budget is births, the rest R = 0.8 N / targets
+    particles per target; one group per run; run r has Philox run word r."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    runs, targets = [], []
+    for r in range(n_runs):
+        N = rng.uniform(1e4, 2e5)
+        lam = rng.uniform(10.0, 100.0)
+        n = int(rng.integers(1, 13))
+        runs.append(dict(partitions=1, births_per_step=int(round(0.2 * N)), clutter_rate=float(lam),
+                         particles_per_target=0.8 * N / n, run_id=r))
+        targets.append(n)
+    return runs, targets
 
 
 def workload_seed(config_index: int, run: int) -> int:

@@ -228,3 +228,20 @@ def test_call_order_and_argument_errors(gpu):
     f.resample(1)
     f.exchange(1)
     f.close()
+
+
+def test_gaussian_birth_density_matches_oracle(gpu):
+    """birth_density 1 (the section-4 Gaussian birth intensity): init and
+    predict with births against the oracle, FP64."""
+    from paper_1503_03769_amd.scenario import PAPER_MODEL
+    K, cap = 4, 2048
+    p = dict(PAPER_MODEL)
+    f = P.make_filter(p, "fp64", cap, max_meas=64)
+    f.init()
+    f.predict(1)
+    Xg, Wg, ng = f.read_state()
+    st = orc.State(K, cap)
+    orc.init(p, st, 1234, 0)
+    orc.predict(p, st, 1, 1234, 0)
+    P.check_states(Xg, Wg, ng, st, "fp64")
+    f.close()

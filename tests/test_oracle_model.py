@@ -114,3 +114,24 @@ def test_init_equal_weights(orc):
     for j in range(4):
         w = st.W[j * cap:j * cap + 250]
         assert np.all(w == 1.0 / 250)
+
+
+def test_gaussian_birth_density_moments(orc):
+    """birth_density 1: births follow N(x_bar, diag(std^2)) of section 4 and
+    each carries m_b / J_j."""
+    from paper_1503_03769_amd.scenario import PAPER_MODEL
+    p = dict(PAPER_MODEL, partitions=1, births_per_step=20000, particles_per_target=100.0)
+    st = orc.State(1, 20200)
+    st.n[0] = 100
+    orc.predict(p, st, 3, 5, 0)
+    X = st.X[:, 100:20100]
+    W = st.W[100:20100]
+    assert np.allclose(W, p["birth_mass"] / 20000, rtol=1e-15)
+    mean, std = np.array(p["birth_mean"]), np.array(p["birth_std"])
+    n = X.shape[1]
+    for d in range(4):
+        assert abs(X[d].mean() - mean[d]) < 5 * std[d] / np.sqrt(n)
+        assert abs(X[d].std() / std[d] - 1) < 0.03
+    # the four coordinates are independent
+    c = np.corrcoef(X)
+    assert np.all(np.abs(c - np.eye(4)) < 0.05)
