@@ -42,12 +42,13 @@ class OrcModel(ctypes.Structure):
         ("birth_proposal", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
         ("birth_density", ctypes.c_int32), ("reserved3", ctypes.c_int32),
         ("birth_mean", ctypes.c_double * 4), ("birth_std", ctypes.c_double * 4),
+        ("sigma_w", ctypes.c_double), ("birth_sigma_w", ctypes.c_double),
     ]
 
 
 def model_struct(p: dict) -> OrcModel:
     m = OrcModel()
-    m.dim = 4
+    m.dim = int(p.get("dim", 4))
     m.partitions = int(p["partitions"])
     m.births_per_step = int(p["births_per_step"])
     for k in ("T", "sigma_a", "sensor_x", "sensor_y", "sigma_r", "sigma_theta", "p_S", "p_D",
@@ -62,6 +63,8 @@ def model_struct(p: dict) -> OrcModel:
     for i in range(4):
         m.birth_mean[i] = float(p.get("birth_mean", (0.0,) * 4)[i])
         m.birth_std[i] = float(p.get("birth_std", (1.0,) * 4)[i])
+    m.sigma_w = float(p.get("sigma_w", 0.0))
+    m.birth_sigma_w = float(p.get("birth_sigma_w", 0.0))
     return m
 
 
@@ -145,16 +148,16 @@ def births_in_partition(p, j):
 
 
 class State:
-    """Particle state in the oracle layout: X[4][K*cap], W[K*cap], n[K]."""
+    """Particle state in the oracle layout: X[dim][K*cap], W[K*cap], n[K]."""
 
-    def __init__(self, K, cap):
+    def __init__(self, K, cap, dim=4):
         self.K, self.cap = K, cap
-        self.X = np.zeros((4, K * cap), dtype=np.float64)
+        self.X = np.zeros((dim, K * cap), dtype=np.float64)
         self.W = np.zeros(K * cap, dtype=np.float64)
         self.n = np.zeros(K, dtype=np.int32)
 
     def copy(self):
-        s = State(self.K, self.cap)
+        s = State(self.K, self.cap, self.X.shape[0])
         s.X[:] = self.X
         s.W[:] = self.W
         s.n[:] = self.n
@@ -270,7 +273,7 @@ def fuse(p, M, ext):
 
 def resample(p, st, step, seed, run):
     """Returns (new State, counts [K*cap], mass_q [K])."""
-    out = State(st.K, st.cap)
+    out = State(st.K, st.cap, st.X.shape[0])
     counts = np.zeros(st.K * st.cap, dtype=np.int32)
     mq = np.zeros(st.K)
     _check(lib().orc_resample(ctypes.byref(model_struct(p)), st.cap, step, seed, run,
@@ -309,7 +312,7 @@ class OracleFilter:
     def __init__(self, p, cap, seed, run, mlp_theta=None, mlp_hidden=128):
         self.p, self.seed, self.run = p, seed, run
         self.mlp_theta, self.mlp_hidden = mlp_theta, mlp_hidden
-        self.st = State(int(p["partitions"]), cap)
+        self.st = State(int(p["partitions"]), cap, int(p.get("dim", 4)))
         init(p, self.st, seed, run)
 
     def step(self, k, Z):

@@ -119,11 +119,20 @@ double orc_likelihood(const orc_model* m, double zr, double zth, double x, doubl
  * paper's Gaussian one on the large workloads), or the Gaussian N(x_bar, Q)
  * of section 4 with diagonal Q (birth_density 1). */
 static void orc_draw_birth(const orc_model* m, uint64_t seed, uint32_t c0, uint32_t step,
-                           uint32_t purpose, uint32_t run, double s[4])
+                           uint32_t purpose, uint32_t run, double s[5])
 {
     uint32_t a[4], b[4];
     orc_block(seed, c0, step, purpose, 0, run, a);
     orc_block(seed, c0, step, purpose, 1, run, b);
+    s[4] = 0.0;
+    if (m->dim == 5) {
+        /* turn rate N(0, birth_sigma_w^2) from a third block */
+        uint32_t c[4];
+        double w1, w2;
+        orc_block(seed, c0, step, purpose, 2, run, c);
+        orc_normal_pair(orc_u53(c[0], c[1]), orc_u53(c[2], c[3]), &w1, &w2);
+        s[4] = m->birth_sigma_w * w1;
+    }
     double ux = orc_u53(a[0], a[1]), uy = orc_u53(a[2], a[3]);
     double n1, n2;
     orc_normal_pair(orc_u53(b[0], b[1]), orc_u53(b[2], b[3]), &n1, &n2);
@@ -161,9 +170,9 @@ int orc_init(const orc_model* m, int cap, uint64_t seed, uint32_t run,
     for (int j = 0; j < K; ++j) {
         for (int s = 0; s < M0; ++s) {
             uint32_t g = (uint32_t)(j * cap + s);
-            double st[4];
+            double st[5];
             orc_draw_birth(m, seed, g, 0, ORC_INIT, run, st);
-            for (int d = 0; d < 4; ++d) XS(X, d, g) = st[d];
+            for (int d = 0; d < m->dim; ++d) XS(X, d, g) = st[d];
             /* Reading: omega_0 = 1/M generalises to init_mass / M. */
             W[g] = m->init_mass / (double)M0;
         }
@@ -202,11 +211,37 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
             v[1] *= m->sigma_a;
             double x[4], y[4];
             for (int d = 0; d < 4; ++d) x[d] = XS(X, d, g);
-            for (int a = 0; a < 4; ++a) {
-                double acc = 0.0;
-                for (int b = 0; b < 4; ++b) acc += F[a][b] * x[b];
-                for (int b = 0; b < 2; ++b) acc += G[a][b] * v[b];
-                y[a] = acc;
+            if (m->dim == 5) {
+                /* Coordinated turn at the particle's rate w (not in the paper;
+                 * the textbook model): the velocity turns by wT and the
+                 * position follows the arc, x' = x + (sin wT / w) vx -
+                 * ((1 - cos wT) / w) vy, y' = y + ((1 - cos wT) / w) vx +
+                 * (sin wT / w) vy, with the limits T and 0 at w = 0; then
+                 * the same acceleration noise as the CV model, and
+                 * w' = w + T sigma_w n. */
+                double w = XS(X, 4, g);
+                double sn = sin(w * T), cs = cos(w * T);
+                double fa = w != 0.0 ? sn / w : T;
+                double fb = w != 0.0 ? (1.0 - cs) / w : 0.0;
+                double Fc[4][4] = { { 1, fa, 0, -fb }, { 0, cs, 0, -sn }, { 0, fb, 1, fa }, { 0, sn, 0, cs } };
+                for (int a = 0; a < 4; ++a) {
+                    double acc = 0.0;
+                    for (int b = 0; b < 4; ++b) acc += Fc[a][b] * x[b];
+                    for (int b = 0; b < 2; ++b) acc += G[a][b] * v[b];
+                    y[a] = acc;
+                }
+                uint32_t r2[4];
+                double nw1, nw2;
+                orc_block(seed, g, step, ORC_PREDICT, 1, run, r2);
+                orc_normal_pair(orc_u53(r2[0], r2[1]), orc_u53(r2[2], r2[3]), &nw1, &nw2);
+                XS(X, 4, g) = w + T * m->sigma_w * nw1;
+            } else {
+                for (int a = 0; a < 4; ++a) {
+                    double acc = 0.0;
+                    for (int b = 0; b < 4; ++b) acc += F[a][b] * x[b];
+                    for (int b = 0; b < 2; ++b) acc += G[a][b] * v[b];
+                    y[a] = acc;
+                }
             }
             for (int d = 0; d < 4; ++d) XS(X, d, g) = y[d];
             W[g] = m->p_S * W[g];
@@ -217,9 +252,9 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
          * here and drawn by orc_birth_from_measurements once Z_k is known. */
         for (int b = 0; b < Jj && m->birth_proposal == 0; ++b) {
             uint32_t g = (uint32_t)(j * cap + ns + b);
-            double st[4];
+            double st[5];
             orc_draw_birth(m, seed, g, step, ORC_BIRTH, run, st);
-            for (int d = 0; d < 4; ++d) XS(X, d, g) = st[d];
+            for (int d = 0; d < m->dim; ++d) XS(X, d, g) = st[d];
             W[g] = m->birth_mass / (double)Jj;
         }
         n[j] = ns + Jj;
@@ -238,6 +273,20 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
 /* factors cancel, leaving m_b U(x) / (J_j q_pos(x)) with U the uniform       */
 /* density of the surveillance region.                                        */
 /* ------------------------------------------------------------------------ */
+
+/* dim 5: the turn rate of a birth drawn from a measurement-driven or learned
+ * proposal comes from the birth density's own N(0, birth_sigma_w^2) (block
+ * sub 4), so its density cancels in the Eq 6 weight. */
+static void orc_birth_turn_rate(const orc_model* m, uint64_t seed, uint32_t g, uint32_t step, uint32_t run,
+                                double* X, size_t KC)
+{
+    if (m->dim != 5) return;
+    uint32_t c[4];
+    double w1, w2;
+    orc_block(seed, g, step, ORC_BIRTH, 4, run, c);
+    orc_normal_pair(orc_u53(c[0], c[1]), orc_u53(c[2], c[3]), &w1, &w2);
+    XS(X, 4, g) = m->birth_sigma_w * w1;
+}
 
 static double orc_gauss(double d, double sigma)
 {
@@ -306,6 +355,7 @@ int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint
             XS(X, 1, g) = m->birth_sigma_v * n1;
             XS(X, 2, g) = y;
             XS(X, 3, g) = m->birth_sigma_v * n2;
+            orc_birth_turn_rate(m, seed, g, step, run, X, KC);
             int inside = x >= m->region[0] && x <= m->region[1] && y >= m->region[2] && y <= m->region[3];
             double q = orc_birth_proposal_density(m, Z, M, x, y);
             W[g] = inside ? m->birth_mass * (1.0 / area) / ((double)Jj * q) : 0.0;
@@ -524,7 +574,7 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
                 c += q[i];
             }
             size_t dst = base + (size_t)mm;
-            for (int d = 0; d < 4; ++d) XS(Xout, d, dst) = XS(X, d, base + i);
+            for (int d = 0; d < m->dim; ++d) XS(Xout, d, dst) = XS(X, d, base + i);
             Wout[dst] = mq / (double)L;
             counts[base + i] += 1;
         }
@@ -563,17 +613,17 @@ int orc_exchange(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
     int L = (int)floor(m->exchange_fraction * (double)nmin);
     if (L <= 0) return 0;
     size_t KC = (size_t)K * (size_t)cap;
-    double* Xs = (double*)malloc(sizeof(double) * 4 * KC);
+    double* Xs = (double*)malloc(sizeof(double) * (size_t)m->dim * KC);
     double* Ws = (double*)malloc(sizeof(double) * KC);
     if (!Xs || !Ws) { free(Xs); free(Ws); return -2; }
-    memcpy(Xs, X, sizeof(double) * 4 * KC);
+    memcpy(Xs, X, sizeof(double) * (size_t)m->dim * KC);
     memcpy(Ws, W, sizeof(double) * KC);
     for (int j = 0; j < K; ++j) {
         int jn = (j + 1) % K;
         for (int mm = 0; mm < L; ++mm) {
             size_t src = (size_t)j * cap + (size_t)orc_exchange_slot(seed, step, run, j, n[j], L, mm);
             size_t dst = (size_t)jn * cap + (size_t)orc_exchange_slot(seed, step, run, jn, n[jn], L, mm);
-            for (int d = 0; d < 4; ++d) XS(X, d, dst) = XS(Xs, d, src);
+            for (int d = 0; d < m->dim; ++d) XS(X, d, dst) = XS(Xs, d, src);
             W[dst] = Ws[src];
         }
     }
@@ -594,7 +644,7 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
                       const double* Z, int M, double* X, double* W, int32_t* n,
                       double* Wupd, double* Xout, double* Wout, int32_t* nout)
 {
-    if (m->partitions != 1) return -1;
+    if (m->partitions != 1 || m->dim != 4) return -1;
     size_t KC = (size_t)cap;
     int L0 = n[0];
     int Jk = m->births_per_step;
@@ -768,6 +818,7 @@ int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t 
                 x[3] = t[4] + t[8] * nv2;
             }
             for (int d = 0; d < 4; ++d) XS(X, d, g) = x[d];
+            orc_birth_turn_rate(m, seed, g, step, run, X, KC);
             double gam = m->birth_mass * orc_prior_density(m, x);
             W[g] = gam > 0.0 ? gam / ((double)Jj * orc_mixture_proposal_density(m, table, M, x)) : 0.0;
         }

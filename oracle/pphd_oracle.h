@@ -10,6 +10,7 @@
  *
  * State layout used by every function (all arrays owned by the caller):
  *   X : double[dim][K*cap]  component d of slot s in partition j is X[d*K*cap + j*cap + s]
+ *                           (dim = 4 or 5, the model's)
  *   W : double[K*cap]       weight of the same slot
  *   n : int32[K]            number of occupied slots of partition j (slots 0..n[j]-1)
  *
@@ -21,7 +22,8 @@
 #include <stdint.h>
 
 typedef struct {
-    int32_t dim;              /* 4: constant-velocity state [x, vx, y, vy] */
+    int32_t dim;              /* 4: constant-velocity state [x, vx, y, vy];
+                                 5: coordinated-turn state [x, vx, y, vy, omega] */
     int32_t partitions;       /* K, number of processing elements / groups */
     int32_t births_per_step;  /* J, split over the K groups */
     int32_t reserved;
@@ -44,6 +46,8 @@ typedef struct {
     int32_t reserved3;
     double birth_mean[4];
     double birth_std[4];
+    double sigma_w;           /* dim 5: turn-rate noise (rad/s per unit time) */
+    double birth_sigma_w;     /* dim 5: turn-rate spread of the birth density */
 } orc_model;
 
 enum { ORC_INIT = 1, ORC_PREDICT = 2, ORC_BIRTH = 3, ORC_RESAMPLE = 4, ORC_EXCHANGE = 5, ORC_PAIRS = 6 };
