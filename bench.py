@@ -236,16 +236,32 @@ def bench_batch(args, w):
 
     from paper_1503_03769_amd import pphd
     from paper_1503_03769_amd.metrics import ospa, positions
-    from paper_1503_03769_amd.scenario import batch_runs, make_scenario, workload_seed
+    from paper_1503_03769_amd.scenario import make_scenario, workload_runs, workload_seed
 
     p = w["model"]
     prec = pphd.PPHD_FP32 if w["precision"] == "fp32" else pphd.PPHD_FP64
     total = args.warmup + args.steps
     seed = workload_seed(w["config_index"], args.run)
-    runs, targets = batch_runs(w["n_runs"], seed)
+    runs, targets = workload_runs(w, seed)
     R, Mx, cap = len(runs), w["max_meas"], w["cap"]
-    scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), targets[i], total, seed + 7919 * (i + 1))
+    scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), targets[i], total, seed + 7919 * (i + 1),
+                          turn_sigma=w.get("turn_sigma", 0.0))
             for i, r in enumerate(runs)]
+    net, mlp_info = None, None
+    if int(p.get("birth_proposal", 0)) == 2:
+        from paper_1503_03769_amd.proposal import train_proposal
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net, losses = train_proposal(p, seed=1)
+        torch.cuda.synchronize()
+        mlp_info = {"train_s": time.perf_counter() - t0, "train_steps": int(len(losses)),
+                    "final_loss": float(np.mean(losses[-50:])), "pairs": 1 << 20}
+
+    def make_batch():
+        bb = pphd.Batch(p, runs, prec, cap, Mx, seed)
+        if net is not None:
+            bb.attach_mlp(net)
+        return bb
     packs = [pphd.Batch.pack([scen[i][1][k] for i in range(R)]) for k in range(total + 1)]
     Ms = np.array([[scen[i][1][k].shape[0] for i in range(R)] for k in range(total + 1)])
     assert Ms.max() <= Mx
@@ -263,7 +279,7 @@ def bench_batch(args, w):
         dwin.copy_(wdev[k])
 
     # ---- pass A: timed graph replays ----------------------------------------
-    b = pphd.Batch(p, runs, prec, cap, Mx, seed)
+    b = make_batch()
     b.init()
     b.capture(dz, R * Mx, dwin, dout, Mx, dn, 1)
     for k in range(1, args.warmup + 1):
@@ -280,8 +296,9 @@ def bench_batch(args, w):
     del b
 
     kern, pairs, parts, ospas = {}, [], [], []
+    group_run = np.repeat(np.arange(R), [int(r["partitions"]) for r in runs])  # run of every group
     # ---- pass B: eager batch, per-kernel HIP-event times, counts, estimates --
-    g = pphd.Batch(p, runs, prec, cap, Mx, seed)
+    g = make_batch()
     g.init()
     pairs, parts = [], []
     est_hist = torch.zeros((total + 1, R * Mx * 40), dtype=torch.uint8, device="cuda")
@@ -292,7 +309,7 @@ def bench_batch(args, w):
         g.predict(k)
         if k > args.warmup:
             n = g.read_counts()
-            pairs.append(int(np.dot(n, Ms[k])))
+            pairs.append(int(np.dot(n, Ms[k][group_run])))
             parts.append(int(n.sum()))
         g.update_device(zdev[k], zdev[k].shape[0], wdev[k])
         g.extract_device(est_hist[k], n_hist[k], Mx)
@@ -315,7 +332,10 @@ def bench_batch(args, w):
     for r in (runs if not args.no_sequential else []):
         q = dict(p, partitions=r["partitions"], births_per_step=r["births_per_step"],
                  clutter_rate=r["clutter_rate"], particles_per_target=r["particles_per_target"])
-        singles.append(pphd.Filter(q, prec, cap, Mx, seed, r["run_id"]))
+        f = pphd.Filter(q, prec, cap, Mx, seed, r["run_id"])
+        if net is not None:
+            f.attach_mlp(net)
+        singles.append(f)
     zsets = [[torch.from_numpy(np.ascontiguousarray(scen[i][1][k])).cuda() for k in range(seq_steps + 3)]
              for i in range(R)]
     one = torch.zeros(Mx * 40, dtype=torch.uint8, device="cuda")
@@ -364,9 +384,11 @@ def bench_batch(args, w):
         "config": {
             "workload": args.workload,
             "runs": R,
-            "particle_budget_range": [1e4, 2e5],
-            "clutter_rate_range": [10, 100],
-            "targets_range": [1, 12],
+            "state_dim": int(p.get("dim", 4)),
+            "groups_per_run": sorted({int(r["partitions"]) for r in runs}),
+            "clutter_rates": [float(min(r["clutter_rate"] for r in runs)), float(max(r["clutter_rate"] for r in runs))],
+            "targets": [int(min(targets)), int(max(targets))],
+            "birth_proposal": int(p.get("birth_proposal", 0)),
             "mean_particles_per_run": float(np.mean(parts)) / R,
             "mean_measurements_per_run": float(Ms[args.warmup + 1:].mean()),
             "launch": "one HIP-graph replay per step (every stage of every run)",
@@ -380,12 +402,21 @@ def bench_batch(args, w):
         per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
         line["kernels"] = per
         line["roofline"] = roofline(pphd, kern, float(np.mean(pairs)))
+    if mlp_info is not None:
+        line["learned_proposal"] = mlp_info
     if args.cpu_seconds > 0:
         r = runs[0]
-        q = dict(p, partitions=r["partitions"], births_per_step=r["births_per_step"],
-                 clutter_rate=r["clutter_rate"], particles_per_target=r["particles_per_target"])
-        cb = cpu_baseline(q, dict(w, cap=cap), scen[0][0], scen[0][1], seed, r["run_id"], args.cpu_seconds)
-        cb["sample"] = "run 0 of the batch from t = 0, " + cb["sample"].split(", ", 1)[-1]
+        # a run with many groups is sampled as 4 of its groups (same particles
+        # and births per group) so that one oracle step fits the time budget
+        Ks = min(int(r["partitions"]), 4)
+        f = Ks / float(r["partitions"])
+        q = dict(p, partitions=Ks, births_per_step=int(round(r["births_per_step"] * f)),
+                 clutter_rate=r["clutter_rate"], particles_per_target=r["particles_per_target"] * f)
+        theta = net.get_params().astype(np.float64) if net is not None else None
+        cb = cpu_baseline(q, dict(w, cap=cap), scen[0][0], scen[0][1], seed, r["run_id"], args.cpu_seconds, theta)
+        what = "run 0 of the batch" if Ks == r["partitions"] else \
+            f"{Ks} of the {r['partitions']} groups of run 0 (same particles and births per group)"
+        cb["sample"] = what + " from t = 0, " + cb["sample"].split(", ", 1)[-1]
         line["cpu_baseline"] = cb
     return line
 

@@ -58,10 +58,15 @@ typedef enum {
  * Model of one filter run (section 4 simulation model; parameters are the
  * caller's).  State is 4-D constant velocity [x, vx, y, vy]; the sensor
  * measures [range, bearing] = [|p - s|, atan2(p_y - s_y, p_x - s_x)] with
- * independent Gaussian noise.
+ * independent Gaussian noise.  State arrays of the ABI hold dim components
+ * (double[dim][K*cap]); estimates report [x, vx, y, vy].
  */
 typedef struct {
-    int32_t dim;              /* must be 4                                              */
+    int32_t dim;              /* 4: constant velocity [x, vx, y, vy] (section 4);        */
+                              /* 5: coordinated turn [x, vx, y, vy, omega] (not in the    */
+                              /*    paper): x' = x + (sin wT/w) vx - ((1-cos wT)/w) vy,   */
+                              /*    y' = y + ((1-cos wT)/w) vx + (sin wT/w) vy, the       */
+                              /*    velocity turned by wT, plus the CV acceleration noise */
     int32_t partitions;       /* K >= 1 groups (processing elements)                    */
     int32_t births_per_step;  /* J >= 0 births per step over all groups; group j gets   */
                               /* J/K, plus one when j < J mod K (Step 1, section 3.1)   */
@@ -90,6 +95,8 @@ typedef struct {
     int32_t reserved2;        /* must be 0                                                */
     double birth_mean[4];     /* density 1: mean of [x, vx, y, vy]                        */
     double birth_std[4];      /* density 1: standard deviations (> 0)                     */
+    double sigma_w;           /* dim 5: turn-rate noise, omega' = omega + T sigma_w n     */
+    double birth_sigma_w;     /* dim 5: births draw omega ~ N(0, birth_sigma_w^2)         */
 } pphd_model;
 
 /* One fused (global) estimate: the mean of the local estimates that carry the
@@ -265,7 +272,8 @@ const char* pphd_kernel_name(int32_t kernel_class);
  * order).  pphd_init, pphd_predict, pphd_resample, pphd_exchange,
  * pphd_read_state, pphd_write_state, pphd_set_tuning, pphd_set_timing and
  * pphd_destroy accept a batch handle; state arrays hold the groups of all runs
- * in run order (group g = run_g0 + j).  birth_proposal 0 and 1 only. */
+ * in run order (group g = run_g0 + j).  With birth_proposal 2 the attached
+ * network (pphd_attach_mlp) runs once over the step's concatenated set. */
 typedef struct {
     int32_t partitions;           /* K_r >= 1 groups of the run                      */
     int32_t births_per_step;      /* J_r >= 0, split over its groups as for a filter */

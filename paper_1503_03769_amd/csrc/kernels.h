@@ -28,11 +28,13 @@ struct DevModel {
     int K, J, cap, M0, proposal, density;  // density: birth density option (1 = Gaussian)
     uint32_t key0, key1, run, pad;
     double bmean[4], bstd[4];              // Gaussian birth density
+    int dim, pad3;                         // 4: CV [x, vx, y, vy]; 5: coordinated turn, + omega
+    double sigma_w, birth_sigma_w;         // turn-rate noise and birth spread (dim 5)
 };
 
 template <typename T>
 struct SoA {
-    T* x[4];
+    T* x[5];  // x[4] (the turn rate) only with dim 5
     T* w;
 };
 
@@ -160,10 +162,18 @@ __device__ __forceinline__ double wave_incl_scan(double v)
 // velocity N(0, sigma_v^2 I); or (density 1) the Gaussian N(mean, diag std^2)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void draw_birth(const DevModel& m, uint32_t slot, uint32_t step, uint32_t purpose,
-                                           uint32_t run, double s[4])
+                                           uint32_t run, double s[5])
 {
     Block4 a = rng_block(m.key0, m.key1, slot, step, purpose, 0, run);
     Block4 b = rng_block(m.key0, m.key1, slot, step, purpose, 1, run);
+    s[4] = 0.0;
+    if (m.dim == 5) {
+        // turn rate N(0, birth_sigma_w^2) from a third block
+        const Block4 c = rng_block(m.key0, m.key1, slot, step, purpose, 2, run);
+        double w1, w2;
+        normal_pair(uniform53(c.a, c.b), uniform53(c.c, c.d), w1, w2);
+        s[4] = m.birth_sigma_w * w1;
+    }
     double ux = uniform53(a.a, a.b), uy = uniform53(a.c, a.d);
     double n1, n2;
     normal_pair(uniform53(b.a, b.b), uniform53(b.c, b.d), n1, n2);
@@ -197,10 +207,9 @@ __global__ __launch_bounds__(256) void k_init(DevModel m, const Grp* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) nsurv[j] = gr.M0;
     if (s >= gr.M0) return;
     const size_t g = (size_t)j * m.cap + s;
-    double v[4];
+    double v[5];
     draw_birth(m, (uint32_t)(gr.jl * m.cap + s), 0u, RNG_INIT, gr.rng_run, v);
-#pragma unroll
-    for (int d = 0; d < 4; ++d) st.x[d][g] = (T)v[d];
+    for (int d = 0; d < m.dim; ++d) st.x[d][g] = (T)v[d];
     st.w[g] = (T)(m.init_mass / (double)gr.M0);
 }
 
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
     if (s >= total) return;
     const size_t g = (size_t)j * m.cap + s;
     const uint32_t c0 = (uint32_t)(gr.jl * m.cap + s);
-    double v[4], w;
+    double v[5], w;
     if (s < ns) {
         Block4 r = rng_block(m.key0, m.key1, c0, step, RNG_PREDICT, 0, gr.rng_run);
         double n1, n2;
@@ -256,10 +265,29 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
         const double ax = m.sigma_a * n1, ay = m.sigma_a * n2;
         const double half_t2 = m.T * m.T / 2;
         const double x = st.x[0][g], vx = st.x[1][g], y = st.x[2][g], vy = st.x[3][g];
-        v[0] = x + m.T * vx + half_t2 * ax;
-        v[1] = vx + m.T * ax;
-        v[2] = y + m.T * vy + half_t2 * ay;
-        v[3] = vy + m.T * ay;
+        if (m.dim == 5) {
+            // coordinated turn at the particle's rate: the velocity turns by
+            // omega T, the position follows the arc (limits T and 0 at omega = 0)
+            const double om = st.x[4][g];
+            double sn, cs;
+            sincos(om * m.T, &sn, &cs);
+            const double fa = om != 0.0 ? sn / om : m.T;
+            const double fb = om != 0.0 ? (1.0 - cs) / om : 0.0;
+            v[0] = x + fa * vx - fb * vy + half_t2 * ax;
+            v[1] = cs * vx - sn * vy + m.T * ax;
+            v[2] = y + fb * vx + fa * vy + half_t2 * ay;
+            v[3] = sn * vx + cs * vy + m.T * ay;
+            const Block4 r2 = rng_block(m.key0, m.key1, c0, step, RNG_PREDICT, 1, gr.rng_run);
+            double w1, w2;
+            normal_pair(uniform53(r2.a, r2.b), uniform53(r2.c, r2.d), w1, w2);
+            v[4] = om + m.T * m.sigma_w * w1;
+        } else {
+            v[0] = x + m.T * vx + half_t2 * ax;
+            v[1] = vx + m.T * ax;
+            v[2] = y + m.T * vy + half_t2 * ay;
+            v[3] = vy + m.T * ay;
+            v[4] = 0.0;
+        }
         w = m.pS * (double)st.w[g];
     } else {
         if (m.proposal != 0) return;  // drawn by k_birth_meas once Z_k is known
@@ -272,9 +300,21 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
         t[d] = (T)v[d];
         st.x[d][g] = t[d];
     }
+    if (m.dim == 5) st.x[4][g] = (T)v[4];
     const T tw = (T)w;
     st.w[g] = tw;
     store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
+}
+
+// dim 5: the turn rate of a birth drawn from a measurement-driven or learned
+// proposal comes from the birth density's N(0, birth_sigma_w^2) (block sub 4),
+// so its density cancels in the Eq 6 weight
+__device__ __forceinline__ double birth_turn_rate(const DevModel& m, uint32_t c0, uint32_t step, uint32_t run)
+{
+    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 4, run);
+    double w1, w2;
+    normal_pair(uniform53(c.a, c.b), uniform53(c.c, c.d), w1, w2);
+    return m.birth_sigma_w * w1;
 }
 
 // geometry of a state written from the host.  grid (ceil(cap/256), K)
@@ -376,6 +416,7 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
     st.x[1][g] = (T)(m.sigma_v * n1);
     st.x[2][g] = ty;
     st.x[3][g] = (T)(m.sigma_v * n2);
+    if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
     st.w[g] = tw;
     store_geometry(m, geo, g, (double)tx, (double)ty, (double)tw);
 }
@@ -477,6 +518,7 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __rest
             tx[d] = (T)x[d];
             st.x[d][g] = tx[d];
         }
+        if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
         const T tw = (T)w;
         st.w[g] = tw;
         store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
@@ -1196,7 +1238,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
 {
     __shared__ long long s_end[256];
     __shared__ long long s_first;
-    __shared__ T s_x[4][256];
+    __shared__ T s_x[5][256];
     __shared__ double s_q[3][4];
     const int j = blockIdx.y, t = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
@@ -1225,8 +1267,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         s_q[2][wv] = lane_value(qin, 63);
     }
     if (sidx < n) {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) s_x[d][tid] = in.x[d][gb + sidx];
+        for (int d = 0; d < m.dim; ++d) s_x[d][tid] = in.x[d][gb + sidx];
     }
     __syncthreads();
     const double Qd = (s_q[0][0] + s_q[0][1]) + (s_q[0][2] + s_q[0][3]);
@@ -1277,8 +1318,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
             const int mid = (lo + hi + 1) >> 1;
             if (s_end[mid - 1] <= c) lo = mid; else hi = mid - 1;
         }
-#pragma unroll
-        for (int d = 0; d < 4; ++d) out.x[d][gb + c] = s_x[d][lo];
+        for (int d = 0; d < m.dim; ++d) out.x[d][gb + c] = s_x[d][lo];
         out.w[gb + c] = (T)wc;
     }
 }
@@ -1328,10 +1368,9 @@ __global__ __launch_bounds__(256) void k_xchg_gather(DevModel m, const Grp* __re
     if (mm >= L || mm >= Lmax) return;
     const uint32_t step = step_of(step_arg, dstep);
     const size_t src = (size_t)j * m.cap + (size_t)exchange_slot(m, gr, gr.jl, nsurv[j], L, mm, step);
-    T* o = stage + ((size_t)j * Lmax + mm) * 5;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) o[d] = st.x[d][src];
-    o[4] = st.w[src];
+    T* o = stage + ((size_t)j * Lmax + mm) * 6;
+    for (int d = 0; d < m.dim; ++d) o[d] = st.x[d][src];
+    o[5] = st.w[src];
 }
 
 template <typename T>
@@ -1349,10 +1388,9 @@ __global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __r
     const int jln = (gr.jl + 1) % gr.K;
     const int jn = gr.g0 + jln;
     const size_t dst = (size_t)jn * m.cap + (size_t)exchange_slot(m, gr, jln, nsurv[jn], L, mm, step);
-    const T* o = stage + ((size_t)j * Lmax + mm) * 5;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) st.x[d][dst] = o[d];
-    st.w[dst] = o[4];
+    const T* o = stage + ((size_t)j * Lmax + mm) * 6;
+    for (int d = 0; d < m.dim; ++d) st.x[d][dst] = o[d];
+    st.w[dst] = o[5];
 }
 
 // ---------------------------------------------------------------------------

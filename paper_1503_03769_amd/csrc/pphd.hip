@@ -113,7 +113,8 @@ struct pphd_filter {
     int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0, tiles256 = 0;
     int pt1 = 0, pt2 = 0, mz = MZ_DEFAULT, wtiles_max = 0;
     // device arrays (inside the workspace)
-    void* X[2][4] = {};
+    void* X[2][5] = {};  // component arrays of the two particle sets (X[.][4] with dim 5 only)
+    int dim = 4;
     void* W[2] = {};
     int *nsurv = nullptr, *ncur = nullptr, *clampctr = nullptr;
     double* zbuf = nullptr;
@@ -151,7 +152,8 @@ namespace {
 bool model_ok(const pphd_model* m, std::string& why, bool batch = false)
 {
     if (!m) { why = "model is NULL"; return false; }
-    if (m->dim != 4) { why = "dim must be 4"; return false; }
+    if (m->dim != 4 && m->dim != 5) { why = "dim must be 4 or 5"; return false; }
+    if (m->dim == 5 && (!(m->sigma_w >= 0) || !(m->birth_sigma_w >= 0))) { why = "sigma_w, birth_sigma_w must be >= 0"; return false; }
     if (!batch && m->partitions < 1) { why = "partitions must be >= 1"; return false; }
     if (!batch && m->births_per_step < 0) { why = "births_per_step must be >= 0"; return false; }
     if (m->precision != PPHD_FP64 && m->precision != PPHD_FP32) { why = "precision must be 0 or 1"; return false; }
@@ -180,7 +182,7 @@ size_t carve(pphd_filter* f, char* base)
     Layout L;
     const size_t KC = f->KC, K = f->K, Mx = f->max_meas, es = f->esz;
     for (int b = 0; b < 2; ++b) {
-        for (int d = 0; d < 4; ++d) f->X[b][d] = L.take<char>(base, KC * es);
+        for (int d = 0; d < f->dim; ++d) f->X[b][d] = L.take<char>(base, KC * es);
         f->W[b] = L.take<char>(base, KC * es);
     }
     f->nsurv = L.take<int>(base, K * 4);
@@ -220,7 +222,7 @@ size_t carve(pphd_filter* f, char* base)
     f->tsum = L.take<double>(base, K * f->rtiles * 8);
     f->massq = L.take<double>(base, K * 8);
     f->counts = L.take<int>(base, KC * 4);
-    f->stage = L.take<char>(base, K * (size_t)f->Lmax * 5 * es);
+    f->stage = L.take<char>(base, K * (size_t)f->Lmax * 6 * es);
     if (f->model.birth_proposal == 2) {
         f->mix_tab = L.take<double>(base, (size_t)f->z_cap * 4 * MIX_TAB * 8);
         f->mix_raw = L.take<float>(base, Mx * PPHD_MLP_OUTPUTS * 4);
@@ -270,6 +272,7 @@ void set_geometry(pphd_filter* f, const pphd_model* m, const pphd_run_desc* runs
                   int32_t max_meas, bool batch)
 {
     f->model = *m;
+    f->dim = m->dim;
     f->batch = batch;
     f->nruns = nruns;
     f->runs.assign(runs, runs + nruns);
@@ -375,6 +378,9 @@ void fill_devmodel(pphd_filter* f)
     d.alpha = m.birth_alpha;
     d.proposal = m.birth_proposal;
     d.density = m.birth_density;
+    d.dim = m.dim;
+    d.sigma_w = m.sigma_w;
+    d.birth_sigma_w = m.birth_sigma_w;
     for (int k = 0; k < 4; ++k) {
         d.bmean[k] = m.birth_mean[k];
         d.bstd[k] = m.birth_std[k];
@@ -396,7 +402,7 @@ template <typename T>
 SoA<T> soa(pphd_filter* f, int b)
 {
     SoA<T> s;
-    for (int d = 0; d < 4; ++d) s.x[d] = (T*)f->X[b][d];
+    for (int d = 0; d < 5; ++d) s.x[d] = (T*)f->X[b][d];
     s.w = (T*)f->W[b];
     return s;
 }
@@ -658,7 +664,6 @@ pphd_status create_impl(const pphd_model* model, const pphd_run_desc* runs, int 
     *out = nullptr;
     if (!model_ok(model, why, batch) || !runs_ok(model, runs, nruns, why) || !sizes_ok(runs, nruns, cap, max_meas, why))
         return fail(PPHD_EINVAL, "%s", why.c_str());
-    if (batch && model->birth_proposal == 2) return fail(PPHD_EINVAL, "batches support birth_proposal 0 and 1");
     if (!workspace) return fail(PPHD_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(PPHD_EINVAL, "workspace must be 256-byte aligned");
     pphd_filter* f = new (std::nothrow) pphd_filter();
@@ -881,7 +886,7 @@ pphd_status pphd_read_state(pphd_filter* f, double* x, double* w, int32_t* count
         return PPHD_OK;
     };
     if (x)
-        for (int d = 0; d < 4; ++d) {
+        for (int d = 0; d < f->dim; ++d) {
             pphd_status s = fetch(f->X[f->cur][d], x + (size_t)d * f->KC);
             if (s != PPHD_OK) return s;
         }
@@ -917,7 +922,7 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
         }
         return PPHD_OK;
     };
-    for (int d = 0; d < 4; ++d) {
+    for (int d = 0; d < f->dim; ++d) {
         pphd_status s = put(f->X[f->cur][d], x + (size_t)d * f->KC);
         if (s != PPHD_OK) return s;
     }
@@ -1113,6 +1118,8 @@ pphd_status pphd_batch_update(pphd_filter* f, const double* z, int32_t z_count, 
     if (f->phase != PPHD_PHASE_PREDICTED) return fail(PPHD_ESTATE, "update needs phase PREDICTED (have %d)", f->phase);
     if (z_count < 0 || z_count > f->z_cap) return fail(PPHD_EINVAL, "z_count = %d outside [0, %d]", z_count, f->z_cap);
     if (!windows || (z_count > 0 && !z)) return fail(PPHD_EINVAL, "z and windows are required");
+    if (f->births_pending && f->model.birth_proposal == 2 && f->Jmax > 0 && !f->mlp)
+        return fail(PPHD_ESTATE, "birth_proposal 2 needs pphd_attach_mlp");
     if (f->z_pending) HIP_TRY(hipEventSynchronize(f->z_done));
     const int32_t* dwin = windows;
     if (!on_device) {
@@ -1191,6 +1198,8 @@ pphd_status pphd_batch_capture(pphd_filter* f, const double* d_z, int32_t z_coun
     if (z_count < 0 || z_count > f->z_cap) return fail(PPHD_EINVAL, "z_count = %d outside [0, %d]", z_count, f->z_cap);
     if (!d_windows || !d_out || !d_n_out || cap < 1 || (z_count > 0 && !d_z))
         return fail(PPHD_EINVAL, "bad buffers");
+    if (f->model.birth_proposal == 2 && f->Jmax > 0 && !f->mlp)
+        return fail(PPHD_ESTATE, "birth_proposal 2 needs pphd_attach_mlp");
     if (f->z_pending) HIP_TRY(hipEventSynchronize(f->z_done));
     HIP_TRY(hipStreamSynchronize(f->stream));
     HIP_TRY(hipMemcpy(f->dstep, &first_step, 4, hipMemcpyHostToDevice));

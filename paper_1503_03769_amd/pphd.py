@@ -49,6 +49,7 @@ class pphd_model(ctypes.Structure):
         ("birth_proposal", ctypes.c_int32), ("reserved", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
         ("birth_density", ctypes.c_int32), ("reserved2", ctypes.c_int32),
         ("birth_mean", ctypes.c_double * 4), ("birth_std", ctypes.c_double * 4),
+        ("sigma_w", ctypes.c_double), ("birth_sigma_w", ctypes.c_double),
     ]
 
 
@@ -151,7 +152,7 @@ def _ptr(a):
 
 def model_struct(p: dict, precision: int) -> pphd_model:
     m = pphd_model()
-    m.dim = 4
+    m.dim = int(p.get("dim", 4))
     m.partitions = int(p["partitions"])
     m.births_per_step = int(p["births_per_step"])
     m.precision = int(precision)
@@ -167,6 +168,8 @@ def model_struct(p: dict, precision: int) -> pphd_model:
     for i in range(4):
         m.birth_mean[i] = float(p.get("birth_mean", (0.0,) * 4)[i])
         m.birth_std[i] = float(p.get("birth_std", (1.0,) * 4)[i])
+    m.sigma_w = float(p.get("sigma_w", 0.0))
+    m.birth_sigma_w = float(p.get("birth_sigma_w", 0.0))
     return m
 
 
@@ -395,6 +398,7 @@ class Filter:
         self.cap = int(cap)
         self.max_meas = int(max_meas)
         self.precision = int(precision)
+        self.dim = int(params.get("dim", 4))
         self.model = model_struct(params, precision)
         nbytes = pphd_workspace_size(self.model, self.cap, self.max_meas)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
@@ -458,7 +462,7 @@ class Filter:
     # state access
     def read_state(self):
         KC = self.K * self.cap
-        X = np.zeros((4, KC))
+        X = np.zeros((self.dim, KC))
         W = np.zeros(KC)
         n = np.zeros(self.K, dtype=np.int32)
         pphd_read_state(self.h, X.ctypes.data, W.ctypes.data, n.ctypes.data)
@@ -473,7 +477,7 @@ class Filter:
         X = np.ascontiguousarray(X, dtype=np.float64)
         W = np.ascontiguousarray(W, dtype=np.float64)
         n = np.ascontiguousarray(n, dtype=np.int32)
-        assert X.shape == (4, self.K * self.cap) and W.shape == (self.K * self.cap,) and n.shape == (self.K,)
+        assert X.shape == (self.dim, self.K * self.cap) and W.shape == (self.K * self.cap,) and n.shape == (self.K,)
         pphd_write_state(self.h, X.ctypes.data, W.ctypes.data, n.ctypes.data, int(phase))
 
     def read_update(self):
@@ -556,6 +560,7 @@ class Batch(Filter):
         self.cap = int(cap)
         self.max_meas = int(max_meas)
         self.precision = int(precision)
+        self.dim = int(params.get("dim", 4))
         self.model = model_struct(dict(params, partitions=1, births_per_step=0, clutter_rate=0.0,
                                        particles_per_target=1.0), precision)
         self._table = run_table(runs)

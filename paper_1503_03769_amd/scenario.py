@@ -61,6 +61,16 @@ WORKLOADS = {
         model=dict(BASE_MODEL, birth_proposal=1, birth_alpha=0.1),
         n_runs=256, steps=40, cap=300000, precision="fp32", max_meas=192, config_index=3,
         batch=True),
+    # Dense stress: 16 runs of 50 targets each in one batch, clutter rate 200,
+    # the 5-D coordinated-turn state (truth targets turn at rates N(0, 0.02^2)),
+    # K = 256 groups per run, 4e6 particles at 50 targets plus 2e5 births,
+    # learned birth proposal.
+    "dense_ct_fp32_16runs": dict(
+        model=dict(BASE_MODEL, dim=5, sigma_w=0.01, birth_sigma_w=0.02, clutter_rate=200.0,
+                   particles_per_target=8.0e4, births_per_step=200000, partitions=256, birth_proposal=2,
+                   birth_alpha=0.1),
+        n_runs=16, n_targets=50, steps=30, cap=32768, precision="fp32", max_meas=320, config_index=5,
+        batch=True, turn_sigma=0.02),
 }
 
 
@@ -143,6 +153,19 @@ def batch_runs(n_runs: int, seed: int):
     return runs, targets
 
 
+def workload_runs(w: dict, seed: int):
+    """Run table and target counts of a batch workload: random budgets for
+    the many-run batch (batch_runs), identical runs (the model's own values,
+    run word r) otherwise."""
+    if "n_targets" not in w:
+        return batch_runs(w["n_runs"], seed)
+    p = w["model"]
+    runs = [dict(partitions=int(p["partitions"]), births_per_step=int(p["births_per_step"]),
+                 clutter_rate=float(p["clutter_rate"]), particles_per_target=float(p["particles_per_target"]),
+                 run_id=r) for r in range(w["n_runs"])]
+    return runs, [int(w["n_targets"])] * w["n_runs"]
+
+
 def workload_seed(config_index: int, run: int) -> int:
     return 0x5EED0000 + 1000 * int(config_index) + int(run)
 
@@ -152,6 +175,19 @@ def _cv_step(rng, s, T, sigma_a):
     x, vx, y, vy = s
     return np.array([x + T * vx + 0.5 * T * T * a[0], vx + T * a[0],
                      y + T * vy + 0.5 * T * T * a[1], vy + T * a[1]])
+
+
+def _ct_step(rng, s, T, sigma_a, w):
+    """Coordinated turn at the constant rate w plus CV acceleration noise."""
+    a = rng.normal(0.0, sigma_a, size=2)
+    x, vx, y, vy = s
+    if w != 0.0:
+        sn, cs = math.sin(w * T), math.cos(w * T)
+        fa, fb = sn / w, (1.0 - cs) / w
+    else:
+        sn, cs, fa, fb = 0.0, 1.0, T, 0.0
+    return np.array([x + fa * vx - fb * vy + 0.5 * T * T * a[0], cs * vx - sn * vy + T * a[0],
+                     y + fb * vx + fa * vy + 0.5 * T * T * a[1], sn * vx + cs * vy + T * a[1]])
 
 
 def _reflect(s, lo, hi, ip, iv):
@@ -165,12 +201,14 @@ def _reflect(s, lo, hi, ip, iv):
 
 
 def make_scenario(model: dict, n_targets: int, steps: int, seed: int, start_box=(-800.0, 800.0, -800.0, 800.0),
-                  start_sigma_v=10.0, surveillance=(-1000.0, 1000.0, -1000.0, 1000.0)):
+                  start_sigma_v=10.0, surveillance=(-1000.0, 1000.0, -1000.0, 1000.0), turn_sigma=0.0):
     """Returns (truth, Z): truth[k] is an array [n_alive, 4] and Z[k] an array
     [M_k, 2] of (range, bearing) for k = 1..steps (index 0 is unused).
     start_box / start_sigma_v: where targets appear and their velocity spread;
-    surveillance: the square targets are reflected at."""
+    surveillance: the square targets are reflected at; turn_sigma > 0: each
+    target turns at a constant rate drawn from N(0, turn_sigma^2)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    turns = rng.normal(0.0, turn_sigma, size=n_targets) if turn_sigma > 0 else np.zeros(n_targets)
     T, sa = model["T"], model["sigma_a"]
     xmin, xmax, ymin, ymax = surveillance
     births = [1 + int(math.floor(rng.uniform() * steps / 10)) for _ in range(n_targets)]
@@ -187,7 +225,10 @@ def make_scenario(model: dict, n_targets: int, steps: int, seed: int, start_box=
                 states[i] = np.array([rng.uniform(start_box[0], start_box[1]), rng.normal(0, start_sigma_v),
                                       rng.uniform(start_box[2], start_box[3]), rng.normal(0, start_sigma_v)])
             else:
-                states[i] = _cv_step(rng, states[i], T, sa)
+                if turn_sigma > 0:
+                    states[i] = _ct_step(rng, states[i], T, sa, float(turns[i]))
+                else:
+                    states[i] = _cv_step(rng, states[i], T, sa)
                 states[i] = _reflect(states[i], xmin, xmax, 0, 1)
                 states[i] = _reflect(states[i], ymin, ymax, 2, 3)
             alive.append(states[i].copy())

@@ -181,6 +181,11 @@ def test_batch_argument_errors(gpu):
     with pytest.raises(pphd.PphdError) as e:
         pphd.pphd_update(b.h, z.ctypes.data, 10, 0)
     assert e.value.code == pphd.PPHD_EINVAL
-    with pytest.raises(pphd.PphdError):
-        pphd.Batch(dict(p, birth_proposal=2), RUNS, pphd.PPHD_FP32, CAP, MAXM, SEED)
+    q = pphd.Batch(dict(p, birth_proposal=2, birth_alpha=0.1), RUNS, pphd.PPHD_FP32, CAP, MAXM, SEED)
+    q.init()
+    q.predict(1)
+    with pytest.raises(pphd.PphdError) as e:      # no network attached
+        q.update([np.zeros((0, 2))] * len(RUNS))
+    assert e.value.code == pphd.PPHD_ESTATE
+    q.close()
     b.close()
