@@ -326,8 +326,8 @@ def bench_batch(args, w):
                                  dtype=pphd.ESTIMATE_DTYPE)
             ospas.append(ospa(positions(recs["state"]), positions(scen[r][0][k])))
 
-    # ---- pass C: the same runs as separate filters, one after another --------
-    seq_steps = 3
+    # ---- pass C: the same runs as separate filters, one after another, over
+    # the same steps (the timed window is the same as pass A's) ---------------
     singles = []
     for r in (runs if not args.no_sequential else []):
         q = dict(p, partitions=r["partitions"], births_per_step=r["births_per_step"],
@@ -336,8 +336,8 @@ def bench_batch(args, w):
         if net is not None:
             f.attach_mlp(net)
         singles.append(f)
-    zsets = [[torch.from_numpy(np.ascontiguousarray(scen[i][1][k])).cuda() for k in range(seq_steps + 3)]
-             for i in range(R)]
+    zsets = [[torch.from_numpy(np.ascontiguousarray(scen[i][1][k])).cuda() for k in range(total + 1)]
+             for i in range(R)] if singles else []
     one = torch.zeros(Mx * 40, dtype=torch.uint8, device="cuda")
     n1 = torch.zeros(1, dtype=torch.int32, device="cuda")
 
@@ -353,14 +353,14 @@ def bench_batch(args, w):
     if singles:
         for f in singles:
             f.init()
-        seq_step(1)
-        seq_step(2)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for k in range(3, 3 + seq_steps):
+        for k in range(1, args.warmup + 1):
             seq_step(k)
         torch.cuda.synchronize()
-        seq_ms = (time.perf_counter() - t1) * 1e3 / seq_steps
+        t1 = time.perf_counter()
+        for k in range(args.warmup + 1, total + 1):
+            seq_step(k)
+        torch.cuda.synchronize()
+        seq_ms = (time.perf_counter() - t1) * 1e3 / args.steps
     for f in singles:
         f.close()
 

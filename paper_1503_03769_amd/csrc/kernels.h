@@ -349,6 +349,13 @@ __device__ __forceinline__ double wrap_pi(double d)
 // 2^-126 vanish, far under the mixture's alpha U floor), exp in double otherwise
 __device__ __forceinline__ double neg_exp(double a, float) { return (double)__builtin_amdgcn_exp2f((float)(-a * 1.4426950408889634)); }
 __device__ __forceinline__ double neg_exp(double a, double) { return exp(-a); }
+// exponent beyond which neg_exp returns 0 (or a denormal): e^-104 < 2^-149 in
+// float, e^-745 below the smallest double; a term whose partial exponent
+// already exceeds it is skipped without changing the sum by more than a denormal
+__device__ __forceinline__ double neg_exp_cut(float) { return 104.0; }
+__device__ __forceinline__ double neg_exp_cut(double) { return 745.0; }
+
+constexpr int BIRTH_ZCHUNK = 1024;  // measurements staged in LDS at a time by k_birth_meas
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
@@ -356,11 +363,13 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
                                                     int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
                                                     const uint32_t* __restrict__ dstep)
 {
+    __shared__ double sz[2 * BIRTH_ZCHUNK];
     const int j = blockIdx.y;
     const Grp gr = gd[j];
     const int b = blockIdx.x * 256 + threadIdx.x;
     const int Jj = gr.Jj;
-    if (b >= Jj) return;
+    if (blockIdx.x * 256 >= Jj) return;  // whole workgroup idle
+    const bool active = b < Jj;
     const uint32_t step = step_of(step_arg, dstep);
     const ZView zv = zview(gr, win, Zall, Mall);
     const double* Z = zv.Z;
@@ -395,21 +404,36 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
         const double rho = sqrt(dx * dx + dy * dy);
         const double phi = atan2(dy, dx);
         const double isr = 1.0 / m.sigma_r, ist = 1.0 / m.sigma_th;
+        const double cut = neg_exp_cut(T(0));
         double mix = 0.0;
-        for (int p = 0; p < M; ++p) {
-            const double zr = Z[2 * p], zt = Z[2 * p + 1];
-            const double er = (rho - zr) * isr, et = wrap_pi(phi - zt) * ist;
-            double t = neg_exp(0.5 * (er * er + et * et), T(0));
-            // the negative-range branch: exactly zero in double once r_p > 40 sigma_r
-            if (zr < 40.0 * m.sigma_r) {
-                const double fr = (rho + zr) * isr, ft = wrap_pi(phi + 3.14159265358979323846 - zt) * ist;
-                t += neg_exp(0.5 * (fr * fr + ft * ft), T(0));
+        // the run's measurements pass through LDS in chunks shared by the workgroup
+        for (int p0 = 0; p0 < M; p0 += BIRTH_ZCHUNK) {
+            const int pn = M - p0 < BIRTH_ZCHUNK ? M - p0 : BIRTH_ZCHUNK;
+            __syncthreads();
+            for (int i = threadIdx.x; i < 2 * pn; i += 256) sz[i] = Z[2 * p0 + i];
+            __syncthreads();
+            if (!active) continue;
+            for (int p = 0; p < pn; ++p) {
+                const double zr = sz[2 * p], zt = sz[2 * p + 1];
+                const double er = (rho - zr) * isr;
+                double t = 0.0;
+                // the range residual alone decides most far measurements
+                if (0.5 * er * er < cut) {
+                    const double et = wrap_pi(phi - zt) * ist;
+                    t = neg_exp(0.5 * (er * er + et * et), T(0));
+                }
+                // the negative-range branch: exactly zero in double once r_p > 40 sigma_r
+                if (zr < 40.0 * m.sigma_r) {
+                    const double fr = (rho + zr) * isr, ft = wrap_pi(phi + 3.14159265358979323846 - zt) * ist;
+                    t += neg_exp(0.5 * (fr * fr + ft * ft), T(0));
+                }
+                mix += t;
             }
-            mix += t;
         }
         mix *= 1.0 / (2.0 * 3.14159265358979323846 * m.sigma_r * m.sigma_th * rho);
         q = m.alpha * u + (1.0 - m.alpha) * mix / (double)M;
     }
+    if (!active) return;
     const double w = inside ? m.birth_mass * m.inv_area / ((double)Jj * q) : 0.0;
     const T tx = (T)x, ty = (T)y, tw = (T)w;
     st.x[0][g] = tx;
@@ -428,8 +452,8 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
 // Draws per slot: position uniforms (sub 0), velocity normals (sub 1), the
 // choice of measurement and component (sub 2) and the two position normals of
 // a Gaussian component (sub 3).  Weight gamma(x) / (J_j q(x)), gamma(x) =
-// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).  grid (ceil(J_max/4), K), one
-// wavefront per birth.
+// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).  grid (ceil(J_max/16), K),
+// 1024 threads, one wavefront per birth.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double normal_pdf(double d, double sigma)
 {
@@ -437,20 +461,30 @@ __device__ __forceinline__ double normal_pdf(double d, double sigma)
     return exp(-0.5 * e * e) / (2.5066282746310002 * sigma);
 }
 
+constexpr int MIX_CHUNK = 512;   // mixture-table entries staged in LDS at a time by k_birth_mix
+// groups with at least this many births per step use k_birth_mix_lanes (one
+// lane per birth); smaller ones k_birth_mix (one wavefront per birth), which
+// keeps the chip busy when births are few
+constexpr int MIX_LANES_MIN = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
-                                                   const int* __restrict__ nsurv, const double* __restrict__ taball,
-                                                   int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
-                                                   const uint32_t* __restrict__ dstep)
+__global__ __launch_bounds__(1024) void k_birth_mix(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                    const int* __restrict__ nsurv, const double* __restrict__ taball,
+                                                    int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
+                                                    const uint32_t* __restrict__ dstep)
 {
-    // one wavefront per birth: every lane draws the same particle, the lanes
-    // split the 4 M mixture terms of its proposal density
+    // one wavefront per birth, 16 per workgroup: every lane draws the same
+    // particle, the lanes split the 4 M mixture terms of its proposal density
+    // (lane l takes terms l, l + 64, ...); the table passes through LDS in
+    // chunks that the 16 births share
+    __shared__ double s_lc[MIX_CHUNK], s_mu[4][MIX_CHUNK], s_is[4][MIX_CHUNK];
     const int j = blockIdx.y;
     const Grp gr = gd[j];
-    const int b = blockIdx.x * 4 + wave_in_block();
+    const int b = blockIdx.x * 16 + wave_in_block();
     const int lane = threadIdx.x & 63;
     const int Jj = gr.Jj;
-    if (b >= Jj) return;
+    if (blockIdx.x * 16 >= Jj || Jj >= MIX_LANES_MIN) return;  // whole workgroup idle, or a lane-variant group
+    const bool active = b < Jj;         // wave-uniform
     const uint32_t step = step_of(step_arg, dstep);
     // the table rows of this run's measurements
     const double* tab = taball;
@@ -469,7 +503,7 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __rest
     normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), nv1, nv2);
     const double uc = uniform53(c.a, c.b), uk = uniform53(c.c, c.d);
     double x[4];
-    if (M == 0 || uc <= m.alpha) {
+    if (M == 0 || uc <= m.alpha || !active) {
         x[0] = m.reg0 + uniform53(a.a, a.b) * (m.reg1 - m.reg0);
         x[1] = m.sigma_v * nv1;
         x[2] = m.reg2 + uniform53(a.c, a.d) * (m.reg3 - m.reg2);
@@ -495,17 +529,38 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __rest
     }
     const bool inside = x[0] >= m.reg0 && x[0] <= m.reg1 && x[2] >= m.reg2 && x[2] <= m.reg3;
     const double bd = inside ? m.inv_area * normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v) : 0.0;
+    const bool needq = active && bd > 0.0 && M > 0;  // wave-uniform
+    const double cut = neg_exp_cut(T(0));
+    double mix = 0.0;
+    for (int e0 = 0; e0 < M * 4; e0 += MIX_CHUNK) {
+        const int en = M * 4 - e0 < MIX_CHUNK ? M * 4 - e0 : MIX_CHUNK;
+        __syncthreads();
+        for (int i = threadIdx.x; i < en; i += 1024) {
+            const double* t = tab + (size_t)(e0 + i) * MIX_TAB;
+            s_lc[i] = t[2];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                s_mu[d][i] = t[4 + d];
+                s_is[d][i] = t[12 + d];
+            }
+        }
+        __syncthreads();
+        if (!needq) continue;
+        for (int i = lane; i < en; i += 64) {
+            const double d0 = (x[0] - s_mu[0][i]) * s_is[0][i], d2 = (x[2] - s_mu[2][i]) * s_is[2][i];
+            // position part first: a far component is skipped before its exponential
+            const double ap = 0.5 * (d0 * d0 + d2 * d2) - s_lc[i];
+            if (ap < cut) {
+                const double d1 = (x[1] - s_mu[1][i]) * s_is[1][i], d3 = (x[3] - s_mu[3][i]) * s_is[3][i];
+                mix += neg_exp(ap + 0.5 * (d1 * d1 + d3 * d3), T(0));
+            }
+        }
+    }
+    if (!active) return;
     double w = 0.0;
     if (bd > 0.0) {
         double q = bd;
         if (M > 0) {
-            double mix = 0.0;
-            for (int p = lane; p < M * 4; p += 64) {
-                const double* t = tab + (size_t)p * MIX_TAB;
-                const double d0 = (x[0] - t[4]) * t[12], d1 = (x[1] - t[5]) * t[13];
-                const double d2 = (x[2] - t[6]) * t[14], d3 = (x[3] - t[7]) * t[15];
-                mix += neg_exp(0.5 * (d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3) - t[2], T(0));
-            }
             mix = wave_sum(mix);
             q = m.alpha * bd + (1.0 - m.alpha) * mix / (double)M;
         }
@@ -523,6 +578,111 @@ __global__ __launch_bounds__(256) void k_birth_mix(DevModel m, const Grp* __rest
         st.w[g] = tw;
         store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
     }
+}
+
+// The same births for groups with many of them: one lane per birth, the
+// mixture table broadcast to the lanes from LDS (every lane reads the same
+// entry), so the draws of 64 births share one instruction stream.  Terms are
+// summed in table order.  grid (ceil(J_max/256), K).
+template <typename T>
+__global__ __launch_bounds__(256) void k_birth_mix_lanes(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
+                                                         Geo geo, const int* __restrict__ nsurv,
+                                                         const double* __restrict__ taball, int Mall,
+                                                         const ZWin* __restrict__ win, uint32_t step_arg,
+                                                         const uint32_t* __restrict__ dstep)
+{
+    __shared__ double s_lc[MIX_CHUNK], s_mu[4][MIX_CHUNK], s_is[4][MIX_CHUNK];
+    const int j = blockIdx.y;
+    const Grp gr = gd[j];
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int Jj = gr.Jj;
+    if (blockIdx.x * 256 >= Jj || Jj < MIX_LANES_MIN) return;  // whole workgroup idle, or a wave-variant group
+    const bool active = b < Jj;
+    const uint32_t step = step_of(step_arg, dstep);
+    const double* tab = taball;
+    int M = Mall;
+    if (win) {
+        const ZWin w = win[gr.run];
+        tab = taball + (size_t)w.off * 4 * MIX_TAB;
+        M = w.M;
+    }
+    const size_t g = (size_t)j * m.cap + nsurv[j] + b;
+    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + nsurv[j] + b);
+    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, gr.rng_run);
+    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, gr.rng_run);
+    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, gr.rng_run);
+    double nv1, nv2;
+    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), nv1, nv2);
+    const double uc = uniform53(c.a, c.b), uk = uniform53(c.c, c.d);
+    double x[4];
+    if (M == 0 || uc <= m.alpha || !active) {
+        x[0] = m.reg0 + uniform53(a.a, a.b) * (m.reg1 - m.reg0);
+        x[1] = m.sigma_v * nv1;
+        x[2] = m.reg2 + uniform53(a.c, a.d) * (m.reg3 - m.reg2);
+        x[3] = m.sigma_v * nv2;
+    } else {
+        int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
+        p = p > M - 1 ? M - 1 : p;
+        int comp = 3;
+        for (int k = 0; k < 4; ++k) {
+            if (uk <= tab[(size_t)(p * 4 + k) * MIX_TAB + 1]) {
+                comp = k;
+                break;
+            }
+        }
+        const double* t = tab + (size_t)(p * 4 + comp) * MIX_TAB;
+        const Block4 e = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 3, gr.rng_run);
+        double e1, e2;
+        normal_pair(uniform53(e.a, e.b), uniform53(e.c, e.d), e1, e2);
+        x[0] = t[4] + t[8] * e1;
+        x[1] = t[5] + t[9] * nv1;
+        x[2] = t[6] + t[10] * e2;
+        x[3] = t[7] + t[11] * nv2;
+    }
+    const bool inside = x[0] >= m.reg0 && x[0] <= m.reg1 && x[2] >= m.reg2 && x[2] <= m.reg3;
+    const double bd = inside ? m.inv_area * normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v) : 0.0;
+    const bool needq = active && bd > 0.0;
+    const double cut = neg_exp_cut(T(0));
+    double mix = 0.0;
+    for (int e0 = 0; e0 < M * 4; e0 += MIX_CHUNK) {
+        const int en = M * 4 - e0 < MIX_CHUNK ? M * 4 - e0 : MIX_CHUNK;
+        __syncthreads();
+        for (int i = threadIdx.x; i < en; i += 256) {
+            const double* t = tab + (size_t)(e0 + i) * MIX_TAB;
+            s_lc[i] = t[2];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                s_mu[d][i] = t[4 + d];
+                s_is[d][i] = t[12 + d];
+            }
+        }
+        __syncthreads();
+        if (!needq) continue;
+        for (int i = 0; i < en; ++i) {
+            const double d0 = (x[0] - s_mu[0][i]) * s_is[0][i], d2 = (x[2] - s_mu[2][i]) * s_is[2][i];
+            const double ap = 0.5 * (d0 * d0 + d2 * d2) - s_lc[i];
+            if (ap < cut) {
+                const double d1 = (x[1] - s_mu[1][i]) * s_is[1][i], d3 = (x[3] - s_mu[3][i]) * s_is[3][i];
+                mix += neg_exp(ap + 0.5 * (d1 * d1 + d3 * d3), T(0));
+            }
+        }
+    }
+    if (!active) return;
+    double w = 0.0;
+    if (bd > 0.0) {
+        const double q = M > 0 ? m.alpha * bd + (1.0 - m.alpha) * mix / (double)M : bd;
+        w = m.birth_mass * bd / ((double)Jj * q);
+    }
+    T tx[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        tx[d] = (T)x[d];
+        st.x[d][g] = tx[d];
+    }
+    if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
+    const T tw = (T)w;
+    st.w[g] = tw;
+    store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
 }
 
 // scaled squared residual q(z, x) + c

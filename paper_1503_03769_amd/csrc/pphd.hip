@@ -494,9 +494,20 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                    ms = f->mix_preset ? mlp_head_table(f->model, f->stream, a.dz, f->mix_raw, rows, f->mix_tab)
                                       : mlp_mixture_table(f->mlp, f->stream, a.dz, rows, f->mix_tab));
             if (ms != PPHD_OK) return ms;
-            LAUNCH(f, PPHD_K_BIRTH_MIX,
-                   hipLaunchKernelGGL((k_birth_mix<T>), dim3((Jmax + 3) / 4, K), dim3(256), 0, f->stream, dm,
-                                      f->gd, st, geo, f->nsurv, f->mix_tab, a.M, a.win, f->last_step, a.dstep));
+            // a group's own birth count picks the variant, so a run draws the
+            // same births alone or in a batch
+            int jmin = Jmax;
+            for (const Grp& gg : f->hgd) jmin = std::min(jmin, gg.Jj);
+            if (jmin < MIX_LANES_MIN)
+                LAUNCH(f, PPHD_K_BIRTH_MIX,
+                       hipLaunchKernelGGL((k_birth_mix<T>), dim3((std::min(Jmax, MIX_LANES_MIN) + 15) / 16, K),
+                                          dim3(1024), 0, f->stream, dm, f->gd, st, geo, f->nsurv, f->mix_tab, a.M,
+                                          a.win, f->last_step, a.dstep));
+            if (Jmax >= MIX_LANES_MIN)
+                LAUNCH(f, PPHD_K_BIRTH_MIX,
+                       hipLaunchKernelGGL((k_birth_mix_lanes<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0,
+                                          f->stream, dm, f->gd, st, geo, f->nsurv, f->mix_tab, a.M, a.win,
+                                          f->last_step, a.dstep));
         }
         f->mix_preset = false;
         f->births_pending = false;

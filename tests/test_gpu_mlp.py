@@ -147,9 +147,9 @@ def test_training_lowers_the_loss(gpu):
     net.close()
 
 
-def _births_case(gpu, prec, M_raw_seed=3):
+def _births_case(gpu, prec, M_raw_seed=3, births=900):
     K, cap = 3, 4096
-    p = dict(BASE_MODEL, partitions=K, births_per_step=900, birth_proposal=2, birth_alpha=0.1)
+    p = dict(BASE_MODEL, partitions=K, births_per_step=births, birth_proposal=2, birth_alpha=0.1)
     truth, Z = make_scenario(p, 3, 4, 17)
     Zk = Z[4]
     raw = random_mixture_outputs(Zk.shape[0], M_raw_seed)
@@ -157,10 +157,12 @@ def _births_case(gpu, prec, M_raw_seed=3):
     return p, K, cap, Zk, raw, X, W, n
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_births_from_given_outputs_match_oracle(gpu, prec):
-    print(f"mlp: births from given outputs {prec}", flush=True)
-    p, K, cap, Zk, raw, X, W, n = _births_case(gpu, prec)
+@pytest.mark.parametrize("prec,births", [("fp64", 900), ("fp32", 900), ("fp64", 3000), ("fp32", 3000)])
+def test_births_from_given_outputs_match_oracle(gpu, prec, births):
+    """300 births per group take the one-wavefront-per-birth kernel, 1000 the
+    one-lane-per-birth kernel."""
+    print(f"mlp: births from given outputs {prec} {births}", flush=True)
+    p, K, cap, Zk, raw, X, W, n = _births_case(gpu, prec, births=births)
     f = P.make_filter(p, prec, cap)
     f.write_state(X, W, n, gpu.PHASE_READY)
     f.predict(4)
