@@ -243,8 +243,8 @@ enum {
     PPHD_K_FINALIZE = 4, PPHD_K_FUSE = 5, PPHD_K_RS_TILES = 6, PPHD_K_RS_EXPAND = 7,
     PPHD_K_XCHG_GATHER = 8, PPHD_K_XCHG_SCATTER = 9, PPHD_K_INIT = 10, PPHD_K_WMAX = 11,
     PPHD_K_GEOM = 12, PPHD_K_WFINAL = 13, PPHD_K_BIRTH = 14, PPHD_K_MLP_INFER = 15,
-    PPHD_K_BIRTH_MIX = 16,
-    PPHD_K_COUNT = 17
+    PPHD_K_BIRTH_MIX = 16, PPHD_K_ZPREP = 17,
+    PPHD_K_COUNT = 18
 };
 
 /* Enables (1) or disables (0) per-launch HIP-event timing on the filter's

@@ -867,6 +867,282 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, const Grp* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Bearing-frame passes (kappa > 0, PASS_FRAMES), measurement side prepared
+// once per update by k_zprep: each run's measurements are scaled (r c_r and
+// the frame's bearing times c_t) and stably reordered so that frame A
+// (|theta| <= pi/2) comes first.  The passes walk that order with scalar
+// (wave-uniform) loads, one select-free loop per frame, and map each entry
+// back to its original index for every per-measurement output.
+// ---------------------------------------------------------------------------
+struct ZPrep {
+    double* zs;   // [rows][2]: scaled range, scaled frame bearing, in frame order per run
+    int* orig;    // [rows]: original index of the entry within its run
+    int* pos;     // [rows]: frame-order position of original measurement p (the inverse)
+    int* nA;      // [runs]: entries of frame A
+};
+struct ZPrepC {
+    const double* zs;
+    const int* orig;
+    const int* pos;
+    const int* nA;
+};
+// per-group measurement results of the first pass again in frame order, for
+// the second pass (H, F and the candidate flag of k_cz_combine)
+template <typename T>
+struct ZSorted {
+    int* H;
+    T* F;
+    int* flag;
+};
+
+// one workgroup per run.  grid (runs), 256 threads.
+__global__ __launch_bounds__(256) void k_zprep(DevModel m, const double* __restrict__ Zall, int Mall,
+                                               const ZWin* __restrict__ win, ZPrep zp)
+{
+    __shared__ int s_cnt[4];
+    __shared__ int s_base;
+    const int run = blockIdx.x;
+    int off = 0, M = Mall;
+    if (win) {
+        off = win[run].off;
+        M = win[run].M;
+    }
+    const double* Z = Zall + 2 * (size_t)off;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // pass 1: number of frame-A measurements
+    int cA = 0;
+    for (int p = threadIdx.x; p < M; p += 256) cA += fabs(Z[2 * p + 1]) > 0.5 * 3.14159265358979323846 ? 0 : 1;
+    cA = (int)wave_sum((double)cA);
+    if (lane == 0) s_cnt[wv] = cA;
+    __syncthreads();
+    const int nA = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    if (threadIdx.x == 0) {
+        zp.nA[run] = nA;
+        s_base = 0;
+    }
+    // pass 2: stable positions, 256 measurements at a time
+    for (int p0 = 0; p0 < M; p0 += 256) {
+        __syncthreads();
+        const int p = p0 + threadIdx.x;
+        const bool valid = p < M;
+        ZFrame zf{ 0.0, 0.0, false };
+        if (valid) zf = z_frame(m, Z[2 * p], Z[2 * p + 1]);
+        const int isA = valid && !zf.b ? 1 : 0;
+        const int incl = (int)wave_incl_scan((double)isA);
+        if (lane == 63) s_cnt[wv] = incl;
+        __syncthreads();
+        int before = s_base;
+        for (int w2 = 0; w2 < wv; ++w2) before += s_cnt[w2];
+        const int exA = before + incl - isA;  // frame-A entries before p in the run
+        if (valid) {
+            const int pos = isA ? exA : nA + (p - exA);
+            zp.zs[2 * ((size_t)off + pos)] = zf.zr;
+            zp.zs[2 * ((size_t)off + pos) + 1] = zf.zt;
+            zp.orig[(size_t)off + pos] = p;
+            zp.pos[(size_t)off + p] = pos;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    }
+}
+
+// 64-lane sum left in lane 63 (other lanes hold partial sums): quad and row
+// swizzles, then the row broadcasts 15 and 31 fold rows 0-2 into row 3.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum_last(float v)
+{
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    v += dpp_rows<0x142, 0xA>(v);
+    v += dpp_rows<0x143, 0xC>(v);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_last(double v) { return wave_sum(v); }
+
+// first pass in frames: as k_cz (PASS_FRAMES), the measurement side read
+// from the prepared order
+template <typename T, int PT>
+__global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __restrict__ gd, Geo geo,
+                                                   const T* __restrict__ W, const int* __restrict__ ncur,
+                                                   int Mall, const ZWin* __restrict__ win, ZPrepC zp, int Mmax,
+                                                   Split sp, double* __restrict__ ps, int* __restrict__ ph,
+                                                   double* __restrict__ pw)
+{
+    constexpr int WT = 64 * PT;
+    const int j = blockIdx.y;
+    const Grp gr = gd[j];
+    int off = 0, M = Mall;
+    if (win) {
+        off = win[gr.run].off;
+        M = win[gr.run].M;
+    }
+    const int zsplit = zsplit_for(M, sp.mz), MZ = (M + zsplit - 1) / zsplit;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + wave_in_block();
+    const int tile = gw / zsplit, zc = gw - tile * zsplit;
+    const int n = ncur[j];
+    const int base = tile * WT;
+    if (tile >= sp.wtiles || base >= n) return;
+    const size_t gb = (size_t)j * m.cap;
+    double rho[PT], phi[PT], phib[PT], nlw[PT];
+    double lwmax = -__builtin_inf();
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int s = base + i * 64 + lane;
+        rho[i] = 0.0;
+        phi[i] = 0.0;
+        phib[i] = 0.0;
+        nlw[i] = __builtin_inf();
+        if (s < n) {
+            rho[i] = geo.rho[gb + s];
+            phi[i] = geo.phi[gb + s];
+            phib[i] = geo.phib[gb + s];
+            const double lw = geo.lw[gb + s];
+            nlw[i] = -lw;
+            lwmax = lw > lwmax ? lw : lwmax;
+        }
+    }
+    if (zc == 0) {
+        double ws = 0.0;
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int s = base + i * 64 + lane;
+            if (s < n) ws += (double)W[gb + s];
+        }
+        ws = wave_sum(ws);
+        if (lane == 0) pw[(size_t)j * sp.wtiles + tile] = ws;
+    }
+    const double wmx = wave_max(lwmax);
+    const double hw = (wmx == -__builtin_inf()) ? 0.0 : ceil(wmx);
+#pragma unroll
+    for (int i = 0; i < PT; ++i) nlw[i] += hw;
+    const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
+    const int p0 = zc * MZ, p1 = (p0 + MZ < M) ? p0 + MZ : M;
+    const double* zs = zp.zs + 2 * (size_t)off;
+    const int nA = zp.nA[gr.run];
+    auto one = [&](int p, const double* ang) {
+        const double zr = zs[2 * p], zt = zs[2 * p + 1];
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], nlw[i]));
+        const T sw = wave_sum_last(s);
+        if (lane == 63) {
+            ps[pbase + p] = (double)sw;  // frame order; k_cz_combine maps back
+            ph[pbase + p] = (int)hw;
+        }
+    };
+    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
+    for (int p = p0; p < a1; ++p) one(p, phi);
+    for (int p = b0; p < p1; ++p) one(p, phib);
+}
+
+// second pass in frames: as k_weight<T, PT, true>, the measurement side read
+// from the prepared order
+template <typename T, int PT>
+__global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                       const int* __restrict__ ncur, int Mall,
+                                                       const ZWin* __restrict__ win, ZPrepC zp, int Mmax, Split sp,
+                                                       const int* __restrict__ zHs, const T* __restrict__ zFs,
+                                                       const int* __restrict__ zfls, double* __restrict__ pzeta,
+                                                       T* __restrict__ accp)
+{
+    constexpr int WT = 64 * PT;
+    const int j = blockIdx.y;
+    const Grp gr = gd[j];
+    int off = 0, M = Mall;
+    if (win) {
+        off = win[gr.run].off;
+        M = win[gr.run].M;
+    }
+    const int zsplit = zsplit_for(M, sp.mz), MZ = (M + zsplit - 1) / zsplit;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + wave_in_block();
+    const int tile = gw / zsplit, zc = gw - tile * zsplit;
+    const int n = ncur[j];
+    const int base = tile * WT;
+    if (tile >= sp.wtiles || base >= n) return;
+    const size_t gb = (size_t)j * m.cap;
+    const size_t zb = (size_t)j * Mmax;
+    double rho[PT], phi[PT], phib[PT];
+    T acc[PT];
+    // the tile's weighted states for the local estimates of candidate labels,
+    // read once (0 in empty slots)
+    T uw[PT], ux[4][PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int s = base + i * 64 + lane;
+        rho[i] = 0.0;
+        phi[i] = 0.0;
+        phib[i] = 0.0;
+        acc[i] = 0;
+        uw[i] = 0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) ux[d][i] = 0;
+        if (s < n) {
+            rho[i] = geo.rho[gb + s];
+            phi[i] = geo.phi[gb + s];
+            phib[i] = geo.phib[gb + s];
+            uw[i] = (T)(m.wscale * (double)st.w[gb + s]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) ux[d][i] = st.x[d][gb + s];
+        }
+    }
+    const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
+    const int p0 = zc * MZ, p1 = (p0 + MZ < M) ? p0 + MZ : M;
+    const double* zs = zp.zs + 2 * (size_t)off;
+    const int nA = zp.nA[gr.run];
+    auto one = [&](int p, const double* ang) {
+        // every per-measurement operand in frame order: independent scalar loads
+        const double zr = zs[2 * p], zt = zs[2 * p + 1];
+        const double H = (double)zHs[zb + p];
+        const T F = zFs[zb + p];
+        const int fl = zfls[zb + p];
+        if (fl == 0) {
+#pragma unroll
+            for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H)) * F;
+        } else {
+            T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
+#pragma unroll
+            for (int i = 0; i < PT; ++i) {
+                const T e = fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H));
+                acc[i] += e * F;
+                const T u = e * uw[i];
+                u0 += u * ux[0][i];
+                u1 += u * ux[1][i];
+                u2 += u * ux[2][i];
+                u3 += u * ux[3][i];
+                u4 += u;
+            }
+            const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
+                         r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
+            if (lane == 0) {
+                double* o = pzeta + (pz + (fl - 1)) * 5;
+                o[0] = r0;
+                o[1] = r1;
+                o[2] = r2;
+                o[3] = r3;
+                o[4] = r4;
+            }
+        }
+    };
+    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
+    for (int p = p0; p < a1; ++p) one(p, phi);
+    for (int p = b0; p < p1; ++p) one(p, phib);
+    const size_t KC = (size_t)m.K * m.cap;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int s = base + i * 64 + lane;
+        if (s < n) accp[(size_t)zc * KC + gb + s] = acc[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Combine the first-pass partials of group j (one 1024-thread workgroup per
 // group; one wavefront per measurement, lanes over the group's tiles in a
 // fixed tree order):
@@ -882,7 +1158,8 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, const Grp* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __restrict__ gd,
                                                      const int* __restrict__ ncur, int Mall,
-                                                     const ZWin* __restrict__ win, int Mmax,
+                                                     const ZWin* __restrict__ win, const int* __restrict__ zpos,
+                                                     ZSorted<T> zsort, int Mmax,
                                                      int wtiles, int WT, const double* __restrict__ ps,
                                                      const int* __restrict__ ph, const double* __restrict__ pw,
                                                      int* __restrict__ zH, T* __restrict__ zF,
@@ -896,20 +1173,24 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
     const int j = blockIdx.x;
     const Grp gr = gd[j];
     const int M = zview(gr, win, nullptr, Mall).M;
+    // frame-order passes (zpos != nullptr) keep their partials, and want H, F
+    // and the flag, in frame order
+    const int zoff = win ? win[gr.run].off : 0;
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const int n = ncur[j];
     const int nw = (n + WT - 1) / WT;
     const size_t zb = (size_t)j * Mmax;
     for (int p = wv; p < M; p += 16) {
+        const int pp = zpos ? zpos[zoff + p] : p;
         int H = -2147483647 - 1;
         for (int t = lane; t < nw; t += 64) {
-            const size_t o = ((size_t)j * wtiles + t) * Mmax + p;
+            const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
             if (ps[o] > 0.0 && ph[o] > H) H = ph[o];
         }
         H = wave_max(H);
         double S = 0.0;
         for (int t = lane; t < nw; t += 64) {
-            const size_t o = ((size_t)j * wtiles + t) * Mmax + p;
+            const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
             if (ps[o] > 0.0) S += ldexp(ps[o], ph[o] - H);
         }
         S = wave_sum(S);
@@ -929,6 +1210,11 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
             zdW[zb + p] = dW;
             zflag[zb + p] = 0;
             sm_dw[p] = dW;
+            if (zpos) {
+                zsort.H[zb + pp] = H;
+                zsort.F[zb + pp] = (T)F;
+                zsort.flag[zb + pp] = 0;
+            }
         }
     }
     double wsum = 0.0;
@@ -969,6 +1255,7 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
         if (rank < nc) {
             cand[zb + rank] = q;
             zflag[zb + q] = rank + 1;
+            if (zpos) zsort.flag[zb + zpos[zoff + q]] = rank + 1;
         }
     }
 }

@@ -54,7 +54,7 @@ constexpr int MZ_DEFAULT = 16;
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
     "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
-    "k_geom", "k_wfinal", "k_birth_meas", "k_mlp_infer", "k_birth_mix",
+    "k_geom", "k_wfinal", "k_birth_meas", "k_mlp_infer", "k_birth_mix", "k_zprep",
 };
 
 struct Layout {
@@ -87,6 +87,9 @@ struct pphd_filter {
     ZWin* win = nullptr;          // measurement windows of the batched update [nruns]
     int32_t* uwin = nullptr;      // windows as given by the caller [nruns][2]
     uint32_t* dstep = nullptr;    // step counter of captured graphs
+    ZPrep zprep{};                // frame-ordered measurements of the bearing-frame passes
+    int *zHs = nullptr, *zfls = nullptr;  // H and candidate flags in frame order
+    void* zFs = nullptr;                  // F in frame order
     int z_cap = 0;                // measurements the batch's set buffer holds
     int Jmax = 0, M0max = 0;
     int32_t* pin_win = nullptr;
@@ -194,6 +197,13 @@ size_t carve(pphd_filter* f, char* base)
     f->win = L.take<ZWin>(base, (size_t)f->nruns * sizeof(ZWin));
     f->uwin = L.take<int32_t>(base, (size_t)f->nruns * 8);
     f->dstep = L.take<uint32_t>(base, 4);
+    f->zprep.zs = L.take<double>(base, (size_t)f->z_cap * 2 * 8);
+    f->zprep.orig = L.take<int>(base, (size_t)f->z_cap * 4);
+    f->zprep.pos = L.take<int>(base, (size_t)f->z_cap * 4);
+    f->zHs = L.take<int>(base, K * Mx * 4);
+    f->zFs = L.take<char>(base, K * Mx * es);
+    f->zfls = L.take<int>(base, K * Mx * 4);
+    f->zprep.nA = L.take<int>(base, (size_t)f->nruns * 4);
     f->p1s = L.take<double>(base, K * f->wtiles_max * Mx * 8);
     f->p1h = L.take<int>(base, K * f->wtiles_max * Mx * 4);
     f->p1w = L.take<double>(base, K * f->wtiles_max * 8);
@@ -513,10 +523,15 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         f->births_pending = false;
     }
     dim3 g1((f->wtiles1 * zs + 3) / 4, K), g2((f->wtiles2 * zs + 3) / 4, K);
+    const ZPrepC zpc{ f->zprep.zs, f->zprep.orig, f->zprep.pos, f->zprep.nA };
+    const bool frames = f->pass_mode == PASS_FRAMES;
+    const ZSorted<T> zsort{ f->zHs, (T*)f->zFs, f->zfls };
     if (f->pass_mode == PASS_FRAMES) {
+        LAUNCH(f, PPHD_K_ZPREP,
+               hipLaunchKernelGGL(k_zprep, dim3(f->nruns), dim3(256), 0, f->stream, dm, a.dz, a.M, a.win, f->zprep));
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz<T, PT1, PASS_FRAMES>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
-                                  (const T*)st.w, f->ncur, a.dz, a.M, a.win, Mx, s1, f->p1s, f->p1h, f->p1w));
+               hipLaunchKernelGGL((k_cz_frames<T, PT1>), g1, dim3(256), 0, f->stream, dm, f->gd, geo, (const T*)st.w,
+                                  f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w));
     } else if (f->pass_mode == PASS_WRAP) {
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
@@ -528,12 +543,13 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     }
     LAUNCH(f, PPHD_K_CZ_COMBINE,
            hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
-                              f->gd, f->ncur, a.M, a.win, Mx, f->wtiles1, f->wt1, f->p1s, f->p1h, f->p1w, f->zH,
+                              f->gd, f->ncur, a.M, a.win, frames ? f->zprep.pos : nullptr, zsort, Mx, f->wtiles1,
+                              f->wt1, f->p1s, f->p1h, f->p1w, f->zH,
                               (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand));
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_WEIGHT,
-               hipLaunchKernelGGL((k_weight<T, PT2, true>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
-                                  a.dz, a.M, a.win, Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta,
+               hipLaunchKernelGGL((k_weight_frames<T, PT2>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
+                                  a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
                                   (T*)f->accp));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
