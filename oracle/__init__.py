@@ -95,6 +95,7 @@ def lib():
         L.orc_birth_proposal_density.argtypes = [M, D, c_int, ctypes.c_double, ctypes.c_double]
         L.orc_birth_proposal_density.restype = ctypes.c_double
         L.orc_birth_from_measurements.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
+        L.orc_bearing_bucket.argtypes = [M, ctypes.c_double, ctypes.c_double]
         L.orc_mixture_proposal_density.argtypes = [M, D, c_int, D]
         L.orc_mixture_proposal_density.restype = ctypes.c_double
         L.orc_birth_from_mixture.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
@@ -193,6 +194,11 @@ def birth_from_measurements(p, st, step, seed, run, Z):
     Z, Zb = _zbuf(Z)
     _check(lib().orc_birth_from_measurements(ctypes.byref(model_struct(p)), st.cap, step, seed, run, _d(Zb),
                                               Z.shape[0], _d(st.X), _d(st.W), _i(st.n)), "birth_from_measurements")
+
+
+def bearing_bucket(p, x, y):
+    """Bearing bucket (0..63) the resampling orders parents by."""
+    return lib().orc_bearing_bucket(ctypes.byref(model_struct(p)), float(x), float(y))
 
 
 def _table(table, M):

@@ -512,6 +512,22 @@ int orc_fuse(const orc_model* m, int M, const int32_t* sel, const double* zeta,
 /*  - Children are written in parent order.                                  */
 /* counts[j*cap+i] receives the number of children of parent slot i.         */
 /* ------------------------------------------------------------------------ */
+/* Bearing bucket of a position, 0 .. ORC_BUCKETS-1: the "diamond angle"
+ * d in [0, 4) of the offset from the sensor (a monotonic stand-in for the
+ * bearing measured counter-clockwise from the +x axis, computed with one
+ * correctly rounded division), times ORC_BUCKETS/4, rounded down. */
+#define ORC_BUCKETS 64
+int orc_bearing_bucket(const orc_model* m, double x, double y)
+{
+    double dx = x - m->sensor_x, dy = y - m->sensor_y;
+    double d;
+    if (dx == 0.0 && dy == 0.0) d = 0.0;
+    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
+    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+    int b = (int)floor(d * (ORC_BUCKETS / 4.0));
+    return b < 0 ? 0 : (b > ORC_BUCKETS - 1 ? ORC_BUCKETS - 1 : b);
+}
+
 int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                  const double* X, const double* W, const int32_t* n,
                  double* Xout, double* Wout, int32_t* nout, int32_t* counts, double* mass_q)
@@ -520,12 +536,22 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
     size_t KC = (size_t)K * (size_t)cap;
     double Rj = m->particles_per_target / (double)K;
     uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
-    if (!q) return -2;
+    int* order = (int*)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
+    if (!q || !order) { free(q); free(order); return -2; }
     for (int j = 0; j < K; ++j) {
         size_t base = (size_t)j * (size_t)cap;
         int nj = n[j];
         int cap_children = cap - orc_births_in_partition(m, j);
         for (int i = 0; i < cap; ++i) counts[base + i] = 0;
+        /* Reading (order of the parents): the parents are taken in bearing-
+         * bucket order, buckets ascending and slot order within a bucket (a
+         * stable counting sort), so that children near each other in bearing
+         * sit next to each other; counts[] follows that order. */
+        int hist[ORC_BUCKETS + 1];
+        for (int b = 0; b <= ORC_BUCKETS; ++b) hist[b] = 0;
+        for (int i = 0; i < nj; ++i) hist[1 + orc_bearing_bucket(m, XS(X, 0, base + i), XS(X, 2, base + i))] += 1;
+        for (int b = 0; b < ORC_BUCKETS; ++b) hist[b + 1] += hist[b];
+        for (int i = 0; i < nj; ++i) order[hist[orc_bearing_bucket(m, XS(X, 0, base + i), XS(X, 2, base + i))]++] = i;
         /* quantisation */
         double wmax = 0.0;
         for (int i = 0; i < nj; ++i)
@@ -539,7 +565,7 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
             while (((int64_t)1 << b) < (int64_t)nj) ++b; /* 2^b >= n */
             S = 52 - b - e;
             for (int i = 0; i < nj; ++i) {
-                q[i] = (uint64_t)floor(ldexp(W[base + i], S));
+                q[i] = (uint64_t)floor(ldexp(W[base + order[i]], S));
                 Q += q[i];
             }
         }
@@ -574,12 +600,13 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
                 c += q[i];
             }
             size_t dst = base + (size_t)mm;
-            for (int d = 0; d < m->dim; ++d) XS(Xout, d, dst) = XS(X, d, base + i);
+            for (int d = 0; d < m->dim; ++d) XS(Xout, d, dst) = XS(X, d, base + order[i]);
             Wout[dst] = mq / (double)L;
             counts[base + i] += 1;
         }
     }
     free(q);
+    free(order);
     return 0;
 }
 
@@ -695,11 +722,20 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
     }
     free(Ck);
     /* 3) resampling: mass N_k, then L_k = round(N_k R) systematic draws.
-     * Same quantisation and point rule as the grouped filter. */
+     * Same quantisation and point rule as the grouped filter, over the
+     * particles listed bucket by bucket (bearing buckets ascending, slot order
+     * inside a bucket). */
     double wmax = 0.0;
     for (int i = 0; i < N; ++i) if (Wupd[i] > wmax) wmax = Wupd[i];
     uint64_t* q = (uint64_t*)calloc((size_t)(N > 0 ? N : 1), sizeof(uint64_t));
-    if (!q) return -2;
+    int* list = (int*)calloc((size_t)(N > 0 ? N : 1), sizeof(int));
+    if (!q || !list) { free(q); free(list); return -2; }
+    {
+        int len = 0;
+        for (int b = 0; b < 64; ++b)
+            for (int i = 0; i < N; ++i)
+                if (orc_bearing_bucket(m, XS(X, 0, i), XS(X, 2, i)) == b) list[len++] = i;
+    }
     uint64_t Q = 0;
     int S = 0;
     if (N > 0 && wmax > 0.0) {
@@ -707,7 +743,7 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
         frexp(wmax, &e);
         while (((int64_t)1 << b) < (int64_t)N) ++b;
         S = 52 - b - e;
-        for (int i = 0; i < N; ++i) { q[i] = (uint64_t)floor(ldexp(Wupd[i], S)); Q += q[i]; }
+        for (int i = 0; i < N; ++i) { q[i] = (uint64_t)floor(ldexp(Wupd[list[i]], S)); Q += q[i]; }
     }
     int64_t L = 0;
     double Nk = 0.0;
@@ -729,11 +765,12 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
         for (int64_t k = 0; k < L; ++k) {
             unsigned __int128 point = ((unsigned __int128)(((uint64_t)k << 32) + (uint64_t)r4[0])) * Q;
             while (!(point < ((c * (unsigned __int128)L) << 32))) { ++i; c += q[i]; }
-            for (int d = 0; d < 4; ++d) XS(Xout, d, k) = XS(X, d, i);
+            for (int d = 0; d < 4; ++d) XS(Xout, d, k) = XS(X, d, list[i]);
             Wout[k] = Nk / (double)L;
         }
     }
     free(q);
+    free(list);
     return 0;
 }
 

@@ -84,6 +84,7 @@ int orc_extract(const orc_model* m, int M, const double* dW, const double* zeta_
                 const double* mass, int32_t* LT, int32_t* sel, double* zeta);
 int orc_fuse(const orc_model* m, int M, const int32_t* sel, const double* zeta,
              double* est_state, int32_t* est_label, int32_t* est_votes, int32_t* n_est);
+int orc_bearing_bucket(const orc_model* m, double x, double y);
 int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                  const double* X, const double* W, const int32_t* n,
                  double* Xout, double* Wout, int32_t* nout, int32_t* counts, double* mass_q);

@@ -10,6 +10,18 @@ import pytest
 from paper_1503_03769_amd.scenario import BASE_MODEL
 
 
+def _bucket(x, y, sx=0.0, sy=0.0):
+    """Diamond-angle bearing bucket (0..63), written out for the test."""
+    dx, dy = x - sx, y - sy
+    if dx == 0.0 and dy == 0.0:
+        d = 0.0
+    elif dy >= 0.0:
+        d = dy / (dx + dy) if dx >= 0.0 else 1.0 - dx / (dy - dx)
+    else:
+        d = 2.0 - dy / (-dx - dy) if dx < 0.0 else 3.0 + dx / (dx - dy)
+    return min(63, max(0, math.floor(d * 16.0)))
+
+
 def _brute_counts(w, L, r):
     """Systematic resampling from the definition, in exact rationals: point m
     sits at (m + r/2^32) W / L; parent i takes the points in [c_{i-1}, c_i)."""
@@ -48,12 +60,15 @@ def test_resample_counts_match_exact_brute_force(orc, case):
             k[:] = 256                         # equal weights
         ks.append(k)
         st.W[j * cap:j * cap + n] = k / 2.0 ** 20   # dyadic weights: quantisation is exact
-        st.X[:, j * cap:j * cap + n] = rng.normal(size=(4, n))
+        st.X[:, j * cap:j * cap + n] = rng.normal(size=(4, n)) * 500.0
     step, seed, run = 3 + case, 0xABC + case, case % 4
     out, counts, mq = orc.resample(p, st, step, seed, run)
     for j in range(K):
         n = int(st.n[j])
-        w = [Fraction(int(v), 2 ** 20) for v in ks[j]]
+        # the parents in bearing-bucket order (stable)
+        b = [_bucket(st.X[0, j * cap + i], st.X[2, j * cap + i]) for i in range(n)]
+        order = sorted(range(n), key=lambda i: (b[i], i))
+        w = [Fraction(int(ks[j][i]), 2 ** 20) for i in order]
         W = sum(w, Fraction(0))
         Jj = orc.births_in_partition(p, j)
         L = math.floor(W * Fraction(R / K) + Fraction(1, 2)) if W > 0 else 0
@@ -71,8 +86,8 @@ def test_resample_counts_match_exact_brute_force(orc, case):
         for wi, ci in zip(w, got):
             e = L * wi / W
             assert math.floor(e) <= ci <= math.ceil(e)
-        # children in parent order, each with weight W / L
-        kids = np.repeat(np.arange(n), got)
+        # children in that parent order, each with weight W / L
+        kids = np.repeat(np.array(order, dtype=int), got)
         assert np.array_equal(out.X[:, j * cap:j * cap + L], st.X[:, j * cap + kids])
         assert np.all(out.W[j * cap:j * cap + L] == float(W) / L)
         if ks[j].size and np.all(ks[j] == ks[j][0]) and L == n:
@@ -137,3 +152,19 @@ def test_exchange_noop_for_one_group(orc):
     X0 = st.X.copy()
     orc.exchange(p, st, 1, 1, 0)
     assert np.array_equal(st.X, X0)
+
+
+def test_bearing_bucket_follows_the_bearing(orc):
+    """The bucket is non-decreasing in the bearing measured counter-clockwise
+    from the +x axis, covers 0..63, and agrees with the written-out form."""
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=4000) * 800
+    y = rng.normal(size=4000) * 800
+    ang = np.mod(np.arctan2(y, x), 2 * math.pi)
+    b = np.array([orc.bearing_bucket(BASE_MODEL, xi, yi) for xi, yi in zip(x, y)])
+    o = np.argsort(ang)
+    assert np.all(np.diff(b[o]) >= 0)
+    assert b.min() == 0 and b.max() == 63
+    assert all(orc.bearing_bucket(BASE_MODEL, xi, yi) == _bucket(xi, yi) for xi, yi in zip(x[:200], y[:200]))
+    # the axes: +x, +y, -x, -y start buckets 0, 16, 32, 48
+    assert [orc.bearing_bucket(BASE_MODEL, *v) for v in ((5.0, 0.0), (0.0, 5.0), (-5.0, 0.0), (0.0, -5.0))] == [0, 16, 32, 48]
