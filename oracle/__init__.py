@@ -96,6 +96,7 @@ def lib():
         L.orc_birth_proposal_density.restype = ctypes.c_double
         L.orc_birth_from_measurements.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
         L.orc_bearing_bucket.argtypes = [M, ctypes.c_double, ctypes.c_double]
+        L.orc_sort_by_bucket.argtypes = [M, ctypes.c_size_t, D, D, ctypes.c_size_t, c_int]
         L.orc_mixture_proposal_density.argtypes = [M, D, c_int, D]
         L.orc_mixture_proposal_density.restype = ctypes.c_double
         L.orc_birth_from_mixture.argtypes = [M, c_int, u32, u64, u32, D, c_int, D, D, I]
@@ -199,6 +200,13 @@ def birth_from_measurements(p, st, step, seed, run, Z):
 def bearing_bucket(p, x, y):
     """Bearing bucket (0..63) the resampling orders parents by."""
     return lib().orc_bearing_bucket(ctypes.byref(model_struct(p)), float(x), float(y))
+
+
+def sort_by_bucket(p, st, base, count):
+    """Stable bearing-bucket order of the slots [base, base + count) of st
+    (the order births take once drawn)."""
+    _check(lib().orc_sort_by_bucket(ctypes.byref(model_struct(dict(p, dim=st.X.shape[0]))), st.K * st.cap, _d(st.X),
+                                    _d(st.W), int(base), int(count)), "sort_by_bucket")
 
 
 def _table(table, M):

@@ -257,6 +257,7 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
             for (int d = 0; d < m->dim; ++d) XS(X, d, g) = st[d];
             W[g] = m->birth_mass / (double)Jj;
         }
+        if (m->birth_proposal == 0 && orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
         n[j] = ns + Jj;
     }
     return 0;
@@ -360,6 +361,7 @@ int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint
             double q = orc_birth_proposal_density(m, Z, M, x, y);
             W[g] = inside ? m->birth_mass * (1.0 / area) / ((double)Jj * q) : 0.0;
         }
+        if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
     }
     return 0;
 }
@@ -528,6 +530,41 @@ int orc_bearing_bucket(const orc_model* m, double x, double y)
     return b < 0 ? 0 : (b > ORC_BUCKETS - 1 ? ORC_BUCKETS - 1 : b);
 }
 
+/* Reading (order of the births): a group's births are drawn slot by slot, each
+ * from the random numbers of the slot it is drawn in, and then put in stable
+ * bearing-bucket order over those same slots (buckets ascending, drawing
+ * order inside a bucket), as the parents of the resampling are, so that
+ * neighbouring slots hold births of similar bearing.  Counting sort over the
+ * slots [base, base + count) of a particle array with KC slots per component. */
+int orc_sort_by_bucket(const orc_model* m, size_t KC, double* X, double* W, size_t base, int count)
+{
+    if (count <= 1) return 0;
+    int* key = (int*)malloc(sizeof(int) * (size_t)count);
+    double* tx = (double*)malloc(sizeof(double) * (size_t)count * 5);
+    double* tw = (double*)malloc(sizeof(double) * (size_t)count);
+    if (!key || !tx || !tw) { free(key); free(tx); free(tw); return -2; }
+    int start[ORC_BUCKETS + 1];
+    for (int b = 0; b <= ORC_BUCKETS; ++b) start[b] = 0;
+    for (int i = 0; i < count; ++i) {
+        key[i] = orc_bearing_bucket(m, XS(X, 0, base + i), XS(X, 2, base + i));
+        start[key[i] + 1] += 1;
+    }
+    for (int b = 0; b < ORC_BUCKETS; ++b) start[b + 1] += start[b];
+    for (int i = 0; i < count; ++i) {
+        int to = start[key[i]]++;
+        for (int d = 0; d < m->dim; ++d) tx[(size_t)d * count + to] = XS(X, d, base + i);
+        tw[to] = W[base + i];
+    }
+    for (int i = 0; i < count; ++i) {
+        for (int d = 0; d < m->dim; ++d) XS(X, d, base + i) = tx[(size_t)d * count + i];
+        W[base + i] = tw[i];
+    }
+    free(key);
+    free(tx);
+    free(tw);
+    return 0;
+}
+
 int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                  const double* X, const double* W, const int32_t* n,
                  double* Xout, double* Wout, int32_t* nout, int32_t* counts, double* mass_q)
@@ -615,8 +652,12 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
 /* The paper moves particle i of group k onto particle i of group k+1 for    */
 /* i = 1..L, for every k at once, with the L particles chosen at random.     */
 /* Readings: one L for all groups, L = floor(rho_x min_j n_j) (so L < n_j/2); */
-/* group j's chosen slots are S_j(m) = (o_j + m*floor(n_j/L)) mod n_j,        */
-/* m = 0..L-1, with the offset o_j drawn from the EXCHANGE stream; the       */
+/* group j's L slots are a systematic sample, one slot per stratum: with a    */
+/* uniform u_j = a/2^32 from the EXCHANGE stream and b_j = floor(u_j n_j),    */
+/*   S_j(m) = floor((m n_j + b_j) / L),  m = 0..L-1,                          */
+/* so every slot is chosen with probability about L/n_j and S_j(m) is the    */
+/* floor of a point of [m n_j/L, (m+1) n_j/L): the quantile m/L of the        */
+/* group's slot order (distinct slots, as n_j/L >= 2).  The                    */
 /* particle-weight couple in S_j(m) replaces the one in S_{j+1}(m).  All     */
 /* copies read the state before the exchange, so the exchange permutes the   */
 /* particles: group sizes and the global multiset of couples are unchanged.  */
@@ -625,9 +666,8 @@ static uint64_t orc_exchange_slot(uint64_t seed, uint32_t step, uint32_t run, in
 {
     uint32_t a[4];
     orc_block(seed, (uint32_t)j, step, ORC_EXCHANGE, 0, run, a);
-    uint64_t o = ((uint64_t)a[0] * (uint64_t)nj) >> 32;
-    uint64_t stride = (uint64_t)(nj / L);
-    return (o + (uint64_t)mm * stride) % (uint64_t)nj;
+    uint64_t b = ((uint64_t)a[0] * (uint64_t)nj) >> 32;
+    return ((uint64_t)mm * (uint64_t)nj + b) / (uint64_t)L;
 }
 
 int orc_exchange(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
@@ -703,6 +743,25 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
         XS(X, 2, i) = m->region[2] + uy * (m->region[3] - m->region[2]);
         XS(X, 3, i) = m->birth_sigma_v * v2;
         W[i] = m->birth_mass / (double)Jk;
+    }
+    /* the births in bearing-bucket order over their slots: listed bucket by
+     * bucket, drawing order inside a bucket */
+    if (Jk > 1) {
+        double* bx = (double*)malloc(sizeof(double) * 5 * (size_t)Jk);
+        if (!bx) return -2;
+        int len = 0;
+        for (int b = 0; b < 64; ++b)
+            for (int i = L0; i < L0 + Jk; ++i)
+                if (orc_bearing_bucket(m, XS(X, 0, i), XS(X, 2, i)) == b) {
+                    for (int d = 0; d < 4; ++d) bx[5 * len + d] = XS(X, d, i);
+                    bx[5 * len + 4] = W[i];
+                    ++len;
+                }
+        for (int k = 0; k < Jk; ++k) {
+            for (int d = 0; d < 4; ++d) XS(X, d, L0 + k) = bx[5 * k + d];
+            W[L0 + k] = bx[5 * k + 4];
+        }
+        free(bx);
     }
     int N = L0 + Jk;
     n[0] = N;
@@ -859,6 +918,7 @@ int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t 
             double gam = m->birth_mass * orc_prior_density(m, x);
             W[g] = gam > 0.0 ? gam / ((double)Jj * orc_mixture_proposal_density(m, table, M, x)) : 0.0;
         }
+        if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
     }
     return 0;
 }

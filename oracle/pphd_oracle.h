@@ -19,6 +19,7 @@
  */
 #ifndef PPHD_ORACLE_H
 #define PPHD_ORACLE_H
+#include <stddef.h>
 #include <stdint.h>
 
 typedef struct {
@@ -85,6 +86,9 @@ int orc_extract(const orc_model* m, int M, const double* dW, const double* zeta_
 int orc_fuse(const orc_model* m, int M, const int32_t* sel, const double* zeta,
              double* est_state, int32_t* est_label, int32_t* est_votes, int32_t* n_est);
 int orc_bearing_bucket(const orc_model* m, double x, double y);
+/* Stable bearing-bucket order of the slots [base, base + count) of a particle
+ * array with KC slots per component (births, after they are drawn). */
+int orc_sort_by_bucket(const orc_model* m, size_t KC, double* X, double* W, size_t base, int count);
 int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                  const double* X, const double* W, const int32_t* n,
                  double* Xout, double* Wout, int32_t* nout, int32_t* counts, double* mass_q);

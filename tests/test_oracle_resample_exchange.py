@@ -168,3 +168,79 @@ def test_bearing_bucket_follows_the_bearing(orc):
     assert all(orc.bearing_bucket(BASE_MODEL, xi, yi) == _bucket(xi, yi) for xi, yi in zip(x[:200], y[:200]))
     # the axes: +x, +y, -x, -y start buckets 0, 16, 32, 48
     assert [orc.bearing_bucket(BASE_MODEL, *v) for v in ((5.0, 0.0), (0.0, 5.0), (-5.0, 0.0), (0.0, -5.0))] == [0, 16, 32, 48]
+
+
+def test_exchange_takes_one_slot_per_stratum(orc):
+    """The m-th couple a group receives comes from stratum m of its ring
+    predecessor (the floor of a point of [m n/L, (m+1) n/L) in the slot order)
+    and lands in stratum m of the receiver; over many steps every slot is sent
+    about L/n of the time."""
+    K, counts = 3, [397, 250, 311]
+    p, st0, cap = _exchange_setup(orc, K, counts, 5)
+    L = math.floor(0.1 * min(counts))
+    sent = [np.zeros(n) for n in counts]
+    for step in range(1, 401):
+        st = orc.State(K, cap)
+        st.X[:] = st0.X
+        st.W[:] = st0.W
+        st.n[:] = st0.n
+        orc.exchange(p, st, step, 0x77, 2)
+        for j in range(K):
+            prev = (j - 1) % K
+            src_of = {tuple(st0.X[:, prev * cap + s]): s for s in range(counts[prev])}
+            got = [s for s in range(counts[j]) if not np.array_equal(st.X[:, j * cap + s], st0.X[:, j * cap + s])]
+            assert len(got) == L
+            for m, s in enumerate(sorted(got)):
+                src = src_of[tuple(st.X[:, j * cap + s])]
+                assert m * counts[j] // L <= s <= ((m + 1) * counts[j] - 1) // L
+                assert m * counts[prev] // L <= src <= ((m + 1) * counts[prev] - 1) // L
+                sent[prev][src] += 1
+    for j in range(K):
+        freq = sent[j] / 400
+        assert abs(freq.mean() - L / counts[j]) < 0.01
+        assert freq.max() < 3 * L / counts[j]
+
+
+def test_sort_by_bucket_is_a_stable_counting_sort(orc):
+    """The births' reordering equals numpy's stable argsort of the written-out
+    bucket key over the slot range, other slots untouched."""
+    p = dict(BASE_MODEL, partitions=2)
+    cap = 600
+    st = orc.State(2, cap)
+    rng = np.random.default_rng(11)
+    st.X[:] = rng.uniform(-1000, 1000, size=st.X.shape)
+    st.X[:, 700:720] = st.X[:, 700:701]            # equal keys keep their order
+    st.X[1, 700:720] = np.arange(20)               # (told apart by the velocity)
+    st.W[:] = rng.uniform(0, 1, size=st.W.shape)
+    X0, W0 = st.X.copy(), st.W.copy()
+    base, count = 650, 400
+    orc.sort_by_bucket(p, st, base, count)
+    keys = [_bucket(X0[0, base + i], X0[2, base + i]) for i in range(count)]
+    order = np.argsort(np.array(keys), kind="stable")
+    assert np.array_equal(st.X[:, base:base + count], X0[:, base + order])
+    assert np.array_equal(st.W[base:base + count], W0[base + order])
+    rest = np.r_[0:base, base + count:2 * cap]
+    assert np.array_equal(st.X[:, rest], X0[:, rest]) and np.array_equal(st.W[rest], W0[rest])
+
+
+@pytest.mark.parametrize("prop", [0, 1])
+def test_births_are_in_bucket_order(orc, prop):
+    """Each group's birth slots are in non-decreasing bearing bucket (written-
+    out key) with the birth-density and the measurement-driven proposal."""
+    K, cap, J = 3, 2048, 700
+    p = dict(BASE_MODEL, partitions=K, births_per_step=J, birth_proposal=prop, birth_alpha=0.2)
+    st = orc.State(K, cap)
+    for j in range(K):
+        st.n[j] = 100 + 50 * j
+    rng = np.random.default_rng(3)
+    st.X[:] = rng.normal(0, 300, size=st.X.shape)
+    st.W[:] = 0.01
+    orc.predict(p, st, 4, 21, 2)
+    if prop == 1:
+        Z = np.stack([rng.uniform(50, 1400, 30), rng.uniform(-math.pi, math.pi, 30)], axis=1)
+        orc.birth_from_measurements(p, st, 4, 21, 2, Z)
+    for j in range(K):
+        ns = int(st.n[j]) - J // K - (1 if j < J % K else 0)
+        b = [_bucket(st.X[0, j * cap + s], st.X[2, j * cap + s]) for s in range(ns, int(st.n[j]))]
+        assert all(b[i] <= b[i + 1] for i in range(len(b) - 1))
+        assert len(set(b)) > 20
