@@ -55,8 +55,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the groups over "
+              "several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -141,7 +141,10 @@ pphd_status pphd_init(pphd_filter* f);
  * q_p placing the particle at range N(r_p, sigma_r^2), bearing
  * N(theta_p, sigma_theta^2) with velocity N(0, sigma_v^2 I), and weight
  * gamma(x) / (J_j q(x)) (Eq 6); birth_proposal 2 reserves them the same way for
- * the learned mixtures of pphd_mlp.h.  step: the time index k >= 1.
+ * the learned mixtures of pphd_mlp.h.  Once drawn (each from the Philox
+ * numbers of the slot it is drawn in), a group's births are put in stable
+ * bearing-bucket order over their slots, as the resampling orders parents.
+ * step: the time index k >= 1.
  * Phase READY or RESAMPLED -> PREDICTED. */
 pphd_status pphd_predict(pphd_filter* f, uint32_t step);
 
@@ -171,14 +174,19 @@ pphd_status pphd_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t ca
                                 int32_t* d_n_out);
 
 /* Step 5: every group quantises its weights, draws L' = round(N_j R_j)
- * children by systematic resampling (one Philox uniform per group; children
- * in parent order), clamps L' to cap - J_j and gives each child weight
- * N_j / L'.  step: the time index of the preceding predict.
+ * children by systematic resampling (one Philox uniform per group) over its
+ * parents taken in bearing-bucket order (the "diamond angle" of the offset
+ * from the sensor in 64 buckets, ascending; slot order inside a bucket;
+ * children in that parent order), clamps L' to cap - J_j and gives each
+ * child weight N_j / L'.  step: the time index of the preceding predict.
  * Phase UPDATED -> RESAMPLED. */
 pphd_status pphd_resample(pphd_filter* f, uint32_t step);
 
-/* Step 6: ring exchange j -> j+1 (mod K) of floor(rho_x min(L'_j, L'_{j+1}))
- * particle-weight couples per group, all read before any is written.  No-op
+/* Step 6: ring exchange j -> j+1 (mod K) within each run of L = floor(rho_x
+ * min_j L'_j) particle-weight couples per group, all read before any is
+ * written.  Group j sends a systematic sample of its slots, one per stratum:
+ * S_j(m) = floor((m L'_j + floor(u_j L'_j)) / L), u_j a Philox uniform per
+ * group and step; the couple in S_j(m) replaces the one in S_{j+1}(m).  No-op
  * for K = 1.  Phase RESAMPLED -> READY. */
 pphd_status pphd_exchange(pphd_filter* f, uint32_t step);
 
@@ -243,8 +251,8 @@ enum {
     PPHD_K_FINALIZE = 4, PPHD_K_FUSE = 5, PPHD_K_RS_TILES = 6, PPHD_K_RS_EXPAND = 7,
     PPHD_K_XCHG_GATHER = 8, PPHD_K_XCHG_SCATTER = 9, PPHD_K_INIT = 10, PPHD_K_WMAX = 11,
     PPHD_K_GEOM = 12, PPHD_K_WFINAL = 13, PPHD_K_BIRTH = 14, PPHD_K_MLP_INFER = 15,
-    PPHD_K_BIRTH_MIX = 16, PPHD_K_ZPREP = 17,
-    PPHD_K_COUNT = 18
+    PPHD_K_BIRTH_MIX = 16, PPHD_K_ZPREP = 17, PPHD_K_RS_ORDER = 18,
+    PPHD_K_BIRTH_ORDER = 19, PPHD_K_COUNT = 20
 };
 
 /* Enables (1) or disables (0) per-launch HIP-event timing on the filter's

@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 SHAPES = {"fp32": [4, 8, 16], "fp64": [2, 4, 8]}
-MEAS_PER_WAVE = [8, 16, 32, 64]
+MEAS_PER_WAVE = [8, 16, 32, 64, 128, 256]
 
 
 def tune(workload: str, first: int, last: int, verbose: bool = True):

@@ -12,7 +12,8 @@ DEPS = SOURCES + [os.path.join(CSRC, h) for h in ("kernels.h", "philox_dev.h", "
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
-    # packed FP32 instructions stay off ("Build flags")
+    # packed FP32 instructions stay off: some of their forms have given wrong
+    # results on this hardware without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

@@ -779,25 +779,24 @@ __global__ __launch_bounds__(256) void k_cz(DevModel m, const Grp* __restrict__ 
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
-        rho[i] = 0.0;
-        phi[i] = 0.0;
-        phib[i] = 0.0;
-        nlw[i] = __builtin_inf();
-        if (s < n) {
-            rho[i] = geo.rho[gb + s];
-            phi[i] = geo.phi[gb + s];
-            if (FRAMES) phib[i] = geo.phib[gb + s];
-            const double lw = geo.lw[gb + s];
-            nlw[i] = -lw;
-            lwmax = lw > lwmax ? lw : lwmax;
-        }
+        // unconditional loads (lanes past the group's end read its slot base
+        // and drop the value), so all of them are in flight at once
+        const bool ok = s < n;
+        const size_t g = gb + (ok ? s : base);
+        const double r = geo.rho[g], a = geo.phi[g], b = FRAMES ? geo.phib[g] : 0.0, lw = geo.lw[g];
+        rho[i] = ok ? r : 0.0;
+        phi[i] = ok ? a : 0.0;
+        phib[i] = ok ? b : 0.0;
+        nlw[i] = ok ? -lw : __builtin_inf();
+        lwmax = ok && lw > lwmax ? lw : lwmax;
     }
     if (zc == 0) {
         double ws = 0.0;
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
             const int s = base + i * 64 + lane;
-            if (s < n) ws += (double)W[gb + s];
+            const double wv = (double)W[gb + (s < n ? s : base)];
+            ws += s < n ? wv : 0.0;
         }
         ws = wave_sum(ws);
         if (lane == 0) pw[(size_t)j * sp.wtiles + tile] = ws;
@@ -965,55 +964,128 @@ __device__ __forceinline__ float wave_sum_last(float v)
 }
 __device__ __forceinline__ double wave_sum_last(double v) { return wave_sum(v); }
 
+// Tile culling.  A term 2^-e with e above exp2_cut<T>() is exactly zero in T
+// (2^-150 rounds to zero in float, 2^-1075 in double; the cuts leave a wide
+// margin for the rounding of the bound itself).  Every exponent of a tile is
+// at least the squared distance of the scaled measurement from the tile's
+// box [rho_lo, rho_hi] x [ang_lo, ang_hi] (plus the pass's shift), so a
+// measurement whose bound exceeds the cut contributes exactly zero to every
+// sum of the tile and is skipped; each lane tests one measurement and a
+// ballot leaves the ones to evaluate.  Results are bit-identical to the full
+// evaluation: the skipped terms are +0 and every sum starts at +0.
+template <typename T>
+__device__ __forceinline__ constexpr double exp2_cut();
+template <>
+__device__ __forceinline__ constexpr double exp2_cut<float>() { return 200.0; }
+template <>
+__device__ __forceinline__ constexpr double exp2_cut<double>() { return 1100.0; }
+
+struct TileBox {
+    double rlo, rhi, alo, ahi, blo, bhi;  // range, frame-A bearing, frame-B bearing
+};
+template <int PT>
+__device__ __forceinline__ TileBox tile_box(const double* rho, const double* phi, const double* phib, int base, int n,
+                                            int lane)
+{
+    double rlo = __builtin_inf(), rhi = -__builtin_inf(), alo = rlo, ahi = rhi, blo = rlo, bhi = rhi;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        if (base + i * 64 + lane < n) {
+            rlo = fmin(rlo, rho[i]);
+            rhi = fmax(rhi, rho[i]);
+            alo = fmin(alo, phi[i]);
+            ahi = fmax(ahi, phi[i]);
+            blo = fmin(blo, phib[i]);
+            bhi = fmax(bhi, phib[i]);
+        }
+    }
+    return TileBox{ -wave_max(-rlo), wave_max(rhi), -wave_max(-alo), wave_max(ahi), -wave_max(-blo), wave_max(bhi) };
+}
+__device__ __forceinline__ double box_dist2(double zr, double zt, double rlo, double rhi, double lo, double hi)
+{
+    const double dr = fmax(0.0, fmax(rlo - zr, zr - rhi));
+    const double dt = fmax(0.0, fmax(lo - zt, zt - hi));
+    return fma(dr, dr, dt * dt);
+}
+
+// ---------------------------------------------------------------------------
+// Tile list of the frame passes: every group's wave tiles of WT slots,
+// numbered group after group (pre[j] = the first tile of group j, pre[K] =
+// all tiles; grp[t] = the group of tile t).  The passes then loop over the
+// list, every wavefront taking tiles w, w + W, ... (W = waves in the grid),
+// so the grid does not depend on the particle counts and no wavefront starts
+// on an empty tile.  One workgroup of 1024 threads; thread i takes a
+// contiguous run of ceil(K/1024) groups.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_tile_map(const int* __restrict__ ncur, int K, int WT, int* __restrict__ pre,
+                                                   int* __restrict__ grp)
+{
+    __shared__ int s_w[16];
+    const int G = (K + 1023) / 1024;
+    const int j0 = threadIdx.x * G < K ? threadIdx.x * G : K, j1 = j0 + G < K ? j0 + G : K;
+    int c = 0;
+    for (int j = j0; j < j1; ++j) c += (ncur[j] + WT - 1) / WT;
+    const int incl = (int)wave_incl_scan((double)c);  // exact: tile counts stay below 2^53
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) s_w[wv] = incl;
+    __syncthreads();
+    int pos = incl - c;
+    for (int w = 0; w < wv; ++w) pos += s_w[w];
+    for (int j = j0; j < j1; ++j) {
+        pre[j] = pos;
+        const int cj = (ncur[j] + WT - 1) / WT;
+        for (int t = 0; t < cj; ++t) grp[pos + t] = j;
+        pos += cj;
+    }
+    if (threadIdx.x == 1023) pre[K] = pos;
+}
+
 // first pass in frames: as k_cz (PASS_FRAMES), the measurement side read
-// from the prepared order
+// from the prepared order, tiles culled; tile `tile` of group j, every
+// measurement of the run in one wavefront
 template <typename T, int PT>
-__global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __restrict__ gd, Geo geo,
-                                                   const T* __restrict__ W, const int* __restrict__ ncur,
-                                                   int Mall, const ZWin* __restrict__ win, ZPrepC zp, int Mmax,
-                                                   Split sp, double* __restrict__ ps, int* __restrict__ ph,
-                                                   double* __restrict__ pw)
+__device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __restrict__ gd, const Geo& geo,
+                                               const T* __restrict__ W, const int* __restrict__ ncur, int Mall,
+                                               const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
+                                               const Split& sp, double* __restrict__ ps, int* __restrict__ ph,
+                                               double* __restrict__ pw, int j, int tile)
 {
     constexpr int WT = 64 * PT;
-    const int j = blockIdx.y;
     const Grp gr = gd[j];
     int off = 0, M = Mall;
     if (win) {
         off = win[gr.run].off;
         M = win[gr.run].M;
     }
-    const int zsplit = zsplit_for(M, sp.mz), MZ = (M + zsplit - 1) / zsplit;
+    const int zc = 0;
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + wave_in_block();
-    const int tile = gw / zsplit, zc = gw - tile * zsplit;
     const int n = ncur[j];
     const int base = tile * WT;
-    if (tile >= sp.wtiles || base >= n) return;
+    if (base >= n) return;
     const size_t gb = (size_t)j * m.cap;
     double rho[PT], phi[PT], phib[PT], nlw[PT];
     double lwmax = -__builtin_inf();
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
-        rho[i] = 0.0;
-        phi[i] = 0.0;
-        phib[i] = 0.0;
-        nlw[i] = __builtin_inf();
-        if (s < n) {
-            rho[i] = geo.rho[gb + s];
-            phi[i] = geo.phi[gb + s];
-            phib[i] = geo.phib[gb + s];
-            const double lw = geo.lw[gb + s];
-            nlw[i] = -lw;
-            lwmax = lw > lwmax ? lw : lwmax;
-        }
+        // unconditional loads (lanes past the group's end read its slot base
+        // and drop the value), so all of them are in flight at once
+        const bool ok = s < n;
+        const size_t g = gb + (ok ? s : base);
+        const double r = geo.rho[g], a = geo.phi[g], b = geo.phib[g], lw = geo.lw[g];
+        rho[i] = ok ? r : 0.0;
+        phi[i] = ok ? a : 0.0;
+        phib[i] = ok ? b : 0.0;
+        nlw[i] = ok ? -lw : __builtin_inf();
+        lwmax = ok && lw > lwmax ? lw : lwmax;
     }
     if (zc == 0) {
         double ws = 0.0;
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
             const int s = base + i * 64 + lane;
-            if (s < n) ws += (double)W[gb + s];
+            const double wv = (double)W[gb + (s < n ? s : base)];
+            ws += s < n ? wv : 0.0;
         }
         ws = wave_sum(ws);
         if (lane == 0) pw[(size_t)j * sp.wtiles + tile] = ws;
@@ -1023,11 +1095,11 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
 #pragma unroll
     for (int i = 0; i < PT; ++i) nlw[i] += hw;
     const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
-    const int p0 = zc * MZ, p1 = (p0 + MZ < M) ? p0 + MZ : M;
+    const int p0 = 0, p1 = M;
     const double* zs = zp.zs + 2 * (size_t)off;
     const int nA = zp.nA[gr.run];
-    auto one = [&](int p, const double* ang) {
-        const double zr = zs[2 * p], zt = zs[2 * p + 1];
+    const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
+    auto one = [&](int p, double zr, double zt, const double* ang) {
         T s = 0;
 #pragma unroll
         for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], nlw[i]));
@@ -1037,36 +1109,71 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
             ph[pbase + p] = (int)hw;
         }
     };
+    // every nlw is >= 0 (hw is the ceiling of the tile's largest log weight).
+    // Lane l tests measurement c0 + l; the ones left are read from their lane.
+    auto frame = [&](int pa, int pb, const double* ang, double lo, double hi) {
+        for (int c0 = pa; c0 < pb; c0 += 64) {
+            const int p = c0 + lane;
+            bool need = false;
+            double zr = 0.0, zt = 0.0;
+            if (p < pb) {
+                zr = zs[2 * p];
+                zt = zs[2 * p + 1];
+                need = box_dist2(zr, zt, bx.rlo, bx.rhi, lo, hi) <= exp2_cut<T>();
+                if (!need) {
+                    ps[pbase + p] = 0.0;
+                    ph[pbase + p] = (int)hw;
+                }
+            }
+            for (uint64_t live = __ballot(need); live; live &= live - 1) {
+                const int l = __builtin_ctzll(live);
+                one(c0 + l, lane_value(zr, l), lane_value(zt, l), ang);
+            }
+        }
+    };
     const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
-    for (int p = p0; p < a1; ++p) one(p, phi);
-    for (int p = b0; p < p1; ++p) one(p, phib);
+    frame(p0, a1, phi, bx.alo, bx.ahi);
+    frame(b0, p1, phib, bx.blo, bx.bhi);
+}
+
+template <typename T, int PT>
+__global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __restrict__ gd, Geo geo,
+                                                   const T* __restrict__ W, const int* __restrict__ ncur,
+                                                   int Mall, const ZWin* __restrict__ win, ZPrepC zp, int Mmax,
+                                                   Split sp, double* __restrict__ ps, int* __restrict__ ph,
+                                                   double* __restrict__ pw, int K, const int* __restrict__ tpre,
+                                                   const int* __restrict__ tgrp)
+{
+    const int total = tpre[K];
+    for (int t = blockIdx.x * 4 + wave_in_block(); t < total; t += gridDim.x * 4) {
+        const int j = tgrp[t];
+        cz_frames_tile<T, PT>(m, gd, geo, W, ncur, Mall, win, zp, Mmax, sp, ps, ph, pw, j, t - tpre[j]);
+    }
 }
 
 // second pass in frames: as k_weight<T, PT, true>, the measurement side read
-// from the prepared order
+// from the prepared order, tiles culled; tile `tile` of group j, every
+// measurement of the run in one wavefront
 template <typename T, int PT>
-__global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
-                                                       const int* __restrict__ ncur, int Mall,
-                                                       const ZWin* __restrict__ win, ZPrepC zp, int Mmax, Split sp,
-                                                       const int* __restrict__ zHs, const T* __restrict__ zFs,
-                                                       const int* __restrict__ zfls, double* __restrict__ pzeta,
-                                                       T* __restrict__ accp)
+__device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp* __restrict__ gd, const SoA<T>& st,
+                                                   const Geo& geo, const int* __restrict__ ncur, int Mall,
+                                                   const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
+                                                   const Split& sp, const int* __restrict__ zHs,
+                                                   const T* __restrict__ zFs, const int* __restrict__ zfls,
+                                                   double* __restrict__ pzeta, T* __restrict__ accp, int j, int tile)
 {
     constexpr int WT = 64 * PT;
-    const int j = blockIdx.y;
     const Grp gr = gd[j];
     int off = 0, M = Mall;
     if (win) {
         off = win[gr.run].off;
         M = win[gr.run].M;
     }
-    const int zsplit = zsplit_for(M, sp.mz), MZ = (M + zsplit - 1) / zsplit;
+    const int zc = 0;
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + wave_in_block();
-    const int tile = gw / zsplit, zc = gw - tile * zsplit;
     const int n = ncur[j];
     const int base = tile * WT;
-    if (tile >= sp.wtiles || base >= n) return;
+    if (base >= n) return;
     const size_t gb = (size_t)j * m.cap;
     const size_t zb = (size_t)j * Mmax;
     double rho[PT], phi[PT], phib[PT];
@@ -1077,32 +1184,27 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
-        rho[i] = 0.0;
-        phi[i] = 0.0;
-        phib[i] = 0.0;
+        // unconditional loads, values of lanes past the group's end dropped
+        const bool ok = s < n;
+        const size_t g = gb + (ok ? s : base);
+        const double r = geo.rho[g], a = geo.phi[g], b = geo.phib[g];
+        const T wv = st.w[g];
+        T xv[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) xv[d] = st.x[d][g];
+        rho[i] = ok ? r : 0.0;
+        phi[i] = ok ? a : 0.0;
+        phib[i] = ok ? b : 0.0;
         acc[i] = 0;
-        uw[i] = 0;
+        uw[i] = ok ? (T)(m.wscale * (double)wv) : (T)0;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) ux[d][i] = 0;
-        if (s < n) {
-            rho[i] = geo.rho[gb + s];
-            phi[i] = geo.phi[gb + s];
-            phib[i] = geo.phib[gb + s];
-            uw[i] = (T)(m.wscale * (double)st.w[gb + s]);
-#pragma unroll
-            for (int d = 0; d < 4; ++d) ux[d][i] = st.x[d][gb + s];
-        }
+        for (int d = 0; d < 4; ++d) ux[d][i] = ok ? xv[d] : (T)0;
     }
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
-    const int p0 = zc * MZ, p1 = (p0 + MZ < M) ? p0 + MZ : M;
+    const int p0 = 0, p1 = M;
     const double* zs = zp.zs + 2 * (size_t)off;
     const int nA = zp.nA[gr.run];
-    auto one = [&](int p, const double* ang) {
-        // every per-measurement operand in frame order: independent scalar loads
-        const double zr = zs[2 * p], zt = zs[2 * p + 1];
-        const double H = (double)zHs[zb + p];
-        const T F = zFs[zb + p];
-        const int fl = zfls[zb + p];
+    auto one = [&](int p, double zr, double zt, double H, T F, int fl, const double* ang) {
         if (fl == 0) {
 #pragma unroll
             for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H)) * F;
@@ -1131,14 +1233,64 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
             }
         }
     };
+    const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
+    // the exponent is the squared distance plus the measurement's shift H;
+    // lane l tests and holds the operands of measurement c0 + l (frame order)
+    auto frame = [&](int pa, int pb, const double* ang, double lo, double hi) {
+        for (int c0 = pa; c0 < pb; c0 += 64) {
+            const int p = c0 + lane;
+            bool need = false;
+            double zr = 0.0, zt = 0.0, H = 0.0;
+            T F = 0;
+            int fl = 0;
+            if (p < pb) {
+                zr = zs[2 * p];
+                zt = zs[2 * p + 1];
+                H = (double)zHs[zb + p];
+                F = zFs[zb + p];
+                fl = zfls[zb + p];
+                need = box_dist2(zr, zt, bx.rlo, bx.rhi, lo, hi) + H <= exp2_cut<T>();
+                if (!need && fl != 0) {
+                    double* o = pzeta + (pz + (fl - 1)) * 5;
+                    o[0] = 0.0;
+                    o[1] = 0.0;
+                    o[2] = 0.0;
+                    o[3] = 0.0;
+                    o[4] = 0.0;
+                }
+            }
+            for (uint64_t live = __ballot(need); live; live &= live - 1) {
+                const int l = __builtin_ctzll(live);
+                one(c0 + l, lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l),
+                    lane_value(fl, l), ang);
+            }
+        }
+    };
     const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
-    for (int p = p0; p < a1; ++p) one(p, phi);
-    for (int p = b0; p < p1; ++p) one(p, phib);
+    frame(p0, a1, phi, bx.alo, bx.ahi);
+    frame(b0, p1, phib, bx.blo, bx.bhi);
     const size_t KC = (size_t)m.K * m.cap;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
         if (s < n) accp[(size_t)zc * KC + gb + s] = acc[i];
+    }
+}
+
+template <typename T, int PT>
+__global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                       const int* __restrict__ ncur, int Mall,
+                                                       const ZWin* __restrict__ win, ZPrepC zp, int Mmax, Split sp,
+                                                       const int* __restrict__ zHs, const T* __restrict__ zFs,
+                                                       const int* __restrict__ zfls, double* __restrict__ pzeta,
+                                                       T* __restrict__ accp, int K, const int* __restrict__ tpre,
+                                                       const int* __restrict__ tgrp)
+{
+    const int total = tpre[K];
+    for (int t = blockIdx.x * 4 + wave_in_block(); t < total; t += gridDim.x * 4) {
+        const int j = tgrp[t];
+        weight_frames_tile<T, PT>(m, gd, st, geo, ncur, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, j,
+                                  t - tpre[j]);
     }
 }
 
@@ -1297,15 +1449,13 @@ __global__ __launch_bounds__(256) void k_weight(DevModel m, const Grp* __restric
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
-        rho[i] = 0.0;
-        phi[i] = 0.0;
-        phib[i] = 0.0;
+        const bool ok = s < n;
+        const size_t g = gb + (ok ? s : base);
+        const double r = geo.rho[g], a = geo.phi[g], b = FRAMES ? geo.phib[g] : 0.0;
+        rho[i] = ok ? r : 0.0;
+        phi[i] = ok ? a : 0.0;
+        phib[i] = ok ? b : 0.0;
         acc[i] = 0;
-        if (s < n) {
-            rho[i] = geo.rho[gb + s];
-            phi[i] = geo.phi[gb + s];
-            if (FRAMES) phib[i] = geo.phib[gb + s];
-        }
     }
     // exponential of one pair in the measurement's frame (or with the wrap)
     auto term = [&](double zr, double zt, bool fb, double H, int i) -> T {
@@ -1621,6 +1771,145 @@ __global__ __launch_bounds__(256) void k_wmax(DevModel m, const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Step 5, parent order: the parents of every group are taken in bearing-
+// bucket order (buckets ascending, slot order inside a bucket) so that the
+// children of nearby parents sit together and a likelihood-pass tile spans a
+// narrow bearing range.  The bucket is the "diamond angle" d in [0, 4) of the
+// offset from the sensor (monotonic in the bearing counter-clockwise from +x,
+// one correctly rounded division), times BEARING_BUCKETS/4, rounded down.
+// A stable counting sort in three launches: per-tile bucket histograms,
+// bucket-major offsets per group, scatter into the other particle set.
+// ---------------------------------------------------------------------------
+constexpr int BEARING_BUCKETS = 64;
+
+__device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
+{
+    const double dx = x - m.sx, dy = y - m.sy;
+    double d;
+    if (dx == 0.0 && dy == 0.0) d = 0.0;
+    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
+    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+    const int b = (int)floor(d * (BEARING_BUCKETS / 4.0));
+    return b < 0 ? 0 : (b > BEARING_BUCKETS - 1 ? BEARING_BUCKETS - 1 : b);
+}
+
+// The sort runs over the slots [first_j, end_j) of every group j: all of a
+// group's particles (first == nullptr: from slot 0) before the resampling, or
+// its births once drawn (first = the survivor count).
+__device__ __forceinline__ int range_first(const int* first, int j) { return first ? first[j] : 0; }
+
+// grid (tiles, K), 256 threads: bucket of every slot, per-tile histograms
+template <typename T>
+__global__ __launch_bounds__(256) void k_bk_hist(DevModel m, SoA<T> st, const int* __restrict__ first,
+                                                 const int* __restrict__ end, int rtiles, int* __restrict__ bkt,
+                                                 int* __restrict__ hist)
+{
+    __shared__ int h[BEARING_BUCKETS];
+    const int j = blockIdx.y, t = blockIdx.x;
+    const int a = range_first(first, j), n = end[j] - a;
+    if (t * 256 >= n) return;
+    if (threadIdx.x < BEARING_BUCKETS) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int s = t * 256 + threadIdx.x;
+    const size_t g = (size_t)j * m.cap + a + s;
+    if (s < n) {
+        const int b = bearing_bucket(m, (double)st.x[0][g], (double)st.x[2][g]);
+        bkt[g] = b;
+        atomicAdd(&h[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < BEARING_BUCKETS)
+        hist[((size_t)j * rtiles + t) * BEARING_BUCKETS + threadIdx.x] = h[threadIdx.x];
+}
+
+// grid (K), 1024 threads: bucket-major exclusive offsets, off[t][b] = all
+// slots of lower buckets + slots of bucket b in lower tiles.  Lane b of wave
+// g sums bucket b over the g-th of 16 contiguous tile segments; the segment
+// totals meet in LDS.
+__global__ __launch_bounds__(1024) void k_bk_scan(const int* __restrict__ first, const int* __restrict__ end,
+                                                  int rtiles, const int* __restrict__ hist, int* __restrict__ off)
+{
+    __shared__ int seg[16][BEARING_BUCKETS];
+    __shared__ int base[BEARING_BUCKETS];
+    const int j = blockIdx.x, b = threadIdx.x & 63, g = wave_in_block();
+    const int ntl = (end[j] - range_first(first, j) + 255) / 256;
+    const int per = (ntl + 15) / 16;
+    const int t0 = g * per < ntl ? g * per : ntl, t1 = t0 + per < ntl ? t0 + per : ntl;
+    const int* hj = hist + (size_t)j * rtiles * BEARING_BUCKETS;
+    int tot = 0;
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t) tot += hj[(size_t)t * BEARING_BUCKETS + b];
+    seg[g][b] = tot;
+    __syncthreads();
+    if (g == 0) {
+        int all = 0;
+        for (int q = 0; q < 16; ++q) all += seg[q][b];
+        const int incl = (int)wave_incl_scan((double)all);  // exact: counts stay below 2^53
+        base[b] = incl - all;
+    }
+    __syncthreads();
+    int run = base[b];
+    for (int q = 0; q < g; ++q) run += seg[q][b];
+    int* oj = off + (size_t)j * rtiles * BEARING_BUCKETS;
+    for (int t = t0; t < t1; ++t) {
+        oj[(size_t)t * BEARING_BUCKETS + b] = run;
+        run += hj[(size_t)t * BEARING_BUCKETS + b];
+    }
+}
+
+// grid (tiles, K), 256 threads: slot s of the range goes to off[t][b] + (slots
+// of bucket b before it in its tile), in the other particle set
+template <typename T>
+__global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T> out, const int* __restrict__ first,
+                                                    const int* __restrict__ end, int rtiles,
+                                                    const int* __restrict__ bkt, const int* __restrict__ off)
+{
+    __shared__ int wh[4][BEARING_BUCKETS];  // per-wave bucket counts
+    const int j = blockIdx.y, t = blockIdx.x;
+    const int a = range_first(first, j), n = end[j] - a;
+    if (t * 256 >= n) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 4 * BEARING_BUCKETS; i += 256) (&wh[0][0])[i] = 0;
+    __syncthreads();
+    const int s = t * 256 + threadIdx.x;
+    const size_t gb = (size_t)j * m.cap + a;
+    const bool live = s < n;
+    const int b = live ? bkt[gb + s] : BEARING_BUCKETS;
+    // lanes of this wave with the same bucket: intersect the ballots of the
+    // seven bits of b (bit 6 tells the out-of-range lanes apart)
+    unsigned long long peers = ~0ull;
+    for (int bit = 0; bit < 7; ++bit) {
+        const unsigned long long v = __ballot((b >> bit) & 1);
+        peers &= ((b >> bit) & 1) ? v : ~v;
+    }
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int rank = __popcll(peers & below);
+    if (live && rank == 0) wh[wv][b] = __popcll(peers);
+    __syncthreads();
+    if (!live) return;
+    for (int w = 0; w < wv; ++w) rank += wh[w][b];
+    const int dst = off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] + rank;
+    for (int d = 0; d < m.dim; ++d) out.x[d][gb + dst] = in.x[d][gb + s];
+    out.w[gb + dst] = in.w[gb + s];
+}
+
+// births back from the other set in their sorted order, with their geometry
+// (a function of the stored state).  grid (ceil(Jmax/256), K)
+template <typename T>
+__global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T> to, Geo geo,
+                                                 const int* __restrict__ first, const int* __restrict__ end)
+{
+    const int j = blockIdx.y;
+    const int s = first[j] + blockIdx.x * 256 + threadIdx.x;
+    if (s >= end[j]) return;
+    const size_t g = (size_t)j * m.cap + s;
+    for (int d = 0; d < m.dim; ++d) to.x[d][g] = from.x[d][g];
+    const T x = from.x[0][g], y = from.x[2][g], w = from.w[g];
+    to.w[g] = w;
+    store_geometry(m, geo, g, (double)x, (double)y, (double)w);
+}
+
+// ---------------------------------------------------------------------------
 // Step 5, resampling, pass A: integer-valued weights q = floor(w 2^S) and their
 // exact per-tile totals (tiles of 256 parents).  grid (rtiles, K).
 // ---------------------------------------------------------------------------
@@ -1772,8 +2061,10 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
 
 // ---------------------------------------------------------------------------
 // Step 6, ring exchange j -> j+1 within each run.  One count L = floor(rho_x
-// min_j n_j) over the run's groups; group j's chosen slots are S_j(m) =
-// (o_j + m floor(n_j/L)) mod n_j with o_j from the EXCHANGE stream, and the
+// min_j n_j) over the run's groups; group j's chosen slots are a systematic
+// sample, one per stratum: S_j(m) = floor((m n_j + b_j)/L), b_j = floor(u_j
+// n_j) with u_j from the EXCHANGE stream, so S_j(m) sits at the quantile m/L
+// of the group's slot order (kept in bearing order by the resampling); the
 // couple in S_j(m) replaces the one in S_{j+1}(m).  A gather into a staging
 // buffer followed by a scatter (two launches) makes every read see the state
 // before the exchange, so the exchange is a permutation of the particles.
@@ -1798,8 +2089,8 @@ __device__ __forceinline__ uint64_t exchange_slot(const DevModel& m, const Grp& 
                                                   uint32_t step)
 {
     const Block4 a = rng_block(m.key0, m.key1, (uint32_t)jl, step, RNG_EXCHANGE, 0, gr.rng_run);
-    const uint64_t o = ((uint64_t)a.a * (uint64_t)nj) >> 32;
-    return (o + (uint64_t)mm * (uint64_t)(nj / L)) % (uint64_t)nj;
+    const uint64_t b = ((uint64_t)a.a * (uint64_t)nj) >> 32;
+    return ((uint64_t)mm * (uint64_t)nj + b) / (uint64_t)L;
 }
 
 template <typename T>

@@ -54,7 +54,7 @@ constexpr int MZ_DEFAULT = 16;
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
     "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
-    "k_geom", "k_wfinal", "k_birth_meas", "k_mlp_infer", "k_birth_mix", "k_zprep",
+    "k_geom", "k_wfinal", "k_birth_meas", "k_mlp_infer", "k_birth_mix", "k_zprep", "k_bk_scatter", "k_bk_back",
 };
 
 struct Layout {
@@ -95,6 +95,7 @@ struct pphd_filter {
     int32_t* pin_win = nullptr;
     hipGraph_t graph[2] = {};          // captured batch steps, starting from particle set 0 / 1
     hipGraphExec_t graph_exec[2] = {};
+    int graph_next[2] = {0, 1};        // particle set a captured step leaves current
     size_t KC = 0;
     size_t esz = 8;
     hipStream_t stream = nullptr;
@@ -137,6 +138,8 @@ struct pphd_filter {
     int* nest = nullptr;
     double *tsum = nullptr, *massq = nullptr;
     int* counts = nullptr;
+    int *bkt = nullptr, *bhist = nullptr, *boff = nullptr;  // bearing-bucket order of the parents
+    int *tpre1 = nullptr, *tgrp1 = nullptr, *tpre2 = nullptr, *tgrp2 = nullptr;  // tile lists of the two passes
     void* stage = nullptr;
     // host side
     double* pin_z = nullptr;
@@ -232,6 +235,13 @@ size_t carve(pphd_filter* f, char* base)
     f->tsum = L.take<double>(base, K * f->rtiles * 8);
     f->massq = L.take<double>(base, K * 8);
     f->counts = L.take<int>(base, KC * 4);
+    f->bkt = L.take<int>(base, KC * 4);
+    f->tpre1 = L.take<int>(base, (K + 1) * 4);
+    f->tgrp1 = L.take<int>(base, K * f->wtiles_max * 4);
+    f->tpre2 = L.take<int>(base, (K + 1) * 4);
+    f->tgrp2 = L.take<int>(base, K * f->wtiles_max * 4);
+    f->bhist = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
+    f->boff = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->stage = L.take<char>(base, K * (size_t)f->Lmax * 6 * es);
     if (f->model.birth_proposal == 2) {
         f->mix_tab = L.take<double>(base, (size_t)f->z_cap * 4 * MIX_TAB * 8);
@@ -478,6 +488,9 @@ pphd_status launch(pphd_filter* f, int cls, F&& fn)
         if (s_ != PPHD_OK) return s_;                                \
     } while (0)
 
+template <typename T>
+pphd_status order_births(pphd_filter* f);
+
 template <typename T, int PT1, int PT2>
 pphd_status run_update(pphd_filter* f, const UpdArgs& a)
 {
@@ -521,17 +534,35 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         }
         f->mix_preset = false;
         f->births_pending = false;
+        if (dm.proposal != 0) {
+            pphd_status os = order_births<T>(f);
+            if (os != PPHD_OK) return os;
+        }
     }
     dim3 g1((f->wtiles1 * zs + 3) / 4, K), g2((f->wtiles2 * zs + 3) / 4, K);
     const ZPrepC zpc{ f->zprep.zs, f->zprep.orig, f->zprep.pos, f->zprep.nA };
     const bool frames = f->pass_mode == PASS_FRAMES;
     const ZSorted<T> zsort{ f->zHs, (T*)f->zFs, f->zfls };
+    // frame passes: one wavefront per tile of the tile lists, all of a run's
+    // measurements in it (one chunk); grids of at most 2048 workgroups
+    const int* tpre2 = f->wt2 == f->wt1 ? f->tpre1 : f->tpre2;
+    const int* tgrp2 = f->wt2 == f->wt1 ? f->tgrp1 : f->tgrp2;
+    const dim3 gl1((unsigned)std::min<int64_t>(2048, ((int64_t)K * f->wtiles1 + 3) / 4));
+    const dim3 gl2((unsigned)std::min<int64_t>(2048, ((int64_t)K * f->wtiles2 + 3) / 4));
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_ZPREP,
                hipLaunchKernelGGL(k_zprep, dim3(f->nruns), dim3(256), 0, f->stream, dm, a.dz, a.M, a.win, f->zprep));
+        LAUNCH(f, PPHD_K_ZPREP,
+               hipLaunchKernelGGL(k_tile_map, dim3(1), dim3(1024), 0, f->stream, f->ncur, K, f->wt1, f->tpre1,
+                                  f->tgrp1));
+        if (f->wt2 != f->wt1)
+            LAUNCH(f, PPHD_K_ZPREP,
+                   hipLaunchKernelGGL(k_tile_map, dim3(1), dim3(1024), 0, f->stream, f->ncur, K, f->wt2, f->tpre2,
+                                      f->tgrp2));
         LAUNCH(f, PPHD_K_CZ,
-               hipLaunchKernelGGL((k_cz_frames<T, PT1>), g1, dim3(256), 0, f->stream, dm, f->gd, geo, (const T*)st.w,
-                                  f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w));
+               hipLaunchKernelGGL((k_cz_frames<T, PT1>), gl1, dim3(256), 0, f->stream, dm, f->gd, geo,
+                                  (const T*)st.w, f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w, K,
+                                  f->tpre1, f->tgrp1));
     } else if (f->pass_mode == PASS_WRAP) {
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
@@ -548,9 +579,9 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                               (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand));
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_WEIGHT,
-               hipLaunchKernelGGL((k_weight_frames<T, PT2>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
-                                  a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
-                                  (T*)f->accp));
+               hipLaunchKernelGGL((k_weight_frames<T, PT2>), gl2, dim3(256), 0, f->stream, dm, f->gd, st, geo,
+                                  f->ncur, a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
+                                  (T*)f->accp, K, tpre2, tgrp2));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
@@ -559,7 +590,8 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     }
     LAUNCH(f, PPHD_K_WFINAL,
            hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
-                              (const T*)f->accp, a.M, a.win, f->mz, f->tiles256, f->p2mass, f->p2max));
+                              (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256, f->p2mass,
+                              f->p2max));
     LAUNCH(f, PPHD_K_FINALIZE,
            hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
@@ -592,6 +624,8 @@ pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
     LAUNCH(f, PPHD_K_PREDICT,
            hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
                               f->nsurv, f->ncur, step, dstep));
+    // births of the birth density are drawn by k_predict
+    if (f->dm.proposal == 0) return order_births<T>(f);
     return PPHD_OK;
 }
 
@@ -604,10 +638,52 @@ pphd_status run_init(pphd_filter* f)
     return PPHD_OK;
 }
 
+// Stable bearing-bucket order of the slots [first_j, ncur_j) of every group,
+// from the current particle set into the other one (first == nullptr: every
+// slot).  tiles: 256-slot tiles to cover the longest range.
+template <typename T>
+pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles)
+{
+    dim3 g(tiles, f->K);
+    SoA<T> cur = soa<T>(f, f->cur), oth = soa<T>(f, 1 - f->cur);
+    LAUNCH(f, cls,
+           hipLaunchKernelGGL((k_bk_hist<T>), g, dim3(256), 0, f->stream, f->dm, cur, first, f->ncur, f->rtiles,
+                              f->bkt, f->bhist));
+    LAUNCH(f, cls,
+           hipLaunchKernelGGL(k_bk_scan, dim3(f->K), dim3(1024), 0, f->stream, first, f->ncur, f->rtiles, f->bhist,
+                              f->boff));
+    LAUNCH(f, cls,
+           hipLaunchKernelGGL((k_bk_scatter<T>), g, dim3(256), 0, f->stream, f->dm, cur, oth, first, f->ncur,
+                              f->rtiles, f->bkt, f->boff));
+    return PPHD_OK;
+}
+
+// the births of every group (slots [nsurv_j, ncur_j)) in bearing-bucket order
+// once drawn: sorted into the other set, then back with their geometry
+template <typename T>
+pphd_status order_births(pphd_filter* f)
+{
+    if (f->Jmax <= 0) return PPHD_OK;
+    const int bt = (f->Jmax + 255) / 256;
+    pphd_status s = bucket_order<T>(f, PPHD_K_BIRTH_ORDER, f->nsurv, bt);
+    if (s != PPHD_OK) return s;
+    LAUNCH(f, PPHD_K_BIRTH_ORDER,
+           hipLaunchKernelGGL((k_bk_back<T>), dim3(bt, f->K), dim3(256), 0, f->stream, f->dm, soa<T>(f, 1 - f->cur),
+                              soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur));
+    return PPHD_OK;
+}
+
 template <typename T>
 pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
     dim3 g(f->rtiles, f->K);
+    // parents into bearing-bucket order (into the other set), then the
+    // systematic resampling back into this one
+    {
+        pphd_status s = bucket_order<T>(f, PPHD_K_RS_ORDER, nullptr, f->rtiles);
+        if (s != PPHD_OK) return s;
+        f->cur = 1 - f->cur;
+    }
     SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
     LAUNCH(f, PPHD_K_RS_TILES,
            hipLaunchKernelGGL((k_rs_tiles<T>), g, dim3(256), 0, f->stream, f->dm, (const T*)in.w, f->ncur, f->rsS,
@@ -1251,6 +1327,7 @@ pphd_status pphd_batch_capture(pphd_filter* f, const double* d_z, int32_t z_coun
         }
         s = f->prec == PPHD_FP64 ? step_all<double>(f, d_z, z_count, d_windows, (EstimateRec*)d_out, cap, d_n_out)
                                  : step_all<float>(f, d_z, z_count, d_windows, (EstimateRec*)d_out, cap, d_n_out);
+        f->graph_next[i] = f->cur;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (s == PPHD_OK && e != hipSuccess) s = fail(PPHD_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
@@ -1276,7 +1353,7 @@ pphd_status pphd_batch_launch(pphd_filter* f)
     if (f->phase != PPHD_PHASE_READY && f->phase != PPHD_PHASE_RESAMPLED)
         return fail(PPHD_ESTATE, "launch needs phase READY or RESAMPLED (have %d)", f->phase);
     HIP_TRY(hipGraphLaunch(f->graph_exec[f->cur], f->stream));
-    f->cur = 1 - f->cur;
+    f->cur = f->graph_next[f->cur];
     f->phase = PPHD_PHASE_READY;
     return PPHD_OK;
 }

@@ -21,7 +21,7 @@ PPHD_FP64, PPHD_FP32 = 0, 1
 PHASE_READY, PHASE_PREDICTED, PHASE_UPDATED, PHASE_RESAMPLED = 1, 2, 3, 4
 KERNEL_CLASSES = ["predict", "cz", "cz_combine", "weight", "finalize", "fuse", "rs_tiles", "rs_expand",
                   "xchg_gather", "xchg_scatter", "init", "wmax", "geom", "wfinal", "birth_meas",
-                  "mlp_infer", "birth_mix", "zprep"]
+                  "mlp_infer", "birth_mix", "zprep", "rs_order", "birth_order"]
 MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 128, 36, 38052
 K_COUNT = len(KERNEL_CLASSES)
 

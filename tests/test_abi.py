@@ -57,7 +57,7 @@ def test_workspace_size_and_argument_errors():
     with pytest.raises(pphd.PphdError):
         pphd.pphd_workspace_size(m, w["cap"], 0)
     assert pphd.pphd_kernel_name(3) == "k_weight"
-    assert [pphd.pphd_kernel_name(i) for i in range(pphd.K_COUNT)][-3:] == ["k_mlp_infer", "k_birth_mix", "k_zprep"]
+    assert [pphd.pphd_kernel_name(i) for i in range(pphd.K_COUNT)][-5:] == ["k_mlp_infer", "k_birth_mix", "k_zprep", "k_bk_scatter", "k_bk_back"]
     assert pphd.pphd_kernel_name(pphd.K_COUNT) is None
 
 
