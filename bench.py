@@ -13,6 +13,7 @@ Prints one JSON line:
   cpu_baseline the FP64 oracle on the host for a bounded sample of the run
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,13 +25,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue peak of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# lane-operations per second (non-packed FP32 / FP64 instructions).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic issue slots of one likelihood evaluation of a particle-measurement
-# pair: 2 residuals, 2 for the bearing wrap, 2 fused multiply-adds for the
-# Mahalanobis term, 1 accumulate, plus one exponential at quarter rate (4).
-SLOTS_PER_PAIR_EVAL = 11
+# HBM peak of the MI355X (bytes/s).
+HBM_PEAK_GBS = 8000.0
+# Wave tile of the frame passes (64 lanes x 4 particles per lane, the tuned shape).
+PASS_TILE = 256
+# Kernel sources a stored counter summary was taken on.
+KERNEL_SOURCES = ("paper_1503_03769_amd/csrc/kernels.h", "paper_1503_03769_amd/csrc/pphd.hip")
+
+
+def pass_bytes(counts, Mg, esz, tile=PASS_TILE):
+    """Algorithmic HBM bytes of one launch of each likelihood pass, from the
+    particle count and the measurement count of every group.
+      first pass:  per particle the geometry (scaled range, two frame bearings,
+                   log2 weight: 4 doubles) and the weight; per tile and
+                   measurement the partial sum and its exponent (8 + 4 bytes),
+                   per tile the weight total (8 bytes);
+      second pass: per particle the geometry (3 doubles), the weight and the
+                   four CV components read and the updated sum written.
+    The measurement rows a tile reads are shared by every tile of the run and
+    are not counted."""
+    counts = np.asarray(counts, dtype=np.int64)
+    Mg = np.asarray(Mg, dtype=np.int64)
+    n = int(counts.sum())
+    tiles = -(-counts // tile)
+    cz = n * (32 + esz) + int((tiles * (12 * Mg + 8)).sum())
+    weight = n * (24 + 6 * esz)
+    return cz, weight
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel_class, workload):
+    """HBM bytes per launch of the dominant pass from the committed counter
+    summary (profiles/traffic_<class>_<workload>.txt: FETCH_SIZE and
+    WRITE_SIZE per dispatch, scaled by a plain copy's counters), or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
 def parse():
@@ -135,6 +182,8 @@ def main():
     kern = {}
     pairs = []
     parts = []
+    pbytes = []
+    esz = 4 if prec == pphd.PPHD_FP32 else 8
     if not args.no_timing_pass:
         g = make()
         g.init()
@@ -146,6 +195,7 @@ def main():
                 n = g.read_counts()
                 pairs.append(int(n.sum()) * Ms[k])
                 parts.append(int(n.sum()))
+                pbytes.append(pass_bytes(n, np.full(len(n), Ms[k]), esz))
             g.update(zall[offs[k]:offs[k + 1]])
             g.extract_device(est_dev[k], nest_dev[k:k + 1], cap_est)
             g.resample(k)
@@ -194,7 +244,7 @@ def main():
         per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
         line["kernels"] = per
         # dominant kernel: the larger of the two likelihood passes
-        line["roofline"] = roofline(pphd, kern, float(np.mean(pairs)))
+        line["roofline"] = roofline(pphd, kern, np.mean(pbytes, axis=0), args.workload)
     if mlp_info is not None:
         # the same run with births from the birth density itself, same budget
         from paper_1503_03769_amd.runs import run_ospa
@@ -209,22 +259,27 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def roofline(pphd, kern, pairs_per_launch):
-    """The larger of the two likelihood passes against the VALU issue rate."""
+def roofline(pphd, kern, bytes_per_launch, workload):
+    """The larger of the two likelihood passes against HBM bandwidth.  Both
+    skip, per tile, the measurements whose terms are exactly zero, so their
+    floor is moving their particles' data, not evaluating every pair."""
     dom = max(("cz", "weight"), key=lambda c: kern[c][0])
     ms, n = kern[dom]
     avg_s = ms / 1e3 / n
-    achieved = SLOTS_PER_PAIR_EVAL * pairs_per_launch / avg_s / 1e12
+    B = float(bytes_per_launch[0] if dom == "cz" else bytes_per_launch[1])
+    achieved = B / avg_s / 1e9
+    traffic = stored_traffic(dom, workload)
     return {
-        "kernel": pphd.pphd_kernel_name(pphd.KERNEL_CLASSES.index(dom)),
-        "bound": "alu",
+        # every bench workload has clutter, so the passes run in bearing frames
+        "kernel": pphd.pphd_kernel_name(pphd.KERNEL_CLASSES.index(dom)) + "_frames",
+        "bound": "hbm",
         "achieved": achieved,
-        "peak": VALU_PEAK_TOPS,
-        "unit": "TOP/s",
-        "frac": achieved / VALU_PEAK_TOPS,
-        "traffic": None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
         "avg_launch_us": avg_s * 1e6,
-        "work_per_launch": f"{pairs_per_launch:.4g} pairs x {SLOTS_PER_PAIR_EVAL} issue slots",
+        "bytes_per_launch": B,
     }
 
 
@@ -295,7 +350,8 @@ def bench_batch(args, w):
     b.close()
     del b
 
-    kern, pairs, parts, ospas = {}, [], [], []
+    kern, pairs, parts, ospas, pbytes = {}, [], [], [], []
+    esz = 4 if prec == pphd.PPHD_FP32 else 8
     group_run = np.repeat(np.arange(R), [int(r["partitions"]) for r in runs])  # run of every group
     # ---- pass B: eager batch, per-kernel HIP-event times, counts, estimates --
     g = make_batch()
@@ -311,6 +367,7 @@ def bench_batch(args, w):
             n = g.read_counts()
             pairs.append(int(np.dot(n, Ms[k][group_run])))
             parts.append(int(n.sum()))
+            pbytes.append(pass_bytes(n, Ms[k][group_run], esz))
         g.update_device(zdev[k], zdev[k].shape[0], wdev[k])
         g.extract_device(est_hist[k], n_hist[k], Mx)
         g.resample(k)
@@ -401,7 +458,7 @@ def bench_batch(args, w):
     if kern:
         per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
         line["kernels"] = per
-        line["roofline"] = roofline(pphd, kern, float(np.mean(pairs)))
+        line["roofline"] = roofline(pphd, kern, np.mean(pbytes, axis=0), args.workload)
     if mlp_info is not None:
         line["learned_proposal"] = mlp_info
     if args.cpu_seconds > 0:
