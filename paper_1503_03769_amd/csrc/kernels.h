@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
     if (m.dim == 5) st.x[4][g] = (T)v[4];
     const T tw = (T)w;
     st.w[g] = tw;
-    store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
+    // births get their geometry once put in bearing order
+    if (s < ns) store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
 }
 
 // dim 5: the turn rate of a birth drawn from a measurement-driven or learned
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
     st.x[3][g] = (T)(m.sigma_v * n2);
     if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
     st.w[g] = tw;
-    store_geometry(m, geo, g, (double)tx, (double)ty, (double)tw);
+    // the geometry comes with the bearing order (k_birth_sort / k_bk_back)
 }
 
 // ---------------------------------------------------------------------------
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(1024) void k_birth_mix(DevModel m, const Grp* __res
         if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
         const T tw = (T)w;
         st.w[g] = tw;
-        store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
+        // the geometry comes with the bearing order (k_birth_sort / k_bk_back)
     }
 }
 
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(256) void k_birth_mix_lanes(DevModel m, const Grp* 
     if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
     const T tw = (T)w;
     st.w[g] = tw;
-    store_geometry(m, geo, g, (double)tx[0], (double)tx[2], (double)tw);
+    // the geometry comes with the bearing order (k_birth_sort / k_bk_back)
 }
 
 // scaled squared residual q(z, x) + c
@@ -980,32 +981,43 @@ __device__ __forceinline__ constexpr double exp2_cut<float>() { return 200.0; }
 template <>
 __device__ __forceinline__ constexpr double exp2_cut<double>() { return 1100.0; }
 
+// Bounds of a wave tile's scaled range and two frame bearings, in float.
+// Float rounding moves the bound by far less than the cut's margin over the
+// underflow point (50 in float, 25 in double, against errors below 1e-2 at
+// these scales), so a measurement whose bound passes the cut still has
+// exactly zero terms.
 struct TileBox {
-    double rlo, rhi, alo, ahi, blo, bhi;  // range, frame-A bearing, frame-B bearing
+    float rlo, rhi, alo, ahi, blo, bhi;
 };
+__device__ __forceinline__ float wave_min_f(float v) { return -wave_max(-v); }
 template <int PT>
 __device__ __forceinline__ TileBox tile_box(const double* rho, const double* phi, const double* phib, int base, int n,
                                             int lane)
 {
-    double rlo = __builtin_inf(), rhi = -__builtin_inf(), alo = rlo, ahi = rhi, blo = rlo, bhi = rhi;
+    const float inf = __builtin_inff();
+    float rlo = inf, rhi = -inf, alo = inf, ahi = -inf, blo = inf, bhi = -inf;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         if (base + i * 64 + lane < n) {
-            rlo = fmin(rlo, rho[i]);
-            rhi = fmax(rhi, rho[i]);
-            alo = fmin(alo, phi[i]);
-            ahi = fmax(ahi, phi[i]);
-            blo = fmin(blo, phib[i]);
-            bhi = fmax(bhi, phib[i]);
+            const float r = (float)rho[i], a = (float)phi[i], c = (float)phib[i];
+            rlo = fminf(rlo, r);
+            rhi = fmaxf(rhi, r);
+            alo = fminf(alo, a);
+            ahi = fmaxf(ahi, a);
+            blo = fminf(blo, c);
+            bhi = fmaxf(bhi, c);
         }
     }
-    return TileBox{ -wave_max(-rlo), wave_max(rhi), -wave_max(-alo), wave_max(ahi), -wave_max(-blo), wave_max(bhi) };
+    return TileBox{ wave_min_f(rlo), wave_max(rhi), wave_min_f(alo), wave_max(ahi), wave_min_f(blo), wave_max(bhi) };
 }
-__device__ __forceinline__ double box_dist2(double zr, double zt, double rlo, double rhi, double lo, double hi)
+// the measurement's terms in the tile can reach 2^-cut: squared distance
+// from the box in the measurement's frame, plus the pass's shift
+__device__ __forceinline__ bool box_needed(const TileBox& b, bool frame_b, float zr, float zt, float shift, float cut)
 {
-    const double dr = fmax(0.0, fmax(rlo - zr, zr - rhi));
-    const double dt = fmax(0.0, fmax(lo - zt, zt - hi));
-    return fma(dr, dr, dt * dt);
+    const float lo = frame_b ? b.blo : b.alo, hi = frame_b ? b.bhi : b.ahi;
+    const float dr = fmaxf(0.0f, fmaxf(b.rlo - zr, zr - b.rhi));
+    const float dt = fmaxf(0.0f, fmaxf(lo - zt, zt - hi));
+    return fmaf(dr, dr, fmaf(dt, dt, shift)) <= cut;
 }
 
 // ---------------------------------------------------------------------------
@@ -1063,6 +1075,12 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
     const int base = tile * WT;
     if (base >= n) return;
     const size_t gb = (size_t)j * m.cap;
+    const double* zs = zp.zs + 2 * (size_t)off;
+    const int nA = zp.nA[gr.run];
+    // the first 64 measurements of each frame, loaded with the particles
+    const int qa = lane < nA && lane < M ? lane : 0, qb = nA + lane < M ? nA + lane : 0;
+    const double zra0 = M > 0 ? zs[2 * qa] : 0.0, zta0 = M > 0 ? zs[2 * qa + 1] : 0.0;
+    const double zrb0 = M > 0 ? zs[2 * qb] : 0.0, ztb0 = M > 0 ? zs[2 * qb + 1] : 0.0;
     double rho[PT], phi[PT], phib[PT], nlw[PT];
     double lwmax = -__builtin_inf();
 #pragma unroll
@@ -1096,8 +1114,6 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
     for (int i = 0; i < PT; ++i) nlw[i] += hw;
     const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
     const int p0 = 0, p1 = M;
-    const double* zs = zp.zs + 2 * (size_t)off;
-    const int nA = zp.nA[gr.run];
     const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
     auto one = [&](int p, double zr, double zt, const double* ang) {
         T s = 0;
@@ -1109,31 +1125,57 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
             ph[pbase + p] = (int)hw;
         }
     };
+    // two measurements at once: independent chains for the latency-bound
+    // tiles that keep many of them
+    auto two = [&](int p, double zr, double zt, int q, double yr, double yt, const double* ang) {
+        T s = 0, t = 0;
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            s += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], nlw[i]));
+            t += fast_exp2(-(T)sq_resid_nowrap(yr, yt, rho[i], ang[i], nlw[i]));
+        }
+        const T sw = wave_sum_last(s), tw = wave_sum_last(t);
+        if (lane == 63) {
+            ps[pbase + p] = (double)sw;
+            ph[pbase + p] = (int)hw;
+            ps[pbase + q] = (double)tw;
+            ph[pbase + q] = (int)hw;
+        }
+    };
     // every nlw is >= 0 (hw is the ceiling of the tile's largest log weight).
     // Lane l tests measurement c0 + l; the ones left are read from their lane.
-    auto frame = [&](int pa, int pb, const double* ang, double lo, double hi) {
+    auto frame = [&](int pa, int pb, const double* ang, bool fb, double zr0, double zt0) {
         for (int c0 = pa; c0 < pb; c0 += 64) {
             const int p = c0 + lane;
             bool need = false;
             double zr = 0.0, zt = 0.0;
             if (p < pb) {
-                zr = zs[2 * p];
-                zt = zs[2 * p + 1];
-                need = box_dist2(zr, zt, bx.rlo, bx.rhi, lo, hi) <= exp2_cut<T>();
+                zr = c0 == pa ? zr0 : zs[2 * p];
+                zt = c0 == pa ? zt0 : zs[2 * p + 1];
+                need = box_needed(bx, fb, (float)zr, (float)zt, 0.0f, (float)exp2_cut<T>());
                 if (!need) {
                     ps[pbase + p] = 0.0;
                     ph[pbase + p] = (int)hw;
                 }
             }
-            for (uint64_t live = __ballot(need); live; live &= live - 1) {
+            uint64_t live = __ballot(need);
+            while (live) {
                 const int l = __builtin_ctzll(live);
-                one(c0 + l, lane_value(zr, l), lane_value(zt, l), ang);
+                live &= live - 1;
+                if (live) {
+                    const int l2 = __builtin_ctzll(live);
+                    live &= live - 1;
+                    two(c0 + l, lane_value(zr, l), lane_value(zt, l), c0 + l2, lane_value(zr, l2),
+                        lane_value(zt, l2), ang);
+                } else {
+                    one(c0 + l, lane_value(zr, l), lane_value(zt, l), ang);
+                }
             }
         }
     };
     const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
-    frame(p0, a1, phi, bx.alo, bx.ahi);
-    frame(b0, p1, phib, bx.blo, bx.bhi);
+    frame(p0, a1, phi, false, zra0, zta0);
+    frame(b0, p1, phib, true, zrb0, ztb0);
 }
 
 template <typename T, int PT>
@@ -1176,6 +1218,21 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     if (base >= n) return;
     const size_t gb = (size_t)j * m.cap;
     const size_t zb = (size_t)j * Mmax;
+    const double* zs = zp.zs + 2 * (size_t)off;
+    const int nA = zp.nA[gr.run];
+    // the operands of the first 64 measurements of each frame, loaded with
+    // the particles (frame order)
+    struct ZOp {
+        double zr, zt, H;
+        T F;
+        int fl;
+    };
+    auto zop = [&](int q) {
+        return ZOp{ zs[2 * q], zs[2 * q + 1], (double)zHs[zb + q], zFs[zb + q], zfls[zb + q] };
+    };
+    const int qa = lane < nA && lane < M ? lane : 0, qb = nA + lane < M ? nA + lane : 0;
+    const ZOp za0 = M > 0 ? zop(qa) : ZOp{ 0.0, 0.0, 0.0, (T)0, 0 };
+    const ZOp zb0 = M > 0 ? zop(qb) : ZOp{ 0.0, 0.0, 0.0, (T)0, 0 };
     double rho[PT], phi[PT], phib[PT];
     T acc[PT];
     // the tile's weighted states for the local estimates of candidate labels,
@@ -1202,8 +1259,6 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     }
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
     const int p0 = 0, p1 = M;
-    const double* zs = zp.zs + 2 * (size_t)off;
-    const int nA = zp.nA[gr.run];
     auto one = [&](int p, double zr, double zt, double H, T F, int fl, const double* ang) {
         if (fl == 0) {
 #pragma unroll
@@ -1234,9 +1289,20 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         }
     };
     const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
+    // two non-candidate measurements at once (independent exponentials; each
+    // particle's sum still takes the measurements in order)
+    auto two = [&](double zr, double zt, double H, T F, double yr, double yt, double G, T E, const double* ang) {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const T e = fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H));
+            const T f = fast_exp2(-(T)sq_resid_nowrap(yr, yt, rho[i], ang[i], G));
+            acc[i] += e * F;
+            acc[i] += f * E;
+        }
+    };
     // the exponent is the squared distance plus the measurement's shift H;
     // lane l tests and holds the operands of measurement c0 + l (frame order)
-    auto frame = [&](int pa, int pb, const double* ang, double lo, double hi) {
+    auto frame = [&](int pa, int pb, const double* ang, bool fb, ZOp first) {
         for (int c0 = pa; c0 < pb; c0 += 64) {
             const int p = c0 + lane;
             bool need = false;
@@ -1244,12 +1310,13 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
             T F = 0;
             int fl = 0;
             if (p < pb) {
-                zr = zs[2 * p];
-                zt = zs[2 * p + 1];
-                H = (double)zHs[zb + p];
-                F = zFs[zb + p];
-                fl = zfls[zb + p];
-                need = box_dist2(zr, zt, bx.rlo, bx.rhi, lo, hi) + H <= exp2_cut<T>();
+                const ZOp o = c0 == pa ? first : zop(p);
+                zr = o.zr;
+                zt = o.zt;
+                H = o.H;
+                F = o.F;
+                fl = o.fl;
+                need = box_needed(bx, fb, (float)zr, (float)zt, (float)H, (float)exp2_cut<T>());
                 if (!need && fl != 0) {
                     double* o = pzeta + (pz + (fl - 1)) * 5;
                     o[0] = 0.0;
@@ -1259,16 +1326,30 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
                     o[4] = 0.0;
                 }
             }
-            for (uint64_t live = __ballot(need); live; live &= live - 1) {
+            // in measurement order: candidates (fl != 0) one at a time, two
+            // consecutive others at once
+            const uint64_t cand = __ballot(need && fl != 0);
+            uint64_t live = __ballot(need);
+            while (live) {
                 const int l = __builtin_ctzll(live);
-                one(c0 + l, lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l),
-                    lane_value(fl, l), ang);
+                live &= live - 1;
+                if ((cand >> l) & 1ull) {
+                    one(c0 + l, lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l),
+                        lane_value(fl, l), ang);
+                } else if (live && !((cand >> __builtin_ctzll(live)) & 1ull)) {
+                    const int l2 = __builtin_ctzll(live);
+                    live &= live - 1;
+                    two(lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l), lane_value(zr, l2),
+                        lane_value(zt, l2), lane_value(H, l2), lane_value(F, l2), ang);
+                } else {
+                    one(c0 + l, lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l), 0, ang);
+                }
             }
         }
     };
     const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
-    frame(p0, a1, phi, bx.alo, bx.ahi);
-    frame(b0, p1, phib, bx.blo, bx.bhi);
+    frame(p0, a1, phi, false, za0);
+    frame(b0, p1, phib, true, zb0);
     const size_t KC = (size_t)m.K * m.cap;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -1553,6 +1634,64 @@ __device__ __forceinline__ int quant_shift(double wmax, int n)
 }
 
 // ---------------------------------------------------------------------------
+// Step 5, parent order: the parents of every group are taken in bearing-
+// bucket order (buckets ascending, slot order inside a bucket) so that the
+// children of nearby parents sit together and a likelihood-pass tile spans a
+// narrow bearing range.  The bucket is the "diamond angle" d in [0, 4) of the
+// offset from the sensor (monotonic in the bearing counter-clockwise from +x,
+// one correctly rounded division), times BEARING_BUCKETS/4, rounded down.
+// A stable counting sort in three launches: per-tile bucket histograms,
+// bucket-major offsets per group, scatter into the other particle set.
+// ---------------------------------------------------------------------------
+constexpr int BEARING_BUCKETS = 64;
+
+__device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
+{
+    const double dx = x - m.sx, dy = y - m.sy;
+    double d;
+    if (dx == 0.0 && dy == 0.0) d = 0.0;
+    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
+    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+    const int b = (int)floor(d * (BEARING_BUCKETS / 4.0));
+    return b < 0 ? 0 : (b > BEARING_BUCKETS - 1 ? BEARING_BUCKETS - 1 : b);
+}
+
+// Bucket-major exclusive offsets of group j's ntl tiles, off[t][b] = all
+// slots of lower buckets + slots of bucket b in lower tiles, by a workgroup
+// of NW wavefronts: lane b of wave g sums bucket b over the g-th of NW
+// contiguous tile segments; the segment totals meet in LDS.
+template <int NW>
+__device__ __forceinline__ void bucket_offsets(int j, int ntl, int rtiles, const int* __restrict__ hist,
+                                               int* __restrict__ off)
+{
+    __shared__ int seg[NW][BEARING_BUCKETS];
+    __shared__ int base[BEARING_BUCKETS];
+    const int b = threadIdx.x & 63, g = wave_in_block();
+    const int per = (ntl + NW - 1) / NW;
+    const int t0 = g * per < ntl ? g * per : ntl, t1 = t0 + per < ntl ? t0 + per : ntl;
+    const int* hj = hist + (size_t)j * rtiles * BEARING_BUCKETS;
+    int tot = 0;
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t) tot += hj[(size_t)t * BEARING_BUCKETS + b];
+    seg[g][b] = tot;
+    __syncthreads();
+    if (g == 0) {
+        int all = 0;
+        for (int q = 0; q < NW; ++q) all += seg[q][b];
+        const int incl = (int)wave_incl_scan((double)all);  // exact: counts stay below 2^53
+        base[b] = incl - all;
+    }
+    __syncthreads();
+    int run = base[b];
+    for (int q = 0; q < g; ++q) run += seg[q][b];
+    int* oj = off + (size_t)j * rtiles * BEARING_BUCKETS;
+    for (int t = t0; t < t1; ++t) {
+        oj[(size_t)t * BEARING_BUCKETS + b] = run;
+        run += hj[(size_t)t * BEARING_BUCKETS + b];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // New weights from the chunk sums (chunk order fixed) and Step 3 per group.
 // k_wfinal: every workgroup turns 256 slots into
 //   w <- nu w + wscale w sum_chunks acc
@@ -1566,9 +1705,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restrict__ gd, T* __restrict__ W,
                                                 const int* __restrict__ ncur, const T* __restrict__ accp, int Mall,
                                                 const ZWin* __restrict__ win, int mz, int tiles256,
-                                                double* __restrict__ pmass, double* __restrict__ pmax)
+                                                double* __restrict__ pmass, double* __restrict__ pmax,
+                                                const T* __restrict__ X0, const T* __restrict__ X2,
+                                                int* __restrict__ bkt, int* __restrict__ bhist)
 {
     __shared__ double rs[4], rm[4];
+    __shared__ int h[BEARING_BUCKETS];
     const int j = blockIdx.y;
     const int zsplit = zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
     const int s = blockIdx.x * 256 + threadIdx.x;
@@ -1579,6 +1721,8 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t KC = (size_t)m.K * m.cap;
     const size_t g = (size_t)j * m.cap + s;
+    if (threadIdx.x < BEARING_BUCKETS) h[threadIdx.x] = 0;
+    __syncthreads();
     double wn = 0.0;
     if (s < n) {
         T acc = 0;
@@ -1587,6 +1731,11 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
         const T t = (T)(m.nu * w + m.wscale * w * (double)acc);
         W[g] = t;
         wn = (double)t;
+        // the parent's bearing bucket for the resampling's order (the
+        // positions stay as they are until then)
+        const int b = bearing_bucket(m, (double)X0[g], (double)X2[g]);
+        bkt[g] = b;
+        atomicAdd(&h[b], 1);
     }
     const double sm = wave_sum(wn), mx = wave_max(wn);
     if (lane == 0) {
@@ -1598,6 +1747,8 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
         pmass[(size_t)j * tiles256 + blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
         pmax[(size_t)j * tiles256 + blockIdx.x] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
     }
+    if (threadIdx.x < BEARING_BUCKETS) bhist[((size_t)j * tiles256 + blockIdx.x) * BEARING_BUCKETS + threadIdx.x] =
+        h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, const int* __restrict__ ncur,
@@ -1607,7 +1758,9 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
                                                   const double* __restrict__ pzeta, const int* __restrict__ cand,
                                                   const int* __restrict__ ncand, double* __restrict__ fmass,
                                                   int* __restrict__ fLT, int* __restrict__ rsS,
-                                                  int* __restrict__ sel, double* __restrict__ zeta)
+                                                  int* __restrict__ sel, double* __restrict__ zeta,
+                                                  int rtiles, const int* __restrict__ bhist, int* __restrict__ boff,
+                                                  double* __restrict__ tsum)
 {
     const int j = blockIdx.x;
     const int M = zview(gd[j], win, nullptr, Mall).M;
@@ -1665,6 +1818,10 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
             }
         }
     }
+    // the resampling's parent order (bucket offsets of the group's tiles from
+    // k_wfinal's histograms) and its tile sums cleared for k_bk_scatter
+    for (int t = threadIdx.x; t < nt; t += 256) tsum[(size_t)j * rtiles + t] = 0.0;
+    bucket_offsets<4>(j, nt, rtiles, bhist, boff);
 }
 
 // ---------------------------------------------------------------------------
@@ -1770,29 +1927,6 @@ __global__ __launch_bounds__(256) void k_wmax(DevModel m, const T* __restrict__ 
     if (threadIdx.x == 0) rsS[j] = quant_shift(red[0], n);
 }
 
-// ---------------------------------------------------------------------------
-// Step 5, parent order: the parents of every group are taken in bearing-
-// bucket order (buckets ascending, slot order inside a bucket) so that the
-// children of nearby parents sit together and a likelihood-pass tile spans a
-// narrow bearing range.  The bucket is the "diamond angle" d in [0, 4) of the
-// offset from the sensor (monotonic in the bearing counter-clockwise from +x,
-// one correctly rounded division), times BEARING_BUCKETS/4, rounded down.
-// A stable counting sort in three launches: per-tile bucket histograms,
-// bucket-major offsets per group, scatter into the other particle set.
-// ---------------------------------------------------------------------------
-constexpr int BEARING_BUCKETS = 64;
-
-__device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
-{
-    const double dx = x - m.sx, dy = y - m.sy;
-    double d;
-    if (dx == 0.0 && dy == 0.0) d = 0.0;
-    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
-    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
-    const int b = (int)floor(d * (BEARING_BUCKETS / 4.0));
-    return b < 0 ? 0 : (b > BEARING_BUCKETS - 1 ? BEARING_BUCKETS - 1 : b);
-}
-
 // The sort runs over the slots [first_j, end_j) of every group j: all of a
 // group's particles (first == nullptr: from slot 0) before the resampling, or
 // its births once drawn (first = the survivor count).
@@ -1822,47 +1956,30 @@ __global__ __launch_bounds__(256) void k_bk_hist(DevModel m, SoA<T> st, const in
         hist[((size_t)j * rtiles + t) * BEARING_BUCKETS + threadIdx.x] = h[threadIdx.x];
 }
 
-// grid (K), 1024 threads: bucket-major exclusive offsets, off[t][b] = all
-// slots of lower buckets + slots of bucket b in lower tiles.  Lane b of wave
-// g sums bucket b over the g-th of 16 contiguous tile segments; the segment
-// totals meet in LDS.
+// grid (K), 1024 threads; tsum (optional): the group's resampling tile sums,
+// cleared for k_bk_scatter to accumulate
 __global__ __launch_bounds__(1024) void k_bk_scan(const int* __restrict__ first, const int* __restrict__ end,
-                                                  int rtiles, const int* __restrict__ hist, int* __restrict__ off)
+                                                  int rtiles, const int* __restrict__ hist, int* __restrict__ off,
+                                                  double* __restrict__ tsum)
 {
-    __shared__ int seg[16][BEARING_BUCKETS];
-    __shared__ int base[BEARING_BUCKETS];
-    const int j = blockIdx.x, b = threadIdx.x & 63, g = wave_in_block();
+    const int j = blockIdx.x;
     const int ntl = (end[j] - range_first(first, j) + 255) / 256;
-    const int per = (ntl + 15) / 16;
-    const int t0 = g * per < ntl ? g * per : ntl, t1 = t0 + per < ntl ? t0 + per : ntl;
-    const int* hj = hist + (size_t)j * rtiles * BEARING_BUCKETS;
-    int tot = 0;
-#pragma unroll 4
-    for (int t = t0; t < t1; ++t) tot += hj[(size_t)t * BEARING_BUCKETS + b];
-    seg[g][b] = tot;
-    __syncthreads();
-    if (g == 0) {
-        int all = 0;
-        for (int q = 0; q < 16; ++q) all += seg[q][b];
-        const int incl = (int)wave_incl_scan((double)all);  // exact: counts stay below 2^53
-        base[b] = incl - all;
-    }
-    __syncthreads();
-    int run = base[b];
-    for (int q = 0; q < g; ++q) run += seg[q][b];
-    int* oj = off + (size_t)j * rtiles * BEARING_BUCKETS;
-    for (int t = t0; t < t1; ++t) {
-        oj[(size_t)t * BEARING_BUCKETS + b] = run;
-        run += hj[(size_t)t * BEARING_BUCKETS + b];
-    }
+    if (tsum)
+        for (int t = threadIdx.x; t < ntl; t += 1024) tsum[(size_t)j * rtiles + t] = 0.0;
+    bucket_offsets<16>(j, ntl, rtiles, hist, off);
 }
 
 // grid (tiles, K), 256 threads: slot s of the range goes to off[t][b] + (slots
 // of bucket b before it in its tile), in the other particle set
+// With tsum (the parents before Step 5), each parent's integer weight
+// q = floor(w 2^S) is also added to the sum of the resampling tile it lands
+// in: exact integer sums in FP64 (below 2^53), so the order of the atomic
+// additions does not matter.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T> out, const int* __restrict__ first,
                                                     const int* __restrict__ end, int rtiles,
-                                                    const int* __restrict__ bkt, const int* __restrict__ off)
+                                                    const int* __restrict__ bkt, const int* __restrict__ off,
+                                                    const int* __restrict__ rsS, double* __restrict__ tsum)
 {
     __shared__ int wh[4][BEARING_BUCKETS];  // per-wave bucket counts
     const int j = blockIdx.y, t = blockIdx.x;
@@ -1886,11 +2003,108 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     int rank = __popcll(peers & below);
     if (live && rank == 0) wh[wv][b] = __popcll(peers);
     __syncthreads();
-    if (!live) return;
-    for (int w = 0; w < wv; ++w) rank += wh[w][b];
-    const int dst = off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] + rank;
-    for (int d = 0; d < m.dim; ++d) out.x[d][gb + dst] = in.x[d][gb + s];
-    out.w[gb + dst] = in.w[gb + s];
+    int dst = -1;
+    if (live) {
+        for (int w = 0; w < wv; ++w) rank += wh[w][b];
+        dst = off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] + rank;
+        for (int d = 0; d < m.dim; ++d) out.x[d][gb + dst] = in.x[d][gb + s];
+        out.w[gb + dst] = in.w[gb + s];
+    }
+    if (!tsum) return;
+    // per destination tile: one wave sum and one atomic addition per distinct tile
+    const double q = live ? floor(ldexp((double)in.w[gb + s], rsS[j])) : 0.0;
+    int tile = live ? (dst >> 8) : -1;
+    for (;;) {
+        const uint64_t act = __ballot(tile >= 0);
+        if (!act) break;
+        const int lead = __builtin_ctzll(act);
+        const int tl = __builtin_amdgcn_readlane(tile, lead);
+        const bool mine = tile == tl;
+        const double sq = wave_sum(mine ? q : 0.0);
+        if (lane == lead) atomicAdd(&tsum[(size_t)j * rtiles + tl], sq);
+        if (mine) tile = -1;
+    }
+}
+
+// A group's births in bearing-bucket order in one workgroup, for groups of at
+// most 1024 * BS births: every thread holds up to BS births in registers
+// (slots nsurv + i, i = c * 1024 + thread), the bucket histogram and its
+// offsets sit in LDS, the stable rank of each birth comes chunk by chunk
+// (ballot peers within a wave, earlier waves' counts of the chunk, earlier
+// chunks' counts), and after a barrier every birth is written back in place
+// at its rank with its geometry.  grid (K), 1024 threads.
+template <typename T, int BS>
+__global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
+                                                     const int* __restrict__ ncur)
+{
+    __shared__ int s_off[BEARING_BUCKETS];
+    __shared__ int s_w[16][BEARING_BUCKETS];
+    const int j = blockIdx.x;
+    const int a = nsurv[j], nb = ncur[j] - a;
+    if (nb <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t gb = (size_t)j * m.cap + a;
+    if (tid < BEARING_BUCKETS) s_off[tid] = 0;
+    __syncthreads();
+    T v[BS][5], w[BS];
+    int b[BS], dst[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const int i = c * 1024 + tid;
+        b[c] = BEARING_BUCKETS;
+        dst[c] = -1;
+        if (i < nb) {
+#pragma unroll
+            for (int d = 0; d < 5; ++d) v[c][d] = d < m.dim ? st.x[d][gb + i] : (T)0;
+            w[c] = st.w[gb + i];
+            b[c] = bearing_bucket(m, (double)v[c][0], (double)v[c][2]);
+            atomicAdd(&s_off[b[c]], 1);
+        }
+    }
+    __syncthreads();
+    if (wv == 0) {
+        const int cnt = s_off[lane];
+        const int incl = (int)wave_incl_scan((double)cnt);
+        s_off[lane] = incl - cnt;
+    }
+    __syncthreads();
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        if (c * 1024 >= nb) break;
+        s_w[wv][lane] = 0;
+        __syncthreads();
+        unsigned long long peers = ~0ull;
+        for (int bit = 0; bit < 7; ++bit) {
+            const unsigned long long q = __ballot((b[c] >> bit) & 1);
+            peers &= ((b[c] >> bit) & 1) ? q : ~q;
+        }
+        const int rank = __popcll(peers & below);
+        if (b[c] < BEARING_BUCKETS && rank == 0) s_w[wv][b[c]] = __popcll(peers);
+        __syncthreads();
+        if (b[c] < BEARING_BUCKETS) {
+            int r = s_off[b[c]] + rank;
+            for (int w2 = 0; w2 < wv; ++w2) r += s_w[w2][b[c]];
+            dst[c] = r;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            int tot = 0;
+            for (int w2 = 0; w2 < 16; ++w2) tot += s_w[w2][lane];
+            s_off[lane] += tot;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        if (dst[c] < 0) continue;
+        const size_t g = gb + dst[c];
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+            if (d < m.dim) st.x[d][g] = v[c][d];
+        st.w[g] = w[c];
+        store_geometry(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
+    }
 }
 
 // births back from the other set in their sorted order, with their geometry
@@ -1910,26 +2124,9 @@ __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T>
 }
 
 // ---------------------------------------------------------------------------
-// Step 5, resampling, pass A: integer-valued weights q = floor(w 2^S) and their
-// exact per-tile totals (tiles of 256 parents).  grid (rtiles, K).
+// Step 5, resampling: integer-valued weights q = floor(w 2^S) and their exact
+// per-tile totals (tiles of 256 ordered parents) come from k_bk_scatter.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_rs_tiles(DevModel m, const T* __restrict__ w, const int* __restrict__ ncur,
-                                                  const int* __restrict__ rsS, int rtiles, double* __restrict__ tsum)
-{
-    __shared__ double red[4];
-    const int j = blockIdx.y, t = blockIdx.x;
-    const int n = ncur[j];
-    const int s = t * 256 + threadIdx.x;
-    if (t * 256 >= n) return;
-    const int S = rsS[j];
-    double q = (s < n) ? floor(ldexp((double)w[(size_t)j * m.cap + s], S)) : 0.0;
-    q = wave_sum(q);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) tsum[(size_t)j * rtiles + t] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
 // Number of systematic points below the cumulative boundary c:
 //   N(c) = #{ m in [0, L) : (m 2^32 + r) Q < c L 2^32 }.
 // A double estimate is corrected with exact 128-bit comparisons.

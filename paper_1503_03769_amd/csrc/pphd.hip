@@ -140,6 +140,7 @@ struct pphd_filter {
     int* counts = nullptr;
     int *bkt = nullptr, *bhist = nullptr, *boff = nullptr;  // bearing-bucket order of the parents
     int *tpre1 = nullptr, *tgrp1 = nullptr, *tpre2 = nullptr, *tgrp2 = nullptr;  // tile lists of the two passes
+    bool order_ready = false;  // the last update left the parents' bucket offsets and cleared tile sums
     void* stage = nullptr;
     // host side
     double* pin_z = nullptr;
@@ -591,11 +592,13 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     LAUNCH(f, PPHD_K_WFINAL,
            hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
                               (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256, f->p2mass,
-                              f->p2max));
+                              f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist));
     LAUNCH(f, PPHD_K_FINALIZE,
            hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
-                              f->fLT, f->rsS, f->sel, f->zeta));
+                              f->fLT, f->rsS, f->sel, f->zeta, f->rtiles, f->bhist, f->boff, f->tsum));
+    // k_wfinal and k_finalize have prepared the resampling's parent order
+    f->order_ready = true;
     return PPHD_OK;
 }
 
@@ -641,20 +644,26 @@ pphd_status run_init(pphd_filter* f)
 // Stable bearing-bucket order of the slots [first_j, ncur_j) of every group,
 // from the current particle set into the other one (first == nullptr: every
 // slot).  tiles: 256-slot tiles to cover the longest range.
+// parents (first == nullptr): the scatter also forms the resampling's tile
+// sums, and the histogram and offsets come from the update when it left them
 template <typename T>
 pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles)
 {
     dim3 g(tiles, f->K);
     SoA<T> cur = soa<T>(f, f->cur), oth = soa<T>(f, 1 - f->cur);
-    LAUNCH(f, cls,
-           hipLaunchKernelGGL((k_bk_hist<T>), g, dim3(256), 0, f->stream, f->dm, cur, first, f->ncur, f->rtiles,
-                              f->bkt, f->bhist));
-    LAUNCH(f, cls,
-           hipLaunchKernelGGL(k_bk_scan, dim3(f->K), dim3(1024), 0, f->stream, first, f->ncur, f->rtiles, f->bhist,
-                              f->boff));
+    const bool parents = first == nullptr;
+    if (!parents || !f->order_ready) {
+        LAUNCH(f, cls,
+               hipLaunchKernelGGL((k_bk_hist<T>), g, dim3(256), 0, f->stream, f->dm, cur, first, f->ncur, f->rtiles,
+                                  f->bkt, f->bhist));
+        LAUNCH(f, cls,
+               hipLaunchKernelGGL(k_bk_scan, dim3(f->K), dim3(1024), 0, f->stream, first, f->ncur, f->rtiles,
+                                  f->bhist, f->boff, parents ? f->tsum : nullptr));
+    }
     LAUNCH(f, cls,
            hipLaunchKernelGGL((k_bk_scatter<T>), g, dim3(256), 0, f->stream, f->dm, cur, oth, first, f->ncur,
-                              f->rtiles, f->bkt, f->boff));
+                              f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr));
+    if (parents) f->order_ready = false;
     return PPHD_OK;
 }
 
@@ -664,6 +673,14 @@ template <typename T>
 pphd_status order_births(pphd_filter* f)
 {
     if (f->Jmax <= 0) return PPHD_OK;
+    // up to 1024 BS births per group: one workgroup per group, in place
+    constexpr int BS = sizeof(T) == 4 ? 8 : 4;
+    if (f->Jmax <= 1024 * BS) {
+        LAUNCH(f, PPHD_K_BIRTH_ORDER,
+               hipLaunchKernelGGL((k_birth_sort<T, BS>), dim3(f->K), dim3(1024), 0, f->stream, f->dm,
+                                  soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur));
+        return PPHD_OK;
+    }
     const int bt = (f->Jmax + 255) / 256;
     pphd_status s = bucket_order<T>(f, PPHD_K_BIRTH_ORDER, f->nsurv, bt);
     if (s != PPHD_OK) return s;
@@ -684,10 +701,8 @@ pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
         if (s != PPHD_OK) return s;
         f->cur = 1 - f->cur;
     }
+    // the tile sums of the ordered parents came with the scatter
     SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
-    LAUNCH(f, PPHD_K_RS_TILES,
-           hipLaunchKernelGGL((k_rs_tiles<T>), g, dim3(256), 0, f->stream, f->dm, (const T*)in.w, f->ncur, f->rsS,
-                              f->rtiles, f->tsum));
     LAUNCH(f, PPHD_K_RS_EXPAND,
            hipLaunchKernelGGL((k_rs_expand<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
                               f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr, f->counts,
@@ -1034,6 +1049,7 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
     const bool is_cur = phase == PPHD_PHASE_PREDICTED || phase == PPHD_PHASE_UPDATED;
     HIP_TRY(hipMemcpy(is_cur ? f->ncur : f->nsurv, count, (size_t)f->K * 4, hipMemcpyHostToDevice));
     f->births_pending = false;  // a written state is complete
+    f->order_ready = false;
     if (phase == PPHD_PHASE_PREDICTED) {
         dim3 g((f->cap + 255) / 256, f->K);
         if (f->prec == PPHD_FP64) {
