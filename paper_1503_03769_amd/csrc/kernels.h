@@ -1021,23 +1021,93 @@ __device__ __forceinline__ bool box_needed(const TileBox& b, bool frame_b, float
 }
 
 // ---------------------------------------------------------------------------
-// Tile list of the frame passes: every group's wave tiles of WT slots,
-// numbered group after group (pre[j] = the first tile of group j, pre[K] =
-// all tiles; grp[t] = the group of tile t).  The passes then loop over the
-// list, every wavefront taking tiles w, w + W, ... (W = waves in the grid),
-// so the grid does not depend on the particle counts and no wavefront starts
-// on an empty tile.  One workgroup of 1024 threads; thread i takes a
-// contiguous run of ceil(K/1024) groups.
+// Work items of the frame passes.  Group j's wave tiles (WT slots each) are
+// its work items, numbered in slot order.  With groups of one size the grid
+// is (groups, X), X fixed by the group count, and the 4X wavefronts of group
+// j take its items w, w + 4X, ... (the workgroups of low X, which hold most of
+// the work, are dispatched first).  With groups of different sizes (a batch
+// of unlike runs) the items of all groups form one list (pre[j]: group j's
+// first item, pre[K]: all items, grp[e]: the group of item e) that a 1-D grid
+// strides over, so every wavefront gets about the same number of items.
+// Either way the grid does not follow the particle counts (it can be
+// captured in a graph) and a wavefront never holds an empty tile.  When
+// a group has few births (under 16 tiles' worth: their bearing order then
+// still leaves each birth tile spread over many buckets, keeping most
+// measurements), each tile holding births is BIRTH_CHUNKS items, each with
+// a contiguous part of the measurements: item e is tile e for e < tA_j (the
+// tiles before the first birth) and else tile tA_j + (e - tA_j) / chunks,
+// chunk (e - tA_j) mod chunks.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_map(const int* __restrict__ ncur, int K, int WT, int* __restrict__ pre,
-                                                   int* __restrict__ grp)
+constexpr int BIRTH_CHUNKS = 4;
+struct TileItem {
+    int tile, chunk, chunks;
+};
+// (clamped to [0, tiles]: a state written from the host may leave any
+// survivor count, and the item count must stay within BIRTH_CHUNKS per tile)
+__device__ __forceinline__ int tiles_before_births(int n, int ns, int WT)
+{
+    const int nt = (n + WT - 1) / WT, ta = ns > 0 ? ns / WT : 0;
+    return ta < nt ? ta : nt;
+}
+__device__ __forceinline__ int birth_chunks(int n, int ns, int WT)
+{
+    return n - (ns > 0 ? ns : 0) < 16 * WT ? BIRTH_CHUNKS : 1;
+}
+__device__ __forceinline__ int tile_items(int n, int ns, int WT)
+{
+    const int nt = (n + WT - 1) / WT, ta = tiles_before_births(n, ns, WT);
+    return ta + (nt - ta) * birth_chunks(n, ns, WT);
+}
+__device__ __forceinline__ TileItem tile_item(int e, int n, int ns, int WT)
+{
+    const int ta = tiles_before_births(n, ns, WT), z = birth_chunks(n, ns, WT);
+    if (e < ta) return TileItem{ e, 0, 1 };
+    return TileItem{ ta + (e - ta) / z, (e - ta) % z, z };
+}
+// a wavefront's walk over its items (wave-uniform): per group (tpre null,
+// grid (K, X)) or over the flat list (grid (X))
+struct WorkCursor {
+    const int *pre, *grp, *ncur, *nsurv;
+    int WT, e, end, stride, j;
+    __device__ __forceinline__ WorkCursor(int K, const int* tpre, const int* tgrp, const int* nc, const int* nsv,
+                                          int wt)
+        : pre(tpre), grp(tgrp), ncur(nc), nsurv(nsv), WT(wt)
+    {
+        if (pre) {
+            e = blockIdx.x * 4 + wave_in_block();
+            stride = gridDim.x * 4;
+            end = pre[K];
+            j = e < end ? grp[e] : 0;
+        } else {
+            j = blockIdx.x;
+            e = blockIdx.y * 4 + wave_in_block();
+            stride = gridDim.y * 4;
+            end = tile_items(ncur[j], nsurv[j], WT);
+        }
+    }
+    __device__ __forceinline__ bool valid() const { return e < end; }
+    __device__ __forceinline__ void next()
+    {
+        e += stride;
+        if (pre && e < end) j = grp[e];
+    }
+    __device__ __forceinline__ TileItem item() const
+    {
+        return tile_item(pre ? e - pre[j] : e, ncur[j], nsurv[j], WT);
+    }
+};
+
+// the flat list: item counts and their prefix (one workgroup of 1024 threads,
+// thread i taking a contiguous run of ceil(K/1024) groups) ...
+__global__ __launch_bounds__(1024) void k_items_scan(const int* __restrict__ ncur, const int* __restrict__ nsurv,
+                                                     int K, int WT, int* __restrict__ pre)
 {
     __shared__ int s_w[16];
     const int G = (K + 1023) / 1024;
     const int j0 = threadIdx.x * G < K ? threadIdx.x * G : K, j1 = j0 + G < K ? j0 + G : K;
     int c = 0;
-    for (int j = j0; j < j1; ++j) c += (ncur[j] + WT - 1) / WT;
-    const int incl = (int)wave_incl_scan((double)c);  // exact: tile counts stay below 2^53
+    for (int j = j0; j < j1; ++j) c += tile_items(ncur[j], nsurv[j], WT);
+    const int incl = (int)wave_incl_scan((double)c);  // exact: counts stay below 2^53
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 63) s_w[wv] = incl;
     __syncthreads();
@@ -1045,11 +1115,15 @@ __global__ __launch_bounds__(1024) void k_tile_map(const int* __restrict__ ncur,
     for (int w = 0; w < wv; ++w) pos += s_w[w];
     for (int j = j0; j < j1; ++j) {
         pre[j] = pos;
-        const int cj = (ncur[j] + WT - 1) / WT;
-        for (int t = 0; t < cj; ++t) grp[pos + t] = j;
-        pos += cj;
+        pos += tile_items(ncur[j], nsurv[j], WT);
     }
     if (threadIdx.x == 1023) pre[K] = pos;
+}
+// ... and every group's entries of grp (grid (K), 256 threads)
+__global__ __launch_bounds__(256) void k_items_fill(const int* __restrict__ pre, int* __restrict__ grp)
+{
+    const int j = blockIdx.x;
+    for (int e = pre[j] + threadIdx.x; e < pre[j + 1]; e += 256) grp[e] = j;
 }
 
 // first pass in frames: as k_cz (PASS_FRAMES), the measurement side read
@@ -1060,7 +1134,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
                                                const T* __restrict__ W, const int* __restrict__ ncur, int Mall,
                                                const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
                                                const Split& sp, double* __restrict__ ps, int* __restrict__ ph,
-                                               double* __restrict__ pw, int j, int tile)
+                                               double* __restrict__ pw, int j, int tile, int zc, int zsplit)
 {
     constexpr int WT = 64 * PT;
     const Grp gr = gd[j];
@@ -1069,7 +1143,8 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
         off = win[gr.run].off;
         M = win[gr.run].M;
     }
-    const int zc = 0;
+    const int MZ = (M + zsplit - 1) / zsplit;
+    const int p0 = zc * MZ < M ? zc * MZ : M, p1 = p0 + MZ < M ? p0 + MZ : M;
     const int lane = threadIdx.x & 63;
     const int n = ncur[j];
     const int base = tile * WT;
@@ -1077,8 +1152,9 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
     const size_t gb = (size_t)j * m.cap;
     const double* zs = zp.zs + 2 * (size_t)off;
     const int nA = zp.nA[gr.run];
-    // the first 64 measurements of each frame, loaded with the particles
-    const int qa = lane < nA && lane < M ? lane : 0, qb = nA + lane < M ? nA + lane : 0;
+    // the first 64 measurements of each frame in [p0, p1), loaded with the particles
+    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
+    const int qa = p0 + lane < a1 ? p0 + lane : 0, qb = b0 + lane < p1 ? b0 + lane : 0;
     const double zra0 = M > 0 ? zs[2 * qa] : 0.0, zta0 = M > 0 ? zs[2 * qa + 1] : 0.0;
     const double zrb0 = M > 0 ? zs[2 * qb] : 0.0, ztb0 = M > 0 ? zs[2 * qb + 1] : 0.0;
     double rho[PT], phi[PT], phib[PT], nlw[PT];
@@ -1113,7 +1189,6 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
 #pragma unroll
     for (int i = 0; i < PT; ++i) nlw[i] += hw;
     const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
-    const int p0 = 0, p1 = M;
     const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
     auto one = [&](int p, double zr, double zt, const double* ang) {
         T s = 0;
@@ -1173,7 +1248,6 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
             }
         }
     };
-    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
     frame(p0, a1, phi, false, zra0, zta0);
     frame(b0, p1, phib, true, zrb0, ztb0);
 }
@@ -1183,13 +1257,15 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
                                                    const T* __restrict__ W, const int* __restrict__ ncur,
                                                    int Mall, const ZWin* __restrict__ win, ZPrepC zp, int Mmax,
                                                    Split sp, double* __restrict__ ps, int* __restrict__ ph,
-                                                   double* __restrict__ pw, int K, const int* __restrict__ tpre,
-                                                   const int* __restrict__ tgrp)
+                                                   double* __restrict__ pw, const int* __restrict__ nsurv, int K,
+                                                   const int* __restrict__ tpre, const int* __restrict__ tgrp)
 {
-    const int total = tpre[K];
-    for (int t = blockIdx.x * 4 + wave_in_block(); t < total; t += gridDim.x * 4) {
-        const int j = tgrp[t];
-        cz_frames_tile<T, PT>(m, gd, geo, W, ncur, Mall, win, zp, Mmax, sp, ps, ph, pw, j, t - tpre[j]);
+    WorkCursor wc(K, tpre, tgrp, ncur, nsurv, 64 * PT);
+    for (; wc.valid(); wc.next()) {
+        const int j = wc.j;
+        const TileItem it = wc.item();
+        cz_frames_tile<T, PT>(m, gd, geo, W, ncur, Mall, win, zp, Mmax, sp, ps, ph, pw, j, it.tile, it.chunk,
+                              it.chunks);
     }
 }
 
@@ -1202,7 +1278,8 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
                                                    const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
                                                    const Split& sp, const int* __restrict__ zHs,
                                                    const T* __restrict__ zFs, const int* __restrict__ zfls,
-                                                   double* __restrict__ pzeta, T* __restrict__ accp, int j, int tile)
+                                                   double* __restrict__ pzeta, T* __restrict__ accp, int j, int tile,
+                                                   int zc, int zsplit)
 {
     constexpr int WT = 64 * PT;
     const Grp gr = gd[j];
@@ -1211,7 +1288,8 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         off = win[gr.run].off;
         M = win[gr.run].M;
     }
-    const int zc = 0;
+    const int MZ = (M + zsplit - 1) / zsplit;
+    const int p0 = zc * MZ < M ? zc * MZ : M, p1 = p0 + MZ < M ? p0 + MZ : M;
     const int lane = threadIdx.x & 63;
     const int n = ncur[j];
     const int base = tile * WT;
@@ -1230,7 +1308,8 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     auto zop = [&](int q) {
         return ZOp{ zs[2 * q], zs[2 * q + 1], (double)zHs[zb + q], zFs[zb + q], zfls[zb + q] };
     };
-    const int qa = lane < nA && lane < M ? lane : 0, qb = nA + lane < M ? nA + lane : 0;
+    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
+    const int qa = p0 + lane < a1 ? p0 + lane : 0, qb = b0 + lane < p1 ? b0 + lane : 0;
     const ZOp za0 = M > 0 ? zop(qa) : ZOp{ 0.0, 0.0, 0.0, (T)0, 0 };
     const ZOp zb0 = M > 0 ? zop(qb) : ZOp{ 0.0, 0.0, 0.0, (T)0, 0 };
     double rho[PT], phi[PT], phib[PT];
@@ -1258,7 +1337,6 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         for (int d = 0; d < 4; ++d) ux[d][i] = ok ? xv[d] : (T)0;
     }
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
-    const int p0 = 0, p1 = M;
     auto one = [&](int p, double zr, double zt, double H, T F, int fl, const double* ang) {
         if (fl == 0) {
 #pragma unroll
@@ -1347,7 +1425,6 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
             }
         }
     };
-    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
     frame(p0, a1, phi, false, za0);
     frame(b0, p1, phib, true, zb0);
     const size_t KC = (size_t)m.K * m.cap;
@@ -1364,14 +1441,15 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
                                                        const ZWin* __restrict__ win, ZPrepC zp, int Mmax, Split sp,
                                                        const int* __restrict__ zHs, const T* __restrict__ zFs,
                                                        const int* __restrict__ zfls, double* __restrict__ pzeta,
-                                                       T* __restrict__ accp, int K, const int* __restrict__ tpre,
-                                                       const int* __restrict__ tgrp)
+                                                       T* __restrict__ accp, const int* __restrict__ nsurv, int K,
+                                                       const int* __restrict__ tpre, const int* __restrict__ tgrp)
 {
-    const int total = tpre[K];
-    for (int t = blockIdx.x * 4 + wave_in_block(); t < total; t += gridDim.x * 4) {
-        const int j = tgrp[t];
+    WorkCursor wc(K, tpre, tgrp, ncur, nsurv, 64 * PT);
+    for (; wc.valid(); wc.next()) {
+        const int j = wc.j;
+        const TileItem it = wc.item();
         weight_frames_tile<T, PT>(m, gd, st, geo, ncur, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, j,
-                                  t - tpre[j]);
+                                  it.tile, it.chunk, it.chunks);
     }
 }
 
@@ -1707,13 +1785,20 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
                                                 const ZWin* __restrict__ win, int mz, int tiles256,
                                                 double* __restrict__ pmass, double* __restrict__ pmax,
                                                 const T* __restrict__ X0, const T* __restrict__ X2,
-                                                int* __restrict__ bkt, int* __restrict__ bhist)
+                                                int* __restrict__ bkt, int* __restrict__ bhist, int wt_births,
+                                                const int* __restrict__ nsurv)
 {
     __shared__ double rs[4], rm[4];
     __shared__ int h[BEARING_BUCKETS];
     const int j = blockIdx.y;
-    const int zsplit = zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
+    // chunks of the second pass: the run's zsplit, or (frame passes, wt_births
+    // = their tile) one, and BIRTH_CHUNKS in the tiles holding births
+    const int zs_run = zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
     const int s = blockIdx.x * 256 + threadIdx.x;
+    const int zsplit = wt_births > 0 ? (s / wt_births >= tiles_before_births(ncur[j], nsurv[j], wt_births)
+                                            ? birth_chunks(ncur[j], nsurv[j], wt_births)
+                                            : 1)
+                                     : zs_run;
     const int n = ncur[j];
     const int nt = (n + 255) / 256;
     const int active = nt > 0 ? nt : 1;

@@ -139,8 +139,9 @@ struct pphd_filter {
     double *tsum = nullptr, *massq = nullptr;
     int* counts = nullptr;
     int *bkt = nullptr, *bhist = nullptr, *boff = nullptr;  // bearing-bucket order of the parents
-    int *tpre1 = nullptr, *tgrp1 = nullptr, *tpre2 = nullptr, *tgrp2 = nullptr;  // tile lists of the two passes
     bool order_ready = false;  // the last update left the parents' bucket offsets and cleared tile sums
+    bool uneven = false;       // groups of different sizes: the frame passes walk flat item lists
+    int *ipre1 = nullptr, *igrp1 = nullptr, *ipre2 = nullptr, *igrp2 = nullptr;  // those lists
     void* stage = nullptr;
     // host side
     double* pin_z = nullptr;
@@ -237,10 +238,10 @@ size_t carve(pphd_filter* f, char* base)
     f->massq = L.take<double>(base, K * 8);
     f->counts = L.take<int>(base, KC * 4);
     f->bkt = L.take<int>(base, KC * 4);
-    f->tpre1 = L.take<int>(base, (K + 1) * 4);
-    f->tgrp1 = L.take<int>(base, K * f->wtiles_max * 4);
-    f->tpre2 = L.take<int>(base, (K + 1) * 4);
-    f->tgrp2 = L.take<int>(base, K * f->wtiles_max * 4);
+    f->ipre1 = L.take<int>(base, (K + 1) * 4);
+    f->igrp1 = L.take<int>(base, K * f->wtiles_max * BIRTH_CHUNKS * 4);  // at most BIRTH_CHUNKS items per tile
+    f->ipre2 = L.take<int>(base, (K + 1) * 4);
+    f->igrp2 = L.take<int>(base, K * f->wtiles_max * BIRTH_CHUNKS * 4);
     f->bhist = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->boff = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->stage = L.take<char>(base, K * (size_t)f->Lmax * 6 * es);
@@ -328,6 +329,17 @@ void set_geometry(pphd_filter* f, const pphd_model* m, const pphd_run_desc* runs
             f->hgd.push_back(g);
         }
     }
+    // groups of clearly different sizes (particles per target or births
+    // apart by more than a quarter) walk flat item lists in the frame passes
+    double rlo = 1e300, rhi = 0.0;
+    int jlo = 1 << 30, jhi = 0;
+    for (const Grp& g : f->hgd) {
+        rlo = std::min(rlo, g.Rj);
+        rhi = std::max(rhi, g.Rj);
+        jlo = std::min(jlo, g.Jj);
+        jhi = std::max(jhi, g.Jj);
+    }
+    f->uneven = !f->hgd.empty() && (rhi > 1.25 * rlo || jhi > 1.25 * std::max(jlo, 1) + 1);
     f->prec = m->precision;
     f->esz = m->precision == PPHD_FP64 ? 8 : 4;
     f->KC = (size_t)f->K * (size_t)cap;
@@ -544,26 +556,47 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     const ZPrepC zpc{ f->zprep.zs, f->zprep.orig, f->zprep.pos, f->zprep.nA };
     const bool frames = f->pass_mode == PASS_FRAMES;
     const ZSorted<T> zsort{ f->zHs, (T*)f->zFs, f->zfls };
-    // frame passes: one wavefront per tile of the tile lists, all of a run's
-    // measurements in it (one chunk); grids of at most 2048 workgroups
-    const int* tpre2 = f->wt2 == f->wt1 ? f->tpre1 : f->tpre2;
-    const int* tgrp2 = f->wt2 == f->wt1 ? f->tgrp1 : f->tgrp2;
-    const dim3 gl1((unsigned)std::min<int64_t>(2048, ((int64_t)K * f->wtiles1 + 3) / 4));
-    const dim3 gl2((unsigned)std::min<int64_t>(2048, ((int64_t)K * f->wtiles2 + 3) / 4));
+    // frame passes: (K, X) grids whose wavefronts stride over each group's
+    // work items, X from the group count (about 8192 wavefronts in all, at
+    // most the items a group can have)
+    auto xdim = [&](int wtiles) {
+        const int64_t most = ((int64_t)wtiles * BIRTH_CHUNKS + 3) / 4, want = (2048 + K - 1) / K;
+        return (unsigned)std::max<int64_t>(1, std::min(most, want));
+    };
+    dim3 gl1(K, xdim(f->wtiles1)), gl2(K, xdim(f->wtiles2));
+    const int* ipre1 = nullptr;
+    const int *igrp1 = nullptr, *ipre2 = nullptr, *igrp2 = nullptr;
+    if (f->pass_mode == PASS_FRAMES && f->uneven) {
+        auto lists = [&](int WT, int* pre, int* grp) -> pphd_status {
+            LAUNCH(f, PPHD_K_ZPREP,
+                   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, f->stream, f->ncur, f->nsurv, K, WT, pre));
+            LAUNCH(f, PPHD_K_ZPREP,
+                   hipLaunchKernelGGL(k_items_fill, dim3(K), dim3(256), 0, f->stream, pre, grp));
+            return PPHD_OK;
+        };
+        pphd_status ls = lists(f->wt1, f->ipre1, f->igrp1);
+        if (ls != PPHD_OK) return ls;
+        ipre1 = f->ipre1;
+        igrp1 = f->igrp1;
+        if (f->wt2 != f->wt1) {
+            ls = lists(f->wt2, f->ipre2, f->igrp2);
+            if (ls != PPHD_OK) return ls;
+            ipre2 = f->ipre2;
+            igrp2 = f->igrp2;
+        } else {
+            ipre2 = ipre1;
+            igrp2 = igrp1;
+        }
+        gl1 = dim3(2048);
+        gl2 = dim3(2048);
+    }
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_ZPREP,
                hipLaunchKernelGGL(k_zprep, dim3(f->nruns), dim3(256), 0, f->stream, dm, a.dz, a.M, a.win, f->zprep));
-        LAUNCH(f, PPHD_K_ZPREP,
-               hipLaunchKernelGGL(k_tile_map, dim3(1), dim3(1024), 0, f->stream, f->ncur, K, f->wt1, f->tpre1,
-                                  f->tgrp1));
-        if (f->wt2 != f->wt1)
-            LAUNCH(f, PPHD_K_ZPREP,
-                   hipLaunchKernelGGL(k_tile_map, dim3(1), dim3(1024), 0, f->stream, f->ncur, K, f->wt2, f->tpre2,
-                                      f->tgrp2));
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz_frames<T, PT1>), gl1, dim3(256), 0, f->stream, dm, f->gd, geo,
-                                  (const T*)st.w, f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w, K,
-                                  f->tpre1, f->tgrp1));
+                                  (const T*)st.w, f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w,
+                                  f->nsurv, K, ipre1, igrp1));
     } else if (f->pass_mode == PASS_WRAP) {
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
@@ -582,7 +615,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight_frames<T, PT2>), gl2, dim3(256), 0, f->stream, dm, f->gd, st, geo,
                                   f->ncur, a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
-                                  (T*)f->accp, K, tpre2, tgrp2));
+                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
@@ -592,7 +625,8 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     LAUNCH(f, PPHD_K_WFINAL,
            hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
                               (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256, f->p2mass,
-                              f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist));
+                              f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist, frames ? f->wt2 : 0,
+                              f->nsurv));
     LAUNCH(f, PPHD_K_FINALIZE,
            hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
