@@ -110,8 +110,9 @@ typedef struct {
 typedef struct pphd_filter pphd_filter;
 
 /* Bytes of device workspace a filter with this model needs.
- * cap_per_partition: particle slots per group (must hold round(R/K) initial
- * particles and L' + J_j after every resampling; L' is clamped to fit).
+ * cap_per_partition: particle slots per group, 1 .. 65535 * 256 (must hold
+ * round(R/K) initial particles and L' + J_j after every resampling; L' is
+ * clamped to fit).
  * max_meas: the largest measurement count a later pphd_update may pass (>= 1).
  * Returns PPHD_EINVAL for an invalid model or sizes. */
 pphd_status pphd_workspace_size(const pphd_model* model, int64_t cap_per_partition,

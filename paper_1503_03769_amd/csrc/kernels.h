@@ -28,15 +28,26 @@ struct DevModel {
     int K, J, cap, M0, proposal, density;  // density: birth density option (1 = Gaussian)
     uint32_t key0, key1, run, pad;
     double bmean[4], bstd[4];              // Gaussian birth density
-    int dim, pad3;                         // 4: CV [x, vx, y, vy]; 5: coordinated turn, + omega
+    int dim, tile_major;                   // dim 4: CV [x, vx, y, vy]; 5: coordinated turn, + omega
+                                           // tile_major: per-slot grids are (tiles, groups)
     double sigma_w, birth_sigma_w;         // turn-rate noise and birth spread (dim 5)
 };
+
+__device__ __forceinline__ int slot_group(const DevModel& m) { return m.tile_major ? blockIdx.y : blockIdx.x; }
+__device__ __forceinline__ int slot_tile(const DevModel& m) { return m.tile_major ? blockIdx.x : blockIdx.y; }
 
 template <typename T>
 struct SoA {
     T* x[5];  // x[4] (the turn rate) only with dim 5
     T* w;
 };
+
+// Per-slot kernels run on grids (groups, tiles of the capacity), so that
+// every group's first tiles (which hold its particles) are dispatched before
+// the capacity's empty tail.  Groups of clearly different sizes use (tiles,
+// groups) instead (DevModel::tile_major): consecutive workgroups then take
+// consecutive tiles of one group, spread over the chip's dies, where the
+// group-major order would give whole groups to one die each.
 
 // Per-group constants.  A filter is a batch of independent runs; each run has
 // K_r groups (partitions), and global group g owns the particle slots
@@ -201,10 +212,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_init(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
                                               int* __restrict__ nsurv)
 {
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) nsurv[j] = gr.M0;
+    const int s = slot_tile(m) * 256 + threadIdx.x;
+    if (slot_tile(m) == 0 && threadIdx.x == 0) nsurv[j] = gr.M0;
     if (s >= gr.M0) return;
     const size_t g = (size_t)j * m.cap + s;
     double v[5];
@@ -245,15 +256,15 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
                                                  const int* __restrict__ nsurv, int* __restrict__ ncur,
                                                  uint32_t step_arg, const uint32_t* __restrict__ dstep)
 {
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
     const uint32_t step = step_of(step_arg, dstep);
-    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int s = slot_tile(m) * 256 + threadIdx.x;
     const int ns = nsurv[j];
     const int Jj = gr.Jj;
     // the host guarantees ns + J_j <= cap; the clamp keeps every store inside the group
     const int total = ns + Jj < m.cap ? ns + Jj : m.cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ncur[j] = total;
+    if (slot_tile(m) == 0 && threadIdx.x == 0) ncur[j] = total;
     if (s >= total) return;
     const size_t g = (size_t)j * m.cap + s;
     const uint32_t c0 = (uint32_t)(gr.jl * m.cap + s);
@@ -322,8 +333,8 @@ __device__ __forceinline__ double birth_turn_rate(const DevModel& m, uint32_t c0
 template <typename T>
 __global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ ncur)
 {
-    const int j = blockIdx.y;
-    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int j = slot_group(m);
+    const int s = slot_tile(m) * 256 + threadIdx.x;
     if (s >= ncur[j]) return;
     const size_t g = (size_t)j * m.cap + s;
     store_geometry(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)st.w[g]);
@@ -365,11 +376,11 @@ __global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __res
                                                     const uint32_t* __restrict__ dstep)
 {
     __shared__ double sz[2 * BIRTH_ZCHUNK];
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
-    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int b = slot_tile(m) * 256 + threadIdx.x;
     const int Jj = gr.Jj;
-    if (blockIdx.x * 256 >= Jj) return;  // whole workgroup idle
+    if (slot_tile(m) * 256 >= Jj) return;  // whole workgroup idle
     const bool active = b < Jj;
     const uint32_t step = step_of(step_arg, dstep);
     const ZView zv = zview(gr, win, Zall, Mall);
@@ -479,12 +490,12 @@ __global__ __launch_bounds__(1024) void k_birth_mix(DevModel m, const Grp* __res
     // (lane l takes terms l, l + 64, ...); the table passes through LDS in
     // chunks that the 16 births share
     __shared__ double s_lc[MIX_CHUNK], s_mu[4][MIX_CHUNK], s_is[4][MIX_CHUNK];
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
-    const int b = blockIdx.x * 16 + wave_in_block();
+    const int b = slot_tile(m) * 16 + wave_in_block();
     const int lane = threadIdx.x & 63;
     const int Jj = gr.Jj;
-    if (blockIdx.x * 16 >= Jj || Jj >= MIX_LANES_MIN) return;  // whole workgroup idle, or a lane-variant group
+    if (slot_tile(m) * 16 >= Jj || Jj >= MIX_LANES_MIN) return;  // whole workgroup idle, or a lane-variant group
     const bool active = b < Jj;         // wave-uniform
     const uint32_t step = step_of(step_arg, dstep);
     // the table rows of this run's measurements
@@ -593,11 +604,11 @@ __global__ __launch_bounds__(256) void k_birth_mix_lanes(DevModel m, const Grp* 
                                                          const uint32_t* __restrict__ dstep)
 {
     __shared__ double s_lc[MIX_CHUNK], s_mu[4][MIX_CHUNK], s_is[4][MIX_CHUNK];
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
-    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int b = slot_tile(m) * 256 + threadIdx.x;
     const int Jj = gr.Jj;
-    if (blockIdx.x * 256 >= Jj || Jj < MIX_LANES_MIN) return;  // whole workgroup idle, or a wave-variant group
+    if (slot_tile(m) * 256 >= Jj || Jj < MIX_LANES_MIN) return;  // whole workgroup idle, or a wave-variant group
     const bool active = b < Jj;
     const uint32_t step = step_of(step_arg, dstep);
     const double* tab = taball;
@@ -1790,11 +1801,11 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
 {
     __shared__ double rs[4], rm[4];
     __shared__ int h[BEARING_BUCKETS];
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     // chunks of the second pass: the run's zsplit, or (frame passes, wt_births
     // = their tile) one, and BIRTH_CHUNKS in the tiles holding births
     const int zs_run = zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
-    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int s = slot_tile(m) * 256 + threadIdx.x;
     const int zsplit = wt_births > 0 ? (s / wt_births >= tiles_before_births(ncur[j], nsurv[j], wt_births)
                                             ? birth_chunks(ncur[j], nsurv[j], wt_births)
                                             : 1)
@@ -1802,7 +1813,7 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
     const int n = ncur[j];
     const int nt = (n + 255) / 256;
     const int active = nt > 0 ? nt : 1;
-    if ((int)blockIdx.x >= active) return;
+    if ((int)slot_tile(m) >= active) return;
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t KC = (size_t)m.K * m.cap;
     const size_t g = (size_t)j * m.cap + s;
@@ -1829,10 +1840,10 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        pmass[(size_t)j * tiles256 + blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
-        pmax[(size_t)j * tiles256 + blockIdx.x] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
+        pmass[(size_t)j * tiles256 + slot_tile(m)] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+        pmax[(size_t)j * tiles256 + slot_tile(m)] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
     }
-    if (threadIdx.x < BEARING_BUCKETS) bhist[((size_t)j * tiles256 + blockIdx.x) * BEARING_BUCKETS + threadIdx.x] =
+    if (threadIdx.x < BEARING_BUCKETS) bhist[((size_t)j * tiles256 + slot_tile(m)) * BEARING_BUCKETS + threadIdx.x] =
         h[threadIdx.x];
 }
 
@@ -2024,7 +2035,7 @@ __global__ __launch_bounds__(256) void k_bk_hist(DevModel m, SoA<T> st, const in
                                                  int* __restrict__ hist)
 {
     __shared__ int h[BEARING_BUCKETS];
-    const int j = blockIdx.y, t = blockIdx.x;
+    const int j = slot_group(m), t = slot_tile(m);
     const int a = range_first(first, j), n = end[j] - a;
     if (t * 256 >= n) return;
     if (threadIdx.x < BEARING_BUCKETS) h[threadIdx.x] = 0;
@@ -2067,7 +2078,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
                                                     const int* __restrict__ rsS, double* __restrict__ tsum)
 {
     __shared__ int wh[4][BEARING_BUCKETS];  // per-wave bucket counts
-    const int j = blockIdx.y, t = blockIdx.x;
+    const int j = slot_group(m), t = slot_tile(m);
     const int a = range_first(first, j), n = end[j] - a;
     if (t * 256 >= n) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -2198,8 +2209,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T> to, Geo geo,
                                                  const int* __restrict__ first, const int* __restrict__ end)
 {
-    const int j = blockIdx.y;
-    const int s = first[j] + blockIdx.x * 256 + threadIdx.x;
+    const int j = slot_group(m);
+    const int s = first[j] + slot_tile(m) * 256 + threadIdx.x;
     if (s >= end[j]) return;
     const size_t g = (size_t)j * m.cap + s;
     for (int d = 0; d < m.dim; ++d) to.x[d][g] = from.x[d][g];
@@ -2258,7 +2269,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     __shared__ long long s_first;
     __shared__ T s_x[5][256];
     __shared__ double s_q[3][4];
-    const int j = blockIdx.y, t = blockIdx.x;
+    const int j = slot_group(m), t = slot_tile(m);
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const int n = ncur[j];
     const int ntl = (n + 255) / 256;
@@ -2380,10 +2391,10 @@ __global__ __launch_bounds__(256) void k_xchg_gather(DevModel m, const Grp* __re
                                                      const int* __restrict__ nsurv, T* __restrict__ stage, int Lmax,
                                                      uint32_t step_arg, const uint32_t* __restrict__ dstep)
 {
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
     if (gr.K < 2) return;
-    const int mm = blockIdx.x * 256 + threadIdx.x;
+    const int mm = slot_tile(m) * 256 + threadIdx.x;
     const int L = exchange_count(m, gr, nsurv);
     if (mm >= L || mm >= Lmax) return;
     const uint32_t step = step_of(step_arg, dstep);
@@ -2398,10 +2409,10 @@ __global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __r
                                                       const int* __restrict__ nsurv, const T* __restrict__ stage,
                                                       int Lmax, uint32_t step_arg, const uint32_t* __restrict__ dstep)
 {
-    const int j = blockIdx.y;
+    const int j = slot_group(m);
     const Grp gr = gd[j];
     if (gr.K < 2) return;
-    const int mm = blockIdx.x * 256 + threadIdx.x;
+    const int mm = slot_tile(m) * 256 + threadIdx.x;
     const int L = exchange_count(m, gr, nsurv);
     if (mm >= L || mm >= Lmax) return;
     const uint32_t step = step_of(step_arg, dstep);

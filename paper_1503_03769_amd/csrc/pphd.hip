@@ -357,7 +357,8 @@ void set_geometry(pphd_filter* f, const pphd_model* m, const pphd_run_desc* runs
 
 bool sizes_ok(const pphd_run_desc* runs, int nruns, int64_t cap, int32_t max_meas, std::string& why)
 {
-    if (cap < 1 || cap > (1ll << 30) / 4) { why = "cap_per_partition out of range"; return false; }
+    // (tiles of 256 slots index the second grid dimension: at most 65535)
+    if (cap < 1 || cap > 65535ll * 256) { why = "cap_per_partition out of range"; return false; }
     if (max_meas < 1 || max_meas > 65536) { why = "max_meas must be in [1, 65536]"; return false; }
     int64_t groups = 0;
     for (int r = 0; r < nruns; ++r) {
@@ -419,6 +420,9 @@ void fill_devmodel(pphd_filter* f)
         d.bstd[k] = m.birth_std[k];
     }
     d.K = f->K;  // groups over all runs
+    // per-slot grids (tiles, groups) for groups of clearly different sizes
+    // (the second grid dimension holds at most 65535 groups)
+    d.tile_major = f->uneven && f->K <= 65535 ? 1 : 0;
     d.J = f->Jmax;
     d.cap = f->cap;
     d.M0 = f->M0max;
@@ -443,6 +447,13 @@ SoA<T> soa(pphd_filter* f, int b)
 Geo geo_of(pphd_filter* f)
 {
     return Geo{ f->geo_rho, f->geo_phi, f->geo_phib, f->geo_lw };
+}
+
+// grid of a per-slot kernel over `tiles` tiles of every group (the order the
+// device model names)
+dim3 slot_grid(const pphd_filter* f, int tiles)
+{
+    return f->dm.tile_major ? dim3(tiles, f->K) : dim3(f->K, tiles);
 }
 
 // zsplit of a measurement count, as the passes derive it
@@ -519,7 +530,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         const int Jmax = f->Jmax;
         if (Jmax > 0 && dm.proposal == 1) {
             LAUNCH(f, PPHD_K_BIRTH,
-                   hipLaunchKernelGGL((k_birth_meas<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0, f->stream, dm,
+                   hipLaunchKernelGGL((k_birth_meas<T>), slot_grid(f, (Jmax + 255) / 256), dim3(256), 0, f->stream, dm,
                                       f->gd, st, geo, f->nsurv, a.dz, a.M, a.win, f->last_step, a.dstep));
         } else if (Jmax > 0 && dm.proposal == 2) {
             // mixture table of this step's measurements: from the outputs the
@@ -536,12 +547,12 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
             for (const Grp& gg : f->hgd) jmin = std::min(jmin, gg.Jj);
             if (jmin < MIX_LANES_MIN)
                 LAUNCH(f, PPHD_K_BIRTH_MIX,
-                       hipLaunchKernelGGL((k_birth_mix<T>), dim3((std::min(Jmax, MIX_LANES_MIN) + 15) / 16, K),
+                       hipLaunchKernelGGL((k_birth_mix<T>), slot_grid(f, (std::min(Jmax, MIX_LANES_MIN) + 15) / 16),
                                           dim3(1024), 0, f->stream, dm, f->gd, st, geo, f->nsurv, f->mix_tab, a.M,
                                           a.win, f->last_step, a.dstep));
             if (Jmax >= MIX_LANES_MIN)
                 LAUNCH(f, PPHD_K_BIRTH_MIX,
-                       hipLaunchKernelGGL((k_birth_mix_lanes<T>), dim3((Jmax + 255) / 256, K), dim3(256), 0,
+                       hipLaunchKernelGGL((k_birth_mix_lanes<T>), slot_grid(f, (Jmax + 255) / 256), dim3(256), 0,
                                           f->stream, dm, f->gd, st, geo, f->nsurv, f->mix_tab, a.M, a.win,
                                           f->last_step, a.dstep));
         }
@@ -623,7 +634,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                                   (T*)f->accp));
     }
     LAUNCH(f, PPHD_K_WFINAL,
-           hipLaunchKernelGGL((k_wfinal<T>), dim3(f->tiles256, K), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
+           hipLaunchKernelGGL((k_wfinal<T>), slot_grid(f, f->tiles256), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
                               (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256, f->p2mass,
                               f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist, frames ? f->wt2 : 0,
                               f->nsurv));
@@ -657,7 +668,7 @@ pphd_status dispatch_update(pphd_filter* f, const UpdArgs& a)
 template <typename T>
 pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
-    dim3 g((f->cap + 255) / 256, f->K);
+    dim3 g = slot_grid(f, (f->cap + 255) / 256);
     LAUNCH(f, PPHD_K_PREDICT,
            hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
                               f->nsurv, f->ncur, step, dstep));
@@ -669,7 +680,7 @@ pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 template <typename T>
 pphd_status run_init(pphd_filter* f)
 {
-    dim3 g((f->M0max + 255) / 256, f->K);
+    dim3 g = slot_grid(f, (f->M0max + 255) / 256);
     LAUNCH(f, PPHD_K_INIT,
            hipLaunchKernelGGL((k_init<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), f->nsurv));
     return PPHD_OK;
@@ -683,7 +694,7 @@ pphd_status run_init(pphd_filter* f)
 template <typename T>
 pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles)
 {
-    dim3 g(tiles, f->K);
+    dim3 g = slot_grid(f, tiles);
     SoA<T> cur = soa<T>(f, f->cur), oth = soa<T>(f, 1 - f->cur);
     const bool parents = first == nullptr;
     if (!parents || !f->order_ready) {
@@ -719,7 +730,7 @@ pphd_status order_births(pphd_filter* f)
     pphd_status s = bucket_order<T>(f, PPHD_K_BIRTH_ORDER, f->nsurv, bt);
     if (s != PPHD_OK) return s;
     LAUNCH(f, PPHD_K_BIRTH_ORDER,
-           hipLaunchKernelGGL((k_bk_back<T>), dim3(bt, f->K), dim3(256), 0, f->stream, f->dm, soa<T>(f, 1 - f->cur),
+           hipLaunchKernelGGL((k_bk_back<T>), slot_grid(f, bt), dim3(256), 0, f->stream, f->dm, soa<T>(f, 1 - f->cur),
                               soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur));
     return PPHD_OK;
 }
@@ -727,7 +738,7 @@ pphd_status order_births(pphd_filter* f)
 template <typename T>
 pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
-    dim3 g(f->rtiles, f->K);
+    dim3 g = slot_grid(f, f->rtiles);
     // parents into bearing-bucket order (into the other set), then the
     // systematic resampling back into this one
     {
@@ -751,7 +762,7 @@ pphd_status run_exchange(pphd_filter* f, uint32_t step, const uint32_t* dstep)
     bool any = false;
     for (const pphd_run_desc& r : f->runs) any = any || r.partitions > 1;
     if (!any) return PPHD_OK;
-    dim3 g((f->Lmax + 255) / 256, f->K);
+    dim3 g = slot_grid(f, (f->Lmax + 255) / 256);
     SoA<T> st = soa<T>(f, f->cur);
     LAUNCH(f, PPHD_K_XCHG_GATHER,
            hipLaunchKernelGGL((k_xchg_gather<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, st, f->nsurv,
@@ -1085,7 +1096,7 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
     f->births_pending = false;  // a written state is complete
     f->order_ready = false;
     if (phase == PPHD_PHASE_PREDICTED) {
-        dim3 g((f->cap + 255) / 256, f->K);
+        dim3 g = slot_grid(f, (f->cap + 255) / 256);
         if (f->prec == PPHD_FP64) {
             LAUNCH(f, PPHD_K_GEOM,
                    hipLaunchKernelGGL((k_geom<double>), g, dim3(256), 0, f->stream, f->dm, soa<double>(f, f->cur),
