@@ -1069,9 +1069,12 @@ __device__ __forceinline__ int tile_items(int n, int ns, int WT)
     const int nt = (n + WT - 1) / WT, ta = tiles_before_births(n, ns, WT);
     return ta + (nt - ta) * birth_chunks(n, ns, WT);
 }
+// item e of a group, counted from its last item: the birth tiles (the
+// heaviest items) go to the first wavefronts
 __device__ __forceinline__ TileItem tile_item(int e, int n, int ns, int WT)
 {
     const int ta = tiles_before_births(n, ns, WT), z = birth_chunks(n, ns, WT);
+    e = tile_items(n, ns, WT) - 1 - e;
     if (e < ta) return TileItem{ e, 0, 1 };
     return TileItem{ ta + (e - ta) / z, (e - ta) % z, z };
 }

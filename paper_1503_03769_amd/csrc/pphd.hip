@@ -568,10 +568,11 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     const bool frames = f->pass_mode == PASS_FRAMES;
     const ZSorted<T> zsort{ f->zHs, (T*)f->zFs, f->zfls };
     // frame passes: (K, X) grids whose wavefronts stride over each group's
-    // work items, X from the group count (about 8192 wavefronts in all, at
-    // most the items a group can have)
+    // work items, X from the group count (about 4096 wavefronts in all, what
+    // the chip holds at these kernels' register use; at most the items a
+    // group can have)
     auto xdim = [&](int wtiles) {
-        const int64_t most = ((int64_t)wtiles * BIRTH_CHUNKS + 3) / 4, want = (2048 + K - 1) / K;
+        const int64_t most = ((int64_t)wtiles * BIRTH_CHUNKS + 3) / 4, want = (1024 + K - 1) / K;
         return (unsigned)std::max<int64_t>(1, std::min(most, want));
     };
     dim3 gl1(K, xdim(f->wtiles1)), gl2(K, xdim(f->wtiles2));
@@ -598,8 +599,8 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
             ipre2 = ipre1;
             igrp2 = igrp1;
         }
-        gl1 = dim3(2048);
-        gl2 = dim3(2048);
+        gl1 = dim3(1024);
+        gl2 = dim3(1024);
     }
     if (f->pass_mode == PASS_FRAMES) {
         LAUNCH(f, PPHD_K_ZPREP,
