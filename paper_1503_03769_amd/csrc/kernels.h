@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
         }
         w = m.pS * (double)st.w[g];
     } else {
-        if (m.proposal != 0) return;  // drawn by k_birth_meas once Z_k is known
+        if (m.proposal != 0) return;  // drawn by k_birth_draw once Z_k is known
         draw_birth(m, c0, step, RNG_BIRTH, gr.rng_run, v);
         w = m.birth_mass / (double)Jj;
     }
@@ -341,7 +341,15 @@ __global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, co
 }
 
 // ---------------------------------------------------------------------------
-// Births from the measurement-driven proposal of Eq 6 (birth_proposal 1):
+// Births from a measurement-driven proposal of Eq 6 in three launches: the
+// draw (positions and velocities, the weight left for later), the bearing
+// order (k_birth_sort / the range sort, which also records each birth's
+// drawing index), and the weight (one lane per ordered birth: the birth's
+// position is drawn again from its drawing slot's Philox numbers, in double,
+// and its proposal density summed over the terms that the wavefront's
+// bounding box does not put below the exponential's underflow).
+//
+// birth_proposal 1 (the measurement-driven mixture):
 //   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p q_p(x),
 // q_p drawing range N(r_p, sigma_r^2) and bearing N(theta_p, sigma_theta^2)
 // around the sensor.  Position density of q_p at distance rho, bearing phi:
@@ -349,7 +357,12 @@ __global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, co
 // / rho (a negative drawn range lands on the opposite side; 1/rho is the
 // polar Jacobian).  Weight gamma/(J_j q) = m_b U(x) / (J_j q_pos(x)) since
 // both components draw velocity from N(0, sigma_v^2 I).
-// grid (ceil(J_max/256), K).
+// birth_proposal 2 (the learned mixtures):
+//   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p sum_c pi_pc N(x; mu_pc, diag sigma_pc^2),
+// draws per slot: position uniforms (sub 0), velocity normals (sub 1), the
+// choice of measurement and component (sub 2) and the two position normals
+// of a Gaussian component (sub 3); weight gamma(x) / (J_j q(x)), gamma(x) =
+// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wrap_pi(double d)
 {
@@ -367,315 +380,227 @@ __device__ __forceinline__ double neg_exp(double a, double) { return exp(-a); }
 __device__ __forceinline__ double neg_exp_cut(float) { return 104.0; }
 __device__ __forceinline__ double neg_exp_cut(double) { return 745.0; }
 
-constexpr int BIRTH_ZCHUNK = 1024;  // measurements staged in LDS at a time by k_birth_meas
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_birth_meas(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
-                                                    const int* __restrict__ nsurv, const double* __restrict__ Zall,
-                                                    int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
-                                                    const uint32_t* __restrict__ dstep)
-{
-    __shared__ double sz[2 * BIRTH_ZCHUNK];
-    const int j = slot_group(m);
-    const Grp gr = gd[j];
-    const int b = slot_tile(m) * 256 + threadIdx.x;
-    const int Jj = gr.Jj;
-    if (slot_tile(m) * 256 >= Jj) return;  // whole workgroup idle
-    const bool active = b < Jj;
-    const uint32_t step = step_of(step_arg, dstep);
-    const ZView zv = zview(gr, win, Zall, Mall);
-    const double* Z = zv.Z;
-    const int M = zv.M;
-    const size_t g = (size_t)j * m.cap + nsurv[j] + b;
-    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + nsurv[j] + b);
-    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, gr.rng_run);
-    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, gr.rng_run);
-    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, gr.rng_run);
-    const double u1 = uniform53(a.a, a.b), u2 = uniform53(a.c, a.d), uc = uniform53(c.a, c.b);
-    double x, y;
-    if (M == 0 || uc <= m.alpha) {
-        x = m.reg0 + u1 * (m.reg1 - m.reg0);
-        y = m.reg2 + u2 * (m.reg3 - m.reg2);
-    } else {
-        int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
-        p = p > M - 1 ? M - 1 : p;
-        double e1, e2;
-        normal_pair(u1, u2, e1, e2);
-        const double R = Z[2 * p] + m.sigma_r * e1;
-        const double th = Z[2 * p + 1] + m.sigma_th * e2;
-        x = m.sx + R * cos(th);
-        y = m.sy + R * sin(th);
-    }
-    double n1, n2;
-    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), n1, n2);
-    const bool inside = x >= m.reg0 && x <= m.reg1 && y >= m.reg2 && y <= m.reg3;
-    const double u = inside ? m.inv_area : 0.0;
-    double q = u;
-    if (M > 0) {
-        const double dx = x - m.sx, dy = y - m.sy;
-        const double rho = sqrt(dx * dx + dy * dy);
-        const double phi = atan2(dy, dx);
-        const double isr = 1.0 / m.sigma_r, ist = 1.0 / m.sigma_th;
-        const double cut = neg_exp_cut(T(0));
-        double mix = 0.0;
-        // the run's measurements pass through LDS in chunks shared by the workgroup
-        for (int p0 = 0; p0 < M; p0 += BIRTH_ZCHUNK) {
-            const int pn = M - p0 < BIRTH_ZCHUNK ? M - p0 : BIRTH_ZCHUNK;
-            __syncthreads();
-            for (int i = threadIdx.x; i < 2 * pn; i += 256) sz[i] = Z[2 * p0 + i];
-            __syncthreads();
-            if (!active) continue;
-            for (int p = 0; p < pn; ++p) {
-                const double zr = sz[2 * p], zt = sz[2 * p + 1];
-                const double er = (rho - zr) * isr;
-                double t = 0.0;
-                // the range residual alone decides most far measurements
-                if (0.5 * er * er < cut) {
-                    const double et = wrap_pi(phi - zt) * ist;
-                    t = neg_exp(0.5 * (er * er + et * et), T(0));
-                }
-                // the negative-range branch: exactly zero in double once r_p > 40 sigma_r
-                if (zr < 40.0 * m.sigma_r) {
-                    const double fr = (rho + zr) * isr, ft = wrap_pi(phi + 3.14159265358979323846 - zt) * ist;
-                    t += neg_exp(0.5 * (fr * fr + ft * ft), T(0));
-                }
-                mix += t;
-            }
-        }
-        mix *= 1.0 / (2.0 * 3.14159265358979323846 * m.sigma_r * m.sigma_th * rho);
-        q = m.alpha * u + (1.0 - m.alpha) * mix / (double)M;
-    }
-    if (!active) return;
-    const double w = inside ? m.birth_mass * m.inv_area / ((double)Jj * q) : 0.0;
-    const T tx = (T)x, ty = (T)y, tw = (T)w;
-    st.x[0][g] = tx;
-    st.x[1][g] = (T)(m.sigma_v * n1);
-    st.x[2][g] = ty;
-    st.x[3][g] = (T)(m.sigma_v * n2);
-    if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
-    st.w[g] = tw;
-    // the geometry comes with the bearing order (k_birth_sort / k_bk_back)
-}
-
-// ---------------------------------------------------------------------------
-// Births from the learned proposal of Eq 6 (birth_proposal 2):
-//   q(x) = alpha gamma(x)/m_b + (1 - alpha) (1/M) sum_p sum_c pi_pc N(x; mu_pc, diag sigma_pc^2),
-// the table holding each measurement's mixture (layout in mlp_internal.h).
-// Draws per slot: position uniforms (sub 0), velocity normals (sub 1), the
-// choice of measurement and component (sub 2) and the two position normals of
-// a Gaussian component (sub 3).  Weight gamma(x) / (J_j q(x)), gamma(x) =
-// m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).  grid (ceil(J_max/16), K),
-// 1024 threads, one wavefront per birth.
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ double normal_pdf(double d, double sigma)
 {
     const double e = d / sigma;
     return exp(-0.5 * e * e) / (2.5066282746310002 * sigma);
 }
 
-constexpr int MIX_CHUNK = 512;   // mixture-table entries staged in LDS at a time by k_birth_mix
-// groups with at least this many births per step use k_birth_mix_lanes (one
-// lane per birth); smaller ones k_birth_mix (one wavefront per birth), which
-// keeps the chip busy when births are few
-constexpr int MIX_LANES_MIN = 512;
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_birth_mix(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
-                                                    const int* __restrict__ nsurv, const double* __restrict__ taball,
-                                                    int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
-                                                    const uint32_t* __restrict__ dstep)
+// the measurements or mixture rows of group gr's run
+struct BirthSrc {
+    const double* Z;    // proposal 1: the run's measurements
+    const double* tab;  // proposal 2: the run's mixture table
+    int M;
+};
+__device__ __forceinline__ BirthSrc birth_src(const Grp& gr, const ZWin* win, const double* Zall,
+                                              const double* taball, int Mall)
 {
-    // one wavefront per birth, 16 per workgroup: every lane draws the same
-    // particle, the lanes split the 4 M mixture terms of its proposal density
-    // (lane l takes terms l, l + 64, ...); the table passes through LDS in
-    // chunks that the 16 births share
-    __shared__ double s_lc[MIX_CHUNK], s_mu[4][MIX_CHUNK], s_is[4][MIX_CHUNK];
-    const int j = slot_group(m);
-    const Grp gr = gd[j];
-    const int b = slot_tile(m) * 16 + wave_in_block();
-    const int lane = threadIdx.x & 63;
-    const int Jj = gr.Jj;
-    if (slot_tile(m) * 16 >= Jj || Jj >= MIX_LANES_MIN) return;  // whole workgroup idle, or a lane-variant group
-    const bool active = b < Jj;         // wave-uniform
-    const uint32_t step = step_of(step_arg, dstep);
-    // the table rows of this run's measurements
-    const double* tab = taball;
-    int M = Mall;
+    BirthSrc b{ Zall, taball, Mall };
     if (win) {
         const ZWin w = win[gr.run];
-        tab = taball + (size_t)w.off * 4 * MIX_TAB;
-        M = w.M;
+        b.Z = Zall ? Zall + 2 * (size_t)w.off : nullptr;
+        b.tab = taball ? taball + (size_t)w.off * 4 * MIX_TAB : nullptr;
+        b.M = w.M;
     }
-    const size_t g = (size_t)j * m.cap + nsurv[j] + b;
-    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + nsurv[j] + b);
-    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, gr.rng_run);
-    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, gr.rng_run);
-    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, gr.rng_run);
-    double nv1, nv2;
-    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), nv1, nv2);
-    const double uc = uniform53(c.a, c.b), uk = uniform53(c.c, c.d);
-    double x[4];
-    if (M == 0 || uc <= m.alpha || !active) {
+    return b;
+}
+
+// one birth of proposal PROP drawn at Philox slot c0: state [x, vx, y, vy]
+template <int PROP>
+__device__ __forceinline__ void draw_proposal_birth(const DevModel& m, uint32_t c0, uint32_t step, uint32_t run,
+                                                    const BirthSrc& src, double* x)
+{
+    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, run);
+    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, run);
+    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, run);
+    double n1, n2;
+    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), n1, n2);
+    const double uc = uniform53(c.a, c.b);
+    const int M = src.M;
+    if (M == 0 || uc <= m.alpha) {
         x[0] = m.reg0 + uniform53(a.a, a.b) * (m.reg1 - m.reg0);
-        x[1] = m.sigma_v * nv1;
+        x[1] = m.sigma_v * n1;
         x[2] = m.reg2 + uniform53(a.c, a.d) * (m.reg3 - m.reg2);
-        x[3] = m.sigma_v * nv2;
+        x[3] = m.sigma_v * n2;
+        return;
+    }
+    int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
+    p = p > M - 1 ? M - 1 : p;
+    if (PROP == 1) {
+        double e1, e2;
+        normal_pair(uniform53(a.a, a.b), uniform53(a.c, a.d), e1, e2);
+        const double R = src.Z[2 * p] + m.sigma_r * e1;
+        const double th = src.Z[2 * p + 1] + m.sigma_th * e2;
+        x[0] = m.sx + R * cos(th);
+        x[1] = m.sigma_v * n1;
+        x[2] = m.sy + R * sin(th);
+        x[3] = m.sigma_v * n2;
     } else {
-        int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
-        p = p > M - 1 ? M - 1 : p;
+        const double uk = uniform53(c.c, c.d);
         int comp = 3;
         for (int k = 0; k < 4; ++k) {
-            if (uk <= tab[(size_t)(p * 4 + k) * MIX_TAB + 1]) {
+            if (uk <= src.tab[(size_t)(p * 4 + k) * MIX_TAB + 1]) {
                 comp = k;
                 break;
             }
         }
-        const double* t = tab + (size_t)(p * 4 + comp) * MIX_TAB;
-        const Block4 e = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 3, gr.rng_run);
+        const double* t = src.tab + (size_t)(p * 4 + comp) * MIX_TAB;
+        const Block4 e = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 3, run);
         double e1, e2;
         normal_pair(uniform53(e.a, e.b), uniform53(e.c, e.d), e1, e2);
         x[0] = t[4] + t[8] * e1;
-        x[1] = t[5] + t[9] * nv1;
+        x[1] = t[5] + t[9] * n1;
         x[2] = t[6] + t[10] * e2;
-        x[3] = t[7] + t[11] * nv2;
-    }
-    const bool inside = x[0] >= m.reg0 && x[0] <= m.reg1 && x[2] >= m.reg2 && x[2] <= m.reg3;
-    const double bd = inside ? m.inv_area * normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v) : 0.0;
-    const bool needq = active && bd > 0.0 && M > 0;  // wave-uniform
-    const double cut = neg_exp_cut(T(0));
-    double mix = 0.0;
-    for (int e0 = 0; e0 < M * 4; e0 += MIX_CHUNK) {
-        const int en = M * 4 - e0 < MIX_CHUNK ? M * 4 - e0 : MIX_CHUNK;
-        __syncthreads();
-        for (int i = threadIdx.x; i < en; i += 1024) {
-            const double* t = tab + (size_t)(e0 + i) * MIX_TAB;
-            s_lc[i] = t[2];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                s_mu[d][i] = t[4 + d];
-                s_is[d][i] = t[12 + d];
-            }
-        }
-        __syncthreads();
-        if (!needq) continue;
-        for (int i = lane; i < en; i += 64) {
-            const double d0 = (x[0] - s_mu[0][i]) * s_is[0][i], d2 = (x[2] - s_mu[2][i]) * s_is[2][i];
-            // position part first: a far component is skipped before its exponential
-            const double ap = 0.5 * (d0 * d0 + d2 * d2) - s_lc[i];
-            if (ap < cut) {
-                const double d1 = (x[1] - s_mu[1][i]) * s_is[1][i], d3 = (x[3] - s_mu[3][i]) * s_is[3][i];
-                mix += neg_exp(ap + 0.5 * (d1 * d1 + d3 * d3), T(0));
-            }
-        }
-    }
-    if (!active) return;
-    double w = 0.0;
-    if (bd > 0.0) {
-        double q = bd;
-        if (M > 0) {
-            mix = wave_sum(mix);
-            q = m.alpha * bd + (1.0 - m.alpha) * mix / (double)M;
-        }
-        w = m.birth_mass * bd / ((double)Jj * q);
-    }
-    if (lane == 0) {
-        T tx[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            tx[d] = (T)x[d];
-            st.x[d][g] = tx[d];
-        }
-        if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
-        const T tw = (T)w;
-        st.w[g] = tw;
-        // the geometry comes with the bearing order (k_birth_sort / k_bk_back)
+        x[3] = t[7] + t[11] * n2;
     }
 }
 
-// The same births for groups with many of them: one lane per birth, the
-// mixture table broadcast to the lanes from LDS (every lane reads the same
-// entry), so the draws of 64 births share one instruction stream.  Terms are
-// summed in table order.  grid (ceil(J_max/256), K).
-template <typename T>
-__global__ __launch_bounds__(256) void k_birth_mix_lanes(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
-                                                         Geo geo, const int* __restrict__ nsurv,
-                                                         const double* __restrict__ taball, int Mall,
-                                                         const ZWin* __restrict__ win, uint32_t step_arg,
-                                                         const uint32_t* __restrict__ dstep)
+// the draw: births b < (placed births of group j) at slots nsurv_j + b, with
+// their turn rates (dim 5); weights follow in k_birth_weight.
+// grid (groups, ceil(J_max/256)) (or transposed, DevModel::tile_major).
+template <typename T, int PROP>
+__global__ __launch_bounds__(256) void k_birth_draw(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
+                                                    const int* __restrict__ nsurv, const int* __restrict__ ncur,
+                                                    const double* __restrict__ Zall, const double* __restrict__ taball,
+                                                    int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
+                                                    const uint32_t* __restrict__ dstep)
 {
-    __shared__ double s_lc[MIX_CHUNK], s_mu[4][MIX_CHUNK], s_is[4][MIX_CHUNK];
     const int j = slot_group(m);
     const Grp gr = gd[j];
+    const int ns = nsurv[j], nb = ncur[j] - ns;
     const int b = slot_tile(m) * 256 + threadIdx.x;
-    const int Jj = gr.Jj;
-    if (slot_tile(m) * 256 >= Jj || Jj < MIX_LANES_MIN) return;  // whole workgroup idle, or a wave-variant group
-    const bool active = b < Jj;
+    if (b >= nb) return;
     const uint32_t step = step_of(step_arg, dstep);
-    const double* tab = taball;
-    int M = Mall;
-    if (win) {
-        const ZWin w = win[gr.run];
-        tab = taball + (size_t)w.off * 4 * MIX_TAB;
-        M = w.M;
-    }
-    const size_t g = (size_t)j * m.cap + nsurv[j] + b;
-    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + nsurv[j] + b);
-    const Block4 a = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 0, gr.rng_run);
-    const Block4 v = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 1, gr.rng_run);
-    const Block4 c = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 2, gr.rng_run);
-    double nv1, nv2;
-    normal_pair(uniform53(v.a, v.b), uniform53(v.c, v.d), nv1, nv2);
-    const double uc = uniform53(c.a, c.b), uk = uniform53(c.c, c.d);
+    const BirthSrc src = birth_src(gr, win, Zall, taball, Mall);
+    const uint32_t c0 = (uint32_t)(gr.jl * m.cap + ns + b);
     double x[4];
-    if (M == 0 || uc <= m.alpha || !active) {
-        x[0] = m.reg0 + uniform53(a.a, a.b) * (m.reg1 - m.reg0);
-        x[1] = m.sigma_v * nv1;
-        x[2] = m.reg2 + uniform53(a.c, a.d) * (m.reg3 - m.reg2);
-        x[3] = m.sigma_v * nv2;
-    } else {
-        int p = (int)floor((uc - m.alpha) / (1.0 - m.alpha) * (double)M);
-        p = p > M - 1 ? M - 1 : p;
-        int comp = 3;
-        for (int k = 0; k < 4; ++k) {
-            if (uk <= tab[(size_t)(p * 4 + k) * MIX_TAB + 1]) {
-                comp = k;
-                break;
-            }
-        }
-        const double* t = tab + (size_t)(p * 4 + comp) * MIX_TAB;
-        const Block4 e = rng_block(m.key0, m.key1, c0, step, RNG_BIRTH, 3, gr.rng_run);
-        double e1, e2;
-        normal_pair(uniform53(e.a, e.b), uniform53(e.c, e.d), e1, e2);
-        x[0] = t[4] + t[8] * e1;
-        x[1] = t[5] + t[9] * nv1;
-        x[2] = t[6] + t[10] * e2;
-        x[3] = t[7] + t[11] * nv2;
-    }
+    draw_proposal_birth<PROP>(m, c0, step, gr.rng_run, src, x);
+    const size_t g = (size_t)j * m.cap + ns + b;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) st.x[d][g] = (T)x[d];
+    if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
+    st.w[g] = (T)0;
+}
+
+// distance of t from the arc [lo, lo + span] (span in [0, 2 pi])
+__device__ __forceinline__ double arc_dist(double t, double lo, double span)
+{
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    double u = wrap_pi(t - lo);
+    if (u < 0.0) u += two_pi;  // [0, 2 pi)
+    return u <= span ? 0.0 : fmin(u - span, two_pi - u);
+}
+// distance of v from [lo, hi]
+__device__ __forceinline__ double box_gap(double v, double lo, double hi) { return fmax(0.0, fmax(lo - v, v - hi)); }
+
+// the weight: lane = ordered birth s of group j (drawn at index borig[slot]);
+// the wavefront's 64 births bound the terms: proposal 1 by their range
+// interval and bearing arc, proposal 2 by their x and y intervals.  Terms
+// whose bound reaches the cut are exactly those the per-term test of the
+// full sum skips, or below it by a denormal at most.  Then the geometry.
+// grid (groups, ceil(J_max/256)) (or transposed).
+template <typename T, int PROP>
+__global__ __launch_bounds__(256) void k_birth_weight(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                      const int* __restrict__ nsurv, const int* __restrict__ ncur,
+                                                      const int* __restrict__ borig, const double* __restrict__ Zall,
+                                                      const double* __restrict__ taball, int Mall,
+                                                      const ZWin* __restrict__ win, uint32_t step_arg,
+                                                      const uint32_t* __restrict__ dstep)
+{
+    const int j = slot_group(m);
+    const Grp gr = gd[j];
+    const int ns = nsurv[j], nb = ncur[j] - ns;
+    if (slot_tile(m) * 256 >= nb) return;  // whole workgroup idle
+    const int lane = threadIdx.x & 63;
+    const int b = slot_tile(m) * 256 + threadIdx.x;
+    const bool active = b < nb;
+    if (__ballot(active) == 0) return;     // whole wavefront idle
+    const uint32_t step = step_of(step_arg, dstep);
+    const BirthSrc src = birth_src(gr, win, Zall, taball, Mall);
+    const int M = src.M;
+    const size_t g = (size_t)j * m.cap + ns + (active ? b : 0);
+    const int o = active ? borig[g] : 0;
+    double x[4];
+    draw_proposal_birth<PROP>(m, (uint32_t)(gr.jl * m.cap + ns + o), step, gr.rng_run, src, x);
     const bool inside = x[0] >= m.reg0 && x[0] <= m.reg1 && x[2] >= m.reg2 && x[2] <= m.reg3;
-    const double bd = inside ? m.inv_area * normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v) : 0.0;
-    const bool needq = active && bd > 0.0;
+    double bd = inside ? m.inv_area : 0.0;  // gamma / m_b at x (proposal 1: the position part)
+    if (PROP == 2 && inside) bd *= normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v);
+    const bool use = active && bd > 0.0;    // births whose weight needs the density
     const double cut = neg_exp_cut(T(0));
     double mix = 0.0;
-    for (int e0 = 0; e0 < M * 4; e0 += MIX_CHUNK) {
-        const int en = M * 4 - e0 < MIX_CHUNK ? M * 4 - e0 : MIX_CHUNK;
-        __syncthreads();
-        for (int i = threadIdx.x; i < en; i += 256) {
-            const double* t = tab + (size_t)(e0 + i) * MIX_TAB;
-            s_lc[i] = t[2];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                s_mu[d][i] = t[4 + d];
-                s_is[d][i] = t[12 + d];
+    if (M > 0 && __ballot(use) != 0) {
+        const double inf = __builtin_inf();
+        if (PROP == 1) {
+            const double dx = x[0] - m.sx, dy = x[2] - m.sy;
+            const double rho = sqrt(dx * dx + dy * dy), phi = atan2(dy, dx);
+            const double isr = 1.0 / m.sigma_r, ist = 1.0 / m.sigma_th;
+            // the births' range interval and smallest bearing arc (in the
+            // frame whose seam the births avoid)
+            const double pi = 3.14159265358979323846;
+            const double phb = phi > 0.0 ? phi - pi : phi + pi;
+            const double rlo = -wave_max(use ? -rho : -inf), rhi = wave_max(use ? rho : -inf);
+            const double alo = -wave_max(use ? -phi : -inf), ahi = wave_max(use ? phi : -inf);
+            const double blo = -wave_max(use ? -phb : -inf), bhi = wave_max(use ? phb : -inf);
+            const bool fa = ahi - alo <= bhi - blo;
+            const double lo = fa ? alo : blo + pi, span = fa ? ahi - alo : bhi - blo;
+            for (int c0 = 0; c0 < M; c0 += 64) {
+                const int p = c0 + lane;
+                bool need = false;
+                double zr = 0.0, zt = 0.0;
+                if (p < M) {
+                    zr = src.Z[2 * p];
+                    zt = src.Z[2 * p + 1];
+                    const double er = box_gap(zr, rlo, rhi) * isr, et = arc_dist(zt, lo, span) * ist;
+                    need = 0.5 * (er * er + et * et) < cut;
+                    if (zr < 40.0 * m.sigma_r) {
+                        const double fr = box_gap(-zr, rlo, rhi) * isr, ft = arc_dist(zt - pi, lo, span) * ist;
+                        need = need || 0.5 * (fr * fr + ft * ft) < cut;
+                    }
+                }
+                for (uint64_t live = __ballot(need); live; live &= live - 1) {
+                    const int l = __builtin_ctzll(live);
+                    const double r_p = lane_value(zr, l), t_p = lane_value(zt, l);
+                    const double er = (rho - r_p) * isr;
+                    double t = 0.0;
+                    // the range residual alone decides most far measurements
+                    if (0.5 * er * er < cut) {
+                        const double et = wrap_pi(phi - t_p) * ist;
+                        t = neg_exp(0.5 * (er * er + et * et), T(0));
+                    }
+                    // the negative-range branch: exactly zero in double once r_p > 40 sigma_r
+                    if (r_p < 40.0 * m.sigma_r) {
+                        const double fr = (rho + r_p) * isr, ft = wrap_pi(phi + pi - t_p) * ist;
+                        t += neg_exp(0.5 * (fr * fr + ft * ft), T(0));
+                    }
+                    mix += t;
+                }
             }
-        }
-        __syncthreads();
-        if (!needq) continue;
-        for (int i = 0; i < en; ++i) {
-            const double d0 = (x[0] - s_mu[0][i]) * s_is[0][i], d2 = (x[2] - s_mu[2][i]) * s_is[2][i];
-            const double ap = 0.5 * (d0 * d0 + d2 * d2) - s_lc[i];
-            if (ap < cut) {
-                const double d1 = (x[1] - s_mu[1][i]) * s_is[1][i], d3 = (x[3] - s_mu[3][i]) * s_is[3][i];
-                mix += neg_exp(ap + 0.5 * (d1 * d1 + d3 * d3), T(0));
+            mix *= 1.0 / (2.0 * pi * m.sigma_r * m.sigma_th * rho);
+        } else {
+            const double xlo = -wave_max(use ? -x[0] : -inf), xhi = wave_max(use ? x[0] : -inf);
+            const double ylo = -wave_max(use ? -x[2] : -inf), yhi = wave_max(use ? x[2] : -inf);
+            for (int e0 = 0; e0 < 4 * M; e0 += 64) {
+                const int e = e0 + lane;
+                bool need = false;
+                const double* t = src.tab + (size_t)(e < 4 * M ? e : 0) * MIX_TAB;
+                const double lc = t[2], mu0 = t[4], mu1 = t[5], mu2 = t[6], mu3 = t[7];
+                const double is0 = t[12], is1 = t[13], is2 = t[14], is3 = t[15];
+                if (e < 4 * M) {
+                    const double d0 = box_gap(mu0, xlo, xhi) * is0, d2 = box_gap(mu2, ylo, yhi) * is2;
+                    need = 0.5 * (d0 * d0 + d2 * d2) - lc < cut;
+                }
+                // position part first: a far component is skipped before its exponential
+                for (uint64_t live = __ballot(need); live; live &= live - 1) {
+                    const int l = __builtin_ctzll(live);
+                    const double d0 = (x[0] - lane_value(mu0, l)) * lane_value(is0, l);
+                    const double d2 = (x[2] - lane_value(mu2, l)) * lane_value(is2, l);
+                    const double ap = 0.5 * (d0 * d0 + d2 * d2) - lane_value(lc, l);
+                    if (ap < cut) {
+                        const double d1 = (x[1] - lane_value(mu1, l)) * lane_value(is1, l);
+                        const double d3 = (x[3] - lane_value(mu3, l)) * lane_value(is3, l);
+                        mix += neg_exp(ap + 0.5 * (d1 * d1 + d3 * d3), T(0));
+                    }
+                }
             }
         }
     }
@@ -683,18 +608,11 @@ __global__ __launch_bounds__(256) void k_birth_mix_lanes(DevModel m, const Grp* 
     double w = 0.0;
     if (bd > 0.0) {
         const double q = M > 0 ? m.alpha * bd + (1.0 - m.alpha) * mix / (double)M : bd;
-        w = m.birth_mass * bd / ((double)Jj * q);
+        w = m.birth_mass * bd / ((double)gr.Jj * q);
     }
-    T tx[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        tx[d] = (T)x[d];
-        st.x[d][g] = tx[d];
-    }
-    if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
     const T tw = (T)w;
     st.w[g] = tw;
-    // the geometry comes with the bearing order (k_birth_sort / k_bk_back)
+    store_geometry(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)tw);
 }
 
 // scaled squared residual q(z, x) + c
@@ -1078,39 +996,6 @@ __device__ __forceinline__ TileItem tile_item(int e, int n, int ns, int WT)
     if (e < ta) return TileItem{ e, 0, 1 };
     return TileItem{ ta + (e - ta) / z, (e - ta) % z, z };
 }
-// a wavefront's walk over its items (wave-uniform): per group (tpre null,
-// grid (K, X)) or over the flat list (grid (X))
-struct WorkCursor {
-    const int *pre, *grp, *ncur, *nsurv;
-    int WT, e, end, stride, j;
-    __device__ __forceinline__ WorkCursor(int K, const int* tpre, const int* tgrp, const int* nc, const int* nsv,
-                                          int wt)
-        : pre(tpre), grp(tgrp), ncur(nc), nsurv(nsv), WT(wt)
-    {
-        if (pre) {
-            e = blockIdx.x * 4 + wave_in_block();
-            stride = gridDim.x * 4;
-            end = pre[K];
-            j = e < end ? grp[e] : 0;
-        } else {
-            j = blockIdx.x;
-            e = blockIdx.y * 4 + wave_in_block();
-            stride = gridDim.y * 4;
-            end = tile_items(ncur[j], nsurv[j], WT);
-        }
-    }
-    __device__ __forceinline__ bool valid() const { return e < end; }
-    __device__ __forceinline__ void next()
-    {
-        e += stride;
-        if (pre && e < end) j = grp[e];
-    }
-    __device__ __forceinline__ TileItem item() const
-    {
-        return tile_item(pre ? e - pre[j] : e, ncur[j], nsurv[j], WT);
-    }
-};
-
 // the flat list: item counts and their prefix (one workgroup of 1024 threads,
 // thread i taking a contiguous run of ceil(K/1024) groups) ...
 __global__ __launch_bounds__(1024) void k_items_scan(const int* __restrict__ ncur, const int* __restrict__ nsurv,
@@ -1274,10 +1159,14 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
                                                    double* __restrict__ pw, const int* __restrict__ nsurv, int K,
                                                    const int* __restrict__ tpre, const int* __restrict__ tgrp)
 {
-    WorkCursor wc(K, tpre, tgrp, ncur, nsurv, 64 * PT);
-    for (; wc.valid(); wc.next()) {
-        const int j = wc.j;
-        const TileItem it = wc.item();
+    // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
+    const bool flat = tpre != nullptr;
+    const int w0 = (flat ? blockIdx.x : blockIdx.y) * 4 + wave_in_block();
+    const int stride = (flat ? gridDim.x : gridDim.y) * 4;
+    const int end = flat ? tpre[K] : tile_items(ncur[blockIdx.x], nsurv[blockIdx.x], 64 * PT);
+    for (int e = w0; e < end; e += stride) {
+        const int j = flat ? tgrp[e] : (int)blockIdx.x;
+        const TileItem it = tile_item(flat ? e - tpre[j] : e, ncur[j], nsurv[j], 64 * PT);
         cz_frames_tile<T, PT>(m, gd, geo, W, ncur, Mall, win, zp, Mmax, sp, ps, ph, pw, j, it.tile, it.chunk,
                               it.chunks);
     }
@@ -1458,10 +1347,14 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
                                                        T* __restrict__ accp, const int* __restrict__ nsurv, int K,
                                                        const int* __restrict__ tpre, const int* __restrict__ tgrp)
 {
-    WorkCursor wc(K, tpre, tgrp, ncur, nsurv, 64 * PT);
-    for (; wc.valid(); wc.next()) {
-        const int j = wc.j;
-        const TileItem it = wc.item();
+    // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
+    const bool flat = tpre != nullptr;
+    const int w0 = (flat ? blockIdx.x : blockIdx.y) * 4 + wave_in_block();
+    const int stride = (flat ? gridDim.x : gridDim.y) * 4;
+    const int end = flat ? tpre[K] : tile_items(ncur[blockIdx.x], nsurv[blockIdx.x], 64 * PT);
+    for (int e = w0; e < end; e += stride) {
+        const int j = flat ? tgrp[e] : (int)blockIdx.x;
+        const TileItem it = tile_item(flat ? e - tpre[j] : e, ncur[j], nsurv[j], 64 * PT);
         weight_frames_tile<T, PT>(m, gd, st, geo, ncur, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, j,
                                   it.tile, it.chunk, it.chunks);
     }
@@ -2078,7 +1971,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T> out, const int* __restrict__ first,
                                                     const int* __restrict__ end, int rtiles,
                                                     const int* __restrict__ bkt, const int* __restrict__ off,
-                                                    const int* __restrict__ rsS, double* __restrict__ tsum)
+                                                    const int* __restrict__ rsS, double* __restrict__ tsum,
+                                                    int* __restrict__ orig)
 {
     __shared__ int wh[4][BEARING_BUCKETS];  // per-wave bucket counts
     const int j = slot_group(m), t = slot_tile(m);
@@ -2108,6 +2002,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
         dst = off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] + rank;
         for (int d = 0; d < m.dim; ++d) out.x[d][gb + dst] = in.x[d][gb + s];
         out.w[gb + dst] = in.w[gb + s];
+        if (orig) orig[gb + dst] = s;
     }
     if (!tsum) return;
     // per destination tile: one wave sum and one atomic addition per distinct tile
@@ -2132,9 +2027,12 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
 // (ballot peers within a wave, earlier waves' counts of the chunk, earlier
 // chunks' counts), and after a barrier every birth is written back in place
 // at its rank with its geometry.  grid (K), 1024 threads.
+// borig (optional): each ordered slot's drawing index; with_geo: write the
+// geometry (births whose weights are already final)
 template <typename T, int BS>
 __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
-                                                     const int* __restrict__ ncur)
+                                                     const int* __restrict__ ncur, int* __restrict__ borig,
+                                                     int with_geo)
 {
     __shared__ int s_off[BEARING_BUCKETS];
     __shared__ int s_w[16][BEARING_BUCKETS];
@@ -2202,7 +2100,8 @@ __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo 
         for (int d = 0; d < 5; ++d)
             if (d < m.dim) st.x[d][g] = v[c][d];
         st.w[g] = w[c];
-        store_geometry(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
+        if (borig) borig[g] = c * 1024 + tid;
+        if (with_geo) store_geometry(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
     }
 }
 
@@ -2210,7 +2109,8 @@ __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo 
 // (a function of the stored state).  grid (ceil(Jmax/256), K)
 template <typename T>
 __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T> to, Geo geo,
-                                                 const int* __restrict__ first, const int* __restrict__ end)
+                                                 const int* __restrict__ first, const int* __restrict__ end,
+                                                 int with_geo)
 {
     const int j = slot_group(m);
     const int s = first[j] + slot_tile(m) * 256 + threadIdx.x;
@@ -2219,7 +2119,7 @@ __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T>
     for (int d = 0; d < m.dim; ++d) to.x[d][g] = from.x[d][g];
     const T x = from.x[0][g], y = from.x[2][g], w = from.w[g];
     to.w[g] = w;
-    store_geometry(m, geo, g, (double)x, (double)y, (double)w);
+    if (with_geo) store_geometry(m, geo, g, (double)x, (double)y, (double)w);
 }
 
 // ---------------------------------------------------------------------------

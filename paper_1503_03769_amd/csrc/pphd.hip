@@ -54,7 +54,7 @@ constexpr int MZ_DEFAULT = 16;
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
     "k_rs_tiles", "k_rs_expand", "k_xchg_gather", "k_xchg_scatter", "k_init", "k_wmax",
-    "k_geom", "k_wfinal", "k_birth_meas", "k_mlp_infer", "k_birth_mix", "k_zprep", "k_bk_scatter", "k_bk_back",
+    "k_geom", "k_wfinal", "k_birth_weight", "k_mlp_infer", "k_birth_mix", "k_zprep", "k_bk_scatter", "k_bk_back",
 };
 
 struct Layout {
@@ -139,6 +139,7 @@ struct pphd_filter {
     double *tsum = nullptr, *massq = nullptr;
     int* counts = nullptr;
     int *bkt = nullptr, *bhist = nullptr, *boff = nullptr;  // bearing-bucket order of the parents
+    int* borig = nullptr;  // drawing index of each ordered birth
     bool order_ready = false;  // the last update left the parents' bucket offsets and cleared tile sums
     bool uneven = false;       // groups of different sizes: the frame passes walk flat item lists
     int *ipre1 = nullptr, *igrp1 = nullptr, *ipre2 = nullptr, *igrp2 = nullptr;  // those lists
@@ -238,6 +239,7 @@ size_t carve(pphd_filter* f, char* base)
     f->massq = L.take<double>(base, K * 8);
     f->counts = L.take<int>(base, KC * 4);
     f->bkt = L.take<int>(base, KC * 4);
+    f->borig = L.take<int>(base, KC * 4);
     f->ipre1 = L.take<int>(base, (K + 1) * 4);
     f->igrp1 = L.take<int>(base, K * f->wtiles_max * BIRTH_CHUNKS * 4);  // at most BIRTH_CHUNKS items per tile
     f->ipre2 = L.take<int>(base, (K + 1) * 4);
@@ -513,7 +515,7 @@ pphd_status launch(pphd_filter* f, int cls, F&& fn)
     } while (0)
 
 template <typename T>
-pphd_status order_births(pphd_filter* f);
+pphd_status order_births(pphd_filter* f, bool weights_later);
 
 template <typename T, int PT1, int PT2>
 pphd_status run_update(pphd_filter* f, const UpdArgs& a)
@@ -527,41 +529,44 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     // a group's own chunk count exit at once)
     const int zs = a.win ? ZSPLIT_MAX : host_zsplit(a.M, f->mz);
     if (f->births_pending) {
+        // births of the measurement-driven proposals: draw, bearing order
+        // (recording each birth's drawing index), weights with the geometry
         const int Jmax = f->Jmax;
-        if (Jmax > 0 && dm.proposal == 1) {
-            LAUNCH(f, PPHD_K_BIRTH,
-                   hipLaunchKernelGGL((k_birth_meas<T>), slot_grid(f, (Jmax + 255) / 256), dim3(256), 0, f->stream, dm,
-                                      f->gd, st, geo, f->nsurv, a.dz, a.M, a.win, f->last_step, a.dstep));
-        } else if (Jmax > 0 && dm.proposal == 2) {
-            // mixture table of this step's measurements: from the outputs the
-            // caller set, else from the attached network
-            const int rows = a.win ? a.zrows : a.M;
-            pphd_status ms = PPHD_OK;
-            LAUNCH(f, PPHD_K_MLP_INFER,
-                   ms = f->mix_preset ? mlp_head_table(f->model, f->stream, a.dz, f->mix_raw, rows, f->mix_tab)
-                                      : mlp_mixture_table(f->mlp, f->stream, a.dz, rows, f->mix_tab));
-            if (ms != PPHD_OK) return ms;
-            // a group's own birth count picks the variant, so a run draws the
-            // same births alone or in a batch
-            int jmin = Jmax;
-            for (const Grp& gg : f->hgd) jmin = std::min(jmin, gg.Jj);
-            if (jmin < MIX_LANES_MIN)
-                LAUNCH(f, PPHD_K_BIRTH_MIX,
-                       hipLaunchKernelGGL((k_birth_mix<T>), slot_grid(f, (std::min(Jmax, MIX_LANES_MIN) + 15) / 16),
-                                          dim3(1024), 0, f->stream, dm, f->gd, st, geo, f->nsurv, f->mix_tab, a.M,
-                                          a.win, f->last_step, a.dstep));
-            if (Jmax >= MIX_LANES_MIN)
-                LAUNCH(f, PPHD_K_BIRTH_MIX,
-                       hipLaunchKernelGGL((k_birth_mix_lanes<T>), slot_grid(f, (Jmax + 255) / 256), dim3(256), 0,
-                                          f->stream, dm, f->gd, st, geo, f->nsurv, f->mix_tab, a.M, a.win,
-                                          f->last_step, a.dstep));
+        if (Jmax > 0 && (dm.proposal == 1 || dm.proposal == 2)) {
+            const int cls = dm.proposal == 1 ? PPHD_K_BIRTH : PPHD_K_BIRTH_MIX;
+            if (dm.proposal == 2) {
+                // mixture table of this step's measurements: from the outputs
+                // the caller set, else from the attached network
+                const int rows = a.win ? a.zrows : a.M;
+                pphd_status ms = PPHD_OK;
+                LAUNCH(f, PPHD_K_MLP_INFER,
+                       ms = f->mix_preset ? mlp_head_table(f->model, f->stream, a.dz, f->mix_raw, rows, f->mix_tab)
+                                          : mlp_mixture_table(f->mlp, f->stream, a.dz, rows, f->mix_tab));
+                if (ms != PPHD_OK) return ms;
+            }
+            const dim3 gb = slot_grid(f, (Jmax + 255) / 256);
+            const double* tab = dm.proposal == 2 ? f->mix_tab : nullptr;
+            if (dm.proposal == 1)
+                LAUNCH(f, cls,
+                       hipLaunchKernelGGL((k_birth_draw<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, f->nsurv,
+                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
+            else
+                LAUNCH(f, cls,
+                       hipLaunchKernelGGL((k_birth_draw<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st, f->nsurv,
+                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
+            pphd_status os = order_births<T>(f, true);
+            if (os != PPHD_OK) return os;
+            if (dm.proposal == 1)
+                LAUNCH(f, cls,
+                       hipLaunchKernelGGL((k_birth_weight<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
+                                          f->nsurv, f->ncur, f->borig, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
+            else
+                LAUNCH(f, cls,
+                       hipLaunchKernelGGL((k_birth_weight<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
+                                          f->nsurv, f->ncur, f->borig, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
         }
         f->mix_preset = false;
         f->births_pending = false;
-        if (dm.proposal != 0) {
-            pphd_status os = order_births<T>(f);
-            if (os != PPHD_OK) return os;
-        }
     }
     dim3 g1((f->wtiles1 * zs + 3) / 4, K), g2((f->wtiles2 * zs + 3) / 4, K);
     const ZPrepC zpc{ f->zprep.zs, f->zprep.orig, f->zprep.pos, f->zprep.nA };
@@ -674,7 +679,7 @@ pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
            hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
                               f->nsurv, f->ncur, step, dstep));
     // births of the birth density are drawn by k_predict
-    if (f->dm.proposal == 0) return order_births<T>(f);
+    if (f->dm.proposal == 0) return order_births<T>(f, false);
     return PPHD_OK;
 }
 
@@ -693,7 +698,7 @@ pphd_status run_init(pphd_filter* f)
 // parents (first == nullptr): the scatter also forms the resampling's tile
 // sums, and the histogram and offsets come from the update when it left them
 template <typename T>
-pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles)
+pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, int* orig = nullptr)
 {
     dim3 g = slot_grid(f, tiles);
     SoA<T> cur = soa<T>(f, f->cur), oth = soa<T>(f, 1 - f->cur);
@@ -708,31 +713,36 @@ pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles)
     }
     LAUNCH(f, cls,
            hipLaunchKernelGGL((k_bk_scatter<T>), g, dim3(256), 0, f->stream, f->dm, cur, oth, first, f->ncur,
-                              f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr));
+                              f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr, orig));
     if (parents) f->order_ready = false;
     return PPHD_OK;
 }
 
 // the births of every group (slots [nsurv_j, ncur_j)) in bearing-bucket order
-// once drawn: sorted into the other set, then back with their geometry
+// once drawn (in place, or sorted into the other set and back), with their
+// geometry; weights_later: the births' weights (and so their geometry) come
+// after the order, which then records each ordered slot's drawing index in
+// borig
 template <typename T>
-pphd_status order_births(pphd_filter* f)
+pphd_status order_births(pphd_filter* f, bool weights_later)
 {
     if (f->Jmax <= 0) return PPHD_OK;
+    int* orig = weights_later ? f->borig : nullptr;
+    const int geo_now = weights_later ? 0 : 1;
     // up to 1024 BS births per group: one workgroup per group, in place
     constexpr int BS = sizeof(T) == 4 ? 8 : 4;
     if (f->Jmax <= 1024 * BS) {
         LAUNCH(f, PPHD_K_BIRTH_ORDER,
                hipLaunchKernelGGL((k_birth_sort<T, BS>), dim3(f->K), dim3(1024), 0, f->stream, f->dm,
-                                  soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur));
+                                  soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur, orig, geo_now));
         return PPHD_OK;
     }
     const int bt = (f->Jmax + 255) / 256;
-    pphd_status s = bucket_order<T>(f, PPHD_K_BIRTH_ORDER, f->nsurv, bt);
+    pphd_status s = bucket_order<T>(f, PPHD_K_BIRTH_ORDER, f->nsurv, bt, orig);
     if (s != PPHD_OK) return s;
     LAUNCH(f, PPHD_K_BIRTH_ORDER,
            hipLaunchKernelGGL((k_bk_back<T>), slot_grid(f, bt), dim3(256), 0, f->stream, f->dm, soa<T>(f, 1 - f->cur),
-                              soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur));
+                              soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur, geo_now));
     return PPHD_OK;
 }
 
