@@ -36,6 +36,31 @@ struct DevModel {
 __device__ __forceinline__ int slot_group(const DevModel& m) { return m.tile_major ? blockIdx.y : blockIdx.x; }
 __device__ __forceinline__ int slot_tile(const DevModel& m) { return m.tile_major ? blockIdx.x : blockIdx.y; }
 
+// ---------------------------------------------------------------------------
+// Bearing order: before the systematic resampling (Step 5) every group's
+// parents, and once drawn its births, are taken in bearing-bucket order
+// (buckets ascending, slot order inside a bucket), so that nearby particles
+// sit together and a likelihood-pass tile spans a narrow bearing range.  The
+// bucket is the "diamond angle" d in [0, 4) of the offset from the sensor
+// (monotonic in the bearing counter-clockwise from +x, one correctly rounded
+// division), times BEARING_BUCKETS/4, rounded down; a birth's bucket is that
+// of its position as drawn (in double, before the storage rounding).  A
+// stable counting sort: per-tile bucket histograms, bucket-major offsets per
+// group, a scatter into the other particle set.
+// ---------------------------------------------------------------------------
+constexpr int BEARING_BUCKETS = 64;
+
+__device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
+{
+    const double dx = x - m.sx, dy = y - m.sy;
+    double d;
+    if (dx == 0.0 && dy == 0.0) d = 0.0;
+    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
+    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+    const int b = (int)floor(d * (BEARING_BUCKETS / 4.0));
+    return b < 0 ? 0 : (b > BEARING_BUCKETS - 1 ? BEARING_BUCKETS - 1 : b);
+}
+
 template <typename T>
 struct SoA {
     T* x[5];  // x[4] (the turn rate) only with dim 5
@@ -254,7 +279,8 @@ __device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_
 template <typename T>
 __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
                                                  const int* __restrict__ nsurv, int* __restrict__ ncur,
-                                                 uint32_t step_arg, const uint32_t* __restrict__ dstep)
+                                                 uint32_t step_arg, const uint32_t* __restrict__ dstep,
+                                                 int* __restrict__ bkt)
 {
     const int j = slot_group(m);
     const Grp gr = gd[j];
@@ -314,8 +340,10 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
     if (m.dim == 5) st.x[4][g] = (T)v[4];
     const T tw = (T)w;
     st.w[g] = tw;
-    // births get their geometry once put in bearing order
+    // births get their geometry once put in bearing order, by the bucket of
+    // the position as drawn
     if (s < ns) store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
+    else bkt[g] = bearing_bucket(m, v[0], v[2]);
 }
 
 // dim 5: the turn rate of a birth drawn from a measurement-driven or learned
@@ -463,7 +491,7 @@ __global__ __launch_bounds__(256) void k_birth_draw(DevModel m, const Grp* __res
                                                     const int* __restrict__ nsurv, const int* __restrict__ ncur,
                                                     const double* __restrict__ Zall, const double* __restrict__ taball,
                                                     int Mall, const ZWin* __restrict__ win, uint32_t step_arg,
-                                                    const uint32_t* __restrict__ dstep)
+                                                    const uint32_t* __restrict__ dstep, int* __restrict__ bkt)
 {
     const int j = slot_group(m);
     const Grp gr = gd[j];
@@ -480,6 +508,7 @@ __global__ __launch_bounds__(256) void k_birth_draw(DevModel m, const Grp* __res
     for (int d = 0; d < 4; ++d) st.x[d][g] = (T)x[d];
     if (m.dim == 5) st.x[4][g] = (T)birth_turn_rate(m, c0, step, gr.rng_run);
     st.w[g] = (T)0;
+    bkt[g] = bearing_bucket(m, x[0], x[2]);
 }
 
 // distance of t from the arc [lo, lo + span] (span in [0, 2 pi])
@@ -1618,28 +1647,6 @@ __device__ __forceinline__ int quant_shift(double wmax, int n)
     return 52 - ceil_log2(n) - e;
 }
 
-// ---------------------------------------------------------------------------
-// Step 5, parent order: the parents of every group are taken in bearing-
-// bucket order (buckets ascending, slot order inside a bucket) so that the
-// children of nearby parents sit together and a likelihood-pass tile spans a
-// narrow bearing range.  The bucket is the "diamond angle" d in [0, 4) of the
-// offset from the sensor (monotonic in the bearing counter-clockwise from +x,
-// one correctly rounded division), times BEARING_BUCKETS/4, rounded down.
-// A stable counting sort in three launches: per-tile bucket histograms,
-// bucket-major offsets per group, scatter into the other particle set.
-// ---------------------------------------------------------------------------
-constexpr int BEARING_BUCKETS = 64;
-
-__device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
-{
-    const double dx = x - m.sx, dy = y - m.sy;
-    double d;
-    if (dx == 0.0 && dy == 0.0) d = 0.0;
-    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
-    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
-    const int b = (int)floor(d * (BEARING_BUCKETS / 4.0));
-    return b < 0 ? 0 : (b > BEARING_BUCKETS - 1 ? BEARING_BUCKETS - 1 : b);
-}
 
 // Bucket-major exclusive offsets of group j's ntl tiles, off[t][b] = all
 // slots of lower buckets + slots of bucket b in lower tiles, by a workgroup
@@ -1925,10 +1932,11 @@ __global__ __launch_bounds__(256) void k_wmax(DevModel m, const T* __restrict__ 
 __device__ __forceinline__ int range_first(const int* first, int j) { return first ? first[j] : 0; }
 
 // grid (tiles, K), 256 threads: bucket of every slot, per-tile histograms
+// keys_stored: the slots' buckets are already in bkt (births)
 template <typename T>
 __global__ __launch_bounds__(256) void k_bk_hist(DevModel m, SoA<T> st, const int* __restrict__ first,
                                                  const int* __restrict__ end, int rtiles, int* __restrict__ bkt,
-                                                 int* __restrict__ hist)
+                                                 int* __restrict__ hist, int keys_stored)
 {
     __shared__ int h[BEARING_BUCKETS];
     const int j = slot_group(m), t = slot_tile(m);
@@ -1939,8 +1947,8 @@ __global__ __launch_bounds__(256) void k_bk_hist(DevModel m, SoA<T> st, const in
     const int s = t * 256 + threadIdx.x;
     const size_t g = (size_t)j * m.cap + a + s;
     if (s < n) {
-        const int b = bearing_bucket(m, (double)st.x[0][g], (double)st.x[2][g]);
-        bkt[g] = b;
+        const int b = keys_stored ? bkt[g] : bearing_bucket(m, (double)st.x[0][g], (double)st.x[2][g]);
+        if (!keys_stored) bkt[g] = b;
         atomicAdd(&h[b], 1);
     }
     __syncthreads();
@@ -2032,7 +2040,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
 template <typename T, int BS>
 __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
                                                      const int* __restrict__ ncur, int* __restrict__ borig,
-                                                     int with_geo)
+                                                     int with_geo, const int* __restrict__ bkt)
 {
     __shared__ int s_off[BEARING_BUCKETS];
     __shared__ int s_w[16][BEARING_BUCKETS];
@@ -2054,7 +2062,7 @@ __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo 
 #pragma unroll
             for (int d = 0; d < 5; ++d) v[c][d] = d < m.dim ? st.x[d][gb + i] : (T)0;
             w[c] = st.w[gb + i];
-            b[c] = bearing_bucket(m, (double)v[c][0], (double)v[c][2]);
+            b[c] = bkt[gb + i];  // the bucket of the birth as drawn
             atomicAdd(&s_off[b[c]], 1);
         }
     }

@@ -549,11 +549,11 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
             if (dm.proposal == 1)
                 LAUNCH(f, cls,
                        hipLaunchKernelGGL((k_birth_draw<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, f->nsurv,
-                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
+                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep, f->bkt));
             else
                 LAUNCH(f, cls,
                        hipLaunchKernelGGL((k_birth_draw<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st, f->nsurv,
-                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
+                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep, f->bkt));
             pphd_status os = order_births<T>(f, true);
             if (os != PPHD_OK) return os;
             if (dm.proposal == 1)
@@ -677,7 +677,7 @@ pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
     dim3 g = slot_grid(f, (f->cap + 255) / 256);
     LAUNCH(f, PPHD_K_PREDICT,
            hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
-                              f->nsurv, f->ncur, step, dstep));
+                              f->nsurv, f->ncur, step, dstep, f->bkt));
     // births of the birth density are drawn by k_predict
     if (f->dm.proposal == 0) return order_births<T>(f, false);
     return PPHD_OK;
@@ -706,7 +706,7 @@ pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, i
     if (!parents || !f->order_ready) {
         LAUNCH(f, cls,
                hipLaunchKernelGGL((k_bk_hist<T>), g, dim3(256), 0, f->stream, f->dm, cur, first, f->ncur, f->rtiles,
-                                  f->bkt, f->bhist));
+                                  f->bkt, f->bhist, parents ? 0 : 1));
         LAUNCH(f, cls,
                hipLaunchKernelGGL(k_bk_scan, dim3(f->K), dim3(1024), 0, f->stream, first, f->ncur, f->rtiles,
                                   f->bhist, f->boff, parents ? f->tsum : nullptr));
@@ -734,7 +734,7 @@ pphd_status order_births(pphd_filter* f, bool weights_later)
     if (f->Jmax <= 1024 * BS) {
         LAUNCH(f, PPHD_K_BIRTH_ORDER,
                hipLaunchKernelGGL((k_birth_sort<T, BS>), dim3(f->K), dim3(1024), 0, f->stream, f->dm,
-                                  soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur, orig, geo_now));
+                                  soa<T>(f, f->cur), geo_of(f), f->nsurv, f->ncur, orig, geo_now, f->bkt));
         return PPHD_OK;
     }
     const int bt = (f->Jmax + 255) / 256;

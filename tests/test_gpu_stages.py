@@ -24,6 +24,10 @@ PREDICT_CASES = [
     ("fp64", 1, [3000], 500, 8192),
     ("fp64", 3, [3000, 1234, 0], 100, 5000),
     ("fp32", 4, [9000, 4097, 1, 0], 77, 12000),
+    # more births per group than one workgroup orders in registers (8192 in
+    # FP32, 4096 in FP64): the multi-launch bearing order
+    ("fp32", 2, [2000, 500], 20000, 13000),
+    ("fp64", 1, [300], 5000, 6000),
 ]
 
 
@@ -159,15 +163,18 @@ def test_exchange_exact(gpu, prec, K, counts):
     f.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_measurement_driven_births(gpu, prec):
+@pytest.mark.parametrize("prec,K,J,counts,cap", [("fp64", 3, 900, [2000, 700, 0], 4096),
+                                                 ("fp32", 3, 900, [2000, 700, 0], 4096),
+                                                 ("fp32", 2, 18000, [1500, 300], 11000),
+                                                 ("fp64", 1, 5000, [800], 6000)])
+def test_measurement_driven_births(gpu, prec, K, J, counts, cap):
     """Eq 6 with p_k(.|Z_k): predict reserves the birth slots, update draws
-    them from the measurement-driven mixture and then updates all weights."""
-    print(f"measurement-driven births {prec}", flush=True)
-    K, cap = 3, 4096
-    p = dict(BASE_MODEL, partitions=K, births_per_step=900, birth_proposal=1, birth_alpha=0.1)
+    them from the measurement-driven mixture and then updates all weights
+    (the last two cases order their births in several launches)."""
+    print(f"measurement-driven births {prec} K={K} J={J}", flush=True)
+    p = dict(BASE_MODEL, partitions=K, births_per_step=J, birth_proposal=1, birth_alpha=0.1)
     truth, Z = _scen(p, n=4)
-    X, W, n = P.cloud(K, cap, [2000, 700, 0], 13, truth, prec)
+    X, W, n = P.cloud(K, cap, counts, 13, truth, prec)
     f = P.make_filter(p, prec, cap)
     f.write_state(X, W, n, pphd.PHASE_READY)
     f.predict(4)
