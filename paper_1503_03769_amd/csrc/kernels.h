@@ -2335,6 +2335,61 @@ __global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __r
     st.w[dst] = o[5];
 }
 
+// Step 6 in one launch for runs of at most 1024 groups: stratum m moves one
+// couple per group, S_j(m) -> S_{j+1}(m), so a workgroup that holds whole
+// strata of one run (1024 / K_r strata, thread = (stratum, group)) reads its
+// couples, waits, and writes each to the next group's slot of the same
+// stratum.  Workgroups touch different strata, so every read still sees the
+// state before the exchange.  The run's count L and each group's offset b_j
+// are formed once per workgroup.  grid (runs, ceil(Lmax / (1024 / K_r))).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_xchg_ring(DevModel m, const Grp* __restrict__ gd,
+                                                   const int* __restrict__ run_g0, SoA<T> st,
+                                                   const int* __restrict__ nsurv, int Lmax, uint32_t step_arg,
+                                                   const uint32_t* __restrict__ dstep)
+{
+    __shared__ T s_c[6][1024];
+    __shared__ uint64_t s_b[1024];
+    __shared__ int s_n[1024];
+    __shared__ int s_min[16];
+    const Grp g0 = gd[run_g0[blockIdx.x]];
+    const int Kr = g0.K;
+    if (Kr < 2 || Kr > 1024) return;
+    const int spb = 1024 / Kr;
+    if ((int)blockIdx.y * spb >= Lmax) return;  // whole workgroup idle
+    const uint32_t step = step_of(step_arg, dstep);
+    const int tid = threadIdx.x;
+    int mn = 2147483647;
+    if (tid < Kr) {
+        const int n = nsurv[g0.g0 + tid];
+        const Block4 a = rng_block(m.key0, m.key1, (uint32_t)tid, step, RNG_EXCHANGE, 0, g0.rng_run);
+        s_n[tid] = n;
+        s_b[tid] = ((uint64_t)a.a * (uint64_t)n) >> 32;
+        mn = n;
+    }
+    mn = -wave_max(-mn);
+    if ((tid & 63) == 0) s_min[tid >> 6] = mn;
+    __syncthreads();
+    mn = s_min[0];
+    for (int w = 1; w < 16; ++w) mn = s_min[w] < mn ? s_min[w] : mn;
+    const int L = (int)floor(m.xfrac * (double)mn);
+    const int ml = tid / Kr, jl = tid - ml * Kr;
+    const int mm = (int)blockIdx.y * spb + ml;
+    const bool live = ml < spb && mm < L;
+    if (live) {
+        const size_t src = (size_t)(g0.g0 + jl) * m.cap + ((uint64_t)mm * (uint64_t)s_n[jl] + s_b[jl]) / (uint64_t)L;
+        for (int d = 0; d < m.dim; ++d) s_c[d][tid] = st.x[d][src];
+        s_c[5][tid] = st.w[src];
+    }
+    __syncthreads();
+    if (live) {
+        const int jn = jl + 1 < Kr ? jl + 1 : 0;
+        const size_t dst = (size_t)(g0.g0 + jn) * m.cap + ((uint64_t)mm * (uint64_t)s_n[jn] + s_b[jn]) / (uint64_t)L;
+        for (int d = 0; d < m.dim; ++d) st.x[d][dst] = s_c[d][tid];
+        st.w[dst] = s_c[5][tid];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched updates: the runs' measurement windows as given, clamped into the
 // step's set (count to [0, max_meas], the window inside [0, zrows)), so no

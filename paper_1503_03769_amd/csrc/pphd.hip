@@ -771,10 +771,25 @@ template <typename T>
 pphd_status run_exchange(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
     bool any = false;
-    for (const pphd_run_desc& r : f->runs) any = any || r.partitions > 1;
+    int kmax = 1;
+    for (const pphd_run_desc& r : f->runs) {
+        any = any || r.partitions > 1;
+        kmax = std::max(kmax, (int)r.partitions);
+    }
     if (!any) return PPHD_OK;
-    dim3 g = slot_grid(f, (f->Lmax + 255) / 256);
     SoA<T> st = soa<T>(f, f->cur);
+    // runs of at most 1024 groups: one launch over whole strata
+    if (kmax <= 1024) {
+        const int spb = 1024 / kmax;
+        const int64_t gy = ((int64_t)f->Lmax + spb - 1) / spb;
+        if (gy <= 65535) {
+            LAUNCH(f, PPHD_K_XCHG_SCATTER,
+                   hipLaunchKernelGGL((k_xchg_ring<T>), dim3(f->nruns, (unsigned)gy), dim3(1024), 0, f->stream, f->dm,
+                                      f->gd, f->run_g0, st, f->nsurv, f->Lmax, step, dstep));
+            return PPHD_OK;
+        }
+    }
+    dim3 g = slot_grid(f, (f->Lmax + 255) / 256);
     LAUNCH(f, PPHD_K_XCHG_GATHER,
            hipLaunchKernelGGL((k_xchg_gather<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, st, f->nsurv,
                               (T*)f->stage, f->Lmax, step, dstep));

@@ -252,3 +252,25 @@ def test_gaussian_birth_density_matches_oracle(gpu):
     orc.predict(p, st, 1, 1234, 0)
     P.check_states(Xg, Wg, ng, st, "fp64")
     f.close()
+
+
+def test_exchange_exact_many_groups(gpu):
+    """A run of more groups than one workgroup holds per stratum (1100 > 1024)
+    takes the two-launch exchange; it must equal the oracle's exactly."""
+    K, cap = 1100, 128
+    print(f"exchange fp32 K={K}", flush=True)
+    rng = np.random.default_rng(12)
+    counts = [int(c) for c in rng.integers(40, 120, K)]
+    p = dict(BASE_MODEL, partitions=K, births_per_step=0)
+    X, W, n = P.cloud(K, cap, counts, 45, None, "fp32")
+    f = P.make_filter(p, "fp32", cap)
+    f.write_state(X, W, n, pphd.PHASE_RESAMPLED)
+    f.exchange(5)
+    Xg, Wg, ng = f.read_state()
+    st = P.oracle_state(K, cap, X, W, n)
+    orc.exchange(p, st, 5, 1234, 0)
+    assert np.array_equal(ng, st.n)
+    for j in range(K):
+        sl = slice(j * cap, j * cap + int(n[j]))
+        assert np.array_equal(Xg[:, sl], st.X[:, sl]) and np.array_equal(Wg[sl], st.W[sl])
+    f.close()
