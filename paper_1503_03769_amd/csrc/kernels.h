@@ -1993,6 +1993,11 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     const size_t gb = (size_t)j * m.cap + a;
     const bool live = s < n;
     const int b = live ? bkt[gb + s] : BEARING_BUCKETS;
+    // the parent's state, loaded with its bucket (the destination waits on the offsets)
+    T v[5], pw = 0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) v[d] = live && d < m.dim ? in.x[d][gb + s] : (T)0;
+    if (live) pw = in.w[gb + s];
     // lanes of this wave with the same bucket: intersect the ballots of the
     // seven bits of b (bit 6 tells the out-of-range lanes apart)
     unsigned long long peers = ~0ull;
@@ -2008,13 +2013,15 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     if (live) {
         for (int w = 0; w < wv; ++w) rank += wh[w][b];
         dst = off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] + rank;
-        for (int d = 0; d < m.dim; ++d) out.x[d][gb + dst] = in.x[d][gb + s];
-        out.w[gb + dst] = in.w[gb + s];
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+            if (d < m.dim) out.x[d][gb + dst] = v[d];
+        out.w[gb + dst] = pw;
         if (orig) orig[gb + dst] = s;
     }
     if (!tsum) return;
     // per destination tile: one wave sum and one atomic addition per distinct tile
-    const double q = live ? floor(ldexp((double)in.w[gb + s], rsS[j])) : 0.0;
+    const double q = live ? floor(ldexp((double)pw, rsS[j])) : 0.0;
     int tile = live ? (dst >> 8) : -1;
     for (;;) {
         const uint64_t act = __ballot(tile >= 0);
@@ -2190,14 +2197,21 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     const int S = rsS[j];
     // group total Q and this tile's exclusive prefix P (exact integer sums),
     // and this thread's integer weight with its in-wave inclusive prefix
+    // the parent's state and weight first (independent of the sums below)
+    const int sidx = base + tid;
+    const bool have = sidx < n;
+    const size_t gs = gb + (have ? sidx : 0);
+    T pv[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) pv[d] = d < m.dim ? in.x[d][gs] : (T)0;
+    const T pwt = in.w[gs];
     double qa = 0.0, qp = 0.0;
     for (int u = tid; u < ntl; u += 256) {
         const double v = tsum[(size_t)j * rtiles + u];
         qa += v;
         if (u < t) qp += v;
     }
-    const int sidx = base + tid;
-    const double q = (sidx < n) ? floor(ldexp((double)in.w[gb + sidx], S)) : 0.0;
+    const double q = have ? floor(ldexp((double)pwt, S)) : 0.0;
     const double qin = wave_incl_scan(q);
     qa = wave_sum(qa);
     qp = wave_sum(qp);
@@ -2206,8 +2220,10 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         s_q[1][wv] = qp;
         s_q[2][wv] = lane_value(qin, 63);
     }
-    if (sidx < n) {
-        for (int d = 0; d < m.dim; ++d) s_x[d][tid] = in.x[d][gb + sidx];
+    if (have) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+            if (d < m.dim) s_x[d][tid] = pv[d];
     }
     __syncthreads();
     const double Qd = (s_q[0][0] + s_q[0][1]) + (s_q[0][2] + s_q[0][3]);
@@ -2337,7 +2353,7 @@ __global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __r
 
 // Step 6 in one launch for runs of at most 1024 groups: stratum m moves one
 // couple per group, S_j(m) -> S_{j+1}(m), so a workgroup that holds whole
-// strata of one run (1024 / K_r strata, thread = (stratum, group)) reads its
+// strata of one run (1024 / K_r strata, thread = (group, stratum)) reads its
 // couples, waits, and writes each to the next group's slot of the same
 // stratum.  Workgroups touch different strata, so every read still sees the
 // state before the exchange.  The run's count L and each group's offset b_j
@@ -2373,9 +2389,11 @@ __global__ __launch_bounds__(1024) void k_xchg_ring(DevModel m, const Grp* __res
     mn = s_min[0];
     for (int w = 1; w < 16; ++w) mn = s_min[w] < mn ? s_min[w] : mn;
     const int L = (int)floor(m.xfrac * (double)mn);
-    const int ml = tid / Kr, jl = tid - ml * Kr;
+    // stratum fastest: neighbouring lanes take neighbouring strata of one
+    // group, whose slots lie about n/L apart
+    const int jl = tid / spb, ml = tid - jl * spb;
     const int mm = (int)blockIdx.y * spb + ml;
-    const bool live = ml < spb && mm < L;
+    const bool live = jl < Kr && mm < L;
     if (live) {
         const size_t src = (size_t)(g0.g0 + jl) * m.cap + ((uint64_t)mm * (uint64_t)s_n[jl] + s_b[jl]) / (uint64_t)L;
         for (int d = 0; d < m.dim; ++d) s_c[d][tid] = st.x[d][src];
