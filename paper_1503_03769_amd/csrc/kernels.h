@@ -1430,15 +1430,26 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
     for (int p = wv; p < M; p += 16) {
         const int pp = zpos ? zpos[zoff + p] : p;
         int H = -2147483647 - 1;
-        for (int t = lane; t < nw; t += 64) {
-            const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
-            if (ps[o] > 0.0 && ph[o] > H) H = ph[o];
-        }
-        H = wave_max(H);
         double S = 0.0;
-        for (int t = lane; t < nw; t += 64) {
-            const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
-            if (ps[o] > 0.0) S += ldexp(ps[o], ph[o] - H);
+        if (nw <= 64) {
+            // one tile per lane, read once
+            const size_t o = ((size_t)j * wtiles + (lane < nw ? lane : 0)) * Mmax + pp;
+            const double v = ps[o];
+            const int h = ph[o];
+            const double sv = lane < nw ? v : 0.0;
+            if (sv > 0.0) H = h;
+            H = wave_max(H);
+            if (sv > 0.0) S = ldexp(sv, h - H);
+        } else {
+            for (int t = lane; t < nw; t += 64) {
+                const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
+                if (ps[o] > 0.0 && ph[o] > H) H = ph[o];
+            }
+            H = wave_max(H);
+            for (int t = lane; t < nw; t += 64) {
+                const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
+                if (ps[o] > 0.0) S += ldexp(ps[o], ph[o] - H);
+            }
         }
         S = wave_sum(S);
         double C = 0.0, F = 0.0, dW = 0.0;
