@@ -25,7 +25,7 @@ SHAPES = {"fp32": [4, 8, 16], "fp64": [2, 4, 8]}
 MEAS_PER_WAVE = [8, 16, 32, 64, 128, 256]
 
 
-def tune(workload: str, first: int, last: int, verbose: bool = True):
+def tune(workload: str, first: int, last: int, verbose: bool = True, meas_per_wave=None):
     import torch
 
     from . import pphd
@@ -60,7 +60,7 @@ def tune(workload: str, first: int, last: int, verbose: bool = True):
         def update(f, k):
             f.update(zdev[k])
     results = []
-    for pt1, pt2, mz in itertools.product(SHAPES[prec_name], SHAPES[prec_name], MEAS_PER_WAVE):
+    for pt1, pt2, mz in itertools.product(SHAPES[prec_name], SHAPES[prec_name], meas_per_wave or MEAS_PER_WAVE):
         f = make()
         f.set_tuning(pt1, pt2, mz)
         f.init()
@@ -90,8 +90,11 @@ def main():
     ap.add_argument("--workload", default="large_fp32_10tgt_k64")
     ap.add_argument("--steps", type=int, nargs=2, default=[20, 40])
     ap.add_argument("--out", default=TUNING_PATH)
+    ap.add_argument("--meas-per-wave", type=int, nargs="+", default=None,
+                    help="the measurement chunks to try (the bearing-frame passes of workloads with clutter "
+                         "take all of a run's measurements per wavefront and ignore it)")
     args = ap.parse_args()
-    best, _ = tune(args.workload, args.steps[0], args.steps[1])
+    best, _ = tune(args.workload, args.steps[0], args.steps[1], meas_per_wave=args.meas_per_wave)
     data = {}
     if os.path.exists(args.out):
         with open(args.out) as fh:
