@@ -146,6 +146,15 @@ __device__ __forceinline__ double lane_value(double v, int l)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
 }
 __device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// element i of an array at a wave-uniform base, addressed by a 32-bit byte
+// offset (a base pointer in scalar registers plus one vector register per
+// load instead of a 64-bit vector address); i * sizeof(U) must stay below
+// 2^32, which holds within one group's slots (at most 65535 * 256)
+template <typename U>
+__device__ __forceinline__ U ld_slot(const U* __restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(U));
+}
 // index of this thread's wavefront in the workgroup, as a wave-uniform value
 __device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 // quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140
@@ -1230,73 +1239,72 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     const size_t zb = (size_t)j * Mmax;
     const double* zs = zp.zs + 2 * (size_t)off;
     const int nA = zp.nA[gr.run];
-    // the operands of the first 64 measurements of each frame, loaded with
-    // the particles (frame order)
+    // lane l holds the operands of measurement c0 + l of [p0, p1) (frame
+    // order: frame A below nA, frame B from nA); the first 64 are loaded with
+    // the particles
     struct ZOp {
-        double zr, zt, H;
+        double zr, zt;
+        int H;
         T F;
         int fl;
     };
-    auto zop = [&](int q) {
-        return ZOp{ zs[2 * q], zs[2 * q + 1], (double)zHs[zb + q], zFs[zb + q], zfls[zb + q] };
-    };
-    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
-    const int qa = p0 + lane < a1 ? p0 + lane : 0, qb = b0 + lane < p1 ? b0 + lane : 0;
-    const ZOp za0 = M > 0 ? zop(qa) : ZOp{ 0.0, 0.0, 0.0, (T)0, 0 };
-    const ZOp zb0 = M > 0 ? zop(qb) : ZOp{ 0.0, 0.0, 0.0, (T)0, 0 };
+    auto zop = [&](int q) { return ZOp{ zs[2 * q], zs[2 * q + 1], zHs[zb + q], zFs[zb + q], zfls[zb + q] }; };
+    const ZOp z0 = p0 < p1 ? zop(p0 + lane < p1 ? p0 + lane : p0) : ZOp{ 0.0, 0.0, 0, (T)0, 0 };
+    // the group's arrays (wave-uniform bases, slot offsets below 2^32 bytes)
+    const double *grho = geo.rho + gb, *gphi = geo.phi + gb, *gphib = geo.phib + gb;
+    const T *gw = st.w + gb, *gx0 = st.x[0] + gb, *gx1 = st.x[1] + gb, *gx2 = st.x[2] + gb, *gx3 = st.x[3] + gb;
     double rho[PT], phi[PT], phib[PT];
     T acc[PT];
-    // the tile's weighted states for the local estimates of candidate labels,
-    // read once (0 in empty slots)
-    T uw[PT], ux[4][PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
         // unconditional loads, values of lanes past the group's end dropped
         const bool ok = s < n;
-        const size_t g = gb + (ok ? s : base);
-        const double r = geo.rho[g], a = geo.phi[g], b = geo.phib[g];
-        const T wv = st.w[g];
-        T xv[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) xv[d] = st.x[d][g];
+        const uint32_t g = ok ? s : base;
+        const double r = ld_slot(grho, g), a = ld_slot(gphi, g), b = ld_slot(gphib, g);
         rho[i] = ok ? r : 0.0;
         phi[i] = ok ? a : 0.0;
         phib[i] = ok ? b : 0.0;
         acc[i] = 0;
-        uw[i] = ok ? (T)(m.wscale * (double)wv) : (T)0;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) ux[d][i] = ok ? xv[d] : (T)0;
     }
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
-    auto one = [&](int p, double zr, double zt, double H, T F, int fl, const double* ang) {
-        if (fl == 0) {
+    // a candidate label's local-estimate sums (the tile's weighted states are
+    // read here, by the tiles that keep the candidate: 0 in empty slots)
+    auto cand = [&](double zr, double zt, double H, T F, int fl, const double* ang) {
+        T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
 #pragma unroll
-            for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H)) * F;
-        } else {
-            T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
-#pragma unroll
-            for (int i = 0; i < PT; ++i) {
-                const T e = fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H));
-                acc[i] += e * F;
-                const T u = e * uw[i];
-                u0 += u * ux[0][i];
-                u1 += u * ux[1][i];
-                u2 += u * ux[2][i];
-                u3 += u * ux[3][i];
-                u4 += u;
-            }
-            const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
-                         r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
-            if (lane == 0) {
-                double* o = pzeta + (pz + (fl - 1)) * 5;
-                o[0] = r0;
-                o[1] = r1;
-                o[2] = r2;
-                o[3] = r3;
-                o[4] = r4;
-            }
+        for (int i = 0; i < PT; ++i) {
+            const int s = base + i * 64 + lane;
+            const bool ok = s < n;
+            uint32_t g = ok ? s : base;
+            // formed here, not hoisted out of the measurement loop (20 live
+            // 64-bit addresses would cost 40 registers for the whole pass)
+            __asm__ volatile("" : "+v"(g));
+            const T wv = ld_slot(gw, g), x0 = ld_slot(gx0, g), x1 = ld_slot(gx1, g), x2 = ld_slot(gx2, g),
+                    x3 = ld_slot(gx3, g);
+            const T e = fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H));
+            acc[i] += e * F;
+            const T u = ok ? e * (T)(m.wscale * (double)wv) : (T)0;
+            u0 += u * x0;
+            u1 += u * x1;
+            u2 += u * x2;
+            u3 += u * x3;
+            u4 += u;
         }
+        const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
+                     r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
+        if (lane == 0) {
+            double* o = pzeta + (pz + (fl - 1)) * 5;
+            o[0] = r0;
+            o[1] = r1;
+            o[2] = r2;
+            o[3] = r3;
+            o[4] = r4;
+        }
+    };
+    auto one = [&](double zr, double zt, double H, T F, const double* ang) {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) acc[i] += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H)) * F;
     };
     const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
     // two non-candidate measurements at once (independent exponentials; each
@@ -1310,55 +1318,51 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
             acc[i] += f * E;
         }
     };
-    // the exponent is the squared distance plus the measurement's shift H;
-    // lane l tests and holds the operands of measurement c0 + l (frame order)
-    auto frame = [&](int pa, int pb, const double* ang, bool fb, ZOp first) {
-        for (int c0 = pa; c0 < pb; c0 += 64) {
-            const int p = c0 + lane;
-            bool need = false;
-            double zr = 0.0, zt = 0.0, H = 0.0;
-            T F = 0;
-            int fl = 0;
-            if (p < pb) {
-                const ZOp o = c0 == pa ? first : zop(p);
-                zr = o.zr;
-                zt = o.zt;
-                H = o.H;
-                F = o.F;
-                fl = o.fl;
-                need = box_needed(bx, fb, (float)zr, (float)zt, (float)H, (float)exp2_cut<T>());
-                if (!need && fl != 0) {
-                    double* o = pzeta + (pz + (fl - 1)) * 5;
-                    o[0] = 0.0;
-                    o[1] = 0.0;
-                    o[2] = 0.0;
-                    o[3] = 0.0;
-                    o[4] = 0.0;
-                }
-            }
-            // in measurement order: candidates (fl != 0) one at a time, two
-            // consecutive others at once
-            const uint64_t cand = __ballot(need && fl != 0);
-            uint64_t live = __ballot(need);
-            while (live) {
-                const int l = __builtin_ctzll(live);
+    // the kept measurements of one frame in a chunk, in measurement order:
+    // candidates (fl != 0) one at a time, two consecutive others at once
+    auto run = [&](uint64_t live, uint64_t cset, const ZOp& o, const double* ang) {
+        while (live) {
+            const int l = __builtin_ctzll(live);
+            live &= live - 1;
+            if ((cset >> l) & 1ull) {
+                cand(lane_value(o.zr, l), lane_value(o.zt, l), (double)lane_value(o.H, l), lane_value(o.F, l),
+                     lane_value(o.fl, l), ang);
+            } else if (live && !((cset >> __builtin_ctzll(live)) & 1ull)) {
+                const int l2 = __builtin_ctzll(live);
                 live &= live - 1;
-                if ((cand >> l) & 1ull) {
-                    one(c0 + l, lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l),
-                        lane_value(fl, l), ang);
-                } else if (live && !((cand >> __builtin_ctzll(live)) & 1ull)) {
-                    const int l2 = __builtin_ctzll(live);
-                    live &= live - 1;
-                    two(lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l), lane_value(zr, l2),
-                        lane_value(zt, l2), lane_value(H, l2), lane_value(F, l2), ang);
-                } else {
-                    one(c0 + l, lane_value(zr, l), lane_value(zt, l), lane_value(H, l), lane_value(F, l), 0, ang);
-                }
+                two(lane_value(o.zr, l), lane_value(o.zt, l), (double)lane_value(o.H, l), lane_value(o.F, l),
+                    lane_value(o.zr, l2), lane_value(o.zt, l2), (double)lane_value(o.H, l2), lane_value(o.F, l2),
+                    ang);
+            } else {
+                one(lane_value(o.zr, l), lane_value(o.zt, l), (double)lane_value(o.H, l), lane_value(o.F, l), ang);
             }
         }
     };
-    frame(p0, a1, phi, false, za0);
-    frame(b0, p1, phib, true, zb0);
+    // the exponent is the squared distance plus the measurement's shift H;
+    // lane l tests measurement c0 + l in its own frame
+    for (int c0 = p0; c0 < p1; c0 += 64) {
+        const int p = c0 + lane;
+        bool need = false;
+        ZOp o{ 0.0, 0.0, 0, (T)0, 0 };
+        if (p < p1) {
+            o = c0 == p0 ? z0 : zop(p);
+            need = box_needed(bx, p >= nA, (float)o.zr, (float)o.zt, (float)o.H, (float)exp2_cut<T>());
+            if (!need && o.fl != 0) {
+                double* q = pzeta + (pz + (o.fl - 1)) * 5;
+                q[0] = 0.0;
+                q[1] = 0.0;
+                q[2] = 0.0;
+                q[3] = 0.0;
+                q[4] = 0.0;
+            }
+        }
+        const uint64_t cset = __ballot(need && o.fl != 0);
+        const uint64_t live = __ballot(need);
+        const int na = nA - c0 < 0 ? 0 : (nA - c0 > 64 ? 64 : nA - c0);
+        const uint64_t amask = na >= 64 ? ~0ull : ((1ull << na) - 1ull);
+        run(live & amask, cset, o, phi);
+        run(live & ~amask, cset, o, phib);
+    }
     const size_t KC = (size_t)m.K * m.cap;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -1673,9 +1677,16 @@ __device__ __forceinline__ void bucket_offsets(int j, int ntl, int rtiles, const
     const int per = (ntl + NW - 1) / NW;
     const int t0 = g * per < ntl ? g * per : ntl, t1 = t0 + per < ntl ? t0 + per : ntl;
     const int* hj = hist + (size_t)j * rtiles * BEARING_BUCKETS;
+    // tiles in runs of 8, the reads of a run issued together (clamped to the
+    // wave's last tile, values past it dropped)
     int tot = 0;
-#pragma unroll 4
-    for (int t = t0; t < t1; ++t) tot += hj[(size_t)t * BEARING_BUCKETS + b];
+    for (int t = t0; t < t1; t += 8) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = hj[(size_t)(t + u < t1 ? t + u : t1 - 1) * BEARING_BUCKETS + b];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tot += t + u < t1 ? v[u] : 0;
+    }
     seg[g][b] = tot;
     __syncthreads();
     if (g == 0) {
@@ -1688,9 +1699,17 @@ __device__ __forceinline__ void bucket_offsets(int j, int ntl, int rtiles, const
     int run = base[b];
     for (int q = 0; q < g; ++q) run += seg[q][b];
     int* oj = off + (size_t)j * rtiles * BEARING_BUCKETS;
-    for (int t = t0; t < t1; ++t) {
-        oj[(size_t)t * BEARING_BUCKETS + b] = run;
-        run += hj[(size_t)t * BEARING_BUCKETS + b];
+    for (int t = t0; t < t1; t += 8) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = hj[(size_t)(t + u < t1 ? t + u : t1 - 1) * BEARING_BUCKETS + b];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (t + u < t1) {
+                oj[(size_t)(t + u) * BEARING_BUCKETS + b] = run;
+                run += v[u];
+            }
+        }
     }
 }
 
@@ -1736,6 +1755,7 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
     double wn = 0.0;
     if (s < n) {
         T acc = 0;
+#pragma unroll 4
         for (int zc = 0; zc < zsplit; ++zc) acc += accp[(size_t)zc * KC + g];
         const double w = (double)W[g];
         const T t = (T)(m.nu * w + m.wscale * w * (double)acc);
@@ -1786,6 +1806,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     __shared__ double s_ms, s_mm;
     if (wv == 0) {
         double ms = 0.0, mm = 0.0;
+#pragma unroll 4
         for (int t = lane; t < nt; t += 64) {
             ms += pmass[(size_t)j * tiles256 + t];
             mm = vmax(mm, pmax[(size_t)j * tiles256 + t]);
@@ -1810,21 +1831,35 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     }
     __syncthreads();
     const int nw = (n + WT2 - 1) / WT2;
-    for (int c = wv; c < nsel; c += 4) {
-        double a[5] = { 0, 0, 0, 0, 0 };
-        for (int t = lane; t < nw; t += 64) {
-            const double* o = pzeta + (((size_t)j * wtiles2 + t) * Mmax + c) * 5;
+    // a wavefront takes labels c, c + 4, c + 8, c + 12 together, their reads
+    // issued before any of the sums (clamped to label c, values dropped)
+    for (int cb = wv; cb < nsel; cb += 16) {
+        double a[4][5] = {};
+        int pc[4];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) a[k] += o[k];
+        for (int r = 0; r < 4; ++r) pc[r] = cand[zb + (cb + 4 * r < nsel ? cb + 4 * r : cb)];
+        for (int t = lane; t < nw; t += 64) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = cb + 4 * r < nsel ? cb + 4 * r : cb;
+                const double* o = pzeta + (((size_t)j * wtiles2 + t) * Mmax + c) * 5;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) a[r][k] += o[k];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) a[k] = wave_sum(a[k]);
-        if (lane == 0) {
-            const int p = cand[zb + c];
-            sel[zb + p] = 1;
-            if (a[4] > 0.0) {
+        for (int r = 0; r < 4; ++r) {
+            if (cb + 4 * r >= nsel) break;
+            double e[5];
 #pragma unroll
-                for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = a[d] / a[4];
+            for (int k = 0; k < 5; ++k) e[k] = wave_sum(a[r][k]);
+            if (lane == 0) {
+                const int p = pc[r];
+                sel[zb + p] = 1;
+                if (e[4] > 0.0) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = e[d] / e[4];
+                }
             }
         }
     }
@@ -2004,11 +2039,16 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     const size_t gb = (size_t)j * m.cap + a;
     const bool live = s < n;
     const int b = live ? bkt[gb + s] : BEARING_BUCKETS;
-    // the parent's state, loaded with its bucket (the destination waits on the offsets)
-    T v[5], pw = 0;
+    // the parent's state, read with its bucket (every component: x[0] stands
+    // in for an absent turn rate; lanes past the range read slot 0), and the
+    // bucket's offset in this tile once the bucket is in
+    const size_t gs = gb + (live ? s : 0);
+    T v[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) v[d] = live && d < m.dim ? in.x[d][gb + s] : (T)0;
-    if (live) pw = in.w[gb + s];
+    for (int d = 0; d < 5; ++d) v[d] = in.x[d < m.dim ? d : 0][gs];
+    const T pw = in.w[gs];
+    const int S = tsum ? rsS[j] : 0;
+    const int ob = live ? off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] : 0;
     // lanes of this wave with the same bucket: intersect the ballots of the
     // seven bits of b (bit 6 tells the out-of-range lanes apart)
     unsigned long long peers = ~0ull;
@@ -2023,7 +2063,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     int dst = -1;
     if (live) {
         for (int w = 0; w < wv; ++w) rank += wh[w][b];
-        dst = off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] + rank;
+        dst = ob + rank;
 #pragma unroll
         for (int d = 0; d < 5; ++d)
             if (d < m.dim) out.x[d][gb + dst] = v[d];
@@ -2032,7 +2072,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     }
     if (!tsum) return;
     // per destination tile: one wave sum and one atomic addition per distinct tile
-    const double q = live ? floor(ldexp((double)pw, rsS[j])) : 0.0;
+    const double q = live ? floor(ldexp((double)pw, S)) : 0.0;
     int tile = live ? (dst >> 8) : -1;
     for (;;) {
         const uint64_t act = __ballot(tile >= 0);
@@ -2200,6 +2240,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     __shared__ double s_q[3][4];
     const int j = slot_group(m), t = slot_tile(m);
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
+    const Grp gr = gd[j];
     const int n = ncur[j];
     const int ntl = (n + 255) / 256;
     if (t > 0 && t >= ntl) return;
@@ -2212,15 +2253,27 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     const int sidx = base + tid;
     const bool have = sidx < n;
     const size_t gs = gb + (have ? sidx : 0);
+    // (every component read: x[0] stands in for the absent turn rate, so the
+    // reads go out together)
     T pv[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) pv[d] = d < m.dim ? in.x[d][gs] : (T)0;
+    for (int d = 0; d < 5; ++d) pv[d] = in.x[d < m.dim ? d : 0][gs];
     const T pwt = in.w[gs];
+    // the tile sums in runs of four per thread, reads of a run issued
+    // together (clamped, values past the group's tiles dropped)
     double qa = 0.0, qp = 0.0;
-    for (int u = tid; u < ntl; u += 256) {
-        const double v = tsum[(size_t)j * rtiles + u];
-        qa += v;
-        if (u < t) qp += v;
+    for (int u0 = tid; u0 < ntl; u0 += 1024) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = tsum[(size_t)j * rtiles + (u0 + 256 * k < ntl ? u0 + 256 * k : u0)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = u0 + 256 * k;
+            if (u < ntl) {
+                qa += v[k];
+                if (u < t) qp += v[k];
+            }
+        }
     }
     const double q = have ? floor(ldexp((double)pwt, S)) : 0.0;
     const double qin = wave_incl_scan(q);
@@ -2241,7 +2294,6 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     const double Pd = (s_q[1][0] + s_q[1][1]) + (s_q[1][2] + s_q[1][3]);
     double wpre = 0.0;
     for (int w2 = 0; w2 < wv; ++w2) wpre += s_q[2][w2];
-    const Grp gr = gd[j];
     const int Jj = gr.Jj;
     long long L = 0;
     double mq = 0.0;
