@@ -41,7 +41,9 @@ def pass_bytes(counts, Mg, esz, tile=PASS_TILE):
                    measurement the partial sum and its exponent (8 + 4 bytes),
                    per tile the weight total (8 bytes);
       second pass: per particle the geometry (3 doubles), the weight and the
-                   four CV components read and the updated sum written.
+                   four CV components read, the new weight and its bearing
+                   bucket (4 bytes) written; per 256-slot tile the bucket
+                   counts (64 x 4 bytes), weight sum and maximum (16 bytes).
     The measurement rows a tile reads are shared by every tile of the run and
     are not counted."""
     counts = np.asarray(counts, dtype=np.int64)
@@ -49,7 +51,7 @@ def pass_bytes(counts, Mg, esz, tile=PASS_TILE):
     n = int(counts.sum())
     tiles = -(-counts // tile)
     cz = n * (32 + esz) + int((tiles * (12 * Mg + 8)).sum())
-    weight = n * (24 + 6 * esz)
+    weight = n * (28 + 6 * esz) + int((-(-counts // 256)).sum()) * 272
     return cz, weight
 
 

@@ -285,22 +285,11 @@ __device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_
 // Step 1 (Eqs 5, 6): survivors through the CV model, births appended.
 // grid (ceil(cap/256), K)
 // ---------------------------------------------------------------------------
+// one slot of k_predict
 template <typename T>
-__global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
-                                                 const int* __restrict__ nsurv, int* __restrict__ ncur,
-                                                 uint32_t step_arg, const uint32_t* __restrict__ dstep,
-                                                 int* __restrict__ bkt)
+__device__ __forceinline__ void predict_slot(const DevModel& m, const Grp& gr, const SoA<T>& st, const Geo& geo,
+                                             int ns, int Jj, int j, int s, uint32_t step, int* __restrict__ bkt)
 {
-    const int j = slot_group(m);
-    const Grp gr = gd[j];
-    const uint32_t step = step_of(step_arg, dstep);
-    const int s = slot_tile(m) * 256 + threadIdx.x;
-    const int ns = nsurv[j];
-    const int Jj = gr.Jj;
-    // the host guarantees ns + J_j <= cap; the clamp keeps every store inside the group
-    const int total = ns + Jj < m.cap ? ns + Jj : m.cap;
-    if (slot_tile(m) == 0 && threadIdx.x == 0) ncur[j] = total;
-    if (s >= total) return;
     const size_t g = (size_t)j * m.cap + s;
     const uint32_t c0 = (uint32_t)(gr.jl * m.cap + s);
     double v[5], w;
@@ -353,6 +342,26 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
     // the position as drawn
     if (s < ns) store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
     else bkt[g] = bearing_bucket(m, v[0], v[2]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                 const int* __restrict__ nsurv, int* __restrict__ ncur,
+                                                 uint32_t step_arg, const uint32_t* __restrict__ dstep,
+                                                 int* __restrict__ bkt)
+{
+    const int j = slot_group(m);
+    const Grp gr = gd[j];
+    const uint32_t step = step_of(step_arg, dstep);
+    const int ns = nsurv[j];
+    const int Jj = gr.Jj;
+    // the host guarantees ns + J_j <= cap; the clamp keeps every store inside the group
+    const int total = ns + Jj < m.cap ? ns + Jj : m.cap;
+    if (slot_tile(m) == 0 && threadIdx.x == 0) ncur[j] = total;
+    // one tile per workgroup (a loop over tiles would keep the math
+    // library's constants live across it, tripling the registers)
+    const int s = slot_tile(m) * 256 + threadIdx.x;
+    if (s < total) predict_slot(m, gr, st, geo, ns, Jj, j, s, step, bkt);
 }
 
 // dim 5: the turn rate of a birth drawn from a measurement-driven or learned
@@ -1210,6 +1219,79 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
     }
 }
 
+// The second pass finalizes the tiles it covers whole (one measurement chunk,
+// wave tiles of 256k slots): the new weights, the parents' bearing buckets,
+// and per 256-slot tile the bucket histogram and the weight sum and maximum,
+// each formed exactly as k_wfinal forms them (the same sums in the same
+// order), so k_wfinal is left only the tiles split into chunks.
+template <typename T>
+struct WFin {
+    int on;        // finalize single-chunk tiles here
+    T* W;          // weights, replaced in place
+    int* bkt;      // bearing bucket of every slot
+    int* bhist;    // per 256-slot tile bucket counts
+    double* pmass; // per 256-slot tile weight sum
+    double* pmax;  // per 256-slot tile weight maximum
+    int tiles256;  // 256-slot tiles per group
+};
+template <typename T, int PT>
+__device__ __forceinline__ void finalize_tile(const DevModel& m, const WFin<T>& fin, const T* __restrict__ x0,
+                                              const T* __restrict__ x2, const T* acc, int j, int tile, int base,
+                                              int n, int lane)
+{
+    static_assert(PT % 4 == 0, "wave tiles of 256k slots");
+    __shared__ int hfin[4][BEARING_BUCKETS];
+    int* h = hfin[wave_in_block()];
+    const size_t gb = (size_t)j * m.cap;
+    T* Wj = fin.W + gb;
+    T wv[PT], xa[PT], xb[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int s = base + i * 64 + lane;
+        const uint32_t g = s < n ? s : base;
+        wv[i] = ld_slot((const T*)Wj, g);
+        xa[i] = ld_slot(x0, g);
+        xb[i] = ld_slot(x2, g);
+    }
+#pragma unroll
+    for (int k = 0; k < PT / 4; ++k) {
+        const int t256 = tile * (PT / 4) + k;
+        if (t256 * 256 >= n) break;
+        h[lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        double rs[4], rm[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int i = 4 * k + w;
+            const int s = base + i * 64 + lane;
+            double wn = 0.0;
+            if (s < n) {
+                const double wo = (double)wv[i];
+                const T t = (T)(m.nu * wo + m.wscale * wo * (double)acc[i]);
+                Wj[s] = t;
+                wn = (double)t;
+                const int b = bearing_bucket(m, (double)xa[i], (double)xb[i]);
+                fin.bkt[gb + s] = b;
+                atomicAdd(&h[b], 1);
+            }
+            rs[w] = wave_sum(wn);
+            rm[w] = wave_max(wn);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int hv = h[lane];
+        const size_t o = (size_t)j * fin.tiles256 + t256;
+        if (lane == 0) {
+            fin.pmass[o] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+            fin.pmax[o] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
+        }
+        fin.bhist[o * BEARING_BUCKETS + lane] = hv;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // second pass in frames: as k_weight<T, PT, true>, the measurement side read
 // from the prepared order, tiles culled; tile `tile` of group j, every
 // measurement of the run in one wavefront
@@ -1220,7 +1302,7 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
                                                    const Split& sp, const int* __restrict__ zHs,
                                                    const T* __restrict__ zFs, const int* __restrict__ zfls,
                                                    double* __restrict__ pzeta, T* __restrict__ accp, int j, int tile,
-                                                   int zc, int zsplit)
+                                                   int zc, int zsplit, const WFin<T>& fin)
 {
     constexpr int WT = 64 * PT;
     const Grp gr = gd[j];
@@ -1363,6 +1445,12 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         run(live & amask, cset, o, phi);
         run(live & ~amask, cset, o, phib);
     }
+    if constexpr (PT % 4 == 0) {
+        if (fin.on && zsplit == 1) {
+            finalize_tile<T, PT>(m, fin, gx0, gx2, acc, j, tile, base, n, lane);
+            return;
+        }
+    }
     const size_t KC = (size_t)m.K * m.cap;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -1378,7 +1466,8 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
                                                        const int* __restrict__ zHs, const T* __restrict__ zFs,
                                                        const int* __restrict__ zfls, double* __restrict__ pzeta,
                                                        T* __restrict__ accp, const int* __restrict__ nsurv, int K,
-                                                       const int* __restrict__ tpre, const int* __restrict__ tgrp)
+                                                       const int* __restrict__ tpre, const int* __restrict__ tgrp,
+                                                       WFin<T> fin)
 {
     // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
     const bool flat = tpre != nullptr;
@@ -1389,7 +1478,7 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
         const int j = flat ? tgrp[e] : (int)blockIdx.x;
         const TileItem it = tile_item(flat ? e - tpre[j] : e, ncur[j], nsurv[j], 64 * PT);
         weight_frames_tile<T, PT>(m, gd, st, geo, ncur, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, j,
-                                  it.tile, it.chunk, it.chunks);
+                                  it.tile, it.chunk, it.chunks, fin);
     }
 }
 
@@ -1730,23 +1819,34 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
                                                 double* __restrict__ pmass, double* __restrict__ pmax,
                                                 const T* __restrict__ X0, const T* __restrict__ X2,
                                                 int* __restrict__ bkt, int* __restrict__ bhist, int wt_births,
-                                                const int* __restrict__ nsurv)
+                                                const int* __restrict__ nsurv, int fused)
 {
     __shared__ double rs[4], rm[4];
     __shared__ int h[BEARING_BUCKETS];
     const int j = slot_group(m);
-    // chunks of the second pass: the run's zsplit, or (frame passes, wt_births
-    // = their tile) one, and BIRTH_CHUNKS in the tiles holding births
-    const int zs_run = zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
-    const int s = slot_tile(m) * 256 + threadIdx.x;
-    const int zsplit = wt_births > 0 ? (s / wt_births >= tiles_before_births(ncur[j], nsurv[j], wt_births)
-                                            ? birth_chunks(ncur[j], nsurv[j], wt_births)
-                                            : 1)
-                                     : zs_run;
-    const int n = ncur[j];
+    // the slot counts first: the capacity's empty tiles leave after one read
+    const int n = ncur[j], ns = nsurv[j];
+    int tile = slot_tile(m);
+    if (fused) {
+        // the second pass finalized every tile it took in one chunk: only a
+        // group's chunked birth tiles are left (at most 17 wave tiles, from
+        // the first tile holding births), which the grid's tiles count from
+        if (birth_chunks(n, ns, wt_births) == 1) return;
+        tile += tiles_before_births(n, ns, wt_births) * (wt_births / 256);
+    }
     const int nt = (n + 255) / 256;
     const int active = nt > 0 ? nt : 1;
-    if ((int)slot_tile(m) >= active) return;
+    if (tile >= active) return;
+    // chunks of the second pass: the run's zsplit, or (frame passes, wt_births
+    // = their tile) one, and BIRTH_CHUNKS in the tiles holding births
+    const int s = tile * 256 + threadIdx.x;
+    const int zsplit = wt_births > 0 ? (s / wt_births >= tiles_before_births(n, ns, wt_births)
+                                            ? birth_chunks(n, ns, wt_births)
+                                            : 1)
+                                     : zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
+    // tiles of one chunk were finalized by the second pass (fused: its wave
+    // tiles are whole 256-slot tiles, so zsplit is uniform here)
+    if (fused && zsplit == 1) return;
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t KC = (size_t)m.K * m.cap;
     const size_t g = (size_t)j * m.cap + s;
@@ -1774,10 +1874,10 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        pmass[(size_t)j * tiles256 + slot_tile(m)] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
-        pmax[(size_t)j * tiles256 + slot_tile(m)] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
+        pmass[(size_t)j * tiles256 + tile] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+        pmax[(size_t)j * tiles256 + tile] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
     }
-    if (threadIdx.x < BEARING_BUCKETS) bhist[((size_t)j * tiles256 + slot_tile(m)) * BEARING_BUCKETS + threadIdx.x] =
+    if (threadIdx.x < BEARING_BUCKETS) bhist[((size_t)j * tiles256 + tile) * BEARING_BUCKETS + threadIdx.x] =
         h[threadIdx.x];
 }
 
@@ -2086,43 +2186,25 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     }
 }
 
-// A group's births in bearing-bucket order in one workgroup, for groups of at
-// most 1024 * BS births: every thread holds up to BS births in registers
-// (slots nsurv + i, i = c * 1024 + thread), the bucket histogram and its
-// offsets sit in LDS, the stable rank of each birth comes chunk by chunk
-// (ballot peers within a wave, earlier waves' counts of the chunk, earlier
-// chunks' counts), and after a barrier every birth is written back in place
-// at its rank with its geometry.  grid (K), 1024 threads.
-// borig (optional): each ordered slot's drawing index; with_geo: write the
-// geometry (births whose weights are already final)
+// The ranking of k_birth_sort: births c * 1024 + thread (c < BS, first nb
+// of them live) with their states v, weights w and buckets b in registers
+// are written at slot gb + rank (stable within a bucket), with borig and the
+// geometry as asked.  All 1024 threads of the workgroup call it.
 template <typename T, int BS>
-__global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
-                                                     const int* __restrict__ ncur, int* __restrict__ borig,
-                                                     int with_geo, const int* __restrict__ bkt)
+__device__ __forceinline__ void sort_births_block(const DevModel& m, const SoA<T>& st, const Geo& geo, size_t gb,
+                                                  int nb, T (&v)[BS][5], const T (&w)[BS], const int (&b)[BS],
+                                                  int* __restrict__ borig, int with_geo)
 {
     __shared__ int s_off[BEARING_BUCKETS];
     __shared__ int s_w[16][BEARING_BUCKETS];
-    const int j = blockIdx.x;
-    const int a = nsurv[j], nb = ncur[j] - a;
-    if (nb <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const size_t gb = (size_t)j * m.cap + a;
     if (tid < BEARING_BUCKETS) s_off[tid] = 0;
     __syncthreads();
-    T v[BS][5], w[BS];
-    int b[BS], dst[BS];
+    int dst[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
-        const int i = c * 1024 + tid;
-        b[c] = BEARING_BUCKETS;
         dst[c] = -1;
-        if (i < nb) {
-#pragma unroll
-            for (int d = 0; d < 5; ++d) v[c][d] = d < m.dim ? st.x[d][gb + i] : (T)0;
-            w[c] = st.w[gb + i];
-            b[c] = bkt[gb + i];  // the bucket of the birth as drawn
-            atomicAdd(&s_off[b[c]], 1);
-        }
+        if (b[c] < BEARING_BUCKETS) atomicAdd(&s_off[b[c]], 1);
     }
     __syncthreads();
     if (wv == 0) {
@@ -2169,6 +2251,84 @@ __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo 
         if (borig) borig[g] = c * 1024 + tid;
         if (with_geo) store_geometry(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
     }
+}
+
+// A group's births in bearing-bucket order in one workgroup, for groups of at
+// most 1024 * BS births: every thread holds up to BS births in registers
+// (slots nsurv + i, i = c * 1024 + thread), the bucket histogram and its
+// offsets sit in LDS, the stable rank of each birth comes chunk by chunk
+// (ballot peers within a wave, earlier waves' counts of the chunk, earlier
+// chunks' counts), and after a barrier every birth is written back in place
+// at its rank with its geometry.  grid (K), 1024 threads.
+// borig (optional): each ordered slot's drawing index; with_geo: write the
+// geometry (births whose weights are already final)
+template <typename T, int BS>
+__global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo geo, const int* __restrict__ nsurv,
+                                                     const int* __restrict__ ncur, int* __restrict__ borig,
+                                                     int with_geo, const int* __restrict__ bkt)
+{
+    const int j = blockIdx.x;
+    const int a = nsurv[j], nb = ncur[j] - a;
+    if (nb <= 0) return;
+    const int tid = threadIdx.x;
+    const size_t gb = (size_t)j * m.cap + a;
+    T v[BS][5], w[BS];
+    int b[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const int i = c * 1024 + tid;
+        b[c] = BEARING_BUCKETS;
+        if (i < nb) {
+#pragma unroll
+            for (int d = 0; d < 5; ++d) v[c][d] = d < m.dim ? st.x[d][gb + i] : (T)0;
+            w[c] = st.w[gb + i];
+            b[c] = bkt[gb + i];  // the bucket of the birth as drawn
+        }
+    }
+    sort_births_block<T, BS>(m, st, geo, gb, nb, v, w, b, borig, with_geo);
+}
+
+// The births of the measurement-driven proposals drawn and put in bearing
+// order in one workgroup per group (groups of at most 1024 * BS births):
+// birth i is drawn exactly as k_birth_draw draws it (its counter, its bucket
+// from the drawn position, weight 0 until k_birth_weight), held in
+// registers, and written once at its rank with borig = i.  grid (K), 1024
+// threads.
+template <typename T, int BS, int PROP>
+__global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
+                                                          Geo geo, const int* __restrict__ nsurv,
+                                                          const int* __restrict__ ncur,
+                                                          const double* __restrict__ Zall,
+                                                          const double* __restrict__ taball, int Mall,
+                                                          const ZWin* __restrict__ win, uint32_t step_arg,
+                                                          const uint32_t* __restrict__ dstep, int* __restrict__ borig)
+{
+    const int j = blockIdx.x;
+    const Grp gr = gd[j];
+    const int ns = nsurv[j], nb = ncur[j] - ns;
+    if (nb <= 0) return;
+    const int tid = threadIdx.x;
+    const size_t gb = (size_t)j * m.cap + ns;
+    const uint32_t step = step_of(step_arg, dstep);
+    const BirthSrc src = birth_src(gr, win, Zall, taball, Mall);
+    T v[BS][5], w[BS];
+    int b[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const int i = c * 1024 + tid;
+        b[c] = BEARING_BUCKETS;
+        w[c] = (T)0;
+        if (c * 1024 < nb && i < nb) {
+            const uint32_t c0 = (uint32_t)(gr.jl * m.cap + ns + i);
+            double x[4];
+            draw_proposal_birth<PROP>(m, c0, step, gr.rng_run, src, x);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) v[c][d] = (T)x[d];
+            v[c][4] = m.dim == 5 ? (T)birth_turn_rate(m, c0, step, gr.rng_run) : (T)0;
+            b[c] = bearing_bucket(m, x[0], x[2]);
+        }
+    }
+    sort_births_block<T, BS>(m, st, geo, gb, nb, v, w, b, borig, 0);
 }
 
 // births back from the other set in their sorted order, with their geometry

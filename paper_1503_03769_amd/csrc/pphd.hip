@@ -546,16 +546,34 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
             }
             const dim3 gb = slot_grid(f, (Jmax + 255) / 256);
             const double* tab = dm.proposal == 2 ? f->mix_tab : nullptr;
-            if (dm.proposal == 1)
-                LAUNCH(f, cls,
-                       hipLaunchKernelGGL((k_birth_draw<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, f->nsurv,
-                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep, f->bkt));
-            else
-                LAUNCH(f, cls,
-                       hipLaunchKernelGGL((k_birth_draw<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st, f->nsurv,
-                                          f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep, f->bkt));
-            pphd_status os = order_births<T>(f, true);
-            if (os != PPHD_OK) return os;
+            // groups of up to 1024 BS births: drawn and ordered in one
+            // workgroup each; larger ones drawn, then put in bucket order
+            constexpr int BS = sizeof(T) == 4 ? 8 : 4;
+            if (Jmax <= 1024 * BS) {
+                if (dm.proposal == 1)
+                    LAUNCH(f, PPHD_K_BIRTH_ORDER,
+                           hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1>), dim3(K), dim3(1024), 0, f->stream, dm,
+                                              f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step,
+                                              a.dstep, f->borig));
+                else
+                    LAUNCH(f, PPHD_K_BIRTH_ORDER,
+                           hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2>), dim3(K), dim3(1024), 0, f->stream, dm,
+                                              f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step,
+                                              a.dstep, f->borig));
+            } else {
+                if (dm.proposal == 1)
+                    LAUNCH(f, cls,
+                           hipLaunchKernelGGL((k_birth_draw<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st,
+                                              f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep,
+                                              f->bkt));
+                else
+                    LAUNCH(f, cls,
+                           hipLaunchKernelGGL((k_birth_draw<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st,
+                                              f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep,
+                                              f->bkt));
+                pphd_status os = order_births<T>(f, true);
+                if (os != PPHD_OK) return os;
+            }
             if (dm.proposal == 1)
                 LAUNCH(f, cls,
                        hipLaunchKernelGGL((k_birth_weight<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
@@ -628,22 +646,29 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                               f->gd, f->ncur, a.M, a.win, frames ? f->zprep.pos : nullptr, zsort, Mx, f->wtiles1,
                               f->wt1, f->p1s, f->p1h, f->p1w, f->zH,
                               (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand));
+    // frame passes with wave tiles of whole 256-slot tiles finalize the
+    // tiles they cover in one chunk; k_wfinal then takes the chunked ones
+    const bool fused = frames && PT2 % 4 == 0;
     if (f->pass_mode == PASS_FRAMES) {
+        const WFin<T> fin{ fused ? 1 : 0, st.w, f->bkt, f->bhist, f->p2mass, f->p2max, f->tiles256 };
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight_frames<T, PT2>), gl2, dim3(256), 0, f->stream, dm, f->gd, st, geo,
                                   f->ncur, a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
-                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2));
+                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2, fin));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
                                   a.dz, a.M, a.win, Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta,
                                   (T*)f->accp));
     }
+    // fused: the chunked birth tiles only (fewer than 16 wave tiles of births,
+    // so at most 17 wave tiles from the first one holding births)
+    const int wf_tiles = fused ? std::min(f->tiles256, 17 * (f->wt2 / 256)) : f->tiles256;
     LAUNCH(f, PPHD_K_WFINAL,
-           hipLaunchKernelGGL((k_wfinal<T>), slot_grid(f, f->tiles256), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
+           hipLaunchKernelGGL((k_wfinal<T>), slot_grid(f, wf_tiles), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
                               (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256, f->p2mass,
                               f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist, frames ? f->wt2 : 0,
-                              f->nsurv));
+                              f->nsurv, fused ? 1 : 0));
     LAUNCH(f, PPHD_K_FINALIZE,
            hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
