@@ -294,16 +294,19 @@ __device__ __forceinline__ void predict_slot(const DevModel& m, const Grp& gr, c
     const uint32_t c0 = (uint32_t)(gr.jl * m.cap + s);
     double v[5], w;
     if (s < ns) {
+        // the state first: its reads are in flight while the noise is drawn
+        // (x[0] stands in for an absent turn rate)
+        const double x = st.x[0][g], vx = st.x[1][g], y = st.x[2][g], vy = st.x[3][g];
+        const double om = st.x[m.dim == 5 ? 4 : 0][g];
+        const double wold = (double)st.w[g];
         Block4 r = rng_block(m.key0, m.key1, c0, step, RNG_PREDICT, 0, gr.rng_run);
         double n1, n2;
         normal_pair(uniform53(r.a, r.b), uniform53(r.c, r.d), n1, n2);
         const double ax = m.sigma_a * n1, ay = m.sigma_a * n2;
         const double half_t2 = m.T * m.T / 2;
-        const double x = st.x[0][g], vx = st.x[1][g], y = st.x[2][g], vy = st.x[3][g];
         if (m.dim == 5) {
             // coordinated turn at the particle's rate: the velocity turns by
             // omega T, the position follows the arc (limits T and 0 at omega = 0)
-            const double om = st.x[4][g];
             double sn, cs;
             sincos(om * m.T, &sn, &cs);
             const double fa = om != 0.0 ? sn / om : m.T;
@@ -323,7 +326,7 @@ __device__ __forceinline__ void predict_slot(const DevModel& m, const Grp& gr, c
             v[3] = vy + m.T * ay;
             v[4] = 0.0;
         }
-        w = m.pS * (double)st.w[g];
+        w = m.pS * wold;
     } else {
         if (m.proposal != 0) return;  // drawn by k_birth_draw once Z_k is known
         draw_birth(m, c0, step, RNG_BIRTH, gr.rng_run, v);
@@ -659,7 +662,8 @@ __global__ __launch_bounds__(256) void k_birth_weight(DevModel m, const Grp* __r
     }
     const T tw = (T)w;
     st.w[g] = tw;
-    store_geometry(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)tw);
+    // the stored position is the drawn one at storage precision
+    store_geometry(m, geo, g, (double)(T)x[0], (double)(T)x[2], (double)tw);
 }
 
 // scaled squared residual q(z, x) + c
@@ -2342,8 +2346,16 @@ __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T>
     const int s = first[j] + slot_tile(m) * 256 + threadIdx.x;
     if (s >= end[j]) return;
     const size_t g = (size_t)j * m.cap + s;
-    for (int d = 0; d < m.dim; ++d) to.x[d][g] = from.x[d][g];
-    const T x = from.x[0][g], y = from.x[2][g], w = from.w[g];
+    // every component read before any is written (x[0] stands in for an
+    // absent turn rate)
+    T v[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) v[d] = from.x[d < m.dim ? d : 0][g];
+    const T w = from.w[g];
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+        if (d < m.dim) to.x[d][g] = v[d];
+    const T x = v[0], y = v[2];
     to.w[g] = w;
     if (with_geo) store_geometry(m, geo, g, (double)x, (double)y, (double)w);
 }
@@ -2550,8 +2562,14 @@ __global__ __launch_bounds__(256) void k_xchg_gather(DevModel m, const Grp* __re
     const uint32_t step = step_of(step_arg, dstep);
     const size_t src = (size_t)j * m.cap + (size_t)exchange_slot(m, gr, gr.jl, nsurv[j], L, mm, step);
     T* o = stage + ((size_t)j * Lmax + mm) * 6;
-    for (int d = 0; d < m.dim; ++d) o[d] = st.x[d][src];
-    o[5] = st.w[src];
+    T v[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) v[d] = st.x[d < m.dim ? d : 0][src];
+    const T wv = st.w[src];
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+        if (d < m.dim) o[d] = v[d];
+    o[5] = wv;
 }
 
 template <typename T>
@@ -2570,8 +2588,13 @@ __global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __r
     const int jn = gr.g0 + jln;
     const size_t dst = (size_t)jn * m.cap + (size_t)exchange_slot(m, gr, jln, nsurv[jn], L, mm, step);
     const T* o = stage + ((size_t)j * Lmax + mm) * 6;
-    for (int d = 0; d < m.dim; ++d) st.x[d][dst] = o[d];
-    st.w[dst] = o[5];
+    T v[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) v[d] = o[d];
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+        if (d < m.dim) st.x[d][dst] = v[d];
+    st.w[dst] = v[5];
 }
 
 // Step 6 in one launch for runs of at most 1024 groups: stratum m moves one
@@ -2619,8 +2642,14 @@ __global__ __launch_bounds__(1024) void k_xchg_ring(DevModel m, const Grp* __res
     const bool live = jl < Kr && mm < L;
     if (live) {
         const size_t src = (size_t)(g0.g0 + jl) * m.cap + ((uint64_t)mm * (uint64_t)s_n[jl] + s_b[jl]) / (uint64_t)L;
-        for (int d = 0; d < m.dim; ++d) s_c[d][tid] = st.x[d][src];
-        s_c[5][tid] = st.w[src];
+        // every component read at once (x[0] stands in for an absent turn rate)
+        T v[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) v[d] = st.x[d < m.dim ? d : 0][src];
+        const T wv = st.w[src];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) s_c[d][tid] = v[d];
+        s_c[5][tid] = wv;
     }
     __syncthreads();
     if (live) {
