@@ -1239,24 +1239,14 @@ struct WFin {
     int tiles256;  // 256-slot tiles per group
 };
 template <typename T, int PT>
-__device__ __forceinline__ void finalize_tile(const DevModel& m, const WFin<T>& fin, const T* __restrict__ x0,
-                                              const T* __restrict__ x2, const T* acc, int j, int tile, int base,
-                                              int n, int lane)
+__device__ __forceinline__ void finalize_tile(const DevModel& m, const WFin<T>& fin, const T* wv, const T* xa,
+                                              const T* xb, const T* acc, int j, int tile, int base, int n, int lane)
 {
     static_assert(PT % 4 == 0, "wave tiles of 256k slots");
     __shared__ int hfin[4][BEARING_BUCKETS];
     int* h = hfin[wave_in_block()];
     const size_t gb = (size_t)j * m.cap;
     T* Wj = fin.W + gb;
-    T wv[PT], xa[PT], xb[PT];
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-        const int s = base + i * 64 + lane;
-        const uint32_t g = s < n ? s : base;
-        wv[i] = ld_slot((const T*)Wj, g);
-        xa[i] = ld_slot(x0, g);
-        xb[i] = ld_slot(x2, g);
-    }
 #pragma unroll
     for (int k = 0; k < PT / 4; ++k) {
         const int t256 = tile * (PT / 4) + k;
@@ -1341,6 +1331,9 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     const T *gw = st.w + gb, *gx0 = st.x[0] + gb, *gx1 = st.x[1] + gb, *gx2 = st.x[2] + gb, *gx3 = st.x[3] + gb;
     double rho[PT], phi[PT], phib[PT];
     T acc[PT];
+    // with the geometry, the weight and the position (the finalization and
+    // the candidates' sums use them; the velocities are read by candidates)
+    T wv[PT], xa[PT], xb[PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
@@ -1348,6 +1341,9 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         const bool ok = s < n;
         const uint32_t g = ok ? s : base;
         const double r = ld_slot(grho, g), a = ld_slot(gphi, g), b = ld_slot(gphib, g);
+        wv[i] = ld_slot(gw, g);
+        xa[i] = ld_slot(gx0, g);
+        xb[i] = ld_slot(gx2, g);
         rho[i] = ok ? r : 0.0;
         phi[i] = ok ? a : 0.0;
         phib[i] = ok ? b : 0.0;
@@ -1363,17 +1359,16 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
             const int s = base + i * 64 + lane;
             const bool ok = s < n;
             uint32_t g = ok ? s : base;
-            // formed here, not hoisted out of the measurement loop (20 live
-            // 64-bit addresses would cost 40 registers for the whole pass)
+            // formed here, not hoisted out of the measurement loop (live
+            // 64-bit addresses would cost registers for the whole pass)
             __asm__ volatile("" : "+v"(g));
-            const T wv = ld_slot(gw, g), x0 = ld_slot(gx0, g), x1 = ld_slot(gx1, g), x2 = ld_slot(gx2, g),
-                    x3 = ld_slot(gx3, g);
+            const T x1 = ld_slot(gx1, g), x3 = ld_slot(gx3, g);
             const T e = fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H));
             acc[i] += e * F;
-            const T u = ok ? e * (T)(m.wscale * (double)wv) : (T)0;
-            u0 += u * x0;
+            const T u = ok ? e * (T)(m.wscale * (double)wv[i]) : (T)0;
+            u0 += u * xa[i];
             u1 += u * x1;
-            u2 += u * x2;
+            u2 += u * xb[i];
             u3 += u * x3;
             u4 += u;
         }
@@ -1451,7 +1446,7 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     }
     if constexpr (PT % 4 == 0) {
         if (fin.on && zsplit == 1) {
-            finalize_tile<T, PT>(m, fin, gx0, gx2, acc, j, tile, base, n, lane);
+            finalize_tile<T, PT>(m, fin, wv, xa, xb, acc, j, tile, base, n, lane);
             return;
         }
     }
