@@ -1038,6 +1038,10 @@ __device__ __forceinline__ int tile_items(int n, int ns, int WT)
     const int nt = (n + WT - 1) / WT, ta = tiles_before_births(n, ns, WT);
     return ta + (nt - ta) * birth_chunks(n, ns, WT);
 }
+// a group's span in the flat list: its items rounded up to a multiple of 4,
+// so that the four chunks of a birth tile (items 4q .. 4q + 3 of the group)
+// fall to the four wavefronts of one workgroup; the padding items are empty
+__device__ __forceinline__ int list_items(int n, int ns, int WT) { return (tile_items(n, ns, WT) + 3) & ~3; }
 // item e of a group, counted from its last item: the birth tiles (the
 // heaviest items) go to the first wavefronts
 __device__ __forceinline__ TileItem tile_item(int e, int n, int ns, int WT)
@@ -1056,7 +1060,7 @@ __global__ __launch_bounds__(1024) void k_items_scan(const int* __restrict__ ncu
     const int G = (K + 1023) / 1024;
     const int j0 = threadIdx.x * G < K ? threadIdx.x * G : K, j1 = j0 + G < K ? j0 + G : K;
     int c = 0;
-    for (int j = j0; j < j1; ++j) c += tile_items(ncur[j], nsurv[j], WT);
+    for (int j = j0; j < j1; ++j) c += list_items(ncur[j], nsurv[j], WT);
     const int incl = (int)wave_incl_scan((double)c);  // exact: counts stay below 2^53
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 63) s_w[wv] = incl;
@@ -1065,7 +1069,7 @@ __global__ __launch_bounds__(1024) void k_items_scan(const int* __restrict__ ncu
     for (int w = 0; w < wv; ++w) pos += s_w[w];
     for (int j = j0; j < j1; ++j) {
         pre[j] = pos;
-        pos += tile_items(ncur[j], nsurv[j], WT);
+        pos += list_items(ncur[j], nsurv[j], WT);
     }
     if (threadIdx.x == 1023) pre[K] = pos;
 }
@@ -1217,20 +1221,23 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
     const int end = flat ? tpre[K] : tile_items(ncur[blockIdx.x], nsurv[blockIdx.x], 64 * PT);
     for (int e = w0; e < end; e += stride) {
         const int j = flat ? tgrp[e] : (int)blockIdx.x;
-        const TileItem it = tile_item(flat ? e - tpre[j] : e, ncur[j], nsurv[j], 64 * PT);
+        const int le = flat ? e - tpre[j] : e;
+        if (le >= tile_items(ncur[j], nsurv[j], 64 * PT)) continue;  // a list's padding
+        const TileItem it = tile_item(le, ncur[j], nsurv[j], 64 * PT);
         cz_frames_tile<T, PT>(m, gd, geo, W, ncur, Mall, win, zp, Mmax, sp, ps, ph, pw, j, it.tile, it.chunk,
                               it.chunks);
     }
 }
 
-// The second pass finalizes the tiles it covers whole (one measurement chunk,
-// wave tiles of 256k slots): the new weights, the parents' bearing buckets,
-// and per 256-slot tile the bucket histogram and the weight sum and maximum,
-// each formed exactly as k_wfinal forms them (the same sums in the same
-// order), so k_wfinal is left only the tiles split into chunks.
+// The second pass finalizes its tiles (wave tiles of 256k slots): the new
+// weights, the parents' bearing buckets, and per 256-slot tile the bucket
+// histogram and the weight sum and maximum, each formed exactly as k_wfinal
+// forms them (the same sums in the same order).  A birth tile split into
+// chunks is finalized by its chunk-0 wavefront once the workgroup's four
+// chunk sums are in LDS, so k_wfinal is not needed.
 template <typename T>
 struct WFin {
-    int on;        // finalize single-chunk tiles here
+    int on;        // finalize the tiles here
     T* W;          // weights, replaced in place
     int* bkt;      // bearing bucket of every slot
     int* bhist;    // per 256-slot tile bucket counts
@@ -1296,7 +1303,7 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
                                                    const Split& sp, const int* __restrict__ zHs,
                                                    const T* __restrict__ zFs, const int* __restrict__ zfls,
                                                    double* __restrict__ pzeta, T* __restrict__ accp, int j, int tile,
-                                                   int zc, int zsplit, const WFin<T>& fin)
+                                                   int zc, int zsplit, const WFin<T>& fin, int& quads)
 {
     constexpr int WT = 64 * PT;
     const Grp gr = gd[j];
@@ -1445,8 +1452,35 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         run(live & ~amask, cset, o, phib);
     }
     if constexpr (PT % 4 == 0) {
-        if (fin.on && zsplit == 1) {
-            finalize_tile<T, PT>(m, fin, wv, xa, xb, acc, j, tile, base, n, lane);
+        if (fin.on) {
+            if (zsplit == 1) {
+                finalize_tile<T, PT>(m, fin, wv, xa, xb, acc, j, tile, base, n, lane);
+                return;
+            }
+            // a birth tile in BIRTH_CHUNKS items: its chunks are the four
+            // wavefronts of this workgroup (items 4q .. 4q + 3 of the group),
+            // all here together; the chunk-0 wavefront adds the partials in
+            // chunk order (as k_wfinal adds them) and finalizes the tile.
+            // Consecutive chunked tiles of the workgroup alternate buffers:
+            // a buffer is written again only after the next tile's barrier,
+            // which its reader reaches once done, so the other wavefronts go
+            // on at once
+            __shared__ T s_acc[2][BIRTH_CHUNKS][PT][64];
+            const int buf = quads & 1;
+            ++quads;
+#pragma unroll
+            for (int i = 0; i < PT; ++i) s_acc[buf][zc][i][lane] = acc[i];
+            __syncthreads();
+            if (zc == 0) {
+                T tot[PT];
+#pragma unroll
+                for (int i = 0; i < PT; ++i) {
+                    T a = 0;
+                    for (int c = 0; c < BIRTH_CHUNKS; ++c) a += s_acc[buf][c][i][lane];
+                    tot[i] = a;
+                }
+                finalize_tile<T, PT>(m, fin, wv, xa, xb, tot, j, tile, base, n, lane);
+            }
             return;
         }
     }
@@ -1473,11 +1507,14 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
     const int w0 = (flat ? blockIdx.x : blockIdx.y) * 4 + wave_in_block();
     const int stride = (flat ? gridDim.x : gridDim.y) * 4;
     const int end = flat ? tpre[K] : tile_items(ncur[blockIdx.x], nsurv[blockIdx.x], 64 * PT);
+    int quads = 0;  // chunked tiles finalized so far (the same count in all four wavefronts)
     for (int e = w0; e < end; e += stride) {
         const int j = flat ? tgrp[e] : (int)blockIdx.x;
-        const TileItem it = tile_item(flat ? e - tpre[j] : e, ncur[j], nsurv[j], 64 * PT);
+        const int le = flat ? e - tpre[j] : e;
+        if (le >= tile_items(ncur[j], nsurv[j], 64 * PT)) continue;  // a list's padding
+        const TileItem it = tile_item(le, ncur[j], nsurv[j], 64 * PT);
         weight_frames_tile<T, PT>(m, gd, st, geo, ncur, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, j,
-                                  it.tile, it.chunk, it.chunks, fin);
+                                  it.tile, it.chunk, it.chunks, fin, quads);
     }
 }
 
@@ -1818,21 +1855,14 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
                                                 double* __restrict__ pmass, double* __restrict__ pmax,
                                                 const T* __restrict__ X0, const T* __restrict__ X2,
                                                 int* __restrict__ bkt, int* __restrict__ bhist, int wt_births,
-                                                const int* __restrict__ nsurv, int fused)
+                                                const int* __restrict__ nsurv)
 {
     __shared__ double rs[4], rm[4];
     __shared__ int h[BEARING_BUCKETS];
     const int j = slot_group(m);
     // the slot counts first: the capacity's empty tiles leave after one read
     const int n = ncur[j], ns = nsurv[j];
-    int tile = slot_tile(m);
-    if (fused) {
-        // the second pass finalized every tile it took in one chunk: only a
-        // group's chunked birth tiles are left (at most 17 wave tiles, from
-        // the first tile holding births), which the grid's tiles count from
-        if (birth_chunks(n, ns, wt_births) == 1) return;
-        tile += tiles_before_births(n, ns, wt_births) * (wt_births / 256);
-    }
+    const int tile = slot_tile(m);
     const int nt = (n + 255) / 256;
     const int active = nt > 0 ? nt : 1;
     if (tile >= active) return;
@@ -1843,9 +1873,6 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
                                             ? birth_chunks(n, ns, wt_births)
                                             : 1)
                                      : zsplit_for(zview(gd[j], win, nullptr, Mall).M, mz);
-    // tiles of one chunk were finalized by the second pass (fused: its wave
-    // tiles are whole 256-slot tiles, so zsplit is uniform here)
-    if (fused && zsplit == 1) return;
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t KC = (size_t)m.K * m.cap;
     const size_t g = (size_t)j * m.cap + s;

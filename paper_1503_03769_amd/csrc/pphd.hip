@@ -241,9 +241,10 @@ size_t carve(pphd_filter* f, char* base)
     f->bkt = L.take<int>(base, KC * 4);
     f->borig = L.take<int>(base, KC * 4);
     f->ipre1 = L.take<int>(base, (K + 1) * 4);
-    f->igrp1 = L.take<int>(base, K * f->wtiles_max * BIRTH_CHUNKS * 4);  // at most BIRTH_CHUNKS items per tile
+    // at most BIRTH_CHUNKS items per tile, each group's span padded to 4
+    f->igrp1 = L.take<int>(base, K * (f->wtiles_max * BIRTH_CHUNKS + 3) * 4);
     f->ipre2 = L.take<int>(base, (K + 1) * 4);
-    f->igrp2 = L.take<int>(base, K * f->wtiles_max * BIRTH_CHUNKS * 4);
+    f->igrp2 = L.take<int>(base, K * (f->wtiles_max * BIRTH_CHUNKS + 3) * 4);
     f->bhist = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->boff = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->stage = L.take<char>(base, K * (size_t)f->Lmax * 6 * es);
@@ -647,7 +648,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                               f->wt1, f->p1s, f->p1h, f->p1w, f->zH,
                               (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand));
     // frame passes with wave tiles of whole 256-slot tiles finalize the
-    // tiles they cover in one chunk; k_wfinal then takes the chunked ones
+    // weights themselves (k_wfinal only for the other passes)
     const bool fused = frames && PT2 % 4 == 0;
     if (f->pass_mode == PASS_FRAMES) {
         const WFin<T> fin{ fused ? 1 : 0, st.w, f->bkt, f->bhist, f->p2mass, f->p2max, f->tiles256 };
@@ -661,14 +662,12 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                                   a.dz, a.M, a.win, Mx, s2, f->zH, (const T*)f->zF, f->zflag, f->p2zeta,
                                   (T*)f->accp));
     }
-    // fused: the chunked birth tiles only (fewer than 16 wave tiles of births,
-    // so at most 17 wave tiles from the first one holding births)
-    const int wf_tiles = fused ? std::min(f->tiles256, 17 * (f->wt2 / 256)) : f->tiles256;
-    LAUNCH(f, PPHD_K_WFINAL,
-           hipLaunchKernelGGL((k_wfinal<T>), slot_grid(f, wf_tiles), dim3(256), 0, f->stream, dm, f->gd, st.w, f->ncur,
-                              (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256, f->p2mass,
-                              f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist, frames ? f->wt2 : 0,
-                              f->nsurv, fused ? 1 : 0));
+    if (!fused)
+        LAUNCH(f, PPHD_K_WFINAL,
+               hipLaunchKernelGGL((k_wfinal<T>), slot_grid(f, f->tiles256), dim3(256), 0, f->stream, dm, f->gd, st.w,
+                                  f->ncur, (const T*)f->accp, a.M, a.win, frames ? (1 << 30) : f->mz, f->tiles256,
+                                  f->p2mass, f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist,
+                                  frames ? f->wt2 : 0, f->nsurv));
     LAUNCH(f, PPHD_K_FINALIZE,
            hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
