@@ -2414,12 +2414,15 @@ __device__ __forceinline__ double children_count(double mq, double Rj)
 
 // ---------------------------------------------------------------------------
 // Step 5, pass B: exact prefix of q, child counts and parent-order expansion
-// into the other particle set.  Thread t of a tile owns parent base + t; its
-// children occupy slots [N(c_{t-1}), N(c_t)).  The workgroup's children form
-// one contiguous slot range written with coalesced stores (each child finds
-// its parent by binary search over the tile's child offsets in LDS).
-// grid (rtiles, K), 256 threads.
+// into the other particle set.  A workgroup owns RS_TILE = 512 consecutive
+// parents (two of the 256-slot tiles whose sums k_bk_scatter formed), thread
+// t parents base + t and base + 256 + t; parent i's children occupy slots
+// [N(c_{i-1}), N(c_i)).  The workgroup's children form one contiguous slot
+// range written with coalesced stores (each child finds its parent by binary
+// search over the workgroup's child offsets in LDS).
+// grid (ceil(rtiles/2), K) (or transposed), 256 threads.
 // ---------------------------------------------------------------------------
+constexpr int RS_TILE = 512;
 template <typename T>
 __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __restrict__ gd, SoA<T> in, SoA<T> out,
                                                    const int* __restrict__ ncur, int* __restrict__ nsurv,
@@ -2428,66 +2431,82 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
                                                    double* __restrict__ massq, int* __restrict__ clampctr,
                                                    int* __restrict__ counts, int record)
 {
-    __shared__ long long s_end[256];
+    __shared__ long long s_end[RS_TILE];
     __shared__ long long s_first;
-    __shared__ T s_x[5][256];
-    __shared__ double s_q[3][4];
+    __shared__ T s_x[5][RS_TILE];
+    __shared__ double s_q[4][4];
     const int j = slot_group(m), t = slot_tile(m);
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const Grp gr = gd[j];
     const int n = ncur[j];
-    const int ntl = (n + 255) / 256;
+    const int ntl = (n + RS_TILE - 1) / RS_TILE;
     if (t > 0 && t >= ntl) return;
     const size_t gb = (size_t)j * m.cap;
-    const int base = t * 256;
+    const int base = t * RS_TILE;
     const int S = rsS[j];
-    // group total Q and this tile's exclusive prefix P (exact integer sums),
-    // and this thread's integer weight with its in-wave inclusive prefix
-    // the parent's state and weight first (independent of the sums below)
-    const int sidx = base + tid;
-    const bool have = sidx < n;
-    const size_t gs = gb + (have ? sidx : 0);
-    // (every component read: x[0] stands in for the absent turn rate, so the
-    // reads go out together)
-    T pv[5];
+    // the parents' states and weights first (independent of the sums below;
+    // every component read: x[0] stands in for an absent turn rate)
+    bool have[2];
+    T pv[2][5], pwt[2];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) pv[d] = in.x[d < m.dim ? d : 0][gs];
-    const T pwt = in.w[gs];
-    // the tile sums in runs of four per thread, reads of a run issued
-    // together (clamped, values past the group's tiles dropped)
+    for (int h = 0; h < 2; ++h) {
+        const int sidx = base + h * 256 + tid;
+        have[h] = sidx < n;
+        const size_t gs = gb + (have[h] ? sidx : 0);
+#pragma unroll
+        for (int d = 0; d < 5; ++d) pv[h][d] = in.x[d < m.dim ? d : 0][gs];
+        pwt[h] = in.w[gs];
+    }
+    // group total Q and this workgroup's exclusive prefix P over the 256-slot
+    // tile sums (exact integer sums), in runs of four per thread
+    const int ntl256 = (n + 255) / 256, t256 = t * (RS_TILE / 256);
     double qa = 0.0, qp = 0.0;
-    for (int u0 = tid; u0 < ntl; u0 += 1024) {
+    for (int u0 = tid; u0 < ntl256; u0 += 1024) {
         double v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = tsum[(size_t)j * rtiles + (u0 + 256 * k < ntl ? u0 + 256 * k : u0)];
+        for (int k = 0; k < 4; ++k) v[k] = tsum[(size_t)j * rtiles + (u0 + 256 * k < ntl256 ? u0 + 256 * k : u0)];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int u = u0 + 256 * k;
-            if (u < ntl) {
+            if (u < ntl256) {
                 qa += v[k];
-                if (u < t) qp += v[k];
+                if (u < t256) qp += v[k];
             }
         }
     }
-    const double q = have ? floor(ldexp((double)pwt, S)) : 0.0;
-    const double qin = wave_incl_scan(q);
+    // each parent's integer weight and its in-wave inclusive prefix, per half
+    double q[2], qin[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        q[h] = have[h] ? floor(ldexp((double)pwt[h], S)) : 0.0;
+        qin[h] = wave_incl_scan(q[h]);
+    }
     qa = wave_sum(qa);
     qp = wave_sum(qp);
     if (lane == 0) {
         s_q[0][wv] = qa;
         s_q[1][wv] = qp;
-        s_q[2][wv] = lane_value(qin, 63);
+        s_q[2][wv] = lane_value(qin[0], 63);
+        s_q[3][wv] = lane_value(qin[1], 63);
     }
-    if (have) {
 #pragma unroll
-        for (int d = 0; d < 5; ++d)
-            if (d < m.dim) s_x[d][tid] = pv[d];
+    for (int h = 0; h < 2; ++h) {
+        if (have[h]) {
+#pragma unroll
+            for (int d = 0; d < 5; ++d)
+                if (d < m.dim) s_x[d][h * 256 + tid] = pv[h][d];
+        }
     }
     __syncthreads();
     const double Qd = (s_q[0][0] + s_q[0][1]) + (s_q[0][2] + s_q[0][3]);
     const double Pd = (s_q[1][0] + s_q[1][1]) + (s_q[1][2] + s_q[1][3]);
-    double wpre = 0.0;
-    for (int w2 = 0; w2 < wv; ++w2) wpre += s_q[2][w2];
+    // before this thread's wave in each half, and the whole first half
+    double wpre0 = 0.0, wpre1 = 0.0;
+    for (int w2 = 0; w2 < wv; ++w2) {
+        wpre0 += s_q[2][w2];
+        wpre1 += s_q[3][w2];
+    }
+    const double half0 = (s_q[2][0] + s_q[2][1]) + (s_q[2][2] + s_q[2][3]);
     const int Jj = gr.Jj;
     long long L = 0;
     double mq = 0.0;
@@ -2509,24 +2528,36 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         massq[j] = mq;
     }
     if (L == 0 || base >= n) {
-        if (record && sidx < n) counts[gb + sidx] = 0;
+        if (record) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (have[h]) counts[gb + base + h * 256 + tid] = 0;
+        }
         return;
     }
     const double wc = mq / (double)L;
     const uint32_t r = rng_block(m.key0, m.key1, (uint32_t)gr.jl, step_of(step_arg, dstep), RNG_RESAMPLE, 0,
                                  gr.rng_run).a;
     const uint64_t Q = (uint64_t)Qd;
-    const double c_incl = Pd + wpre + qin;            // c_t = q_0 + ... + q_t of the group
-    const long long nend = points_below((uint64_t)c_incl, Q, L, r);
-    s_end[tid] = nend;
+    // c_i = q_0 + ... + q_i of the group (exact: integers below 2^53)
+    const double c0i = Pd + wpre0 + qin[0];
+    const double c1i = Pd + half0 + wpre1 + qin[1];
+    const long long nend0 = points_below((uint64_t)c0i, Q, L, r);
+    const long long nend1 = points_below((uint64_t)c1i, Q, L, r);
+    s_end[tid] = nend0;
+    s_end[256 + tid] = nend1;
     if (tid == 0) s_first = points_below((uint64_t)Pd, Q, L, r);
     __syncthreads();
-    const long long nbeg = tid == 0 ? s_first : s_end[tid - 1];
-    if (record && sidx < n) counts[gb + sidx] = (int)(nend - nbeg);
-    const long long c0 = s_first, c1 = s_end[255];
-    for (long long c = c0 + tid; c < c1; c += 256) {
+    if (record) {
+        const long long b0 = tid == 0 ? s_first : s_end[tid - 1];
+        const long long b1 = s_end[255 + tid];
+        if (have[0]) counts[gb + base + tid] = (int)(nend0 - b0);
+        if (have[1]) counts[gb + base + 256 + tid] = (int)(nend1 - b1);
+    }
+    const long long cb = s_first, ce = s_end[RS_TILE - 1];
+    for (long long c = cb + tid; c < ce; c += 256) {
         // last parent li with start(li) <= c, start(0) = s_first, start(li) = s_end[li-1]
-        int lo = 0, hi = 255;
+        int lo = 0, hi = RS_TILE - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_end[mid - 1] <= c) lo = mid; else hi = mid - 1;

@@ -773,7 +773,8 @@ pphd_status order_births(pphd_filter* f, bool weights_later)
 template <typename T>
 pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
-    dim3 g = slot_grid(f, f->rtiles);
+    // k_rs_expand: RS_TILE parents (two 256-slot tiles) per workgroup
+    dim3 g = slot_grid(f, (f->rtiles * 256 + RS_TILE - 1) / RS_TILE);
     // parents into bearing-bucket order (into the other set), then the
     // systematic resampling back into this one
     {
