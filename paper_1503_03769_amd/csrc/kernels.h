@@ -2154,61 +2154,84 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
                                                     const int* __restrict__ rsS, double* __restrict__ tsum,
                                                     int* __restrict__ orig)
 {
-    __shared__ int wh[4][BEARING_BUCKETS];  // per-wave bucket counts
-    const int j = slot_group(m), t = slot_tile(m);
+    // a workgroup takes the 256-slot tiles 2 t2 and 2 t2 + 1 of the range
+    // (half h: tile 2 t2 + h, one slot per thread), each ranked exactly as a
+    // workgroup of its own would rank it; the reads of both go out first
+    __shared__ int wh[2][4][BEARING_BUCKETS];  // per half, per-wave bucket counts
+    const int j = slot_group(m), t2 = slot_tile(m);
     const int a = range_first(first, j), n = end[j] - a;
-    if (t * 256 >= n) return;
+    if (t2 * 512 >= n) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 4 * BEARING_BUCKETS; i += 256) (&wh[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 2 * 4 * BEARING_BUCKETS; i += 256) (&wh[0][0][0])[i] = 0;
     __syncthreads();
-    const int s = t * 256 + threadIdx.x;
     const size_t gb = (size_t)j * m.cap + a;
-    const bool live = s < n;
-    const int b = live ? bkt[gb + s] : BEARING_BUCKETS;
-    // the parent's state, read with its bucket (every component: x[0] stands
-    // in for an absent turn rate; lanes past the range read slot 0), and the
-    // bucket's offset in this tile once the bucket is in
-    const size_t gs = gb + (live ? s : 0);
-    T v[5];
+    // the parents' buckets and states (every component: x[0] stands in for
+    // an absent turn rate; lanes past the range read slot 0), then each
+    // bucket's offset in its tile once the bucket is in
+    int s[2], b[2], ob[2];
+    bool live[2];
+    T v[2][5], pw[2];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) v[d] = in.x[d < m.dim ? d : 0][gs];
-    const T pw = in.w[gs];
+    for (int h = 0; h < 2; ++h) {
+        s[h] = (2 * t2 + h) * 256 + threadIdx.x;
+        live[h] = s[h] < n;
+        b[h] = live[h] ? bkt[gb + s[h]] : BEARING_BUCKETS;
+        const size_t gs = gb + (live[h] ? s[h] : 0);
+#pragma unroll
+        for (int d = 0; d < 5; ++d) v[h][d] = in.x[d < m.dim ? d : 0][gs];
+        pw[h] = in.w[gs];
+    }
     const int S = tsum ? rsS[j] : 0;
-    const int ob = live ? off[((size_t)j * rtiles + t) * BEARING_BUCKETS + b] : 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        ob[h] = live[h] ? off[((size_t)j * rtiles + 2 * t2 + h) * BEARING_BUCKETS + b[h]] : 0;
     // lanes of this wave with the same bucket: intersect the ballots of the
     // seven bits of b (bit 6 tells the out-of-range lanes apart)
-    unsigned long long peers = ~0ull;
-    for (int bit = 0; bit < 7; ++bit) {
-        const unsigned long long v = __ballot((b >> bit) & 1);
-        peers &= ((b >> bit) & 1) ? v : ~v;
-    }
     const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int rank = __popcll(peers & below);
-    if (live && rank == 0) wh[wv][b] = __popcll(peers);
-    __syncthreads();
-    int dst = -1;
-    if (live) {
-        for (int w = 0; w < wv; ++w) rank += wh[w][b];
-        dst = ob + rank;
+    int rank[2];
 #pragma unroll
-        for (int d = 0; d < 5; ++d)
-            if (d < m.dim) out.x[d][gb + dst] = v[d];
-        out.w[gb + dst] = pw;
-        if (orig) orig[gb + dst] = s;
+    for (int h = 0; h < 2; ++h) {
+        unsigned long long peers = ~0ull;
+        for (int bit = 0; bit < 7; ++bit) {
+            const unsigned long long q = __ballot((b[h] >> bit) & 1);
+            peers &= ((b[h] >> bit) & 1) ? q : ~q;
+        }
+        rank[h] = __popcll(peers & below);
+        if (live[h] && rank[h] == 0) wh[h][wv][b[h]] = __popcll(peers);
+    }
+    __syncthreads();
+    int dst[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        dst[h] = -1;
+        if (live[h]) {
+            int r = rank[h];
+            for (int w = 0; w < wv; ++w) r += wh[h][w][b[h]];
+            dst[h] = ob[h] + r;
+#pragma unroll
+            for (int d = 0; d < 5; ++d)
+                if (d < m.dim) out.x[d][gb + dst[h]] = v[h][d];
+            out.w[gb + dst[h]] = pw[h];
+            if (orig) orig[gb + dst[h]] = s[h];
+        }
     }
     if (!tsum) return;
-    // per destination tile: one wave sum and one atomic addition per distinct tile
-    const double q = live ? floor(ldexp((double)pw, S)) : 0.0;
-    int tile = live ? (dst >> 8) : -1;
-    for (;;) {
-        const uint64_t act = __ballot(tile >= 0);
-        if (!act) break;
-        const int lead = __builtin_ctzll(act);
-        const int tl = __builtin_amdgcn_readlane(tile, lead);
-        const bool mine = tile == tl;
-        const double sq = wave_sum(mine ? q : 0.0);
-        if (lane == lead) atomicAdd(&tsum[(size_t)j * rtiles + tl], sq);
-        if (mine) tile = -1;
+    // per destination tile: one wave sum and one atomic addition per distinct
+    // tile (integer-valued sums below 2^53: exact in any order)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const double q = live[h] ? floor(ldexp((double)pw[h], S)) : 0.0;
+        int tile = live[h] ? (dst[h] >> 8) : -1;
+        for (;;) {
+            const uint64_t act = __ballot(tile >= 0);
+            if (!act) break;
+            const int lead = __builtin_ctzll(act);
+            const int tl = __builtin_amdgcn_readlane(tile, lead);
+            const bool mine = tile == tl;
+            const double sq = wave_sum(mine ? q : 0.0);
+            if (lane == lead) atomicAdd(&tsum[(size_t)j * rtiles + tl], sq);
+            if (mine) tile = -1;
+        }
     }
 }
 

@@ -736,7 +736,8 @@ pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, i
                                   f->bhist, f->boff, parents ? f->tsum : nullptr));
     }
     LAUNCH(f, cls,
-           hipLaunchKernelGGL((k_bk_scatter<T>), g, dim3(256), 0, f->stream, f->dm, cur, oth, first, f->ncur,
+           hipLaunchKernelGGL((k_bk_scatter<T>), slot_grid(f, (tiles + 1) / 2), dim3(256), 0, f->stream, f->dm, cur,
+                              oth, first, f->ncur,
                               f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr, orig));
     if (parents) f->order_ready = false;
     return PPHD_OK;
