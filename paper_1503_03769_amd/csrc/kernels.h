@@ -2009,7 +2009,7 @@ struct EstimateRec {
     int32_t votes;
 };
 
-__global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ gd, const int* __restrict__ run_g0, int Mall,
+__global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int Mall,
                                                const ZWin* __restrict__ win, int Mmax,
                                                const int* __restrict__ sel_all, const double* __restrict__ zeta_all,
                                                EstimateRec* __restrict__ out_all, int cap, int* __restrict__ nout_all)
@@ -2018,7 +2018,7 @@ __global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ gd, const
     __shared__ int s_keep[1024];
     __shared__ int s_wtot[16];
     const int run = blockIdx.x;
-    const Grp gr = gd[run_g0[run]];
+    const Grp gr = rgd[run];  // the run's first group
     const int K = gr.K;
     const int M = zview(gr, win, nullptr, Mall).M;
     const int* sel = sel_all + (size_t)gr.g0 * Mmax;
@@ -2681,8 +2681,7 @@ __global__ __launch_bounds__(256) void k_xchg_scatter(DevModel m, const Grp* __r
 // state before the exchange.  The run's count L and each group's offset b_j
 // are formed once per workgroup.  grid (runs, ceil(Lmax / (1024 / K_r))).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_xchg_ring(DevModel m, const Grp* __restrict__ gd,
-                                                   const int* __restrict__ run_g0, SoA<T> st,
+__global__ __launch_bounds__(1024) void k_xchg_ring(DevModel m, const Grp* __restrict__ rgd, SoA<T> st,
                                                    const int* __restrict__ nsurv, int Lmax, uint32_t step_arg,
                                                    const uint32_t* __restrict__ dstep)
 {
@@ -2690,7 +2689,7 @@ __global__ __launch_bounds__(1024) void k_xchg_ring(DevModel m, const Grp* __res
     __shared__ uint64_t s_b[1024];
     __shared__ int s_n[1024];
     __shared__ int s_min[16];
-    const Grp g0 = gd[run_g0[blockIdx.x]];
+    const Grp g0 = rgd[blockIdx.x];  // the run's first group
     const int Kr = g0.K;
     if (Kr < 2 || Kr > 1024) return;
     const int spb = 1024 / Kr;

@@ -84,6 +84,7 @@ struct pphd_filter {
     std::vector<int> hrun_g0;
     Grp* gd = nullptr;            // device group table [K]
     int* run_g0 = nullptr;        // first group of each run [nruns]
+    Grp* rgd = nullptr;           // the record of each run's first group [nruns]
     ZWin* win = nullptr;          // measurement windows of the batched update [nruns]
     int32_t* uwin = nullptr;      // windows as given by the caller [nruns][2]
     uint32_t* dstep = nullptr;    // step counter of captured graphs
@@ -200,6 +201,7 @@ size_t carve(pphd_filter* f, char* base)
     f->zbuf = L.take<double>(base, (size_t)f->z_cap * 2 * 8);
     f->gd = L.take<Grp>(base, K * sizeof(Grp));
     f->run_g0 = L.take<int>(base, (size_t)f->nruns * 4);
+    f->rgd = L.take<Grp>(base, (size_t)f->nruns * sizeof(Grp));
     f->win = L.take<ZWin>(base, (size_t)f->nruns * sizeof(ZWin));
     f->uwin = L.take<int32_t>(base, (size_t)f->nruns * 8);
     f->dstep = L.take<uint32_t>(base, 4);
@@ -811,7 +813,7 @@ pphd_status run_exchange(pphd_filter* f, uint32_t step, const uint32_t* dstep)
         if (gy <= 65535) {
             LAUNCH(f, PPHD_K_XCHG_SCATTER,
                    hipLaunchKernelGGL((k_xchg_ring<T>), dim3(f->nruns, (unsigned)gy), dim3(1024), 0, f->stream, f->dm,
-                                      f->gd, f->run_g0, st, f->nsurv, f->Lmax, step, dstep));
+                                      f->rgd, st, f->nsurv, f->Lmax, step, dstep));
             return PPHD_OK;
         }
     }
@@ -840,7 +842,7 @@ pphd_status check_handle(pphd_filter* f)
 pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout, int M, const ZWin* win)
 {
     LAUNCH(f, PPHD_K_FUSE,
-           hipLaunchKernelGGL(k_fuse, dim3(f->nruns), dim3(1024), 0, f->stream, f->gd, f->run_g0, M, win, f->max_meas,
+           hipLaunchKernelGGL(k_fuse, dim3(f->nruns), dim3(1024), 0, f->stream, f->rgd, M, win, f->max_meas,
                               f->sel, f->zeta, out, cap, nout));
     return PPHD_OK;
 }
@@ -909,6 +911,10 @@ pphd_status create_impl(const pphd_model* model, const pphd_run_desc* runs, int 
         e = hipMemcpyAsync(f->gd, f->hgd.data(), f->hgd.size() * sizeof(Grp), hipMemcpyHostToDevice, f->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(f->run_g0, f->hrun_g0.data(), f->hrun_g0.size() * 4, hipMemcpyHostToDevice, f->stream);
+    std::vector<Grp> hrgd;
+    for (int g0 : f->hrun_g0) hrgd.push_back(f->hgd[g0]);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f->rgd, hrgd.data(), hrgd.size() * sizeof(Grp), hipMemcpyHostToDevice, f->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) {
         (void)hipHostFree(f->pin_z);
