@@ -246,7 +246,19 @@ pphd_status pphd_read_resample(pphd_filter* f, int32_t* counts, double* mass_q, 
 
 /* ---- timing ------------------------------------------------------------- */
 
-/* Kernel classes timed by the library. */
+/* Kernel classes timed by the library; a class may span several kernels:
+ *   PREDICT k_predict; CZ k_cz_frames or k_cz; CZ_COMBINE k_cz_combine;
+ *   WEIGHT k_weight_frames (which also finalizes the weights) or k_weight;
+ *   WFINAL k_wfinal (passes other than the bearing-frame ones); FINALIZE
+ *   k_finalize; FUSE k_fuse; RS_ORDER the parents' bucket order
+ *   (k_bk_scatter, with k_bk_hist and k_bk_scan when the update did not
+ *   prepare it); RS_EXPAND k_rs_expand; XCHG_SCATTER k_xchg_ring or
+ *   k_xchg_scatter; XCHG_GATHER k_xchg_gather; BIRTH k_birth_draw and
+ *   k_birth_weight (proposal 1); BIRTH_MIX the same for proposal 2;
+ *   BIRTH_ORDER k_birth_draw_sort, k_birth_sort, or the births' bucket
+ *   order; MLP_INFER the mixture table; ZPREP k_zprep and the work lists;
+ *   INIT, WMAX, GEOM their kernels.  RS_TILES times nothing (kept for the
+ *   numbering). */
 enum {
     PPHD_K_PREDICT = 0, PPHD_K_CZ = 1, PPHD_K_CZ_COMBINE = 2, PPHD_K_WEIGHT = 3,
     PPHD_K_FINALIZE = 4, PPHD_K_FUSE = 5, PPHD_K_RS_TILES = 6, PPHD_K_RS_EXPAND = 7,
