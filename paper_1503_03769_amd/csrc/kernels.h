@@ -2147,33 +2147,34 @@ __global__ __launch_bounds__(1024) void k_bk_scan(const int* __restrict__ first,
 // q = floor(w 2^S) is also added to the sum of the resampling tile it lands
 // in: exact integer sums in FP64 (below 2^53), so the order of the atomic
 // additions does not matter.
-template <typename T>
+template <typename T, int NH>
 __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T> out, const int* __restrict__ first,
                                                     const int* __restrict__ end, int rtiles,
                                                     const int* __restrict__ bkt, const int* __restrict__ off,
                                                     const int* __restrict__ rsS, double* __restrict__ tsum,
                                                     int* __restrict__ orig)
 {
-    // a workgroup takes the 256-slot tiles 2 t2 and 2 t2 + 1 of the range
-    // (half h: tile 2 t2 + h, one slot per thread), each ranked exactly as a
-    // workgroup of its own would rank it; the reads of both go out first
-    __shared__ int wh[2][4][BEARING_BUCKETS];  // per half, per-wave bucket counts
+    // a workgroup takes NH 256-slot tiles of the range (half h: tile
+    // NH t2 + h, one slot per thread; NH = 2 where the capacity spans enough
+    // workgroups, else 1), each ranked exactly as a workgroup of its own would
+    // rank it; the reads of all go out first
+    __shared__ int wh[NH][4][BEARING_BUCKETS];  // per half, per-wave bucket counts
     const int j = slot_group(m), t2 = slot_tile(m);
     const int a = range_first(first, j), n = end[j] - a;
-    if (t2 * 512 >= n) return;
+    if (t2 * 256 * NH >= n) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 2 * 4 * BEARING_BUCKETS; i += 256) (&wh[0][0][0])[i] = 0;
+    for (int i = threadIdx.x; i < NH * 4 * BEARING_BUCKETS; i += 256) (&wh[0][0][0])[i] = 0;
     __syncthreads();
     const size_t gb = (size_t)j * m.cap + a;
     // the parents' buckets and states (every component: x[0] stands in for
     // an absent turn rate; lanes past the range read slot 0), then each
     // bucket's offset in its tile once the bucket is in
-    int s[2], b[2], ob[2];
-    bool live[2];
-    T v[2][5], pw[2];
+    int s[NH], b[NH], ob[NH];
+    bool live[NH];
+    T v[NH][5], pw[NH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        s[h] = (2 * t2 + h) * 256 + threadIdx.x;
+    for (int h = 0; h < NH; ++h) {
+        s[h] = (NH * t2 + h) * 256 + threadIdx.x;
         live[h] = s[h] < n;
         b[h] = live[h] ? bkt[gb + s[h]] : BEARING_BUCKETS;
         const size_t gs = gb + (live[h] ? s[h] : 0);
@@ -2183,14 +2184,14 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     }
     const int S = tsum ? rsS[j] : 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-        ob[h] = live[h] ? off[((size_t)j * rtiles + 2 * t2 + h) * BEARING_BUCKETS + b[h]] : 0;
+    for (int h = 0; h < NH; ++h)
+        ob[h] = live[h] ? off[((size_t)j * rtiles + NH * t2 + h) * BEARING_BUCKETS + b[h]] : 0;
     // lanes of this wave with the same bucket: intersect the ballots of the
     // seven bits of b (bit 6 tells the out-of-range lanes apart)
     const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int rank[2];
+    int rank[NH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
         unsigned long long peers = ~0ull;
         for (int bit = 0; bit < 7; ++bit) {
             const unsigned long long q = __ballot((b[h] >> bit) & 1);
@@ -2200,9 +2201,9 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
         if (live[h] && rank[h] == 0) wh[h][wv][b[h]] = __popcll(peers);
     }
     __syncthreads();
-    int dst[2];
+    int dst[NH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
         dst[h] = -1;
         if (live[h]) {
             int r = rank[h];
@@ -2219,7 +2220,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     // per destination tile: one wave sum and one atomic addition per distinct
     // tile (integer-valued sums below 2^53: exact in any order)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
         const double q = live[h] ? floor(ldexp((double)pw[h], S)) : 0.0;
         int tile = live[h] ? (dst[h] >> 8) : -1;
         for (;;) {
@@ -2437,16 +2438,16 @@ __device__ __forceinline__ double children_count(double mq, double Rj)
 
 // ---------------------------------------------------------------------------
 // Step 5, pass B: exact prefix of q, child counts and parent-order expansion
-// into the other particle set.  A workgroup owns RS_TILE = 512 consecutive
-// parents (two of the 256-slot tiles whose sums k_bk_scatter formed), thread
-// t parents base + t and base + 256 + t; parent i's children occupy slots
-// [N(c_{i-1}), N(c_i)).  The workgroup's children form one contiguous slot
-// range written with coalesced stores (each child finds its parent by binary
-// search over the workgroup's child offsets in LDS).
-// grid (ceil(rtiles/2), K) (or transposed), 256 threads.
+// into the other particle set.  A workgroup owns 256 NH consecutive parents
+// (NH of the 256-slot tiles whose sums k_bk_scatter formed; NH = 2 where the
+// capacity spans enough workgroups, else 1), thread t parents base + t,
+// base + 256 + t, ...; parent i's children occupy slots [N(c_{i-1}),
+// N(c_i)).  The workgroup's children form one contiguous slot range written
+// with coalesced stores (each child finds its parent by binary search over
+// the workgroup's child offsets in LDS).
+// grid (ceil(rtiles/NH), K) (or transposed), 256 threads.
 // ---------------------------------------------------------------------------
-constexpr int RS_TILE = 512;
-template <typename T>
+template <typename T, int NH>
 __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __restrict__ gd, SoA<T> in, SoA<T> out,
                                                    const int* __restrict__ ncur, int* __restrict__ nsurv,
                                                    const int* __restrict__ rsS, const double* __restrict__ tsum,
@@ -2454,10 +2455,11 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
                                                    double* __restrict__ massq, int* __restrict__ clampctr,
                                                    int* __restrict__ counts, int record)
 {
+    constexpr int RS_TILE = 256 * NH;
     __shared__ long long s_end[RS_TILE];
     __shared__ long long s_first;
     __shared__ T s_x[5][RS_TILE];
-    __shared__ double s_q[4][4];
+    __shared__ double s_q[2 + NH][4];
     const int j = slot_group(m), t = slot_tile(m);
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     const Grp gr = gd[j];
@@ -2469,10 +2471,10 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     const int S = rsS[j];
     // the parents' states and weights first (independent of the sums below;
     // every component read: x[0] stands in for an absent turn rate)
-    bool have[2];
-    T pv[2][5], pwt[2];
+    bool have[NH];
+    T pv[NH][5], pwt[NH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
         const int sidx = base + h * 256 + tid;
         have[h] = sidx < n;
         const size_t gs = gb + (have[h] ? sidx : 0);
@@ -2498,9 +2500,9 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         }
     }
     // each parent's integer weight and its in-wave inclusive prefix, per half
-    double q[2], qin[2];
+    double q[NH], qin[NH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
         q[h] = have[h] ? floor(ldexp((double)pwt[h], S)) : 0.0;
         qin[h] = wave_incl_scan(q[h]);
     }
@@ -2509,11 +2511,11 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     if (lane == 0) {
         s_q[0][wv] = qa;
         s_q[1][wv] = qp;
-        s_q[2][wv] = lane_value(qin[0], 63);
-        s_q[3][wv] = lane_value(qin[1], 63);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) s_q[2 + h][wv] = lane_value(qin[h], 63);
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
         if (have[h]) {
 #pragma unroll
             for (int d = 0; d < 5; ++d)
@@ -2523,13 +2525,14 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     __syncthreads();
     const double Qd = (s_q[0][0] + s_q[0][1]) + (s_q[0][2] + s_q[0][3]);
     const double Pd = (s_q[1][0] + s_q[1][1]) + (s_q[1][2] + s_q[1][3]);
-    // before this thread's wave in each half, and the whole first half
-    double wpre0 = 0.0, wpre1 = 0.0;
-    for (int w2 = 0; w2 < wv; ++w2) {
-        wpre0 += s_q[2][w2];
-        wpre1 += s_q[3][w2];
+    // before this thread's wave in each half, and the halves before it
+    double wpre[NH], hpre[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        wpre[h] = 0.0;
+        for (int w2 = 0; w2 < wv; ++w2) wpre[h] += s_q[2 + h][w2];
+        hpre[h] = h == 0 ? 0.0 : hpre[h - 1] + ((s_q[1 + h][0] + s_q[1 + h][1]) + (s_q[1 + h][2] + s_q[1 + h][3]));
     }
-    const double half0 = (s_q[2][0] + s_q[2][1]) + (s_q[2][2] + s_q[2][3]);
     const int Jj = gr.Jj;
     long long L = 0;
     double mq = 0.0;
@@ -2553,7 +2556,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     if (L == 0 || base >= n) {
         if (record) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < NH; ++h)
                 if (have[h]) counts[gb + base + h * 256 + tid] = 0;
         }
         return;
@@ -2563,19 +2566,21 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
                                  gr.rng_run).a;
     const uint64_t Q = (uint64_t)Qd;
     // c_i = q_0 + ... + q_i of the group (exact: integers below 2^53)
-    const double c0i = Pd + wpre0 + qin[0];
-    const double c1i = Pd + half0 + wpre1 + qin[1];
-    const long long nend0 = points_below((uint64_t)c0i, Q, L, r);
-    const long long nend1 = points_below((uint64_t)c1i, Q, L, r);
-    s_end[tid] = nend0;
-    s_end[256 + tid] = nend1;
+    long long nend[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        nend[h] = points_below((uint64_t)(Pd + hpre[h] + wpre[h] + qin[h]), Q, L, r);
+        s_end[h * 256 + tid] = nend[h];
+    }
     if (tid == 0) s_first = points_below((uint64_t)Pd, Q, L, r);
     __syncthreads();
     if (record) {
-        const long long b0 = tid == 0 ? s_first : s_end[tid - 1];
-        const long long b1 = s_end[255 + tid];
-        if (have[0]) counts[gb + base + tid] = (int)(nend0 - b0);
-        if (have[1]) counts[gb + base + 256 + tid] = (int)(nend1 - b1);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int i = h * 256 + tid;
+            const long long b0 = i == 0 ? s_first : s_end[i - 1];
+            if (have[h]) counts[gb + base + i] = (int)(nend[h] - b0);
+        }
     }
     const long long cb = s_first, ce = s_end[RS_TILE - 1];
     for (long long c = cb + tid; c < ce; c += 256) {

@@ -461,6 +461,12 @@ dim3 slot_grid(const pphd_filter* f, int tiles)
     return f->dm.tile_major ? dim3(tiles, f->K) : dim3(f->K, tiles);
 }
 
+// 256-slot tiles per workgroup of the resampling's scatter and expansion: two
+// where the capacity spans 4096 or more such workgroups (two reads per
+// thread in flight, half the dispatch rounds), one for small filters, whose
+// workgroups would not fill the chip
+int rs_halves(const pphd_filter* f) { return (size_t)f->K * f->cap >= ((size_t)1 << 20) ? 2 : 1; }
+
 // zsplit of a measurement count, as the passes derive it
 int host_zsplit(int M, int mz)
 {
@@ -737,10 +743,16 @@ pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, i
                hipLaunchKernelGGL(k_bk_scan, dim3(f->K), dim3(1024), 0, f->stream, first, f->ncur, f->rtiles,
                                   f->bhist, f->boff, parents ? f->tsum : nullptr));
     }
-    LAUNCH(f, cls,
-           hipLaunchKernelGGL((k_bk_scatter<T>), slot_grid(f, (tiles + 1) / 2), dim3(256), 0, f->stream, f->dm, cur,
-                              oth, first, f->ncur,
-                              f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr, orig));
+    if (rs_halves(f) == 2)
+        LAUNCH(f, cls,
+               hipLaunchKernelGGL((k_bk_scatter<T, 2>), slot_grid(f, (tiles + 1) / 2), dim3(256), 0, f->stream, f->dm,
+                                  cur, oth, first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS,
+                                  parents ? f->tsum : nullptr, orig));
+    else
+        LAUNCH(f, cls,
+               hipLaunchKernelGGL((k_bk_scatter<T, 1>), slot_grid(f, tiles), dim3(256), 0, f->stream, f->dm, cur, oth,
+                                  first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr,
+                                  orig));
     if (parents) f->order_ready = false;
     return PPHD_OK;
 }
@@ -776,8 +788,9 @@ pphd_status order_births(pphd_filter* f, bool weights_later)
 template <typename T>
 pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
-    // k_rs_expand: RS_TILE parents (two 256-slot tiles) per workgroup
-    dim3 g = slot_grid(f, (f->rtiles * 256 + RS_TILE - 1) / RS_TILE);
+    // k_rs_expand: rs_halves 256-slot tiles per workgroup
+    const int nh = rs_halves(f);
+    dim3 g = slot_grid(f, (f->rtiles + nh - 1) / nh);
     // parents into bearing-bucket order (into the other set), then the
     // systematic resampling back into this one
     {
@@ -787,10 +800,16 @@ pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
     }
     // the tile sums of the ordered parents came with the scatter
     SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
-    LAUNCH(f, PPHD_K_RS_EXPAND,
-           hipLaunchKernelGGL((k_rs_expand<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
-                              f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr, f->counts,
-                              f->record ? 1 : 0));
+    if (nh == 2)
+        LAUNCH(f, PPHD_K_RS_EXPAND,
+               hipLaunchKernelGGL((k_rs_expand<T, 2>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
+                                  f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr,
+                                  f->counts, f->record ? 1 : 0));
+    else
+        LAUNCH(f, PPHD_K_RS_EXPAND,
+               hipLaunchKernelGGL((k_rs_expand<T, 1>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
+                                  f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr,
+                                  f->counts, f->record ? 1 : 0));
     f->cur = 1 - f->cur;
     return PPHD_OK;
 }
