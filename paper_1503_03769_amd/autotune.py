@@ -3,7 +3,8 @@
 For every tile shape (particles per thread of the C(z) pass and of the weight
 pass, measurements per wavefront) it runs the named workload (a single filter
 or a batch of runs) from t = 0 and
-averages the passes' HIP-event times (k_cz + k_weight + k_wfinal) over a
+averages the passes' HIP-event times (C(z) pass + weight pass + k_wfinal
+where it runs) over a
 window of steady-state steps.  The fastest shape is written to tuning.json
 next to this file, keyed by storage precision (and "_batch" for batches);
 `pphd.Filter` and `pphd.Batch` apply it by default.  The shape changes only floating-point summation order.
