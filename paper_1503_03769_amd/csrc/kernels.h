@@ -543,35 +543,19 @@ __device__ __forceinline__ double arc_dist(double t, double lo, double span)
 // distance of v from [lo, hi]
 __device__ __forceinline__ double box_gap(double v, double lo, double hi) { return fmax(0.0, fmax(lo - v, v - hi)); }
 
-// the weight: lane = ordered birth s of group j (drawn at index borig[slot]);
-// the wavefront's 64 births bound the terms: proposal 1 by their range
-// interval and bearing arc, proposal 2 by their x and y intervals.  Terms
-// whose bound reaches the cut are exactly those the per-term test of the
-// full sum skips, or below it by a denormal at most.  Then the geometry.
-// grid (groups, ceil(J_max/256)) (or transposed).
+// The Eq 6 weight of a birth at x drawn from the measurement-driven
+// (PROP 1) or learned-mixture (PROP 2) proposal: lane = one birth of the
+// wavefront (active: a birth is there), whose 64 births bound the density's
+// terms: proposal 1 by their range interval and bearing arc, proposal 2 by
+// their x and y intervals.  Terms whose bound reaches the cut are exactly
+// those the per-term test of the full sum skips, or below it by a denormal
+// at most.  All 64 lanes call it.
 template <typename T, int PROP>
-__global__ __launch_bounds__(256) void k_birth_weight(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
-                                                      const int* __restrict__ nsurv, const int* __restrict__ ncur,
-                                                      const int* __restrict__ borig, const double* __restrict__ Zall,
-                                                      const double* __restrict__ taball, int Mall,
-                                                      const ZWin* __restrict__ win, uint32_t step_arg,
-                                                      const uint32_t* __restrict__ dstep)
+__device__ __forceinline__ double birth_weight_at(const DevModel& m, const BirthSrc& src, int Jj, const double* x,
+                                                  bool active)
 {
-    const int j = slot_group(m);
-    const Grp gr = gd[j];
-    const int ns = nsurv[j], nb = ncur[j] - ns;
-    if (slot_tile(m) * 256 >= nb) return;  // whole workgroup idle
     const int lane = threadIdx.x & 63;
-    const int b = slot_tile(m) * 256 + threadIdx.x;
-    const bool active = b < nb;
-    if (__ballot(active) == 0) return;     // whole wavefront idle
-    const uint32_t step = step_of(step_arg, dstep);
-    const BirthSrc src = birth_src(gr, win, Zall, taball, Mall);
     const int M = src.M;
-    const size_t g = (size_t)j * m.cap + ns + (active ? b : 0);
-    const int o = active ? borig[g] : 0;
-    double x[4];
-    draw_proposal_birth<PROP>(m, (uint32_t)(gr.jl * m.cap + ns + o), step, gr.rng_run, src, x);
     const bool inside = x[0] >= m.reg0 && x[0] <= m.reg1 && x[2] >= m.reg2 && x[2] <= m.reg3;
     double bd = inside ? m.inv_area : 0.0;  // gamma / m_b at x (proposal 1: the position part)
     if (PROP == 2 && inside) bd *= normal_pdf(x[1], m.sigma_v) * normal_pdf(x[3], m.sigma_v);
@@ -654,12 +638,40 @@ __global__ __launch_bounds__(256) void k_birth_weight(DevModel m, const Grp* __r
             }
         }
     }
-    if (!active) return;
     double w = 0.0;
-    if (bd > 0.0) {
+    if (active && bd > 0.0) {
         const double q = M > 0 ? m.alpha * bd + (1.0 - m.alpha) * mix / (double)M : bd;
-        w = m.birth_mass * bd / ((double)gr.Jj * q);
+        w = m.birth_mass * bd / ((double)Jj * q);
     }
+    return w;
+}
+
+// the weights of ordered births: lane = ordered birth s of group j (drawn at
+// index borig[slot], drawn again here), then the geometry.
+// grid (groups, ceil(J_max/256)) (or transposed).
+template <typename T, int PROP>
+__global__ __launch_bounds__(256) void k_birth_weight(DevModel m, const Grp* __restrict__ gd, SoA<T> st, Geo geo,
+                                                      const int* __restrict__ nsurv, const int* __restrict__ ncur,
+                                                      const int* __restrict__ borig, const double* __restrict__ Zall,
+                                                      const double* __restrict__ taball, int Mall,
+                                                      const ZWin* __restrict__ win, uint32_t step_arg,
+                                                      const uint32_t* __restrict__ dstep)
+{
+    const int j = slot_group(m);
+    const Grp gr = gd[j];
+    const int ns = nsurv[j], nb = ncur[j] - ns;
+    if (slot_tile(m) * 256 >= nb) return;  // whole workgroup idle
+    const int b = slot_tile(m) * 256 + threadIdx.x;
+    const bool active = b < nb;
+    if (__ballot(active) == 0) return;     // whole wavefront idle
+    const uint32_t step = step_of(step_arg, dstep);
+    const BirthSrc src = birth_src(gr, win, Zall, taball, Mall);
+    const size_t g = (size_t)j * m.cap + ns + (active ? b : 0);
+    const int o = active ? borig[g] : 0;
+    double x[4];
+    draw_proposal_birth<PROP>(m, (uint32_t)(gr.jl * m.cap + ns + o), step, gr.rng_run, src, x);
+    const double w = birth_weight_at<T, PROP>(m, src, gr.Jj, x, active);
+    if (!active) return;
     const T tw = (T)w;
     st.w[g] = tw;
     // the stored position is the drawn one at storage precision
@@ -2243,14 +2255,14 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
 template <typename T, int BS>
 __device__ __forceinline__ void sort_births_block(const DevModel& m, const SoA<T>& st, const Geo& geo, size_t gb,
                                                   int nb, T (&v)[BS][5], const T (&w)[BS], const int (&b)[BS],
-                                                  int* __restrict__ borig, int with_geo)
+                                                  int* __restrict__ borig, int with_geo, int (&dst)[BS],
+                                                  bool write_w = true)
 {
     __shared__ int s_off[BEARING_BUCKETS];
     __shared__ int s_w[16][BEARING_BUCKETS];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < BEARING_BUCKETS) s_off[tid] = 0;
     __syncthreads();
-    int dst[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
         dst[c] = -1;
@@ -2297,7 +2309,7 @@ __device__ __forceinline__ void sort_births_block(const DevModel& m, const SoA<T
 #pragma unroll
         for (int d = 0; d < 5; ++d)
             if (d < m.dim) st.x[d][g] = v[c][d];
-        st.w[g] = w[c];
+        if (write_w) st.w[g] = w[c];
         if (borig) borig[g] = c * 1024 + tid;
         if (with_geo) store_geometry(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
     }
@@ -2335,16 +2347,23 @@ __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo 
             b[c] = bkt[gb + i];  // the bucket of the birth as drawn
         }
     }
-    sort_births_block<T, BS>(m, st, geo, gb, nb, v, w, b, borig, with_geo);
+    int dst[BS];
+    sort_births_block<T, BS>(m, st, geo, gb, nb, v, w, b, borig, with_geo, dst);
 }
 
 // The births of the measurement-driven proposals drawn and put in bearing
 // order in one workgroup per group (groups of at most 1024 * BS births):
 // birth i is drawn exactly as k_birth_draw draws it (its counter, its bucket
-// from the drawn position, weight 0 until k_birth_weight), held in
-// registers, and written once at its rank with borig = i.  grid (K), 1024
+// from the drawn position), held in registers, and written once at its rank
+// with borig = i.  WEIGHT (FP32, the measurement-driven proposal, groups of
+// at most BIRTH_FUSED_MAX births): the drawn positions also go to LDS (by
+// drawing index, with the drawing index of every rank), and each wavefront
+// then gives 64 consecutive ordered births their Eq 6 weights and geometry,
+// as k_birth_weight would (the same births per wavefront, the same
+// positions); else the weights are 0 until k_birth_weight.  grid (K), 1024
 // threads.
-template <typename T, int BS, int PROP>
+constexpr int BIRTH_FUSED_MAX = 1152;
+template <typename T, int BS, int PROP, bool WEIGHT>
 __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
                                                           Geo geo, const int* __restrict__ nsurv,
                                                           const int* __restrict__ ncur,
@@ -2353,6 +2372,7 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
                                                           const ZWin* __restrict__ win, uint32_t step_arg,
                                                           const uint32_t* __restrict__ dstep, int* __restrict__ borig)
 {
+    static_assert(!WEIGHT || 1024 * BS >= BIRTH_FUSED_MAX, "the fused form holds every birth");
     const int j = blockIdx.x;
     const Grp gr = gd[j];
     const int ns = nsurv[j], nb = ncur[j] - ns;
@@ -2363,6 +2383,8 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
     const BirthSrc src = birth_src(gr, win, Zall, taball, Mall);
     T v[BS][5], w[BS];
     int b[BS];
+    __shared__ double s_xd[WEIGHT ? BIRTH_FUSED_MAX : 1][4];  // positions by drawing index
+    __shared__ int s_inv[WEIGHT ? BIRTH_FUSED_MAX : 1];       // drawing index of each rank
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
         const int i = c * 1024 + tid;
@@ -2376,9 +2398,40 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
             for (int d = 0; d < 4; ++d) v[c][d] = (T)x[d];
             v[c][4] = m.dim == 5 ? (T)birth_turn_rate(m, c0, step, gr.rng_run) : (T)0;
             b[c] = bearing_bucket(m, x[0], x[2]);
+            if constexpr (WEIGHT) {
+                if (i < BIRTH_FUSED_MAX) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) s_xd[i][d] = x[d];
+                }
+            }
         }
     }
-    sort_births_block<T, BS>(m, st, geo, gb, nb, v, w, b, borig, 0);
+    int dst[BS];
+    sort_births_block<T, BS>(m, st, geo, gb, nb, v, w, b, borig, 0, dst, !WEIGHT);
+    if constexpr (WEIGHT) {
+        if (nb > BIRTH_FUSED_MAX) return;  // (the host launches this form only below it)
+#pragma unroll
+        for (int c = 0; c < BS; ++c)
+            if (dst[c] >= 0) s_inv[dst[c]] = c * 1024 + tid;
+        __syncthreads();
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int t0 = wv * 64; t0 < nb; t0 += 1024) {
+            const int i = t0 + lane;
+            const bool active = i < nb;
+            double x[4];
+            const int o = active ? s_inv[i] : 0;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) x[d] = active ? s_xd[o][d] : 0.0;
+            const double wt = birth_weight_at<T, PROP>(m, src, gr.Jj, x, active);
+            if (active) {
+                const size_t g = gb + i;
+                const T tw = (T)wt;
+                st.w[g] = tw;
+                // the stored position is the drawn one at storage precision
+                store_geometry(m, geo, g, (double)(T)x[0], (double)(T)x[2], (double)tw);
+            }
+        }
+    }
 }
 
 // births back from the other set in their sorted order, with their geometry

@@ -555,42 +555,62 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
             }
             const dim3 gb = slot_grid(f, (Jmax + 255) / 256);
             const double* tab = dm.proposal == 2 ? f->mix_tab : nullptr;
-            // groups of up to 1024 BS births: drawn and ordered in one
-            // workgroup each; larger ones drawn, then put in bucket order
+            // FP32 groups of up to BIRTH_FUSED_MAX births of the
+            // measurement-driven proposal: drawn, ordered and weighted in one
+            // workgroup each; up to 1024 BS: drawn and ordered
+            // there, weighted by k_birth_weight; larger ones drawn, put in
+            // bucket order, then weighted
             constexpr int BS = sizeof(T) == 4 ? 8 : 4;
-            if (Jmax <= 1024 * BS) {
-                if (dm.proposal == 1)
+            bool weighted = false;
+            // (FP64 storage and the mixture proposal, whose density loop wants
+            // more wavefronts than a 1024-thread workgroup per group leaves:
+            // the weights by their own kernel)
+            if constexpr (sizeof(T) == 4) {
+                if (Jmax <= BIRTH_FUSED_MAX && dm.proposal == 1) {
+                    weighted = true;
                     LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                           hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1>), dim3(K), dim3(1024), 0, f->stream, dm,
-                                              f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step,
-                                              a.dstep, f->borig));
-                else
-                    LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                           hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2>), dim3(K), dim3(1024), 0, f->stream, dm,
-                                              f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step,
-                                              a.dstep, f->borig));
-            } else {
-                if (dm.proposal == 1)
-                    LAUNCH(f, cls,
-                           hipLaunchKernelGGL((k_birth_draw<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st,
-                                              f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep,
-                                              f->bkt));
-                else
-                    LAUNCH(f, cls,
-                           hipLaunchKernelGGL((k_birth_draw<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st,
-                                              f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep,
-                                              f->bkt));
-                pphd_status os = order_births<T>(f, true);
-                if (os != PPHD_OK) return os;
+                           hipLaunchKernelGGL((k_birth_draw_sort<T, 2, 1, true>), dim3(K), dim3(1024), 0, f->stream,
+                                              dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win,
+                                              f->last_step, a.dstep, f->borig));
+                }
             }
-            if (dm.proposal == 1)
-                LAUNCH(f, cls,
-                       hipLaunchKernelGGL((k_birth_weight<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
-                                          f->nsurv, f->ncur, f->borig, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
-            else
-                LAUNCH(f, cls,
-                       hipLaunchKernelGGL((k_birth_weight<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
-                                          f->nsurv, f->ncur, f->borig, a.dz, tab, a.M, a.win, f->last_step, a.dstep));
+            if (!weighted) {
+                if (Jmax <= 1024 * BS) {
+                    if (dm.proposal == 1)
+                        LAUNCH(f, PPHD_K_BIRTH_ORDER,
+                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1, false>), dim3(K), dim3(1024), 0,
+                                                  f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
+                                                  a.win, f->last_step, a.dstep, f->borig));
+                    else
+                        LAUNCH(f, PPHD_K_BIRTH_ORDER,
+                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2, false>), dim3(K), dim3(1024), 0,
+                                                  f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
+                                                  a.win, f->last_step, a.dstep, f->borig));
+                } else {
+                    if (dm.proposal == 1)
+                        LAUNCH(f, cls,
+                               hipLaunchKernelGGL((k_birth_draw<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st,
+                                                  f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep,
+                                                  f->bkt));
+                    else
+                        LAUNCH(f, cls,
+                               hipLaunchKernelGGL((k_birth_draw<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st,
+                                                  f->nsurv, f->ncur, a.dz, tab, a.M, a.win, f->last_step, a.dstep,
+                                                  f->bkt));
+                    pphd_status os = order_births<T>(f, true);
+                    if (os != PPHD_OK) return os;
+                }
+                if (dm.proposal == 1)
+                    LAUNCH(f, cls,
+                           hipLaunchKernelGGL((k_birth_weight<T, 1>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
+                                              f->nsurv, f->ncur, f->borig, a.dz, tab, a.M, a.win, f->last_step,
+                                              a.dstep));
+                else
+                    LAUNCH(f, cls,
+                           hipLaunchKernelGGL((k_birth_weight<T, 2>), gb, dim3(256), 0, f->stream, dm, f->gd, st, geo,
+                                              f->nsurv, f->ncur, f->borig, a.dz, tab, a.M, a.win, f->last_step,
+                                              a.dstep));
+            }
         }
         f->mix_preset = false;
         f->births_pending = false;

@@ -167,14 +167,20 @@ def test_exchange_exact(gpu, prec, K, counts):
                                                  ("fp32", 3, 900, [2000, 700, 0], 4096),
                                                  ("fp32", 2, 18000, [1500, 300], 11000),
                                                  ("fp64", 1, 5000, [800], 6000),
-                                                 ("fp32", 1100, 330000, [300] * 1100, 1024)])
+                                                 ("fp32", 1100, 330000, [300] * 1100, 1024),
+                                                 ("fp32", 2, 6000, [1500, 300], 8192)])
 def test_measurement_driven_births(gpu, prec, K, J, counts, cap):
     """Eq 6 with p_k(.|Z_k): predict reserves the birth slots, update draws
-    them from the measurement-driven mixture and then updates all weights
-    (the third and fourth cases order their births in several launches; in
-    the last, 1100 groups of 300 survivors and 300 births, each workgroup of
+    them from the measurement-driven mixture and then updates all weights.
+    In FP32 up to 1152 births per group of this proposal are drawn, ordered
+    and weighted in one workgroup each (the second and fifth cases); the
+    first case (FP64)
+    and the last (3000 per group) draw and order them there and weight them
+    in their own kernel; the third and fourth cases order their births in
+    several launches.  In
+    the fifth, 1100 groups of 300 survivors and 300 births, each workgroup of
     the second pass takes two birth tiles split into chunks, whose sums meet
-    in LDS buffers used in turn)."""
+    in LDS buffers used in turn."""
     print(f"measurement-driven births {prec} K={K} J={J}", flush=True)
     p = dict(BASE_MODEL, partitions=K, births_per_step=J, birth_proposal=1, birth_alpha=0.1)
     truth, Z = _scen(p, n=4)
