@@ -189,3 +189,37 @@ def test_batch_argument_errors(gpu):
     assert e.value.code == pphd.PPHD_ESTATE
     q.close()
     b.close()
+
+
+def test_large_uneven_batch_matches_oracle_on_sampled_runs(gpu):
+    """520 one-group FP32 runs of two sizes (the flat work lists of unlike
+    runs), 300 births each: every run has two birth tiles split into chunks,
+    1040 in all over the 1024-workgroup grid, so many workgroups finalize two
+    of them in turn.  After one predict + update, sampled runs against the
+    oracle."""
+    print("large uneven batch", flush=True)
+    p = _model(0)
+    runs = [dict(partitions=1, births_per_step=300, clutter_rate=20.0,
+                 particles_per_target=150.0 if i % 2 else 300.0, run_id=i) for i in range(520)]
+    cap, maxm, seed = 1024, 64, 97
+    Zs = [make_scenario(dict(p, clutter_rate=20.0), 2, 2, 4000 + i)[1] for i in range(len(runs))]
+    b = pphd.Batch(p, runs, pphd.PPHD_FP32, cap, maxm, seed)
+    b.init()
+    b.predict(1)
+    X0, W0, n0 = b.read_state()
+    b.update([Z[1] for Z in Zs])
+    X1, W1, n1 = b.read_state()
+    for r in (0, 1, 257, 518, 519):
+        q = dict(p, partitions=1, births_per_step=300, clutter_rate=20.0,
+                 particles_per_target=runs[r]["particles_per_target"])
+        g0 = int(b.run_g0[r])
+        st = orc.State(1, cap)
+        orc.init(q, st, seed, r)
+        orc.predict(q, st, 1, seed, r)
+        sl = slice(g0 * cap, (g0 + 1) * cap)
+        P.check_states(X0[:, sl], W0[sl], n0[g0:g0 + 1], st, "fp32")
+        st.X[:] = X0[:, sl]
+        st.W[:] = W0[sl]
+        orc.update(q, st, Zs[r][1])
+        P.check_weights(W1[sl], st)
+    b.close()
