@@ -168,7 +168,8 @@ def test_exchange_exact(gpu, prec, K, counts):
                                                  ("fp32", 2, 18000, [1500, 300], 11000),
                                                  ("fp64", 1, 5000, [800], 6000),
                                                  ("fp32", 1100, 330000, [300] * 1100, 1024),
-                                                 ("fp32", 2, 6000, [1500, 300], 8192)])
+                                                 ("fp32", 2, 6000, [1500, 300], 8192),
+                                                 ("fp32", 64, 50000, [14000 + 37 * j for j in range(64)], 32768)])
 def test_measurement_driven_births(gpu, prec, K, J, counts, cap):
     """Eq 6 with p_k(.|Z_k): predict reserves the birth slots, update draws
     them from the measurement-driven mixture and then updates all weights.
@@ -180,7 +181,9 @@ def test_measurement_driven_births(gpu, prec, K, J, counts, cap):
     several launches.  In
     the fifth, 1100 groups of 300 survivors and 300 births, each workgroup of
     the second pass takes two birth tiles split into chunks, whose sums meet
-    in LDS buffers used in turn."""
+    in LDS buffers used in turn.  The seventh has the birth share of the
+    64-group benchmark workload: about 781 births per group of some 14 000
+    survivors, drawn, ordered and weighted in one workgroup each."""
     print(f"measurement-driven births {prec} K={K} J={J}", flush=True)
     p = dict(BASE_MODEL, partitions=K, births_per_step=J, birth_proposal=1, birth_alpha=0.1)
     truth, Z = _scen(p, n=4)
