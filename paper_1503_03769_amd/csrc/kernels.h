@@ -1532,8 +1532,11 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
 
 // ---------------------------------------------------------------------------
 // Combine the first-pass partials of group j (one 1024-thread workgroup per
-// group; one wavefront per measurement, lanes over the group's tiles in a
-// fixed tree order):
+// group).  Lanes take 64 consecutive measurements (one tile's row of partials
+// per load), wavefront w the tiles w, w + 16, ...; each lane keeps a running
+// exponent and sum, rescaled by a power of two when a larger exponent comes
+// (exact outside the subnormal range), and the 16 wavefronts' pairs are then
+// added in wavefront order:
 //   H = max h over tiles with s > 0, S = sum s 2^(h - H)
 //   C = 2^H S,  F = 1/(kappa 2^-H + S) = 2^H/(kappa + C),  dW = S F = C/(kappa + C)
 // Then the candidate labels for Step 3: the top min(LT_c + 1, #dW>0)
@@ -1568,41 +1571,56 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
     const int n = ncur[j];
     const int nw = (n + WT - 1) / WT;
     const size_t zb = (size_t)j * Mmax;
-    for (int p = wv; p < M; p += 16) {
-        const int pp = zpos ? zpos[zoff + p] : p;
-        int H = -2147483647 - 1;
-        double S = 0.0;
-        if (nw <= 64) {
-            // one tile per lane, read once
-            const size_t o = ((size_t)j * wtiles + (lane < nw ? lane : 0)) * Mmax + pp;
-            const double v = ps[o];
-            const int h = ph[o];
-            const double sv = lane < nw ? v : 0.0;
-            if (sv > 0.0) H = h;
-            H = wave_max(H);
-            if (sv > 0.0) S = ldexp(sv, h - H);
-        } else {
-            for (int t = lane; t < nw; t += 64) {
-                const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
-                if (ps[o] > 0.0 && ph[o] > H) H = ph[o];
+    __shared__ int s_h[16][64];
+    __shared__ double s_s[16][64];
+    constexpr int RC = 8;  // tiles per wavefront whose loads are in flight together
+    for (int p0 = 0; p0 < M; p0 += 64) {
+        const int p = p0 + lane;
+        const bool live = p < M;
+        const int pp = live ? (zpos ? zpos[zoff + p] : p) : 0;
+        int Hl = -2147483647 - 1;
+        double Sl = 0.0;
+        for (int t0 = wv; t0 < nw; t0 += 16 * RC) {
+            double v[RC];
+            int h[RC];
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+                const int t = t0 + 16 * r;
+                const size_t o = ((size_t)j * wtiles + (t < nw ? t : 0)) * Mmax + pp;
+                const double x = ps[o];
+                h[r] = ph[o];
+                v[r] = live && t < nw ? x : 0.0;
             }
-            H = wave_max(H);
-            for (int t = lane; t < nw; t += 64) {
-                const size_t o = ((size_t)j * wtiles + t) * Mmax + pp;
-                if (ps[o] > 0.0) S += ldexp(ps[o], ph[o] - H);
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+                if (!(v[r] > 0.0)) continue;
+                if (h[r] > Hl) {
+                    Sl = Sl > 0.0 ? ldexp(Sl, Hl - h[r]) : 0.0;
+                    Hl = h[r];
+                }
+                Sl += ldexp(v[r], h[r] - Hl);
             }
         }
-        S = wave_sum(S);
-        double C = 0.0, F = 0.0, dW = 0.0;
-        if (S > 0.0) {
-            const double D = ldexp(gr.kappa, -H) + S;
-            F = 1.0 / D;
-            dW = S / D;
-            C = ldexp(S, H);
-        } else {
-            H = 0;
-        }
-        if (lane == 0) {
+        s_h[wv][lane] = Hl;
+        s_s[wv][lane] = Sl;
+        __syncthreads();
+        if (wv == 0 && live) {
+            int H = s_h[0][lane];
+            for (int w2 = 1; w2 < 16; ++w2) H = s_h[w2][lane] > H ? s_h[w2][lane] : H;
+            double S = 0.0;
+            for (int w2 = 0; w2 < 16; ++w2) {
+                const double sw = s_s[w2][lane];
+                if (sw > 0.0) S += ldexp(sw, s_h[w2][lane] - H);
+            }
+            double C = 0.0, F = 0.0, dW = 0.0;
+            if (S > 0.0) {
+                const double D = ldexp(gr.kappa, -H) + S;
+                F = 1.0 / D;
+                dW = S / D;
+                C = ldexp(S, H);
+            } else {
+                H = 0;
+            }
             zH[zb + p] = H;
             zF[zb + p] = (T)F;
             zC[zb + p] = C;
@@ -1615,6 +1633,9 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
                 zsort.flag[zb + pp] = 0;
             }
         }
+        // wavefront 0 has read this chunk's pairs before any wavefront writes
+        // the next chunk's
+        __syncthreads();
     }
     double wsum = 0.0;
     for (int t = tid; t < nw; t += 1024) wsum += pw[(size_t)j * wtiles + t];
