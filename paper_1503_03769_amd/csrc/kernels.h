@@ -870,13 +870,13 @@ struct ZPrep {
     double* zs;   // [rows][2]: scaled range, scaled frame bearing, in frame order per run
     int* orig;    // [rows]: original index of the entry within its run
     int* pos;     // [rows]: frame-order position of original measurement p (the inverse)
-    int* nA;      // [runs]: entries of frame A
+    int* rec;     // [runs][4]: window offset, measurement count, entries of frame A, 0
 };
 struct ZPrepC {
     const double* zs;
     const int* orig;
     const int* pos;
-    const int* nA;
+    const int* rec;
 };
 // per-group measurement results of the first pass again in frame order, for
 // the second pass (H, F and the candidate flag of k_cz_combine)
@@ -909,7 +909,8 @@ __global__ __launch_bounds__(256) void k_zprep(DevModel m, const double* __restr
     __syncthreads();
     const int nA = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
     if (threadIdx.x == 0) {
-        zp.nA[run] = nA;
+        // the record the likelihood passes read in one scalar load
+        *reinterpret_cast<int4*>(zp.rec + 4 * run) = make_int4(off, M, nA, 0);
         s_base = 0;
     }
     // pass 2: stable positions, 256 measurements at a time
@@ -1092,39 +1093,46 @@ __global__ __launch_bounds__(256) void k_items_fill(const int* __restrict__ pre,
     for (int e = pre[j] + threadIdx.x; e < pre[j + 1]; e += 256) grp[e] = j;
 }
 
+// the run of a work item's group: read per item from the flat lists, else the
+// workgroup's group's run read once at the start (the empty asm keeps the
+// per-item read behind its branch, so it is not made for every item)
+__device__ __forceinline__ int item_run(const Grp* __restrict__ gd, bool flat, int j, int run0)
+{
+    if (!flat) return run0;
+    int jj = j;
+    __asm__ volatile("" : "+s"(jj));
+    return gd[jj].run;
+}
+// the particle count and survivor count of a work item's group, the same way
+__device__ __forceinline__ int2 item_sizes(const int* __restrict__ ncur, const int* __restrict__ nsurv, bool flat,
+                                           int j, int2 s0)
+{
+    if (!flat) return s0;
+    int jj = j;
+    __asm__ volatile("" : "+s"(jj));
+    return make_int2(ncur[jj], nsurv[jj]);
+}
+
 // first pass in frames: as k_cz (PASS_FRAMES), the measurement side read
 // from the prepared order, tiles culled; tile `tile` of group j, every
 // measurement of the run in one wavefront
 template <typename T, int PT>
 __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __restrict__ gd, const Geo& geo,
-                                               const T* __restrict__ W, const int* __restrict__ ncur, int Mall,
+                                               const T* __restrict__ W, int n, int Mall,
                                                const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
                                                const Split& sp, double* __restrict__ ps, int* __restrict__ ph,
-                                               double* __restrict__ pw, int j, int tile, int zc, int zsplit)
+                                               double* __restrict__ pw, const int* __restrict__ zrec, int j,
+                                               int zrun, int tile, int zc, int zsplit)
 {
     constexpr int WT = 64 * PT;
-    const Grp gr = gd[j];
-    int off = 0, M = Mall;
-    if (win) {
-        off = win[gr.run].off;
-        M = win[gr.run].M;
-    }
-    const int MZ = (M + zsplit - 1) / zsplit;
-    const int p0 = zc * MZ < M ? zc * MZ : M, p1 = p0 + MZ < M ? p0 + MZ : M;
     const int lane = threadIdx.x & 63;
-    const int n = ncur[j];
     const int base = tile * WT;
     if (base >= n) return;
     const size_t gb = (size_t)j * m.cap;
-    const double* zs = zp.zs + 2 * (size_t)off;
-    const int nA = zp.nA[gr.run];
-    // the first 64 measurements of each frame in [p0, p1), loaded with the particles
-    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
-    const int qa = p0 + lane < a1 ? p0 + lane : 0, qb = b0 + lane < p1 ? b0 + lane : 0;
-    const double zra0 = M > 0 ? zs[2 * qa] : 0.0, zta0 = M > 0 ? zs[2 * qa + 1] : 0.0;
-    const double zrb0 = M > 0 ? zs[2 * qb] : 0.0, ztb0 = M > 0 ? zs[2 * qb + 1] : 0.0;
     double rho[PT], phi[PT], phib[PT], nlw[PT];
     double lwmax = -__builtin_inf();
+    // the particles first: they need only the group's size, so they are in
+    // flight while the run's measurement window is looked up
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         const int s = base + i * 64 + lane;
@@ -1139,6 +1147,18 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
         nlw[i] = ok ? -lw : __builtin_inf();
         lwmax = ok && lw > lwmax ? lw : lwmax;
     }
+    // the run's frame split and window, read together
+    // the run's window and frame split (one record)
+    const int4 zr4 = *reinterpret_cast<const int4*>(zrec + 4 * zrun);
+    const int off = zr4.x, M = zr4.y, nA = zr4.z;
+    const int MZ = (M + zsplit - 1) / zsplit;
+    const int p0 = zc * MZ < M ? zc * MZ : M, p1 = p0 + MZ < M ? p0 + MZ : M;
+    const double* zs = zp.zs + 2 * (size_t)off;
+    // the first 64 measurements of each frame in [p0, p1)
+    const int a1 = p1 < nA ? p1 : nA, b0 = p0 > nA ? p0 : nA;
+    const int qa = p0 + lane < a1 ? p0 + lane : 0, qb = b0 + lane < p1 ? b0 + lane : 0;
+    const double zra0 = M > 0 ? zs[2 * qa] : 0.0, zta0 = M > 0 ? zs[2 * qa + 1] : 0.0;
+    const double zrb0 = M > 0 ? zs[2 * qb] : 0.0, ztb0 = M > 0 ? zs[2 * qb + 1] : 0.0;
     if (zc == 0) {
         double ws = 0.0;
 #pragma unroll
@@ -1224,20 +1244,27 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
                                                    int Mall, const ZWin* __restrict__ win, ZPrepC zp, int Mmax,
                                                    Split sp, double* __restrict__ ps, int* __restrict__ ph,
                                                    double* __restrict__ pw, const int* __restrict__ nsurv, int K,
-                                                   const int* __restrict__ tpre, const int* __restrict__ tgrp)
+                                                   const int* __restrict__ tpre, const int* __restrict__ tgrp,
+                                                   const int* __restrict__ zrec)
 {
     // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
     const bool flat = tpre != nullptr;
     const int w0 = (flat ? blockIdx.x : blockIdx.y) * 4 + wave_in_block();
     const int stride = (flat ? gridDim.x : gridDim.y) * 4;
-    const int end = flat ? tpre[K] : tile_items(ncur[blockIdx.x], nsurv[blockIdx.x], 64 * PT);
+    // the group's sizes and run, read once (kept apart from the per-item reads
+    // of the flat lists, so they are not read again per item)
+    int2 s0 = flat ? make_int2(0, 0) : make_int2(ncur[blockIdx.x], nsurv[blockIdx.x]);
+    int run0 = flat ? 0 : gd[blockIdx.x].run;
+    __asm__ volatile("" : "+s"(run0), "+s"(s0.x), "+s"(s0.y));
+    const int end = flat ? tpre[K] : tile_items(s0.x, s0.y, 64 * PT);
     for (int e = w0; e < end; e += stride) {
         const int j = flat ? tgrp[e] : (int)blockIdx.x;
         const int le = flat ? e - tpre[j] : e;
-        if (le >= tile_items(ncur[j], nsurv[j], 64 * PT)) continue;  // a list's padding
-        const TileItem it = tile_item(le, ncur[j], nsurv[j], 64 * PT);
-        cz_frames_tile<T, PT>(m, gd, geo, W, ncur, Mall, win, zp, Mmax, sp, ps, ph, pw, j, it.tile, it.chunk,
-                              it.chunks);
+        const int2 sz = item_sizes(ncur, nsurv, flat, j, s0);
+        if (le >= tile_items(sz.x, sz.y, 64 * PT)) continue;  // a list's padding
+        const TileItem it = tile_item(le, sz.x, sz.y, 64 * PT);
+        cz_frames_tile<T, PT>(m, gd, geo, W, sz.x, Mall, win, zp, Mmax, sp, ps, ph, pw, zrec, j,
+                              item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks);
     }
 }
 
@@ -1310,48 +1337,28 @@ __device__ __forceinline__ void finalize_tile(const DevModel& m, const WFin<T>& 
 // measurement of the run in one wavefront
 template <typename T, int PT>
 __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp* __restrict__ gd, const SoA<T>& st,
-                                                   const Geo& geo, const int* __restrict__ ncur, int Mall,
+                                                   const Geo& geo, int n, int Mall,
                                                    const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
                                                    const Split& sp, const int* __restrict__ zHs,
                                                    const T* __restrict__ zFs, const int* __restrict__ zfls,
-                                                   double* __restrict__ pzeta, T* __restrict__ accp, int j, int tile,
-                                                   int zc, int zsplit, const WFin<T>& fin, int& quads)
+                                                   double* __restrict__ pzeta, T* __restrict__ accp,
+                                                   const int* __restrict__ zrec, int j, int zrun, int tile, int zc,
+                                                   int zsplit, const WFin<T>& fin, int& quads)
 {
     constexpr int WT = 64 * PT;
-    const Grp gr = gd[j];
-    int off = 0, M = Mall;
-    if (win) {
-        off = win[gr.run].off;
-        M = win[gr.run].M;
-    }
-    const int MZ = (M + zsplit - 1) / zsplit;
-    const int p0 = zc * MZ < M ? zc * MZ : M, p1 = p0 + MZ < M ? p0 + MZ : M;
     const int lane = threadIdx.x & 63;
-    const int n = ncur[j];
     const int base = tile * WT;
     if (base >= n) return;
     const size_t gb = (size_t)j * m.cap;
-    const size_t zb = (size_t)j * Mmax;
-    const double* zs = zp.zs + 2 * (size_t)off;
-    const int nA = zp.nA[gr.run];
-    // lane l holds the operands of measurement c0 + l of [p0, p1) (frame
-    // order: frame A below nA, frame B from nA); the first 64 are loaded with
-    // the particles
-    struct ZOp {
-        double zr, zt;
-        int H;
-        T F;
-        int fl;
-    };
-    auto zop = [&](int q) { return ZOp{ zs[2 * q], zs[2 * q + 1], zHs[zb + q], zFs[zb + q], zfls[zb + q] }; };
-    const ZOp z0 = p0 < p1 ? zop(p0 + lane < p1 ? p0 + lane : p0) : ZOp{ 0.0, 0.0, 0, (T)0, 0 };
     // the group's arrays (wave-uniform bases, slot offsets below 2^32 bytes)
     const double *grho = geo.rho + gb, *gphi = geo.phi + gb, *gphib = geo.phib + gb;
     const T *gw = st.w + gb, *gx0 = st.x[0] + gb, *gx1 = st.x[1] + gb, *gx2 = st.x[2] + gb, *gx3 = st.x[3] + gb;
     double rho[PT], phi[PT], phib[PT];
     T acc[PT];
-    // with the geometry, the weight and the position (the finalization and
-    // the candidates' sums use them; the velocities are read by candidates)
+    // the geometry, the weight and the position (the finalization and the
+    // candidates' sums use them; the velocities are read by candidates),
+    // issued before the run's measurement window is looked up: they need only
+    // the group's size, so they are in flight during those reads
     T wv[PT], xa[PT], xb[PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -1368,6 +1375,25 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         phib[i] = ok ? b : 0.0;
         acc[i] = 0;
     }
+    // the run's frame split and window, read together
+    // the run's window and frame split (one record)
+    const int4 zr4 = *reinterpret_cast<const int4*>(zrec + 4 * zrun);
+    const int off = zr4.x, M = zr4.y, nA = zr4.z;
+    const int MZ = (M + zsplit - 1) / zsplit;
+    const int p0 = zc * MZ < M ? zc * MZ : M, p1 = p0 + MZ < M ? p0 + MZ : M;
+    const size_t zb = (size_t)j * Mmax;
+    const double* zs = zp.zs + 2 * (size_t)off;
+    // lane l holds the operands of measurement c0 + l of [p0, p1) (frame
+    // order: frame A below nA, frame B from nA); the first 64 are loaded
+    // right after the particles
+    struct ZOp {
+        double zr, zt;
+        int H;
+        T F;
+        int fl;
+    };
+    auto zop = [&](int q) { return ZOp{ zs[2 * q], zs[2 * q + 1], zHs[zb + q], zFs[zb + q], zfls[zb + q] }; };
+    const ZOp z0 = p0 < p1 ? zop(p0 + lane < p1 ? p0 + lane : p0) : ZOp{ 0.0, 0.0, 0, (T)0, 0 };
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
     // a candidate label's local-estimate sums (the tile's weighted states are
     // read here, by the tiles that keep the candidate: 0 in empty slots)
@@ -1512,21 +1538,27 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
                                                        const int* __restrict__ zfls, double* __restrict__ pzeta,
                                                        T* __restrict__ accp, const int* __restrict__ nsurv, int K,
                                                        const int* __restrict__ tpre, const int* __restrict__ tgrp,
-                                                       WFin<T> fin)
+                                                       WFin<T> fin, const int* __restrict__ zrec)
 {
     // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
     const bool flat = tpre != nullptr;
     const int w0 = (flat ? blockIdx.x : blockIdx.y) * 4 + wave_in_block();
     const int stride = (flat ? gridDim.x : gridDim.y) * 4;
-    const int end = flat ? tpre[K] : tile_items(ncur[blockIdx.x], nsurv[blockIdx.x], 64 * PT);
+    // the group's sizes and run, read once (kept apart from the per-item reads
+    // of the flat lists, so they are not read again per item)
+    int2 s0 = flat ? make_int2(0, 0) : make_int2(ncur[blockIdx.x], nsurv[blockIdx.x]);
+    int run0 = flat ? 0 : gd[blockIdx.x].run;
+    __asm__ volatile("" : "+s"(run0), "+s"(s0.x), "+s"(s0.y));
+    const int end = flat ? tpre[K] : tile_items(s0.x, s0.y, 64 * PT);
     int quads = 0;  // chunked tiles finalized so far (the same count in all four wavefronts)
     for (int e = w0; e < end; e += stride) {
         const int j = flat ? tgrp[e] : (int)blockIdx.x;
         const int le = flat ? e - tpre[j] : e;
-        if (le >= tile_items(ncur[j], nsurv[j], 64 * PT)) continue;  // a list's padding
-        const TileItem it = tile_item(le, ncur[j], nsurv[j], 64 * PT);
-        weight_frames_tile<T, PT>(m, gd, st, geo, ncur, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, j,
-                                  it.tile, it.chunk, it.chunks, fin, quads);
+        const int2 sz = item_sizes(ncur, nsurv, flat, j, s0);
+        if (le >= tile_items(sz.x, sz.y, 64 * PT)) continue;  // a list's padding
+        const TileItem it = tile_item(le, sz.x, sz.y, 64 * PT);
+        weight_frames_tile<T, PT>(m, gd, st, geo, sz.x, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, zrec,
+                                  j, item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks, fin, quads);
     }
 }
 

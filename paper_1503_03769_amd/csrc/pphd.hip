@@ -211,7 +211,7 @@ size_t carve(pphd_filter* f, char* base)
     f->zHs = L.take<int>(base, K * Mx * 4);
     f->zFs = L.take<char>(base, K * Mx * es);
     f->zfls = L.take<int>(base, K * Mx * 4);
-    f->zprep.nA = L.take<int>(base, (size_t)f->nruns * 4);
+    f->zprep.rec = L.take<int>(base, (size_t)f->nruns * 16);
     f->p1s = L.take<double>(base, K * f->wtiles_max * Mx * 8);
     f->p1h = L.take<int>(base, K * f->wtiles_max * Mx * 4);
     f->p1w = L.take<double>(base, K * f->wtiles_max * 8);
@@ -616,7 +616,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         f->births_pending = false;
     }
     dim3 g1((f->wtiles1 * zs + 3) / 4, K), g2((f->wtiles2 * zs + 3) / 4, K);
-    const ZPrepC zpc{ f->zprep.zs, f->zprep.orig, f->zprep.pos, f->zprep.nA };
+    const ZPrepC zpc{ f->zprep.zs, f->zprep.orig, f->zprep.pos, f->zprep.rec };
     const bool frames = f->pass_mode == PASS_FRAMES;
     const ZSorted<T> zsort{ f->zHs, (T*)f->zFs, f->zfls };
     // frame passes: (K, X) grids whose wavefronts stride over each group's
@@ -660,7 +660,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz_frames<T, PT1>), gl1, dim3(256), 0, f->stream, dm, f->gd, geo,
                                   (const T*)st.w, f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w,
-                                  f->nsurv, K, ipre1, igrp1));
+                                  f->nsurv, K, ipre1, igrp1, (const int*)f->zprep.rec));
     } else if (f->pass_mode == PASS_WRAP) {
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
@@ -683,7 +683,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight_frames<T, PT2>), gl2, dim3(256), 0, f->stream, dm, f->gd, st, geo,
                                   f->ncur, a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
-                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2, fin));
+                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2, fin, (const int*)f->zprep.rec));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
