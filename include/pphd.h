@@ -255,8 +255,11 @@ pphd_status pphd_read_resample(pphd_filter* f, int32_t* counts, double* mass_q, 
  *   prepare it); RS_EXPAND k_rs_expand; XCHG_SCATTER k_xchg_ring or
  *   k_xchg_scatter; XCHG_GATHER k_xchg_gather; BIRTH k_birth_draw and
  *   k_birth_weight (proposal 1); BIRTH_MIX the same for proposal 2;
- *   BIRTH_ORDER k_birth_draw_sort, k_birth_sort, or the births' bucket
- *   order; MLP_INFER the mixture table; ZPREP k_zprep and the work lists;
+ *   BIRTH_ORDER k_birth_draw_sort (whose launch also prepares the
+ *   measurements of the bearing-frame passes when it runs), k_birth_sort, or
+ *   the births' bucket order; MLP_INFER the mixture table; ZPREP k_zprep
+ *   (when no k_birth_draw_sort launch prepared the measurements) and the
+ *   work lists;
  *   INIT, WMAX, GEOM their kernels.  RS_TILES times nothing (kept for the
  *   numbering). */
 enum {

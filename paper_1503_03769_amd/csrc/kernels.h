@@ -888,12 +888,13 @@ struct ZSorted {
 };
 
 // one workgroup per run.  grid (runs), 256 threads.
-__global__ __launch_bounds__(256) void k_zprep(DevModel m, const double* __restrict__ Zall, int Mall,
-                                               const ZWin* __restrict__ win, ZPrep zp)
+template <int NT>
+__device__ __forceinline__ void zprep_run(const DevModel& m, const double* __restrict__ Zall, int Mall,
+                                          const ZWin* __restrict__ win, const ZPrep& zp, int run)
 {
-    __shared__ int s_cnt[4];
+    constexpr int NW = NT / 64;
+    __shared__ int s_cnt[NW];
     __shared__ int s_base;
-    const int run = blockIdx.x;
     int off = 0, M = Mall;
     if (win) {
         off = win[run].off;
@@ -903,18 +904,19 @@ __global__ __launch_bounds__(256) void k_zprep(DevModel m, const double* __restr
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // pass 1: number of frame-A measurements
     int cA = 0;
-    for (int p = threadIdx.x; p < M; p += 256) cA += fabs(Z[2 * p + 1]) > 0.5 * 3.14159265358979323846 ? 0 : 1;
+    for (int p = threadIdx.x; p < M; p += NT) cA += fabs(Z[2 * p + 1]) > 0.5 * 3.14159265358979323846 ? 0 : 1;
     cA = (int)wave_sum((double)cA);
     if (lane == 0) s_cnt[wv] = cA;
     __syncthreads();
-    const int nA = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    int nA = 0;
+    for (int w2 = 0; w2 < NW; ++w2) nA += s_cnt[w2];
     if (threadIdx.x == 0) {
         // the record the likelihood passes read in one scalar load
         *reinterpret_cast<int4*>(zp.rec + 4 * run) = make_int4(off, M, nA, 0);
         s_base = 0;
     }
-    // pass 2: stable positions, 256 measurements at a time
-    for (int p0 = 0; p0 < M; p0 += 256) {
+    // pass 2: stable positions, NT measurements at a time
+    for (int p0 = 0; p0 < M; p0 += NT) {
         __syncthreads();
         const int p = p0 + threadIdx.x;
         const bool valid = p < M;
@@ -935,8 +937,14 @@ __global__ __launch_bounds__(256) void k_zprep(DevModel m, const double* __restr
             zp.pos[(size_t)off + p] = pos;
         }
         __syncthreads();
-        if (threadIdx.x == 0) s_base += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        if (threadIdx.x == 0)
+            for (int w2 = 0; w2 < NW; ++w2) s_base += s_cnt[w2];
     }
+}
+__global__ __launch_bounds__(256) void k_zprep(DevModel m, const double* __restrict__ Zall, int Mall,
+                                               const ZWin* __restrict__ win, ZPrep zp)
+{
+    zprep_run<256>(m, Zall, Mall, win, zp, blockIdx.x);
 }
 
 // 64-lane sum left in lane 63 (other lanes hold partial sums): quad and row
@@ -2423,8 +2431,15 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
                                                           const double* __restrict__ Zall,
                                                           const double* __restrict__ taball, int Mall,
                                                           const ZWin* __restrict__ win, uint32_t step_arg,
-                                                          const uint32_t* __restrict__ dstep, int* __restrict__ borig)
+                                                          const uint32_t* __restrict__ dstep, int* __restrict__ borig,
+                                                          int K0, ZPrep zp)
 {
+    // workgroups past the K0 groups prepare the measurements of run
+    // blockIdx.x - K0 for the likelihood passes (no birth reads them)
+    if ((int)blockIdx.x >= K0) {
+        zprep_run<1024>(m, Zall, Mall, win, zp, (int)blockIdx.x - K0);
+        return;
+    }
     static_assert(!WEIGHT || 1024 * BS >= BIRTH_FUSED_MAX, "the fused form holds every birth");
     const int j = blockIdx.x;
     const Grp gr = gd[j];

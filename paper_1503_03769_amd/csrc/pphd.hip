@@ -537,6 +537,11 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     // chunks per tile: exact for one run, the maximum for a batch (waves past
     // a group's own chunk count exit at once)
     const int zs = a.win ? ZSPLIT_MAX : host_zsplit(a.M, f->mz);
+    // the measurement preparation of the frame passes rides in the births'
+    // one-workgroup-per-group launch when there is one (extra workgroups, one
+    // per run), else it has a launch of its own below
+    const int zruns = f->pass_mode == PASS_FRAMES ? f->nruns : 0;
+    bool zprep_done = false;
     if (f->births_pending) {
         // births of the measurement-driven proposals: draw, bearing order
         // (recording each birth's drawing index), weights with the geometry
@@ -569,23 +574,25 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                 if (Jmax <= BIRTH_FUSED_MAX && dm.proposal == 1) {
                     weighted = true;
                     LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                           hipLaunchKernelGGL((k_birth_draw_sort<T, 2, 1, true>), dim3(K), dim3(1024), 0, f->stream,
-                                              dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win,
-                                              f->last_step, a.dstep, f->borig));
+                           hipLaunchKernelGGL((k_birth_draw_sort<T, 2, 1, true>), dim3(K + zruns), dim3(1024), 0,
+                                              f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win,
+                                              f->last_step, a.dstep, f->borig, K, f->zprep));
+                    zprep_done = zruns > 0;
                 }
             }
             if (!weighted) {
                 if (Jmax <= 1024 * BS) {
                     if (dm.proposal == 1)
                         LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1, false>), dim3(K), dim3(1024), 0,
+                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1, false>), dim3(K + zruns), dim3(1024), 0,
                                                   f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
-                                                  a.win, f->last_step, a.dstep, f->borig));
+                                                  a.win, f->last_step, a.dstep, f->borig, K, f->zprep));
                     else
                         LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2, false>), dim3(K), dim3(1024), 0,
+                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2, false>), dim3(K + zruns), dim3(1024), 0,
                                                   f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
-                                                  a.win, f->last_step, a.dstep, f->borig));
+                                                  a.win, f->last_step, a.dstep, f->borig, K, f->zprep));
+                    zprep_done = zruns > 0;
                 } else {
                     if (dm.proposal == 1)
                         LAUNCH(f, cls,
@@ -655,8 +662,10 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         gl2 = dim3(1024);
     }
     if (f->pass_mode == PASS_FRAMES) {
-        LAUNCH(f, PPHD_K_ZPREP,
-               hipLaunchKernelGGL(k_zprep, dim3(f->nruns), dim3(256), 0, f->stream, dm, a.dz, a.M, a.win, f->zprep));
+        if (!zprep_done)
+            LAUNCH(f, PPHD_K_ZPREP,
+                   hipLaunchKernelGGL(k_zprep, dim3(f->nruns), dim3(256), 0, f->stream, dm, a.dz, a.M, a.win,
+                                      f->zprep));
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz_frames<T, PT1>), gl1, dim3(256), 0, f->stream, dm, f->gd, geo,
                                   (const T*)st.w, f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w,
