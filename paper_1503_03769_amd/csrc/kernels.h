@@ -1183,16 +1183,16 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
 #pragma unroll
     for (int i = 0; i < PT; ++i) nlw[i] += hw;
     const size_t pbase = ((size_t)j * sp.wtiles + tile) * Mmax;
+    // every partial of the tile has the exponent hw: stored once, in the
+    // first column of the tile's row
+    if (zc == 0 && lane == 0) ph[pbase] = (int)hw;
     const TileBox bx = tile_box<PT>(rho, phi, phib, base, n, lane);
     auto one = [&](int p, double zr, double zt, const double* ang) {
         T s = 0;
 #pragma unroll
         for (int i = 0; i < PT; ++i) s += fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], nlw[i]));
         const T sw = wave_sum_last(s);
-        if (lane == 63) {
-            ps[pbase + p] = (double)sw;  // frame order; k_cz_combine maps back
-            ph[pbase + p] = (int)hw;
-        }
+        if (lane == 63) ps[pbase + p] = (double)sw;  // frame order; k_cz_combine maps back
     };
     // two measurements at once: independent chains for the latency-bound
     // tiles that keep many of them
@@ -1206,9 +1206,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
         const T sw = wave_sum_last(s), tw = wave_sum_last(t);
         if (lane == 63) {
             ps[pbase + p] = (double)sw;
-            ph[pbase + p] = (int)hw;
             ps[pbase + q] = (double)tw;
-            ph[pbase + q] = (int)hw;
         }
     };
     // every nlw is >= 0 (hw is the ceiling of the tile's largest log weight).
@@ -1222,10 +1220,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
                 zr = c0 == pa ? zr0 : zs[2 * p];
                 zt = c0 == pa ? zt0 : zs[2 * p + 1];
                 need = box_needed(bx, fb, (float)zr, (float)zt, 0.0f, (float)exp2_cut<T>());
-                if (!need) {
-                    ps[pbase + p] = 0.0;
-                    ph[pbase + p] = (int)hw;
-                }
+                if (!need) ps[pbase + p] = 0.0;
             }
             uint64_t live = __ballot(need);
             while (live) {
@@ -1628,7 +1623,9 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
                 const int t = t0 + 16 * r;
                 const size_t o = ((size_t)j * wtiles + (t < nw ? t : 0)) * Mmax + pp;
                 const double x = ps[o];
-                h[r] = ph[o];
+                // the frame passes store a tile's one exponent in its row's
+                // first column
+                h[r] = ph[zpos ? o - pp : o];
                 v[r] = live && t < nw ? x : 0.0;
             }
 #pragma unroll
