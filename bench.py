@@ -38,8 +38,8 @@ def pass_bytes(counts, Mg, esz, tile=PASS_TILE):
     particle count and the measurement count of every group.
       first pass:  per particle the geometry (scaled range, two frame bearings,
                    log2 weight: 4 doubles) and the weight; per tile and
-                   measurement the partial sum and its exponent (8 + 4 bytes),
-                   per tile the weight total (8 bytes);
+                   measurement the partial sum (8 bytes), per tile the
+                   weight total and the partials' exponent (8 + 4 bytes);
       second pass: per particle the geometry (3 doubles), the weight and the
                    four CV components read, the new weight and its bearing
                    bucket (4 bytes) written; per 256-slot tile the bucket
@@ -50,7 +50,7 @@ def pass_bytes(counts, Mg, esz, tile=PASS_TILE):
     Mg = np.asarray(Mg, dtype=np.int64)
     n = int(counts.sum())
     tiles = -(-counts // tile)
-    cz = n * (32 + esz) + int((tiles * (12 * Mg + 8)).sum())
+    cz = n * (32 + esz) + int((tiles * (8 * Mg + 12)).sum())
     weight = n * (28 + 6 * esz) + int((-(-counts // 256)).sum()) * 272
     return cz, weight
 
