@@ -431,10 +431,16 @@ void fill_devmodel(pphd_filter* f)
     d.J = f->Jmax;
     d.cap = f->cap;
     d.M0 = f->M0max;
-    // bearing frames need every wrapped pair to sit at least 160 binary orders
-    // down: (pi/2 c_t)^2 > 160 (sigma_theta below about 0.1 rad)
+    // Bearing frames evaluate each residual without the 2 pi wrap.  A pair
+    // whose frame residual needs the wrap has a wrapped residual of at least
+    // pi/2, so its term is at most 2^-(pi/2 c_t)^2; the frames are exact only
+    // when every such term underflows the storage type: (pi/2 c_t)^2 above
+    // 160 in float (underflow at 2^-150; sigma_theta below about 0.1 rad) and
+    // above 1100 in double (2^-1075; sigma_theta below about 0.04 rad).
+    // Otherwise every pair takes the wrapped residual.
     const double half = 0.5 * 3.14159265358979323846 * d.ct;
-    f->pass_mode = d.kappa > 0.0 ? (half * half > 160.0 ? PASS_FRAMES : PASS_WRAP) : PASS_EXACT;
+    const double wrap_cut = f->prec == PPHD_FP64 ? 1100.0 : 160.0;
+    f->pass_mode = d.kappa > 0.0 ? (half * half > wrap_cut ? PASS_FRAMES : PASS_WRAP) : PASS_EXACT;
     d.key0 = (uint32_t)f->seed;
     d.key1 = (uint32_t)(f->seed >> 32);
     d.run = f->run;

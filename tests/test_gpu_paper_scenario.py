@@ -15,3 +15,77 @@ def test_distributed_filter_matches_full_filter(gpu):
     print(res, flush=True)
     assert abs(res["DCPPHD"] - res["PHD"]) < 0.05 * res["PHD"], res
     assert res["partPHD"] > res["DCPPHD"] and res["partPHD"] > res["PHD"], res
+
+
+def test_paper_model_fp64_update_matches_oracle(gpu):
+    """Step 2 at the section-4 sensor (sigma_theta = 0.05 rad, K = 4, r = 10)
+    in FP64 against the oracle, element by element.  Part of every group sits
+    at bearing about -3.0 rad and one extra measurement at bearing 1.5 rad
+    is more than pi/2 from every particle: its bearing residual against that
+    part needs the 2 pi wrap (|1.5 + 3.0| > pi), and its wrapped terms, near
+    2^-900, are representable in double, so C of that measurement rests on
+    exactly the pairs a wrap-free evaluation would lose."""
+    import math
+
+    import numpy as np
+
+    import oracle as orc
+    from paper_1503_03769_amd import pphd
+    from paper_1503_03769_amd.scenario import PAPER_MODEL, make_paper_scenario
+    from tests import parity as P
+
+    K, cap = 4, 1024
+    p = dict(PAPER_MODEL, clutter_rate=10.0)
+    truth, Zs = make_paper_scenario(p, 30, 1234)
+    k = max(range(1, 31), key=lambda i: (len(truth[i]), len(Zs[i])))
+    rng = np.random.default_rng(5)
+    counts = [700, 650, 720, 600]
+    X = np.zeros((4, K * cap))
+    W = np.zeros(K * cap)
+    for j, nj in enumerate(counts):
+        near = nj // 2
+        idx = rng.integers(0, len(truth[k]), near)
+        sl = slice(j * cap, j * cap + near)
+        X[0, sl] = truth[k][idx, 0] + rng.normal(0, 4, near)
+        X[1, sl] = truth[k][idx, 1] + rng.normal(0, 1, near)
+        X[2, sl] = truth[k][idx, 2] + rng.normal(0, 4, near)
+        X[3, sl] = truth[k][idx, 3] + rng.normal(0, 1, near)
+        far = nj - near
+        r = rng.uniform(90, 110, far)
+        b = rng.normal(-3.0, 0.02, far)
+        sl = slice(j * cap + near, j * cap + nj)
+        X[0, sl], X[2, sl] = r * np.cos(b), r * np.sin(b)
+        X[1, sl], X[3, sl] = rng.normal(0, 1, far), rng.normal(0, 1, far)
+        W[j * cap:j * cap + nj] = np.exp(rng.uniform(-3, 0, nj)) * 1e-3
+    n = np.array(counts, dtype=np.int32)
+    Z = np.vstack([Zs[k], [[100.0, 1.5]]])
+    phi = np.concatenate([np.arctan2(X[2, j * cap:j * cap + c], X[0, j * cap:j * cap + c])
+                          for j, c in enumerate(counts)])
+    gap = np.abs((1.5 - phi + math.pi) % (2 * math.pi) - math.pi)
+    assert gap.min() > 0.5 * math.pi
+    print(f"paper model FP64 update: M = {Z.shape[0]}, wrapped gap to the extra measurement "
+          f"{gap.min():.3f}..{gap.max():.3f} rad", flush=True)
+    f = P.make_filter(p, "fp64", cap, max_meas=64)
+    f.write_state(X, W, n, pphd.PHASE_PREDICTED)
+    f.update(Z)
+    Xg, Wg, ng = f.read_state()
+    ug = f.read_update()
+    lg = f.read_local()
+    est_g, _ = f.extract()
+    st = P.oracle_state(K, cap, X, W, n)
+    uo = orc.update(p, st, Z)
+    eo = orc.extract(p, Z.shape[0], uo)
+    fo = orc.fuse(p, Z.shape[0], eo)
+    # the extra measurement's C lives on the wrapped pairs alone, far above
+    # the 1e-300 floor of the FP64 comparison
+    assert np.all(uo["C"][:, -1] > 1e-290), uo["C"][:, -1]
+    P.check_cz(ug["C"], uo["C"], orc.kappa(p), "fp64")
+    P.check_weights(Wg, st)
+    np.testing.assert_allclose(ug["mass"], uo["mass"], rtol=1e-9)
+    np.testing.assert_allclose(ug["dW"], uo["dW"], rtol=0, atol=1e-12)
+    P.check_selection(lg["sel"], lg["zeta"], ug["mass"], ug["LT"], uo, eo, tol=1e-9)
+    assert list(est_g["label"]) == list(fo["label"])
+    assert list(est_g["votes"]) == list(fo["votes"])
+    if len(fo["label"]):
+        np.testing.assert_allclose(est_g["state"], fo["state"], rtol=1e-9, atol=1e-9)
+    f.close()
