@@ -152,7 +152,7 @@ DENSE_CASES = [
      "FP64, 8 groups, frame split at 100"),
     ("fp32", 256, (800, 1300), 200.0, 50, 256 * 150, 1, 34, 320, None, 4,
      "256 groups, lambda 200 (about 250 measurements)"),
-    ("fp32", 256, (800, 1300), 200.0, 50, 256 * 120, 1, 35, 320, (190, 70), 4,
+    ("fp32", 256, (800, 1300), 200.0, 50, 256 * 120, 1, 35, 384, (190, 70), 4,
      "256 groups, frame split at 190 (third chunk)"),
     ("fp32", 256, (800, 1300), 200.0, 50, 256 * 150, 2, 36, 320, None, 5,
      "dense-stress combination: CT 5-D, learned-mixture births, 256 groups, lambda 200"),

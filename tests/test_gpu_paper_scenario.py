@@ -19,12 +19,15 @@ def test_distributed_filter_matches_full_filter(gpu):
 
 def test_paper_model_fp64_update_matches_oracle(gpu):
     """Step 2 at the section-4 sensor (sigma_theta = 0.05 rad, K = 4, r = 10)
-    in FP64 against the oracle, element by element.  Part of every group sits
-    at bearing about -3.0 rad and one extra measurement at bearing 1.5 rad
-    is more than pi/2 from every particle: its bearing residual against that
-    part needs the 2 pi wrap (|1.5 + 3.0| > pi), and its wrapped terms, near
-    2^-900, are representable in double, so C of that measurement rests on
-    exactly the pairs a wrap-free evaluation would lose."""
+    in FP64 against the oracle, element by element.  Half of every group sits
+    around the targets of scan 18 (bearings -0.83 to -1.04 rad, ranges over
+    60 m); the other half sits at bearing about -3.0 rad.  One extra
+    measurement at bearing 1.5 rad is more than pi/2 from every particle.  Its
+    residual against the -3.0 rad part needs the 2 pi wrap (|1.5 + 3.0| > pi)
+    and wraps to about 1.78 rad, closer than the 2 rad or more that separate
+    it from the other half, so C of that measurement rests on the wrapped
+    pairs.  Their terms, near 2^-900, are representable in double: exactly the
+    pairs a wrap-free evaluation would lose."""
     import math
 
     import numpy as np
@@ -37,7 +40,7 @@ def test_paper_model_fp64_update_matches_oracle(gpu):
     K, cap = 4, 1024
     p = dict(PAPER_MODEL, clutter_rate=10.0)
     truth, Zs = make_paper_scenario(p, 30, 1234)
-    k = max(range(1, 31), key=lambda i: (len(truth[i]), len(Zs[i])))
+    k = 18
     rng = np.random.default_rng(5)
     counts = [700, 650, 720, 600]
     X = np.zeros((4, K * cap))
@@ -63,8 +66,12 @@ def test_paper_model_fp64_update_matches_oracle(gpu):
                           for j, c in enumerate(counts)])
     gap = np.abs((1.5 - phi + math.pi) % (2 * math.pi) - math.pi)
     assert gap.min() > 0.5 * math.pi
+    # the wrapped pairs (raw residual beyond pi) are the closest ones
+    wrapped = np.abs(1.5 - phi) > math.pi
+    assert wrapped.any() and gap[~wrapped].min() > gap[wrapped].max() + 0.1
     print(f"paper model FP64 update: M = {Z.shape[0]}, wrapped gap to the extra measurement "
-          f"{gap.min():.3f}..{gap.max():.3f} rad", flush=True)
+          f"{gap[wrapped].min():.3f}..{gap[wrapped].max():.3f} rad, others from {gap[~wrapped].min():.3f} rad",
+          flush=True)
     f = P.make_filter(p, "fp64", cap, max_meas=64)
     f.write_state(X, W, n, pphd.PHASE_PREDICTED)
     f.update(Z)
