@@ -28,7 +28,7 @@ PURPOSE_INIT, PURPOSE_PREDICT, PURPOSE_BIRTH, PURPOSE_RESAMPLE, PURPOSE_EXCHANGE
 class OrcModel(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("partitions", ctypes.c_int32),
-        ("births_per_step", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("births_per_step", ctypes.c_int32), ("global_cz", ctypes.c_int32),
         ("T", ctypes.c_double), ("sigma_a", ctypes.c_double),
         ("sensor_x", ctypes.c_double), ("sensor_y", ctypes.c_double),
         ("sigma_r", ctypes.c_double), ("sigma_theta", ctypes.c_double),
@@ -51,6 +51,7 @@ def model_struct(p: dict) -> OrcModel:
     m.dim = int(p.get("dim", 4))
     m.partitions = int(p["partitions"])
     m.births_per_step = int(p["births_per_step"])
+    m.global_cz = int(p.get("global_cz", 0))
     for k in ("T", "sigma_a", "sensor_x", "sensor_y", "sigma_r", "sigma_theta", "p_S", "p_D",
               "clutter_rate", "r_min", "r_max", "th_min", "th_max", "birth_mass",
               "birth_sigma_v", "init_mass", "particles_per_target", "exchange_fraction"):

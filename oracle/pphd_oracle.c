@@ -92,6 +92,28 @@ double orc_kappa(const orc_model* m)
     return m->clutter_rate / area;
 }
 
+/* The global-C reading of Eq 11 (global_cz = 1).  Eq 11 sums over one
+ * group's particles; read instead as one C_k(z) over every group, the K
+ * particle sets become K parts of a single PHD, each carrying 1/K of its
+ * mass: the initial mass and the birth mass are split over the groups
+ * (omega_0 = 1/(M K)), and a group's own weight sum estimates the target
+ * number divided by K.  Step 3's LT and Step 5's child count therefore take
+ * K times the group's mass.  With global_cz = 0 every quantity below is the
+ * paper's per-group one. */
+static double orc_birth_mass(const orc_model* m)
+{
+    return m->global_cz ? m->birth_mass / (double)m->partitions : m->birth_mass;
+}
+static double orc_init_mass(const orc_model* m)
+{
+    return m->global_cz ? m->init_mass / (double)m->partitions : m->init_mass;
+}
+/* the target number a group's mass stands for */
+static double orc_count_mass(const orc_model* m, double mass)
+{
+    return m->global_cz ? (double)m->partitions * mass : mass;
+}
+
 static double orc_wrap(double d)
 {
     /* Reading: the bearing residual is taken modulo 2*pi into [-pi, pi). */
@@ -174,7 +196,7 @@ int orc_init(const orc_model* m, int cap, uint64_t seed, uint32_t run,
             orc_draw_birth(m, seed, g, 0, ORC_INIT, run, st);
             for (int d = 0; d < m->dim; ++d) XS(X, d, g) = st[d];
             /* Reading: omega_0 = 1/M generalises to init_mass / M. */
-            W[g] = m->init_mass / (double)M0;
+            W[g] = orc_init_mass(m) / (double)M0;
         }
         n[j] = M0;
     }
@@ -255,7 +277,7 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
             double st[5];
             orc_draw_birth(m, seed, g, step, ORC_BIRTH, run, st);
             for (int d = 0; d < m->dim; ++d) XS(X, d, g) = st[d];
-            W[g] = m->birth_mass / (double)Jj;
+            W[g] = orc_birth_mass(m) / (double)Jj;
         }
         if (m->birth_proposal == 0 && orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
         n[j] = ns + Jj;
@@ -359,7 +381,7 @@ int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint
             orc_birth_turn_rate(m, seed, g, step, run, X, KC);
             int inside = x >= m->region[0] && x <= m->region[1] && y >= m->region[2] && y <= m->region[3];
             double q = orc_birth_proposal_density(m, Z, M, x, y);
-            W[g] = inside ? m->birth_mass * (1.0 / area) / ((double)Jj * q) : 0.0;
+            W[g] = inside ? orc_birth_mass(m) * (1.0 / area) / ((double)Jj * q) : 0.0;
         }
         if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
     }
@@ -376,7 +398,22 @@ int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint
 /*   mass[j]           sum_i w~_k^{i,j} after the update                      */
 /* W is overwritten with the updated weights (Eq 15).                        */
 /* Reading: C is computed per group, over the group's own particles.         */
+/* With global_cz = 1 (the global-C reading) C still holds each group's own  */
+/* C_j(z_p), but the denominator of Eq 12 is kappa + sum_j C_j(z_p) over all */
+/* groups, added in group order.                                             */
 /* ------------------------------------------------------------------------ */
+static double* orc_psi(const orc_model* m, size_t KC, const double* Z, int M, const double* X, size_t base, int nj)
+{
+    /* psi_{k,z}(x) = p_D g(z|x) for every particle/measurement pair. */
+    double* psi = (double*)malloc(sizeof(double) * (size_t)(nj > 0 ? nj : 1) * (size_t)(M > 0 ? M : 1));
+    if (!psi) return NULL;
+    for (int i = 0; i < nj; ++i)
+        for (int p = 0; p < M; ++p)
+            psi[(size_t)i * M + p] = m->p_D * orc_likelihood(m, Z[2 * p], Z[2 * p + 1],
+                                                             XS(X, 0, base + i), XS(X, 2, base + i));
+    return psi;
+}
+
 int orc_update(const orc_model* m, int cap, const double* Z, int M,
                const double* X, double* W, const int32_t* n,
                double* C, double* dW, double* dW0, double* zeta_num, double* mass)
@@ -385,16 +422,31 @@ int orc_update(const orc_model* m, int cap, const double* Z, int M,
     size_t KC = (size_t)K * (size_t)cap;
     double kappa = orc_kappa(m);
     double nu = 1.0 - m->p_D; /* nu(x) = 1 - P_D(x), from Eq 4 */
+    /* the global C of every measurement (global_cz = 1): each group's Eq 11
+     * first, then their sum */
+    double* Cg = NULL;
+    if (m->global_cz) {
+        Cg = (double*)calloc((size_t)(M > 0 ? M : 1), sizeof(double));
+        if (!Cg) return -2;
+        for (int j = 0; j < K; ++j) {
+            size_t base = (size_t)j * (size_t)cap;
+            double* psi = orc_psi(m, KC, Z, M, X, base, n[j]);
+            if (!psi) { free(Cg); return -2; }
+            for (int p = 0; p < M; ++p) {
+                double c = 0.0;
+                for (int i = 0; i < n[j]; ++i) c += psi[(size_t)i * M + p] * W[base + i];
+                C[(size_t)j * M + p] = c;
+            }
+            free(psi);
+        }
+        for (int p = 0; p < M; ++p)
+            for (int j = 0; j < K; ++j) Cg[p] += C[(size_t)j * M + p];
+    }
     for (int j = 0; j < K; ++j) {
         int nj = n[j];
         size_t base = (size_t)j * (size_t)cap;
-        /* psi_{k,z}(x) = p_D g(z|x) for every particle/measurement pair. */
-        double* psi = (double*)malloc(sizeof(double) * (size_t)(nj > 0 ? nj : 1) * (size_t)(M > 0 ? M : 1));
-        if (!psi) return -2;
-        for (int i = 0; i < nj; ++i)
-            for (int p = 0; p < M; ++p)
-                psi[(size_t)i * M + p] = m->p_D * orc_likelihood(m, Z[2 * p], Z[2 * p + 1],
-                                                                 XS(X, 0, base + i), XS(X, 2, base + i));
+        double* psi = orc_psi(m, KC, Z, M, X, base, nj);
+        if (!psi) { free(Cg); return -2; }
         /* Eq 11 */
         for (int p = 0; p < M; ++p) {
             double c = 0.0;
@@ -411,7 +463,8 @@ int orc_update(const orc_model* m, int cap, const double* Z, int M,
             double wnew = 0.0;
             for (int p = 0; p < M; ++p) {
                 /* Eq 12 and Eq 13 */
-                double G = psi[(size_t)i * M + p] / (kappa + C[(size_t)j * M + p]);
+                double den = kappa + (Cg ? Cg[p] : C[(size_t)j * M + p]);
+                double G = psi[(size_t)i * M + p] / den;
                 double dw = G * wpred;
                 wnew += dw;
                 dW[(size_t)j * M + p] += dw;                       /* Eq 16 */
@@ -428,6 +481,7 @@ int orc_update(const orc_model* m, int cap, const double* Z, int M,
         mass[j] = msum;
         free(psi);
     }
+    free(Cg);
     return 0;
 }
 
@@ -445,7 +499,7 @@ int orc_extract(const orc_model* m, int M, const double* dW, const double* zeta_
 {
     int K = m->partitions;
     for (int j = 0; j < K; ++j) {
-        double lt = floor(mass[j] + 0.5);
+        double lt = floor(orc_count_mass(m, mass[j]) + 0.5);
         int L = lt < 0 ? 0 : (lt > (double)M ? M : (int)lt);
         LT[j] = L;
         for (int p = 0; p < M; ++p) {
@@ -610,7 +664,7 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
         double mq = 0.0;
         if (Q > 0) {
             mq = ldexp((double)Q, -S);
-            double t = mq * Rj;
+            double t = orc_count_mass(m, mq) * Rj;
             t = t + 0.5;
             double Lf = floor(t);
             if (Lf > (double)cap_children) Lf = (double)cap_children;
@@ -915,7 +969,7 @@ int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t 
             }
             for (int d = 0; d < 4; ++d) XS(X, d, g) = x[d];
             orc_birth_turn_rate(m, seed, g, step, run, X, KC);
-            double gam = m->birth_mass * orc_prior_density(m, x);
+            double gam = orc_birth_mass(m) * orc_prior_density(m, x);
             W[g] = gam > 0.0 ? gam / ((double)Jj * orc_mixture_proposal_density(m, table, M, x)) : 0.0;
         }
         if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;

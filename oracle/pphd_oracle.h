@@ -27,7 +27,10 @@ typedef struct {
                                  5: coordinated-turn state [x, vx, y, vy, omega] */
     int32_t partitions;       /* K, number of processing elements / groups */
     int32_t births_per_step;  /* J, split over the K groups */
-    int32_t reserved;
+    int32_t global_cz;        /* 0: C_k(z) per group, Eq 11 as printed (each group carries the
+                                    full PHD mass);
+                                 1: C_k(z) summed over all groups before Eq 12, the groups
+                                    splitting the PHD mass (each carries 1/K of it) */
     double T, sigma_a;                              /* CV model */
     double sensor_x, sensor_y, sigma_r, sigma_theta; /* range-bearing sensor */
     double p_S, p_D;
