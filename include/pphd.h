@@ -87,7 +87,13 @@ typedef struct {
                               /*    driven mixture of Eq 6's p_k(.|Z_k) (see below);      */
                               /* 2: births drawn in pphd_update from the learned          */
                               /*    per-measurement mixtures (pphd_mlp.h)                 */
-    int32_t reserved;         /* must be 0                                                */
+    int32_t global_cz;        /* 0: C_k(z) of Eq 11 per group, each group carrying the     */
+                              /*    full PHD mass (the paper's Step 2);                    */
+                              /* 1: one C_k(z) summed over all groups of the run before    */
+                              /*    Eq 12, the groups splitting the PHD mass: initial and  */
+                              /*    birth masses are divided by K, and Step 3's LT and     */
+                              /*    Step 5's child count take K times a group's mass.      */
+                              /*    Batches need every run to have the same partitions.   */
     double birth_alpha;       /* proposals 1, 2: weight of gamma/m_b in the mixture, [0,1] */
     int32_t birth_density;    /* 0: gamma/m_b = U(region) x N(0, birth_sigma_v^2 I);       */
                               /* 1: gamma/m_b = N(birth_mean, diag(birth_std^2)), the      */

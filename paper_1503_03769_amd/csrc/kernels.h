@@ -83,7 +83,8 @@ struct Grp {
     int jl, K, g0, run;  // partition within the run, partitions of the run, run's first group, run index
     int Jj, M0;          // births per step, initial particles
     uint32_t rng_run;    // Philox run word of the run
-    int pad0;
+    int mk;              // target number per unit of a group's mass: 1, or K when the groups split one
+                         // PHD (one C(z) over all groups); Step 3's LT and Step 5's L' use mk times the mass
     double kappa, Rj;    // clutter density of the run; particles per target of the group (R/K)
 };
 
@@ -734,8 +735,10 @@ __device__ __forceinline__ int zsplit_for(int M, int mz)
 // Step 2, first pass (Eq 11): C_j(z) for every group and measurement.
 // Per wave and measurement the wave returns the scaled partial sum
 //   s = sum_i 2^(-q_i + lw_i - h),   C = 2^h s  (h an integer shift),
-// written to ps/ph[(j*wtiles + tile)*Mmax + p]; pw[j*wtiles + tile] holds the
-// tile's sum of weights.
+// written to ps[(j*wtiles + tile)*Mmax + p] with its shift at the same index
+// of ph (one shift per (tile, measurement)); pw[j*wtiles + tile] holds the
+// tile's sum of weights.  The bearing-frame pass (k_cz_frames) has one shift
+// per tile and writes it only at column 0 of the tile's row of ph.
 // EXACT = false (kappa > 0): h = ceil(max_i lw_i) of the wave, a bound that
 //   needs no per-pair work; a term lost to float underflow is below
 //   2^-126 w_i, far under the 1e-5 kappa tolerance of C.
@@ -1579,8 +1582,63 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
 // sum dW) is the closed form of the updated mass (the sums of Eq 8 swapped);
 // the exact count LT differs from LT_c by at most one, so the candidates
 // always cover it.  zflag[p] = 1 + rank, or 0.
+// With zS (one C over all groups of the run) the workgroup only stores each
+// measurement's (S, H) of its group, and C = 2^H S; k_cz_global does the rest.
 // grid (K), 1024 threads, dynamic LDS Mmax doubles.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void combine_candidates(const DevModel& m, const Grp& gr, int j, int M, int nw,
+                                                   const double* __restrict__ pw, int wtiles,
+                                                   const double* __restrict__ sm_dw, int zoff,
+                                                   const int* __restrict__ zpos, ZSorted<T> zsort, size_t zb,
+                                                   int* __restrict__ zflag, int* __restrict__ cand,
+                                                   int* __restrict__ ncand)
+{
+    __shared__ double s_red[16];
+    __shared__ int s_redi[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
+    double wsum = 0.0;
+    for (int t = tid; t < nw; t += 1024) wsum += pw[(size_t)j * wtiles + t];
+    double dsum = 0.0;
+    int pos = 0;
+    for (int q = tid; q < M; q += 1024) {
+        dsum += sm_dw[q];
+        pos += sm_dw[q] > 0.0 ? 1 : 0;
+    }
+    dsum = wave_sum(dsum);
+    wsum = wave_sum(wsum);
+    pos = (int)wave_sum((double)pos);
+    if (lane == 0) {
+        s_red[wv] = m.nu * wsum + dsum;
+        s_redi[wv] = pos;
+    }
+    __syncthreads();
+    double mass_c = 0.0;
+    int npos = 0;
+    for (int w2 = 0; w2 < 16; ++w2) {
+        mass_c += s_red[w2];
+        npos += s_redi[w2];
+    }
+    const double lt = floor((double)gr.mk * mass_c + 0.5);
+    const int LTc = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
+    const int nc = LTc + 1 < npos ? LTc + 1 : npos;
+    if (tid == 0) ncand[j] = nc;
+    for (int q = tid; q < M; q += 1024) {
+        const double v = sm_dw[q];
+        if (!(v > 0.0)) continue;
+        int rank = 0;
+        for (int r = 0; r < M; ++r) {
+            const double u = sm_dw[r];
+            rank += (u > v || (u == v && r < q)) ? 1 : 0;
+        }
+        if (rank < nc) {
+            cand[zb + rank] = q;
+            zflag[zb + q] = rank + 1;
+            if (zpos) zsort.flag[zb + zpos[zoff + q]] = rank + 1;
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __restrict__ gd,
                                                      const int* __restrict__ ncur, int Mall,
@@ -1591,11 +1649,9 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
                                                      int* __restrict__ zH, T* __restrict__ zF,
                                                      double* __restrict__ zC, double* __restrict__ zdW,
                                                      int* __restrict__ zflag, int* __restrict__ cand,
-                                                     int* __restrict__ ncand)
+                                                     int* __restrict__ ncand, double* __restrict__ zS)
 {
     extern __shared__ double sm_dw[];
-    __shared__ double s_red[16];
-    __shared__ int s_redi[16];
     const int j = blockIdx.x;
     const Grp gr = gd[j];
     const int M = zview(gr, win, nullptr, Mall).M;
@@ -1658,63 +1714,109 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
             } else {
                 H = 0;
             }
-            zH[zb + p] = H;
-            zF[zb + p] = (T)F;
-            zC[zb + p] = C;
-            zdW[zb + p] = dW;
-            zflag[zb + p] = 0;
-            sm_dw[p] = dW;
-            if (zpos) {
-                zsort.H[zb + pp] = H;
-                zsort.F[zb + pp] = (T)F;
-                zsort.flag[zb + pp] = 0;
+            if (zS) {
+                // one C over all groups: this group's (S, H) for k_cz_global
+                zS[zb + p] = S;
+                zH[zb + p] = H;
+                zC[zb + p] = C;
+            } else {
+                zH[zb + p] = H;
+                zF[zb + p] = (T)F;
+                zC[zb + p] = C;
+                zdW[zb + p] = dW;
+                zflag[zb + p] = 0;
+                sm_dw[p] = dW;
+                if (zpos) {
+                    zsort.H[zb + pp] = H;
+                    zsort.F[zb + pp] = (T)F;
+                    zsort.flag[zb + pp] = 0;
+                }
             }
         }
         // wavefront 0 has read this chunk's pairs before any wavefront writes
         // the next chunk's
         __syncthreads();
     }
-    double wsum = 0.0;
-    for (int t = tid; t < nw; t += 1024) wsum += pw[(size_t)j * wtiles + t];
+    if (zS) return;
     __syncthreads();
-    double dsum = 0.0;
-    int pos = 0;
-    for (int q = tid; q < M; q += 1024) {
-        dsum += sm_dw[q];
-        pos += sm_dw[q] > 0.0 ? 1 : 0;
-    }
-    dsum = wave_sum(dsum);
-    wsum = wave_sum(wsum);
-    pos = (int)wave_sum((double)pos);
-    if (lane == 0) {
-        s_red[wv] = m.nu * wsum + dsum;
-        s_redi[wv] = pos;
+    combine_candidates<T>(m, gr, j, M, nw, pw, wtiles, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
+}
+
+// ---------------------------------------------------------------------------
+// One C(z) over all groups of a run (the global-C reading of Eq 11): for
+// every measurement of group j's run, the groups' pairs (S_q, H_q) from
+// k_cz_combine give
+//   H = max H_q over the groups with S_q > 0,  S = sum_q S_q 2^(H_q - H)
+// (lanes over the groups, one wavefront tree sum), and group j takes
+//   F = 1/(kappa 2^-H + S) = 2^H/(kappa + C),  dW_j = S_j 2^(H_j - H) F = C_j/(kappa + C)
+// with C = 2^H S, so the second pass divides every term by kappa + C.  The
+// group's candidate labels then follow as in k_cz_combine.  Every group of a
+// run forms the same H and S in the same order.
+// grid (K), 1024 threads, dynamic LDS Mmax doubles.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_cz_global(DevModel m, const Grp* __restrict__ gd,
+                                                    const int* __restrict__ ncur, int Mall,
+                                                    const ZWin* __restrict__ win, const int* __restrict__ zpos,
+                                                    ZSorted<T> zsort, int Mmax, int wtiles, int WT,
+                                                    const double* __restrict__ pw, const double* __restrict__ zS,
+                                                    const int* __restrict__ zHg, int* __restrict__ zH,
+                                                    T* __restrict__ zF, double* __restrict__ zdW,
+                                                    int* __restrict__ zflag, int* __restrict__ cand,
+                                                    int* __restrict__ ncand)
+{
+    extern __shared__ double sm_dw[];
+    const int j = blockIdx.x;
+    const Grp gr = gd[j];
+    const int M = zview(gr, win, nullptr, Mall).M;
+    const int zoff = win ? win[gr.run].off : 0;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
+    const size_t zb = (size_t)j * Mmax;
+    for (int p = wv; p < M; p += 16) {
+        int hl = -2147483647 - 1;
+        for (int q0 = 0; q0 < gr.K; q0 += 64) {
+            const int q = q0 + lane;
+            if (q < gr.K) {
+                const size_t o = (size_t)(gr.g0 + q) * Mmax + p;
+                if (zS[o] > 0.0) hl = zHg[o] > hl ? zHg[o] : hl;
+            }
+        }
+        const int H = wave_max(hl);
+        double sl = 0.0;
+        for (int q0 = 0; q0 < gr.K; q0 += 64) {
+            const int q = q0 + lane;
+            if (q < gr.K) {
+                const size_t o = (size_t)(gr.g0 + q) * Mmax + p;
+                if (zS[o] > 0.0) sl += ldexp(zS[o], zHg[o] - H);
+            }
+        }
+        const double S = wave_sum(sl);
+        if (lane == 0) {
+            const double Sj = zS[zb + p];
+            double F = 0.0, dW = 0.0;
+            int Hs = 0;
+            if (S > 0.0) {
+                const double D = ldexp(gr.kappa, -H) + S;
+                F = 1.0 / D;
+                dW = Sj > 0.0 ? ldexp(Sj, zHg[zb + p] - H) / D : 0.0;
+                Hs = H;
+            }
+            zH[zb + p] = Hs;
+            zF[zb + p] = (T)F;
+            zdW[zb + p] = dW;
+            zflag[zb + p] = 0;
+            sm_dw[p] = dW;
+            if (zpos) {
+                const int pp = zpos[zoff + p];
+                zsort.H[zb + pp] = Hs;
+                zsort.F[zb + pp] = (T)F;
+                zsort.flag[zb + pp] = 0;
+            }
+        }
     }
     __syncthreads();
-    double mass_c = 0.0;
-    int npos = 0;
-    for (int w2 = 0; w2 < 16; ++w2) {
-        mass_c += s_red[w2];
-        npos += s_redi[w2];
-    }
-    const double lt = floor(mass_c + 0.5);
-    const int LTc = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
-    const int nc = LTc + 1 < npos ? LTc + 1 : npos;
-    if (tid == 0) ncand[j] = nc;
-    for (int q = tid; q < M; q += 1024) {
-        const double v = sm_dw[q];
-        if (!(v > 0.0)) continue;
-        int rank = 0;
-        for (int r = 0; r < M; ++r) {
-            const double u = sm_dw[r];
-            rank += (u > v || (u == v && r < q)) ? 1 : 0;
-        }
-        if (rank < nc) {
-            cand[zb + rank] = q;
-            zflag[zb + q] = rank + 1;
-            if (zpos) zsort.flag[zb + zpos[zoff + q]] = rank + 1;
-        }
-    }
+    const int nw = (ncur[j] + WT - 1) / WT;
+    combine_candidates<T>(m, gr, j, M, nw, pw, wtiles, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
 }
 
 // ---------------------------------------------------------------------------
@@ -2016,7 +2118,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     }
     __syncthreads();
     const double ms = s_ms, mm = s_mm;
-    const double lt = floor(ms + 0.5);
+    const double lt = floor((double)gd[j].mk * ms + 0.5);
     const int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
     const int nc = ncand[j];
     const int nsel = LT < nc ? LT : nc;
@@ -2545,11 +2647,11 @@ __device__ __forceinline__ long long points_below(uint64_t c, uint64_t Q, long l
     return m0;
 }
 
-// L' = floor(N R_j + 0.5) with two separate roundings (no fused multiply-add)
-__device__ __forceinline__ double children_count(double mq, double Rj)
+// L' = floor((mk N) R_j + 0.5) with separate roundings (no fused multiply-add)
+__device__ __forceinline__ double children_count(double mq, int mk, double Rj)
 {
 #pragma clang fp contract(off)
-    double t = mq * Rj;
+    double t = ((double)mk * mq) * Rj;
     t = t + 0.5;
     return floor(t);
 }
@@ -2656,7 +2758,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     double mq = 0.0;
     if (Qd > 0.0) {
         mq = ldexp(Qd, -S);
-        double Lf = children_count(mq, gr.Rj);
+        double Lf = children_count(mq, gr.mk, gr.Rj);
         const double lim = (double)(m.cap - Jj);
         bool clamped = false;
         if (Lf > lim) {

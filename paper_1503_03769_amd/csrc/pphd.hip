@@ -128,6 +128,8 @@ struct pphd_filter {
     int *zH = nullptr, *zflag = nullptr, *cand = nullptr, *ncand = nullptr;
     void* zF = nullptr;
     double *zC = nullptr, *zdW = nullptr;
+    double* zS = nullptr;  // (S, H) of each group's C before the sum over groups (global_cz)
+    int* zHg = nullptr;
     double *p2mass = nullptr, *p2max = nullptr, *p2zeta = nullptr;
     double *geo_rho = nullptr, *geo_phi = nullptr, *geo_phib = nullptr, *geo_lw = nullptr;
     int pass_mode = 0;  // PASS_FRAMES / PASS_WRAP / PASS_EXACT, from the model
@@ -181,7 +183,8 @@ bool model_ok(const pphd_model* m, std::string& why, bool batch = false)
     if (m->birth_density == 1)
         for (int d = 0; d < 4; ++d)
             if (!(m->birth_std[d] > 0)) { why = "birth_std must be > 0"; return false; }
-    if (m->reserved != 0 || m->reserved2 != 0) { why = "reserved fields must be 0"; return false; }
+    if (m->global_cz != 0 && m->global_cz != 1) { why = "global_cz must be 0 or 1"; return false; }
+    if (m->reserved2 != 0) { why = "reserved fields must be 0"; return false; }
     if (!(m->region[1] > m->region[0]) || !(m->region[3] > m->region[2])) { why = "empty surveillance region"; return false; }
     return true;
 }
@@ -219,6 +222,8 @@ size_t carve(pphd_filter* f, char* base)
     f->zF = L.take<char>(base, K * Mx * es);
     f->zC = L.take<double>(base, K * Mx * 8);
     f->zdW = L.take<double>(base, K * Mx * 8);
+    f->zS = L.take<double>(base, K * Mx * 8);
+    f->zHg = L.take<int>(base, K * Mx * 4);
     f->zflag = L.take<int>(base, K * Mx * 4);
     f->cand = L.take<int>(base, K * Mx * 4);
     f->ncand = L.take<int>(base, K * 4);
@@ -290,8 +295,12 @@ bool runs_ok(const pphd_model* m, const pphd_run_desc* runs, int nruns, std::str
         if (!(d.clutter_rate >= 0)) { why = "run clutter_rate must be >= 0"; return false; }
         if (!(d.particles_per_target > 0)) { why = "run particles_per_target must be > 0"; return false; }
         if (d.reserved != 0) { why = "run reserved field must be 0"; return false; }
+        // the split masses are divided by one partition count for all runs
+        if (m->global_cz && d.partitions != runs[0].partitions) {
+            why = "global_cz needs every run to have the same partitions";
+            return false;
+        }
     }
-    (void)m;
     return true;
 }
 
@@ -329,6 +338,7 @@ void set_geometry(pphd_filter* f, const pphd_model* m, const pphd_run_desc* runs
             g.rng_run = d.run_id;
             g.kappa = d.clutter_rate / area;
             g.Rj = d.particles_per_target / (double)d.partitions;
+            g.mk = m->global_cz ? d.partitions : 1;
             f->Jmax = std::max(f->Jmax, g.Jj);
             f->M0max = std::max(f->M0max, g.M0);
             f->hgd.push_back(g);
@@ -396,13 +406,16 @@ void fill_devmodel(pphd_filter* f)
     // the smallest clutter density of the runs decides the pass mode
     d.kappa = f->hgd[0].kappa;
     for (const Grp& g : f->hgd) d.kappa = std::min(d.kappa, g.kappa);
-    d.birth_mass = m.birth_mass;
+    // one C over all groups: the groups split the PHD, each carrying 1/K of
+    // the initial and birth masses (every run has the same K)
+    const double share = m.global_cz ? (double)f->hgd[0].K : 1.0;
+    d.birth_mass = m.global_cz ? m.birth_mass / share : m.birth_mass;
     d.reg0 = m.region[0];
     d.reg1 = m.region[1];
     d.reg2 = m.region[2];
     d.reg3 = m.region[3];
     d.sigma_v = m.birth_sigma_v;
-    d.init_mass = m.init_mass;
+    d.init_mass = m.global_cz ? m.init_mass / share : m.init_mass;
     d.Rj = f->hgd[0].Rj;
     d.xfrac = m.exchange_fraction;
     const double c = std::sqrt(std::log2(std::exp(1.0)) / 2.0);
@@ -685,11 +698,18 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                hipLaunchKernelGGL((k_cz<T, PT1, PASS_EXACT>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
                                   (const T*)st.w, f->ncur, a.dz, a.M, a.win, Mx, s1, f->p1s, f->p1h, f->p1w));
     }
+    const bool global = f->model.global_cz != 0;
     LAUNCH(f, PPHD_K_CZ_COMBINE,
            hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
                               f->gd, f->ncur, a.M, a.win, frames ? f->zprep.pos : nullptr, zsort, Mx, f->wtiles1,
-                              f->wt1, f->p1s, f->p1h, f->p1w, f->zH,
-                              (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand));
+                              f->wt1, f->p1s, f->p1h, f->p1w, global ? f->zHg : f->zH,
+                              (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand, global ? f->zS : nullptr));
+    if (global)
+        LAUNCH(f, PPHD_K_CZ_COMBINE,
+               hipLaunchKernelGGL((k_cz_global<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
+                                  f->gd, f->ncur, a.M, a.win, frames ? f->zprep.pos : nullptr, zsort, Mx, f->wtiles1,
+                                  f->wt1, (const double*)f->p1w, (const double*)f->zS, (const int*)f->zHg, f->zH,
+                                  (T*)f->zF, f->zdW, f->zflag, f->cand, f->ncand));
     // frame passes with wave tiles of whole 256-slot tiles finalize the
     // weights themselves (k_wfinal only for the other passes)
     const bool fused = frames && PT2 % 4 == 0;

@@ -46,7 +46,7 @@ class pphd_model(ctypes.Structure):
         ("birth_mass", ctypes.c_double), ("region", ctypes.c_double * 4),
         ("birth_sigma_v", ctypes.c_double), ("init_mass", ctypes.c_double),
         ("particles_per_target", ctypes.c_double), ("exchange_fraction", ctypes.c_double),
-        ("birth_proposal", ctypes.c_int32), ("reserved", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
+        ("birth_proposal", ctypes.c_int32), ("global_cz", ctypes.c_int32), ("birth_alpha", ctypes.c_double),
         ("birth_density", ctypes.c_int32), ("reserved2", ctypes.c_int32),
         ("birth_mean", ctypes.c_double * 4), ("birth_std", ctypes.c_double * 4),
         ("sigma_w", ctypes.c_double), ("birth_sigma_w", ctypes.c_double),
@@ -163,6 +163,7 @@ def model_struct(p: dict, precision: int) -> pphd_model:
     for i in range(4):
         m.region[i] = float(p["region"][i])
     m.birth_proposal = int(p.get("birth_proposal", 0))
+    m.global_cz = int(p.get("global_cz", 0))
     m.birth_alpha = float(p.get("birth_alpha", 1.0))
     m.birth_density = int(p.get("birth_density", 0))
     for i in range(4):

@@ -76,3 +76,26 @@ def test_learned_proposal_declarations_and_config_errors():
                 pphd.pphd_mlp_config(4096, 8192, -1.0, 0.9, 0.999, 1e-8)):
         with pytest.raises(pphd.PphdError):
             pphd.pphd_mlp_workspace_size(bad)
+
+
+def test_global_cz_argument_checks():
+    """The global-C reading is 0 or 1, and a batch using it needs every run
+    to have the same partition count (the split masses use one K)."""
+    from paper_1503_03769_amd import pphd
+    from paper_1503_03769_amd.scenario import BASE_MODEL
+    assert pphd.pphd_workspace_size(pphd.model_struct(dict(BASE_MODEL, partitions=4, global_cz=1), pphd.PPHD_FP32),
+                                    4000, 64) > 0
+    with pytest.raises(pphd.PphdError) as e:
+        pphd.pphd_workspace_size(pphd.model_struct(dict(BASE_MODEL, partitions=4, global_cz=2), pphd.PPHD_FP32),
+                                 4000, 64)
+    assert e.value.code == pphd.PPHD_EINVAL
+    runs = [dict(partitions=4, births_per_step=800, clutter_rate=10.0, particles_per_target=2000.0, run_id=0),
+            dict(partitions=2, births_per_step=800, clutter_rate=10.0, particles_per_target=2000.0, run_id=1)]
+    t = pphd.run_table(runs)
+    for gz, ok in ((0, True), (1, False)):
+        m = pphd.model_struct(dict(BASE_MODEL, partitions=1, global_cz=gz), pphd.PPHD_FP32)
+        if ok:
+            assert pphd.pphd_batch_workspace_size(m, ctypes.addressof(t), 2, 2048, 64) > 0
+        else:
+            with pytest.raises(pphd.PphdError):
+                pphd.pphd_batch_workspace_size(m, ctypes.addressof(t), 2, 2048, 64)
