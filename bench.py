@@ -9,8 +9,14 @@ Prints one JSON line:
   value        particle x measurement updates per second (sum over timed steps
                of N_k * M_k, divided by the timed wall time)
   steps_per_s  filter steps per second
-  roofline     the dominant kernel against the VALU issue rate
-  cpu_baseline the FP64 oracle on the host for a bounded sample of the run
+  steps_per_s_pcie  the same steps with every Z_k uploaded from host memory
+               through pphd_update and the fused estimates downloaded with
+               pphd_extract (PCIe included; not the headline)
+  roofline     the dominant kernel against HBM bandwidth
+  variants     the same workload in FP64 storage, and with births drawn from
+               the birth density itself (uniform births, proposal 0)
+  cpu_baseline the FP64 oracle on the host for a bounded sample of the run,
+               on all the host cores the process may use and on one thread
 """
 import argparse
 import hashlib
@@ -29,6 +35,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # Wave tile of the frame passes (64 lanes x 4 particles per lane, the tuned shape).
 PASS_TILE = 256
+BIRTH_PROPOSALS = {0: "birth density (uniform over the region)", 1: "measurement-driven mixture",
+                   2: "learned per-measurement mixtures"}
 # Kernel sources a stored counter summary was taken on.
 KERNEL_SOURCES = ("paper_1503_03769_amd/csrc/kernels.h", "paper_1503_03769_amd/csrc/pphd.hip")
 
@@ -93,6 +101,8 @@ def parse():
                     help="bound on the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-timing-pass", action="store_true",
                     help="skip the HIP-event pass (for profiler runs)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP64 and uniform-birth variants of the workload")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch workloads: skip the run-by-run comparison pass (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -153,9 +163,9 @@ def main():
         mlp_info = {"train_s": time.perf_counter() - t0, "train_steps": int(len(losses)),
                     "final_loss": float(np.mean(losses[-50:])), "pairs": 1 << 20}
 
-    def make():
-        f = pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, args.run)
-        if net is not None:
+    def make(q=p, pr=prec):
+        f = pphd.Filter(q, pr, w["cap"], w["max_meas"], seed, args.run)
+        if net is not None and int(q.get("birth_proposal", 0)) == 2:
             f.attach_mlp(net)
         return f
 
@@ -166,19 +176,60 @@ def main():
         f.resample(k)
         f.exchange(k)
 
+    def step_pcie(f, k):
+        # Z_k from host memory (copied through the library's pinned staging),
+        # the fused estimates back to host memory (a synchronising download)
+        f.predict(k)
+        f.update(Z[k])
+        f.extract()
+        f.resample(k)
+        f.exchange(k)
+
+    def timed(q=p, pr=prec, one=step):
+        f = make(q, pr)
+        f.init()
+        for k in range(1, args.warmup + 1):
+            one(f, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup + 1, total + 1):
+            one(f, k)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        f.close()
+        return el
+
+    def counted(q, pr):
+        """particle x measurement pairs of the timed steps (the same run,
+        bit-identical, with the particle counts read after every predict)"""
+        f = make(q, pr)
+        f.init()
+        n_pairs = 0
+        for k in range(1, total + 1):
+            f.predict(k)
+            if k > args.warmup:
+                n_pairs += int(f.read_counts().sum()) * Ms[k]
+            f.update(zall[offs[k]:offs[k + 1]])
+            f.extract_device(est_dev[k], nest_dev[k:k + 1], cap_est)
+            f.resample(k)
+            f.exchange(k)
+        f.close()
+        return n_pairs
+
+    def run_ospa():
+        nest = nest_dev.cpu().numpy()
+        raw = est_dev.cpu().numpy()
+        d = []
+        for k in range(args.warmup + 1, total + 1):
+            recs = np.frombuffer(raw[k].tobytes(), dtype=pphd.ESTIMATE_DTYPE)[:min(int(nest[k]), cap_est)]
+            d.append(ospa(positions(recs["state"]), positions(truth[k])))
+        return float(np.mean(d))
+
     # ---- pass A: timed ------------------------------------------------------
-    f = make()
-    f.init()
-    for k in range(1, args.warmup + 1):
-        step(f, k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup + 1, total + 1):
-        step(f, k)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    f.close()
+    elapsed = timed()
     ms_per_step = elapsed * 1e3 / args.steps
+    # ---- the same steps with host measurement sets and host estimates -------
+    elapsed_pcie = timed(one=step_pcie)
 
     # ---- pass B: same run, per-kernel HIP-event times and particle counts ----
     kern = {}
@@ -206,12 +257,23 @@ def main():
         g.close()
 
     # estimates of the timed run -> OSPA against the truth
-    nest = nest_dev.cpu().numpy()
-    raw = est_dev.cpu().numpy()
-    ospas = []
-    for k in range(args.warmup + 1, total + 1):
-        recs = np.frombuffer(raw[k].tobytes(), dtype=pphd.ESTIMATE_DTYPE)[:min(int(nest[k]), cap_est)]
-        ospas.append(ospa(positions(recs["state"]), positions(truth[k])))
+    ospa_mean = run_ospa()
+    # ---- variants of the same workload: FP64 storage, uniform births -------
+    variants = {}
+    if not args.no_variants:
+        vlist = []
+        if prec == pphd.PPHD_FP32:
+            vlist.append(("fp64", p, pphd.PPHD_FP64, "FP64 storage and likelihoods (the same run)"))
+        if int(p.get("birth_proposal", 0)) != 0:
+            vlist.append(("uniform_births", dict(p, birth_proposal=0), prec,
+                          "births drawn from the birth density itself (uniform position, weight m_b/J_j)"))
+        for name, q, pr, what in vlist:
+            el = timed(q, pr)
+            n_pairs = counted(q, pr)
+            variants[name] = {"value": n_pairs / el, "unit": "pair-updates/s", "ms_per_step": el * 1e3 / args.steps,
+                              "steps_per_s": args.steps / el, "dtype": "f64" if pr == pphd.PPHD_FP64 else "f32",
+                              "birth_proposal": int(q.get("birth_proposal", 0)), "ospa_mean": run_ospa(),
+                              "what": what}
 
     value = float(sum(pairs)) / elapsed if pairs else None
     line = {
@@ -223,6 +285,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "steps_per_s": 1e3 / ms_per_step,
+        "steps_per_s_pcie": args.steps / elapsed_pcie,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -230,6 +293,8 @@ def main():
         "data": "synthetic (seeded truth tracks, detections and Poisson clutter)",
         "config": {
             "workload": args.workload,
+            "birth_proposal": int(p.get("birth_proposal", 0)),
+            "birth_proposal_name": BIRTH_PROPOSALS[int(p.get("birth_proposal", 0))],
             "partitions": int(p["partitions"]),
             "targets": int(w["n_targets"]),
             "clutter_rate": float(p["clutter_rate"]),
@@ -239,9 +304,11 @@ def main():
             "mean_measurements": float(np.mean([Ms[k] for k in range(args.warmup + 1, total + 1)])),
             "parallelism": f"{int(p['partitions'])} particle partitions on one GPU",
         },
-        "ospa_mean": float(np.mean(ospas)),
+        "ospa_mean": ospa_mean,
         "ospa_params": {"p": 1, "c": 100.0},
     }
+    if variants:
+        line["variants"] = variants
     if kern:
         per = {name: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for name, (ms, n) in kern.items() if n}
         line["kernels"] = per
@@ -480,10 +547,29 @@ def bench_batch(args, w):
     return line
 
 
-def cpu_baseline(p, w, truth, Z, seed, run, budget_s, mlp_theta=None):
-    """The FP64 oracle, single thread, on the same workload from t = 0 for as
-    many steps as fit in about budget_s seconds."""
+def host_cpu():
+    """The host's CPU model name, logical CPU count and the CPUs this process
+    may run on."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def oracle_sample(p, w, Z, seed, run, budget_s, threads, mlp_theta=None):
+    """The FP64 oracle on the same run from t = 0 for as many steps as fit in
+    about budget_s seconds, with its per-group loops on `threads` threads."""
     import oracle as orc
+    orc.set_threads(threads)
     o = orc.OracleFilter(p, w["cap"], seed, run, mlp_theta=mlp_theta)
     pairs = 0
     steps = 0
@@ -495,17 +581,21 @@ def cpu_baseline(p, w, truth, Z, seed, run, budget_s, mlp_theta=None):
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    cpu = "unknown"
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                cpu = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": pairs / el, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} steps of the same run (seed {seed}), FP64 C oracle, one thread",
-            "steps_per_s": steps / el, "cpu": cpu}
+    return pairs / el, steps / el, steps
+
+
+def cpu_baseline(p, w, truth, Z, seed, run, budget_s, mlp_theta=None):
+    """The FP64 oracle as it stands (plain C, one group per OpenMP thread) on
+    the host: on every CPU this process may use (the reported value), and on
+    one thread, each for about half of budget_s."""
+    model, nproc, usable = host_cpu()
+    v_all, s_all, n_all = oracle_sample(p, w, Z, seed, run, 0.5 * budget_s, usable, mlp_theta)
+    v_one, s_one, n_one = oracle_sample(p, w, Z, seed, run, 0.5 * budget_s, 1, mlp_theta)
+    return {"value": v_all, "unit": "pair-updates/s", "cores": usable, "kind": "oracle",
+            "sample": f"first {n_all} steps of the same run (seed {seed}), FP64 C oracle, its groups on "
+                      f"{usable} threads",
+            "steps_per_s": s_all, "cpu": model, "nproc": nproc, "usable_cpus": usable,
+            "single_thread": {"value": v_one, "steps_per_s": s_one, "steps": n_one, "cores": 1}}
 
 
 if __name__ == "__main__":

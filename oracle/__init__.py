@@ -83,6 +83,8 @@ def lib():
         M = ctypes.POINTER(OrcModel)
         c_int, u32, u64 = ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64
         L.orc_philox4x32_10.argtypes = [U, U, U]
+        L.orc_set_threads.argtypes = [c_int]
+        L.orc_threads.restype = c_int
         L.orc_u53.argtypes = [u32, u32]
         L.orc_u53.restype = ctypes.c_double
         L.orc_kappa.argtypes = [M]
@@ -132,6 +134,15 @@ def philox(ctr, key):
     o = (ctypes.c_uint32 * 4)()
     lib().orc_philox4x32_10(c, k, o)
     return [int(o[i]) for i in range(4)]
+
+
+def set_threads(n):
+    """Threads of the per-group loops (the results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads():
+    return int(lib().orc_threads())
 
 
 def u53(a, b):

@@ -1,4 +1,5 @@
-"""Build the oracle shared library (plain C, gcc, FP64, no fused multiply-add).
+"""Build the oracle shared library (plain C, gcc, FP64, no fused multiply-add,
+OpenMP over independent groups).
 
 Test infrastructure only: the oracle is built so that the test suite, the
 smoke check and the benchmark's CPU-baseline leg can call it.
@@ -13,7 +14,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fopenmp", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

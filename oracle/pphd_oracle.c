@@ -10,6 +10,7 @@
  *
  * Readings of points the paper leaves open are marked "Reading:".
  */
+#include <omp.h>
 #include "pphd_oracle.h"
 
 #include <math.h>
@@ -58,6 +59,16 @@ static void orc_block(uint64_t seed, uint32_t c0, uint32_t step, uint32_t purpos
 
 /* Uniform on (0, 1]: the 53-bit integer formed from all of a and the top 21
  * bits of b, plus one, times 2^-53 (exact in FP64). */
+/* Threads of the per-group loops (OpenMP; results do not depend on it). */
+void orc_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+int orc_threads(void)
+{
+    return omp_get_max_threads();
+}
+
 double orc_u53(uint32_t a, uint32_t b)
 {
     uint64_t k = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
@@ -217,10 +228,15 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
     /* Reading: the gain column per axis is [T^2/2, T] (the paper prints 1,
      * which equals T at T = 1). */
     double G[4][2] = { { T * T / 2, 0 }, { T, 0 }, { 0, T * T / 2 }, { 0, T } };
+    for (int j = 0; j < K; ++j)
+        if (n[j] + orc_births_in_partition(m, j) > cap) return -3;
+    /* groups are independent: one thread per group (results do not depend
+     * on the thread count) */
+    int err = 0;
+#pragma omp parallel for schedule(dynamic) reduction(min : err)
     for (int j = 0; j < K; ++j) {
         int Jj = orc_births_in_partition(m, j);
         int ns = n[j];
-        if (ns + Jj > cap) return -3;
         /* Survivors, Eq 5 with proposal q = f and no spawning:
          * x~ = F x + Gamma (sigma_a * nu), weight phi/q * w = p_S * w. */
         for (int s = 0; s < ns; ++s) {
@@ -279,10 +295,10 @@ int orc_predict(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint3
             for (int d = 0; d < m->dim; ++d) XS(X, d, g) = st[d];
             W[g] = orc_birth_mass(m) / (double)Jj;
         }
-        if (m->birth_proposal == 0 && orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
+        if (m->birth_proposal == 0 && orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) err = -2;
         n[j] = ns + Jj;
     }
-    return 0;
+    return err;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -346,10 +362,13 @@ int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint
     int K = m->partitions;
     size_t KC = (size_t)K * (size_t)cap;
     double area = (m->region[1] - m->region[0]) * (m->region[3] - m->region[2]);
+    for (int j = 0; j < K; ++j)
+        if (n[j] < orc_births_in_partition(m, j)) return -1;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic) reduction(min : err)
     for (int j = 0; j < K; ++j) {
         int Jj = orc_births_in_partition(m, j);
         int ns = n[j] - Jj;
-        if (ns < 0) return -1;
         for (int b = 0; b < Jj; ++b) {
             uint32_t g = (uint32_t)(j * cap + ns + b);
             uint32_t a[4], v[4], c[4];
@@ -383,9 +402,9 @@ int orc_birth_from_measurements(const orc_model* m, int cap, uint32_t step, uint
             double q = orc_birth_proposal_density(m, Z, M, x, y);
             W[g] = inside ? orc_birth_mass(m) * (1.0 / area) / ((double)Jj * q) : 0.0;
         }
-        if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
+        if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) err = -2;
     }
-    return 0;
+    return err;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -425,13 +444,15 @@ int orc_update(const orc_model* m, int cap, const double* Z, int M,
     /* the global C of every measurement (global_cz = 1): each group's Eq 11
      * first, then their sum */
     double* Cg = NULL;
+    int err = 0;
     if (m->global_cz) {
         Cg = (double*)calloc((size_t)(M > 0 ? M : 1), sizeof(double));
         if (!Cg) return -2;
+#pragma omp parallel for schedule(dynamic) reduction(min : err)
         for (int j = 0; j < K; ++j) {
             size_t base = (size_t)j * (size_t)cap;
             double* psi = orc_psi(m, KC, Z, M, X, base, n[j]);
-            if (!psi) { free(Cg); return -2; }
+            if (!psi) { err = -2; continue; }
             for (int p = 0; p < M; ++p) {
                 double c = 0.0;
                 for (int i = 0; i < n[j]; ++i) c += psi[(size_t)i * M + p] * W[base + i];
@@ -439,14 +460,17 @@ int orc_update(const orc_model* m, int cap, const double* Z, int M,
             }
             free(psi);
         }
+        if (err) { free(Cg); return err; }
         for (int p = 0; p < M; ++p)
             for (int j = 0; j < K; ++j) Cg[p] += C[(size_t)j * M + p];
     }
+    /* groups are independent once C is known: one thread per group */
+#pragma omp parallel for schedule(dynamic) reduction(min : err)
     for (int j = 0; j < K; ++j) {
         int nj = n[j];
         size_t base = (size_t)j * (size_t)cap;
         double* psi = orc_psi(m, KC, Z, M, X, base, nj);
-        if (!psi) { free(Cg); return -2; }
+        if (!psi) { err = -2; continue; }
         /* Eq 11 */
         for (int p = 0; p < M; ++p) {
             double c = 0.0;
@@ -482,7 +506,7 @@ int orc_update(const orc_model* m, int cap, const double* Z, int M,
         free(psi);
     }
     free(Cg);
-    return 0;
+    return err;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -626,10 +650,13 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
     int K = m->partitions;
     size_t KC = (size_t)K * (size_t)cap;
     double Rj = m->particles_per_target / (double)K;
-    uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
-    int* order = (int*)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
-    if (!q || !order) { free(q); free(order); return -2; }
+    int err = 0;
+    /* groups resample independently: one thread per group */
+#pragma omp parallel for schedule(dynamic) reduction(min : err)
     for (int j = 0; j < K; ++j) {
+        uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
+        int* order = (int*)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
+        if (!q || !order) { free(q); free(order); err = -2; continue; }
         size_t base = (size_t)j * (size_t)cap;
         int nj = n[j];
         int cap_children = cap - orc_births_in_partition(m, j);
@@ -673,7 +700,7 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
         }
         mass_q[j] = mq;
         nout[j] = (int32_t)L;
-        if (L == 0) continue;
+        if (L == 0) { free(q); free(order); continue; }
         uint32_t r4[4];
         orc_block(seed, (uint32_t)j, step, ORC_RESAMPLE, 0, run, r4);
         uint64_t r = r4[0];
@@ -695,9 +722,10 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
             Wout[dst] = mq / (double)L;
             counts[base + i] += 1;
         }
+        free(q);
+        free(order);
     }
-    free(q);
-    free(order);
+    if (err) return err;
     return 0;
 }
 
@@ -930,10 +958,13 @@ int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t 
 {
     int K = m->partitions;
     size_t KC = (size_t)K * (size_t)cap;
+    for (int j = 0; j < K; ++j)
+        if (n[j] < orc_births_in_partition(m, j)) return -1;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic) reduction(min : err)
     for (int j = 0; j < K; ++j) {
         int Jj = orc_births_in_partition(m, j);
         int ns = n[j] - Jj;
-        if (ns < 0) return -1;
         for (int b = 0; b < Jj; ++b) {
             uint32_t g = (uint32_t)(j * cap + ns + b);
             uint32_t a[4], v[4], c[4], e[4];
@@ -972,9 +1003,9 @@ int orc_birth_from_mixture(const orc_model* m, int cap, uint32_t step, uint64_t 
             double gam = orc_birth_mass(m) * orc_prior_density(m, x);
             W[g] = gam > 0.0 ? gam / ((double)Jj * orc_mixture_proposal_density(m, table, M, x)) : 0.0;
         }
-        if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) return -2;
+        if (orc_sort_by_bucket(m, KC, X, W, (size_t)j * cap + ns, Jj) != 0) err = -2;
     }
-    return 0;
+    return err;
 }
 
 /* Training pairs for the learned proposal: state from the birth density,

@@ -57,6 +57,10 @@ typedef struct {
 enum { ORC_INIT = 1, ORC_PREDICT = 2, ORC_BIRTH = 3, ORC_RESAMPLE = 4, ORC_EXCHANGE = 5, ORC_PAIRS = 6 };
 
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* The per-group loops of predict, births, update and resample run one group
+ * per thread (OpenMP); the results are the same for any thread count. */
+void   orc_set_threads(int n);
+int    orc_threads(void);
 double orc_u53(uint32_t a, uint32_t b);
 void   orc_normal_pair(double u1, double u2, double* n1, double* n2);
 int    orc_births_in_partition(const orc_model* m, int j);

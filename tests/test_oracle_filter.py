@@ -30,3 +30,24 @@ def test_mass_tracks_true_count(orc, K):
     # mass follows the count: small bias and spread well below one target
     assert abs(errs.mean()) < 0.35, errs.mean()
     assert np.sqrt(np.mean(errs ** 2)) < 0.8, np.sqrt(np.mean(errs ** 2))
+
+
+def test_thread_count_does_not_change_results(orc):
+    """The oracle runs its independent groups one per thread; one thread and
+    four threads give the same filter bit for bit."""
+    p = dict(BASE_MODEL, partitions=6, particles_per_target=600.0 * 6, births_per_step=1200, clutter_rate=20.0,
+             birth_proposal=1, birth_alpha=0.1)
+    truth, Z = make_scenario(p, 3, 4, 17)
+    outs = []
+    before = orc.threads()
+    try:
+        for nt in (1, 4):
+            orc.set_threads(nt)
+            f = orc.OracleFilter(p, 1500, 8, 2)
+            for k in range(1, 5):
+                out = f.step(k, Z[k])
+            outs.append((f.st.X.copy(), f.st.W.copy(), f.st.n.copy(), out["upd"]["C"].copy()))
+    finally:
+        orc.set_threads(before)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
