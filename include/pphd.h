@@ -164,6 +164,19 @@ pphd_status pphd_predict(pphd_filter* f, uint32_t step);
  * 0 <= m <= max_meas.  Phase PREDICTED -> UPDATED. */
 pphd_status pphd_update(pphd_filter* f, const double* z, int32_t m, int32_t z_on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pphd_update
+ * with the first likelihood pass's partial sums in a static device array of
+ * the library (64 MiB per device, held until the process ends) instead of the
+ * workspace.  Same arguments, phases and results as pphd_update, bit for bit;
+ * it calls no allocating routine.  The partials need
+ * K * ceil(cap / (64 p)) * (12 max_meas + 8) bytes, p = 4 in FP32 and 2 in
+ * FP64 (each of the three parts rounded up to 256 bytes); a filter above
+ * 64 MiB gets PPHD_EINVAL.  All filters on one device share the array: calls
+ * that overlap on one device (other streams or threads) race.  Not with
+ * kernel timing on (PPHD_EINVAL); not for batches. */
+pphd_status pphd_update_noalloc(pphd_filter* f, const double* z, int32_t m, int32_t z_on_device);
+
 /* Steps 3 and 4: each group keeps its round(sum w) best-supported measurement
  * labels with local estimates (Eqs 16-18); labels reported by more than half
  * of the groups are averaged into global estimates, ordered by label.

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,6 +101,7 @@ struct pphd_filter {
     size_t KC = 0;
     size_t esz = 8;
     hipStream_t stream = nullptr;
+    int device = 0;  // the device current at create
     uint64_t seed = 0;
     uint32_t run = 0;
     int phase = 0;  // 0 = created, otherwise a pphd_phase
@@ -969,6 +971,7 @@ pphd_status create_impl(const pphd_model* model, const pphd_run_desc* runs, int 
     f->seed = seed;
     f->run = run_id;
     f->stream = (hipStream_t)stream;
+    if (hipGetDevice(&f->device) != hipSuccess) f->device = 0;
     fill_devmodel(f);
     hipError_t e = hipHostMalloc((void**)&f->pin_z, (size_t)f->z_cap * 2 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&f->pin_win, (size_t)f->nruns * 8, hipHostMallocDefault);
@@ -1586,6 +1589,78 @@ pphd_status pphd_set_birth_mixture(pphd_filter* f, const float* raw, int32_t m, 
     f->mix_preset = true;
     f->mix_preset_m = m;
     return PPHD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free update.  pphd_update_noalloc is pphd_update with the first
+// likelihood pass's partial sums (per group, wave tile and measurement: the
+// scaled sum, its exponent, and per tile the weight sum) in the static device
+// array `scratch` instead of the caller's workspace.  Every device holds its
+// own copy of the array for the life of the process, and every call on a
+// device shares it; nothing in it needs clearing, since the first pass
+// writes every partial that the combine reads in the same update.
+// ---------------------------------------------------------------------------
+constexpr size_t PPHD_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[PPHD_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The device address of `scratch` on device dev, looked up once per device
+// with that device current (host code never passes the array's own name).
+pphd_status scratch_on(int dev, char** out)
+{
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(PPHD_EDEVICE, "device %d has no static scratch slot", dev);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return fail(PPHD_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = scratch_ptr[dev];
+    return PPHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pphd_status pphd_update_noalloc(pphd_filter* f, const double* z, int32_t m, int32_t z_on_device)
+{
+    CHECK_HANDLE(f);
+    if (f->batch) return fail(PPHD_EINVAL, "a batch is updated with pphd_batch_update");
+    if (f->timing) return fail(PPHD_EINVAL, "pphd_update_noalloc records no kernel times (turn timing off)");
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t n = (size_t)f->K * (size_t)f->wtiles_max;
+    const size_t bs = up(n * (size_t)f->max_meas * 8), bh = up(n * (size_t)f->max_meas * 4), bw = up(n * 8);
+    if (bs + bh + bw > PPHD_SCRATCH_BYTES)
+        return fail(PPHD_EINVAL, "the first pass's partials need %zu bytes; the static scratch holds %zu",
+                    bs + bh + bw, PPHD_SCRATCH_BYTES);
+    char* base = nullptr;
+    pphd_status st = scratch_on(f->device, &base);
+    if (st != PPHD_OK) return st;
+    double* const ks = f->p1s;
+    int* const kh = f->p1h;
+    double* const kw = f->p1w;
+    f->p1s = reinterpret_cast<double*>(base);
+    f->p1h = reinterpret_cast<int*>(base + bs);
+    f->p1w = reinterpret_cast<double*>(base + bs + bh);
+    st = pphd_update(f, z, m, z_on_device);
+    f->p1s = ks;
+    f->p1h = kh;
+    f->p1w = kw;
+    return st;
 }
 
 }  // extern "C"

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pphd_init": (_I32, [_P]),
     "pphd_predict": (_I32, [_P, _U32]),
     "pphd_update": (_I32, [_P, _P, _I32, _I32]),
+    "pphd_update_noalloc": (_I32, [_P, _P, _I32, _I32]),
     "pphd_extract": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32), _P]),
     "pphd_extract_device": (_I32, [_P, _P, _I32, _P]),
     "pphd_resample": (_I32, [_P, _U32]),
@@ -199,6 +200,10 @@ def pphd_predict(h, step):
 
 def pphd_update(h, z, m, z_on_device):
     _chk(lib().pphd_update(h, z, m, z_on_device))
+
+
+def pphd_update_noalloc(h, z, m, z_on_device):
+    _chk(lib().pphd_update_noalloc(h, z, m, z_on_device))
 
 
 def pphd_extract(h, out_ptr, cap, mass_ptr=None):
