@@ -63,6 +63,28 @@ def pass_bytes(counts, Mg, esz, tile=PASS_TILE):
     return cz, weight
 
 
+def step_bytes(counts, births, esz, dim=4):
+    """Algorithmic HBM bytes of one launch of the per-particle kernels around
+    the passes, from each group's particle count after the births and its
+    births:
+      birth_order (births drawn, ordered and weighed, with the survivors'
+                   prediction in the same launch): per survivor the state and
+                   weight read and written ((dim + 1) values each way) and its
+                   four FP64 geometry values written; per birth its state,
+                   weight and geometry written;
+      rs_expand   (the systematic expansion, with the ring exchange fused):
+                   per parent its state and weight read, per child the same
+                   written (the children number about as many as the
+                   parents), and one 8-byte tile sum per 256 parents."""
+    counts = np.asarray(counts, dtype=np.int64)
+    births = np.asarray(births, dtype=np.int64)
+    rec = (dim + 1) * esz
+    surv = int((counts - births).clip(min=0).sum())
+    front = surv * (2 * rec + 32) + int(births.sum()) * (rec + 32)
+    expand = int(counts.sum()) * 2 * rec + int((-(-counts // 256)).sum()) * 8
+    return front, expand
+
+
 def source_hash():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -101,6 +123,8 @@ def parse():
                     help="bound on the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-timing-pass", action="store_true",
                     help="skip the HIP-event pass (for profiler runs)")
+    ap.add_argument("--no-pcie", action="store_true",
+                    help="skip the pass with host measurement sets and host estimates (for profiler runs)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP64 and uniform-birth variants of the workload")
     ap.add_argument("--no-sequential", action="store_true",
@@ -207,9 +231,12 @@ def main():
         n_pairs = 0
         for k in range(1, total + 1):
             f.predict(k)
+            f.update(zall[offs[k]:offs[k + 1]])
+            # (the counts after the update are the predicted ones: the update
+            # changes weights only; read here, the predict still rides in the
+            # update's first launch as in the timed pass)
             if k > args.warmup:
                 n_pairs += int(f.read_counts().sum()) * Ms[k]
-            f.update(zall[offs[k]:offs[k + 1]])
             f.extract_device(est_dev[k], nest_dev[k:k + 1], cap_est)
             f.resample(k)
             f.exchange(k)
@@ -229,9 +256,12 @@ def main():
     elapsed = timed()
     ms_per_step = elapsed * 1e3 / args.steps
     # ---- the same steps with host measurement sets and host estimates -------
-    elapsed_pcie = timed(one=step_pcie)
+    elapsed_pcie = timed(one=step_pcie) if not args.no_pcie else None
 
     # ---- pass B: same run, per-kernel HIP-event times and particle counts ----
+    K_ = int(p["partitions"])
+    J_ = int(p["births_per_step"])
+    births_per_group = np.array([J_ // K_ + (1 if j < J_ % K_ else 0) for j in range(K_)])
     kern = {}
     pairs = []
     parts = []
@@ -244,12 +274,13 @@ def main():
             if k == args.warmup + 1:
                 g.set_timing(True)
             g.predict(k)
+            g.update(zall[offs[k]:offs[k + 1]])
             if k > args.warmup:
                 n = g.read_counts()
                 pairs.append(int(n.sum()) * Ms[k])
                 parts.append(int(n.sum()))
-                pbytes.append(pass_bytes(n, np.full(len(n), Ms[k]), esz))
-            g.update(zall[offs[k]:offs[k + 1]])
+                pbytes.append(pass_bytes(n, np.full(len(n), Ms[k]), esz)
+                              + step_bytes(n, births_per_group, esz, int(p.get("dim", 4))))
             g.extract_device(est_dev[k], nest_dev[k:k + 1], cap_est)
             g.resample(k)
             g.exchange(k)
@@ -285,7 +316,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "steps_per_s": 1e3 / ms_per_step,
-        "steps_per_s_pcie": args.steps / elapsed_pcie,
+        "steps_per_s_pcie": args.steps / elapsed_pcie if elapsed_pcie else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -328,27 +359,44 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+ROOF_CLASSES = ("cz", "weight", "birth_order", "rs_expand")
+ROOF_KERNELS = {"cz": "k_cz_frames", "weight": "k_weight_frames", "birth_order": "k_birth_draw_sort",
+                "rs_expand": "k_rs_expand"}
+
+
 def roofline(pphd, kern, bytes_per_launch, workload):
-    """The larger of the two likelihood passes against HBM bandwidth.  Both
-    skip, per tile, the measurements whose terms are exactly zero, so their
-    floor is moving their particles' data, not evaluating every pair."""
-    dom = max(("cz", "weight"), key=lambda c: kern[c][0])
-    ms, n = kern[dom]
-    avg_s = ms / 1e3 / n
-    B = float(bytes_per_launch[0] if dom == "cz" else bytes_per_launch[1])
+    """The longest of the per-particle kernels (the two likelihood passes, the
+    births' launch that also predicts the survivors, the resampling expansion
+    that also exchanges) against HBM bandwidth: algorithmic bytes per launch
+    over its average duration.  The passes skip, per tile, the measurements
+    whose terms are exactly zero, so their floor too is moving their
+    particles' data.  Every class's figures are listed under "kernels"."""
+    rows = {}
+    for i, c in enumerate(ROOF_CLASSES):
+        if c not in kern or not kern[c][1]:
+            continue
+        if c == "birth_order" and kern.get("predict", (0, 0))[1]:
+            continue  # the prediction had a launch of its own: these bytes do not describe that launch
+        ms, n = kern[c]
+        avg_s = ms / 1e3 / n
+        B = float(bytes_per_launch[i])
+        rows[c] = (avg_s, B)
+    dom = max(rows, key=lambda c: rows[c][0])
+    avg_s, B = rows[dom]
     achieved = B / avg_s / 1e9
-    traffic = stored_traffic(dom, workload)
     return {
-        # every bench workload has clutter, so the passes run in bearing frames
-        "kernel": pphd.pphd_kernel_name(pphd.KERNEL_CLASSES.index(dom)) + "_frames",
+        "kernel": ROOF_KERNELS[dom],
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": traffic,
+        "traffic": stored_traffic(dom, workload),
         "avg_launch_us": avg_s * 1e6,
         "bytes_per_launch": B,
+        "others": {ROOF_KERNELS[c]: {"avg_launch_us": a * 1e6, "bytes_per_launch": b, "GB_s": b / a / 1e9,
+                                     "frac": b / a / 1e9 / HBM_PEAK_GBS, "traffic": stored_traffic(c, workload)}
+                   for c, (a, b) in rows.items() if c != dom},
     }
 
 
@@ -422,6 +470,9 @@ def bench_batch(args, w):
     kern, pairs, parts, ospas, pbytes = {}, [], [], [], []
     esz = 4 if prec == pphd.PPHD_FP32 else 8
     group_run = np.repeat(np.arange(R), [int(r["partitions"]) for r in runs])  # run of every group
+    group_births = np.concatenate([[int(r["births_per_step"]) // int(r["partitions"])
+                                    + (1 if j < int(r["births_per_step"]) % int(r["partitions"]) else 0)
+                                    for j in range(int(r["partitions"]))] for r in runs])
     # ---- pass B: eager batch, per-kernel HIP-event times, counts, estimates --
     g = make_batch()
     g.init()
@@ -432,12 +483,12 @@ def bench_batch(args, w):
         if k == args.warmup + 1 and not args.no_timing_pass:
             g.set_timing(True)
         g.predict(k)
+        g.update_device(zdev[k], zdev[k].shape[0], wdev[k])
         if k > args.warmup:
             n = g.read_counts()
             pairs.append(int(np.dot(n, Ms[k][group_run])))
             parts.append(int(n.sum()))
-            pbytes.append(pass_bytes(n, Ms[k][group_run], esz))
-        g.update_device(zdev[k], zdev[k].shape[0], wdev[k])
+            pbytes.append(pass_bytes(n, Ms[k][group_run], esz) + step_bytes(n, group_births, esz, int(p.get("dim", 4))))
         g.extract_device(est_hist[k], n_hist[k], Mx)
         g.resample(k)
         g.exchange(k)

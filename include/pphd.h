@@ -119,7 +119,8 @@ typedef struct pphd_filter pphd_filter;
  * cap_per_partition: particle slots per group, 1 .. 65535 * 256 (must hold
  * round(R/K) initial particles and L' + J_j after every resampling; L' is
  * clamped to fit).
- * max_meas: the largest measurement count a later pphd_update may pass (>= 1).
+ * max_meas: the largest measurement count a later pphd_update may pass, in
+ * [1, 6144] (the C(z) combination keeps one double per measurement in LDS).
  * Returns PPHD_EINVAL for an invalid model or sizes. */
 pphd_status pphd_workspace_size(const pphd_model* model, int64_t cap_per_partition,
                                 int32_t max_meas, size_t* bytes);

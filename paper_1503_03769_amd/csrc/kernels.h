@@ -49,6 +49,15 @@ __device__ __forceinline__ int slot_tile(const DevModel& m) { return m.tile_majo
 // group, a scatter into the other particle set.
 // ---------------------------------------------------------------------------
 constexpr int BEARING_BUCKETS = 64;
+// Each group's quantised parent total Q is accumulated in QSLOTS partial
+// sums (exact integers in any order), so that the atomic additions of the
+// resampling's scatter spread over that many addresses
+constexpr int QSLOTS = 8;
+__device__ __forceinline__ double group_q(const double* __restrict__ qtot, int g)
+{
+    const double* q = qtot + (size_t)g * QSLOTS;
+    return ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+}
 
 __device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
 {
@@ -366,6 +375,33 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
     // library's constants live across it, tripling the registers)
     const int s = slot_tile(m) * 256 + threadIdx.x;
     if (s < total) predict_slot(m, gr, st, geo, ns, Jj, j, s, step, bkt);
+}
+
+// Step 1 for 1024 slots of one group, as k_predict does it for 256 (the
+// prediction rides in the births' launch when the births are drawn there):
+// part w takes group w mod K, slots [1024 floor(w / K), +1024), so every
+// group's first slots come first (groups of clearly different sizes: the
+// group's slot blocks one after another, spreading it over the chip's dies)
+template <typename T>
+__device__ __forceinline__ void predict_part(const DevModel& m, const Grp* __restrict__ gd, const SoA<T>& st,
+                                             const Geo& geo, const int* __restrict__ nsurv, int* __restrict__ ncur,
+                                             uint32_t step, int* __restrict__ bkt, int w, int K)
+{
+    int j, t4;
+    if (m.tile_major) {
+        const int per = (m.cap + 1023) / 1024;
+        j = w / per;
+        t4 = w - j * per;
+    } else {
+        j = w % K;
+        t4 = w / K;
+    }
+    const Grp gr = gd[j];
+    const int ns = nsurv[j];
+    const int total = ns + gr.Jj < m.cap ? ns + gr.Jj : m.cap;
+    if (t4 == 0 && threadIdx.x == 0) ncur[j] = total;
+    const int s = t4 * 1024 + threadIdx.x;
+    if (s < ns) predict_slot(m, gr, st, geo, ns, gr.Jj, j, s, step, bkt);
 }
 
 // dim 5: the turn rate of a birth drawn from a measurement-driven or learned
@@ -2088,7 +2124,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
                                                   int* __restrict__ fLT, int* __restrict__ rsS,
                                                   int* __restrict__ sel, double* __restrict__ zeta,
                                                   int rtiles, const int* __restrict__ bhist, int* __restrict__ boff,
-                                                  double* __restrict__ tsum)
+                                                  double* __restrict__ tsum, double* __restrict__ qtot)
 {
     const int j = blockIdx.x;
     const int M = zview(gd[j], win, nullptr, Mall).M;
@@ -2162,8 +2198,10 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
         }
     }
     // the resampling's parent order (bucket offsets of the group's tiles from
-    // k_wfinal's histograms) and its tile sums cleared for k_bk_scatter
+    // k_wfinal's histograms) and its tile sums and group total cleared for
+    // k_bk_scatter
     for (int t = threadIdx.x; t < nt; t += 256) tsum[(size_t)j * rtiles + t] = 0.0;
+    if (threadIdx.x < QSLOTS) qtot[(size_t)j * QSLOTS + threadIdx.x] = 0.0;
     bucket_offsets<4>(j, nt, rtiles, bhist, boff);
 }
 
@@ -2304,12 +2342,14 @@ __global__ __launch_bounds__(256) void k_bk_hist(DevModel m, SoA<T> st, const in
 // cleared for k_bk_scatter to accumulate
 __global__ __launch_bounds__(1024) void k_bk_scan(const int* __restrict__ first, const int* __restrict__ end,
                                                   int rtiles, const int* __restrict__ hist, int* __restrict__ off,
-                                                  double* __restrict__ tsum)
+                                                  double* __restrict__ tsum, double* __restrict__ qtot)
 {
     const int j = blockIdx.x;
     const int ntl = (end[j] - range_first(first, j) + 255) / 256;
-    if (tsum)
+    if (tsum) {
         for (int t = threadIdx.x; t < ntl; t += 1024) tsum[(size_t)j * rtiles + t] = 0.0;
+        if (threadIdx.x < QSLOTS) qtot[(size_t)j * QSLOTS + threadIdx.x] = 0.0;
+    }
     bucket_offsets<16>(j, ntl, rtiles, hist, off);
 }
 
@@ -2324,7 +2364,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
                                                     const int* __restrict__ end, int rtiles,
                                                     const int* __restrict__ bkt, const int* __restrict__ off,
                                                     const int* __restrict__ rsS, double* __restrict__ tsum,
-                                                    int* __restrict__ orig)
+                                                    int* __restrict__ orig, double* __restrict__ qtot)
 {
     // a workgroup takes NH 256-slot tiles of the range (half h: tile
     // NH t2 + h, one slot per thread; NH = 2 where the capacity spans enough
@@ -2390,7 +2430,11 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     }
     if (!tsum) return;
     // per destination tile: one wave sum and one atomic addition per distinct
-    // tile (integer-valued sums below 2^53: exact in any order)
+    // tile (integer-valued sums below 2^53: exact in any order); the group's
+    // total Q the same way, one addition per workgroup into one of the
+    // group's QSLOTS partial sums
+    __shared__ double s_qw[4];
+    double qw = 0.0;
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
         const double q = live[h] ? floor(ldexp((double)pw[h], S)) : 0.0;
@@ -2403,9 +2447,14 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
             const bool mine = tile == tl;
             const double sq = wave_sum(mine ? q : 0.0);
             if (lane == lead) atomicAdd(&tsum[(size_t)j * rtiles + tl], sq);
+            qw += sq;
             if (mine) tile = -1;
         }
     }
+    if (lane == 0) s_qw[wv] = qw;
+    __syncthreads();
+    const double qg = (s_qw[0] + s_qw[1]) + (s_qw[2] + s_qw[3]);
+    if (threadIdx.x == 0 && qg > 0.0) atomicAdd(&qtot[(size_t)j * QSLOTS + (t2 & (QSLOTS - 1))], qg);
 }
 
 // The ranking of k_birth_sort: births c * 1024 + thread (c < BS, first nb
@@ -2526,23 +2575,32 @@ constexpr int BIRTH_FUSED_MAX = 1152;
 template <typename T, int BS, int PROP, bool WEIGHT>
 __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
                                                           Geo geo, const int* __restrict__ nsurv,
-                                                          const int* __restrict__ ncur,
+                                                          int* __restrict__ ncur,
                                                           const double* __restrict__ Zall,
                                                           const double* __restrict__ taball, int Mall,
                                                           const ZWin* __restrict__ win, uint32_t step_arg,
                                                           const uint32_t* __restrict__ dstep, int* __restrict__ borig,
-                                                          int K0, ZPrep zp)
+                                                          int K0, ZPrep zp, int zruns, int* __restrict__ bkt)
 {
     // workgroups past the K0 groups prepare the measurements of run
-    // blockIdx.x - K0 for the likelihood passes (no birth reads them)
+    // blockIdx.x - K0 for the likelihood passes (no birth reads them); the
+    // ones past those, if any, predict the survivors (Step 1), 1024 slots
+    // each: the births fill the slots after the survivors, so the two parts
+    // touch different slots and run side by side
     if ((int)blockIdx.x >= K0) {
-        zprep_run<1024>(m, Zall, Mall, win, zp, (int)blockIdx.x - K0);
+        const int w = (int)blockIdx.x - K0;
+        if (w < zruns) {
+            zprep_run<1024>(m, Zall, Mall, win, zp, w);
+            return;
+        }
+        predict_part<T>(m, gd, st, geo, nsurv, ncur, step_of(step_arg, dstep), bkt, w - zruns, K0);
         return;
     }
     static_assert(!WEIGHT || 1024 * BS >= BIRTH_FUSED_MAX, "the fused form holds every birth");
     const int j = blockIdx.x;
     const Grp gr = gd[j];
-    const int ns = nsurv[j], nb = ncur[j] - ns;
+    // the births' slots [ns, min(ns + J_j, cap)), as the prediction sets them
+    const int ns = nsurv[j], nb = (ns + gr.Jj < m.cap ? ns + gr.Jj : m.cap) - ns;
     if (nb <= 0) return;
     const int tid = threadIdx.x;
     const size_t gb = (size_t)j * m.cap + ns;
@@ -2656,6 +2714,23 @@ __device__ __forceinline__ double children_count(double mq, int mk, double Rj)
     return floor(t);
 }
 
+// a group's child count L' from its exact quantised total Q and shift S:
+// children_count of the mass 2^-S Q, clamped to [0, cap - J_j]; *clamped
+// tells whether the capacity cut it
+__device__ __forceinline__ long long group_children(double Qd, int S, const Grp& g, int cap, bool* clamped)
+{
+    *clamped = false;
+    if (!(Qd > 0.0)) return 0;
+    double Lf = children_count(ldexp(Qd, -S), g.mk, g.Rj);
+    const double lim = (double)(cap - g.Jj);
+    if (Lf > lim) {
+        Lf = lim;
+        *clamped = true;
+    }
+    if (Lf < 0.0) Lf = 0.0;
+    return (long long)Lf;
+}
+
 // ---------------------------------------------------------------------------
 // Step 5, pass B: exact prefix of q, child counts and parent-order expansion
 // into the other particle set.  A workgroup owns 256 NH consecutive parents
@@ -2673,7 +2748,9 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
                                                    const int* __restrict__ rsS, const double* __restrict__ tsum,
                                                    int rtiles, uint32_t step_arg, const uint32_t* __restrict__ dstep,
                                                    double* __restrict__ massq, int* __restrict__ clampctr,
-                                                   int* __restrict__ counts, int record)
+                                                   int* __restrict__ counts, int record,
+                                                   const double* __restrict__ qtot, int xchg, uint32_t xstep_arg,
+                                                   const uint32_t* __restrict__ xdstep)
 {
     constexpr int RS_TILE = 256 * NH;
     __shared__ long long s_end[RS_TILE];
@@ -2701,6 +2778,36 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
 #pragma unroll
         for (int d = 0; d < 5; ++d) pv[h][d] = in.x[d < m.dim ? d : 0][gs];
         pwt[h] = in.w[gs];
+    }
+    // Step 6 in the same pass (xchg): the run's exchange count
+    // Lx = floor(rho_x min_i L'_i) from every group's total (each L'_i formed
+    // exactly as group i's own workgroups form it), and the strata offsets of
+    // this group and the next; child c = S_j(m) of this group is written to
+    // slot S_{j+1}(m) of the next group instead of its own slot, which in
+    // turn receives child S_{j-1}(m) of the previous group.  Every slot is
+    // written once and no child is read, so this is the exchange of the
+    // resampled set.  The run's counts are read here, with the parents, and
+    // meet at the workgroup's one barrier below.
+    __shared__ double s_xmin[4];
+    __shared__ long long s_nnext;
+    const bool xrun = xchg && gr.K >= 2;
+    const int jn = gr.jl + 1 < gr.K ? gr.jl + 1 : 0;
+    uint32_t xa = 0, xan = 0;
+    if (xrun) {
+        // (counts below 2^31: exact in double)
+        double mn = 1e300;
+        for (int i = tid; i < gr.K; i += 256) {
+            const int g = gr.g0 + i;
+            bool c2;
+            const long long Li = group_children(group_q(qtot, g), rsS[g], gd[g], m.cap, &c2);
+            mn = (double)Li < mn ? (double)Li : mn;
+            if (i == jn) s_nnext = Li;
+        }
+        mn = -wave_max(-mn);
+        if (lane == 0) s_xmin[wv] = mn;
+        const uint32_t xs = step_of(xstep_arg, xdstep);
+        xa = rng_block(m.key0, m.key1, (uint32_t)gr.jl, xs, RNG_EXCHANGE, 0, gr.rng_run).a;
+        xan = rng_block(m.key0, m.key1, (uint32_t)jn, xs, RNG_EXCHANGE, 0, gr.rng_run).a;
     }
     // group total Q and this workgroup's exclusive prefix P over the 256-slot
     // tile sums (exact integer sums), in runs of four per thread
@@ -2753,25 +2860,26 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         for (int w2 = 0; w2 < wv; ++w2) wpre[h] += s_q[2 + h][w2];
         hpre[h] = h == 0 ? 0.0 : hpre[h - 1] + ((s_q[1 + h][0] + s_q[1 + h][1]) + (s_q[1 + h][2] + s_q[1 + h][3]));
     }
-    const int Jj = gr.Jj;
-    long long L = 0;
-    double mq = 0.0;
-    if (Qd > 0.0) {
-        mq = ldexp(Qd, -S);
-        double Lf = children_count(mq, gr.mk, gr.Rj);
-        const double lim = (double)(m.cap - Jj);
-        bool clamped = false;
-        if (Lf > lim) {
-            Lf = lim;
-            clamped = true;
-        }
-        if (Lf < 0.0) Lf = 0.0;
-        L = (long long)Lf;
-        if (t == 0 && tid == 0 && clamped) atomicAdd(clampctr, 1);
-    }
+    bool clamped = false;
+    const long long L = group_children(Qd, S, gr, m.cap, &clamped);
+    const double mq = Qd > 0.0 ? ldexp(Qd, -S) : 0.0;
     if (t == 0 && tid == 0) {
+        if (clamped) atomicAdd(clampctr, 1);
         nsurv[j] = (int)L;
         massq[j] = mq;
+    }
+    long long xL = 0, xb = 0, xn = 0, xbn = 0;
+    size_t xgb = 0;
+    if (xrun) {
+        double mn = s_xmin[0];
+        for (int w2 = 1; w2 < 4; ++w2) mn = s_xmin[w2] < mn ? s_xmin[w2] : mn;
+        xL = (long long)floor(m.xfrac * mn);
+        if (xL > 0) {
+            xn = s_nnext;
+            xb = (long long)(((uint64_t)xa * (uint64_t)L) >> 32);
+            xbn = (long long)(((uint64_t)xan * (uint64_t)xn) >> 32);
+            xgb = (size_t)(gr.g0 + jn) * m.cap;
+        }
     }
     if (L == 0 || base >= n) {
         if (record) {
@@ -2810,8 +2918,29 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
             const int mid = (lo + hi + 1) >> 1;
             if (s_end[mid - 1] <= c) lo = mid; else hi = mid - 1;
         }
-        for (int d = 0; d < m.dim; ++d) out.x[d][gb + c] = s_x[d][lo];
-        out.w[gb + c] = (T)wc;
+        size_t dst = gb + c;
+        if (xL > 0) {
+            // the stratum m with S_j(m) = floor((m L' + b_j) / Lx) = c, if any:
+            // the least m with m L' + b_j >= c Lx (strata lie at least
+            // L'/Lx > 1 slots apart, so there is at most one).  The quotients
+            // are estimated in double and settled by exact integer products
+            // (all below 2^53), which avoids 64-bit division per child.
+            const long long lo = c * xL;
+            long long mm = (long long)ceil((double)(lo - xb) / (double)L);
+            mm = mm < 0 ? 0 : mm;
+            if (mm * L + xb < lo) ++mm;
+            else if (mm > 0 && (mm - 1) * L + xb >= lo) --mm;
+            if (mm < xL && mm * L + xb < lo + xL) {
+                // S_{j+1}(m) = floor((m L'_{j+1} + b_{j+1}) / Lx)
+                const long long num = mm * xn + xbn;
+                long long q = (long long)floor((double)num / (double)xL);
+                if (q * xL > num) --q;
+                else if ((q + 1) * xL <= num) ++q;
+                dst = xgb + (size_t)q;
+            }
+        }
+        for (int d = 0; d < m.dim; ++d) out.x[d][dst] = s_x[d][lo];
+        out.w[dst] = (T)wc;
     }
 }
 

@@ -110,6 +110,10 @@ struct pphd_filter {
     uint32_t last_step = 0;
     bool record = false;
     bool births_pending = false;  // birth slots reserved by predict, drawn in update
+    // a prediction that waits for the update, whose births' launch carries it
+    bool pr_pending = false;
+    uint32_t pr_step = 0;
+    const uint32_t* pr_dstep = nullptr;
     // learned proposal (birth_proposal 2)
     pphd_mlp* mlp = nullptr;
     bool mix_preset = false;  // pphd_set_birth_mixture outputs wait for the next update
@@ -142,6 +146,11 @@ struct pphd_filter {
     EstimateRec* est = nullptr;
     int* nest = nullptr;
     double *tsum = nullptr, *massq = nullptr;
+    double* qtot = nullptr;  // each group's quantised parent total Q in QSLOTS partial sums
+    // the expansion of a resampling whose exchange may still be fused into it
+    bool rs_pending = false;
+    uint32_t rs_step = 0;
+    const uint32_t* rs_dstep = nullptr;
     int* counts = nullptr;
     int *bkt = nullptr, *bhist = nullptr, *boff = nullptr;  // bearing-bucket order of the parents
     int* borig = nullptr;  // drawing index of each ordered birth
@@ -246,6 +255,7 @@ size_t carve(pphd_filter* f, char* base)
     f->nest = L.take<int>(base, (size_t)f->nruns * 4);
     f->tsum = L.take<double>(base, K * f->rtiles * 8);
     f->massq = L.take<double>(base, K * 8);
+    f->qtot = L.take<double>(base, K * QSLOTS * 8);
     f->counts = L.take<int>(base, KC * 4);
     f->bkt = L.take<int>(base, KC * 4);
     f->borig = L.take<int>(base, KC * 4);
@@ -376,7 +386,10 @@ bool sizes_ok(const pphd_run_desc* runs, int nruns, int64_t cap, int32_t max_mea
 {
     // (tiles of 256 slots index the second grid dimension: at most 65535)
     if (cap < 1 || cap > 65535ll * 256) { why = "cap_per_partition out of range"; return false; }
-    if (max_meas < 1 || max_meas > 65536) { why = "max_meas must be in [1, 65536]"; return false; }
+    // k_cz_combine and k_cz_global keep one double per measurement in LDS
+    // next to about 13 KB of their own: at most 6144 measurements stay
+    // within a workgroup's 64 KB
+    if (max_meas < 1 || max_meas > 6144) { why = "max_meas must be in [1, 6144]"; return false; }
     int64_t groups = 0;
     for (int r = 0; r < nruns; ++r) {
         const pphd_run_desc& d = runs[r];
@@ -546,6 +559,10 @@ pphd_status launch(pphd_filter* f, int cls, F&& fn)
 
 template <typename T>
 pphd_status order_births(pphd_filter* f, bool weights_later);
+template <typename T>
+bool births_in_one_launch(const pphd_filter* f);
+int predict_parts(const pphd_filter* f);
+pphd_status flush_predict(pphd_filter* f);
 
 template <typename T, int PT1, int PT2>
 pphd_status run_update(pphd_filter* f, const UpdArgs& a)
@@ -563,6 +580,13 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     // per run), else it has a launch of its own below
     const int zruns = f->pass_mode == PASS_FRAMES ? f->nruns : 0;
     bool zprep_done = false;
+    // a pending prediction rides in the births' launch, else it goes first
+    if (f->pr_pending && !(f->births_pending && births_in_one_launch<T>(f))) {
+        pphd_status ps = flush_predict(f);
+        if (ps != PPHD_OK) return ps;
+    }
+    const int npred = f->pr_pending ? predict_parts(f) : 0;
+    f->pr_pending = false;
     if (f->births_pending) {
         // births of the measurement-driven proposals: draw, bearing order
         // (recording each birth's drawing index), weights with the geometry
@@ -595,9 +619,9 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                 if (Jmax <= BIRTH_FUSED_MAX && dm.proposal == 1) {
                     weighted = true;
                     LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                           hipLaunchKernelGGL((k_birth_draw_sort<T, 2, 1, true>), dim3(K + zruns), dim3(1024), 0,
-                                              f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M, a.win,
-                                              f->last_step, a.dstep, f->borig, K, f->zprep));
+                           hipLaunchKernelGGL((k_birth_draw_sort<T, 2, 1, true>), dim3(K + zruns + npred), dim3(1024),
+                                              0, f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
+                                              a.win, f->last_step, a.dstep, f->borig, K, f->zprep, zruns, f->bkt));
                     zprep_done = zruns > 0;
                 }
             }
@@ -605,14 +629,16 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                 if (Jmax <= 1024 * BS) {
                     if (dm.proposal == 1)
                         LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1, false>), dim3(K + zruns), dim3(1024), 0,
-                                                  f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
-                                                  a.win, f->last_step, a.dstep, f->borig, K, f->zprep));
+                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 1, false>), dim3(K + zruns + npred),
+                                                  dim3(1024), 0, f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur,
+                                                  a.dz, tab, a.M, a.win, f->last_step, a.dstep, f->borig, K,
+                                                  f->zprep, zruns, f->bkt));
                     else
                         LAUNCH(f, PPHD_K_BIRTH_ORDER,
-                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2, false>), dim3(K + zruns), dim3(1024), 0,
-                                                  f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur, a.dz, tab, a.M,
-                                                  a.win, f->last_step, a.dstep, f->borig, K, f->zprep));
+                               hipLaunchKernelGGL((k_birth_draw_sort<T, BS, 2, false>), dim3(K + zruns + npred),
+                                                  dim3(1024), 0, f->stream, dm, f->gd, st, geo, f->nsurv, f->ncur,
+                                                  a.dz, tab, a.M, a.win, f->last_step, a.dstep, f->borig, K,
+                                                  f->zprep, zruns, f->bkt));
                     zprep_done = zruns > 0;
                 } else {
                     if (dm.proposal == 1)
@@ -736,7 +762,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     LAUNCH(f, PPHD_K_FINALIZE,
            hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
-                              f->fLT, f->rsS, f->sel, f->zeta, f->rtiles, f->bhist, f->boff, f->tsum));
+                              f->fLT, f->rsS, f->sel, f->zeta, f->rtiles, f->bhist, f->boff, f->tsum, f->qtot));
     // k_wfinal and k_finalize have prepared the resampling's parent order
     f->order_ready = true;
     return PPHD_OK;
@@ -760,9 +786,53 @@ pphd_status dispatch_update(pphd_filter* f, const UpdArgs& a)
     return fail(PPHD_EINVAL, "no kernel for tile shape %d/%d", f->pt1, f->pt2);
 }
 
+pphd_status flush_resample(pphd_filter* f);
+
+// births of a measurement-driven proposal drawn and ordered by
+// k_birth_draw_sort, one workgroup per group (the update's launch that can
+// also carry the survivors' prediction)
+template <typename T>
+bool births_in_one_launch(const pphd_filter* f)
+{
+    constexpr int BS = sizeof(T) == 4 ? 8 : 4;
+    return (f->dm.proposal == 1 || f->dm.proposal == 2) && f->Jmax > 0 && f->Jmax <= 1024 * BS;
+}
+
+// workgroups of 1024 slots that predict every group's survivors
+int predict_parts(const pphd_filter* f) { return f->K * ((f->cap + 1023) / 1024); }
+
+template <typename T>
+pphd_status launch_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
+{
+    dim3 g = slot_grid(f, (f->cap + 255) / 256);
+    LAUNCH(f, PPHD_K_PREDICT,
+           hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
+                              f->nsurv, f->ncur, step, dstep, f->bkt));
+    return PPHD_OK;
+}
+
+// a prediction still waiting for the update, launched on its own
+pphd_status flush_predict(pphd_filter* f)
+{
+    if (!f->pr_pending) return PPHD_OK;
+    f->pr_pending = false;
+    return f->prec == PPHD_FP64 ? launch_predict<double>(f, f->pr_step, f->pr_dstep)
+                                : launch_predict<float>(f, f->pr_step, f->pr_dstep);
+}
+
 template <typename T>
 pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
+    pphd_status fs = flush_resample(f);
+    if (fs != PPHD_OK) return fs;
+    if (births_in_one_launch<T>(f)) {
+        // the update draws the births in one launch per step; the survivors'
+        // prediction rides in it (it needs nothing the births change)
+        f->pr_pending = true;
+        f->pr_step = step;
+        f->pr_dstep = dstep;
+        return PPHD_OK;
+    }
     dim3 g = slot_grid(f, (f->cap + 255) / 256);
     LAUNCH(f, PPHD_K_PREDICT,
            hipLaunchKernelGGL((k_predict<T>), g, dim3(256), 0, f->stream, f->dm, f->gd, soa<T>(f, f->cur), geo_of(f),
@@ -798,18 +868,18 @@ pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, i
                                   f->bkt, f->bhist, parents ? 0 : 1));
         LAUNCH(f, cls,
                hipLaunchKernelGGL(k_bk_scan, dim3(f->K), dim3(1024), 0, f->stream, first, f->ncur, f->rtiles,
-                                  f->bhist, f->boff, parents ? f->tsum : nullptr));
+                                  f->bhist, f->boff, parents ? f->tsum : nullptr, f->qtot));
     }
     if (rs_halves(f) == 2)
         LAUNCH(f, cls,
                hipLaunchKernelGGL((k_bk_scatter<T, 2>), slot_grid(f, (tiles + 1) / 2), dim3(256), 0, f->stream, f->dm,
                                   cur, oth, first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS,
-                                  parents ? f->tsum : nullptr, orig));
+                                  parents ? f->tsum : nullptr, orig, f->qtot));
     else
         LAUNCH(f, cls,
                hipLaunchKernelGGL((k_bk_scatter<T, 1>), slot_grid(f, tiles), dim3(256), 0, f->stream, f->dm, cur, oth,
                                   first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr,
-                                  orig));
+                                  orig, f->qtot));
     if (parents) f->order_ready = false;
     return PPHD_OK;
 }
@@ -845,30 +915,49 @@ pphd_status order_births(pphd_filter* f, bool weights_later)
 template <typename T>
 pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
+    // parents into bearing-bucket order (into the other set), with the
+    // resampling's tile sums and group totals; the systematic expansion back
+    // into this set waits for the next call, so that an exchange can ride in it
+    pphd_status s = bucket_order<T>(f, PPHD_K_RS_ORDER, nullptr, f->rtiles);
+    if (s != PPHD_OK) return s;
+    f->cur = 1 - f->cur;
+    f->rs_pending = true;
+    f->rs_step = step;
+    f->rs_dstep = dstep;
+    return PPHD_OK;
+}
+
+// The pending expansion (xchg: with the ring exchange of step xstep fused).
+template <typename T>
+pphd_status run_expand(pphd_filter* f, bool xchg, uint32_t xstep, const uint32_t* xdstep)
+{
     // k_rs_expand: rs_halves 256-slot tiles per workgroup
     const int nh = rs_halves(f);
     dim3 g = slot_grid(f, (f->rtiles + nh - 1) / nh);
-    // parents into bearing-bucket order (into the other set), then the
-    // systematic resampling back into this one
-    {
-        pphd_status s = bucket_order<T>(f, PPHD_K_RS_ORDER, nullptr, f->rtiles);
-        if (s != PPHD_OK) return s;
-        f->cur = 1 - f->cur;
-    }
-    // the tile sums of the ordered parents came with the scatter
     SoA<T> in = soa<T>(f, f->cur), out = soa<T>(f, 1 - f->cur);
+    const int x = xchg ? 1 : 0;
     if (nh == 2)
         LAUNCH(f, PPHD_K_RS_EXPAND,
                hipLaunchKernelGGL((k_rs_expand<T, 2>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
-                                  f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr,
-                                  f->counts, f->record ? 1 : 0));
+                                  f->nsurv, f->rsS, f->tsum, f->rtiles, f->rs_step, f->rs_dstep, f->massq,
+                                  f->clampctr, f->counts, f->record ? 1 : 0, (const double*)f->qtot, x, xstep,
+                                  xdstep));
     else
         LAUNCH(f, PPHD_K_RS_EXPAND,
                hipLaunchKernelGGL((k_rs_expand<T, 1>), g, dim3(256), 0, f->stream, f->dm, f->gd, in, out, f->ncur,
-                                  f->nsurv, f->rsS, f->tsum, f->rtiles, step, dstep, f->massq, f->clampctr,
-                                  f->counts, f->record ? 1 : 0));
+                                  f->nsurv, f->rsS, f->tsum, f->rtiles, f->rs_step, f->rs_dstep, f->massq,
+                                  f->clampctr, f->counts, f->record ? 1 : 0, (const double*)f->qtot, x, xstep,
+                                  xdstep));
     f->cur = 1 - f->cur;
+    f->rs_pending = false;
     return PPHD_OK;
+}
+
+// completes a resampling whose expansion is still pending (no exchange)
+pphd_status flush_resample(pphd_filter* f)
+{
+    if (!f->rs_pending) return PPHD_OK;
+    return f->prec == PPHD_FP64 ? run_expand<double>(f, false, 0, nullptr) : run_expand<float>(f, false, 0, nullptr);
 }
 
 template <typename T>
@@ -879,6 +968,13 @@ pphd_status run_exchange(pphd_filter* f, uint32_t step, const uint32_t* dstep)
     for (const pphd_run_desc& r : f->runs) {
         any = any || r.partitions > 1;
         kmax = std::max(kmax, (int)r.partitions);
+    }
+    // right after the resampling: the exchange rides in its expansion (runs
+    // of up to 1024 groups, whose workgroups each form the run's count)
+    if (f->rs_pending) {
+        if (any && kmax <= 1024) return run_expand<T>(f, true, step, dstep);
+        pphd_status s = run_expand<T>(f, false, 0, nullptr);
+        if (s != PPHD_OK) return s;
     }
     if (!any) return PPHD_OK;
     SoA<T> st = soa<T>(f, f->cur);
@@ -1059,6 +1155,8 @@ pphd_status pphd_destroy(pphd_filter* f)
 pphd_status pphd_init(pphd_filter* f)
 {
     CHECK_HANDLE(f);
+    f->rs_pending = false;  // t = 0 replaces whatever a resampling or a prediction left
+    f->pr_pending = false;
     f->cur = 0;
     pphd_status s = f->prec == PPHD_FP64 ? run_init<double>(f) : run_init<float>(f);
     if (s != PPHD_OK) return s;
@@ -1167,6 +1265,13 @@ pphd_status pphd_exchange(pphd_filter* f, uint32_t step)
 pphd_status pphd_read_state(pphd_filter* f, double* x, double* w, int32_t* count)
 {
     CHECK_HANDLE(f);
+    {
+        // work still pending from the last calls first: a resampling's
+        // expansion, a prediction waiting for the update
+        pphd_status fs = flush_resample(f);
+        if (fs == PPHD_OK) fs = flush_predict(f);
+        if (fs != PPHD_OK) return fs;
+    }
     if (f->phase == 0) return fail(PPHD_ESTATE, "filter has no state yet (call pphd_init or pphd_write_state)");
     const bool current_is_cur = f->phase == PPHD_PHASE_PREDICTED || f->phase == PPHD_PHASE_UPDATED;
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -1198,6 +1303,13 @@ pphd_status pphd_read_state(pphd_filter* f, double* x, double* w, int32_t* count
 pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, const int32_t* count, int32_t phase)
 {
     CHECK_HANDLE(f);
+    {
+        // work still pending from the last calls first: a resampling's
+        // expansion, a prediction waiting for the update
+        pphd_status fs = flush_resample(f);
+        if (fs == PPHD_OK) fs = flush_predict(f);
+        if (fs != PPHD_OK) return fs;
+    }
     if (!x || !w || !count) return fail(PPHD_EINVAL, "x, w and count are required");
     if (phase != PPHD_PHASE_READY && phase != PPHD_PHASE_RESAMPLED && phase != PPHD_PHASE_PREDICTED &&
         phase != PPHD_PHASE_UPDATED)
@@ -1314,6 +1426,13 @@ pphd_status pphd_set_tuning(pphd_filter* f, int32_t pt_cz, int32_t pt_weight, in
 pphd_status pphd_set_record_counts(pphd_filter* f, int32_t enable)
 {
     CHECK_HANDLE(f);
+    {
+        // work still pending from the last calls first: a resampling's
+        // expansion, a prediction waiting for the update
+        pphd_status fs = flush_resample(f);
+        if (fs == PPHD_OK) fs = flush_predict(f);
+        if (fs != PPHD_OK) return fs;
+    }
     f->record = enable != 0;
     return PPHD_OK;
 }
@@ -1321,6 +1440,13 @@ pphd_status pphd_set_record_counts(pphd_filter* f, int32_t enable)
 pphd_status pphd_read_resample(pphd_filter* f, int32_t* counts, double* mass_q, int64_t* clamped)
 {
     CHECK_HANDLE(f);
+    {
+        // work still pending from the last calls first: a resampling's
+        // expansion, a prediction waiting for the update
+        pphd_status fs = flush_resample(f);
+        if (fs == PPHD_OK) fs = flush_predict(f);
+        if (fs != PPHD_OK) return fs;
+    }
     if (f->phase != PPHD_PHASE_RESAMPLED && f->phase != PPHD_PHASE_READY)
         return fail(PPHD_ESTATE, "no resample results (phase %d)", f->phase);
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -1499,6 +1625,10 @@ pphd_status pphd_batch_capture(pphd_filter* f, const double* d_z, int32_t z_coun
         return fail(PPHD_EINVAL, "bad buffers");
     if (f->model.birth_proposal == 2 && f->Jmax > 0 && !f->mlp)
         return fail(PPHD_ESTATE, "birth_proposal 2 needs pphd_attach_mlp");
+    {
+        pphd_status fs = flush_resample(f);
+        if (fs != PPHD_OK) return fs;
+    }
     if (f->z_pending) HIP_TRY(hipEventSynchronize(f->z_done));
     HIP_TRY(hipStreamSynchronize(f->stream));
     HIP_TRY(hipMemcpy(f->dstep, &first_step, 4, hipMemcpyHostToDevice));
@@ -1545,6 +1675,13 @@ pphd_status pphd_batch_capture(pphd_filter* f, const double* d_z, int32_t z_coun
 pphd_status pphd_batch_launch(pphd_filter* f)
 {
     CHECK_HANDLE(f);
+    {
+        // work still pending from the last calls first: a resampling's
+        // expansion, a prediction waiting for the update
+        pphd_status fs = flush_resample(f);
+        if (fs == PPHD_OK) fs = flush_predict(f);
+        if (fs != PPHD_OK) return fs;
+    }
     if (!f->batch || !f->graph_exec[0] || !f->graph_exec[1]) return fail(PPHD_ESTATE, "no captured step (pphd_batch_capture)");
     if (f->phase != PPHD_PHASE_READY && f->phase != PPHD_PHASE_RESAMPLED)
         return fail(PPHD_ESTATE, "launch needs phase READY or RESAMPLED (have %d)", f->phase);
