@@ -187,8 +187,8 @@ def main():
         mlp_info = {"train_s": time.perf_counter() - t0, "train_steps": int(len(losses)),
                     "final_loss": float(np.mean(losses[-50:])), "pairs": 1 << 20}
 
-    def make(q=p, pr=prec):
-        f = pphd.Filter(q, pr, w["cap"], w["max_meas"], seed, args.run)
+    def make(q=p, pr=prec, tuned=True):
+        f = pphd.Filter(q, pr, w["cap"], w["max_meas"], seed, args.run, apply_tuning=tuned)
         if net is not None and int(q.get("birth_proposal", 0)) == 2:
             f.attach_mlp(net)
         return f
@@ -209,8 +209,8 @@ def main():
         f.resample(k)
         f.exchange(k)
 
-    def timed(q=p, pr=prec, one=step):
-        f = make(q, pr)
+    def timed(q=p, pr=prec, one=step, tuned=True):
+        f = make(q, pr, tuned)
         f.init()
         for k in range(1, args.warmup + 1):
             one(f, k)
@@ -255,6 +255,11 @@ def main():
     # ---- pass A: timed ------------------------------------------------------
     elapsed = timed()
     ms_per_step = elapsed * 1e3 / args.steps
+    probe = make()
+    shape = probe.tuning
+    probe.close()
+    # the same steps with the library's default launch shape
+    elapsed_default = timed(tuned=False) if shape else None
     # ---- the same steps with host measurement sets and host estimates -------
     elapsed_pcie = timed(one=step_pcie) if not args.no_pcie else None
 
@@ -337,6 +342,9 @@ def main():
         },
         "ospa_mean": ospa_mean,
         "ospa_params": {"p": 1, "c": 100.0},
+        "tuning": tuning_record(pphd, shape, elapsed, elapsed_default, args.steps, False, prec,
+                                int(p["partitions"]), w["cap"],
+                                float(p["clutter_rate"]) + 10.0),
     }
     if variants:
         line["variants"] = variants
@@ -429,8 +437,8 @@ def bench_batch(args, w):
         mlp_info = {"train_s": time.perf_counter() - t0, "train_steps": int(len(losses)),
                     "final_loss": float(np.mean(losses[-50:])), "pairs": 1 << 20}
 
-    def make_batch():
-        bb = pphd.Batch(p, runs, prec, cap, Mx, seed)
+    def make_batch(tuned=True):
+        bb = pphd.Batch(p, runs, prec, cap, Mx, seed, apply_tuning=tuned)
         if net is not None:
             bb.attach_mlp(net)
         return bb
@@ -451,21 +459,27 @@ def bench_batch(args, w):
         dwin.copy_(wdev[k])
 
     # ---- pass A: timed graph replays ----------------------------------------
-    b = make_batch()
-    b.init()
-    b.capture(dz, R * Mx, dwin, dout, Mx, dn, 1)
-    for k in range(1, args.warmup + 1):
-        fill(k)
-        b.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup + 1, total + 1):
-        fill(k)
-        b.launch()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    b.close()
-    del b
+    def replayed(tuned=True):
+        bb = make_batch(tuned)
+        bb.init()
+        bb.capture(dz, R * Mx, dwin, dout, Mx, dn, 1)
+        for k in range(1, args.warmup + 1):
+            fill(k)
+            bb.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup + 1, total + 1):
+            fill(k)
+            bb.launch()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        shape = bb.tuning
+        bb.close()
+        return el, shape
+
+    elapsed, shape = replayed()
+    # the same replays with the library's default launch shape
+    elapsed_default = replayed(tuned=False)[0] if shape else None
 
     kern, pairs, parts, ospas, pbytes = {}, [], [], [], []
     esz = 4 if prec == pphd.PPHD_FP32 else 8
@@ -572,6 +586,9 @@ def bench_batch(args, w):
         },
         "ospa_mean": float(np.mean(ospas)),
         "ospa_params": {"p": 1, "c": 100.0},
+        "tuning": tuning_record(pphd, shape, elapsed, elapsed_default, args.steps, True, prec,
+                                sum(int(r["partitions"]) for r in runs), cap,
+                                float(np.mean([r["clutter_rate"] for r in runs])) + 10.0),
         "sequential_single_filters_ms_per_step": seq_ms,
         "speedup_vs_sequential": seq_ms / ms_per_step if seq_ms else None,
     }
@@ -596,6 +613,20 @@ def bench_batch(args, w):
         cb["sample"] = what + " from t = 0, " + cb["sample"].split(", ", 1)[-1]
         line["cpu_baseline"] = cb
     return line
+
+
+def tuning_record(pphd, shape, elapsed, elapsed_default, steps, batch, prec, groups, cap, meas):
+    """The autotuned launch shape the run used (pphd.lookup_tuning: its
+    bucket, else the nearest of the same kind) and the measured gain over the
+    library's default shape on the same steps."""
+    rec = {"bucket": pphd.tuning_bucket(prec, batch, groups, cap, meas), "shape": None, "gain_vs_default": None}
+    if shape:
+        rec["shape"] = {k: shape[k] for k in ("pt_cz", "pt_weight", "pass_workgroups", "rs_tiles", "meas_per_wave")
+                        if k in shape}
+        rec["tuned_on"] = shape.get("workload")
+        rec["ms_per_step_default_shape"] = elapsed_default * 1e3 / steps
+        rec["gain_vs_default"] = elapsed_default / elapsed
+    return rec
 
 
 def host_cpu():

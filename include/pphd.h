@@ -254,6 +254,15 @@ pphd_status pphd_read_local(pphd_filter* f, int32_t* sel, double* zeta);
  * update; must not be called between pphd_update and pphd_resample. */
 pphd_status pphd_set_tuning(pphd_filter* f, int32_t pt_cz, int32_t pt_weight, int32_t meas_per_wave);
 
+/* Launch shape of the other tunable kernels (the autotuner's second set of
+ * knobs; results do not change, only the schedule):
+ * pass_workgroups: workgroups of one bearing-frame pass launch (their
+ *   wavefronts stride over the work items); 0 = 1024, else [64, 65535].
+ * rs_tiles: 256-slot tiles per workgroup of the resampling's scatter and
+ *   expansion, 1 or 2; 0 = two where K * cap >= 2^20, else one.
+ * Allowed in any phase. */
+pphd_status pphd_set_launch_shape(pphd_filter* f, int32_t pass_workgroups, int32_t rs_tiles);
+
 /* Enables (1) or disables (0) recording of per-parent child counts in
  * resample, which costs one int32 store per parent. */
 pphd_status pphd_set_record_counts(pphd_filter* f, int32_t enable);

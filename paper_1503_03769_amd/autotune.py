@@ -1,21 +1,30 @@
-"""Tile-shape autotuner for the two likelihood passes of pphd_update.
+"""Launch-shape autotuner of the filter step.
 
-For every tile shape (particles per thread of the C(z) pass and of the weight
-pass, measurements per wavefront) it runs the named workload (a single filter
-or a batch of runs) from t = 0 and
-averages the passes' HIP-event times (C(z) pass + weight pass + k_wfinal
-where it runs) over a
-window of steady-state steps.  The fastest shape is written to tuning.json
-next to this file, keyed by storage precision (and "_batch" for batches);
-`pphd.Filter` and `pphd.Batch` apply it by default.  The shape changes only floating-point summation order.
+For a named workload (a single filter or a batch of runs) it sweeps
+  - particles per thread of the C(z) pass and of the weight pass,
+  - workgroups per bearing-frame pass launch (the grid whose wavefronts
+    stride over the passes' work items),
+  - 256-slot tiles per workgroup of the resampling scatter and expansion,
+and times whole steps (eager launches, measurement sets resident in device
+memory, wall clock between synchronisations over a window of steady-state
+steps).  The fastest shape goes into tuning.json next to this file under the
+workload's bucket (precision, single filter or batch, rounded log2 of the
+groups, of the slots per group and of the expected measurements per run; see
+pphd.tuning_bucket), with the default shape's time beside it.  pphd.Filter
+and pphd.Batch look their bucket up (else the nearest one of the same kind)
+when they are created.  The measurements-per-wavefront knob only matters for
+the passes without bearing frames (no clutter), so it is swept only there.
+Particles per thread change the floating-point summation order; the other
+knobs change only the schedule.
 
-    python -m paper_1503_03769_amd.autotune [--workload NAME] [--steps A B]
+    python -m paper_1503_03769_amd.autotune [--workloads NAME ...] [--steps A B]
 """
 import argparse
 import itertools
 import json
 import os
 import sys
+import time
 
 import numpy as np
 
@@ -23,89 +32,132 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 SHAPES = {"fp32": [4, 8, 16], "fp64": [2, 4, 8]}
-MEAS_PER_WAVE = [8, 16, 32, 64, 128, 256]
+PASS_WORKGROUPS = [512, 1024, 2048]
+RS_TILES = [1, 2]
+MEAS_PER_WAVE = [8, 16, 32, 64]
 
 
-def tune(workload: str, first: int, last: int, verbose: bool = True, meas_per_wave=None):
+def _setup(workload, last):
+    """(make(shape or None), step(f, k), bucket) for a workload; make(None)
+    builds the filter with the library's default shape."""
     import torch
 
     from . import pphd
-    from .scenario import WORKLOADS, make_scenario, workload_seed
-
-    from .scenario import batch_runs
+    from .scenario import WORKLOADS, make_scenario, workload_runs, workload_seed
 
     w = WORKLOADS[workload]
     p = w["model"]
-    prec_name = w["precision"]
-    prec = pphd.PPHD_FP32 if prec_name == "fp32" else pphd.PPHD_FP64
+    prec = pphd.PPHD_FP32 if w["precision"] == "fp32" else pphd.PPHD_FP64
     seed = workload_seed(w["config_index"], 0)
+    net = None
+    if int(p.get("birth_proposal", 0)) == 2:
+        from .proposal import train_proposal
+        net, _ = train_proposal(p, seed=1)
+
+    def shape(f, sh):
+        if sh is not None:
+            f.set_tuning(sh["pt_cz"], sh["pt_weight"], sh["meas_per_wave"])
+            f.set_launch_shape(sh["pass_workgroups"], sh["rs_tiles"])
+        if net is not None:
+            f.attach_mlp(net)
+        return f
+
     if w.get("batch"):
-        runs, targets = batch_runs(w["n_runs"], seed)
-        scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), targets[i], last, seed + 7919 * (i + 1))
+        runs, targets = workload_runs(w, seed)
+        scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), targets[i], last, seed + 7919 * (i + 1),
+                              turn_sigma=w.get("turn_sigma", 0.0))
                 for i, r in enumerate(runs)]
         packs = [None] + [pphd.Batch.pack([scen[i][1][k] for i in range(len(runs))]) for k in range(1, last + 1)]
         zdev = [None] + [(torch.from_numpy(z).cuda(), torch.from_numpy(win).cuda()) for z, win in packs[1:]]
 
-        def make():
-            return pphd.Batch(p, runs, prec, w["cap"], w["max_meas"], seed, apply_tuning=False)
+        def make(sh):
+            return shape(pphd.Batch(p, runs, prec, w["cap"], w["max_meas"], seed, apply_tuning=False), sh)
 
         def update(f, k):
             f.update_device(zdev[k][0], zdev[k][0].shape[0], zdev[k][1])
+        lam = float(np.mean([float(r["clutter_rate"]) for r in runs]))
+        bucket = pphd.tuning_bucket(prec, True, sum(int(r["partitions"]) for r in runs), w["cap"], lam + 10.0)
     else:
         truth, Z = make_scenario(p, w["n_targets"], last, seed)
         zdev = [None] + [torch.from_numpy(np.ascontiguousarray(Z[k])).cuda() for k in range(1, last + 1)]
 
-        def make():
-            return pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, 0, apply_tuning=False)
+        def make(sh):
+            return shape(pphd.Filter(p, prec, w["cap"], w["max_meas"], seed, 0, apply_tuning=False), sh)
 
         def update(f, k):
             f.update(zdev[k])
+        bucket = pphd.tuning_bucket(prec, False, int(p["partitions"]), w["cap"], float(p["clutter_rate"]) + 10.0)
+
+    def step(f, k):
+        f.predict(k)
+        update(f, k)
+        f.resample(k)
+        f.exchange(k)
+
+    frames = float(p["clutter_rate"]) > 0.0
+    return make, step, bucket, w["precision"], frames
+
+
+def time_shape(make, step, sh, first, last):
+    """Wall-clock milliseconds per step over steps first..last."""
+    import torch
+    f = make(sh)
+    f.init()
+    for k in range(1, first):
+        step(f, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(first, last + 1):
+        step(f, k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    f.close()
+    return 1e3 * el / (last - first + 1)
+
+
+def tune(workload: str, first: int, last: int, verbose: bool = True):
+    make, step, bucket, prec_name, frames = _setup(workload, last)
+    mzs = [16] if frames else MEAS_PER_WAVE
+    base = time_shape(make, step, None, first, last)
+    if verbose:
+        print(f"{workload} ({bucket}): default shape {base:.4f} ms per step", flush=True)
     results = []
-    for pt1, pt2, mz in itertools.product(SHAPES[prec_name], SHAPES[prec_name], meas_per_wave or MEAS_PER_WAVE):
-        f = make()
-        f.set_tuning(pt1, pt2, mz)
-        f.init()
-        for k in range(1, last + 1):
-            if k == first:
-                f.set_timing(True)
-            f.predict(k)
-            update(f, k)
-            f.resample(k)
-            f.exchange(k)
-        t = f.read_timing()
-        f.close()
-        n = max(t["cz"][1], 1)
-        us = 1e3 * (t["cz"][0] + t["weight"][0] + t["wfinal"][0]) / n
-        results.append((us, pt1, pt2, mz))
+    for pt1, pt2, pw, rt, mz in itertools.product(SHAPES[prec_name], SHAPES[prec_name], PASS_WORKGROUPS, RS_TILES,
+                                                  mzs):
+        sh = dict(pt_cz=pt1, pt_weight=pt2, pass_workgroups=pw, rs_tiles=rt, meas_per_wave=mz)
+        ms = time_shape(make, step, sh, first, last)
+        results.append((ms, sh))
         if verbose:
-            print(f"pt_cz={pt1:2d} pt_weight={pt2:2d} meas_per_wave={mz:3d}: {us:8.2f} us per update "
-                  f"(cz {1e3 * t['cz'][0] / n:6.2f}, weight {1e3 * t['weight'][0] / n:6.2f})", flush=True)
-    results.sort()
-    us, pt1, pt2, mz = results[0]
-    return dict(pt_cz=pt1, pt_weight=pt2, meas_per_wave=mz, passes_us=us, workload=workload,
-                steps=[first, last]), results
+            print(f"  pt_cz={pt1:2d} pt_weight={pt2:2d} pass_workgroups={pw:5d} rs_tiles={rt} "
+                  f"meas_per_wave={mz:3d}: {ms:.4f} ms per step", flush=True)
+    results.sort(key=lambda r: r[0])
+    # the winner timed once more, against the default right after it
+    ms_best, best = results[0]
+    again = time_shape(make, step, best, first, last)
+    base2 = time_shape(make, step, None, first, last)
+    entry = dict(best, ms_per_step=min(ms_best, again), default_ms_per_step=min(base, base2), workload=workload,
+                 steps=[first, last])
+    return bucket, entry, results
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="large_fp32_10tgt_k64")
-    ap.add_argument("--steps", type=int, nargs=2, default=[20, 40])
+    ap.add_argument("--workloads", nargs="+",
+                    default=["large_fp32_10tgt_k64", "batch_fp32_256runs", "learned_fp32_10tgt",
+                             "dense_ct_fp32_16runs", "plain_fp64_3tgt"])
+    ap.add_argument("--steps", type=int, nargs=2, default=[11, 30])
     ap.add_argument("--out", default=TUNING_PATH)
-    ap.add_argument("--meas-per-wave", type=int, nargs="+", default=None,
-                    help="the measurement chunks to try (the bearing-frame passes of workloads with clutter "
-                         "take all of a run's measurements per wavefront and ignore it)")
     args = ap.parse_args()
-    best, _ = tune(args.workload, args.steps[0], args.steps[1], meas_per_wave=args.meas_per_wave)
     data = {}
     if os.path.exists(args.out):
         with open(args.out) as fh:
-            data = json.load(fh)
-    from .scenario import WORKLOADS
-    w = WORKLOADS[args.workload]
-    data[w["precision"] + ("_batch" if w.get("batch") else "")] = best
-    with open(args.out, "w") as fh:
-        json.dump(data, fh, indent=1, sort_keys=True)
-    print(json.dumps(best), flush=True)
+            data = {k: v for k, v in json.load(fh).items() if "/" in k}
+    for wl in args.workloads:
+        bucket, entry, _ = tune(wl, args.steps[0], args.steps[1])
+        data[bucket] = entry
+        print(json.dumps({bucket: entry}), flush=True)
+        with open(args.out, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":

@@ -51,6 +51,9 @@ pphd_status fail(pphd_status s, const char* fmt, ...)
 // at most ZSPLIT_MAX chunks).  Workspace arrays are sized for the smallest PT.
 constexpr int PT_DEFAULT_F32 = 8, PT_DEFAULT_F64 = 4, PT_MIN_F32 = 4, PT_MIN_F64 = 2, PR = 1;
 constexpr int MZ_DEFAULT = 16;
+// workgroups of one bearing-frame pass launch (about what the chip keeps
+// resident at these kernels' register use)
+constexpr int PASS_WGS_DEFAULT = 1024;
 
 const char* kKernelNames[PPHD_K_COUNT] = {
     "k_predict", "k_cz", "k_cz_combine", "k_weight", "k_finalize", "k_fuse",
@@ -123,6 +126,8 @@ struct pphd_filter {
     bool timing = false;
     int wt1 = 0, wt2 = 0, wtiles1 = 0, wtiles2 = 0, rtiles = 0, Lmax = 0, tiles256 = 0;
     int pt1 = 0, pt2 = 0, mz = MZ_DEFAULT, wtiles_max = 0;
+    int pass_wgs = PASS_WGS_DEFAULT;  // workgroups of a bearing-frame pass launch
+    int rs_tiles = 0;                 // 256-slot tiles per resampling workgroup (0: by capacity)
     // device arrays (inside the workspace)
     void* X[2][5] = {};  // component arrays of the two particle sets (X[.][4] with dim 5 only)
     int dim = 4;
@@ -499,7 +504,14 @@ dim3 slot_grid(const pphd_filter* f, int tiles)
 // where the capacity spans 4096 or more such workgroups (two reads per
 // thread in flight, half the dispatch rounds), one for small filters, whose
 // workgroups would not fill the chip
-int rs_halves(const pphd_filter* f) { return (size_t)f->K * f->cap >= ((size_t)1 << 20) ? 2 : 1; }
+// 256-slot tiles per workgroup of the resampling scatter and expansion: as
+// set by pphd_set_launch_shape, else two where the capacity spans at least
+// 2^20 slots
+int rs_halves(const pphd_filter* f)
+{
+    if (f->rs_tiles == 1 || f->rs_tiles == 2) return f->rs_tiles;
+    return (size_t)f->K * f->cap >= ((size_t)1 << 20) ? 2 : 1;
+}
 
 // zsplit of a measurement count, as the passes derive it
 int host_zsplit(int M, int mz)
@@ -678,7 +690,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     // the chip holds at these kernels' register use; at most the items a
     // group can have)
     auto xdim = [&](int wtiles) {
-        const int64_t most = ((int64_t)wtiles * BIRTH_CHUNKS + 3) / 4, want = (1024 + K - 1) / K;
+        const int64_t most = ((int64_t)wtiles * BIRTH_CHUNKS + 3) / 4, want = (f->pass_wgs + K - 1) / K;
         return (unsigned)std::max<int64_t>(1, std::min(most, want));
     };
     dim3 gl1(K, xdim(f->wtiles1)), gl2(K, xdim(f->wtiles2));
@@ -705,8 +717,8 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
             ipre2 = ipre1;
             igrp2 = igrp1;
         }
-        gl1 = dim3(1024);
-        gl2 = dim3(1024);
+        gl1 = dim3(f->pass_wgs);
+        gl2 = dim3(f->pass_wgs);
     }
     if (f->pass_mode == PASS_FRAMES) {
         if (!zprep_done)
@@ -1420,6 +1432,16 @@ pphd_status pphd_set_tuning(pphd_filter* f, int32_t pt_cz, int32_t pt_weight, in
     f->wt2 = 64 * f->pt2;
     f->wtiles1 = (int)((f->cap + f->wt1 - 1) / f->wt1);
     f->wtiles2 = (int)((f->cap + f->wt2 - 1) / f->wt2);
+    return PPHD_OK;
+}
+pphd_status pphd_set_launch_shape(pphd_filter* f, int32_t pass_workgroups, int32_t rs_tiles)
+{
+    CHECK_HANDLE(f);
+    if (pass_workgroups != 0 && (pass_workgroups < 64 || pass_workgroups > 65535))
+        return fail(PPHD_EINVAL, "pass_workgroups must be 0 or in [64, 65535]");
+    if (rs_tiles < 0 || rs_tiles > 2) return fail(PPHD_EINVAL, "rs_tiles must be 0, 1 or 2");
+    f->pass_wgs = pass_workgroups ? pass_workgroups : PASS_WGS_DEFAULT;
+    f->rs_tiles = rs_tiles;
     return PPHD_OK;
 }
 

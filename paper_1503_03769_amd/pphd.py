@@ -93,6 +93,7 @@ SIGNATURES = {
     "pphd_read_local": (_I32, [_P, _P, _P]),
     "pphd_set_record_counts": (_I32, [_P, _I32]),
     "pphd_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
+    "pphd_set_launch_shape": (_I32, [_P, _I32, _I32]),
     "pphd_read_resample": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
     "pphd_set_timing": (_I32, [_P, _I32]),
     "pphd_read_timing": (_I32, [_P, _P, _P]),
@@ -244,6 +245,10 @@ def pphd_read_local(h, sel_ptr, zeta_ptr):
     _chk(lib().pphd_read_local(h, sel_ptr, zeta_ptr))
 
 
+def pphd_set_launch_shape(h, pass_workgroups, rs_tiles):
+    _chk(lib().pphd_set_launch_shape(h, pass_workgroups, rs_tiles))
+
+
 def pphd_set_tuning(h, pt_cz, pt_weight, meas_per_wave):
     _chk(lib().pphd_set_tuning(h, int(pt_cz), int(pt_weight), int(meas_per_wave)))
 
@@ -379,12 +384,53 @@ TUNING_PATH = os.path.join(_HERE, "tuning.json")
 
 
 def load_tuning():
-    """Tile shapes chosen by the autotuner (autotune.py), keyed by precision."""
+    """The autotuner's table (autotune.py): launch shapes keyed by bucket."""
     import json
     if os.path.exists(TUNING_PATH):
         with open(TUNING_PATH) as fh:
             return json.load(fh)
     return {}
+
+
+def tuning_bucket(precision: int, batch: bool, groups: int, cap: int, measurements: float) -> str:
+    """Key of the autotuner's table: storage precision, single filter or batch,
+    and the rounded base-2 logarithms of the groups over all runs, of the
+    slots per group (the capacity, which sizes every grid) and of the expected
+    measurements per run (clutter rate plus ten)."""
+    import math
+
+    def lg(v):
+        return int(round(math.log2(max(v, 1))))
+    kind = ("fp64" if precision == PPHD_FP64 else "fp32") + ("_batch" if batch else "")
+    return f"{kind}/g{lg(groups)}/cap{lg(cap)}/m{lg(measurements)}"
+
+
+def lookup_tuning(precision: int, batch: bool, groups: int, cap: int, measurements: float):
+    """The tuned shape of this bucket, else of the nearest bucket of the same
+    kind (precision, single or batch), else None (the library's defaults)."""
+    import re
+    table = load_tuning()
+    key = tuning_bucket(precision, batch, groups, cap, measurements)
+    if key in table:
+        return table[key]
+    kind = key.split("/")[0]
+    want = [int(v) for v in re.findall(r"-?\d+", key.split("/", 1)[1])]
+    best, dist = None, None
+    for k, v in table.items():
+        parts = k.split("/")
+        if len(parts) != 4 or parts[0] != kind:
+            continue
+        have = [int(x) for x in re.findall(r"-?\d+", k.split("/", 1)[1])]
+        d = sum(abs(a - b) for a, b in zip(have, want))
+        if dist is None or d < dist:
+            best, dist = v, d
+    return best
+
+
+def apply_tuning_to(h, t):
+    if t:
+        pphd_set_tuning(h, t["pt_cz"], t["pt_weight"], t.get("meas_per_wave", 16))
+        pphd_set_launch_shape(h, t.get("pass_workgroups", 0), t.get("rs_tiles", 0))
 
 
 # ---- convenience object (allocation through torch, arrays through numpy) ---
@@ -414,10 +460,10 @@ class Filter:
         self.h = pphd_create(self.model, self.cap, self.max_meas, aligned, nbytes, int(seed), int(run_id),
                              self.stream.cuda_stream)
         self.last_m = 0
+        self.tuning = None
         if apply_tuning:
-            t = load_tuning().get("fp64" if self.precision == PPHD_FP64 else "fp32")
-            if t:
-                pphd_set_tuning(self.h, t["pt_cz"], t["pt_weight"], t["meas_per_wave"])
+            self.tuning = lookup_tuning(self.precision, False, self.K, self.cap, float(params["clutter_rate"]) + 10.0)
+            apply_tuning_to(self.h, self.tuning)
 
     def close(self):
         if getattr(self, "h", None) is not None:
@@ -505,6 +551,9 @@ class Filter:
     def set_tuning(self, pt_cz, pt_weight, meas_per_wave):
         pphd_set_tuning(self.h, pt_cz, pt_weight, meas_per_wave)
 
+    def set_launch_shape(self, pass_workgroups, rs_tiles):
+        pphd_set_launch_shape(self.h, pass_workgroups, rs_tiles)
+
     def attach_mlp(self, mlp):
         """Network whose mixtures the births of birth_proposal 2 draw from."""
         pphd_attach_mlp(self.h, mlp.h if mlp is not None else None)
@@ -578,12 +627,11 @@ class Batch(Filter):
         self.h = pphd_batch_create(self.model, ctypes.addressof(self._table), self.nruns, self.cap, self.max_meas,
                                    aligned, nbytes, int(seed), self.stream.cuda_stream)
         self.last_m = 0
+        self.tuning = None
         if apply_tuning:
-            key = "fp64" if self.precision == PPHD_FP64 else "fp32"
-            tun = load_tuning()
-            t = tun.get(key + "_batch", tun.get(key))
-            if t:
-                pphd_set_tuning(self.h, t["pt_cz"], t["pt_weight"], t["meas_per_wave"])
+            lam = float(np.mean([float(r["clutter_rate"]) for r in runs]))
+            self.tuning = lookup_tuning(self.precision, True, self.K, self.cap, lam + 10.0)
+            apply_tuning_to(self.h, self.tuning)
 
     @staticmethod
     def pack(Zs):

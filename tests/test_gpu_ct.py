@@ -53,13 +53,13 @@ def test_ct_batch_with_learned_proposal_equals_singles(gpu):
     net = pphd.Mlp(p, batch=512, dataset=4096, seed=3)
     net.set_params(random_mlp_params(21, scale=0.5))
     scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), 3, steps, 50 + i) for i, r in enumerate(runs)]
-    b = pphd.Batch(p, runs, pphd.PPHD_FP32, cap, maxm, seed)
+    b = pphd.Batch(p, runs, pphd.PPHD_FP32, cap, maxm, seed, apply_tuning=False)
     b.attach_mlp(net)
     singles = []
     for r in runs:
         q = dict(p, partitions=r["partitions"], births_per_step=r["births_per_step"],
                  clutter_rate=r["clutter_rate"], particles_per_target=r["particles_per_target"])
-        f = pphd.Filter(q, pphd.PPHD_FP32, cap, maxm, seed, r["run_id"])
+        f = pphd.Filter(q, pphd.PPHD_FP32, cap, maxm, seed, r["run_id"], apply_tuning=False)
         f.attach_mlp(net)
         singles.append(f)
     b.init()

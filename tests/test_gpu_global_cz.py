@@ -119,8 +119,9 @@ def test_global_batch_equals_single_filters(gpu):
             for r, lam in enumerate((10.0, 40.0, 25.0))]
     cap, Mx = 2048, 128
     scen = [make_scenario(dict(p, clutter_rate=r["clutter_rate"]), 4, 3, 90 + i) for i, r in enumerate(runs)]
-    b = pphd.Batch(p, runs, pphd.PPHD_FP32, cap, Mx, 55)
-    singles = [pphd.Filter(dict(p, clutter_rate=r["clutter_rate"]), pphd.PPHD_FP32, cap, Mx, 55, r["run_id"])
+    b = pphd.Batch(p, runs, pphd.PPHD_FP32, cap, Mx, 55, apply_tuning=False)
+    singles = [pphd.Filter(dict(p, clutter_rate=r["clutter_rate"]), pphd.PPHD_FP32, cap, Mx, 55, r["run_id"],
+                           apply_tuning=False)
                for r in runs]
     b.init()
     for f in singles:
