@@ -785,8 +785,10 @@ int orc_exchange(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
 /* The textbook particle PHD filter of section 2.2 on one particle set,      */
 /* written separately from the grouped functions above: Eq 5 (survivors),    */
 /* Eq 6 (births), Eq 7 (C_k), Eq 8 (weights), then the mass N_k and the      */
-/* resampling of the same section.  It uses the same random streams as the   */
-/* grouped filter with one group, so the two must agree when K = 1.          */
+/* resampling of the same section, with no reordering of the particles.  It  */
+/* uses the same random streams as the grouped filter with one group, so at  */
+/* K = 1 the two agree up to the order of the births and of the parents     */
+/* (the grouped filter's bearing order).                                     */
 /* Wupd receives the updated (pre-resampling) weights.                       */
 /* ------------------------------------------------------------------------ */
 int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
@@ -826,25 +828,6 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
         XS(X, 3, i) = m->birth_sigma_v * v2;
         W[i] = m->birth_mass / (double)Jk;
     }
-    /* the births in bearing-bucket order over their slots: listed bucket by
-     * bucket, drawing order inside a bucket */
-    if (Jk > 1) {
-        double* bx = (double*)malloc(sizeof(double) * 5 * (size_t)Jk);
-        if (!bx) return -2;
-        int len = 0;
-        for (int b = 0; b < 64; ++b)
-            for (int i = L0; i < L0 + Jk; ++i)
-                if (orc_bearing_bucket(m, XS(X, 0, i), XS(X, 2, i)) == b) {
-                    for (int d = 0; d < 4; ++d) bx[5 * len + d] = XS(X, d, i);
-                    bx[5 * len + 4] = W[i];
-                    ++len;
-                }
-        for (int k = 0; k < Jk; ++k) {
-            for (int d = 0; d < 4; ++d) XS(X, d, L0 + k) = bx[5 * k + d];
-            W[L0 + k] = bx[5 * k + 4];
-        }
-        free(bx);
-    }
     int N = L0 + Jk;
     n[0] = N;
     /* 2) update, Eq 7 and Eq 8 */
@@ -862,21 +845,18 @@ int orc_textbook_step(const orc_model* m, int cap, uint32_t step, uint64_t seed,
         Wupd[i] = bracket * W[i];
     }
     free(Ck);
-    /* 3) resampling: mass N_k, then L_k = round(N_k R) systematic draws.
-     * Same quantisation and point rule as the grouped filter, over the
-     * particles listed bucket by bucket (bearing buckets ascending, slot order
-     * inside a bucket). */
+    /* 3) resampling: mass N_k, then L_k = round(N_k R) systematic draws over
+     * the particles in slot order (births in drawing order after the
+     * survivors; no reordering anywhere in this filter).  Same quantisation
+     * and point rule as the grouped filter, so the two draw the same number
+     * of children from the same weights, each parent's count being the floor
+     * or the ceiling of L_k w_i / sum w in either order. */
     double wmax = 0.0;
     for (int i = 0; i < N; ++i) if (Wupd[i] > wmax) wmax = Wupd[i];
     uint64_t* q = (uint64_t*)calloc((size_t)(N > 0 ? N : 1), sizeof(uint64_t));
     int* list = (int*)calloc((size_t)(N > 0 ? N : 1), sizeof(int));
     if (!q || !list) { free(q); free(list); return -2; }
-    {
-        int len = 0;
-        for (int b = 0; b < 64; ++b)
-            for (int i = 0; i < N; ++i)
-                if (orc_bearing_bucket(m, XS(X, 0, i), XS(X, 2, i)) == b) list[len++] = i;
-    }
+    for (int i = 0; i < N; ++i) list[i] = i;
     uint64_t Q = 0;
     int S = 0;
     if (N > 0 && wmax > 0.0) {

@@ -53,25 +53,57 @@ def test_fuse_single_group_keeps_all(orc):
 
 def test_grouped_filter_with_one_group_is_the_textbook_filter(orc):
     """Algorithm 1 with K = 1 reduces to the particle PHD filter of section 2.2
-    (Eqs 5-8 and its resampling); both consume the same random streams."""
+    (Eqs 5-8 and systematic resampling), written separately in the oracle
+    with no particle reordering.  One step of each from the same state, at
+    eight states of the grouped filter's run: the predicted survivors agree
+    slot by slot, the births agree as a set (the same Philox draws; the
+    grouped filter puts them in bearing order), every updated weight agrees,
+    and both resamplings draw the same number of children with the same
+    weight, each parent getting the floor or the ceiling of L w_i / sum w in
+    both (so their counts differ by at most one)."""
     p = dict(BASE_MODEL, partitions=1, particles_per_target=300.0, births_per_step=150)
     truth, Z = make_scenario(p, 3, 8, 77)
     cap = 4096
     seed, run = 21, 2
     g = orc.State(1, cap)
     orc.init(p, g, seed, run)
+
+    def key_order(X, W, n):
+        return np.lexsort(np.vstack([W[:n], X[::-1, :n]]))
+
     for k in range(1, 9):
         t = g.copy()
+        L0 = int(g.n[0])
         orc.predict(p, g, k, seed, run)
         orc.update(p, g, Z[k])
         Wupd, res = orc.textbook_step(p, t, k, seed, run, Z[k])
         n = int(g.n[0])
         assert int(t.n[0]) == n
-        assert np.array_equal(t.X[:, :n], g.X[:, :n])          # Eq 5 / Eq 6 draws coincide
-        assert np.allclose(Wupd[:n], g.W[:n], rtol=1e-13, atol=0)   # Eq 8 vs Eqs 12-15
-        g, counts, mq = orc.resample(p, g, k, seed, run)
-        L = int(g.n[0])
-        assert int(res.n[0]) == L and int(counts.sum()) == L
-        assert np.array_equal(res.X[:, :L], g.X[:, :L])
-        assert np.allclose(res.W[:L], g.W[:L], rtol=1e-13, atol=0)
-        orc.exchange(p, g, k, seed, run)                        # a no-op at K = 1
+        # Eq 5: survivors in place; Eq 6: the same births, in another order
+        assert np.array_equal(t.X[:, :L0], g.X[:, :L0])
+        og, ot = key_order(g.X, np.zeros(cap), n), key_order(t.X, np.zeros(cap), n)
+        assert np.array_equal(t.X[:, ot], g.X[:, og])
+        # Eq 8 against Eqs 12-15, particle by particle
+        np.testing.assert_allclose(Wupd[ot], g.W[og], rtol=1e-13, atol=0)
+        assert len(np.unique(g.X[0, :n])) == n  # states identify particles below
+        parents_g = {x: i for i, x in enumerate(g.X[0, :n])}
+        gr, counts_g, mq = orc.resample(p, g, k, seed, run)
+        L = int(gr.n[0])
+        assert int(res.n[0]) == L and int(counts_g.sum()) == L
+        np.testing.assert_allclose(res.W[:L], gr.W[:L], rtol=1e-13, atol=0)
+        # each parent's children in the textbook draw (children are copies)
+        counts_t = np.zeros(n, dtype=np.int64)
+        for x in res.X[0, :L]:
+            counts_t[parents_g[x]] += 1
+        assert counts_t.sum() == L
+        # the grouped filter's counts follow its bearing order of the parents
+        counts_by_slot = np.zeros(n, dtype=np.int64)
+        for x in gr.X[0, :L]:
+            counts_by_slot[parents_g[x]] += 1
+        W = g.W[:n]
+        ideal = L * W / W.sum()
+        for c in (counts_t, counts_by_slot):
+            assert np.all(c >= np.floor(ideal) - 1e-9) and np.all(c <= np.ceil(ideal) + 1e-9)
+        assert np.abs(counts_t - counts_by_slot).max() <= 1
+        orc.exchange(p, gr, k, seed, run)                       # a no-op at K = 1
+        g = gr
