@@ -126,7 +126,7 @@ def parse():
     ap.add_argument("--no-pcie", action="store_true",
                     help="skip the pass with host measurement sets and host estimates (for profiler runs)")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the FP64 and uniform-birth variants of the workload")
+                    help="skip the FP64 and uniform-birth variants of the workload and the default-shape pass")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch workloads: skip the run-by-run comparison pass (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -259,7 +259,7 @@ def main():
     shape = probe.tuning
     probe.close()
     # the same steps with the library's default launch shape
-    elapsed_default = timed(tuned=False) if shape else None
+    elapsed_default = timed(tuned=False) if shape and not args.no_variants else None
     # ---- the same steps with host measurement sets and host estimates -------
     elapsed_pcie = timed(one=step_pcie) if not args.no_pcie else None
 
@@ -479,7 +479,7 @@ def bench_batch(args, w):
 
     elapsed, shape = replayed()
     # the same replays with the library's default launch shape
-    elapsed_default = replayed(tuned=False)[0] if shape else None
+    elapsed_default = replayed(tuned=False)[0] if shape and not args.no_variants else None
 
     kern, pairs, parts, ospas, pbytes = {}, [], [], [], []
     esz = 4 if prec == pphd.PPHD_FP32 else 8
@@ -624,8 +624,9 @@ def tuning_record(pphd, shape, elapsed, elapsed_default, steps, batch, prec, gro
         rec["shape"] = {k: shape[k] for k in ("pt_cz", "pt_weight", "pass_workgroups", "rs_tiles", "meas_per_wave")
                         if k in shape}
         rec["tuned_on"] = shape.get("workload")
-        rec["ms_per_step_default_shape"] = elapsed_default * 1e3 / steps
-        rec["gain_vs_default"] = elapsed_default / elapsed
+        if elapsed_default:
+            rec["ms_per_step_default_shape"] = elapsed_default * 1e3 / steps
+            rec["gain_vs_default"] = elapsed_default / elapsed
     return rec
 
 

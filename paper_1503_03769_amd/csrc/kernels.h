@@ -1622,9 +1622,17 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
 // measurement's (S, H) of its group, and C = 2^H S; k_cz_global does the rest.
 // grid (K), 1024 threads, dynamic LDS Mmax doubles.
 // ---------------------------------------------------------------------------
+// this thread's share of the group's tile weight sums (threads take tiles
+// tid, tid + 1024, ...), read ahead of the candidates that use it
+__device__ __forceinline__ double tile_weight_share(const double* __restrict__ pw, int j, int wtiles, int nw)
+{
+    double wsum = 0.0;
+    for (int t = threadIdx.x; t < nw; t += 1024) wsum += pw[(size_t)j * wtiles + t];
+    return wsum;
+}
+
 template <typename T>
-__device__ __forceinline__ void combine_candidates(const DevModel& m, const Grp& gr, int j, int M, int nw,
-                                                   const double* __restrict__ pw, int wtiles,
+__device__ __forceinline__ void combine_candidates(const DevModel& m, const Grp& gr, int j, int M, double wsum,
                                                    const double* __restrict__ sm_dw, int zoff,
                                                    const int* __restrict__ zpos, ZSorted<T> zsort, size_t zb,
                                                    int* __restrict__ zflag, int* __restrict__ cand,
@@ -1633,8 +1641,6 @@ __device__ __forceinline__ void combine_candidates(const DevModel& m, const Grp&
     __shared__ double s_red[16];
     __shared__ int s_redi[16];
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
-    double wsum = 0.0;
-    for (int t = tid; t < nw; t += 1024) wsum += pw[(size_t)j * wtiles + t];
     double dsum = 0.0;
     int pos = 0;
     for (int q = tid; q < M; q += 1024) {
@@ -1698,6 +1704,7 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
     const int n = ncur[j];
     const int nw = (n + WT - 1) / WT;
     const size_t zb = (size_t)j * Mmax;
+    const double wsum = zS ? 0.0 : tile_weight_share(pw, j, wtiles, nw);
     __shared__ int s_h[16][64];
     __shared__ double s_s[16][64];
     constexpr int RC = 8;  // tiles per wavefront whose loads are in flight together
@@ -1775,7 +1782,7 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
     }
     if (zS) return;
     __syncthreads();
-    combine_candidates<T>(m, gr, j, M, nw, pw, wtiles, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
+    combine_candidates<T>(m, gr, j, M, wsum, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
 }
 
 // ---------------------------------------------------------------------------
@@ -1808,6 +1815,7 @@ __global__ __launch_bounds__(1024) void k_cz_global(DevModel m, const Grp* __res
     const int zoff = win ? win[gr.run].off : 0;
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t zb = (size_t)j * Mmax;
+    const double wsum = tile_weight_share(pw, j, wtiles, (ncur[j] + WT - 1) / WT);
     for (int p = wv; p < M; p += 16) {
         int hl = -2147483647 - 1;
         for (int q0 = 0; q0 < gr.K; q0 += 64) {
@@ -1851,8 +1859,7 @@ __global__ __launch_bounds__(1024) void k_cz_global(DevModel m, const Grp* __res
         }
     }
     __syncthreads();
-    const int nw = (ncur[j] + WT - 1) / WT;
-    combine_candidates<T>(m, gr, j, M, nw, pw, wtiles, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
+    combine_candidates<T>(m, gr, j, M, wsum, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
 }
 
 // ---------------------------------------------------------------------------
@@ -2137,53 +2144,44 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
 #pragma unroll
         for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = 0.0;
     }
-    __shared__ double s_ms, s_mm;
+    // Every read that does not wait for the group's mass goes out first: the
+    // tile masses and maxima (wavefront 0), the first round of candidate
+    // labels' partial sums (labels c, c + 4, c + 8, c + 12 of wavefront c,
+    // those below the candidate count; the count LT decides later which are
+    // kept), and, inside bucket_offsets, the tiles' bucket histograms.
+    const int nc = ncand[j];
+    const int nw = (n + WT2 - 1) / WT2;
+    double ms = 0.0, mm = 0.0;
     if (wv == 0) {
-        double ms = 0.0, mm = 0.0;
 #pragma unroll 4
         for (int t = lane; t < nt; t += 64) {
             ms += pmass[(size_t)j * tiles256 + t];
             mm = vmax(mm, pmax[(size_t)j * tiles256 + t]);
         }
-        ms = wave_sum(ms);
-        mm = wave_max(mm);
-        if (lane == 0) {
-            s_ms = ms;
-            s_mm = mm;
-        }
     }
-    __syncthreads();
-    const double ms = s_ms, mm = s_mm;
-    const double lt = floor((double)gd[j].mk * ms + 0.5);
-    const int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
-    const int nc = ncand[j];
-    const int nsel = LT < nc ? LT : nc;
-    if (threadIdx.x == 0) {
-        fmass[j] = ms;
-        fLT[j] = LT;
-        rsS[j] = quant_shift(mm, n);
-    }
-    __syncthreads();
-    const int nw = (n + WT2 - 1) / WT2;
-    // a wavefront takes labels c, c + 4, c + 8, c + 12 together, their reads
-    // issued before any of the sums (clamped to label c, values dropped)
-    for (int cb = wv; cb < nsel; cb += 16) {
-        double a[4][5] = {};
-        int pc[4];
+    // candidate round of labels cb, cb + 4, cb + 8, cb + 12 (below lim; the
+    // others clamped to cb, values dropped)
+    auto load_round = [&](int cb, int lim, double (&a)[4][5], int (&pc)[4]) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pc[r] = cand[zb + (cb + 4 * r < nsel ? cb + 4 * r : cb)];
+        for (int r = 0; r < 4; ++r) {
+            pc[r] = cand[zb + (cb + 4 * r < lim ? cb + 4 * r : cb)];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) a[r][k] = 0.0;
+        }
         for (int t = lane; t < nw; t += 64) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int c = cb + 4 * r < nsel ? cb + 4 * r : cb;
+                const int c = cb + 4 * r < lim ? cb + 4 * r : cb;
                 const double* o = pzeta + (((size_t)j * wtiles2 + t) * Mmax + c) * 5;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) a[r][k] += o[k];
             }
         }
+    };
+    auto finish_round = [&](int cb, int lim, const double (&a)[4][5], const int (&pc)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (cb + 4 * r >= nsel) break;
+            if (cb + 4 * r >= lim) break;
             double e[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) e[k] = wave_sum(a[r][k]);
@@ -2196,22 +2194,55 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
                 }
             }
         }
-    }
+    };
+    double a0[4][5];
+    int pc0[4];
+    if (wv < nc) load_round(wv, nc, a0, pc0);
     // the resampling's parent order (bucket offsets of the group's tiles from
-    // k_wfinal's histograms) and its tile sums and group total cleared for
-    // k_bk_scatter
+    // the weight pass's histograms) and its tile sums and group total cleared
+    // for k_bk_scatter
     for (int t = threadIdx.x; t < nt; t += 256) tsum[(size_t)j * rtiles + t] = 0.0;
     if (threadIdx.x < QSLOTS) qtot[(size_t)j * QSLOTS + threadIdx.x] = 0.0;
     bucket_offsets<4>(j, nt, rtiles, bhist, boff);
+    __shared__ double s_ms, s_mm;
+    if (wv == 0) {
+        ms = wave_sum(ms);
+        mm = wave_max(mm);
+        if (lane == 0) {
+            s_ms = ms;
+            s_mm = mm;
+        }
+    }
+    __syncthreads();
+    ms = s_ms;
+    mm = s_mm;
+    const double lt = floor((double)gd[j].mk * ms + 0.5);
+    const int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
+    const int nsel = LT < nc ? LT : nc;
+    if (threadIdx.x == 0) {
+        fmass[j] = ms;
+        fLT[j] = LT;
+        rsS[j] = quant_shift(mm, n);
+    }
+    // (the labels' zeroing above happened before the barriers in between)
+    if (wv < nsel) finish_round(wv, nsel, a0, pc0);
+    for (int cb = wv + 16; cb < nsel; cb += 16) {
+        double a[4][5];
+        int pc[4];
+        load_round(cb, nsel, a, pc);
+        finish_round(cb, nsel, a, pc);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Step 4, fusion at the central unit (one 1024-thread workgroup per run).  One
-// wavefront per label counts the run's groups that report it and averages
-// their estimates (tree sum over groups in a fixed order); a label is kept
-// when 2*votes > K.  Kept records are staged in LDS and written in label
-// order to the run's output (cap records at out + run*cap, count at
-// nout[run]).  grid (runs), 1024 threads.
+// Step 4, fusion at the central unit (one 1024-thread workgroup per run).
+// Labels go 64 at a time, one per lane; wavefront w takes the run's groups
+// w, w + 16, w + 32, ... and counts and sums the estimates of the groups that
+// report the label (every read of the chunk issued before any sum); the 16
+// wavefronts' partial sums are then added in wavefront order in LDS, so the
+// order of the additions is fixed.  A label is kept when 2 votes > K, and the
+// kept records are written in label order to the run's output (cap records
+// at out + run cap, count at nout[run]).  grid (runs), 1024 threads.
 // ---------------------------------------------------------------------------
 struct EstimateRec {
     double state[4];
@@ -2224,9 +2255,8 @@ __global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int 
                                                const int* __restrict__ sel_all, const double* __restrict__ zeta_all,
                                                EstimateRec* __restrict__ out_all, int cap, int* __restrict__ nout_all)
 {
-    __shared__ EstimateRec s_rec[1024];
-    __shared__ int s_keep[1024];
-    __shared__ int s_wtot[16];
+    constexpr int GPT = 4;  // groups per thread whose reads go out together
+    __shared__ double s_part[16][5][64];
     const int run = blockIdx.x;
     const Grp gr = rgd[run];  // the run's first group
     const int K = gr.K;
@@ -2234,53 +2264,63 @@ __global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int 
     const int* sel = sel_all + (size_t)gr.g0 * Mmax;
     const double* zeta = zeta_all + (size_t)gr.g0 * Mmax * 4;
     EstimateRec* out = out_all + (size_t)run * cap;
-    int* nout = nout_all + run;
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
     int offset = 0;
-    for (int p0 = 0; p0 < M; p0 += 1024) {
-        const int pe = (p0 + 1024 < M) ? p0 + 1024 : M;
-        s_keep[tid] = 0;
-        __syncthreads();
-        for (int p = p0 + wv; p < pe; p += 16) {
-            double v = 0.0, a[4] = { 0, 0, 0, 0 };
-            for (int j0 = 0; j0 < K; j0 += 64) {
-                const int j = j0 + lane;
-                if (j < K && sel[(size_t)j * Mmax + p]) {
-                    v += 1.0;
+    for (int p0 = 0; p0 < M; p0 += 64) {
+        const int p = p0 + lane;
+        const bool live = p < M;
+        const int pc = live ? p : 0;
+        double v = 0.0, a[4] = { 0.0, 0.0, 0.0, 0.0 };
+        for (int j0 = wv; j0 < K; j0 += 16 * GPT) {
+            int sv[GPT];
+            double4 zv[GPT];
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) a[d] += zeta[((size_t)j * Mmax + p) * 4 + d];
+            for (int u = 0; u < GPT; ++u) {
+                const int j = j0 + 16 * u < K ? j0 + 16 * u : wv;
+                sv[u] = sel[(size_t)j * Mmax + pc];
+                zv[u] = *reinterpret_cast<const double4*>(zeta + ((size_t)j * Mmax + pc) * 4);
+            }
+#pragma unroll
+            for (int u = 0; u < GPT; ++u) {
+                if (j0 + 16 * u < K && live && sv[u]) {
+                    v += 1.0;
+                    a[0] += zv[u].x;
+                    a[1] += zv[u].y;
+                    a[2] += zv[u].z;
+                    a[3] += zv[u].w;
                 }
             }
-            const int votes = (int)wave_sum(v);
-            double r[4];
+        }
+        s_part[wv][0][lane] = v;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) r[d] = wave_sum(a[d]);
-            if (lane == 0 && 2 * votes > K) {
+        for (int d = 0; d < 4; ++d) s_part[wv][1 + d][lane] = a[d];
+        __syncthreads();
+        if (wv == 0) {
+            double vs = 0.0, r[4] = { 0.0, 0.0, 0.0, 0.0 };
+            for (int w2 = 0; w2 < 16; ++w2) {
+                vs += s_part[w2][0][lane];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) r[d] += s_part[w2][1 + d][lane];
+            }
+            const int votes = (int)vs;
+            const bool keep = live && 2 * votes > K;
+            const unsigned long long kb = __ballot(keep);
+            const int idx = offset + __popcll(kb & (lane ? (~0ull >> (64 - lane)) : 0ull));
+            if (keep && idx < cap) {
                 EstimateRec e;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) e.state[d] = r[d] / (double)votes;
                 e.label = p;
                 e.votes = votes;
-                s_rec[p - p0] = e;
-                s_keep[p - p0] = 1;
+                out[idx] = e;
             }
+            offset += __popcll(kb);
         }
-        __syncthreads();
-        const int k = s_keep[tid];
-        const double inc = wave_incl_scan((double)k);
-        if (lane == 63) s_wtot[wv] = (int)inc;
-        __syncthreads();
-        int pre = 0, tot = 0;
-        for (int w2 = 0; w2 < 16; ++w2) {
-            pre += w2 < wv ? s_wtot[w2] : 0;
-            tot += s_wtot[w2];
-        }
-        const int idx = offset + pre + (int)inc - k;
-        if (k && idx < cap) out[idx] = s_rec[tid];
-        offset += tot;
+        // (wavefront 0's offset is the only one used; the LDS partials are
+        // read before the next chunk writes them)
         __syncthreads();
     }
-    if (tid == 0) *nout = offset;
+    if (tid == 0) nout_all[run] = offset;
 }
 
 // ---------------------------------------------------------------------------
@@ -2597,6 +2637,10 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
         return;
     }
     static_assert(!WEIGHT || 1024 * BS >= BIRTH_FUSED_MAX, "the fused form holds every birth");
+    // a group's births are one workgroup's chain of draws, ranking and
+    // weights, the launch's longest path: their wavefronts issue ahead of the
+    // prediction's on a shared compute unit
+    __builtin_amdgcn_s_setprio(3);
     const int j = blockIdx.x;
     const Grp gr = gd[j];
     // the births' slots [ns, min(ns + J_j, cap)), as the prediction sets them
