@@ -107,10 +107,14 @@ double orc_kappa(const orc_model* m)
  * group's particles; read instead as one C_k(z) over every group, the K
  * particle sets become K parts of a single PHD, each carrying 1/K of its
  * mass: the initial mass and the birth mass are split over the groups
- * (omega_0 = 1/(M K)), and a group's own weight sum estimates the target
- * number divided by K.  Step 3's LT and Step 5's child count therefore take
- * K times the group's mass.  With global_cz = 0 every quantity below is the
- * paper's per-group one. */
+ * (omega_0 = 1/(M K)).  The target number is then the run's total mass:
+ * Step 3 takes LT = round(sum over groups of their masses) in every group,
+ * and Step 5 allocates children non-proportionally, as in the DRNA scheme
+ * the method builds on: every group draws round(N_total R_j) children (its
+ * share of the particles for the whole PHD), each of weight N_j / L'_j, so
+ * that a group's weight, not its particle count, carries its share of the
+ * mass.  With global_cz = 0 every quantity below is the paper's per-group
+ * one. */
 static double orc_birth_mass(const orc_model* m)
 {
     return m->global_cz ? m->birth_mass / (double)m->partitions : m->birth_mass;
@@ -119,10 +123,14 @@ static double orc_init_mass(const orc_model* m)
 {
     return m->global_cz ? m->init_mass / (double)m->partitions : m->init_mass;
 }
-/* the target number a group's mass stands for */
-static double orc_count_mass(const orc_model* m, double mass)
+/* the mass that Step 3's LT and Step 5's child count take for group j:
+ * its own, or (global_cz) the run's total, added in group order */
+static double orc_count_mass(const orc_model* m, const double* mass, int j)
 {
-    return m->global_cz ? (double)m->partitions * mass : mass;
+    if (!m->global_cz) return mass[j];
+    double tot = 0.0;
+    for (int q = 0; q < m->partitions; ++q) tot += mass[q];
+    return tot;
 }
 
 static double orc_wrap(double d)
@@ -523,7 +531,7 @@ int orc_extract(const orc_model* m, int M, const double* dW, const double* zeta_
 {
     int K = m->partitions;
     for (int j = 0; j < K; ++j) {
-        double lt = floor(orc_count_mass(m, mass[j]) + 0.5);
+        double lt = floor(orc_count_mass(m, mass, j) + 0.5);
         int L = lt < 0 ? 0 : (lt > (double)M ? M : (int)lt);
         LT[j] = L;
         for (int p = 0; p < M; ++p) {
@@ -643,6 +651,24 @@ int orc_sort_by_bucket(const orc_model* m, size_t KC, double* X, double* W, size
     return 0;
 }
 
+/* Quantised mass Q 2^-S of n weights (w_max < 2^e, S = 52 - ceil(log2 n) - e,
+ * q_i = floor(w_i 2^S), Q their sum); 0 for no positive weight.  The sum is
+ * of integers, so it does not depend on the order of the weights. */
+static double orc_quantised_mass(const double* w, int n)
+{
+    double wmax = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (w[i] > wmax) wmax = w[i];
+    if (n <= 0 || wmax <= 0.0) return 0.0;
+    int e, b = 0;
+    frexp(wmax, &e);
+    while (((int64_t)1 << b) < (int64_t)n) ++b;
+    int S = 52 - b - e;
+    uint64_t Q = 0;
+    for (int i = 0; i < n; ++i) Q += (uint64_t)floor(ldexp(w[i], S));
+    return Q > 0 ? ldexp((double)Q, -S) : 0.0;
+}
+
 int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint32_t run,
                  const double* X, const double* W, const int32_t* n,
                  double* Xout, double* Wout, int32_t* nout, int32_t* counts, double* mass_q)
@@ -651,6 +677,11 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
     size_t KC = (size_t)K * (size_t)cap;
     double Rj = m->particles_per_target / (double)K;
     int err = 0;
+    /* each group's quantised mass first (Step 5's count may take the run's
+     * total); the quantisation is order-free */
+    double* mqa = (double*)calloc((size_t)K, sizeof(double));
+    if (!mqa) return -2;
+    for (int j = 0; j < K; ++j) mqa[j] = orc_quantised_mass(W + (size_t)j * cap, n[j]);
     /* groups resample independently: one thread per group */
 #pragma omp parallel for schedule(dynamic) reduction(min : err)
     for (int j = 0; j < K; ++j) {
@@ -691,7 +722,7 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
         double mq = 0.0;
         if (Q > 0) {
             mq = ldexp((double)Q, -S);
-            double t = orc_count_mass(m, mq) * Rj;
+            double t = orc_count_mass(m, mqa, j) * Rj;
             t = t + 0.5;
             double Lf = floor(t);
             if (Lf > (double)cap_children) Lf = (double)cap_children;
@@ -725,6 +756,7 @@ int orc_resample(const orc_model* m, int cap, uint32_t step, uint64_t seed, uint
         free(q);
         free(order);
     }
+    free(mqa);
     if (err) return err;
     return 0;
 }

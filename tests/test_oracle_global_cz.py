@@ -1,7 +1,9 @@
 """Pins of the oracle's global-C reading of Eq 11 (global_cz = 1): the K
 groups are K parts of one PHD, C_k(z) is summed over all of them before
-Eq 12, and each group carries 1/K of the mass (initial mass, birth mass),
-so Step 3's LT and Step 5's child count take K times the group's mass.
+Eq 12, and each group carries 1/K of the mass (initial mass, birth mass);
+Step 3's LT is the run's total mass, rounded, in every group, and Step 5
+gives every group round(N_total R_j) children of weight N_j / L'_j (the
+non-proportional allocation of the DRNA scheme).
 
 The pins do not restate the oracle's code: the update of K groups must equal
 the single-group update of their union (a K = 1 filter, which is the
@@ -131,32 +133,35 @@ def test_masses_are_split_over_the_groups(orc):
             assert math.isclose(tot, p["birth_mass"], rel_tol=1e-12)
 
 
-def test_target_number_and_child_count_take_k_times_the_group_mass(orc):
-    """Step 3 and Step 5 read a group's mass as 1/K of the target number.
-    Four groups of mass 0.3 each (1.2 targets in all): LT = round(1.2) = 1 in
-    every group, where the per-group reading rounds 0.3 to 0; each group gets
-    round(4 * 0.3 * R_j) children of weight 0.3 / L'."""
+def test_target_number_and_child_counts_follow_the_total_mass(orc):
+    """Step 3 and Step 5 read the run's total mass.  Four groups of masses
+    0.1, 0.2, 0.3 and 0.6 (1.2 targets in all): LT = round(1.2) = 1 in every
+    group (the groups' own masses would give 0, 0, 0, 1); every group draws
+    round(1.2 R_j) children, each of weight N_j / L'_j, so the groups' masses
+    stay 0.1, 0.2, 0.3 and 0.6."""
     K, cap, n = 4, 600, 500
     p = dict(BASE_MODEL, partitions=K, particles_per_target=4 * 250.0, births_per_step=0, global_cz=1)
+    masses = [0.1, 0.2, 0.3, 0.6]
     M = 3
     dW = np.tile(np.array([0.05, 0.2, 0.1]), (K, 1))
     zn = np.ones((K, M, 4))
-    mass = np.full(K, 0.3)
-    e = orc.extract(p, M, dict(dW=dW, zeta_num=zn, mass=mass))
+    e = orc.extract(p, M, dict(dW=dW, zeta_num=zn, mass=np.array(masses)))
     assert list(e["LT"]) == [1] * K
     assert all(list(np.nonzero(e["sel"][j])[0]) == [1] for j in range(K))
-    e0 = orc.extract(dict(p, global_cz=0), M, dict(dW=dW, zeta_num=zn, mass=mass))
-    assert list(e0["LT"]) == [0] * K
+    e0 = orc.extract(dict(p, global_cz=0), M, dict(dW=dW, zeta_num=zn, mass=np.array(masses)))
+    assert list(e0["LT"]) == [0, 0, 0, 1]
     st = orc.State(K, cap)
     st.n[:] = n
     for j in range(K):
-        st.W[j * cap:j * cap + n] = 0.3 / n  # dyadic-free but exact enough: the count is far from a tie
+        st.W[j * cap:j * cap + n] = masses[j] / n
         st.X[0, j * cap:j * cap + n] = np.linspace(10.0, 500.0, n)
         st.X[2, j * cap:j * cap + n] = 100.0
     out, counts, mq = orc.resample(p, st, 1, 5, 0)
     R_j = p["particles_per_target"] / K
-    assert list(out.n) == [int(math.floor(4 * 0.3 * R_j + 0.5))] * K  # 300 children
+    assert list(out.n) == [int(math.floor(1.2 * R_j + 0.5))] * K  # 300 children each
     for j in range(K):
         assert counts[j * cap:(j + 1) * cap].sum() == out.n[j]
         np.testing.assert_allclose(out.W[j * cap:j * cap + out.n[j]], mq[j] / out.n[j], rtol=0, atol=0)
-        assert math.isclose(mq[j], 0.3, rel_tol=1e-12)
+        assert math.isclose(mq[j], masses[j], rel_tol=1e-12)
+    out0, _, _ = orc.resample(dict(p, global_cz=0), st, 1, 5, 0)
+    assert list(out0.n) == [int(math.floor(mj * R_j + 0.5)) for mj in masses]
