@@ -92,8 +92,8 @@ struct Grp {
     int jl, K, g0, run;  // partition within the run, partitions of the run, run's first group, run index
     int Jj, M0;          // births per step, initial particles
     uint32_t rng_run;    // Philox run word of the run
-    int mk;              // target number per unit of a group's mass: 1, or K when the groups split one
-                         // PHD (one C(z) over all groups); Step 3's LT and Step 5's L' use mk times the mass
+    int gz;              // 1 when one C(z) spans the run's groups (they split one PHD): Step 3's LT and
+                         // Step 5's L' then take the run's total mass instead of the group's own
     double kappa, Rj;    // clutter density of the run; particles per target of the group (R/K)
 };
 
@@ -1631,12 +1631,16 @@ __device__ __forceinline__ double tile_weight_share(const double* __restrict__ p
     return wsum;
 }
 
+// The candidate count is LT + 1 (LT from the group's mass, or, with
+// run_mass >= 0, from the run's total mass when one C(z) spans the groups):
+// one more than Step 3 keeps, so that a rounding difference from the final
+// mass cannot leave out a label.
 template <typename T>
 __device__ __forceinline__ void combine_candidates(const DevModel& m, const Grp& gr, int j, int M, double wsum,
                                                    const double* __restrict__ sm_dw, int zoff,
                                                    const int* __restrict__ zpos, ZSorted<T> zsort, size_t zb,
                                                    int* __restrict__ zflag, int* __restrict__ cand,
-                                                   int* __restrict__ ncand)
+                                                   int* __restrict__ ncand, double run_mass)
 {
     __shared__ double s_red[16];
     __shared__ int s_redi[16];
@@ -1661,7 +1665,7 @@ __device__ __forceinline__ void combine_candidates(const DevModel& m, const Grp&
         mass_c += s_red[w2];
         npos += s_redi[w2];
     }
-    const double lt = floor((double)gr.mk * mass_c + 0.5);
+    const double lt = floor((run_mass >= 0.0 ? run_mass : mass_c) + 0.5);
     const int LTc = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
     const int nc = LTc + 1 < npos ? LTc + 1 : npos;
     if (tid == 0) ncand[j] = nc;
@@ -1782,7 +1786,7 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
     }
     if (zS) return;
     __syncthreads();
-    combine_candidates<T>(m, gr, j, M, wsum, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
+    combine_candidates<T>(m, gr, j, M, wsum, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand, -1.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1793,8 +1797,11 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
 // (lanes over the groups, one wavefront tree sum), and group j takes
 //   F = 1/(kappa 2^-H + S) = 2^H/(kappa + C),  dW_j = S_j 2^(H_j - H) F = C_j/(kappa + C)
 // with C = 2^H S, so the second pass divides every term by kappa + C.  The
-// group's candidate labels then follow as in k_cz_combine.  Every group of a
-// run forms the same H and S in the same order.
+// group's candidate labels then follow as in k_cz_combine, with LT from the
+// run's total mass nu sum_q sum_i w_i + sum_p S/(kappa 2^-H + S) (thread q
+// adds group q's tile weight sums in tile order; wavefront w the labels w,
+// w + 16, ...; both reduced in wavefront order).  Every group of a run forms
+// the same H, S and total in the same order.
 // grid (K), 1024 threads, dynamic LDS Mmax doubles.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1816,6 +1823,12 @@ __global__ __launch_bounds__(1024) void k_cz_global(DevModel m, const Grp* __res
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t zb = (size_t)j * Mmax;
     const double wsum = tile_weight_share(pw, j, wtiles, (ncur[j] + WT - 1) / WT);
+    double wrun = 0.0, drun = 0.0;
+    for (int q = threadIdx.x; q < gr.K; q += 1024) {
+        const int g = gr.g0 + q;
+        const int nwq = (ncur[g] + WT - 1) / WT;
+        for (int t = 0; t < nwq; ++t) wrun += pw[(size_t)g * wtiles + t];
+    }
     for (int p = wv; p < M; p += 16) {
         int hl = -2147483647 - 1;
         for (int q0 = 0; q0 < gr.K; q0 += 64) {
@@ -1844,6 +1857,7 @@ __global__ __launch_bounds__(1024) void k_cz_global(DevModel m, const Grp* __res
                 F = 1.0 / D;
                 dW = Sj > 0.0 ? ldexp(Sj, zHg[zb + p] - H) / D : 0.0;
                 Hs = H;
+                drun += S / D;
             }
             zH[zb + p] = Hs;
             zF[zb + p] = (T)F;
@@ -1858,8 +1872,19 @@ __global__ __launch_bounds__(1024) void k_cz_global(DevModel m, const Grp* __res
             }
         }
     }
+    __shared__ double s_run[16][2];
+    wrun = wave_sum(wrun);
+    if (lane == 0) {
+        s_run[wv][0] = wrun;
+        s_run[wv][1] = drun;
+    }
     __syncthreads();
-    combine_candidates<T>(m, gr, j, M, wsum, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand);
+    double wr = 0.0, dr = 0.0;
+    for (int w2 = 0; w2 < 16; ++w2) {
+        wr += s_run[w2][0];
+        dr += s_run[w2][1];
+    }
+    combine_candidates<T>(m, gr, j, M, wsum, sm_dw, zoff, zpos, zsort, zb, zflag, cand, ncand, m.nu * wr + dr);
 }
 
 // ---------------------------------------------------------------------------
@@ -2159,6 +2184,19 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
             mm = vmax(mm, pmax[(size_t)j * tiles256 + t]);
         }
     }
+    // one C(z) over the run's groups: LT from the run's total mass (thread q
+    // adds group q's tile masses in tile order, then a reduction in
+    // wavefront order; every group of the run forms the same total)
+    const Grp gr = gd[j];
+    double mrun = 0.0;
+    if (gr.gz) {
+        for (int q = threadIdx.x; q < gr.K; q += 256) {
+            const int g = gr.g0 + q;
+            const int ntq = (ncur[g] + 255) / 256;
+            for (int t = 0; t < ntq; ++t) mrun += pmass[(size_t)g * tiles256 + t];
+        }
+        mrun = wave_sum(mrun);
+    }
     // candidate round of labels cb, cb + 4, cb + 8, cb + 12 (below lim; the
     // others clamped to cb, values dropped)
     auto load_round = [&](int cb, int lim, double (&a)[4][5], int (&pc)[4]) {
@@ -2204,7 +2242,8 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     for (int t = threadIdx.x; t < nt; t += 256) tsum[(size_t)j * rtiles + t] = 0.0;
     if (threadIdx.x < QSLOTS) qtot[(size_t)j * QSLOTS + threadIdx.x] = 0.0;
     bucket_offsets<4>(j, nt, rtiles, bhist, boff);
-    __shared__ double s_ms, s_mm;
+    __shared__ double s_ms, s_mm, s_mrun[4];
+    if (lane == 0) s_mrun[wv] = mrun;
     if (wv == 0) {
         ms = wave_sum(ms);
         mm = wave_max(mm);
@@ -2216,7 +2255,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     __syncthreads();
     ms = s_ms;
     mm = s_mm;
-    const double lt = floor((double)gd[j].mk * ms + 0.5);
+    const double lt = floor((gr.gz ? (s_mrun[0] + s_mrun[1]) + (s_mrun[2] + s_mrun[3]) : ms) + 0.5);
     const int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
     const int nsel = LT < nc ? LT : nc;
     if (threadIdx.x == 0) {
@@ -2749,23 +2788,24 @@ __device__ __forceinline__ long long points_below(uint64_t c, uint64_t Q, long l
     return m0;
 }
 
-// L' = floor((mk N) R_j + 0.5) with separate roundings (no fused multiply-add)
-__device__ __forceinline__ double children_count(double mq, int mk, double Rj)
+// L' = floor(N R_j + 0.5) with separate roundings (no fused multiply-add)
+__device__ __forceinline__ double children_count(double N, double Rj)
 {
 #pragma clang fp contract(off)
-    double t = ((double)mk * mq) * Rj;
+    double t = N * Rj;
     t = t + 0.5;
     return floor(t);
 }
 
-// a group's child count L' from its exact quantised total Q and shift S:
-// children_count of the mass 2^-S Q, clamped to [0, cap - J_j]; *clamped
+// a group's child count L' from its exact quantised total Q (0: no children)
+// and the mass N that Step 5 counts with (the group's 2^-S Q, or the run's
+// total when one C(z) spans the groups), clamped to [0, cap - J_j]; *clamped
 // tells whether the capacity cut it
-__device__ __forceinline__ long long group_children(double Qd, int S, const Grp& g, int cap, bool* clamped)
+__device__ __forceinline__ long long group_children(double Qd, double N, const Grp& g, int cap, bool* clamped)
 {
     *clamped = false;
     if (!(Qd > 0.0)) return 0;
-    double Lf = children_count(ldexp(Qd, -S), g.mk, g.Rj);
+    double Lf = children_count(N, g.Rj);
     const double lim = (double)(cap - g.Jj);
     if (Lf > lim) {
         Lf = lim;
@@ -2773,6 +2813,32 @@ __device__ __forceinline__ long long group_children(double Qd, int S, const Grp&
     }
     if (Lf < 0.0) Lf = 0.0;
     return (long long)Lf;
+}
+
+// The run's total quantised mass, the sum over its groups, in group order, of
+// 2^-S_q Q_q: the mass Step 5 counts with when one C(z) spans the groups.
+// Every thread of the 256-thread workgroup gets it (contains barriers).
+__device__ double run_quantised_mass(const Grp& gr, const double* __restrict__ qtot, const int* __restrict__ rsS)
+{
+    __shared__ double s_m[256];
+    __shared__ double s_tot;
+    double tot = 0.0;  // thread 0's running sum
+    for (int q0 = 0; q0 < gr.K; q0 += 256) {
+        const int q = q0 + (int)threadIdx.x;
+        if (q < gr.K) {
+            const double Qq = group_q(qtot, gr.g0 + q);
+            s_m[threadIdx.x] = Qq > 0.0 ? ldexp(Qq, -rsS[gr.g0 + q]) : 0.0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int e = gr.K - q0 < 256 ? gr.K - q0 : 256;
+            for (int i = 0; i < e; ++i) tot += s_m[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s_tot = tot;
+    __syncthreads();
+    return s_tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -2836,6 +2902,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     __shared__ long long s_nnext;
     const bool xrun = xchg && gr.K >= 2;
     const int jn = gr.jl + 1 < gr.K ? gr.jl + 1 : 0;
+    const double ntot = gr.gz ? run_quantised_mass(gr, qtot, rsS) : 0.0;
     uint32_t xa = 0, xan = 0;
     if (xrun) {
         // (counts below 2^31: exact in double)
@@ -2843,7 +2910,9 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         for (int i = tid; i < gr.K; i += 256) {
             const int g = gr.g0 + i;
             bool c2;
-            const long long Li = group_children(group_q(qtot, g), rsS[g], gd[g], m.cap, &c2);
+            const double Qg = group_q(qtot, g);
+            const double Ng = gr.gz ? ntot : (Qg > 0.0 ? ldexp(Qg, -rsS[g]) : 0.0);
+            const long long Li = group_children(Qg, Ng, gd[g], m.cap, &c2);
             mn = (double)Li < mn ? (double)Li : mn;
             if (i == jn) s_nnext = Li;
         }
@@ -2905,8 +2974,8 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         hpre[h] = h == 0 ? 0.0 : hpre[h - 1] + ((s_q[1 + h][0] + s_q[1 + h][1]) + (s_q[1 + h][2] + s_q[1 + h][3]));
     }
     bool clamped = false;
-    const long long L = group_children(Qd, S, gr, m.cap, &clamped);
     const double mq = Qd > 0.0 ? ldexp(Qd, -S) : 0.0;
+    const long long L = group_children(Qd, gr.gz ? ntot : mq, gr, m.cap, &clamped);
     if (t == 0 && tid == 0) {
         if (clamped) atomicAdd(clampctr, 1);
         nsurv[j] = (int)L;

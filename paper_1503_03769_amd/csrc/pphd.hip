@@ -355,7 +355,7 @@ void set_geometry(pphd_filter* f, const pphd_model* m, const pphd_run_desc* runs
             g.rng_run = d.run_id;
             g.kappa = d.clutter_rate / area;
             g.Rj = d.particles_per_target / (double)d.partitions;
-            g.mk = m->global_cz ? d.partitions : 1;
+            g.gz = m->global_cz ? 1 : 0;
             f->Jmax = std::max(f->Jmax, g.Jj);
             f->M0max = std::max(f->M0max, g.M0);
             f->hgd.push_back(g);

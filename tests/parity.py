@@ -90,15 +90,16 @@ def check_cz(Cg, Co, kappa, prec):
     return worst
 
 
-def check_selection(sel_g, zeta_g, mass_g, LT_g, upd_o, ext_o, tol=1e-5, mk=1):
+def check_selection(sel_g, zeta_g, mass_g, LT_g, upd_o, ext_o, tol=1e-5, run_total=False):
     """Local estimates: LT and the label sets must agree except where the
     oracle's own numbers sit within the tolerance of a rounding or ranking
     boundary; common labels' estimates agree to 1e-5 of the state scale.
-    mk: target number per unit of group mass (K when the groups split one
-    PHD)."""
+    run_total: LT follows the total mass of the groups (one run whose groups
+    split one PHD) instead of each group's own."""
     K, M = upd_o["dW"].shape
+    total = float(np.sum(upd_o["mass"]))
     for j in range(K):
-        m = mk * upd_o["mass"][j]
+        m = total if run_total else upd_o["mass"][j]
         near_half = abs((m - np.floor(m)) - 0.5) < tol * max(1.0, m)
         if not near_half:
             assert LT_g[j] == ext_o["LT"][j], (j, LT_g[j], ext_o["LT"][j], m)

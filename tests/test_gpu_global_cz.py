@@ -1,6 +1,7 @@
 """The global-C reading of Eq 11 (global_cz = 1) on the GPU against the
 oracle: one C(z) summed over every group of the run before Eq 12, the groups
-splitting the PHD mass, LT and child counts from K times a group's mass.
+splitting the PHD mass, LT from the run's total mass and every group drawing
+round(N_total R_j) children.
 
 Step 2-4 parity element by element (each group's own C_j, every weight, the
 group masses, Delta W, LT and label sets, fused estimates) in FP32 at the
@@ -62,7 +63,7 @@ def test_global_update_matches_oracle(gpu, case):
     ew = P.check_weights(Wg, st)
     np.testing.assert_allclose(ug["mass"], uo["mass"], rtol=1e-6 if prec == "fp32" else 1e-9, atol=1e-300)
     np.testing.assert_allclose(ug["dW"], uo["dW"], rtol=0, atol=1e-5 if prec == "fp32" else 1e-12)
-    P.check_selection(lg["sel"], lg["zeta"], ug["mass"], ug["LT"], uo, eo, mk=K)
+    P.check_selection(lg["sel"], lg["zeta"], ug["mass"], ug["LT"], uo, eo, run_total=True)
     if np.array_equal(lg["sel"], eo["sel"]):
         assert list(est_g["label"]) == list(fo["label"])
         assert list(est_g["votes"]) == list(fo["votes"])
