@@ -190,7 +190,10 @@ pphd_status pphd_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_
 /* As pphd_extract, but the records and their count are written to device
  * memory in stream order (d_out: cap records, d_n_out: one int32); no
  * synchronisation.  Records beyond cap are dropped; *d_n_out holds the full
- * count. */
+ * count.  The first such call after an update also sorts the parents for the
+ * coming pphd_resample in the same launch (into the other particle set, which
+ * no other call reads); the estimates are complete when the stream reaches
+ * the call, as with any launch. */
 pphd_status pphd_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t cap,
                                 int32_t* d_n_out);
 

@@ -2274,14 +2274,17 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
 }
 
 // ---------------------------------------------------------------------------
-// Step 4, fusion at the central unit (one 1024-thread workgroup per run).
+// Step 4, fusion at the central unit (one workgroup of NW wavefronts per run).
 // Labels go 64 at a time, one per lane; wavefront w takes the run's groups
-// w, w + 16, w + 32, ... and counts and sums the estimates of the groups that
-// report the label (every read of the chunk issued before any sum); the 16
-// wavefronts' partial sums are then added in wavefront order in LDS, so the
-// order of the additions is fixed.  A label is kept when 2 votes > K, and the
-// kept records are written in label order to the run's output (cap records
-// at out + run cap, count at nout[run]).  grid (runs), 1024 threads.
+// w, w + NW, w + 2 NW, ... and counts and sums the estimates of the groups
+// that report the label (every read of the chunk issued before any sum); the
+// NW wavefronts' partial sums are then added in wavefront order in LDS, so
+// the order of the additions is fixed for a given NW.  A label is kept when
+// 2 votes > K, and the kept records are written in label order to the run's
+// output (cap records at out + run cap, count at nout[run]).  It runs as
+// k_fuse or in the first workgroups of the resampling's scatter launch
+// (which needs the same update's results and nothing the fusion writes), in
+// both with 4 wavefronts, so both give the same sums.
 // ---------------------------------------------------------------------------
 struct EstimateRec {
     double state[4];
@@ -2289,39 +2292,49 @@ struct EstimateRec {
     int32_t votes;
 };
 
-__global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int Mall,
-                                               const ZWin* __restrict__ win, int Mmax,
-                                               const int* __restrict__ sel_all, const double* __restrict__ zeta_all,
-                                               EstimateRec* __restrict__ out_all, int cap, int* __restrict__ nout_all)
+struct FuseArgs {
+    const Grp* rgd;  // each run's first group
+    int Mall;        // measurements (single run) or 0 with win
+    const ZWin* win;
+    int Mmax;
+    const int* sel;
+    const double* zeta;
+    EstimateRec* out;
+    int cap;
+    int* nout;
+    int nruns;  // 0: no fusion in the launch
+};
+
+template <int NW>
+__device__ __forceinline__ void fuse_run(const FuseArgs& fa, int run, double (*s_part)[5][64])
 {
     constexpr int GPT = 4;  // groups per thread whose reads go out together
-    __shared__ double s_part[16][5][64];
-    const int run = blockIdx.x;
-    const Grp gr = rgd[run];  // the run's first group
+    const Grp gr = fa.rgd[run];  // the run's first group
     const int K = gr.K;
-    const int M = zview(gr, win, nullptr, Mall).M;
-    const int* sel = sel_all + (size_t)gr.g0 * Mmax;
-    const double* zeta = zeta_all + (size_t)gr.g0 * Mmax * 4;
-    EstimateRec* out = out_all + (size_t)run * cap;
-    const int tid = threadIdx.x, lane = tid & 63, wv = wave_in_block();
+    const int M = zview(gr, fa.win, nullptr, fa.Mall).M;
+    const int Mmax = fa.Mmax;
+    const int* sel = fa.sel + (size_t)gr.g0 * Mmax;
+    const double* zeta = fa.zeta + (size_t)gr.g0 * Mmax * 4;
+    EstimateRec* out = fa.out + (size_t)run * fa.cap;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int offset = 0;
     for (int p0 = 0; p0 < M; p0 += 64) {
         const int p = p0 + lane;
         const bool live = p < M;
         const int pc = live ? p : 0;
         double v = 0.0, a[4] = { 0.0, 0.0, 0.0, 0.0 };
-        for (int j0 = wv; j0 < K; j0 += 16 * GPT) {
+        for (int j0 = wv; j0 < K; j0 += NW * GPT) {
             int sv[GPT];
             double4 zv[GPT];
 #pragma unroll
             for (int u = 0; u < GPT; ++u) {
-                const int j = j0 + 16 * u < K ? j0 + 16 * u : wv;
+                const int j = j0 + NW * u < K ? j0 + NW * u : wv;
                 sv[u] = sel[(size_t)j * Mmax + pc];
                 zv[u] = *reinterpret_cast<const double4*>(zeta + ((size_t)j * Mmax + pc) * 4);
             }
 #pragma unroll
             for (int u = 0; u < GPT; ++u) {
-                if (j0 + 16 * u < K && live && sv[u]) {
+                if (j0 + NW * u < K && live && sv[u]) {
                     v += 1.0;
                     a[0] += zv[u].x;
                     a[1] += zv[u].y;
@@ -2336,7 +2349,7 @@ __global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int 
         __syncthreads();
         if (wv == 0) {
             double vs = 0.0, r[4] = { 0.0, 0.0, 0.0, 0.0 };
-            for (int w2 = 0; w2 < 16; ++w2) {
+            for (int w2 = 0; w2 < NW; ++w2) {
                 vs += s_part[w2][0][lane];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) r[d] += s_part[w2][1 + d][lane];
@@ -2345,7 +2358,7 @@ __global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int 
             const bool keep = live && 2 * votes > K;
             const unsigned long long kb = __ballot(keep);
             const int idx = offset + __popcll(kb & (lane ? (~0ull >> (64 - lane)) : 0ull));
-            if (keep && idx < cap) {
+            if (keep && idx < fa.cap) {
                 EstimateRec e;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) e.state[d] = r[d] / (double)votes;
@@ -2359,7 +2372,15 @@ __global__ __launch_bounds__(1024) void k_fuse(const Grp* __restrict__ rgd, int 
         // read before the next chunk writes them)
         __syncthreads();
     }
-    if (tid == 0) nout_all[run] = offset;
+    if (tid == 0) fa.nout[run] = offset;
+}
+
+constexpr int FUSE_WAVES = 4;
+// grid (runs), 256 threads
+__global__ __launch_bounds__(256) void k_fuse(FuseArgs fa)
+{
+    __shared__ double s_part[FUSE_WAVES][5][64];
+    fuse_run<FUSE_WAVES>(fa, blockIdx.x, s_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -2433,7 +2454,10 @@ __global__ __launch_bounds__(1024) void k_bk_scan(const int* __restrict__ first,
 }
 
 // grid (tiles, K), 256 threads: slot s of the range goes to off[t][b] + (slots
-// of bucket b before it in its tile), in the other particle set
+// of bucket b before it in its tile), in the other particle set.  With
+// frows > 0 the first frows tile rows of the grid (dispatched first) are the
+// fusion of Step 4 instead: workgroup (group j, row r) fuses run j frows + r
+// (those below fa.nruns), the scatter's tiles following at row frows.
 // With tsum (the parents before Step 5), each parent's integer weight
 // q = floor(w 2^S) is also added to the sum of the resampling tile it lands
 // in: exact integer sums in FP64 (below 2^53), so the order of the atomic
@@ -2443,14 +2467,25 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
                                                     const int* __restrict__ end, int rtiles,
                                                     const int* __restrict__ bkt, const int* __restrict__ off,
                                                     const int* __restrict__ rsS, double* __restrict__ tsum,
-                                                    int* __restrict__ orig, double* __restrict__ qtot)
+                                                    int* __restrict__ orig, double* __restrict__ qtot, FuseArgs fa,
+                                                    int frows)
 {
+    // one LDS buffer: the fusion's partial sums, or the scatter's per-half,
+    // per-wave bucket counts
+    __shared__ double s_lds[FUSE_WAVES * 5 * 64];
+    static_assert(NH * 4 * BEARING_BUCKETS * sizeof(int) <= sizeof(s_lds), "bucket counts fit");
+    const int j = slot_group(m), trow = slot_tile(m);
+    if (trow < frows) {
+        const int run = j * frows + trow;
+        if (run < fa.nruns) fuse_run<FUSE_WAVES>(fa, run, reinterpret_cast<double(*)[5][64]>(s_lds));
+        return;
+    }
     // a workgroup takes NH 256-slot tiles of the range (half h: tile
     // NH t2 + h, one slot per thread; NH = 2 where the capacity spans enough
     // workgroups, else 1), each ranked exactly as a workgroup of its own would
     // rank it; the reads of all go out first
-    __shared__ int wh[NH][4][BEARING_BUCKETS];  // per half, per-wave bucket counts
-    const int j = slot_group(m), t2 = slot_tile(m);
+    int(*wh)[4][BEARING_BUCKETS] = reinterpret_cast<int(*)[4][BEARING_BUCKETS]>(s_lds);
+    const int t2 = trow - frows;
     const int a = range_first(first, j), n = end[j] - a;
     if (t2 * 256 * NH >= n) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

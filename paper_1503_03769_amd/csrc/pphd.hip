@@ -160,6 +160,7 @@ struct pphd_filter {
     int *bkt = nullptr, *bhist = nullptr, *boff = nullptr;  // bearing-bucket order of the parents
     int* borig = nullptr;  // drawing index of each ordered birth
     bool order_ready = false;  // the last update left the parents' bucket offsets and cleared tile sums
+    bool prescattered = false;  // the parents' scatter of the coming resampling ran with the fusion
     bool uneven = false;       // groups of different sizes: the frame passes walk flat item lists
     int *ipre1 = nullptr, *igrp1 = nullptr, *ipre2 = nullptr, *igrp2 = nullptr;  // those lists
     void* stage = nullptr;
@@ -777,6 +778,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                               f->fLT, f->rsS, f->sel, f->zeta, f->rtiles, f->bhist, f->boff, f->tsum, f->qtot));
     // k_wfinal and k_finalize have prepared the resampling's parent order
     f->order_ready = true;
+    f->prescattered = false;
     return PPHD_OK;
 }
 
@@ -868,12 +870,21 @@ pphd_status run_init(pphd_filter* f)
 // slot).  tiles: 256-slot tiles to cover the longest range.
 // parents (first == nullptr): the scatter also forms the resampling's tile
 // sums, and the histogram and offsets come from the update when it left them
+// fuse (parents, with the update's offsets ready): the launch also runs the
+// fusion of Step 4 in its first workgroups
 template <typename T>
-pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, int* orig = nullptr)
+pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, int* orig = nullptr,
+                         const FuseArgs* fuse = nullptr)
 {
-    dim3 g = slot_grid(f, tiles);
     SoA<T> cur = soa<T>(f, f->cur), oth = soa<T>(f, 1 - f->cur);
     const bool parents = first == nullptr;
+    FuseArgs fa{};
+    int frows = 0;
+    if (fuse && parents && f->order_ready) {
+        fa = *fuse;
+        frows = (fa.nruns + f->K - 1) / f->K;
+    }
+    dim3 g = slot_grid(f, tiles);
     if (!parents || !f->order_ready) {
         LAUNCH(f, cls,
                hipLaunchKernelGGL((k_bk_hist<T>), g, dim3(256), 0, f->stream, f->dm, cur, first, f->ncur, f->rtiles,
@@ -884,14 +895,14 @@ pphd_status bucket_order(pphd_filter* f, int cls, const int* first, int tiles, i
     }
     if (rs_halves(f) == 2)
         LAUNCH(f, cls,
-               hipLaunchKernelGGL((k_bk_scatter<T, 2>), slot_grid(f, (tiles + 1) / 2), dim3(256), 0, f->stream, f->dm,
-                                  cur, oth, first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS,
-                                  parents ? f->tsum : nullptr, orig, f->qtot));
+               hipLaunchKernelGGL((k_bk_scatter<T, 2>), slot_grid(f, (tiles + 1) / 2 + frows), dim3(256), 0, f->stream,
+                                  f->dm, cur, oth, first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS,
+                                  parents ? f->tsum : nullptr, orig, f->qtot, fa, frows));
     else
         LAUNCH(f, cls,
-               hipLaunchKernelGGL((k_bk_scatter<T, 1>), slot_grid(f, tiles), dim3(256), 0, f->stream, f->dm, cur, oth,
-                                  first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS, parents ? f->tsum : nullptr,
-                                  orig, f->qtot));
+               hipLaunchKernelGGL((k_bk_scatter<T, 1>), slot_grid(f, tiles + frows), dim3(256), 0, f->stream, f->dm,
+                                  cur, oth, first, f->ncur, f->rtiles, f->bkt, f->boff, f->rsS,
+                                  parents ? f->tsum : nullptr, orig, f->qtot, fa, frows));
     if (parents) f->order_ready = false;
     return PPHD_OK;
 }
@@ -928,10 +939,14 @@ template <typename T>
 pphd_status run_resample(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
     // parents into bearing-bucket order (into the other set), with the
-    // resampling's tile sums and group totals; the systematic expansion back
-    // into this set waits for the next call, so that an exchange can ride in it
-    pphd_status s = bucket_order<T>(f, PPHD_K_RS_ORDER, nullptr, f->rtiles);
-    if (s != PPHD_OK) return s;
+    // resampling's tile sums and group totals (unless the fusion's launch did
+    // it); the systematic expansion back into this set waits for the next
+    // call, so that an exchange can ride in it
+    if (!f->prescattered) {
+        pphd_status s = bucket_order<T>(f, PPHD_K_RS_ORDER, nullptr, f->rtiles);
+        if (s != PPHD_OK) return s;
+    }
+    f->prescattered = false;
     f->cur = 1 - f->cur;
     f->rs_pending = true;
     f->rs_step = step;
@@ -1025,10 +1040,31 @@ pphd_status check_handle(pphd_filter* f)
 
 pphd_status run_fuse(pphd_filter* f, EstimateRec* out, int cap, int* nout, int M, const ZWin* win)
 {
-    LAUNCH(f, PPHD_K_FUSE,
-           hipLaunchKernelGGL(k_fuse, dim3(f->nruns), dim3(1024), 0, f->stream, f->rgd, M, win, f->max_meas,
-                              f->sel, f->zeta, out, cap, nout));
+    const FuseArgs fa{ f->rgd, M, win, f->max_meas, f->sel, f->zeta, out, cap, nout, f->nruns };
+    LAUNCH(f, PPHD_K_FUSE, hipLaunchKernelGGL(k_fuse, dim3(f->nruns), dim3(256), 0, f->stream, fa));
     return PPHD_OK;
+}
+
+// The fusion for estimates left in device memory: right after an update it
+// rides in the launch of the coming resampling's parent scatter (which
+// needs the same update's results, writes only the other particle set and
+// the resampling's sums, and is kept for pphd_resample); otherwise alone.
+// The estimates are complete when the stream reaches the launch either way.
+template <typename T>
+pphd_status run_fuse_device(pphd_filter* f, EstimateRec* out, int cap, int* nout, int M, const ZWin* win)
+{
+    if (!f->order_ready || f->prescattered) return run_fuse(f, out, cap, nout, M, win);
+    const FuseArgs fa{ f->rgd, M, win, f->max_meas, f->sel, f->zeta, out, cap, nout, f->nruns };
+    pphd_status s = bucket_order<T>(f, PPHD_K_RS_ORDER, nullptr, f->rtiles, nullptr, &fa);
+    if (s != PPHD_OK) return s;
+    f->prescattered = true;
+    return PPHD_OK;
+}
+
+pphd_status fuse_device(pphd_filter* f, EstimateRec* out, int cap, int* nout, int M, const ZWin* win)
+{
+    return f->prec == PPHD_FP64 ? run_fuse_device<double>(f, out, cap, nout, M, win)
+                                : run_fuse_device<float>(f, out, cap, nout, M, win);
 }
 
 }  // namespace
@@ -1169,6 +1205,7 @@ pphd_status pphd_init(pphd_filter* f)
     CHECK_HANDLE(f);
     f->rs_pending = false;  // t = 0 replaces whatever a resampling or a prediction left
     f->pr_pending = false;
+    f->prescattered = false;
     f->cur = 0;
     pphd_status s = f->prec == PPHD_FP64 ? run_init<double>(f) : run_init<float>(f);
     if (s != PPHD_OK) return s;
@@ -1230,7 +1267,7 @@ pphd_status pphd_extract_device(pphd_filter* f, pphd_estimate* d_out, int32_t ca
     if (!d_n_out || (cap > 0 && !d_out) || cap < 0) return fail(PPHD_EINVAL, "bad output buffers");
     if (f->batch) return fail(PPHD_EINVAL, "a batch's estimates come from pphd_batch_extract(_device)");
     static_assert(sizeof(pphd_estimate) == sizeof(EstimateRec), "record layout");
-    return run_fuse(f, (EstimateRec*)d_out, cap, d_n_out, f->last_m, nullptr);
+    return fuse_device(f, (EstimateRec*)d_out, cap, d_n_out, f->last_m, nullptr);
 }
 
 pphd_status pphd_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out, double* mass)
@@ -1354,6 +1391,7 @@ pphd_status pphd_write_state(pphd_filter* f, const double* x, const double* w, c
     HIP_TRY(hipMemcpy(is_cur ? f->ncur : f->nsurv, count, (size_t)f->K * 4, hipMemcpyHostToDevice));
     f->births_pending = false;  // a written state is complete
     f->order_ready = false;
+    f->prescattered = false;
     if (phase == PPHD_PHASE_PREDICTED) {
         dim3 g = slot_grid(f, (f->cap + 255) / 256);
         if (f->prec == PPHD_FP64) {
@@ -1543,7 +1581,7 @@ pphd_status step_all(pphd_filter* f, const double* dz, int z_count, const int32_
     if (s != PPHD_OK) return s;
     s = dispatch_update(f, UpdArgs{ dz, 0, f->win, z_count, f->dstep });
     if (s != PPHD_OK) return s;
-    s = run_fuse(f, out, cap, nout, 0, f->win);
+    s = run_fuse_device<T>(f, out, cap, nout, 0, f->win);
     if (s != PPHD_OK) return s;
     s = run_resample<T>(f, 0, f->dstep);
     if (s != PPHD_OK) return s;
@@ -1608,7 +1646,7 @@ pphd_status pphd_batch_extract_device(pphd_filter* f, pphd_estimate* d_out, int3
     if (f->phase != PPHD_PHASE_UPDATED || f->last_m != -2)
         return fail(PPHD_ESTATE, "extract needs phase UPDATED after an update (have %d)", f->phase);
     if (!d_n_out || !d_out || cap < 1) return fail(PPHD_EINVAL, "bad output buffers");
-    return run_fuse(f, (EstimateRec*)d_out, cap, d_n_out, 0, f->win);
+    return fuse_device(f, (EstimateRec*)d_out, cap, d_n_out, 0, f->win);
 }
 
 pphd_status pphd_batch_extract(pphd_filter* f, pphd_estimate* out, int32_t cap, int32_t* n_out, double* mass)
