@@ -281,6 +281,19 @@ struct Geo {
     double* lw;
 };
 
+// log2 of a positive weight: in double for FP64 storage; for FP32 storage
+// the exponent exactly and the mantissa's log2 in float (within about 2e-7,
+// a relative change of the same size in the particle's likelihood terms,
+// far below the weights' own storage rounding)
+__device__ __forceinline__ double weight_log2(double v, double) { return log2(v); }
+__device__ __forceinline__ double weight_log2(double v, float)
+{
+    int e;
+    const double f = frexp(v, &e);  // v = f 2^e, f in [1/2, 1)
+    return (double)e + (double)log2f((float)f);
+}
+
+template <typename T>
 __device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_t g, double x, double y, double w)
 {
     const double dx = x - m.sx, dy = y - m.sy;
@@ -288,7 +301,7 @@ __device__ __forceinline__ void store_geometry(const DevModel& m, Geo geo, size_
     const double ph = atan2(dy, dx);
     geo.phi[g] = ph * m.ct;
     geo.phib[g] = (ph < 0.0 ? ph + 3.14159265358979323846 : ph - 3.14159265358979323846) * m.ct;
-    geo.lw[g] = (w > 0.0) ? log2(m.wscale * w) : -__builtin_inf();
+    geo.lw[g] = (w > 0.0) ? weight_log2(m.wscale * w, T(0)) : -__builtin_inf();
 }
 
 // ---------------------------------------------------------------------------
@@ -353,7 +366,7 @@ __device__ __forceinline__ void predict_slot(const DevModel& m, const Grp& gr, c
     st.w[g] = tw;
     // births get their geometry once put in bearing order, by the bucket of
     // the position as drawn
-    if (s < ns) store_geometry(m, geo, g, (double)t[0], (double)t[2], (double)tw);
+    if (s < ns) store_geometry<T>(m, geo, g, (double)t[0], (double)t[2], (double)tw);
     else bkt[g] = bearing_bucket(m, v[0], v[2]);
 }
 
@@ -423,7 +436,7 @@ __global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, co
     const int s = slot_tile(m) * 256 + threadIdx.x;
     if (s >= ncur[j]) return;
     const size_t g = (size_t)j * m.cap + s;
-    store_geometry(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)st.w[g]);
+    store_geometry<T>(m, geo, g, (double)st.x[0][g], (double)st.x[2][g], (double)st.w[g]);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,10 +463,13 @@ __global__ __launch_bounds__(256) void k_geom(DevModel m, SoA<T> st, Geo geo, co
 // of a Gaussian component (sub 3); weight gamma(x) / (J_j q(x)), gamma(x) =
 // m_b U(x, y) N(vx; 0, sv^2) N(vy; 0, sv^2).
 // ---------------------------------------------------------------------------
+// d - 2 pi k, the integer k nearest d / (2 pi): the residual in [-pi, pi]
+// up to rounding (a product by 1/(2 pi) in place of a division; at the
+// seam either sign gives the same square)
 __device__ __forceinline__ double wrap_pi(double d)
 {
     const double two_pi = 2.0 * 3.14159265358979323846;
-    return d - two_pi * floor((d + 3.14159265358979323846) / two_pi);
+    return d - two_pi * rint(d * (1.0 / two_pi));
 }
 
 // exp(-a) for a >= 0: hardware exp2 in float for the FP32 path (terms below
@@ -712,7 +728,7 @@ __global__ __launch_bounds__(256) void k_birth_weight(DevModel m, const Grp* __r
     const T tw = (T)w;
     st.w[g] = tw;
     // the stored position is the drawn one at storage precision
-    store_geometry(m, geo, g, (double)(T)x[0], (double)(T)x[2], (double)tw);
+    store_geometry<T>(m, geo, g, (double)(T)x[0], (double)(T)x[2], (double)tw);
 }
 
 // scaled squared residual q(z, x) + c
@@ -2634,7 +2650,7 @@ __device__ __forceinline__ void sort_births_block(const DevModel& m, const SoA<T
             if (d < m.dim) st.x[d][g] = v[c][d];
         if (write_w) st.w[g] = w[c];
         if (borig) borig[g] = c * 1024 + tid;
-        if (with_geo) store_geometry(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
+        if (with_geo) store_geometry<T>(m, geo, g, (double)v[c][0], (double)v[c][2], (double)w[c]);
     }
 }
 
@@ -2683,8 +2699,8 @@ __global__ __launch_bounds__(1024) void k_birth_sort(DevModel m, SoA<T> st, Geo 
 // drawing index, with the drawing index of every rank), and each wavefront
 // then gives 64 consecutive ordered births their Eq 6 weights and geometry,
 // as k_birth_weight would (the same births per wavefront, the same
-// positions); else the weights are 0 until k_birth_weight.  grid (K), 1024
-// threads.
+// positions); else the weights are 0 until k_birth_weight.  grid (K),
+// 1024 threads.
 constexpr int BIRTH_FUSED_MAX = 1152;
 template <typename T, int BS, int PROP, bool WEIGHT>
 __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp* __restrict__ gd, SoA<T> st,
@@ -2771,7 +2787,7 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
                 const T tw = (T)wt;
                 st.w[g] = tw;
                 // the stored position is the drawn one at storage precision
-                store_geometry(m, geo, g, (double)(T)x[0], (double)(T)x[2], (double)tw);
+                store_geometry<T>(m, geo, g, (double)(T)x[0], (double)(T)x[2], (double)tw);
             }
         }
     }
@@ -2799,7 +2815,7 @@ __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T>
         if (d < m.dim) to.x[d][g] = v[d];
     const T x = v[0], y = v[2];
     to.w[g] = w;
-    if (with_geo) store_geometry(m, geo, g, (double)x, (double)y, (double)w);
+    if (with_geo) store_geometry<T>(m, geo, g, (double)x, (double)y, (double)w);
 }
 
 // ---------------------------------------------------------------------------
@@ -2809,10 +2825,12 @@ __global__ __launch_bounds__(256) void k_bk_back(DevModel m, SoA<T> from, SoA<T>
 // Number of systematic points below the cumulative boundary c:
 //   N(c) = #{ m in [0, L) : (m 2^32 + r) Q < c L 2^32 }.
 // A double estimate is corrected with exact 128-bit comparisons.
-__device__ __forceinline__ long long points_below(uint64_t c, uint64_t Q, long long L, uint32_t r)
+// (LQ = L / Q in double, formed once per workgroup: the estimate is within
+// one of the count and the exact comparisons settle it)
+__device__ __forceinline__ long long points_below(uint64_t c, uint64_t Q, long long L, uint32_t r, double LQ)
 {
     const unsigned __int128 rhs = ((unsigned __int128)c * (unsigned __int128)(uint64_t)L) << 32;
-    double est = ceil((double)c * (double)L / (double)Q - (double)r * 0x1p-32);
+    double est = ceil((double)c * LQ - (double)r * 0x1p-32);
     long long m0 = est < 0.0 ? 0 : (est > (double)L ? L : (long long)est);
     auto below = [&](long long mm) {
         const unsigned __int128 lhs = (unsigned __int128)((((uint64_t)mm) << 32) + (uint64_t)r) * (unsigned __int128)Q;
@@ -3041,14 +3059,15 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     const uint32_t r = rng_block(m.key0, m.key1, (uint32_t)gr.jl, step_of(step_arg, dstep), RNG_RESAMPLE, 0,
                                  gr.rng_run).a;
     const uint64_t Q = (uint64_t)Qd;
+    const double LQ = (double)L / Qd;
     // c_i = q_0 + ... + q_i of the group (exact: integers below 2^53)
     long long nend[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-        nend[h] = points_below((uint64_t)(Pd + hpre[h] + wpre[h] + qin[h]), Q, L, r);
+        nend[h] = points_below((uint64_t)(Pd + hpre[h] + wpre[h] + qin[h]), Q, L, r, LQ);
         s_end[h * 256 + tid] = nend[h];
     }
-    if (tid == 0) s_first = points_below((uint64_t)Pd, Q, L, r);
+    if (tid == 0) s_first = points_below((uint64_t)Pd, Q, L, r, LQ);
     __syncthreads();
     if (record) {
 #pragma unroll
@@ -3059,6 +3078,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         }
     }
     const long long cb = s_first, ce = s_end[RS_TILE - 1];
+    const double rL = 1.0 / (double)L, rxL = xL > 0 ? 1.0 / (double)xL : 0.0;
     for (long long c = cb + tid; c < ce; c += 256) {
         // last parent li with start(li) <= c, start(0) = s_first, start(li) = s_end[li-1]
         int lo = 0, hi = RS_TILE - 1;
@@ -3071,17 +3091,19 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
             // the stratum m with S_j(m) = floor((m L' + b_j) / Lx) = c, if any:
             // the least m with m L' + b_j >= c Lx (strata lie at least
             // L'/Lx > 1 slots apart, so there is at most one).  The quotients
-            // are estimated in double and settled by exact integer products
-            // (all below 2^53), which avoids 64-bit division per child.
+            // are estimated in double (products by the workgroup's
+            // reciprocals 1/L' and 1/Lx: within one of the quotient) and
+            // settled by exact integer products (all below 2^53), which
+            // avoids 64-bit division per child.
             const long long lo = c * xL;
-            long long mm = (long long)ceil((double)(lo - xb) / (double)L);
+            long long mm = (long long)ceil((double)(lo - xb) * rL);
             mm = mm < 0 ? 0 : mm;
             if (mm * L + xb < lo) ++mm;
             else if (mm > 0 && (mm - 1) * L + xb >= lo) --mm;
             if (mm < xL && mm * L + xb < lo + xL) {
                 // S_{j+1}(m) = floor((m L'_{j+1} + b_{j+1}) / Lx)
                 const long long num = mm * xn + xbn;
-                long long q = (long long)floor((double)num / (double)xL);
+                long long q = (long long)floor((double)num * rxL);
                 if (q * xL > num) --q;
                 else if ((q + 1) * xL <= num) ++q;
                 dst = xgb + (size_t)q;
