@@ -154,7 +154,7 @@ pphd_status reduce(pphd_mlp* h, int mode, int ntiles, double inv_n, float* loss_
     ad.eps = (float)h->cfg.eps;
     ad.bc1 = (float)(1.0 / (1.0 - std::pow(h->cfg.beta1, (double)std::max(t, 1))));
     ad.bc2 = (float)(1.0 / (1.0 - std::pow(h->cfg.beta2, (double)std::max(t, 1))));
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_ALL + NTHR - 1) / NTHR), dim3(NTHR), 0, h->stream, mode, h->part,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_ALL + RP - 1) / RP), dim3(NTHR), 0, h->stream, mode, h->part,
                        h->ploss, ntiles, inv_n, h->theta, h->am, h->av, h->grad, ad, h->Wt2, h->Wi2, h->Wt3,
                        h->Wi3, h->Wt4, h->Wi4, loss_out);
     MLP_LAUNCHED("k_mlp_reduce");

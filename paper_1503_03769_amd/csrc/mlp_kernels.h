@@ -3,19 +3,23 @@
 // Network 2 -> 128 -> 128 -> 128 -> 36 with ReLU, mapping a measurement to a
 // 4-component diagonal Gaussian mixture over [x, vx, y, vy] (definition in
 // include/pphd_mlp.h).  Layers 2-4 and their backward products run on the
-// matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32 accumulation);
-// layer 1, the mixture head and the loss run in FP32 on the vector units.
+// matrix cores (v_mfma_f32_16x16x32_bf16, gfx950's BF16 form with 32-deep
+// contractions: BF16 operands, FP32 accumulation; the 16-deep form only for
+// the last 16 of the output layer's 48 padded rows); layer 1, the mixture
+// head and the loss run in FP32 on the vector units.
 //
 // One workgroup (4 wavefronts) takes a tile of 64 pairs and keeps every
 // activation of the tile in LDS, so a training step reads each weight matrix
 // from L2 a few times per tile and writes one gradient partial per tile; a
 // second kernel sums the partials in a fixed order and takes the Adam step.
 //
-// MFMA 16x16x16 operand layout (lane l, r = l % 16, q = l / 16, e = 0..3):
-//   A[r][4q + e],  B[4q + e][r],  C[4q + e][r].
+// MFMA operand layouts (lane l, r = l % 16, q = l / 16):
+//   16x16x32: A[r][8q + i],  B[8q + i][r] (i = 0..7),  C[4q + e][r] (e = 0..3);
+//   16x16x16: A[r][4q + e],  B[4q + e][r],  C[4q + e][r].
 // Matrix products are arranged so that every operand read from a row-major
-// array is 4 consecutive BF16 values (one 8-byte load), except the weight
-// gradients, whose contraction runs over the pairs and gathers 4 rows.
+// array is 8 (or 4) consecutive BF16 values (one 16- or 8-byte load), except
+// the weight gradients, whose contraction runs over the pairs and gathers 8
+// rows.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -43,6 +47,8 @@ constexpr int TAB = MIX_TAB;  // doubles per mixture-table entry
 enum : uint32_t { RNG_PAIRS = 6, RNG_MLP_INIT = 7 };
 
 typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Features and normalised state: f = ((s + r (cos, sin) th) - c) / h,
@@ -77,16 +83,16 @@ __device__ __forceinline__ uint64_t pack4(float a, float b, float c, float d)
 }
 __device__ __forceinline__ float bf16_value(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
 __device__ __forceinline__ bf4 ld8(const uint16_t* p) { return __builtin_bit_cast(bf4, *(const uint64_t*)p); }
-__device__ __forceinline__ bf4 gather4(const uint16_t* p, int stride)
+__device__ __forceinline__ bf8 ld16(const uint16_t* p) { return __builtin_bit_cast(bf8, *(const u4v*)p); }
+__device__ __forceinline__ bf8 gather8(const uint16_t* p, int stride)
 {
-    bf4 v;
-    v[0] = (short)p[0];
-    v[1] = (short)p[stride];
-    v[2] = (short)p[2 * stride];
-    v[3] = (short)p[3 * stride];
-    return v;
+    u4v v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (uint32_t)p[2 * i * stride] | ((uint32_t)p[(2 * i + 1) * stride] << 16);
+    return __builtin_bit_cast(bf8, v);
 }
 __device__ __forceinline__ f4 mma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ f4 mma32(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 // 1 where a stored ReLU output is positive (its BF16 magnitude bits nonzero)
 __device__ __forceinline__ float relu_mask(uint64_t v, int e) { return ((v >> (16 * e)) & 0x7FFFu) ? 1.0f : 0.0f; }
 
@@ -115,14 +121,14 @@ __device__ __forceinline__ void hidden_fwd(const uint16_t* __restrict__ Wt, cons
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) acc[t][sb] = f4{ 0, 0, 0, 0 };
 #pragma unroll 2
-    for (int kb = 0; kb < H / 16; ++kb) {
-        const bf4 a0 = ld8(Wt + ((2 * w) * 16 + r) * H + kb * 16 + 4 * q);
-        const bf4 a1 = ld8(Wt + ((2 * w + 1) * 16 + r) * H + kb * 16 + 4 * q);
+    for (int kb = 0; kb < H / 32; ++kb) {
+        const bf8 a0 = ld16(Wt + ((2 * w) * 16 + r) * H + kb * 32 + 8 * q);
+        const bf8 a1 = ld16(Wt + ((2 * w + 1) * 16 + r) * H + kb * 32 + 8 * q);
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
-            const bf4 bb = ld8(In + (sb * 16 + r) * HP + kb * 16 + 4 * q);
-            acc[0][sb] = mma(a0, bb, acc[0][sb]);
-            acc[1][sb] = mma(a1, bb, acc[1][sb]);
+            const bf8 bb = ld16(In + (sb * 16 + r) * HP + kb * 32 + 8 * q);
+            acc[0][sb] = mma32(a0, bb, acc[0][sb]);
+            acc[1][sb] = mma32(a1, bb, acc[1][sb]);
         }
     }
 #pragma unroll
@@ -150,10 +156,10 @@ __device__ __forceinline__ void output_fwd(const uint16_t* __restrict__ Wt4, con
 #pragma unroll
     for (int sb = 0; sb < 4; ++sb) acc[sb] = f4{ 0, 0, 0, 0 };
 #pragma unroll 2
-    for (int kb = 0; kb < H / 16; ++kb) {
-        const bf4 a = ld8(Wt4 + (w * 16 + r) * H + kb * 16 + 4 * q);
+    for (int kb = 0; kb < H / 32; ++kb) {
+        const bf8 a = ld16(Wt4 + (w * 16 + r) * H + kb * 32 + 8 * q);
 #pragma unroll
-        for (int sb = 0; sb < 4; ++sb) acc[sb] = mma(a, ld8(In + (sb * 16 + r) * HP + kb * 16 + 4 * q), acc[sb]);
+        for (int sb = 0; sb < 4; ++sb) acc[sb] = mma32(a, ld16(In + (sb * 16 + r) * HP + kb * 32 + 8 * q), acc[sb]);
     }
     const int j0 = w * 16 + 4 * q;
 #pragma unroll
@@ -166,7 +172,8 @@ __device__ __forceinline__ void output_fwd(const uint16_t* __restrict__ Wt4, con
 
 // Backward through a layer's weights: G_out[s][k] = mask(Hk[s][k]) *
 // sum_j G_in[s][j] W[j][k], with Wi = W^T stored row-major ([k][j], row
-// length NJ) and the contraction over j in NJ/16 steps.
+// length NJ) and the contraction over j in 32-deep steps (a 16-deep one for
+// the rest when NJ is an odd multiple of 16).
 template <int NJ>
 __device__ __forceinline__ void back_data(const uint16_t* __restrict__ Wi, const uint16_t* Gin, const uint16_t* Hk,
                                           uint16_t* Gout, int w, int lane)
@@ -177,13 +184,25 @@ __device__ __forceinline__ void back_data(const uint16_t* __restrict__ Wi, const
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) acc[t][sb] = f4{ 0, 0, 0, 0 };
+    static_assert(NJ % 16 == 0, "whole 16-deep blocks");
 #pragma unroll 2
-    for (int jb = 0; jb < NJ / 16; ++jb) {
-        const bf4 a0 = ld8(Wi + ((2 * w) * 16 + r) * NJ + jb * 16 + 4 * q);
-        const bf4 a1 = ld8(Wi + ((2 * w + 1) * 16 + r) * NJ + jb * 16 + 4 * q);
+    for (int jb = 0; jb < NJ / 32; ++jb) {
+        const bf8 a0 = ld16(Wi + ((2 * w) * 16 + r) * NJ + jb * 32 + 8 * q);
+        const bf8 a1 = ld16(Wi + ((2 * w + 1) * 16 + r) * NJ + jb * 32 + 8 * q);
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
-            const bf4 bb = ld8(Gin + (sb * 16 + r) * HP + jb * 16 + 4 * q);
+            const bf8 bb = ld16(Gin + (sb * 16 + r) * HP + jb * 32 + 8 * q);
+            acc[0][sb] = mma32(a0, bb, acc[0][sb]);
+            acc[1][sb] = mma32(a1, bb, acc[1][sb]);
+        }
+    }
+    if constexpr (NJ % 32 == 16) {
+        constexpr int j0 = NJ - 16;
+        const bf4 a0 = ld8(Wi + ((2 * w) * 16 + r) * NJ + j0 + 4 * q);
+        const bf4 a1 = ld8(Wi + ((2 * w + 1) * 16 + r) * NJ + j0 + 4 * q);
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) {
+            const bf4 bb = ld8(Gin + (sb * 16 + r) * HP + j0 + 4 * q);
             acc[0][sb] = mma(a0, bb, acc[0][sb]);
             acc[1][sb] = mma(a1, bb, acc[1][sb]);
         }
@@ -215,18 +234,19 @@ __device__ __forceinline__ void weight_grad(const uint16_t* G, int jb0, const ui
     for (int t = 0; t < NJB; ++t)
 #pragma unroll
         for (int u = 0; u < NKB; ++u) acc[t][u] = f4{ 0, 0, 0, 0 };
+    static_assert(TS % 32 == 0, "whole 32-deep blocks of pairs");
 #pragma unroll
-    for (int ss = 0; ss < TS / 16; ++ss) {
-        const int s0 = ss * 16 + 4 * q;
-        bf4 a[NJB], b[NKB];
+    for (int ss = 0; ss < TS / 32; ++ss) {
+        const int s0 = ss * 32 + 8 * q;
+        bf8 a[NJB], b[NKB];
 #pragma unroll
-        for (int t = 0; t < NJB; ++t) a[t] = gather4(G + s0 * HP + (jb0 + t) * 16 + r, HP);
+        for (int t = 0; t < NJB; ++t) a[t] = gather8(G + s0 * HP + (jb0 + t) * 16 + r, HP);
 #pragma unroll
-        for (int u = 0; u < NKB; ++u) b[u] = gather4(Hk + s0 * HP + (kb0 + u) * 16 + r, HP);
+        for (int u = 0; u < NKB; ++u) b[u] = gather8(Hk + s0 * HP + (kb0 + u) * 16 + r, HP);
 #pragma unroll
         for (int t = 0; t < NJB; ++t)
 #pragma unroll
-            for (int u = 0; u < NKB; ++u) acc[t][u] = mma(a[t], b[u], acc[t][u]);
+            for (int u = 0; u < NKB; ++u) acc[t][u] = mma32(a[t], b[u], acc[t][u]);
     }
 #pragma unroll
     for (int t = 0; t < NJB; ++t)
@@ -350,9 +370,11 @@ __device__ __forceinline__ void features_of(const Norm& n, double r, double th, 
 
 // ---- kernels ---------------------------------------------------------------
 
+// (activation rows are read 16 bytes at a time: 16-byte aligned, a row
+// pitch of 272 bytes)
 struct TrainLds {
-    uint16_t h[3][TS * HP];  // h1, h2, h3 of the tile, [pair][unit]
-    uint16_t g[2][TS * HP];  // back-propagated terms, [pair][unit]
+    alignas(16) uint16_t h[3][TS * HP];  // h1, h2, h3 of the tile, [pair][unit]
+    alignas(16) uint16_t g[2][TS * HP];  // back-propagated terms, [pair][unit]
     float o[TS * NOP];       // outputs, then d loss / d o
     float f[TS][2];
     float xi[TS][4];
@@ -454,7 +476,7 @@ __global__ __launch_bounds__(NTHR) void k_mlp_train(Net net, Norm nrm, const flo
 }
 
 struct InferLds {
-    uint16_t h[2][TS * HP];
+    alignas(16) uint16_t h[2][TS * HP];
     float o[TS * NOP];
     float f[TS][2];
 };
@@ -514,23 +536,47 @@ __global__ __launch_bounds__(NTHR) void k_mix_head(Norm nrm, const double* __res
 struct Adam {
     float lr, beta1, beta2, eps, bc1, bc2;  // bc = 1 / (1 - beta^t)
 };
+// Sum of the tiles' gradient partials, Adam step and the BF16 copies.  A
+// workgroup takes RP consecutive parameters; its threads (chunk c, parameter
+// u) add the tiles of chunk c (RC chunks of consecutive tiles) in tile
+// order, and the RC chunk sums are added in chunk order, so the order is
+// fixed; many workgroups keep enough reads in flight.  grid (ceil(P_ALL/RP)).
+constexpr int RP = 32, RC = NTHR / RP;
 __global__ __launch_bounds__(NTHR) void k_mlp_reduce(int mode, const float* __restrict__ part,
                                                      const double* __restrict__ ploss, int ntiles, double inv_n,
                                                      float* theta, float* am, float* av, float* grad, Adam ad,
                                                      uint16_t* Wt2, uint16_t* Wi2, uint16_t* Wt3, uint16_t* Wi3,
                                                      uint16_t* Wt4, uint16_t* Wi4, float* loss_out)
 {
-    const int p = blockIdx.x * NTHR + threadIdx.x;
-    if (p == 0 && loss_out) {
+    __shared__ double s_acc[RC][RP];
+    const int u = threadIdx.x % RP, c = threadIdx.x / RP;
+    const int p = blockIdx.x * RP + u;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
         double acc = 0.0;
         for (int t = 0; t < ntiles; ++t) acc += ploss[t];
         *loss_out = (float)(acc * inv_n);
     }
-    if (p >= P_ALL) return;
+    const int per = (ntiles + RC - 1) / RC, t0 = c * per, t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    if (mode != 2) {
+        double acc = 0.0;
+        if (p < P_ALL) {
+            for (int ta = t0; ta < t1; ta += 8) {
+                float v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = ta + k < t1 ? part[(size_t)(ta + k) * P_ALL + p] : 0.0f;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (ta + k < t1) acc += (double)v[k];
+            }
+        }
+        s_acc[c][u] = acc;
+    }
+    __syncthreads();
+    if (c != 0 || p >= P_ALL) return;
     float th = theta[p];
     if (mode != 2) {
         double acc = 0.0;
-        for (int t = 0; t < ntiles; ++t) acc += (double)part[(size_t)t * P_ALL + p];
+        for (int k = 0; k < RC; ++k) acc += s_acc[k][u];
         const float g = (float)(acc * inv_n);
         if (mode == 0) {
             grad[p] = g;

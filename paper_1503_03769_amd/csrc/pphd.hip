@@ -574,6 +574,8 @@ template <typename T>
 pphd_status order_births(pphd_filter* f, bool weights_later);
 template <typename T>
 bool births_in_one_launch(const pphd_filter* f);
+template <typename T>
+bool predict_rides(const pphd_filter* f);
 int predict_parts(const pphd_filter* f);
 pphd_status flush_predict(pphd_filter* f);
 
@@ -594,7 +596,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     const int zruns = f->pass_mode == PASS_FRAMES ? f->nruns : 0;
     bool zprep_done = false;
     // a pending prediction rides in the births' launch, else it goes first
-    if (f->pr_pending && !(f->births_pending && births_in_one_launch<T>(f))) {
+    if (f->pr_pending && !(f->births_pending && predict_rides<T>(f))) {
         pphd_status ps = flush_predict(f);
         if (ps != PPHD_OK) return ps;
     }
@@ -804,12 +806,21 @@ pphd_status flush_resample(pphd_filter* f);
 
 // births of a measurement-driven proposal drawn and ordered by
 // k_birth_draw_sort, one workgroup per group (the update's launch that can
-// also carry the survivors' prediction)
+// also carry the survivors' prediction: for filters of up to
+// PREDICT_RIDE_SLOTS slots, where saving a launch pays; larger ones predict
+// in k_predict's own launch, whose 256-thread workgroups run at the
+// occupancy of the prediction's registers rather than the births')
+constexpr int64_t PREDICT_RIDE_SLOTS = (int64_t)1 << 23;
 template <typename T>
 bool births_in_one_launch(const pphd_filter* f)
 {
     constexpr int BS = sizeof(T) == 4 ? 8 : 4;
     return (f->dm.proposal == 1 || f->dm.proposal == 2) && f->Jmax > 0 && f->Jmax <= 1024 * BS;
+}
+template <typename T>
+bool predict_rides(const pphd_filter* f)
+{
+    return births_in_one_launch<T>(f) && (int64_t)f->K * f->cap <= PREDICT_RIDE_SLOTS;
 }
 
 // workgroups of 1024 slots that predict every group's survivors
@@ -839,7 +850,7 @@ pphd_status run_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
 {
     pphd_status fs = flush_resample(f);
     if (fs != PPHD_OK) return fs;
-    if (births_in_one_launch<T>(f)) {
+    if (predict_rides<T>(f)) {
         // the update draws the births in one launch per step; the survivors'
         // prediction rides in it (it needs nothing the births change)
         f->pr_pending = true;
