@@ -669,22 +669,24 @@ __device__ __forceinline__ double birth_weight_at(const DevModel& m, const Birth
             for (int e0 = 0; e0 < 4 * M; e0 += 64) {
                 const int e = e0 + lane;
                 bool need = false;
-                const double* t = src.tab + (size_t)(e < 4 * M ? e : 0) * MIX_TAB;
-                const double lc = t[2], mu0 = t[4], mu1 = t[5], mu2 = t[6], mu3 = t[7];
-                const double is0 = t[12], is1 = t[13], is2 = t[14], is3 = t[15];
+                // the bound reads the five values it needs
                 if (e < 4 * M) {
-                    const double d0 = box_gap(mu0, xlo, xhi) * is0, d2 = box_gap(mu2, ylo, yhi) * is2;
-                    need = 0.5 * (d0 * d0 + d2 * d2) - lc < cut;
+                    const double* t = src.tab + (size_t)e * MIX_TAB;
+                    const double d0 = box_gap(t[4], xlo, xhi) * t[12], d2 = box_gap(t[6], ylo, yhi) * t[14];
+                    need = 0.5 * (d0 * d0 + d2 * d2) - t[2] < cut;
                 }
-                // position part first: a far component is skipped before its exponential
+                // a kept term's entry is the same for the whole wavefront
+                // (scalar reads); position part first: a far component is
+                // skipped before its exponential
                 for (uint64_t live = __ballot(need); live; live &= live - 1) {
                     const int l = __builtin_ctzll(live);
-                    const double d0 = (x[0] - lane_value(mu0, l)) * lane_value(is0, l);
-                    const double d2 = (x[2] - lane_value(mu2, l)) * lane_value(is2, l);
-                    const double ap = 0.5 * (d0 * d0 + d2 * d2) - lane_value(lc, l);
+                    const double* t = src.tab + (size_t)(e0 + l) * MIX_TAB;
+                    const double d0 = (x[0] - t[4]) * t[12];
+                    const double d2 = (x[2] - t[6]) * t[14];
+                    const double ap = 0.5 * (d0 * d0 + d2 * d2) - t[2];
                     if (ap < cut) {
-                        const double d1 = (x[1] - lane_value(mu1, l)) * lane_value(is1, l);
-                        const double d3 = (x[3] - lane_value(mu3, l)) * lane_value(is3, l);
+                        const double d1 = (x[1] - t[5]) * t[13];
+                        const double d3 = (x[3] - t[7]) * t[15];
                         mix += neg_exp(ap + 0.5 * (d1 * d1 + d3 * d3), T(0));
                     }
                 }
