@@ -1455,19 +1455,32 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
     auto zop = [&](int q) { return ZOp{ zs[2 * q], zs[2 * q + 1], zHs[zb + q], zFs[zb + q], zfls[zb + q] }; };
     const ZOp z0 = p0 < p1 ? zop(p0 + lane < p1 ? p0 + lane : p0) : ZOp{ 0.0, 0.0, 0, (T)0, 0 };
     const size_t pz = ((size_t)j * sp.wtiles + tile) * Mmax;
-    // a candidate label's local-estimate sums (the tile's weighted states are
-    // read here, by the tiles that keep the candidate: 0 in empty slots)
+    // the velocities, read once by tiles that keep a candidate label: issued
+    // when a chunk first holds one, so the reads overlap that chunk's other
+    // measurements instead of stalling every candidate
+    T v1[PT], v3[PT];
+    bool have_v = false;
+    auto load_velocities = [&]() {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int s = base + i * 64 + lane;
+            uint32_t g = s < n ? s : base;
+            // formed here, not hoisted out of the measurement loop (live
+            // 64-bit addresses would cost registers for the whole pass)
+            __asm__ volatile("" : "+v"(g));
+            v1[i] = ld_slot(gx1, g);
+            v3[i] = ld_slot(gx3, g);
+        }
+        have_v = true;
+    };
+    // a candidate label's local-estimate sums (0 in empty slots)
     auto cand = [&](double zr, double zt, double H, T F, int fl, const double* ang) {
         T u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0;
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
             const int s = base + i * 64 + lane;
             const bool ok = s < n;
-            uint32_t g = ok ? s : base;
-            // formed here, not hoisted out of the measurement loop (live
-            // 64-bit addresses would cost registers for the whole pass)
-            __asm__ volatile("" : "+v"(g));
-            const T x1 = ld_slot(gx1, g), x3 = ld_slot(gx3, g);
+            const T x1 = v1[i], x3 = v3[i];
             const T e = fast_exp2(-(T)sq_resid_nowrap(zr, zt, rho[i], ang[i], H));
             acc[i] += e * F;
             const T u = ok ? e * (T)(m.wscale * (double)wv[i]) : (T)0;
@@ -1544,6 +1557,7 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
         }
         const uint64_t cset = __ballot(need && o.fl != 0);
         const uint64_t live = __ballot(need);
+        if (cset && !have_v) load_velocities();
         const int na = nA - c0 < 0 ? 0 : (nA - c0 > 64 ? 64 : nA - c0);
         const uint64_t amask = na >= 64 ? ~0ull : ((1ull << na) - 1ull);
         run(live & amask, cset, o, phi);
