@@ -2,7 +2,8 @@
 r = 0): the distributed filter with K = 4 groups of N/K particles tracks as
 well as the standard filter with N particles, and both beat the standard
 filter with only N/K particles.  60 paired Monte Carlo runs (the same tracks
-for the three methods), run as GPU batches."""
+for the three methods), run as GPU batches.  At r = 10 the order of the
+N/K filter holds, and the count errors are mostly misses from a low mass."""
 import pytest
 
 from paper_1503_03769_amd.paper_table import run_config
@@ -15,6 +16,45 @@ def test_distributed_filter_matches_full_filter(gpu):
     print(res, flush=True)
     assert abs(res["DCPPHD"] - res["PHD"]) < 0.05 * res["PHD"], res
     assert res["partPHD"] > res["DCPPHD"] and res["partPHD"] > res["PHD"], res
+
+
+def test_clutter_keeps_the_order_and_the_mass_runs_low(gpu):
+    """r = 10: the filter with only N/K particles stays the least accurate.
+    With p_D = 1 and clutter every detected target adds C/(kappa + C) < 1 to
+    the updated mass (Eqs 12-15), so the mass runs below the number of
+    targets and Step 3's round(mass) misses targets far more often than it
+    adds one: the count errors behind the larger OSPA with clutter."""
+    import numpy as np
+
+    from paper_1503_03769_amd import pphd
+    from paper_1503_03769_amd.scenario import PAPER_MODEL, make_paper_scenario
+
+    res = {m: run_config(m, 10.0, 60, 50)["mean_ospa"] for m in ("PHD", "DCPPHD", "partPHD")}
+    print(res, flush=True)
+    assert res["partPHD"] > res["DCPPHD"] and res["partPHD"] > res["PHD"], res
+    p = dict(PAPER_MODEL, clutter_rate=10.0, partitions=1, particles_per_target=800.0, births_per_step=800)
+    bias, low, high = [], 0, 0
+    for i in range(12):
+        truth, Z = make_paper_scenario(p, 50, 77000 + i)
+        f = pphd.Filter(p, pphd.PPHD_FP64, 8192, max(z.shape[0] for z in Z[1:]) + 1, 4242, i)
+        f.init()
+        for k in range(1, 51):
+            f.predict(k)
+            f.update(Z[k])
+            u = f.read_update()
+            f.resample(k)
+            f.exchange(k)
+            n = truth[k].shape[0]
+            if n == 0:
+                continue
+            mass = float(u["mass"].sum())
+            bias.append(mass - n)
+            low += int(u["LT"][0]) < n
+            high += int(u["LT"][0]) > n
+        f.close()
+    print(f"mean(mass - n) {np.mean(bias):+.3f}; round(mass) low in {low}, high in {high} of {len(bias)} scans",
+          flush=True)
+    assert np.mean(bias) < -0.1 and low > 2 * high
 
 
 def test_paper_model_fp64_update_matches_oracle(gpu):
