@@ -631,16 +631,25 @@ def tuning_record(pphd, shape, elapsed, elapsed_default, steps, batch, prec, gro
 
 
 def host_cpu():
-    """The host's CPU model name, logical CPU count and the CPUs this process
-    may run on."""
+    """The host's CPU model name (with the family, model and stepping numbers
+    /proc/cpuinfo gives, since a virtual machine may shorten the name),
+    logical CPU count and the CPUs this process may run on."""
     model = "unknown"
+    ids = {}
     try:
         for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
+            key = ln.split(":", 1)[0].strip()
+            if key == "model name" and model == "unknown":
                 model = ln.split(":", 1)[1].strip()
+            elif key in ("cpu family", "model", "stepping") and key not in ids:
+                ids[key] = ln.split(":", 1)[1].strip()
+            elif not ln.strip() and model != "unknown":
                 break
     except OSError:
         pass
+    if ids:
+        model += " (family " + ids.get("cpu family", "?") + ", model " + ids.get("model", "?") + \
+            ", stepping " + ids.get("stepping", "?") + ")"
     try:
         usable = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
