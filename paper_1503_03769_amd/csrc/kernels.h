@@ -390,11 +390,13 @@ __global__ __launch_bounds__(256) void k_predict(DevModel m, const Grp* __restri
     if (s < total) predict_slot(m, gr, st, geo, ns, Jj, j, s, step, bkt);
 }
 
-// Step 1 for 1024 slots of one group, as k_predict does it for 256 (the
+// Step 1 for 2048 slots of one group, as k_predict does it for 256 (the
 // prediction rides in the births' launch when the births are drawn there):
-// part w takes group w mod K, slots [1024 floor(w / K), +1024), so every
-// group's first slots come first (groups of clearly different sizes: the
-// group's slot blocks one after another, spreading it over the chip's dies)
+// part w takes group w mod K, slots [2048 floor(w / K), +2048), two per
+// thread, so every group's first slots come first (groups of clearly
+// different sizes: the group's slot blocks one after another, spreading it
+// over the chip's dies).  Two slots per thread halve the workgroups to
+// dispatch, most of which are empty (the parts follow the capacity)
 template <typename T>
 __device__ __forceinline__ void predict_part(const DevModel& m, const Grp* __restrict__ gd, const SoA<T>& st,
                                              const Geo& geo, const int* __restrict__ nsurv, int* __restrict__ ncur,
@@ -402,7 +404,7 @@ __device__ __forceinline__ void predict_part(const DevModel& m, const Grp* __res
 {
     int j, t4;
     if (m.tile_major) {
-        const int per = (m.cap + 1023) / 1024;
+        const int per = (m.cap + 2047) / 2048;
         j = w / per;
         t4 = w - j * per;
     } else {
@@ -413,8 +415,9 @@ __device__ __forceinline__ void predict_part(const DevModel& m, const Grp* __res
     const int ns = nsurv[j];
     const int total = ns + gr.Jj < m.cap ? ns + gr.Jj : m.cap;
     if (t4 == 0 && threadIdx.x == 0) ncur[j] = total;
-    const int s = t4 * 1024 + threadIdx.x;
+    const int s = t4 * 2048 + threadIdx.x;
     if (s < ns) predict_slot(m, gr, st, geo, ns, gr.Jj, j, s, step, bkt);
+    if (s + 1024 < ns) predict_slot(m, gr, st, geo, ns, gr.Jj, j, s + 1024, step, bkt);
 }
 
 // dim 5: the turn rate of a birth drawn from a measurement-driven or learned
@@ -2730,7 +2733,7 @@ __global__ __launch_bounds__(1024) void k_birth_draw_sort(DevModel m, const Grp*
 {
     // workgroups past the K0 groups prepare the measurements of run
     // blockIdx.x - K0 for the likelihood passes (no birth reads them); the
-    // ones past those, if any, predict the survivors (Step 1), 1024 slots
+    // ones past those, if any, predict the survivors (Step 1), 2048 slots
     // each: the births fill the slots after the survivors, so the two parts
     // touch different slots and run side by side
     if ((int)blockIdx.x >= K0) {

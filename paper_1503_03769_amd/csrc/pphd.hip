@@ -823,8 +823,8 @@ bool predict_rides(const pphd_filter* f)
     return births_in_one_launch<T>(f) && (int64_t)f->K * f->cap <= PREDICT_RIDE_SLOTS;
 }
 
-// workgroups of 1024 slots that predict every group's survivors
-int predict_parts(const pphd_filter* f) { return f->K * ((f->cap + 1023) / 1024); }
+// workgroups of 2048 slots that predict every group's survivors
+int predict_parts(const pphd_filter* f) { return f->K * ((f->cap + 2047) / 2048); }
 
 template <typename T>
 pphd_status launch_predict(pphd_filter* f, uint32_t step, const uint32_t* dstep)
