@@ -143,3 +143,57 @@ def test_runs_are_deterministic(gpu):
     for j in range(8):
         sl = slice(j * 8192, j * 8192 + int(na[j]))     # slots beyond the count are unspecified
         assert np.array_equal(Xa[:, sl], Xb[:, sl]) and np.array_equal(Wa[sl], Wb[sl])
+
+
+def test_device_extract_fuses_with_the_resampling_scatter(gpu):
+    """pphd_extract_device right after an update launches the resampling's
+    parent scatter with the fusion in its first workgroups; pphd_resample
+    then skips the scatter.  Against host extraction (k_fuse alone, the
+    scatter at pphd_resample): the same estimates and bit-identical particle
+    sets every step.  Also a second device extraction in the same step (the
+    fusion alone, the scatter not repeated) and a state written between the
+    extraction and the resampling (which must scatter the written state)."""
+    import torch
+
+    p = dict(BASE_MODEL, partitions=16, particles_per_target=2.0e4, births_per_step=3000, clutter_rate=50.0,
+             birth_proposal=1, birth_alpha=0.1)
+    truth, Z = make_scenario(p, 6, 7, 5)
+    cap, Mx = 8192, 512
+    host = P.make_filter(p, "fp32", cap, max_meas=Mx, seed=41)
+    dev = P.make_filter(p, "fp32", cap, max_meas=Mx, seed=41)
+    out = torch.zeros((Mx * 40 + 7) // 8, dtype=torch.float64, device="cuda")
+    nout = torch.zeros(1, dtype=torch.int32, device="cuda")
+    host.init()
+    dev.init()
+    for k in range(1, 8):
+        print(f"  step {k}", flush=True)
+        for f in (host, dev):
+            f.predict(k)
+            f.update(Z[k])
+        est_h, _ = host.extract()
+        dev.extract_device(out, nout, Mx)
+        if k == 3:
+            dev.extract_device(out, nout, Mx)       # the fusion again, no second scatter
+        if k == 5:
+            # a written state replaces the one the extraction scattered
+            for f in (host, dev):
+                X, W, n = f.read_state()
+                W = (W * 0.5).astype(W.dtype)
+                f.write_state(X, W, n, pphd.PHASE_UPDATED)
+        torch.cuda.synchronize()
+        n_d = int(nout.cpu()[0])
+        recs = np.frombuffer(out.cpu().numpy().tobytes(), dtype=pphd.ESTIMATE_DTYPE)[:min(n_d, Mx)]
+        assert n_d == len(est_h), (k, n_d, len(est_h))
+        assert list(recs["label"]) == list(est_h["label"]) and list(recs["votes"]) == list(est_h["votes"])
+        assert np.array_equal(recs["state"], est_h["state"]), k
+        for f in (host, dev):
+            f.resample(k)
+            f.exchange(k)
+        Xa, Wa, na = host.read_state()
+        Xb, Wb, nb = dev.read_state()
+        assert np.array_equal(na, nb), k
+        for j in range(16):
+            sl = slice(j * cap, j * cap + int(na[j]))
+            assert np.array_equal(Xa[:, sl], Xb[:, sl]) and np.array_equal(Wa[sl], Wb[sl]), (k, j)
+    host.close()
+    dev.close()
