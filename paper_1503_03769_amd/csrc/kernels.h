@@ -1132,16 +1132,98 @@ __device__ __forceinline__ TileItem tile_item(int e, int n, int ns, int WT)
     if (e < ta) return TileItem{ e, 0, 1 };
     return TileItem{ ta + (e - ta) / z, (e - ta) % z, z };
 }
+// Heavy tiles of the second pass.  A survivors' tile whose first-pass
+// wavefront kept at least HEAVY_KEPT measurements is taken by the second
+// pass as BIRTH_CHUNKS items too (measurement chunks in one workgroup, their
+// sums meeting in LDS), so that a few tiles spanning many measurements do
+// not set the pass's length.  The first pass records each survivors' tile's
+// kept count; k_cz_combine then writes each group's item table for the
+// second pass (tile | chunk << 20 | chunked << 23): the chunked tiles first
+// (births', then heavy survivors' tiles, whole 4-item spans), the others
+// after.  Which tiles are heavy follows from the first pass's results alone,
+// so a run splits the same way alone or in a batch.
+constexpr int HEAVY_KEPT = 16;
+__device__ __forceinline__ TileItem item_decode(int v)
+{
+    const int chunked = (v >> 23) & 1;
+    return TileItem{ v & 0xFFFFF, chunked ? (v >> 20) & 3 : 0, chunked ? BIRTH_CHUNKS : 1 };
+}
+// group j's item table (one 1024-thread workgroup; contains barriers)
+__device__ void build_items(int j, int n, int ns, int WT, const int* __restrict__ tkept, int wtiles,
+                            int* __restrict__ items, int imax, int* __restrict__ nitems)
+{
+    __shared__ int s_cnt[2];
+    __shared__ unsigned char s_heavy[4096];
+    const int nt = (n + WT - 1) / WT, ta = tiles_before_births(n, ns, WT), z = birth_chunks(n, ns, WT);
+    const int nbc = z > 1 ? nt - ta : 0;  // chunked birth tiles
+    int* it = items + (size_t)j * imax;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) {
+        s_cnt[0] = 0;
+        s_cnt[1] = 0;
+    }
+    // (tables beyond 4096 survivors' tiles split no tile)
+    const int tah = ta < 4096 ? ta : 0;
+    for (int t = threadIdx.x; t < tah; t += 1024) s_heavy[t] = tkept[(size_t)j * wtiles + t] >= HEAVY_KEPT ? 1 : 0;
+    __syncthreads();
+    // wavefront 0 ranks the heavy and the light survivors' tiles, 64 at a time
+    if (threadIdx.x < 64) {
+        int nh = 0, nl = 0;
+        for (int t0 = 0; t0 < ta; t0 += 64) {
+            const int t = t0 + lane;
+            const bool live = t < ta;
+            const bool hv = live && t < tah && s_heavy[t];
+            const unsigned long long bh = __ballot(hv), bl = __ballot(live && !hv);
+            const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+            if (hv) {
+                const int pos = 4 * (nbc + nh + __popcll(bh & below));
+#pragma unroll
+                for (int c = 0; c < 4; ++c) it[pos + c] = t | (c << 20) | (1 << 23);
+            } else if (live) {
+                s_heavy[t] = 2;  // light (its position comes once every heavy tile is counted)
+            }
+            nh += __popcll(bh);
+            nl += __popcll(bl);
+        }
+        if (lane == 0) {
+            s_cnt[0] = nh;
+            s_cnt[1] = nl;
+        }
+    }
+    __syncthreads();
+    const int nh = s_cnt[0];
+    // the births' tiles: chunked first, or light at the end
+    for (int e = threadIdx.x; e < 4 * nbc; e += 1024) it[e] = (ta + e / 4) | ((e % 4) << 20) | (1 << 23);
+    const int lbase = 4 * (nbc + nh);
+    if (threadIdx.x < 64) {
+        int nl = 0;
+        for (int t0 = 0; t0 < ta; t0 += 64) {
+            const int t = t0 + lane;
+            const bool light = t < ta && (t >= tah || s_heavy[t] == 2);
+            const unsigned long long bl = __ballot(light);
+            const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+            if (light) it[lbase + nl + __popcll(bl & below)] = t;
+            nl += __popcll(bl);
+        }
+        const int nbl = z > 1 ? 0 : nt - ta;
+        for (int b = lane; b < nbl; b += 64) it[lbase + nl + b] = ta + b;
+        if (lane == 0) nitems[j] = lbase + nl + nbl;
+    }
+}
+
 // the flat list: item counts and their prefix (one workgroup of 1024 threads,
-// thread i taking a contiguous run of ceil(K/1024) groups) ...
+// thread i taking a contiguous run of ceil(K/1024) groups; cnt: the groups'
+// item tables' counts, else the counts the sizes give) ...
 __global__ __launch_bounds__(1024) void k_items_scan(const int* __restrict__ ncur, const int* __restrict__ nsurv,
-                                                     int K, int WT, int* __restrict__ pre)
+                                                     int K, int WT, int* __restrict__ pre,
+                                                     const int* __restrict__ cnt)
 {
     __shared__ int s_w[16];
     const int G = (K + 1023) / 1024;
     const int j0 = threadIdx.x * G < K ? threadIdx.x * G : K, j1 = j0 + G < K ? j0 + G : K;
+    auto items_of = [&](int j) { return cnt ? (cnt[j] + 3) & ~3 : list_items(ncur[j], nsurv[j], WT); };
     int c = 0;
-    for (int j = j0; j < j1; ++j) c += list_items(ncur[j], nsurv[j], WT);
+    for (int j = j0; j < j1; ++j) c += items_of(j);
     const int incl = (int)wave_incl_scan((double)c);  // exact: counts stay below 2^53
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 63) s_w[wv] = incl;
@@ -1150,7 +1232,7 @@ __global__ __launch_bounds__(1024) void k_items_scan(const int* __restrict__ ncu
     for (int w = 0; w < wv; ++w) pos += s_w[w];
     for (int j = j0; j < j1; ++j) {
         pre[j] = pos;
-        pos += list_items(ncur[j], nsurv[j], WT);
+        pos += items_of(j);
     }
     if (threadIdx.x == 1023) pre[K] = pos;
 }
@@ -1190,7 +1272,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
                                                const ZWin* __restrict__ win, const ZPrepC& zp, int Mmax,
                                                const Split& sp, double* __restrict__ ps, int* __restrict__ ph,
                                                double* __restrict__ pw, const int* __restrict__ zrec, int j,
-                                               int zrun, int tile, int zc, int zsplit)
+                                               int zrun, int tile, int zc, int zsplit, int* __restrict__ tkept)
 {
     constexpr int WT = 64 * PT;
     const int lane = threadIdx.x & 63;
@@ -1271,6 +1353,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
     };
     // every nlw is >= 0 (hw is the ceiling of the tile's largest log weight).
     // Lane l tests measurement c0 + l; the ones left are read from their lane.
+    int kept = 0;  // measurements this wavefront keeps (the whole tile's when zsplit = 1)
     auto frame = [&](int pa, int pb, const double* ang, bool fb, double zr0, double zt0) {
         for (int c0 = pa; c0 < pb; c0 += 64) {
             const int p = c0 + lane;
@@ -1283,6 +1366,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
                 if (!need) ps[pbase + p] = 0.0;
             }
             uint64_t live = __ballot(need);
+            kept += __popcll(live);
             while (live) {
                 const int l = __builtin_ctzll(live);
                 live &= live - 1;
@@ -1299,6 +1383,7 @@ __device__ __forceinline__ void cz_frames_tile(const DevModel& m, const Grp* __r
     };
     frame(p0, a1, phi, false, zra0, zta0);
     frame(b0, p1, phib, true, zrb0, ztb0);
+    if (tkept && zsplit == 1 && lane == 0) tkept[(size_t)j * sp.wtiles + tile] = kept;
 }
 
 template <typename T, int PT>
@@ -1308,7 +1393,7 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
                                                    Split sp, double* __restrict__ ps, int* __restrict__ ph,
                                                    double* __restrict__ pw, const int* __restrict__ nsurv, int K,
                                                    const int* __restrict__ tpre, const int* __restrict__ tgrp,
-                                                   const int* __restrict__ zrec)
+                                                   const int* __restrict__ zrec, int* __restrict__ tkept)
 {
     // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
     const bool flat = tpre != nullptr;
@@ -1327,7 +1412,7 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
         if (le >= tile_items(sz.x, sz.y, 64 * PT)) continue;  // a list's padding
         const TileItem it = tile_item(le, sz.x, sz.y, 64 * PT);
         cz_frames_tile<T, PT>(m, gd, geo, W, sz.x, Mall, win, zp, Mmax, sp, ps, ph, pw, zrec, j,
-                              item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks);
+                              item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks, tkept);
     }
 }
 
@@ -1615,9 +1700,13 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
                                                        const int* __restrict__ zfls, double* __restrict__ pzeta,
                                                        T* __restrict__ accp, const int* __restrict__ nsurv, int K,
                                                        const int* __restrict__ tpre, const int* __restrict__ tgrp,
-                                                       WFin<T> fin, const int* __restrict__ zrec)
+                                                       WFin<T> fin, const int* __restrict__ zrec,
+                                                       const int* __restrict__ items, int imax,
+                                                       const int* __restrict__ nitems)
 {
-    // per group (tpre null, grid (K, X)) or over the flat list (grid (X))
+    // per group (tpre null, grid (K, X)) or over the flat list (grid (X));
+    // items: the groups' item tables (heavy tiles split), else the items the
+    // sizes give
     const bool flat = tpre != nullptr;
     const int w0 = (flat ? blockIdx.x : blockIdx.y) * 4 + wave_in_block();
     const int stride = (flat ? gridDim.x : gridDim.y) * 4;
@@ -1625,15 +1714,22 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
     // of the flat lists, so they are not read again per item)
     int2 s0 = flat ? make_int2(0, 0) : make_int2(ncur[blockIdx.x], nsurv[blockIdx.x]);
     int run0 = flat ? 0 : gd[blockIdx.x].run;
-    __asm__ volatile("" : "+s"(run0), "+s"(s0.x), "+s"(s0.y));
-    const int end = flat ? tpre[K] : tile_items(s0.x, s0.y, 64 * PT);
+    int n0 = flat || !items ? 0 : nitems[blockIdx.x];
+    __asm__ volatile("" : "+s"(run0), "+s"(s0.x), "+s"(s0.y), "+s"(n0));
+    const int end = flat ? tpre[K] : (items ? n0 : tile_items(s0.x, s0.y, 64 * PT));
     int quads = 0;  // chunked tiles finalized so far (the same count in all four wavefronts)
     for (int e = w0; e < end; e += stride) {
         const int j = flat ? tgrp[e] : (int)blockIdx.x;
         const int le = flat ? e - tpre[j] : e;
         const int2 sz = item_sizes(ncur, nsurv, flat, j, s0);
-        if (le >= tile_items(sz.x, sz.y, 64 * PT)) continue;  // a list's padding
-        const TileItem it = tile_item(le, sz.x, sz.y, 64 * PT);
+        int cnt = items ? n0 : 0;
+        if (items && flat) {
+            int jj = j;
+            __asm__ volatile("" : "+s"(jj));
+            cnt = nitems[jj];
+        }
+        if (le >= (items ? cnt : tile_items(sz.x, sz.y, 64 * PT))) continue;  // a list's padding
+        const TileItem it = items ? item_decode(items[(size_t)j * imax + le]) : tile_item(le, sz.x, sz.y, 64 * PT);
         weight_frames_tile<T, PT>(m, gd, st, geo, sz.x, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, zrec,
                                   j, item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks, fin, quads);
     }
@@ -1730,12 +1826,17 @@ __global__ __launch_bounds__(1024) void k_cz_combine(DevModel m, const Grp* __re
                                                      int* __restrict__ zH, T* __restrict__ zF,
                                                      double* __restrict__ zC, double* __restrict__ zdW,
                                                      int* __restrict__ zflag, int* __restrict__ cand,
-                                                     int* __restrict__ ncand, double* __restrict__ zS)
+                                                     int* __restrict__ ncand, double* __restrict__ zS,
+                                                     const int* __restrict__ nsurv, const int* __restrict__ tkept,
+                                                     int* __restrict__ items, int imax, int WT2,
+                                                     int* __restrict__ nitems)
 {
     extern __shared__ double sm_dw[];
     const int j = blockIdx.x;
     const Grp gr = gd[j];
     const int M = zview(gr, win, nullptr, Mall).M;
+    // the second pass's item table of this group (heavy tiles split)
+    if (items) build_items(j, ncur[j], nsurv[j], WT2, tkept, wtiles, items, imax, nitems);
     // frame-order passes (zpos != nullptr) keep their partials, and want H, F
     // and the flag, in frame order
     const int zoff = win ? win[gr.run].off : 0;

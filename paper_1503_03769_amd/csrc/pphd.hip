@@ -163,6 +163,9 @@ struct pphd_filter {
     bool prescattered = false;  // the parents' scatter of the coming resampling ran with the fusion
     bool uneven = false;       // groups of different sizes: the frame passes walk flat item lists
     int *ipre1 = nullptr, *igrp1 = nullptr, *ipre2 = nullptr, *igrp2 = nullptr;  // those lists
+    // heavy tiles of the second pass: first-pass kept counts, the groups'
+    // item tables and their counts
+    int *tkept = nullptr, *witems = nullptr, *wnitems = nullptr;
     void* stage = nullptr;
     // host side
     double* pin_z = nullptr;
@@ -270,6 +273,9 @@ size_t carve(pphd_filter* f, char* base)
     f->igrp1 = L.take<int>(base, K * (f->wtiles_max * BIRTH_CHUNKS + 3) * 4);
     f->ipre2 = L.take<int>(base, (K + 1) * 4);
     f->igrp2 = L.take<int>(base, K * (f->wtiles_max * BIRTH_CHUNKS + 3) * 4);
+    f->tkept = L.take<int>(base, K * f->wtiles_max * 4);
+    f->witems = L.take<int>(base, K * f->wtiles_max * BIRTH_CHUNKS * 4);
+    f->wnitems = L.take<int>(base, K * 4);
     f->bhist = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->boff = L.take<int>(base, K * (size_t)f->rtiles * BEARING_BUCKETS * 4);
     f->stage = L.take<char>(base, K * (size_t)f->Lmax * 6 * es);
@@ -699,20 +705,29 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
     dim3 gl1(K, xdim(f->wtiles1)), gl2(K, xdim(f->wtiles2));
     const int* ipre1 = nullptr;
     const int *igrp1 = nullptr, *ipre2 = nullptr, *igrp2 = nullptr;
+    // the second pass splits heavy tiles (item tables from the first pass's
+    // kept counts) when both passes use the same tiles and the second pass
+    // finalizes the weights itself
+    const bool split = frames && PT2 % 4 == 0 && f->wt1 == f->wt2;
+    const int imax = f->wtiles_max * BIRTH_CHUNKS;
+    auto lists = [&](int WT, int* pre, int* grp, const int* cnt) -> pphd_status {
+        LAUNCH(f, PPHD_K_ZPREP,
+               hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, f->stream, f->ncur, f->nsurv, K, WT, pre,
+                                  cnt));
+        LAUNCH(f, PPHD_K_ZPREP, hipLaunchKernelGGL(k_items_fill, dim3(K), dim3(256), 0, f->stream, pre, grp));
+        return PPHD_OK;
+    };
     if (f->pass_mode == PASS_FRAMES && f->uneven) {
-        auto lists = [&](int WT, int* pre, int* grp) -> pphd_status {
-            LAUNCH(f, PPHD_K_ZPREP,
-                   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, f->stream, f->ncur, f->nsurv, K, WT, pre));
-            LAUNCH(f, PPHD_K_ZPREP,
-                   hipLaunchKernelGGL(k_items_fill, dim3(K), dim3(256), 0, f->stream, pre, grp));
-            return PPHD_OK;
-        };
-        pphd_status ls = lists(f->wt1, f->ipre1, f->igrp1);
+        pphd_status ls = lists(f->wt1, f->ipre1, f->igrp1, nullptr);
         if (ls != PPHD_OK) return ls;
         ipre1 = f->ipre1;
         igrp1 = f->igrp1;
-        if (f->wt2 != f->wt1) {
-            ls = lists(f->wt2, f->ipre2, f->igrp2);
+        if (split) {
+            // the second pass's lists follow its item tables (after the combine)
+            ipre2 = f->ipre2;
+            igrp2 = f->igrp2;
+        } else if (f->wt2 != f->wt1) {
+            ls = lists(f->wt2, f->ipre2, f->igrp2, nullptr);
             if (ls != PPHD_OK) return ls;
             ipre2 = f->ipre2;
             igrp2 = f->igrp2;
@@ -731,7 +746,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz_frames<T, PT1>), gl1, dim3(256), 0, f->stream, dm, f->gd, geo,
                                   (const T*)st.w, f->ncur, a.M, a.win, zpc, Mx, s1, f->p1s, f->p1h, f->p1w,
-                                  f->nsurv, K, ipre1, igrp1, (const int*)f->zprep.rec));
+                                  f->nsurv, K, ipre1, igrp1, (const int*)f->zprep.rec, split ? f->tkept : nullptr));
     } else if (f->pass_mode == PASS_WRAP) {
         LAUNCH(f, PPHD_K_CZ,
                hipLaunchKernelGGL((k_cz<T, PT1, PASS_WRAP>), g1, dim3(256), 0, f->stream, dm, f->gd, geo,
@@ -746,7 +761,12 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
            hipLaunchKernelGGL((k_cz_combine<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
                               f->gd, f->ncur, a.M, a.win, frames ? f->zprep.pos : nullptr, zsort, Mx, f->wtiles1,
                               f->wt1, f->p1s, f->p1h, f->p1w, global ? f->zHg : f->zH,
-                              (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand, global ? f->zS : nullptr));
+                              (T*)f->zF, f->zC, f->zdW, f->zflag, f->cand, f->ncand, global ? f->zS : nullptr,
+                              f->nsurv, (const int*)f->tkept, split ? f->witems : nullptr, imax, f->wt2, f->wnitems));
+    if (split && f->uneven) {
+        pphd_status ls = lists(f->wt2, f->ipre2, f->igrp2, f->wnitems);
+        if (ls != PPHD_OK) return ls;
+    }
     if (global)
         LAUNCH(f, PPHD_K_CZ_COMBINE,
                hipLaunchKernelGGL((k_cz_global<T>), dim3(K), dim3(1024), (size_t)Mx * sizeof(double), f->stream, dm,
@@ -761,7 +781,8 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight_frames<T, PT2>), gl2, dim3(256), 0, f->stream, dm, f->gd, st, geo,
                                   f->ncur, a.M, a.win, zpc, Mx, s2, f->zHs, (const T*)f->zFs, f->zfls, f->p2zeta,
-                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2, fin, (const int*)f->zprep.rec));
+                                  (T*)f->accp, f->nsurv, K, ipre2, igrp2, fin, (const int*)f->zprep.rec,
+                                  split ? (const int*)f->witems : nullptr, imax, (const int*)f->wnitems));
     } else {
         LAUNCH(f, PPHD_K_WEIGHT,
                hipLaunchKernelGGL((k_weight<T, PT2, false>), g2, dim3(256), 0, f->stream, dm, f->gd, st, geo, f->ncur,
