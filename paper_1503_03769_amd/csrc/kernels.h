@@ -51,11 +51,17 @@ __device__ __forceinline__ int slot_tile(const DevModel& m) { return m.tile_majo
 constexpr int BEARING_BUCKETS = 64;
 // Each group's quantised parent total Q is accumulated in QSLOTS partial
 // sums (exact integers in any order), so that the atomic additions of the
-// resampling's scatter spread over that many addresses
+// resampling's scatter spread over that many addresses.  Slot-major, slot s
+// of group g at qtot[s K + g]: a wavefront reading consecutive groups' totals
+// (every expansion workgroup does, for the exchange count) reads QSLOTS
+// contiguous rows instead of one cache line per group.
 constexpr int QSLOTS = 8;
-__device__ __forceinline__ double group_q(const double* __restrict__ qtot, int g)
+__device__ __forceinline__ double& qslot(double* qtot, int g, int s, int K) { return qtot[(size_t)s * K + g]; }
+__device__ __forceinline__ double group_q(const double* __restrict__ qtot, int g, int K)
 {
-    const double* q = qtot + (size_t)g * QSLOTS;
+    double q[QSLOTS];
+#pragma unroll
+    for (int s = 0; s < QSLOTS; ++s) q[s] = qtot[(size_t)s * K + g];
     return ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
 }
 
@@ -2376,7 +2382,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     // the weight pass's histograms) and its tile sums and group total cleared
     // for k_bk_scatter
     for (int t = threadIdx.x; t < nt; t += 256) tsum[(size_t)j * rtiles + t] = 0.0;
-    if (threadIdx.x < QSLOTS) qtot[(size_t)j * QSLOTS + threadIdx.x] = 0.0;
+    if (threadIdx.x < QSLOTS) qslot(qtot, j, threadIdx.x, gridDim.x) = 0.0;
     bucket_offsets<4>(j, nt, rtiles, bhist, boff);
     __shared__ double s_ms, s_mm, s_mrun[4];
     if (lane == 0) s_mrun[wv] = mrun;
@@ -2584,7 +2590,7 @@ __global__ __launch_bounds__(1024) void k_bk_scan(const int* __restrict__ first,
     const int ntl = (end[j] - range_first(first, j) + 255) / 256;
     if (tsum) {
         for (int t = threadIdx.x; t < ntl; t += 1024) tsum[(size_t)j * rtiles + t] = 0.0;
-        if (threadIdx.x < QSLOTS) qtot[(size_t)j * QSLOTS + threadIdx.x] = 0.0;
+        if (threadIdx.x < QSLOTS) qslot(qtot, j, threadIdx.x, gridDim.x) = 0.0;
     }
     bucket_offsets<16>(j, ntl, rtiles, hist, off);
 }
@@ -2704,7 +2710,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(DevModel m, SoA<T> in, SoA<T
     if (lane == 0) s_qw[wv] = qw;
     __syncthreads();
     const double qg = (s_qw[0] + s_qw[1]) + (s_qw[2] + s_qw[3]);
-    if (threadIdx.x == 0 && qg > 0.0) atomicAdd(&qtot[(size_t)j * QSLOTS + (t2 & (QSLOTS - 1))], qg);
+    if (threadIdx.x == 0 && qg > 0.0) atomicAdd(&qslot(qtot, j, t2 & (QSLOTS - 1), m.K), qg);
 }
 
 // The ranking of k_birth_sort: births c * 1024 + thread (c < BS, first nb
@@ -2991,7 +2997,8 @@ __device__ __forceinline__ long long group_children(double Qd, double N, const G
 // The run's total quantised mass, the sum over its groups, in group order, of
 // 2^-S_q Q_q: the mass Step 5 counts with when one C(z) spans the groups.
 // Every thread of the 256-thread workgroup gets it (contains barriers).
-__device__ double run_quantised_mass(const Grp& gr, const double* __restrict__ qtot, const int* __restrict__ rsS)
+__device__ double run_quantised_mass(const Grp& gr, const double* __restrict__ qtot, const int* __restrict__ rsS,
+                                     int K)
 {
     __shared__ double s_m[256];
     __shared__ double s_tot;
@@ -2999,7 +3006,7 @@ __device__ double run_quantised_mass(const Grp& gr, const double* __restrict__ q
     for (int q0 = 0; q0 < gr.K; q0 += 256) {
         const int q = q0 + (int)threadIdx.x;
         if (q < gr.K) {
-            const double Qq = group_q(qtot, gr.g0 + q);
+            const double Qq = group_q(qtot, gr.g0 + q, K);
             s_m[threadIdx.x] = Qq > 0.0 ? ldexp(Qq, -rsS[gr.g0 + q]) : 0.0;
         }
         __syncthreads();
@@ -3075,7 +3082,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
     __shared__ long long s_nnext;
     const bool xrun = xchg && gr.K >= 2;
     const int jn = gr.jl + 1 < gr.K ? gr.jl + 1 : 0;
-    const double ntot = gr.gz ? run_quantised_mass(gr, qtot, rsS) : 0.0;
+    const double ntot = gr.gz ? run_quantised_mass(gr, qtot, rsS, m.K) : 0.0;
     uint32_t xa = 0, xan = 0;
     if (xrun) {
         // (counts below 2^31: exact in double)
@@ -3083,7 +3090,7 @@ __global__ __launch_bounds__(256) void k_rs_expand(DevModel m, const Grp* __rest
         for (int i = tid; i < gr.K; i += 256) {
             const int g = gr.g0 + i;
             bool c2;
-            const double Qg = group_q(qtot, g);
+            const double Qg = group_q(qtot, g, m.K);
             const double Ng = gr.gz ? ntot : (Qg > 0.0 ? ldexp(Qg, -rsS[g]) : 0.0);
             const long long Li = group_children(Qg, Ng, gd[g], m.cap, &c2);
             mn = (double)Li < mn ? (double)Li : mn;
