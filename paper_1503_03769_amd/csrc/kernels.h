@@ -1158,56 +1158,45 @@ __device__ __forceinline__ TileItem item_decode(int v)
 __device__ void build_items(int j, int n, int ns, int WT, const int* __restrict__ tkept, int wtiles,
                             int* __restrict__ items, int imax, int* __restrict__ nitems)
 {
-    __shared__ int s_cnt[2];
-    __shared__ unsigned char s_heavy[4096];
+    constexpr int HMAX = 4096;  // survivors' tiles a table can split (beyond: none split)
+    __shared__ int s_nh;
+    __shared__ unsigned char s_heavy[HMAX];
     const int nt = (n + WT - 1) / WT, ta = tiles_before_births(n, ns, WT), z = birth_chunks(n, ns, WT);
     const int nbc = z > 1 ? nt - ta : 0;  // chunked birth tiles
     int* it = items + (size_t)j * imax;
     const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) {
-        s_cnt[0] = 0;
-        s_cnt[1] = 0;
-    }
-    // (tables beyond 4096 survivors' tiles split no tile)
-    const int tah = ta < 4096 ? ta : 0;
+    const int tah = ta <= HMAX ? ta : 0;
     for (int t = threadIdx.x; t < tah; t += 1024) s_heavy[t] = tkept[(size_t)j * wtiles + t] >= HEAVY_KEPT ? 1 : 0;
     __syncthreads();
-    // wavefront 0 ranks the heavy and the light survivors' tiles, 64 at a time
+    auto heavy = [&](int t) { return t < tah && s_heavy[t] != 0; };
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // wavefront 0 places the heavy survivors' tiles (4 items each, after the
+    // births' chunked tiles), 64 at a time
     if (threadIdx.x < 64) {
-        int nh = 0, nl = 0;
+        int nh = 0;
         for (int t0 = 0; t0 < ta; t0 += 64) {
             const int t = t0 + lane;
-            const bool live = t < ta;
-            const bool hv = live && t < tah && s_heavy[t];
-            const unsigned long long bh = __ballot(hv), bl = __ballot(live && !hv);
-            const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+            const bool hv = t < ta && heavy(t);
+            const unsigned long long bh = __ballot(hv);
             if (hv) {
                 const int pos = 4 * (nbc + nh + __popcll(bh & below));
 #pragma unroll
                 for (int c = 0; c < 4; ++c) it[pos + c] = t | (c << 20) | (1 << 23);
-            } else if (live) {
-                s_heavy[t] = 2;  // light (its position comes once every heavy tile is counted)
             }
             nh += __popcll(bh);
-            nl += __popcll(bl);
         }
-        if (lane == 0) {
-            s_cnt[0] = nh;
-            s_cnt[1] = nl;
-        }
+        if (lane == 0) s_nh = nh;
     }
     __syncthreads();
-    const int nh = s_cnt[0];
     // the births' tiles: chunked first, or light at the end
     for (int e = threadIdx.x; e < 4 * nbc; e += 1024) it[e] = (ta + e / 4) | ((e % 4) << 20) | (1 << 23);
-    const int lbase = 4 * (nbc + nh);
+    const int lbase = 4 * (nbc + s_nh);
     if (threadIdx.x < 64) {
         int nl = 0;
         for (int t0 = 0; t0 < ta; t0 += 64) {
             const int t = t0 + lane;
-            const bool light = t < ta && (t >= tah || s_heavy[t] == 2);
+            const bool light = t < ta && !heavy(t);
             const unsigned long long bl = __ballot(light);
-            const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
             if (light) it[lbase + nl + __popcll(bl & below)] = t;
             nl += __popcll(bl);
         }
