@@ -2217,7 +2217,8 @@ __device__ __forceinline__ void bucket_offsets(int j, int ntl, int rtiles, const
 // grid (tiles256, K).  k_finalize (grid K) then forms the mass N_j,
 // LT_j = round(N_j) capped at M, the label set I_j (the first LT_j
 // candidates), their local estimates zeta = sum u x / sum u, and the
-// quantisation shift of the group's resampling.  256 threads each.
+// quantisation shift of the group's resampling.  k_wfinal: 256 threads;
+// k_finalize: NW wavefronts (4; 16 measured slower at the benchmark shape).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restrict__ gd, T* __restrict__ W,
@@ -2278,7 +2279,8 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
         h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, const int* __restrict__ ncur,
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_finalize(const Grp* __restrict__ gd, const int* __restrict__ ncur,
                                                   int tiles256, const double* __restrict__ pmass,
                                                   const double* __restrict__ pmax, int Mall,
                                                   const ZWin* __restrict__ win, int Mmax, int wtiles2, int WT2,
@@ -2295,16 +2297,16 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     const int nt = (n + 255) / 256;
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const size_t zb = (size_t)j * Mmax;
-    for (int p = threadIdx.x; p < M; p += 256) {
+    for (int p = threadIdx.x; p < M; p += 64 * NW) {
         sel[zb + p] = 0;
 #pragma unroll
         for (int d = 0; d < 4; ++d) zeta[(zb + p) * 4 + d] = 0.0;
     }
     // Every read that does not wait for the group's mass goes out first: the
     // tile masses and maxima (wavefront 0), the first round of candidate
-    // labels' partial sums (labels c, c + 4, c + 8, c + 12 of wavefront c,
-    // those below the candidate count; the count LT decides later which are
-    // kept), and, inside bucket_offsets, the tiles' bucket histograms.
+    // labels' partial sums (labels c, c + NW, c + 2 NW, c + 3 NW of wavefront
+    // c, those below the candidate count; the count LT decides later which
+    // are kept), and, inside bucket_offsets, the tiles' bucket histograms.
     const int nc = ncand[j];
     const int nw = (n + WT2 - 1) / WT2;
     double ms = 0.0, mm = 0.0;
@@ -2321,26 +2323,26 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     const Grp gr = gd[j];
     double mrun = 0.0;
     if (gr.gz) {
-        for (int q = threadIdx.x; q < gr.K; q += 256) {
+        for (int q = threadIdx.x; q < gr.K; q += 64 * NW) {
             const int g = gr.g0 + q;
             const int ntq = (ncur[g] + 255) / 256;
             for (int t = 0; t < ntq; ++t) mrun += pmass[(size_t)g * tiles256 + t];
         }
         mrun = wave_sum(mrun);
     }
-    // candidate round of labels cb, cb + 4, cb + 8, cb + 12 (below lim; the
-    // others clamped to cb, values dropped)
+    // candidate round of labels cb, cb + NW, cb + 2 NW, cb + 3 NW (below lim;
+    // the others clamped to cb, values dropped)
     auto load_round = [&](int cb, int lim, double (&a)[4][5], int (&pc)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            pc[r] = cand[zb + (cb + 4 * r < lim ? cb + 4 * r : cb)];
+            pc[r] = cand[zb + (cb + NW * r < lim ? cb + NW * r : cb)];
 #pragma unroll
             for (int k = 0; k < 5; ++k) a[r][k] = 0.0;
         }
         for (int t = lane; t < nw; t += 64) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int c = cb + 4 * r < lim ? cb + 4 * r : cb;
+                const int c = cb + NW * r < lim ? cb + NW * r : cb;
                 const double* o = pzeta + (((size_t)j * wtiles2 + t) * Mmax + c) * 5;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) a[r][k] += o[k];
@@ -2350,7 +2352,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     auto finish_round = [&](int cb, int lim, const double (&a)[4][5], const int (&pc)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (cb + 4 * r >= lim) break;
+            if (cb + NW * r >= lim) break;
             double e[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) e[k] = wave_sum(a[r][k]);
@@ -2370,10 +2372,10 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     // the resampling's parent order (bucket offsets of the group's tiles from
     // the weight pass's histograms) and its tile sums and group total cleared
     // for k_bk_scatter
-    for (int t = threadIdx.x; t < nt; t += 256) tsum[(size_t)j * rtiles + t] = 0.0;
+    for (int t = threadIdx.x; t < nt; t += 64 * NW) tsum[(size_t)j * rtiles + t] = 0.0;
     if (threadIdx.x < QSLOTS) qslot(qtot, j, threadIdx.x, gridDim.x) = 0.0;
-    bucket_offsets<4>(j, nt, rtiles, bhist, boff);
-    __shared__ double s_ms, s_mm, s_mrun[4];
+    bucket_offsets<NW>(j, nt, rtiles, bhist, boff);
+    __shared__ double s_ms, s_mm, s_mrun[NW];
     if (lane == 0) s_mrun[wv] = mrun;
     if (wv == 0) {
         ms = wave_sum(ms);
@@ -2386,7 +2388,10 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     __syncthreads();
     ms = s_ms;
     mm = s_mm;
-    const double lt = floor((gr.gz ? (s_mrun[0] + s_mrun[1]) + (s_mrun[2] + s_mrun[3]) : ms) + 0.5);
+    double mr = 0.0;
+    if (gr.gz)
+        for (int w2 = 0; w2 < NW; ++w2) mr += s_mrun[w2];
+    const double lt = floor((gr.gz ? mr : ms) + 0.5);
     const int LT = lt < 0.0 ? 0 : (lt > (double)M ? M : (int)lt);
     const int nsel = LT < nc ? LT : nc;
     if (threadIdx.x == 0) {
@@ -2396,7 +2401,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Grp* __restrict__ gd, co
     }
     // (the labels' zeroing above happened before the barriers in between)
     if (wv < nsel) finish_round(wv, nsel, a0, pc0);
-    for (int cb = wv + 16; cb < nsel; cb += 16) {
+    for (int cb = wv + 4 * NW; cb < nsel; cb += 4 * NW) {
         double a[4][5];
         int pc[4];
         load_round(cb, nsel, a, pc);

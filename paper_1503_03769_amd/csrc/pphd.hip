@@ -796,7 +796,7 @@ pphd_status run_update(pphd_filter* f, const UpdArgs& a)
                                   f->p2mass, f->p2max, (const T*)st.x[0], (const T*)st.x[2], f->bkt, f->bhist,
                                   frames ? f->wt2 : 0, f->nsurv));
     LAUNCH(f, PPHD_K_FINALIZE,
-           hipLaunchKernelGGL(k_finalize, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
+           hipLaunchKernelGGL(k_finalize<4>, dim3(K), dim3(256), 0, f->stream, f->gd, f->ncur, f->tiles256, f->p2mass,
                               f->p2max, a.M, a.win, Mx, f->wtiles2, f->wt2, f->p2zeta, f->cand, f->ncand, f->fmass,
                               f->fLT, f->rsS, f->sel, f->zeta, f->rtiles, f->bhist, f->boff, f->tsum, f->qtot));
     // k_wfinal and k_finalize have prepared the resampling's parent order
