@@ -68,10 +68,15 @@ __device__ __forceinline__ double group_q(const double* __restrict__ qtot, int g
 __device__ __forceinline__ int bearing_bucket(const DevModel& m, double x, double y)
 {
     const double dx = x - m.sx, dy = y - m.sy;
-    double d;
-    if (dx == 0.0 && dy == 0.0) d = 0.0;
-    else if (dy >= 0.0) d = dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (dy - dx);
-    else d = dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+    // the quadrant's offset plus one quotient, selected rather than branched
+    // (one division per slot): 0 + dy/(dx+dy), 1 + (-dx)/(dy-dx),
+    // 2 + (-dy)/(-dx-dy), 3 + dx/(dx-dy); negating a quotient's numerator
+    // negates the correctly rounded quotient exactly
+    const bool up = dy >= 0.0, right = dx >= 0.0;
+    const double num = up ? (right ? dy : -dx) : (right ? dx : -dy);
+    const double den = up ? (right ? dx + dy : dy - dx) : (right ? dx - dy : -dx - dy);
+    const double off = up ? (right ? 0.0 : 1.0) : (right ? 3.0 : 2.0);
+    const double d = (dx == 0.0 && dy == 0.0) ? 0.0 : off + num / den;
     const int b = (int)floor(d * (BEARING_BUCKETS / 4.0));
     return b < 0 ? 0 : (b > BEARING_BUCKETS - 1 ? BEARING_BUCKETS - 1 : b);
 }
@@ -1443,31 +1448,33 @@ __device__ __forceinline__ void finalize_tile(const DevModel& m, const WFin<T>& 
         h[lane] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        double rs[4], rm[4];
+        double wn[4];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const int i = 4 * k + w;
             const int s = base + i * 64 + lane;
-            double wn = 0.0;
+            wn[w] = 0.0;
             if (s < n) {
                 const double wo = (double)wv[i];
                 const T t = (T)(m.nu * wo + m.wscale * wo * (double)acc[i]);
                 Wj[s] = t;
-                wn = (double)t;
+                wn[w] = (double)t;
                 const int b = bearing_bucket(m, (double)xa[i], (double)xb[i]);
                 fin.bkt[gb + s] = b;
                 atomicAdd(&h[b], 1);
             }
-            rs[w] = wave_sum(wn);
-            rm[w] = wave_max(wn);
         }
+        // the 256-slot tile's sum and maximum in k_wfinal's order: the four
+        // slots of a lane first, then one wavefront reduction each
+        const double ts = wave_sum((wn[0] + wn[1]) + (wn[2] + wn[3]));
+        const double tm = wave_max(vmax(vmax(wn[0], wn[1]), vmax(wn[2], wn[3])));
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const int hv = h[lane];
         const size_t o = (size_t)j * fin.tiles256 + t256;
         if (lane == 0) {
-            fin.pmass[o] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
-            fin.pmax[o] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
+            fin.pmass[o] = ts;
+            fin.pmax[o] = tm;
         }
         fin.bhist[o * BEARING_BUCKETS + lane] = hv;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2229,7 +2236,7 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
                                                 int* __restrict__ bkt, int* __restrict__ bhist, int wt_births,
                                                 const int* __restrict__ nsurv)
 {
-    __shared__ double rs[4], rm[4];
+    __shared__ double s_wn[4][64];
     __shared__ int h[BEARING_BUCKETS];
     const int j = slot_group(m);
     // the slot counts first: the capacity's empty tiles leave after one read
@@ -2265,15 +2272,18 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
         bkt[g] = b;
         atomicAdd(&h[b], 1);
     }
-    const double sm = wave_sum(wn), mx = wave_max(wn);
-    if (lane == 0) {
-        rs[wv] = sm;
-        rm[wv] = mx;
-    }
+    // the tile's sum and maximum: lane l adds slots l, l + 64, l + 128 and
+    // l + 192 pairwise, then one wavefront reduction (the order the fused
+    // second pass uses)
+    s_wn[wv][lane] = wn;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        pmass[(size_t)j * tiles256 + tile] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
-        pmax[(size_t)j * tiles256 + tile] = vmax(vmax(rm[0], rm[1]), vmax(rm[2], rm[3]));
+    if (wv == 0) {
+        const double a = s_wn[0][lane], b = s_wn[1][lane], c = s_wn[2][lane], d = s_wn[3][lane];
+        const double sm = wave_sum((a + b) + (c + d)), mx = wave_max(vmax(vmax(a, b), vmax(c, d)));
+        if (lane == 0) {
+            pmass[(size_t)j * tiles256 + tile] = sm;
+            pmax[(size_t)j * tiles256 + tile] = mx;
+        }
     }
     if (threadIdx.x < BEARING_BUCKETS) bhist[((size_t)j * tiles256 + tile) * BEARING_BUCKETS + threadIdx.x] =
         h[threadIdx.x];
