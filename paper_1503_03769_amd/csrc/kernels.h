@@ -1035,7 +1035,27 @@ __device__ __forceinline__ float wave_sum_last(float v)
     v += dpp_rows<0x143, 0xC>(v);
     return v;
 }
-__device__ __forceinline__ double wave_sum_last(double v) { return wave_sum(v); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+// In lane 63 the same value as wave_sum: every lane of a row holds the same
+// row sum R_r after the swizzles, and (R3 + R2) + (R1 + R0) equals
+// (R0 + R1) + (R2 + R3) exactly (each addition commutes).
+__device__ __forceinline__ double wave_sum_last(double v)
+{
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    v += dpp_rows<0x142, 0xA>(v);
+    v += dpp_rows<0x143, 0xC>(v);
+    return v;
+}
 
 // Tile culling.  A term 2^-e with e above exp2_cut<T>() is exactly zero in T
 // (2^-150 rounds to zero in float, 2^-1075 in double; the cuts leave a wide
@@ -1061,7 +1081,26 @@ __device__ __forceinline__ constexpr double exp2_cut<double>() { return 1100.0; 
 struct TileBox {
     float rlo, rhi, alo, ahi, blo, bhi;
 };
-__device__ __forceinline__ float wave_min_f(float v) { return -wave_max(-v); }
+// the 64-lane maximum in every lane: quad and row swizzles, the row
+// broadcasts (rows left out take -inf), then lane 63's value
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows_max(float v)
+{
+    const int ninf = __builtin_bit_cast(int, -__builtin_inff());
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(ninf, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ float wave_max_f(float v)
+{
+    v = fmaxf(v, dpp<0xB1>(v));
+    v = fmaxf(v, dpp<0x4E>(v));
+    v = fmaxf(v, dpp<0x141>(v));
+    v = fmaxf(v, dpp<0x140>(v));
+    v = fmaxf(v, dpp_rows_max<0x142, 0xA>(v));
+    v = fmaxf(v, dpp_rows_max<0x143, 0xC>(v));
+    return lane_value(v, 63);
+}
+__device__ __forceinline__ float wave_min_f(float v) { return -wave_max_f(-v); }
 template <int PT>
 __device__ __forceinline__ TileBox tile_box(const double* rho, const double* phi, const double* phib, int base, int n,
                                             int lane)
@@ -1080,7 +1119,7 @@ __device__ __forceinline__ TileBox tile_box(const double* rho, const double* phi
             bhi = fmaxf(bhi, c);
         }
     }
-    return TileBox{ wave_min_f(rlo), wave_max(rhi), wave_min_f(alo), wave_max(ahi), wave_min_f(blo), wave_max(bhi) };
+    return TileBox{ wave_min_f(rlo), wave_max_f(rhi), wave_min_f(alo), wave_max_f(ahi), wave_min_f(blo), wave_max_f(bhi) };
 }
 // the measurement's terms in the tile can reach 2^-cut: squared distance
 // from the box in the measurement's frame, plus the pass's shift
@@ -1466,13 +1505,13 @@ __device__ __forceinline__ void finalize_tile(const DevModel& m, const WFin<T>& 
         }
         // the 256-slot tile's sum and maximum in k_wfinal's order: the four
         // slots of a lane first, then one wavefront reduction each
-        const double ts = wave_sum((wn[0] + wn[1]) + (wn[2] + wn[3]));
+        const double ts = wave_sum_last((wn[0] + wn[1]) + (wn[2] + wn[3]));
         const double tm = wave_max(vmax(vmax(wn[0], wn[1]), vmax(wn[2], wn[3])));
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const int hv = h[lane];
         const size_t o = (size_t)j * fin.tiles256 + t256;
-        if (lane == 0) {
+        if (lane == 63) {
             fin.pmass[o] = ts;
             fin.pmax[o] = tm;
         }
@@ -1580,9 +1619,10 @@ __device__ __forceinline__ void weight_frames_tile(const DevModel& m, const Grp*
             u3 += u * x3;
             u4 += u;
         }
-        const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
-                     r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
-        if (lane == 0) {
+        const double r0 = wave_sum_last((double)u0), r1 = wave_sum_last((double)u1),
+                     r2 = wave_sum_last((double)u2), r3 = wave_sum_last((double)u3),
+                     r4 = wave_sum_last((double)u4);
+        if (lane == 63) {
             double* o = pzeta + (pz + (fl - 1)) * 5;
             o[0] = r0;
             o[1] = r1;
@@ -2128,9 +2168,10 @@ __global__ __launch_bounds__(256) void k_weight(DevModel m, const Grp* __restric
                         u4 += u;
                     }
                 }
-                const double r0 = wave_sum((double)u0), r1 = wave_sum((double)u1), r2 = wave_sum((double)u2),
-                             r3 = wave_sum((double)u3), r4 = wave_sum((double)u4);
-                if (lane == 0) {
+                const double r0 = wave_sum_last((double)u0), r1 = wave_sum_last((double)u1),
+                             r2 = wave_sum_last((double)u2), r3 = wave_sum_last((double)u3),
+                             r4 = wave_sum_last((double)u4);
+                if (lane == 63) {
                     double* o = pzeta + (pz + (fl - 1)) * 5;
                     o[0] = r0;
                     o[1] = r1;
@@ -2279,8 +2320,8 @@ __global__ __launch_bounds__(256) void k_wfinal(DevModel m, const Grp* __restric
     __syncthreads();
     if (wv == 0) {
         const double a = s_wn[0][lane], b = s_wn[1][lane], c = s_wn[2][lane], d = s_wn[3][lane];
-        const double sm = wave_sum((a + b) + (c + d)), mx = wave_max(vmax(vmax(a, b), vmax(c, d)));
-        if (lane == 0) {
+        const double sm = wave_sum_last((a + b) + (c + d)), mx = wave_max(vmax(vmax(a, b), vmax(c, d)));
+        if (lane == 63) {
             pmass[(size_t)j * tiles256 + tile] = sm;
             pmax[(size_t)j * tiles256 + tile] = mx;
         }
