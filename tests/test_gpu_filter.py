@@ -197,3 +197,37 @@ def test_device_extract_fuses_with_the_resampling_scatter(gpu):
             assert np.array_equal(Xa[:, sl], Xb[:, sl]) and np.array_equal(Wa[sl], Wb[sl]), (k, j)
     host.close()
     dev.close()
+
+
+@pytest.mark.parametrize("pt_cz,pt_weight", [(4, 4), (4, 8), (16, 4), (8, 16)])
+def test_tile_shapes_against_the_oracle(gpu, pt_cz, pt_weight):
+    """The two passes' tile shapes, equal (the second pass then splits its
+    heavy tiles from the first pass's kept counts) and unequal: C(z),
+    weights, masses and the local estimates against the oracle, with
+    clutter (lambda 50) and several hundred particles per group past the
+    last whole tile."""
+    K, lam = 6, 50.0
+    p = dict(BASE_MODEL, partitions=K, clutter_rate=lam, births_per_step=0)
+    truth, Z = make_scenario(p, 10, 8, 314)
+    k = max(range(1, 9), key=lambda i: len(truth[i]))
+    tk, zk = truth[k], Z[k]
+    counts = [5000, 4097, 3333, 1, 2600, 4999]
+    cap = 5120
+    X, W, n = P.cloud(K, cap, counts, 27, tk, "fp32", spread=60.0)
+    f = P.make_filter(p, "fp32", cap, max_meas=128)
+    f.set_tuning(pt_cz, pt_weight, 16)
+    f.write_state(X, W, n, pphd.PHASE_PREDICTED)
+    f.update(zk)
+    Xg, Wg, ng = f.read_state()
+    ug = f.read_update()
+    lg = f.read_local()
+    st = P.oracle_state(K, cap, X, W, n)
+    uo = orc.update(p, st, zk)
+    eo = orc.extract(p, zk.shape[0], uo)
+    kappa = orc.kappa(p)
+    print(f"  M = {zk.shape[0]}", flush=True)
+    P.check_cz(ug["C"], uo["C"], kappa, "fp32")
+    P.check_weights(Wg, st)
+    np.testing.assert_allclose(ug["mass"], uo["mass"], rtol=1e-6, atol=1e-300)
+    P.check_selection(lg["sel"], lg["zeta"], ug["mass"], ug["LT"], uo, eo)
+    f.close()
