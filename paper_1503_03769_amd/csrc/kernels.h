@@ -26,7 +26,7 @@ struct DevModel {
     double cr, ct, period, inv_period, wscale;  // scaled likelihood, see above
     double sigma_r, sigma_th, inv_area, alpha;  // measurement-driven birth proposal
     int K, J, cap, M0, proposal, density;  // density: birth density option (1 = Gaussian)
-    uint32_t key0, key1, run, pad;
+    uint32_t key0, key1, run, one_run;  // one_run: every group belongs to run 0
     double bmean[4], bstd[4];              // Gaussian birth density
     int dim, tile_major;                   // dim 4: CV [x, vx, y, vy]; 5: coordinated turn, + omega
                                            // tile_major: per-slot grids are (tiles, groups)
@@ -1283,8 +1283,10 @@ __global__ __launch_bounds__(256) void k_items_fill(const int* __restrict__ pre,
 }
 
 // the run of a work item's group: read per item from the flat lists, else the
-// workgroup's group's run read once at the start (the empty asm keeps the
-// per-item read behind its branch, so it is not made for every item)
+// workgroup's group's run read once at the start, or 0 without a read when
+// the filter is one run (the measurement record's read then starts at once
+// instead of after the group's); the empty asm keeps the per-item read
+// behind its branch, so it is not made for every item
 __device__ __forceinline__ int item_run(const Grp* __restrict__ gd, bool flat, int j, int run0)
 {
     if (!flat) return run0;
@@ -1441,7 +1443,7 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
     // the group's sizes and run, read once (kept apart from the per-item reads
     // of the flat lists, so they are not read again per item)
     int2 s0 = flat ? make_int2(0, 0) : make_int2(ncur[blockIdx.x], nsurv[blockIdx.x]);
-    int run0 = flat ? 0 : gd[blockIdx.x].run;
+    int run0 = flat || m.one_run ? 0 : gd[blockIdx.x].run;
     __asm__ volatile("" : "+s"(run0), "+s"(s0.x), "+s"(s0.y));
     const int end = flat ? tpre[K] : tile_items(s0.x, s0.y, 64 * PT);
     for (int e = w0; e < end; e += stride) {
@@ -1451,7 +1453,7 @@ __global__ __launch_bounds__(256) void k_cz_frames(DevModel m, const Grp* __rest
         if (le >= tile_items(sz.x, sz.y, 64 * PT)) continue;  // a list's padding
         const TileItem it = tile_item(le, sz.x, sz.y, 64 * PT);
         cz_frames_tile<T, PT>(m, gd, geo, W, sz.x, Mall, win, zp, Mmax, sp, ps, ph, pw, zrec, j,
-                              item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks, tkept);
+                              item_run(gd, flat && !m.one_run, j, run0), it.tile, it.chunk, it.chunks, tkept);
     }
 }
 
@@ -1755,7 +1757,7 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
     // the group's sizes and run, read once (kept apart from the per-item reads
     // of the flat lists, so they are not read again per item)
     int2 s0 = flat ? make_int2(0, 0) : make_int2(ncur[blockIdx.x], nsurv[blockIdx.x]);
-    int run0 = flat ? 0 : gd[blockIdx.x].run;
+    int run0 = flat || m.one_run ? 0 : gd[blockIdx.x].run;
     int n0 = flat || !items ? 0 : nitems[blockIdx.x];
     __asm__ volatile("" : "+s"(run0), "+s"(s0.x), "+s"(s0.y), "+s"(n0));
     const int end = flat ? tpre[K] : (items ? n0 : tile_items(s0.x, s0.y, 64 * PT));
@@ -1773,7 +1775,7 @@ __global__ __launch_bounds__(256) void k_weight_frames(DevModel m, const Grp* __
         if (le >= (items ? cnt : tile_items(sz.x, sz.y, 64 * PT))) continue;  // a list's padding
         const TileItem it = items ? item_decode(items[(size_t)j * imax + le]) : tile_item(le, sz.x, sz.y, 64 * PT);
         weight_frames_tile<T, PT>(m, gd, st, geo, sz.x, Mall, win, zp, Mmax, sp, zHs, zFs, zfls, pzeta, accp, zrec,
-                                  j, item_run(gd, flat, j, run0), it.tile, it.chunk, it.chunks, fin, quads);
+                                  j, item_run(gd, flat && !m.one_run, j, run0), it.tile, it.chunk, it.chunks, fin, quads);
     }
 }
 

@@ -484,6 +484,7 @@ void fill_devmodel(pphd_filter* f)
     d.key0 = (uint32_t)f->seed;
     d.key1 = (uint32_t)(f->seed >> 32);
     d.run = f->run;
+    d.one_run = f->nruns == 1 ? 1 : 0;
 }
 
 template <typename T>
